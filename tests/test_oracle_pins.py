@@ -1,0 +1,466 @@
+"""Pins of the oracle against what the paper and the mathematics fix.
+
+Each test names the passage it rests on. None retypes the oracle's formulas:
+they check lattice identities, exact stencil results on polynomials, moment
+identities of the equilibria and sources, the MRT -> BGK reduction, exact
+invariants of the discrete scheme, closed-form physics (Laplace law, layered
+Poiseuille flow, shear-wave decay, the planar tanh profile) and symmetries.
+"""
+from fractions import Fraction
+import math
+
+import numpy as np
+import pytest
+
+from oracle import lattice as L
+from oracle import model as om
+from oracle import mrt
+from oracle import poiseuille as pz
+from paper_2511_11360_amd import workloads as wl
+
+ALL = [L.D2Q9, L.D2Q5, L.D3Q19, L.D3Q7]
+
+
+# ---------------------------------------------------------------- lattices
+@pytest.mark.parametrize("lat", ALL, ids=lambda l: l.name)
+def test_lattice_moments_exact(lat):
+    """sum w = 1, sum w c = 0, sum w c c = c_s^2 I with c_s^2 = 1/3 exactly
+    (Sec. IV: c_s^2 = 1/3 on both lattices)."""
+    w = lat.w_exact
+    assert sum(w) == 1
+    for a in range(3):
+        assert sum(wi * int(c[a]) for wi, c in zip(w, lat.c)) == 0
+        for b in range(3):
+            s = sum(wi * int(c[a]) * int(c[b]) for wi, c in zip(w, lat.c))
+            exp = Fraction(1, 3) if (a == b and a < lat.dim) else 0
+            assert s == exp, (lat.name, a, b, s)
+
+
+@pytest.mark.parametrize("lat", [L.D2Q9, L.D3Q19], ids=lambda l: l.name)
+def test_fourth_order_isotropy(lat):
+    """sum w c_a c_b c_c c_d = c_s^4 (d_ab d_cd + d_ac d_bd + d_ad d_bc) on the
+    hydrodynamic lattices (needed for the u^2 terms of Eq. fakhari_feq)."""
+    d = lat.dim
+    for a in range(d):
+        for b in range(d):
+            for c in range(d):
+                for e in range(d):
+                    s = sum(wi * int(v[a]) * int(v[b]) * int(v[c]) * int(v[e])
+                            for wi, v in zip(lat.w_exact, lat.c))
+                    k = (a == b) * (c == e) + (a == c) * (b == e) + (a == e) * (b == c)
+                    assert s == Fraction(k, 9)
+
+
+@pytest.mark.parametrize("lat", ALL, ids=lambda l: l.name)
+def test_opposites(lat):
+    for i, j in enumerate(lat.opp):
+        assert np.all(lat.c[j] == -lat.c[i])
+
+
+# ---------------------------------------------------------------- MRT basis
+@pytest.mark.parametrize("lat", [L.D2Q9, L.D3Q19], ids=lambda l: l.name)
+def test_mrt_basis_orthogonal_and_stress_rows(lat):
+    """The moment rows are mutually orthogonal and the stress rows span the
+    traceless symmetric quadratic forms of c (dimension 2 in 2-D, 5 in 3-D)."""
+    M, stress = mrt.basis(lat)
+    G = M @ M.T
+    assert np.allclose(G - np.diag(np.diag(G)), 0.0, atol=1e-12)
+    assert np.linalg.matrix_rank(M) == lat.Q
+    d = lat.dim
+    quad = []
+    for a in range(d):
+        for b in range(a, d):
+            q = lat.c[:, a] * lat.c[:, b] - (a == b) * (lat.c[:, :d] ** 2).sum(1) / d
+            quad.append(q.astype(float))
+    quad = np.array(quad)
+    S = M[stress]
+    assert np.linalg.matrix_rank(S) == d * (d + 1) // 2 - 1
+    # every traceless quadratic form lies in the stress row space
+    coef, *_ = np.linalg.lstsq(S.T, quad.T, rcond=None)
+    assert np.allclose(S.T @ coef, quad.T, atol=1e-12)
+
+
+def _random_node_state(p, seed, amp=0.02):
+    rng = np.random.default_rng(seed)
+    gl, hl = p.lattices
+    shape = p.shape
+    phi = 0.5 + 0.4 * np.sin(2 * np.pi * np.arange(p.nx) / p.nx)[None, None, :] * np.ones(shape)
+    phi = phi + 0.05 * rng.standard_normal(shape)
+    u = 0.03 * rng.standard_normal((3,) + shape)
+    if p.dim == 2:
+        u[2] = 0
+    st = om.init(p, phi, u)
+    st.g = st.g + amp * 1e-2 * rng.standard_normal(st.g.shape) * p.lattices[0].w[:, None, None, None]
+    st.h = st.h + amp * 1e-2 * rng.standard_normal(st.h.shape) * np.maximum(p.lattices[1].w, 0.05)[:, None, None, None]
+    return st
+
+
+@pytest.mark.parametrize("lat", ["D2Q9_D2Q5", "D3Q19_D3Q7"])
+def test_mrt_uniform_rates_is_bgk(lat):
+    """With every moment relaxed at 1/tau the MRT operator is the BGK update of
+    Eq. fakhari_f_simplified: g - (g - g_eq)/tau + (1 - 1/(2 tau)) F_i."""
+    n = 8 if lat.startswith("D2") else 6
+    p = om.Params(lattice=lat, nx=n, ny=n, nz=1 if lat.startswith("D2") else n,
+                  rho_H=3.0, rho_L=1.0, nu_H=0.05, nu_L=0.05, sigma=0.02, W=3.0)
+    st = _random_node_state(p, 1)
+    m = om.macroscopic(p, st)
+    tau = float(np.mean(m["tau"]))
+    assert np.allclose(m["tau"], tau)
+    p.s_other = 1.0 / tau
+    mrt_post = om.collide_g(p, st, m)
+    geq = om.g_eq(p, m["pstar"], m["u"])
+    Fi = om.force_populations(p, m["F"], m["rho"])
+    bgk = st.g - (st.g - geq) / tau + (1 - 1 / (2 * tau)) * Fi
+    assert np.max(np.abs(mrt_post - bgk)) < 1e-15
+
+
+@pytest.mark.parametrize("lat", ["D2Q9_D2Q5", "D3Q19_D3Q7"])
+def test_mrt_conserves_mass_and_adds_force_momentum(lat):
+    """The collision leaves p* = sum g unchanged and raises sum c g by F/rho
+    exactly, whatever the non-stress rate (conserved-moment identities)."""
+    n = 8 if lat.startswith("D2") else 6
+    for so in (1.0, 1.3, 0.7):
+        p = om.Params(lattice=lat, nx=n, ny=n, nz=1 if lat.startswith("D2") else n,
+                      rho_H=3.0, rho_L=1.0, nu_H=0.05, nu_L=0.02, sigma=0.02, W=3.0,
+                      gravity=(1e-4, -2e-4, 0.0), s_other=so)
+        st = _random_node_state(p, 2)
+        m = om.macroscopic(p, st)
+        post = om.collide_g(p, st, m)
+        gl = p.lattices[0]
+        assert np.max(np.abs(post.sum(0) - st.g.sum(0))) < 1e-15
+        for a in range(3):
+            j0 = sum(gl.c[i][a] * st.g[i] for i in range(gl.Q))
+            j1 = sum(gl.c[i][a] * post[i] for i in range(gl.Q))
+            assert np.max(np.abs(j1 - j0 - m["F"][a] / m["rho"])) < 1e-15
+
+
+# ---------------------------------------------------------------- stencils
+def test_stencils_exact_on_polynomials():
+    """The isotropic central stencils of Sec. III reproduce grad of a quadratic
+    and lap of a quadratic exactly (second-order schemes); checked on interior
+    nodes away from the periodic seam, 2-D and 3-D."""
+    rng = np.random.default_rng(3)
+    for lat, shape in (("D2Q9_D2Q5", (1, 9, 11)), ("D3Q19_D3Q7", (7, 8, 9))):
+        nz, ny, nx = shape
+        p = om.Params(lattice=lat, nx=nx, ny=ny, nz=nz)
+        d = p.dim
+        z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+        X = [x.astype(float), y.astype(float), z.astype(float)][:d]
+        A = rng.standard_normal((d, d))
+        A = A + A.T
+        b = rng.standard_normal(d)
+        phi = 0.3 + sum(b[i] * X[i] for i in range(d)) \
+            + sum(A[i, j] * X[i] * X[j] for i in range(d) for j in range(d))
+        grad = om.gradient(p, phi)
+        lap = om.laplacian(p, phi)
+        inner = (slice(1, -1) if d == 3 else slice(None), slice(1, -1), slice(1, -1))
+        for i in range(d):
+            exact = b[i] + 2 * sum(A[i, j] * X[j] for j in range(d))
+            assert np.max(np.abs(grad[i][inner] - exact[inner])) < 1e-11
+        assert np.max(np.abs(lap[inner] - 2 * np.trace(A))) < 1e-11
+
+
+def test_wall_ghost_is_mirror():
+    """At a wall the ghost value equals the first node (n . grad phi = 0 of
+    Sec. II.A at a halfway wall): a field depending on y only has zero normal
+    gradient at both walls when it is symmetric about them."""
+    p = om.Params(nx=4, ny=6, bc=("periodic", "wall", "periodic"))
+    y = np.arange(6.0)
+    phi = np.tile((y * (5 - y))[None, :, None], (1, 1, 4))  # symmetric about 2.5
+    g = om.gradient(p, phi)
+    # the ghost copies the wall node, so the one-sided difference halves
+    assert np.allclose(g[1][0, 0], (phi[0, 1, 0] - phi[0, 0, 0]) / 2)
+    assert np.allclose(g[1][0, -1], (phi[0, -1, 0] - phi[0, -2, 0]) / 2)
+
+
+# ---------------------------------------------------------------- equilibria
+@pytest.mark.parametrize("lat", ["D2Q9_D2Q5", "D3Q19_D3Q7"])
+def test_equilibrium_and_source_moments(lat):
+    """Moments fixed by construction (Eqs. fakhari_geq, fakhari_feq,
+    fakhari_G_modified, fakhari_F, liang2_geq):
+    sum h_eq = phi, sum e h_eq = phi u; sum g_eq = p*, sum c g_eq = u,
+    sum c c g_eq = p* c_s^2 I + u u; sum G = 0, sum e G = c_s^2 (4/W) phi(1-phi) n;
+    sum F_i = 0, sum c F_i = F / rho; CH: sum h_eq = phi, sum e h_eq = phi u,
+    sum e e h_eq = eta mu c_s^2 I."""
+    rng = np.random.default_rng(5)
+    n = 5
+    p = om.Params(lattice=lat, nx=n, ny=n, nz=1 if lat.startswith("D2") else n,
+                  W=3.5, sigma=0.02, eta=0.7)
+    gl, hl = p.lattices
+    d = p.dim
+    shp = p.shape
+    phi = rng.uniform(0.05, 0.95, shp)
+    pst = 0.01 * rng.standard_normal(shp)
+    u = 0.05 * rng.standard_normal((3,) + shp)
+    grad = rng.standard_normal((3,) + shp)
+    if d == 2:
+        u[2] = 0
+        grad[2] = 0
+    mu = 0.01 * rng.standard_normal(shp)
+    tol = 1e-15
+
+    def mom(f, lat_, k=None, l=None):
+        s = 0.0
+        for i in range(lat_.Q):
+            t = f[i]
+            if k is not None:
+                t = t * lat_.c[i][k]
+            if l is not None:
+                t = t * lat_.c[i][l]
+            s = s + t
+        return s
+
+    he = om.h_eq_ac(p, phi, u)
+    assert np.max(np.abs(mom(he, hl) - phi)) < tol
+    for a in range(3):
+        assert np.max(np.abs(mom(he, hl, a) - phi * u[a])) < tol
+    ge = om.g_eq(p, pst, u)
+    assert np.max(np.abs(mom(ge, gl) - pst)) < tol
+    for a in range(3):
+        assert np.max(np.abs(mom(ge, gl, a) - u[a])) < tol
+        for b in range(3):
+            exp = u[a] * u[b] + (a == b and a < d) * pst / 3.0
+            assert np.max(np.abs(mom(ge, gl, a, b) - exp)) < tol
+    G = om.G_ac(p, phi, grad)
+    assert np.max(np.abs(mom(G, hl))) < tol
+    nrm = np.sqrt((grad * grad).sum(0) + p.normal_eps ** 2)
+    for a in range(3):
+        exp = (4.0 / p.W) * phi * (1 - phi) * grad[a] / nrm / 3.0
+        # the regularised normal differs from grad/|grad| by O(eps^2/|grad|^2)
+        assert np.max(np.abs(mom(G, hl, a) - exp)) < tol
+    F = rng.standard_normal((3,) + shp) * 1e-3
+    if d == 2:
+        F[2] = 0
+    rho = rng.uniform(1, 10, shp)
+    Fi = om.force_populations(p, F, rho)
+    assert np.max(np.abs(mom(Fi, gl))) < tol
+    for a in range(3):
+        assert np.max(np.abs(mom(Fi, gl, a) - F[a] / rho)) < tol
+    hc = om.h_eq_ch(p, phi, mu, u)
+    assert np.max(np.abs(mom(hc, hl) - phi)) < tol
+    for a in range(3):
+        assert np.max(np.abs(mom(hc, hl, a) - phi * u[a])) < tol
+        for b in range(3):
+            if a < d and b < d:
+                exp = (a == b) * p.eta * mu / 3.0
+                assert np.max(np.abs(mom(hc, hl, a, b) - exp)) < tol
+
+
+def test_antidiffusion_constant():
+    """sqrt(2 beta / kappa) = 4 / W with beta = 12 sigma / W, kappa = 3 sigma W / 2
+    (Eqs. coefficient1, coefficients): sigma cancels."""
+    for sigma, W in ((0.01, 4.0), (0.3, 2.5), (1e-5, 7.0)):
+        p = om.Params(sigma=sigma, W=W)
+        b, k = om.coefficients(p)
+        assert abs(math.sqrt(2 * b / k) - 4.0 / W) < 1e-15
+
+
+def test_normal_guard():
+    """Where grad phi vanishes the antidiffusion source vanishes, and a
+    round-off-sized gradient gives a round-off-sized source, not a unit normal
+    of arbitrary direction."""
+    p = om.Params(nx=4, ny=4)
+    phi = np.full(p.shape, 0.5)
+    grad = np.zeros((3,) + p.shape)
+    assert np.all(om.G_ac(p, phi, grad) == 0)
+    grad[0] = 1e-17
+    assert np.max(np.abs(om.G_ac(p, phi, grad))) < 1e-12
+    grad[0] = 0.2
+    G = om.G_ac(p, phi, grad)
+    # away from vanishing gradients the source is the paper's: relative
+    # deviation (eps / |grad phi|)^2 / 2 = 1.25e-7 here
+    exact = (1 / 6) * (4 / p.W) * 0.25
+    assert abs(G[1][0, 0, 0] / exact - 1) < 2e-7
+
+
+# ---------------------------------------------------------------- invariants
+@pytest.mark.parametrize("model", ["AC", "CH"])
+def test_phase_conservation_periodic(model):
+    """Conservative phase-field schemes keep sum phi (Sec. III.E: no volume loss
+    of the conservative models): collision conserves sum_a h_a per node and
+    streaming permutes. Bound: rounding only, 2000 steps x 4096 nodes."""
+    d, phi, u = wl.static_droplet_2d()
+    d["model"] = model
+    p = om.Params(**d)
+    st = om.init(p, phi, u)
+    s0 = float(st.h.sum())
+    st = om.run(p, st, 1000 if model == "AC" else 600)
+    rel = abs(float(st.h.sum()) - s0) / s0
+    assert rel < 1e-12, rel
+
+
+def test_phase_conservation_walls_and_gravity():
+    """Same invariant with bounce-back walls and gravity (RT layout, small)."""
+    d, phi, u = wl.rayleigh_taylor_2d(nx=32, ny=64)
+    p = om.Params(**d)
+    st = om.init(p, phi, u)
+    s0 = float(st.h.sum())
+    st = om.run(p, st, 400)
+    assert abs(float(st.h.sum()) - s0) / s0 < 1e-12
+
+
+def test_fixed_point_uniform_phase_at_rest():
+    """Uniform phi, u = 0, p = 0 is a fixed point (no gradient, no force)."""
+    for lat, shape in (("D2Q9_D2Q5", (1, 6, 7)), ("D3Q19_D3Q7", (4, 5, 6))):
+        for model in ("AC", "CH"):
+            p = om.Params(lattice=lat, model=model, nz=shape[0], ny=shape[1], nx=shape[2])
+            st = om.init(p, np.full(shape, 0.8))
+            st2 = om.run(p, st, 5)
+            assert np.max(np.abs(st2.g - st.g)) < 1e-16
+            assert np.max(np.abs(st2.h - st.h)) < 1e-14
+
+
+def test_fixed_point_uniform_flow():
+    """Uniform phi with a uniform velocity and no force: the equilibria are
+    unchanged by collision and streaming (Galilean translation of a uniform state)."""
+    p = om.Params(lattice="D3Q19_D3Q7", nx=5, ny=4, nz=3, rho_H=2.0, rho_L=1.0)
+    u = np.zeros((3,) + p.shape)
+    u[0], u[1], u[2] = 0.03, -0.02, 0.01
+    st = om.init(p, np.full(p.shape, 1.0), u)
+    st2 = om.run(p, st, 4)
+    assert np.max(np.abs(st2.g - st.g)) < 1e-16
+    assert np.max(np.abs(st2.h - st.h)) < 1e-15
+
+
+def test_uniform_force_momentum_growth():
+    """Single phase, periodic, uniform body acceleration g: every node's
+    sum c g grows by exactly g per step (Guo forcing, Eq. fakhari_F with the
+    (1 - 1/(2 tau)) factor and u = sum c g + F/(2 rho))."""
+    p = om.Params(nx=6, ny=5, rho_H=2.0, rho_L=2.0, gravity=(1e-5, -3e-6, 0.0))
+    st = om.init(p, np.full(p.shape, 1.0))
+    n = 50
+    st2 = om.run(p, st, n)
+    gl = p.lattices[0]
+    jx = sum(gl.c[i][0] * st2.g[i] for i in range(gl.Q))
+    jy = sum(gl.c[i][1] * st2.g[i] for i in range(gl.Q))
+    assert np.max(np.abs(jx - n * 1e-5)) < 1e-16
+    assert np.max(np.abs(jy + n * 3e-6)) < 1e-16
+
+
+def test_mirror_symmetry():
+    """A droplet centred on node (32, 32) of a 64^2 periodic box stays symmetric
+    under x -> 64 - x (the scheme and lattice are mirror invariant)."""
+    d, phi, u = wl.static_droplet_2d()
+    p = om.Params(**d)
+    st = om.run(p, om.init(p, phi, u), 200)
+    ph = st.h.sum(0)[0]
+    mirror = np.roll(ph[:, ::-1], 1, axis=1)
+    assert np.max(np.abs(ph - mirror)) < 1e-14
+    assert np.max(np.abs(ph - ph.T)) < 1e-14
+
+
+# ---------------------------------------------------------------- physics
+def test_shear_wave_viscosity():
+    """Single phase: u_x = U sin(2 pi y / L) decays as exp(-nu k^2 t) with
+    nu = c_s^2 (tau - 1/2) (Eq. fakhari_tau_model): pins the stress relaxation."""
+    L_ = 32
+    nu = 0.05
+    p = om.Params(nx=4, ny=L_, nu_H=nu, nu_L=nu)
+    k = 2 * np.pi / L_
+    u = np.zeros((2,) + p.shape)
+    u[0] = 1e-3 * np.sin(k * np.arange(L_))[None, :, None]
+    st = om.init(p, np.full(p.shape, 1.0), u)
+    T = 400
+    st = om.run(p, st, T)
+    _, uu, _, _ = om.fields(p, st)
+    amp = np.sum(uu[0][0, :, 0] * np.sin(k * np.arange(L_))) / (L_ / 2)
+    rate = -np.log(amp / 1e-3) / T
+    assert abs(rate / (nu * k * k) - 1) < 0.01
+
+
+def test_planar_tanh_profile_is_steady():
+    """phi = 1/2 + 1/2 tanh(2 x / W) makes the conservative AC flux of
+    Eq. local_ACE_2 vanish (phi' = (4/W) phi (1 - phi)): at rest the discrete
+    profile stays put up to the stencil's truncation error."""
+    nx = 64
+    d = wl.base_params(nx=nx, ny=4, M=0.05, W=4.0, sigma=1e-4)
+    p = om.Params(**d)
+    x = np.arange(nx, dtype=float)
+    phi1 = 0.5 + 0.5 * np.tanh(2 * (x - 16.0) / 4.0) - 0.5 - 0.5 * np.tanh(2 * (x - 48.0) / 4.0)
+    phi = np.tile(phi1[None, None, :], (1, 4, 1))
+    st = om.run(p, om.init(p, phi), 2000)
+    dev = np.max(np.abs(st.h.sum(0) - phi))
+    assert dev < 1e-2, dev
+    # the residual is the stencils' truncation error: it falls with W
+    d8 = dict(d, W=8.0)
+    p8 = om.Params(**d8)
+    phi8 = np.tile((0.5 + 0.5 * np.tanh(2 * (x - 16.0) / 8.0) - 0.5
+                    - 0.5 * np.tanh(2 * (x - 48.0) / 8.0))[None, None, :], (1, 4, 1))
+    st8 = om.run(p8, om.init(p8, phi8), 2000)
+    dev8 = np.max(np.abs(st8.h.sum(0) - phi8))
+    assert dev8 < dev / 2.5, (dev, dev8)
+    # a profile of the wrong width relaxes visibly towards width W
+    phiw = np.tile((0.5 + 0.5 * np.tanh(2 * (x - 16.0) / 8.0) - 0.5
+                    - 0.5 * np.tanh(2 * (x - 48.0) / 8.0))[None, None, :], (1, 4, 1))
+    stw = om.run(p, om.init(p, phiw), 2000)
+    assert np.max(np.abs(stw.h.sum(0) - phiw)) > 5 * dev
+
+
+def test_ch_chemical_potential_of_tanh_profile():
+    """mu_phi of Eq. chemical_potential vanishes on the planar tanh profile
+    (4 beta phi(phi-1)(phi-1/2) = kappa phi''); the discrete value is bounded by
+    the stencil's truncation error, far below the bulk term's size."""
+    nx = 128
+    p = om.Params(nx=nx, ny=3, W=6.0, sigma=0.01)
+    x = np.arange(nx, dtype=float)
+    phi1 = 0.5 + 0.5 * np.tanh(2 * (x - 32.0) / 6.0) - 0.5 - 0.5 * np.tanh(2 * (x - 96.0) / 6.0)
+    phi = np.tile(phi1[None, None, :], (1, 3, 1))
+    mu = om.chemical_potential(p, phi, om.laplacian(p, phi))
+    beta, _ = om.coefficients(p)
+    bulk = 4 * beta * phi * (phi - 1) * (phi - 0.5)
+    # truncation of the second-order Laplacian ~ (4/W)^2 / 12 of kappa phi''
+    assert np.max(np.abs(mu)) < 0.06 * np.max(np.abs(bulk))
+    # and it converges at second order in 1/W
+    p2 = om.Params(nx=nx, ny=3, W=12.0, sigma=0.01)
+    phi2 = np.tile((0.5 + 0.5 * np.tanh(2 * (x - 32.0) / 12.0) - 0.5
+                    - 0.5 * np.tanh(2 * (x - 96.0) / 12.0))[None, None, :], (1, 3, 1))
+    mu2 = om.chemical_potential(p2, phi2, om.laplacian(p2, phi2))
+    b2, _ = om.coefficients(p2)
+    bulk2 = 4 * b2 * phi2 * (phi2 - 1) * (phi2 - 0.5)
+    r1 = np.max(np.abs(mu)) / np.max(np.abs(bulk))
+    r2 = np.max(np.abs(mu2)) / np.max(np.abs(bulk2))
+    assert 3.0 < r1 / r2 < 5.0, (r1, r2)
+
+
+def test_laplace_law_static_droplet():
+    """Young-Laplace in 2-D, dp = sigma / R, on the static droplet (64^2, R = 16,
+    W = 4, sigma = 0.01, rho ratio 10): within 5 % after 3000 steps."""
+    d, phi, u = wl.static_droplet_2d()
+    p = om.Params(**d)
+    st = om.run(p, om.init(p, phi, u), 3000)
+    dg = om.diagnostics(p, st, centre=(32.0, 32.0), R=16.0)
+    ratio = (dg["p_in"] - dg["p_out"]) * 16.0 / 0.01
+    assert abs(ratio - 1) < 0.05, ratio
+    assert dg["umax"] < 1e-4
+
+
+def test_layered_poiseuille_closed_form():
+    """Sec. III.D: layered Poiseuille flow with density and viscosity ratio
+    1000 against Eq. analytical_solution; the paper's models give
+    L2 Err(u_x) between 0.0053 and 0.0237 (Table poiseuille_velocity)."""
+    d, phi, u = wl.layered_poiseuille()
+    p = om.Params(**d)
+    st = om.run(p, om.init(p, phi, u), 8000)
+    _, uu, _, _ = om.fields(p, st)
+    ux = uu[0][0, :, 0]
+    nu = d["nu_H"]
+    ua = pz.analytic_ux(np.arange(100) + 0.5 - 50.0, 50.0, d["force"][0],
+                        d["rho_H"] * nu, d["rho_L"] * nu, d["W"])
+    err = pz.l2_error(ux, ua)
+    assert err < 0.0237, err
+
+
+def test_poiseuille_closed_form_sharp_limit():
+    """The quadrature of Eq. analytical_solution reduces to the two-layer
+    parabola for a vanishing interface width and to the one-fluid parabola for
+    equal viscosities."""
+    H, G = 1.0, 2.0
+    Y = np.linspace(-0.9, 0.9, 7)
+    ua = pz.analytic_ux(Y, H, G, 3.0, 3.0, 1e-3)
+    assert np.allclose(ua, G * (H * H - Y * Y) / (2 * 3.0), rtol=1e-9)
+    mH, mL = 2.0, 0.5
+    ua = pz.analytic_ux(Y, H, G, mH, mL, 1e-4)
+    C = G * H / 2 * (mH - mL) / (mH + mL)
+    uc = G * H * H / (mH + mL)
+    exact = np.where(Y < 0, uc + (C * Y - G * Y * Y / 2) / mH, uc + (C * Y - G * Y * Y / 2) / mL)
+    assert np.allclose(ua, exact, rtol=1e-4)
