@@ -1,0 +1,190 @@
+/*
+ * pflbm.h -- C ABI of the MI355X phase-field lattice Boltzmann library
+ * (libpflbm.so, HIP for gfx950).
+ *
+ * The library advances a coupled two-phase solver one fused time step per
+ * kernel launch: a hydrodynamic distribution g (D2Q9 or D3Q19, MRT collision
+ * with the force F = F_s + F_b + F_p + F_mu, pressure-normalised equilibrium)
+ * and a phase-field distribution h (D2Q5 or D3Q7, conservative Allen-Cahn or
+ * Cahn-Hilliard). The method is the Fakhari2017 model of Li, Zhang, Wu, Peng,
+ * Wang, "Comparative study and critical assessment of phase-field lattice
+ * Boltzmann models ...", arXiv 2511.11360, Sec. II.C.1 (Eqs.
+ * fakhari_model_simplified, fakhari_tau_model, mu_linear, fakhari_eqs,
+ * fakhari_forces_modified, fakhari_update_all), with the Cahn-Hilliard phase
+ * field of Sec. II.D.1 (Eqs. liang2_geq, liang2_G, backward-Euler time
+ * derivative of Sec. III.B) as the second model. Naming: g here is the paper's
+ * hydrodynamic f_beta, h the paper's phase-field g_alpha, W the paper's
+ * interface width xi, M its mobility M_phi. phi_H = 1, phi_L = 0.
+ *
+ * Conventions shared by every call
+ *  - Every function returns an int status: PFLBM_OK (0) or a negative
+ *    PFLBM_E* code. Nothing throws or aborts across the ABI. After an error on
+ *    a handle, pflbm_last_error() returns a message owned by the handle.
+ *    Errors other than PFLBM_EINVAL are sticky: later calls return
+ *    PFLBM_ESTATE until the handle is destroyed.
+ *  - Field pointers are DEVICE pointers to float64 arrays in canonical
+ *    layout, x fastest: scalars [z][y][x], vectors [d][z][y][x] with
+ *    d = 2 (2-D) or 3, distributions [q][z][y][x] in the canonical population
+ *    order below. The caller owns them; the library never keeps them.
+ *  - The library allocates no device memory. Its whole device state (g, the
+ *    two h buffers, the CH (phi u) state, reduction scratch) lives in one
+ *    caller-owned device buffer of pflbm_state_bytes() bytes passed to
+ *    pflbm_create(), which the caller must keep alive until pflbm_destroy().
+ *  - Calls are asynchronous on the HIP stream given to pflbm_create(), except
+ *    those documented as synchronising.
+ *  - Node (i, j, k) sits at (x, y, z) = (i, j, k). A walled axis has its walls
+ *    half a spacing outside its first and last node (halfway bounce-back).
+ *
+ * Canonical population order
+ *  D2Q9 : 0 rest, 1 (+1,0), 2 (0,+1), 3 (-1,0), 4 (0,-1),
+ *         5 (+1,+1), 6 (-1,+1), 7 (-1,-1), 8 (+1,-1)
+ *  D2Q5 : the first five D2Q9 vectors; weights 1/3, 1/6
+ *  D3Q19: 0 rest, 1 +x, 2 -x, 3 +y, 4 -y, 5 +z, 6 -z, 7 (+x+y), 8 (-x-y),
+ *         9 (+x-y), 10 (-x+y), 11 (+x+z), 12 (-x-z), 13 (+x-z), 14 (-x+z),
+ *         15 (+y+z), 16 (-y-z), 17 (+y-z), 18 (-y+z)
+ *  D3Q7 : the first seven D3Q19 vectors; with c_s^2 = 1/3 (Sec. IV) the rest
+ *         weight is 0 and the face weights 1/6, so for the AC model the rest
+ *         population of h is identically zero and is not stored.
+ */
+#ifndef PFLBM_H
+#define PFLBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define PFLBM_OK            0
+#define PFLBM_EINVAL       -1   /* invalid argument; handle state unchanged */
+#define PFLBM_EUNSUPPORTED -2   /* valid but not supported by this build */
+#define PFLBM_EHIP         -3   /* HIP runtime error (sticky) */
+#define PFLBM_EUNSTABLE    -4   /* NaN/Inf in phi or u, or rho <= 0, detected */
+#define PFLBM_ESTATE       -5   /* handle in an error state */
+
+/* lattice pair: hydrodynamic g + phase-field h */
+#define PFLBM_D2Q9_D2Q5   0
+#define PFLBM_D3Q19_D3Q7  1
+
+/* phase-field model */
+#define PFLBM_AC 0   /* conservative Allen-Cahn, Eqs. fakhari_geq, fakhari_G_modified */
+#define PFLBM_CH 1   /* Cahn-Hilliard, Eqs. liang2_geq, liang2_G */
+
+/* storage / arithmetic form */
+#define PFLBM_FP64        0  /* g, h float64; float64 arithmetic */
+#define PFLBM_FP32        1  /* g, h float32; float32 arithmetic */
+#define PFLBM_MIXED_FP16  2  /* g stored as fp16 of 4096 g_i / w_i, h float32; float32 arithmetic */
+#define PFLBM_MIXED_BF16  3  /* g stored as bf16 of g_i / w_i, h float32; float32 arithmetic */
+
+/* boundary per axis */
+#define PFLBM_PERIODIC 0
+#define PFLBM_WALL     1    /* halfway bounce-back; at most one walled axis */
+
+/* viscosity interpolation */
+#define PFLBM_VISC_LINEAR_MU 0   /* Eq. mu_linear: mu linear in phi, nu = mu / rho */
+#define PFLBM_VISC_LINEAR_NU 1   /* Eq. fakhari_mu_update: nu linear in phi */
+
+typedef struct pflbm_params {
+    int lattice;          /* PFLBM_D2Q9_D2Q5 or PFLBM_D3Q19_D3Q7 */
+    int model;            /* PFLBM_AC or PFLBM_CH */
+    int precision;        /* PFLBM_FP64 ... PFLBM_MIXED_BF16 */
+    int nx, ny, nz;       /* nodes per axis, each >= 1; nz == 1 for 2-D */
+    int bc[3];            /* PFLBM_PERIODIC or PFLBM_WALL per axis x, y, z */
+    double wall_u[2][3];  /* velocity of the low / high wall of the walled axis;
+                             must be tangential to the wall */
+    double rho_H, rho_L;  /* phase densities, > 0 (Eq. fakhari_rho_update) */
+    double nu_H, nu_L;    /* kinematic viscosities; tau = 3 nu + 1/2 > 1/2
+                             (Eq. fakhari_tau_model) */
+    int visc_interp;      /* PFLBM_VISC_LINEAR_MU (paper's default) or _NU */
+    double M;             /* mobility, > 0; tau_phi = 3 M + 1/2 (AC),
+                             3 M / eta + 1/2 (CH) */
+    double W;             /* interface width xi, > 0 */
+    double sigma;         /* surface tension, >= 0; beta = 12 sigma / W,
+                             kappa = 3 sigma W / 2 (Eqs. coefficient1, coefficients) */
+    double eta;           /* CH mobility parameter of Eq. liang2_geq, > 0 */
+    double gravity[3];    /* body acceleration: F_b = rho * gravity */
+    double force[3];      /* uniform force density added to F_b (Sec. III.D drive) */
+    double s_other;       /* MRT rate of every non-stress moment, in (0, 2) */
+    double normal_eps;    /* interface normal n = grad phi / sqrt(|grad phi|^2 + eps^2), >= 0 */
+    int freeze_phi;       /* nonzero: h (hence phi) is not updated (Sec. III.D) */
+    int check_interval;   /* every this many steps pflbm_step checks for NaN/Inf
+                             or rho <= 0 (synchronising); 0 = never */
+    int zblock;           /* z planes per workgroup, 0 = automatic (tuning only) */
+} pflbm_params;
+
+/* FP64 diagnostics of one state (Eq. volume_continuous; volume by counting
+   phi > 1/2 of Sec. IV.A; delta phi_max of Sec. III.A from phi_min/phi_max;
+   umax = max |u|; mean pressure inside r < R - 2W and outside r > R + 2W). */
+typedef struct pflbm_diag {
+    double V_phi;      /* sum (phi - phi_L) / (phi_H - phi_L) */
+    double V_count;    /* number of nodes with phi > 1/2 */
+    double sum_phi;
+    double phi_min, phi_max;
+    double umax;
+    double p_in, p_out;        /* NaN when the region is empty or no centre given */
+    long long n_in, n_out;
+    int unstable;              /* 1 if NaN/Inf in phi or u, or rho <= 0, anywhere */
+} pflbm_diag;
+
+typedef struct pflbm pflbm_t;
+
+/* Bytes of the device state buffer for these parameters. Host pointers. */
+int pflbm_state_bytes(const pflbm_params* params, size_t* bytes);
+
+/* Validate params and bind a handle to the caller's device buffer dev_state
+   (bytes >= pflbm_state_bytes, 256-byte aligned) and HIP stream hip_stream
+   (hipStream_t, NULL = default stream) on the current device. *out receives a
+   host-allocated handle, freed by pflbm_destroy(). */
+int pflbm_create(const pflbm_params* params, void* hip_stream, void* dev_state,
+                 size_t bytes, pflbm_t** out);
+
+/* Equilibrium initialisation: h = h_eq(phi0, u0) (CH with mu_phi(phi0)),
+   g = g_eq(p0 / (rho0 c_s^2), u0); resets the step counter. phi0 [z][y][x],
+   u0 [d][z][y][x] or NULL (zero), p0 [z][y][x] or NULL (zero): device float64. */
+int pflbm_init(pflbm_t* h, const double* phi0, const double* u0, const double* p0);
+
+/* Advance nsteps >= 0 fused time steps (one kernel launch each). Returns
+   PFLBM_EUNSTABLE (and stops) when a check due under check_interval fails. */
+int pflbm_step(pflbm_t* h, int nsteps);
+
+/* Macroscopic fields of the current state (the values the next step uses):
+   phi, u (d components), p = rho c_s^2 sum g, rho. Device float64 outputs,
+   any may be NULL. */
+int pflbm_fields(pflbm_t* h, double* phi, double* u, double* p, double* rho);
+
+/* Diagnostics of the current state, reduced in float64 on the device with a
+   fixed order (bit-reproducible). centre: HOST array of dim doubles or NULL;
+   R: droplet radius for the pressure regions. Synchronises the stream. */
+int pflbm_volume(pflbm_t* h, const double* centre, double R, pflbm_diag* out);
+
+/* Copy the post-streaming distributions out as canonical float64 (decoding
+   the storage form and the in-place streaming layout). Device pointers
+   g [Qg][z][y][x] and hd [Qh][z][y][x] (Qh = 5 or 7, rest included). */
+int pflbm_get_distributions(pflbm_t* h, double* g, double* hd);
+
+/* Overwrite the state from canonical float64 distributions (device pointers,
+   same layout as pflbm_get_distributions); the storage form rounds them.
+   For AC on D3Q7 the rest population of h must be zero. CH keeps its (phi u)
+   state. */
+int pflbm_set_distributions(pflbm_t* h, const double* g, const double* hd);
+
+/* Number of completed steps since pflbm_init. */
+int pflbm_step_count(const pflbm_t* h, long long* steps);
+
+/* Checkpoint: raw copy of the native state (distributions in their storage
+   form, layout parity, step counter, CH state) to/from a caller-owned device
+   buffer of pflbm_checkpoint_bytes() bytes. */
+int pflbm_checkpoint_bytes(const pflbm_t* h, size_t* bytes);
+int pflbm_save_state(pflbm_t* h, void* dev_dst);
+int pflbm_load_state(pflbm_t* h, const void* dev_src);
+
+void pflbm_destroy(pflbm_t* h);
+const char* pflbm_last_error(const pflbm_t* h);
+const char* pflbm_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PFLBM_H */

@@ -1,0 +1,113 @@
+// Internal interface between the C ABI (pflbm.cpp) and the kernels
+// (kernels.hip). Not installed, not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+namespace pfk {
+
+constexpr int TILE_X = 64;      // one wavefront per x row of a tile
+constexpr int TILE_Y = 4;       // rows per workgroup
+constexpr int BLOCK = TILE_X * TILE_Y;
+constexpr int NDIAG = 12;       // per-block partial diagnostics (see kernels.hip)
+constexpr int MAXQ = 19;
+
+enum Mode { MODE_STEP = 0, MODE_FIELDS = 1, MODE_DIAG = 2 };
+
+// physical constants, precomputed on the host (float64, and rounded once to
+// float32 for the float32 forms)
+template <class T>
+struct PhysT {
+    T rhoL, dRho;      // rho = rhoL + phi dRho (phi_H = 1, phi_L = 0)
+    T muL, dMu;        // linear-mu interpolation of rho_X nu_X
+    T nuL, dNu;        // linear-nu interpolation
+    int visc_mu;       // 1: linear mu, 0: linear nu
+    T beta4;           // 4 beta = 48 sigma / W
+    T kappa;           // 3 sigma W / 2
+    T anti;            // sqrt(2 beta / kappa) = 4 / W
+    T eps2;            // normal regularisation eps^2
+    T inv_tau_phi;     // 1 / tau_phi
+    T g_fac_phi;       // 1 - 1 / (2 tau_phi)
+    T eta;             // CH mobility parameter
+    T s_o;             // MRT rate of the non-stress moments
+    T body[3];         // gravity (F_b = rho body + force)
+    T force[3];
+};
+using Phys = PhysT<double>;
+
+template <class T>
+__host__ __device__ inline PhysT<float> to_float(const PhysT<T>& d) {
+    PhysT<float> f;
+    f.rhoL = (float)d.rhoL; f.dRho = (float)d.dRho;
+    f.muL = (float)d.muL; f.dMu = (float)d.dMu;
+    f.nuL = (float)d.nuL; f.dNu = (float)d.dNu;
+    f.visc_mu = d.visc_mu;
+    f.beta4 = (float)d.beta4; f.kappa = (float)d.kappa; f.anti = (float)d.anti;
+    f.eps2 = (float)d.eps2; f.inv_tau_phi = (float)d.inv_tau_phi; f.g_fac_phi = (float)d.g_fac_phi;
+    f.eta = (float)d.eta; f.s_o = (float)d.s_o;
+    for (int k = 0; k < 3; ++k) { f.body[k] = (float)d.body[k]; f.force[k] = (float)d.force[k]; }
+    return f;
+}
+
+struct KArgs {
+    void* g;               // AA in-place hydrodynamic populations [Qg][N]
+    const void* hin;       // phase-field populations read this step [Qhs][N]
+    void* hout;            // phase-field populations written this step [Qhs][N]
+    void* phiu;            // CH (phi u) of the previous step [3][N], compute type
+    double* f_phi;         // MODE_FIELDS outputs (canonical float64), may be null
+    double* f_u;
+    double* f_p;
+    double* f_rho;
+    double* partials;      // MODE_DIAG per-block partials [nblocks][NDIAG]
+    long long N;           // population stride in elements
+    int nx, ny, nz;
+    int ntx, nty, ntz, zb; // tiles per axis, z planes per tile
+    int bc[3];             // 0 periodic, 1 wall
+    int wall_axis;         // -1 none, else 0/1/2
+    int write_h;           // 0 when phi is frozen
+    int has_centre;
+    double centre[3];
+    double r_in, r_out;    // pressure regions r < r_in, r > r_out
+    double gcorr[2][MAXQ]; // moving-wall term of a g population leaving through the low/high wall
+    float gcorrf[2][MAXQ];
+    Phys ph;
+    PhysT<float> phf;
+};
+
+struct InitArgs {
+    void* g;
+    void* h;
+    void* phiu;
+    const double* phi0;
+    const double* u0;      // may be null
+    const double* p0;      // may be null
+    long long N;
+    int nx, ny, nz;
+    int bc[3];
+    Phys ph;
+};
+
+struct IOArgs {
+    void* g;               // native state
+    void* h;               // current phase-field buffer
+    double* cg;            // canonical float64 g [Qg][nodes]
+    double* ch;            // canonical float64 h [Qh][nodes]
+    long long N;
+    int nx, ny, nz;
+    int bc[3];
+    int wall_axis;
+    int parity;            // layout parity of g (0: natural slots)
+    double gcorr[2][MAXQ];
+};
+
+// launchers (kernels.hip); return hipSuccess or the launch error
+hipError_t launch_step(int lattice, int model, int precision, int parity, int mode,
+                       const KArgs& a, hipStream_t s);
+hipError_t launch_init(int lattice, int model, int precision, const InitArgs& a, hipStream_t s);
+hipError_t launch_get(int lattice, int model, int precision, const IOArgs& a, hipStream_t s);
+hipError_t launch_set(int lattice, int model, int precision, const IOArgs& a, hipStream_t s);
+hipError_t launch_reduce(const double* partials, int nblocks, double* out, hipStream_t s);
+hipError_t launch_header(void* dst, long long steps, int parity, int hcur, hipStream_t s);
+
+}  // namespace pfk

@@ -1,0 +1,914 @@
+// HIP kernels of the fused phase-field lattice Boltzmann time step (gfx950).
+//
+// One launch = one time step of the coupled solver of the paper's Sec. II.C.1
+// (Fakhari2017 conservative Allen-Cahn; Cahn-Hilliard h-equation of Sec. II.D.1
+// as the second model). Per node, in this order:
+//   phi = sum_a h_a                                   (Eq. fakhari_phi_update)
+//   grad phi, lap phi from the isotropic central stencils of Sec. III on the
+//   hydrodynamic lattice, ghost phi = periodic image or wall mirror
+//   rho, nu, tau, mu_phi, p* = sum g, F_s, F_b, F_p   (Eqs. fakhari_rho_update,
+//   mu_linear, fakhari_tau_model, chemical_potential, fakhari_p_update, total force)
+//   F_mu = nu (grad u + grad u^T) . grad rho with the strain rate from the
+//   non-equilibrium second moment of g at u* = sum c g + (F_s+F_b+F_p)/(2 rho)
+//   u = sum c g + F/(2 rho)                           (Eq. fakhari_velocity_update)
+//   h: BGK with Eqs. fakhari_geq + fakhari_G_modified (AC) or liang2_geq +
+//   liang2_G with a backward-Euler d(phi u)/dt (CH)
+//   g: MRT with the stress moments at 1/tau and the rest at s_o, Eqs. fakhari_feq
+//   and fakhari_F; in moment space m* = m - S(m - m_eq) + (I - S/2) m_F, which for
+//   an orthogonal basis and two rates is
+//     g* = g - s_o (g - g_eq) - (1/tau - s_o) P (g - g_eq) + (1 - s_o/2) F_i
+//   with P the orthogonal projector on the stress rows (P F_i = 0: F_i is odd
+//   in c). P (g - g_eq) needs only the non-equilibrium second moment.
+//   streaming: g in place (AA pattern: even steps read and write the node's own
+//   slots swapped, odd steps gather from and scatter to the neighbours); h
+//   push-streamed from one buffer into the other. Halfway bounce-back at walls.
+//
+// Layout in HBM: structure of arrays, population-major, x fastest; population
+// stride N elements. g storage: float64, float32, or fp16/bf16 of g_i / w_i.
+//
+// Work decomposition: a workgroup owns a 64 x 4 (x, y) column tile and marches
+// over zb planes in z. phi of three planes (tile plus a one-node halo) is
+// rebuilt from h in LDS as a ring; the h buffer read this step is never written
+// during the step, so halo reads of other tiles' nodes are race-free.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.h"
+#include "lattice.h"
+
+namespace pfk {
+
+// ----------------------------------------------------------------------------
+// storage forms
+
+template <int P> struct Types;
+template <> struct Types<0> { using T = double; using GS = double;   using HS = double; };
+template <> struct Types<1> { using T = float;  using GS = float;    using HS = float;  };
+template <> struct Types<2> { using T = float;  using GS = _Float16; using HS = float;  };
+template <> struct Types<3> { using T = float;  using GS = uint16_t; using HS = float;  };
+
+// g codec: the scaled forms store s_i = K g_i / w_i (fp16, K = 4096) or g_i / w_i
+// (bf16), rounded to nearest even.
+template <int P> struct GCodec {
+    template <class L, int i, class GS, class T>
+    static __device__ __forceinline__ T dec(GS v) { return (T)v; }
+    template <class L, int i, class GS, class T>
+    static __device__ __forceinline__ GS enc(T v) { return (GS)v; }
+};
+template <> struct GCodec<2> {
+    template <class L, int i, class GS, class T>
+    static __device__ __forceinline__ float dec(_Float16 v) {
+        constexpr float s = (float)(L::w(i) / 4096.0);
+        return (float)v * s;
+    }
+    template <class L, int i, class GS, class T>
+    static __device__ __forceinline__ _Float16 enc(float v) {
+        constexpr float s = (float)(4096.0 / L::w(i));
+        return (_Float16)(v * s);
+    }
+};
+template <> struct GCodec<3> {
+    template <class L, int i, class GS, class T>
+    static __device__ __forceinline__ float dec(uint16_t v) {
+        constexpr float s = (float)L::w(i);
+        return __uint_as_float(((uint32_t)v) << 16) * s;
+    }
+    template <class L, int i, class GS, class T>
+    static __device__ __forceinline__ uint16_t enc(float v) {
+        constexpr float s = (float)(1.0 / L::w(i));
+        uint32_t u = __float_as_uint(v * s);
+        u += 0x7FFFu + ((u >> 16) & 1u);
+        return (uint16_t)(u >> 16);
+    }
+};
+
+// ----------------------------------------------------------------------------
+// index helpers
+
+__device__ __forceinline__ int ghost_coord(int v, int n, int bc) {
+    if (bc == 0) {
+        v %= n;
+        return v < 0 ? v + n : v;
+    }
+    return v < 0 ? 0 : (v >= n ? n - 1 : v);
+}
+
+// neighbour x + sgn c_i: linear index, or wall crossing (side 0 low, 1 high)
+template <class L, int i, int sgn>
+__device__ __forceinline__ bool shifted(int nx, int ny, int nz, const int* bc, int x, int y, int z,
+                                        int& idx, int& side) {
+    int co[3] = {x, y, z};
+    const int n[3] = {nx, ny, nz};
+    bool wall = false;
+    side = 0;
+    unroll<3>([&](auto A) {
+        constexpr int ax = A;
+        constexpr int d = sgn * L::c(i, ax);
+        if constexpr (d != 0) {
+            int v = co[ax] + d;
+            if (v < 0 || v >= n[ax]) {
+                if (bc[ax] == 0) {
+                    v = v < 0 ? v + n[ax] : v - n[ax];
+                } else {
+                    wall = true;
+                    side = v < 0 ? 0 : 1;
+                }
+            }
+            co[ax] = v;
+        }
+    });
+    idx = (co[2] * ny + co[1]) * nx + co[0];
+    return wall;
+}
+
+__device__ __forceinline__ int xcd_remap(int bid, int nb) {
+    // consecutive workgroup ids go to different XCDs (round robin over 8);
+    // give each XCD a contiguous run of tiles so halo rows stay in its L2
+    const int per = nb / 8;
+    if (bid >= per * 8) return bid;
+    return (bid % 8) * per + bid / 8;
+}
+
+// ----------------------------------------------------------------------------
+// the node update
+
+template <class T>
+struct NodeOut {
+    T phi, rho, p;
+    T u[3];
+};
+
+template <class T> __device__ __forceinline__ T rcp(T x);
+template <> __device__ __forceinline__ float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ double rcp<double>(double x) { return 1.0 / x; }
+template <class T> __device__ __forceinline__ T rsqrt_(T x);
+template <> __device__ __forceinline__ float rsqrt_<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+template <> __device__ __forceinline__ double rsqrt_<double>(double x) { return 1.0 / sqrt(x); }
+
+// Computes the macroscopic state of one node and, when COLLIDE, hands every
+// post-collision population to gsink(i, value) / hsink(a, value) as soon as it
+// is formed (so that no array of outputs stays live). Populations are treated
+// in opposite pairs (c, -c): equilibria and sources split into a part even in
+// c, shared by the pair, and an odd part that changes sign.
+template <class PAIR, int MODEL, class T, bool COLLIDE, class GSink, class HSink>
+__device__ __forceinline__ void node_update(const PhysT<T>& ph, const T* g, const T* h, const T* phin,
+                                            const T* pu_prev, T* pu_new, NodeOut<T>& mo,
+                                            GSink&& gsink, HSink&& hsink) {
+    using GL = typename PAIR::G;
+    using HL = typename PAIR::H;
+    constexpr bool D3 = PAIR::dim == 3;
+
+    const T phi = phin[0];
+    // isotropic stencils: grad = 3 sum w c phi(x+c), lap = 6 sum w (phi(x+c) - phi)
+    T gr[3] = {(T)0, (T)0, (T)0};
+    T lap = (T)0;
+    unroll<GL::NP>([&](auto K) {
+        constexpr int i = GL::pf(K), o = GL::opp(i);
+        const T dp = phin[i] - phin[o];
+        unroll<3>([&](auto A) {
+            constexpr int a = A;
+            if constexpr (GL::c(i, a) != 0) gr[a] += (T)(3.0 * GL::w(i) * GL::c(i, a)) * dp;
+        });
+        lap += (T)(6.0 * GL::w(i)) * ((phin[i] - phi) + (phin[o] - phi));
+    });
+
+    const T dRho = ph.dRho;
+    const T rho = ph.rhoL + phi * dRho;
+    const T irho = rcp(rho);
+    const T nu = ph.visc_mu ? (ph.muL + phi * ph.dMu) * irho : ph.nuL + phi * ph.dNu;
+    const T itau = rcp((T)3 * nu + (T)0.5);
+    const T mu_phi = ph.beta4 * phi * (phi - (T)1) * (phi - (T)0.5) - ph.kappa * lap;
+
+    // moments of g: p*, j, second moment (xx yy zz xy yz xz)
+    T ps = g[0];
+    T j[3] = {(T)0, (T)0, (T)0};
+    T m2[6] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
+    unroll<GL::NP>([&](auto K) {
+        constexpr int i = GL::pf(K), o = GL::opp(i);
+        constexpr int cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
+        const T s = g[i] + g[o], d = g[i] - g[o];
+        ps += s;
+        if constexpr (cx != 0) { j[0] += (T)cx * d; m2[0] += s; }
+        if constexpr (cy != 0) { j[1] += (T)cy * d; m2[1] += s; }
+        if constexpr (cz != 0) { j[2] += (T)cz * d; m2[2] += s; }
+        if constexpr (cx * cy != 0) m2[3] += (T)(cx * cy) * s;
+        if constexpr (cy * cz != 0) m2[4] += (T)(cy * cz) * s;
+        if constexpr (cx * cz != 0) m2[5] += (T)(cx * cz) * s;
+    });
+
+    // forces: F_s + F_b + F_p, with F_p = -(p/rho) grad rho = -c_s^2 p* dRho grad phi
+    const T inv2rho = (T)0.5 * irho;
+    const T sg = mu_phi - ps * dRho * (T)(1.0 / 3.0);
+    T F[3];
+    unroll<3>([&](auto A) {
+        constexpr int a = A;
+        F[a] = sg * gr[a] + rho * ph.body[a] + ph.force[a];
+    });
+    // strain from the non-equilibrium second moment at u* (sum c c g_eq = p*/3 I + u u)
+    T us[3];
+    unroll<3>([&](auto A) { constexpr int a = A; us[a] = j[a] + F[a] * inv2rho; });
+    const T s3 = ps * (T)(1.0 / 3.0);
+    const T sfac = (T)(-3.0) * itau;            // S = -Pi / (tau c_s^2)
+    T S[6];
+    S[0] = sfac * (m2[0] - s3 - us[0] * us[0]);
+    S[1] = sfac * (m2[1] - s3 - us[1] * us[1]);
+    S[2] = D3 ? sfac * (m2[2] - s3 - us[2] * us[2]) : (T)0;
+    S[3] = sfac * (m2[3] - us[0] * us[1]);
+    S[4] = D3 ? sfac * (m2[4] - us[1] * us[2]) : (T)0;
+    S[5] = D3 ? sfac * (m2[5] - us[0] * us[2]) : (T)0;
+    const T nr = nu * dRho;                     // F_mu = nu S . grad rho
+    F[0] += nr * (S[0] * gr[0] + S[3] * gr[1] + S[5] * gr[2]);
+    F[1] += nr * (S[3] * gr[0] + S[1] * gr[1] + S[4] * gr[2]);
+    F[2] += nr * (S[5] * gr[0] + S[4] * gr[1] + S[2] * gr[2]);
+    T u[3];
+    unroll<3>([&](auto A) { constexpr int a = A; u[a] = j[a] + F[a] * inv2rho; });
+
+    mo.phi = phi;
+    mo.rho = rho;
+    mo.p = rho * s3;
+    mo.u[0] = u[0];
+    mo.u[1] = u[1];
+    mo.u[2] = u[2];
+    if constexpr (!COLLIDE) return;
+
+    // ---- g collision (two-rate MRT, projector form)
+    const T usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const T so = ph.s_o;
+    const T so1 = (T)1 - so;
+    const T dS = itau - so;
+    const T ffac = ((T)1 - (T)0.5 * so) * (T)3 * irho;
+    const T aeq = ps - (T)1.5 * usq;
+    // non-equilibrium second moment at the final u
+    const T pxx = m2[0] - s3 - u[0] * u[0], pyy = m2[1] - s3 - u[1] * u[1];
+    const T pzz = m2[2] - s3 - u[2] * u[2];
+    const T pxy = m2[3] - u[0] * u[1], pyz = m2[4] - u[1] * u[2], pxz = m2[5] - u[0] * u[2];
+    T A0, A1, Axy, Ayz, Axz;
+    if constexpr (D3) {
+        A0 = ((T)2 * pxx - pyy - pzz) * (T)(1.0 / 36.0);   // row 3cx^2 - c^2, norm^2 36
+        A1 = (pyy - pzz) * (T)(1.0 / 12.0);                // row cy^2 - cz^2, norm^2 12
+        Axy = pxy * (T)0.25;
+        Ayz = pyz * (T)0.25;
+        Axz = pxz * (T)0.25;
+    } else {
+        A0 = (pxx - pyy) * (T)0.25;                        // row cx^2 - cy^2, norm^2 4
+        A1 = (T)0;
+        Axy = pxy * (T)0.25;
+        Ayz = (T)0;
+        Axz = (T)0;
+    }
+    // rest population: no odd part, no stress projection
+    gsink(std::integral_constant<int, 0>{}, so1 * g[0] + so * (T)GL::w(0) * aeq);
+    unroll<GL::NP>([&](auto K) {
+        constexpr int i = GL::pf(K), o = GL::opp(i);
+        constexpr int cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
+        constexpr T w = (T)GL::w(i);
+        T cu = (T)0, cf = (T)0;
+        if constexpr (cx != 0) { cu += (T)cx * u[0]; cf += (T)cx * F[0]; }
+        if constexpr (cy != 0) { cu += (T)cy * u[1]; cf += (T)cy * F[1]; }
+        if constexpr (cz != 0) { cu += (T)cz * u[2]; cf += (T)cz * F[2]; }
+        T P = (T)0;
+        if constexpr (D3) {
+            constexpr int q0 = 3 * cx * cx - (cx * cx + cy * cy + cz * cz);
+            constexpr int q1 = cy * cy - cz * cz;
+            if constexpr (q0 != 0) P += (T)q0 * A0;
+            if constexpr (q1 != 0) P += (T)q1 * A1;
+            if constexpr (cx * cy != 0) P += (T)(cx * cy) * Axy;
+            if constexpr (cy * cz != 0) P += (T)(cy * cz) * Ayz;
+            if constexpr (cx * cz != 0) P += (T)(cx * cz) * Axz;
+        } else {
+            constexpr int q0 = cx * cx - cy * cy;
+            if constexpr (q0 != 0) P += (T)q0 * A0;
+            if constexpr (cx * cy != 0) P += (T)(cx * cy) * Axy;
+        }
+        // g_eq = E +/- O with E = w (aeq + 4.5 (c.u)^2), O = 3 w c.u; F_i = +/- w c.F ...
+        const T E = w * (aeq + (T)4.5 * cu * cu);
+        const T base = so * E - dS * P;
+        const T t = so * ((T)3 * w * cu) + ffac * w * cf;
+        gsink(std::integral_constant<int, i>{}, so1 * g[i] + base + t);
+        gsink(std::integral_constant<int, o>{}, so1 * g[o] + base - t);
+    });
+
+    // ---- h collision (BGK): h* = (1 - 1/tau_phi) h + h_eq / tau_phi + (1 - 1/(2 tau_phi)) G
+    const T itp = ph.inv_tau_phi, gfp = ph.g_fac_phi;
+    const T itp1 = (T)1 - itp;
+    if constexpr (MODEL == 0) {
+        const T gg = gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2];
+        const T coef = ph.anti * phi * ((T)1 - phi) * rsqrt_(gg + ph.eps2);
+        const T e0 = phi * ((T)1 - (T)1.5 * usq);
+        if constexpr (HL::w(0) != 0.0)
+            hsink(std::integral_constant<int, 0>{}, itp1 * h[0] + itp * (T)HL::w(0) * e0);
+        unroll<HL::NP>([&](auto K) {
+            constexpr int al = HL::pf(K), o = HL::opp(al);
+            constexpr T w = (T)HL::w(al);
+            constexpr int ex = HL::c(al, 0), ey = HL::c(al, 1), ez = HL::c(al, 2);
+            T eu = (T)0, eg = (T)0;
+            if constexpr (ex != 0) { eu += (T)ex * u[0]; eg += (T)ex * gr[0]; }
+            if constexpr (ey != 0) { eu += (T)ey * u[1]; eg += (T)ey * gr[1]; }
+            if constexpr (ez != 0) { eu += (T)ez * u[2]; eg += (T)ez * gr[2]; }
+            const T base = itp * w * (e0 + (T)4.5 * phi * eu * eu);
+            const T t = itp * ((T)3 * w * phi * eu) + gfp * w * coef * eg;
+            hsink(std::integral_constant<int, al>{}, itp1 * h[al] + base + t);
+            hsink(std::integral_constant<int, o>{}, itp1 * h[o] + base - t);
+        });
+    } else {
+        const T eta = ph.eta;
+        T pu[3], dpu[3];
+        unroll<3>([&](auto A) {
+            constexpr int a = A;
+            pu[a] = phi * u[a];
+            dpu[a] = pu[a] - pu_prev[a];
+            pu_new[a] = pu[a];
+        });
+        const T emu = eta * mu_phi;
+        hsink(std::integral_constant<int, 0>{}, itp1 * h[0] + itp * (phi + ((T)HL::w(0) - (T)1) * emu));
+        unroll<HL::NP>([&](auto K) {
+            constexpr int al = HL::pf(K), o = HL::opp(al);
+            constexpr T w = (T)HL::w(al);
+            constexpr int ex = HL::c(al, 0), ey = HL::c(al, 1), ez = HL::c(al, 2);
+            T ep = (T)0, ed = (T)0;
+            if constexpr (ex != 0) { ep += (T)ex * pu[0]; ed += (T)ex * dpu[0]; }
+            if constexpr (ey != 0) { ep += (T)ey * pu[1]; ed += (T)ey * dpu[1]; }
+            if constexpr (ez != 0) { ep += (T)ez * pu[2]; ed += (T)ez * dpu[2]; }
+            const T base = itp * w * emu;
+            const T t = itp * ((T)3 * w * ep) + gfp * (T)3 * w * ed;
+            hsink(std::integral_constant<int, al>{}, itp1 * h[al] + base + t);
+            hsink(std::integral_constant<int, o>{}, itp1 * h[o] + base - t);
+        });
+    }
+}
+
+// ----------------------------------------------------------------------------
+// block reduction of the diagnostics (fixed order, deterministic)
+
+struct DiagAcc {
+    double v[NDIAG];
+};
+
+__device__ __forceinline__ void diag_init(DiagAcc& d) {
+    for (int k = 0; k < NDIAG; ++k) d.v[k] = 0.0;
+    d.v[3] = 1e300;    // phi_min
+    d.v[4] = -1e300;   // phi_max
+}
+
+__device__ __forceinline__ void diag_combine(double* a, const double* b) {
+    for (int k = 0; k < NDIAG; ++k) {
+        if (k == 3) a[k] = fmin(a[k], b[k]);
+        else if (k == 4 || k == 5 || k == 10) a[k] = fmax(a[k], b[k]);
+        else a[k] += b[k];
+    }
+}
+
+__device__ void block_reduce_diag(DiagAcc& d, double* out) {
+    __shared__ double red[BLOCK / 64][NDIAG];
+    for (int off = 32; off >= 1; off >>= 1) {
+        double o[NDIAG];
+        for (int k = 0; k < NDIAG; ++k) o[k] = __shfl_xor(d.v[k], off, 64);
+        diag_combine(d.v, o);
+    }
+    const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+    if (lane == 0)
+        for (int k = 0; k < NDIAG; ++k) red[wv][k] = d.v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double acc[NDIAG];
+        for (int k = 0; k < NDIAG; ++k) acc[k] = red[0][k];
+        for (int w = 1; w < BLOCK / 64; ++w) diag_combine(acc, red[w]);
+        for (int k = 0; k < NDIAG; ++k) out[k] = acc[k];
+    }
+}
+
+// ----------------------------------------------------------------------------
+// fused step kernel
+
+// Per-thread geometry of the column (x, y) a thread owns for the whole z march:
+// offsets to the x and y neighbours with the periodic wrap folded in, and wall
+// flags. Offsets are in nodes; the z part comes per plane as a uniform value.
+struct Column {
+    int ox[3];       // x offset for c_x = -1, 0, +1
+    int oy[3];       // y offset (nodes) for c_y = -1, 0, +1
+    bool wx[2], wy[2];   // the x / y neighbour at -1 / +1 lies beyond a wall
+};
+
+struct Plane {
+    int oz[3];       // z offset (nodes) for c_z = -1, 0, +1
+    bool wz[2];
+};
+
+__device__ __forceinline__ void axis_offsets(int v, int n, int bc, int stride, int* o, bool* w) {
+    const bool lo = v == 0, hi = v == n - 1;
+    o[0] = (lo && bc == 0) ? (n - 1) * stride : -stride;
+    o[1] = 0;
+    o[2] = (hi && bc == 0) ? -(n - 1) * stride : stride;
+    w[0] = lo && bc != 0;
+    w[1] = hi && bc != 0;
+}
+
+// offset (nodes) of x + sgn c and whether that point lies beyond a wall
+template <class L, int i, int sgn>
+__device__ __forceinline__ int nb_offset(const Column& cl, const Plane& pl, bool& wall) {
+    constexpr int cx = sgn * L::c(i, 0), cy = sgn * L::c(i, 1), cz = sgn * L::c(i, 2);
+    int off = cl.ox[cx + 1] + cl.oy[cy + 1] + pl.oz[cz + 1];
+    bool w = false;
+    if constexpr (cx != 0) w = w || cl.wx[cx > 0];
+    if constexpr (cy != 0) w = w || cl.wy[cy > 0];
+    if constexpr (cz != 0) w = w || pl.wz[cz > 0];
+    wall = w;
+    return off;
+}
+
+// side (0 low, 1 high) of the wall crossed towards x + sgn c (single walled axis)
+template <class L, int i, int sgn>
+__device__ __forceinline__ int wall_side(const Column& cl, const Plane& pl) {
+    constexpr int cx = sgn * L::c(i, 0), cy = sgn * L::c(i, 1), cz = sgn * L::c(i, 2);
+    int side = 0;
+    if constexpr (cx != 0) side = cl.wx[cx > 0] ? (cx > 0) : side;
+    if constexpr (cy != 0) side = cl.wy[cy > 0] ? (cy > 0) : side;
+    if constexpr (cz != 0) side = pl.wz[cz > 0] ? (cz > 0) : side;
+    return side;
+}
+
+template <class PAIR, int MODEL, int PREC, int PARITY, int MODE>
+__global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
+    using GL = typename PAIR::G;
+    using HL = typename PAIR::H;
+    using T = typename Types<PREC>::T;
+    using GS = typename Types<PREC>::GS;
+    using HS = typename Types<PREC>::HS;
+    using GC = GCodec<PREC>;
+    constexpr int QG = GL::Q, QH = HL::Q;
+    constexpr bool D3 = PAIR::dim == 3;
+    constexpr int HOFF = (MODEL == 0 && D3) ? 1 : 0;   // AC on D3Q7: rest population not stored
+    constexpr int QHS = QH - HOFF;
+    constexpr int PW = TILE_X + 2, PSZ = PW * (TILE_Y + 2);
+    constexpr int NPL = D3 ? 3 : 1;
+    constexpr int NFILL = (PSZ + BLOCK - 1) / BLOCK;
+    __shared__ T lphi[NPL * PSZ];
+
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int bx = b % a.ntx, byz = b / a.ntx;
+    const int by = byz % a.nty, bz = byz / a.nty;
+    const int x0 = bx * TILE_X, y0 = by * TILE_Y;
+    const int zs = bz * a.zb;
+    const int ze = min(a.nz, zs + a.zb);
+    const int lx = threadIdx.x % TILE_X, ly = threadIdx.x / TILE_X;
+    const int x = x0 + lx, y = y0 + ly;
+    const bool active = x < a.nx && y < a.ny;
+    const int nx = a.nx, ny = a.ny, nz = a.nz, nxy = nx * ny;
+    const long long N = a.N;
+    const unsigned NU = (unsigned)a.N;
+    GS* __restrict__ G = (GS*)a.g;
+    const HS* __restrict__ Hin = (const HS*)a.hin;
+    HS* __restrict__ Hout = (HS*)a.hout;
+    T* __restrict__ PU = (T*)a.phiu;
+
+    // halo positions this thread fills, fixed over the march (in-plane offsets)
+    int hoff[NFILL];
+    for (int r = 0; r < NFILL; ++r) {
+        const int k = threadIdx.x + r * BLOCK;
+        const int hx = k % PW - 1, hy = k / PW - 1;
+        hoff[r] = ghost_coord(y0 + hy, ny, a.bc[1]) * nx + ghost_coord(x0 + hx, nx, a.bc[0]);
+    }
+    Column cl;
+    axis_offsets(min(x, nx - 1), nx, a.bc[0], 1, cl.ox, cl.wx);
+    axis_offsets(min(y, ny - 1), ny, a.bc[1], nx, cl.oy, cl.wy);
+
+    const PhysT<T>* php;
+    const double* gcd = &a.gcorr[0][0];
+    const float* gcf = &a.gcorrf[0][0];
+    if constexpr (sizeof(T) == 8) php = &a.ph;
+    else php = &a.phf;
+    const PhysT<T>& ph = *php;
+    auto gcorr = [&](int side, int i) -> T {
+        if constexpr (sizeof(T) == 8) return gcd[side * MAXQ + i];
+        else return gcf[side * MAXQ + i];
+    };
+
+    DiagAcc acc;
+    if constexpr (MODE == MODE_DIAG) diag_init(acc);
+
+    auto fill_plane = [&](int zz, int slot) {
+        const int gz = D3 ? ghost_coord(zz, nz, a.bc[2]) : 0;
+        const int base = gz * nxy;
+        for (int r = 0; r < NFILL; ++r) {
+            const int k = threadIdx.x + r * BLOCK;
+            if (r + 1 < NFILL || k < PSZ) {
+                const unsigned idx = (unsigned)(base + hoff[r]);
+                T s = (T)0;
+                unroll<QHS>([&](auto J) {
+                    constexpr int jj = J;
+                    s += (T)Hin[(size_t)jj * N + idx];
+                });
+                lphi[slot * PSZ + k] = s;
+            }
+        }
+    };
+
+    auto do_node = [&](int z, const T* pm, const T* p0, const T* pp) {
+        Plane pl;
+        axis_offsets(z, nz, a.bc[2], nxy, pl.oz, pl.wz);
+        const unsigned idx = (unsigned)(z * nxy + y * nx + x);
+        // post-streaming g of this node
+        T g[QG];
+        unroll<QG>([&](auto I) {
+            constexpr int i = I;
+            if constexpr (PARITY == 0) {
+                g[i] = GC::template dec<GL, i, GS, T>(G[(size_t)i * N + idx]);
+            } else {
+                constexpr int o = GL::opp(i);
+                constexpr int lo = i < o ? i : o;
+                bool wall;
+                const int off = nb_offset<GL, i, -1>(cl, pl, wall);
+                // beyond a wall the population left this node last step: slot i here;
+                // both candidates are addressed from the lower population's base
+                const unsigned e = wall ? (unsigned)(i - lo) * NU + idx
+                                        : (unsigned)(o - lo) * NU + (unsigned)((int)idx + off);
+                T v = GC::template dec<GL, o, GS, T>((G + (size_t)lo * N)[e]);
+                if (wall) v += gcorr(wall_side<GL, i, -1>(cl, pl), o);
+                g[i] = v;
+            }
+        });
+        T h[QH];
+        h[0] = (T)0;
+        unroll<QHS>([&](auto J) {
+            constexpr int jj = J;
+            h[jj + HOFF] = (T)Hin[(size_t)jj * N + idx];
+        });
+        T pu_prev[3] = {(T)0, (T)0, (T)0};
+        if constexpr (MODEL == 1) {
+            pu_prev[0] = PU[idx];
+            pu_prev[1] = PU[N + idx];
+            pu_prev[2] = PU[2 * N + idx];
+        }
+        // phi at the stencil points
+        T phin[QG];
+        unroll<QG>([&](auto I) {
+            constexpr int i = I;
+            constexpr int cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
+            const T* pl_ = cz < 0 ? pm : (cz > 0 ? pp : p0);
+            phin[i] = pl_[(ly + 1 + cy) * PW + (lx + 1 + cx)];
+        });
+        NodeOut<T> mo;
+        T pu_new[3];
+        if constexpr (MODE == MODE_STEP) {
+            // g: AA in place
+            auto gsink = [&](auto I, T v) {
+                constexpr int i = I;
+                constexpr int o = GL::opp(i);
+                if constexpr (PARITY == 0) {
+                    G[(size_t)o * N + idx] = GC::template enc<GL, o, GS, T>(v);
+                } else {
+                    constexpr int lo = i < o ? i : o;
+                    bool wall;
+                    const int off = nb_offset<GL, i, 1>(cl, pl, wall);
+                    if (wall) v += gcorr(wall_side<GL, i, 1>(cl, pl), i);
+                    const unsigned e = wall ? (unsigned)(o - lo) * NU + idx
+                                            : (unsigned)(i - lo) * NU + (unsigned)((int)idx + off);
+                    (G + (size_t)lo * N)[e] = GC::template enc<GL, i, GS, T>(v);
+                }
+            };
+            // h: push into the other buffer
+            auto hsink = [&](auto J, T v) {
+                constexpr int al = J;
+                if constexpr (al >= HOFF) {
+                    if (a.write_h) {
+                        constexpr int o = HL::opp(al);
+                        constexpr int lo = al < o ? al : o;
+                        bool wall;
+                        const int off = nb_offset<HL, al, 1>(cl, pl, wall);
+                        const unsigned e = wall ? (unsigned)(o - lo) * NU + idx
+                                                : (unsigned)(al - lo) * NU + (unsigned)((int)idx + off);
+                        (Hout + (size_t)(lo - HOFF) * N)[e] = (HS)v;
+                    }
+                }
+            };
+            node_update<PAIR, MODEL, T, true>(ph, g, h, phin, pu_prev, pu_new, mo, gsink, hsink);
+            if constexpr (MODEL == 1) {
+                if (a.write_h) {
+                    PU[idx] = pu_new[0];
+                    PU[N + idx] = pu_new[1];
+                    PU[2 * N + idx] = pu_new[2];
+                }
+            }
+        } else {
+            auto none = [](auto, T) {};
+            node_update<PAIR, MODEL, T, false>(ph, g, h, phin, pu_prev, pu_new, mo, none, none);
+            if constexpr (MODE == MODE_FIELDS) {
+                if (a.f_phi) a.f_phi[idx] = (double)mo.phi;
+                if (a.f_rho) a.f_rho[idx] = (double)mo.rho;
+                if (a.f_p) a.f_p[idx] = (double)mo.p;
+                if (a.f_u) {
+                    const long long nn = (long long)nx * ny * nz;
+                    a.f_u[idx] = (double)mo.u[0];
+                    a.f_u[nn + idx] = (double)mo.u[1];
+                    if constexpr (D3) a.f_u[2 * nn + idx] = (double)mo.u[2];
+                }
+            } else {
+                const double phi = (double)mo.phi;
+                const double u2 = (double)mo.u[0] * (double)mo.u[0] +
+                                  (double)mo.u[1] * (double)mo.u[1] +
+                                  (double)mo.u[2] * (double)mo.u[2];
+                acc.v[0] += phi;
+                acc.v[1] += phi > 0.5 ? 1.0 : 0.0;
+                acc.v[2] += phi;
+                acc.v[3] = fmin(acc.v[3], phi);
+                acc.v[4] = fmax(acc.v[4], phi);
+                acc.v[5] = fmax(acc.v[5], u2);
+                const bool bad = !isfinite(phi) || !isfinite(u2) || !((double)mo.rho > 0.0);
+                acc.v[10] = fmax(acc.v[10], bad ? 1.0 : 0.0);
+                if (a.has_centre) {
+                    const double co[3] = {(double)x, (double)y, (double)z};
+                    const int n[3] = {nx, ny, nz};
+                    double r2 = 0.0;
+                    for (int ax = 0; ax < PAIR::dim; ++ax) {
+                        double d = co[ax] - a.centre[ax];
+                        if (a.bc[ax] == 0) d -= n[ax] * rint(d / n[ax]);
+                        r2 += d * d;
+                    }
+                    const double r = sqrt(r2);
+                    if (r < a.r_in) { acc.v[6] += (double)mo.p; acc.v[7] += 1.0; }
+                    if (r > a.r_out) { acc.v[8] += (double)mo.p; acc.v[9] += 1.0; }
+                }
+            }
+        }
+    };
+
+    if constexpr (D3) {
+        fill_plane(zs - 1, 0);
+        fill_plane(zs, 1);
+        for (int z = zs; z < ze; ++z) {
+            const int r = z - zs;
+            fill_plane(z + 1, (r + 2) % 3);
+            __syncthreads();
+            if (active) do_node(z, lphi + (r % 3) * PSZ, lphi + ((r + 1) % 3) * PSZ,
+                                lphi + ((r + 2) % 3) * PSZ);
+            __syncthreads();
+        }
+    } else {
+        fill_plane(0, 0);
+        __syncthreads();
+        if (active) do_node(0, lphi, lphi, lphi);
+    }
+    if constexpr (MODE == MODE_DIAG) {
+        __syncthreads();
+        block_reduce_diag(acc, a.partials + (size_t)blockIdx.x * NDIAG);
+    }
+}
+
+// final reduction over the per-block partials, one workgroup, fixed order
+__global__ __launch_bounds__(BLOCK) void k_reduce(const double* __restrict__ part, int nb,
+                                                  double* __restrict__ out) {
+    DiagAcc d;
+    diag_init(d);
+    for (int b = threadIdx.x; b < nb; b += BLOCK) diag_combine(d.v, part + (size_t)b * NDIAG);
+    block_reduce_diag(d, out);
+}
+
+__global__ void k_header(long long* dst, long long steps, int parity, int hcur) {
+    if (threadIdx.x == 0) {
+        dst[0] = 0x70666c626dLL;   // tag
+        dst[1] = steps;
+        dst[2] = parity;
+        dst[3] = hcur;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// initialisation: h = h_eq(phi0, u0), g = g_eq(p0 / (rho0 c_s^2), u0), natural slots
+
+template <class PAIR, int MODEL, int PREC>
+__global__ __launch_bounds__(256) void k_init(const InitArgs a) {
+    using GL = typename PAIR::G;
+    using HL = typename PAIR::H;
+    using T = typename Types<PREC>::T;
+    using GS = typename Types<PREC>::GS;
+    using HS = typename Types<PREC>::HS;
+    using GC = GCodec<PREC>;
+    constexpr bool D3 = PAIR::dim == 3;
+    constexpr int HOFF = (MODEL == 0 && D3) ? 1 : 0;
+    const long long nn = (long long)a.nx * a.ny * a.nz;
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    const int x = (int)(n % a.nx), y = (int)((n / a.nx) % a.ny), z = (int)(n / ((long long)a.nx * a.ny));
+    const Phys& ph = a.ph;
+    const double phi = a.phi0[n];
+    double u[3] = {0.0, 0.0, 0.0};
+    if (a.u0) {
+        u[0] = a.u0[n];
+        u[1] = a.u0[nn + n];
+        if (D3) u[2] = a.u0[2 * nn + n];
+    }
+    const double rho = ph.rhoL + phi * ph.dRho;
+    const double ps = a.p0 ? 3.0 * a.p0[n] / rho : 0.0;
+    const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    GS* G = (GS*)a.g;
+    HS* H = (HS*)a.h;
+    unroll<GL::Q>([&](auto I) {
+        constexpr int i = I;
+        const double cu = GL::c(i, 0) * u[0] + GL::c(i, 1) * u[1] + GL::c(i, 2) * u[2];
+        const double geq = GL::w(i) * (ps + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+        G[(size_t)i * a.N + n] = GC::template enc<GL, i, GS, T>((T)geq);
+    });
+    if constexpr (MODEL == 0) {
+        unroll<HL::Q - HOFF>([&](auto J) {
+            constexpr int al = J + HOFF;
+            const double eu = HL::c(al, 0) * u[0] + HL::c(al, 1) * u[1] + HL::c(al, 2) * u[2];
+            const double heq = HL::w(al) * phi * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * usq);
+            H[(size_t)(al - HOFF) * a.N + n] = (HS)heq;
+        });
+    } else {
+        // mu_phi(phi0) with the same stencil and ghost rules as the step
+        double lap = 0.0;
+        unroll<GL::Q>([&](auto I) {
+            constexpr int i = I;
+            if constexpr (i > 0) {
+                const int gx = ghost_coord(x + GL::c(i, 0), a.nx, a.bc[0]);
+                const int gy = ghost_coord(y + GL::c(i, 1), a.ny, a.bc[1]);
+                const int gz = ghost_coord(z + GL::c(i, 2), a.nz, a.bc[2]);
+                lap += 6.0 * GL::w(i) * (a.phi0[((long long)gz * a.ny + gy) * a.nx + gx] - phi);
+            }
+        });
+        const double mu = ph.beta4 * phi * (phi - 1.0) * (phi - 0.5) - ph.kappa * lap;
+        unroll<HL::Q>([&](auto J) {
+            constexpr int al = J;
+            double heq;
+            if constexpr (al == 0) {
+                heq = phi + (HL::w(0) - 1.0) * ph.eta * mu;
+            } else {
+                const double ep = HL::c(al, 0) * phi * u[0] + HL::c(al, 1) * phi * u[1] +
+                                  HL::c(al, 2) * phi * u[2];
+                heq = HL::w(al) * ph.eta * mu + 3.0 * HL::w(al) * ep;
+            }
+            H[(size_t)al * a.N + n] = (HS)heq;
+        });
+        T* PU = (T*)a.phiu;
+        PU[n] = (T)(phi * u[0]);
+        PU[a.N + n] = (T)(phi * u[1]);
+        PU[2 * a.N + n] = (T)(phi * u[2]);
+    }
+}
+
+// ----------------------------------------------------------------------------
+// canonical float64 I/O
+
+template <class PAIR, int MODEL, int PREC>
+__global__ __launch_bounds__(256) void k_get(const IOArgs a) {
+    using GL = typename PAIR::G;
+    using HL = typename PAIR::H;
+    using T = typename Types<PREC>::T;
+    using GS = typename Types<PREC>::GS;
+    using HS = typename Types<PREC>::HS;
+    using GC = GCodec<PREC>;
+    constexpr bool D3 = PAIR::dim == 3;
+    constexpr int HOFF = (MODEL == 0 && D3) ? 1 : 0;
+    const long long nn = (long long)a.nx * a.ny * a.nz;
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    const int x = (int)(n % a.nx), y = (int)((n / a.nx) % a.ny), z = (int)(n / ((long long)a.nx * a.ny));
+    const GS* G = (const GS*)a.g;
+    const HS* H = (const HS*)a.h;
+    unroll<GL::Q>([&](auto I) {
+        constexpr int i = I;
+        T v;
+        if (a.parity == 0) {
+            v = GC::template dec<GL, i, GS, T>(G[(size_t)i * a.N + n]);
+        } else {
+            int nb, side;
+            if (shifted<GL, i, -1>(a.nx, a.ny, a.nz, a.bc, x, y, z, nb, side)) {
+                v = GC::template dec<GL, i, GS, T>(G[(size_t)i * a.N + n]) +
+                    (T)a.gcorr[side][GL::opp(i)];
+            } else {
+                constexpr int o = GL::opp(i);
+                v = GC::template dec<GL, o, GS, T>(G[(size_t)o * a.N + nb]);
+            }
+        }
+        a.cg[(size_t)i * nn + n] = (double)v;
+    });
+    unroll<HL::Q>([&](auto J) {
+        constexpr int al = J;
+        if constexpr (al < HOFF) a.ch[(size_t)al * nn + n] = 0.0;
+        else a.ch[(size_t)al * nn + n] = (double)H[(size_t)(al - HOFF) * a.N + n];
+    });
+}
+
+template <class PAIR, int MODEL, int PREC>
+__global__ __launch_bounds__(256) void k_set(const IOArgs a) {
+    using GL = typename PAIR::G;
+    using HL = typename PAIR::H;
+    using T = typename Types<PREC>::T;
+    using GS = typename Types<PREC>::GS;
+    using HS = typename Types<PREC>::HS;
+    using GC = GCodec<PREC>;
+    constexpr bool D3 = PAIR::dim == 3;
+    constexpr int HOFF = (MODEL == 0 && D3) ? 1 : 0;
+    const long long nn = (long long)a.nx * a.ny * a.nz;
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    GS* G = (GS*)a.g;
+    HS* H = (HS*)a.h;
+    unroll<GL::Q>([&](auto I) {
+        constexpr int i = I;
+        G[(size_t)i * a.N + n] = GC::template enc<GL, i, GS, T>((T)a.cg[(size_t)i * nn + n]);
+    });
+    unroll<HL::Q - HOFF>([&](auto J) {
+        constexpr int al = J + HOFF;
+        H[(size_t)(al - HOFF) * a.N + n] = (HS)a.ch[(size_t)al * nn + n];
+    });
+}
+
+// ----------------------------------------------------------------------------
+// dispatch
+
+template <class PAIR, int MODEL, int PREC, int PARITY>
+static hipError_t step_mode(int mode, const KArgs& a, hipStream_t s) {
+    const dim3 grid((unsigned)(a.ntx * a.nty * a.ntz)), block(BLOCK);
+    switch (mode) {
+        case MODE_STEP:
+            hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, PARITY, MODE_STEP>), grid, block, 0, s, a);
+            break;
+        case MODE_FIELDS:
+            hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, PARITY, MODE_FIELDS>), grid, block, 0, s, a);
+            break;
+        default:
+            hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, PARITY, MODE_DIAG>), grid, block, 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+template <class PAIR, int MODEL, int PREC>
+static hipError_t step_parity(int parity, int mode, const KArgs& a, hipStream_t s) {
+    return parity ? step_mode<PAIR, MODEL, PREC, 1>(mode, a, s)
+                  : step_mode<PAIR, MODEL, PREC, 0>(mode, a, s);
+}
+
+template <class PAIR, int MODEL>
+static hipError_t step_prec(int prec, int parity, int mode, const KArgs& a, hipStream_t s) {
+    switch (prec) {
+        case 0: return step_parity<PAIR, MODEL, 0>(parity, mode, a, s);
+        case 1: return step_parity<PAIR, MODEL, 1>(parity, mode, a, s);
+        case 2: return step_parity<PAIR, MODEL, 2>(parity, mode, a, s);
+        default: return step_parity<PAIR, MODEL, 3>(parity, mode, a, s);
+    }
+}
+
+hipError_t launch_step(int lattice, int model, int precision, int parity, int mode,
+                       const KArgs& a, hipStream_t s) {
+    if (lattice == 0)
+        return model ? step_prec<Pair2D, 1>(precision, parity, mode, a, s)
+                     : step_prec<Pair2D, 0>(precision, parity, mode, a, s);
+    return model ? step_prec<Pair3D, 1>(precision, parity, mode, a, s)
+                 : step_prec<Pair3D, 0>(precision, parity, mode, a, s);
+}
+
+#define PFLBM_NODE_DISPATCH(KERNEL, ARGS, NN)                                               \
+    do {                                                                                     \
+        const dim3 grid((unsigned)(((NN) + 255) / 256)), block(256);                          \
+        auto go = [&](auto pair, auto md, auto pr) {                                         \
+            using P_ = decltype(pair);                                                       \
+            constexpr int M_ = decltype(md)::value, R_ = decltype(pr)::value;                \
+            hipLaunchKernelGGL((KERNEL<P_, M_, R_>), grid, block, 0, s, ARGS);               \
+        };                                                                                   \
+        auto prec = [&](auto pair, auto md) {                                                \
+            switch (precision) {                                                             \
+                case 0: go(pair, md, std::integral_constant<int, 0>{}); break;              \
+                case 1: go(pair, md, std::integral_constant<int, 1>{}); break;              \
+                case 2: go(pair, md, std::integral_constant<int, 2>{}); break;              \
+                default: go(pair, md, std::integral_constant<int, 3>{});                    \
+            }                                                                                \
+        };                                                                                   \
+        auto mdl = [&](auto pair) {                                                          \
+            if (model) prec(pair, std::integral_constant<int, 1>{});                         \
+            else prec(pair, std::integral_constant<int, 0>{});                               \
+        };                                                                                   \
+        if (lattice == 0) mdl(Pair2D{});                                                     \
+        else mdl(Pair3D{});                                                                  \
+    } while (0)
+
+hipError_t launch_init(int lattice, int model, int precision, const InitArgs& a, hipStream_t s) {
+    const long long nn = (long long)a.nx * a.ny * a.nz;
+    PFLBM_NODE_DISPATCH(k_init, a, nn);
+    return hipGetLastError();
+}
+
+hipError_t launch_get(int lattice, int model, int precision, const IOArgs& a, hipStream_t s) {
+    const long long nn = (long long)a.nx * a.ny * a.nz;
+    PFLBM_NODE_DISPATCH(k_get, a, nn);
+    return hipGetLastError();
+}
+
+hipError_t launch_set(int lattice, int model, int precision, const IOArgs& a, hipStream_t s) {
+    const long long nn = (long long)a.nx * a.ny * a.nz;
+    PFLBM_NODE_DISPATCH(k_set, a, nn);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double* partials, int nblocks, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(BLOCK), 0, s, partials, nblocks, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_header(void* dst, long long steps, int parity, int hcur, hipStream_t s) {
+    hipLaunchKernelGGL(k_header, dim3(1), dim3(64), 0, s, (long long*)dst, steps, parity, hcur);
+    return hipGetLastError();
+}
+
+}  // namespace pfk

@@ -1,0 +1,478 @@
+// C ABI of libpflbm (declared in include/pflbm.h): validation, device-state
+// layout inside the caller's buffer, in-place streaming parity bookkeeping and
+// kernel launch orchestration. All arithmetic of the method runs in the
+// kernels (kernels.hip); this file only sets up their arguments.
+#include "pflbm.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "internal.h"
+#include "lattice.h"
+
+using namespace pfk;
+
+namespace {
+
+struct Layout {
+    int dim = 0, Qg = 0, Qh = 0, Qhs = 0;
+    size_t sg = 0, sh = 0, sT = 0;   // bytes per stored g, h, compute value
+    long long nodes = 0, N = 0;      // nodes, population stride
+    int ntx = 0, nty = 0, ntz = 0, zb = 0, nblocks = 0;
+    size_t off_g = 0, off_h[2] = {0, 0}, off_pu = 0, off_part = 0, off_res = 0, total = 0;
+    size_t ck_g = 0, ck_h = 0, ck_pu = 0, ck_total = 0;
+};
+
+constexpr size_t ALIGN = 4096;
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+bool finite(double v) { return std::isfinite(v); }
+
+// validate; returns an error message or empty string
+std::string validate(const pflbm_params& p) {
+    if (p.lattice != PFLBM_D2Q9_D2Q5 && p.lattice != PFLBM_D3Q19_D3Q7) return "lattice must be PFLBM_D2Q9_D2Q5 or PFLBM_D3Q19_D3Q7";
+    if (p.model != PFLBM_AC && p.model != PFLBM_CH) return "model must be PFLBM_AC or PFLBM_CH";
+    if (p.precision < PFLBM_FP64 || p.precision > PFLBM_MIXED_BF16) return "unknown precision";
+    if (p.nx < 1 || p.ny < 1 || p.nz < 1) return "nx, ny, nz must be >= 1";
+    if (p.lattice == PFLBM_D2Q9_D2Q5 && p.nz != 1) return "2-D lattice requires nz == 1";
+    const long long nodes = (long long)p.nx * p.ny * p.nz;
+    if (nodes > 0x7fffffffLL) return "more than 2^31-1 nodes";
+    {
+        // kernels address a population pair through 32-bit byte offsets
+        const long long es = p.precision == PFLBM_FP64 ? 8 : 4;
+        if ((nodes + 128) * 3 * es >= 0xffffffffLL) return "too many nodes for this precision";
+    }
+    int walls = 0;
+    for (int a = 0; a < 3; ++a) {
+        if (p.bc[a] != PFLBM_PERIODIC && p.bc[a] != PFLBM_WALL) return "bc must be PFLBM_PERIODIC or PFLBM_WALL";
+        walls += p.bc[a] == PFLBM_WALL;
+    }
+    if (walls > 1) return "walls on more than one axis are not supported";
+    if (p.lattice == PFLBM_D2Q9_D2Q5 && p.bc[2] != PFLBM_PERIODIC) return "2-D lattice requires a periodic z axis";
+    for (int s = 0; s < 2; ++s)
+        for (int a = 0; a < 3; ++a) {
+            if (!finite(p.wall_u[s][a])) return "wall velocity not finite";
+            if (p.bc[a] == PFLBM_WALL && p.wall_u[s][a] != 0.0) return "wall velocity must be tangential to the wall";
+            if (p.lattice == PFLBM_D2Q9_D2Q5 && a == 2 && p.wall_u[s][a] != 0.0) return "2-D wall velocity has a z component";
+        }
+    if (!(p.rho_H > 0) || !(p.rho_L > 0) || !finite(p.rho_H) || !finite(p.rho_L)) return "rho_H and rho_L must be > 0";
+    if (!(p.nu_H > 0) || !(p.nu_L > 0) || !finite(p.nu_H) || !finite(p.nu_L)) return "nu_H and nu_L must be > 0 (tau > 1/2)";
+    if (p.visc_interp != PFLBM_VISC_LINEAR_MU && p.visc_interp != PFLBM_VISC_LINEAR_NU) return "unknown viscosity interpolation";
+    if (!(p.M > 0) || !finite(p.M)) return "M must be > 0";
+    if (!(p.W > 0) || !finite(p.W)) return "W must be > 0";
+    if (!(p.sigma >= 0) || !finite(p.sigma)) return "sigma must be >= 0";
+    if (!(p.eta > 0) || !finite(p.eta)) return "eta must be > 0";
+    if (!(p.s_other > 0 && p.s_other < 2)) return "s_other must be in (0, 2)";
+    if (!(p.normal_eps >= 0) || !finite(p.normal_eps)) return "normal_eps must be >= 0";
+    for (int a = 0; a < 3; ++a)
+        if (!finite(p.gravity[a]) || !finite(p.force[a])) return "body force not finite";
+    if (p.lattice == PFLBM_D2Q9_D2Q5 && (p.gravity[2] != 0.0 || p.force[2] != 0.0)) return "2-D body force has a z component";
+    if (p.check_interval < 0) return "check_interval must be >= 0";
+    if (p.zblock < 0) return "zblock must be >= 0";
+    return "";
+}
+
+Layout make_layout(const pflbm_params& p) {
+    Layout L;
+    const bool d3 = p.lattice == PFLBM_D3Q19_D3Q7;
+    L.dim = d3 ? 3 : 2;
+    L.Qg = d3 ? 19 : 9;
+    L.Qh = d3 ? 7 : 5;
+    L.Qhs = (d3 && p.model == PFLBM_AC) ? 6 : L.Qh;   // AC on D3Q7: rest population is zero
+    L.sT = p.precision == PFLBM_FP64 ? 8 : 4;
+    L.sg = p.precision == PFLBM_FP64 ? 8 : (p.precision == PFLBM_FP32 ? 4 : 2);
+    L.sh = p.precision == PFLBM_FP64 ? 8 : 4;
+    L.nodes = (long long)p.nx * p.ny * p.nz;
+    L.N = (long long)align_up((size_t)L.nodes, 128);
+    L.ntx = (p.nx + TILE_X - 1) / TILE_X;
+    L.nty = (p.ny + TILE_Y - 1) / TILE_Y;
+    if (d3) {
+        L.zb = p.zblock > 0 ? p.zblock : 16;
+        if (L.zb > p.nz) L.zb = p.nz;
+    } else {
+        L.zb = 1;
+    }
+    L.ntz = (p.nz + L.zb - 1) / L.zb;
+    L.nblocks = L.ntx * L.nty * L.ntz;
+    size_t off = 0;
+    L.off_g = off;
+    off = align_up(off + (size_t)L.Qg * L.N * L.sg, ALIGN);
+    for (int k = 0; k < 2; ++k) {
+        L.off_h[k] = off;
+        off = align_up(off + (size_t)L.Qhs * L.N * L.sh, ALIGN);
+    }
+    L.off_pu = off;
+    if (p.model == PFLBM_CH) off = align_up(off + 3 * (size_t)L.N * L.sT, ALIGN);
+    L.off_part = off;
+    off = align_up(off + (size_t)L.nblocks * NDIAG * sizeof(double), ALIGN);
+    L.off_res = off;
+    off = align_up(off + 64 * sizeof(double), ALIGN);
+    L.total = off;
+    // checkpoint: 256-byte header, g, current h, (phi u)
+    L.ck_g = 256;
+    L.ck_h = align_up(L.ck_g + (size_t)L.Qg * L.N * L.sg, 256);
+    L.ck_pu = align_up(L.ck_h + (size_t)L.Qhs * L.N * L.sh, 256);
+    L.ck_total = align_up(L.ck_pu + (p.model == PFLBM_CH ? 3 * (size_t)L.N * L.sT : 0), 256);
+    return L;
+}
+
+template <class GL>
+void wall_terms(const pflbm_params& p, double gcorr[2][MAXQ]) {
+    for (int s = 0; s < 2; ++s)
+        for (int i = 0; i < MAXQ; ++i) gcorr[s][i] = 0.0;
+    for (int s = 0; s < 2; ++s)
+        for (int i = 0; i < GL::Q; ++i) {
+            // population i leaving through wall s: -2 w_i (c_i . u_w) / c_s^2
+            const double cu = GL::c(i, 0) * p.wall_u[s][0] + GL::c(i, 1) * p.wall_u[s][1] +
+                              GL::c(i, 2) * p.wall_u[s][2];
+            gcorr[s][i] = -6.0 * GL::w(i) * cu;
+        }
+}
+
+}  // namespace
+
+struct pflbm {
+    pflbm_params p;
+    Layout L;
+    hipStream_t stream = nullptr;
+    char* base = nullptr;
+    int device = 0;
+    int hcur = 0, parity = 0;
+    long long steps = 0;
+    bool initialised = false;
+    int sticky = 0;
+    std::string err;
+    Phys ph;
+    PhysT<float> phf;
+    double gcorr[2][MAXQ];
+    float gcorrf[2][MAXQ];
+    int wall_axis = -1;
+    double res_host[NDIAG];
+};
+
+namespace {
+
+int fail(pflbm_t* h, int code, const std::string& msg) {
+    if (h) {
+        h->err = msg;
+        if (code != PFLBM_EINVAL && code != PFLBM_EUNSTABLE) h->sticky = code;
+    }
+    return code;
+}
+
+int hip_fail(pflbm_t* h, hipError_t e, const char* where) {
+    return fail(h, PFLBM_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(h, call, where)                       \
+    do {                                             \
+        hipError_t e_ = (call);                      \
+        if (e_ != hipSuccess) return hip_fail(h, e_, where); \
+    } while (0)
+
+int guard(pflbm_t* h) {
+    if (!h) return PFLBM_EINVAL;
+    if (h->sticky) return PFLBM_ESTATE;
+    return PFLBM_OK;
+}
+
+void base_args(pflbm_t* h, KArgs& a) {
+    std::memset(&a, 0, sizeof(a));
+    a.g = h->base + h->L.off_g;
+    a.hin = h->base + h->L.off_h[h->hcur];
+    a.hout = h->base + h->L.off_h[1 - h->hcur];
+    a.phiu = h->base + h->L.off_pu;
+    a.partials = (double*)(h->base + h->L.off_part);
+    a.N = h->L.N;
+    a.nx = h->p.nx;
+    a.ny = h->p.ny;
+    a.nz = h->p.nz;
+    a.ntx = h->L.ntx;
+    a.nty = h->L.nty;
+    a.ntz = h->L.ntz;
+    a.zb = h->L.zb;
+    for (int k = 0; k < 3; ++k) a.bc[k] = h->p.bc[k];
+    a.wall_axis = h->wall_axis;
+    a.write_h = h->p.freeze_phi ? 0 : 1;
+    std::memcpy(a.gcorr, h->gcorr, sizeof(a.gcorr));
+    std::memcpy(a.gcorrf, h->gcorrf, sizeof(a.gcorrf));
+    a.ph = h->ph;
+    a.phf = h->phf;
+}
+
+int run_diag(pflbm_t* h, const double* centre, double R, double* res) {
+    KArgs a;
+    base_args(h, a);
+    if (centre) {
+        a.has_centre = 1;
+        for (int k = 0; k < h->L.dim; ++k) a.centre[k] = centre[k];
+        a.r_in = R - 2.0 * h->p.W;
+        a.r_out = R + 2.0 * h->p.W;
+    }
+    HIPCHK(h, launch_step(h->p.lattice, h->p.model, h->p.precision, h->parity, MODE_DIAG, a, h->stream), "diag kernel");
+    double* dres = (double*)(h->base + h->L.off_res);
+    HIPCHK(h, launch_reduce(a.partials, h->L.nblocks, dres, h->stream), "reduce kernel");
+    HIPCHK(h, hipMemcpyAsync(res, dres, NDIAG * sizeof(double), hipMemcpyDeviceToHost, h->stream), "diag copy");
+    HIPCHK(h, hipStreamSynchronize(h->stream), "diag sync");
+    return PFLBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pflbm_strerror(int status) {
+    switch (status) {
+        case PFLBM_OK: return "ok";
+        case PFLBM_EINVAL: return "invalid argument";
+        case PFLBM_EUNSUPPORTED: return "unsupported";
+        case PFLBM_EHIP: return "HIP runtime error";
+        case PFLBM_EUNSTABLE: return "numerical instability (NaN/Inf or rho <= 0)";
+        case PFLBM_ESTATE: return "handle in error state";
+        default: return "unknown status";
+    }
+}
+
+int pflbm_state_bytes(const pflbm_params* params, size_t* bytes) {
+    if (!params || !bytes) return PFLBM_EINVAL;
+    if (!validate(*params).empty()) return PFLBM_EINVAL;
+    *bytes = make_layout(*params).total;
+    return PFLBM_OK;
+}
+
+int pflbm_create(const pflbm_params* params, void* hip_stream, void* dev_state, size_t bytes,
+                 pflbm_t** out) {
+    if (!params || !out) return PFLBM_EINVAL;
+    *out = nullptr;
+    if (!validate(*params).empty()) return PFLBM_EINVAL;
+    const Layout L = make_layout(*params);
+    if (!dev_state || bytes < L.total || ((uintptr_t)dev_state % 256) != 0) return PFLBM_EINVAL;
+    pflbm_t* h = new (std::nothrow) pflbm();
+    if (!h) return PFLBM_EINVAL;
+    h->p = *params;
+    h->L = L;
+    h->stream = (hipStream_t)hip_stream;
+    h->base = (char*)dev_state;
+    hipGetDevice(&h->device);
+    const pflbm_params& p = h->p;
+    for (int a = 0; a < 3; ++a)
+        if (p.bc[a] == PFLBM_WALL) h->wall_axis = a;
+    if (p.lattice == PFLBM_D2Q9_D2Q5) wall_terms<D2Q9>(p, h->gcorr);
+    else wall_terms<D3Q19>(p, h->gcorr);
+    Phys& ph = h->ph;
+    ph.rhoL = p.rho_L;
+    ph.dRho = p.rho_H - p.rho_L;
+    ph.muL = p.rho_L * p.nu_L;
+    ph.dMu = p.rho_H * p.nu_H - p.rho_L * p.nu_L;
+    ph.nuL = p.nu_L;
+    ph.dNu = p.nu_H - p.nu_L;
+    ph.visc_mu = p.visc_interp == PFLBM_VISC_LINEAR_MU;
+    ph.beta4 = 4.0 * 12.0 * p.sigma / p.W;   // 4 beta, beta = 12 sigma / W
+    ph.kappa = 1.5 * p.sigma * p.W;          // kappa = 3 sigma W / 2
+    ph.anti = 4.0 / p.W;                     // sqrt(2 beta / kappa)
+    ph.eps2 = p.normal_eps * p.normal_eps;
+    const double tau_phi = p.model == PFLBM_CH ? 3.0 * p.M / p.eta + 0.5 : 3.0 * p.M + 0.5;
+    ph.inv_tau_phi = 1.0 / tau_phi;
+    ph.g_fac_phi = 1.0 - 0.5 / tau_phi;
+    ph.eta = p.eta;
+    ph.s_o = p.s_other;
+    for (int a = 0; a < 3; ++a) {
+        ph.body[a] = p.gravity[a];
+        ph.force[a] = p.force[a];
+    }
+    h->phf = to_float(ph);
+    for (int s = 0; s < 2; ++s)
+        for (int i = 0; i < MAXQ; ++i) h->gcorrf[s][i] = (float)h->gcorr[s][i];
+    *out = h;
+    return PFLBM_OK;
+}
+
+void pflbm_destroy(pflbm_t* h) { delete h; }
+
+const char* pflbm_last_error(const pflbm_t* h) { return h ? h->err.c_str() : "null handle"; }
+
+int pflbm_init(pflbm_t* h, const double* phi0, const double* u0, const double* p0) {
+    int st = guard(h);
+    if (st) return st;
+    if (!phi0) return fail(h, PFLBM_EINVAL, "phi0 is null");
+    InitArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.g = h->base + h->L.off_g;
+    a.h = h->base + h->L.off_h[0];
+    a.phiu = h->base + h->L.off_pu;
+    a.phi0 = phi0;
+    a.u0 = u0;
+    a.p0 = p0;
+    a.N = h->L.N;
+    a.nx = h->p.nx;
+    a.ny = h->p.ny;
+    a.nz = h->p.nz;
+    for (int k = 0; k < 3; ++k) a.bc[k] = h->p.bc[k];
+    a.ph = h->ph;
+    HIPCHK(h, launch_init(h->p.lattice, h->p.model, h->p.precision, a, h->stream), "init kernel");
+    h->hcur = 0;
+    h->parity = 0;
+    h->steps = 0;
+    h->initialised = true;
+    return PFLBM_OK;
+}
+
+int pflbm_step(pflbm_t* h, int nsteps) {
+    int st = guard(h);
+    if (st) return st;
+    if (nsteps < 0) return fail(h, PFLBM_EINVAL, "nsteps < 0");
+    if (!h->initialised) return fail(h, PFLBM_EINVAL, "pflbm_init not called");
+    KArgs a;
+    base_args(h, a);
+    for (int k = 0; k < nsteps; ++k) {
+        a.hin = h->base + h->L.off_h[h->hcur];
+        a.hout = h->base + h->L.off_h[1 - h->hcur];
+        HIPCHK(h, launch_step(h->p.lattice, h->p.model, h->p.precision, h->parity, MODE_STEP, a, h->stream), "step kernel");
+        if (!h->p.freeze_phi) h->hcur ^= 1;
+        h->parity ^= 1;
+        h->steps += 1;
+        if (h->p.check_interval > 0 && h->steps % h->p.check_interval == 0) {
+            st = run_diag(h, nullptr, 0.0, h->res_host);
+            if (st) return st;
+            if (h->res_host[10] > 0.0) {
+                char buf[128];
+                std::snprintf(buf, sizeof(buf), "NaN/Inf or rho <= 0 detected after step %lld", h->steps);
+                return fail(h, PFLBM_EUNSTABLE, buf);
+            }
+        }
+    }
+    return PFLBM_OK;
+}
+
+int pflbm_fields(pflbm_t* h, double* phi, double* u, double* p, double* rho) {
+    int st = guard(h);
+    if (st) return st;
+    if (!h->initialised) return fail(h, PFLBM_EINVAL, "pflbm_init not called");
+    KArgs a;
+    base_args(h, a);
+    a.f_phi = phi;
+    a.f_u = u;
+    a.f_p = p;
+    a.f_rho = rho;
+    HIPCHK(h, launch_step(h->p.lattice, h->p.model, h->p.precision, h->parity, MODE_FIELDS, a, h->stream), "fields kernel");
+    return PFLBM_OK;
+}
+
+int pflbm_volume(pflbm_t* h, const double* centre, double R, pflbm_diag* out) {
+    int st = guard(h);
+    if (st) return st;
+    if (!out) return fail(h, PFLBM_EINVAL, "out is null");
+    if (!h->initialised) return fail(h, PFLBM_EINVAL, "pflbm_init not called");
+    st = run_diag(h, centre, R, h->res_host);
+    if (st) return st;
+    const double* r = h->res_host;
+    out->V_phi = r[0];
+    out->V_count = r[1];
+    out->sum_phi = r[2];
+    out->phi_min = r[3];
+    out->phi_max = r[4];
+    out->umax = std::sqrt(r[5]);
+    out->n_in = (long long)r[7];
+    out->n_out = (long long)r[9];
+    out->p_in = r[7] > 0 ? r[6] / r[7] : NAN;
+    out->p_out = r[9] > 0 ? r[8] / r[9] : NAN;
+    out->unstable = r[10] > 0.0 ? 1 : 0;
+    return PFLBM_OK;
+}
+
+static void io_args(pflbm_t* h, IOArgs& a) {
+    std::memset(&a, 0, sizeof(a));
+    a.g = h->base + h->L.off_g;
+    a.h = h->base + h->L.off_h[h->hcur];
+    a.N = h->L.N;
+    a.nx = h->p.nx;
+    a.ny = h->p.ny;
+    a.nz = h->p.nz;
+    for (int k = 0; k < 3; ++k) a.bc[k] = h->p.bc[k];
+    a.wall_axis = h->wall_axis;
+    a.parity = h->parity;
+    std::memcpy(a.gcorr, h->gcorr, sizeof(a.gcorr));
+}
+
+int pflbm_get_distributions(pflbm_t* h, double* g, double* hd) {
+    int st = guard(h);
+    if (st) return st;
+    if (!g || !hd) return fail(h, PFLBM_EINVAL, "null output");
+    if (!h->initialised) return fail(h, PFLBM_EINVAL, "pflbm_init not called");
+    IOArgs a;
+    io_args(h, a);
+    a.cg = g;
+    a.ch = hd;
+    HIPCHK(h, launch_get(h->p.lattice, h->p.model, h->p.precision, a, h->stream), "get kernel");
+    return PFLBM_OK;
+}
+
+int pflbm_set_distributions(pflbm_t* h, const double* g, const double* hd) {
+    int st = guard(h);
+    if (st) return st;
+    if (!g || !hd) return fail(h, PFLBM_EINVAL, "null input");
+    if (!h->initialised) return fail(h, PFLBM_EINVAL, "pflbm_init not called");
+    IOArgs a;
+    io_args(h, a);
+    a.cg = (double*)g;
+    a.ch = (double*)hd;
+    HIPCHK(h, launch_set(h->p.lattice, h->p.model, h->p.precision, a, h->stream), "set kernel");
+    h->parity = 0;
+    return PFLBM_OK;
+}
+
+int pflbm_step_count(const pflbm_t* h, long long* steps) {
+    if (!h || !steps) return PFLBM_EINVAL;
+    *steps = h->steps;
+    return PFLBM_OK;
+}
+
+int pflbm_checkpoint_bytes(const pflbm_t* h, size_t* bytes) {
+    if (!h || !bytes) return PFLBM_EINVAL;
+    *bytes = h->L.ck_total;
+    return PFLBM_OK;
+}
+
+int pflbm_save_state(pflbm_t* h, void* dev_dst) {
+    int st = guard(h);
+    if (st) return st;
+    if (!dev_dst) return fail(h, PFLBM_EINVAL, "null destination");
+    if (!h->initialised) return fail(h, PFLBM_EINVAL, "pflbm_init not called");
+    char* d = (char*)dev_dst;
+    const Layout& L = h->L;
+    HIPCHK(h, launch_header(d, h->steps, h->parity, 0, h->stream), "header kernel");
+    HIPCHK(h, hipMemcpyAsync(d + L.ck_g, h->base + L.off_g, (size_t)L.Qg * L.N * L.sg, hipMemcpyDeviceToDevice, h->stream), "save g");
+    HIPCHK(h, hipMemcpyAsync(d + L.ck_h, h->base + L.off_h[h->hcur], (size_t)L.Qhs * L.N * L.sh, hipMemcpyDeviceToDevice, h->stream), "save h");
+    if (h->p.model == PFLBM_CH)
+        HIPCHK(h, hipMemcpyAsync(d + L.ck_pu, h->base + L.off_pu, 3 * (size_t)L.N * L.sT, hipMemcpyDeviceToDevice, h->stream), "save phiu");
+    return PFLBM_OK;
+}
+
+int pflbm_load_state(pflbm_t* h, const void* dev_src) {
+    int st = guard(h);
+    if (st) return st;
+    if (!dev_src) return fail(h, PFLBM_EINVAL, "null source");
+    const char* s = (const char*)dev_src;
+    const Layout& L = h->L;
+    long long hdr[4];
+    HIPCHK(h, hipMemcpyAsync(hdr, s, sizeof(hdr), hipMemcpyDeviceToHost, h->stream), "load header");
+    HIPCHK(h, hipStreamSynchronize(h->stream), "load sync");
+    if (hdr[0] != 0x70666c626dLL) return fail(h, PFLBM_EINVAL, "not a pflbm checkpoint");
+    HIPCHK(h, hipMemcpyAsync(h->base + L.off_g, s + L.ck_g, (size_t)L.Qg * L.N * L.sg, hipMemcpyDeviceToDevice, h->stream), "load g");
+    HIPCHK(h, hipMemcpyAsync(h->base + L.off_h[0], s + L.ck_h, (size_t)L.Qhs * L.N * L.sh, hipMemcpyDeviceToDevice, h->stream), "load h");
+    if (h->p.model == PFLBM_CH)
+        HIPCHK(h, hipMemcpyAsync(h->base + L.off_pu, s + L.ck_pu, 3 * (size_t)L.N * L.sT, hipMemcpyDeviceToDevice, h->stream), "load phiu");
+    h->steps = hdr[1];
+    h->parity = (int)hdr[2];
+    h->hcur = 0;
+    h->initialised = true;
+    return PFLBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,120 @@
+"""Device-side driver of one solver instance: PyTorch provides the device
+buffer and the stream; every computation runs in libpflbm's kernels."""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import pflbm as P
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Solver:
+    """One coupled PF-LB state on the current CUDA (HIP) device.
+
+    params: workload dict (see workloads.base_params); precision: "fp64",
+    "fp32", "mixed_fp16" or "mixed_bf16"."""
+
+    def __init__(self, params, precision="fp64", check_interval=0, zblock=0, device=None,
+                 stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libpflbm needs a GPU; none is visible")
+        self.d = dict(params)
+        self.precision = precision
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.p = P.make_params(self.d, precision, check_interval, zblock)
+        self.L = P.lib()
+        nb = ctypes.c_size_t()
+        self._check(self.L.pflbm_state_bytes(ctypes.byref(self.p), ctypes.byref(nb)), None)
+        self.state = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        self._check(self.L.pflbm_create(ctypes.byref(self.p), ctypes.c_void_p(self.stream.cuda_stream),
+                                        _ptr(self.state), nb, ctypes.byref(h)), None)
+        self.h = h
+        self.dim = 2 if self.d["lattice"] == "D2Q9_D2Q5" else 3
+        self.shape = (int(self.d["nz"]), int(self.d["ny"]), int(self.d["nx"]))
+        self.Qg, self.Qh = (9, 5) if self.dim == 2 else (19, 7)
+
+    def _check(self, st, h):
+        if st != P.PFLBM_OK:
+            msg = self.L.pflbm_last_error(h).decode() if h else ""
+            raise P.PflbmError(st, msg)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.pflbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dev(self, a, shape):
+        if a is None:
+            return None
+        t = torch.as_tensor(np.asarray(a) if not torch.is_tensor(a) else a)
+        t = t.to(device=self.device, dtype=torch.float64).contiguous()
+        if tuple(t.shape) != tuple(shape):
+            t = t.reshape(shape)
+        return t
+
+    def init(self, phi0, u0=None, p0=None):
+        phi = self._dev(phi0, self.shape)
+        u = self._dev(u0, (self.dim,) + self.shape)
+        pr = self._dev(p0, self.shape)
+        self._keep = (phi, u, pr)   # alive until the stream has consumed them
+        self._check(self.L.pflbm_init(self.h, _ptr(phi), _ptr(u), _ptr(pr)), self.h)
+
+    def step(self, n=1):
+        self._check(self.L.pflbm_step(self.h, int(n)), self.h)
+
+    def fields(self):
+        phi = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        u = torch.empty((self.dim,) + self.shape, dtype=torch.float64, device=self.device)
+        p = torch.empty_like(phi)
+        rho = torch.empty_like(phi)
+        self._check(self.L.pflbm_fields(self.h, _ptr(phi), _ptr(u), _ptr(p), _ptr(rho)), self.h)
+        return phi, u, p, rho
+
+    def volume(self, centre=None, R=0.0):
+        out = P.pflbm_diag()
+        c = (ctypes.c_double * 3)(*(list(centre) + [0.0] * (3 - len(centre)))) if centre is not None else None
+        self._check(self.L.pflbm_volume(self.h, c, float(R), ctypes.byref(out)), self.h)
+        return {k: getattr(out, k) for k, _ in P.pflbm_diag._fields_}
+
+    def get_distributions(self):
+        g = torch.empty((self.Qg,) + self.shape, dtype=torch.float64, device=self.device)
+        h = torch.empty((self.Qh,) + self.shape, dtype=torch.float64, device=self.device)
+        self._check(self.L.pflbm_get_distributions(self.h, _ptr(g), _ptr(h)), self.h)
+        return g, h
+
+    def set_distributions(self, g, h):
+        g = self._dev(g, (self.Qg,) + self.shape)
+        h = self._dev(h, (self.Qh,) + self.shape)
+        self._keep = (g, h)
+        self._check(self.L.pflbm_set_distributions(self.h, _ptr(g), _ptr(h)), self.h)
+
+    def step_count(self):
+        n = ctypes.c_longlong()
+        self._check(self.L.pflbm_step_count(self.h, ctypes.byref(n)), self.h)
+        return n.value
+
+    def checkpoint_bytes(self):
+        n = ctypes.c_size_t()
+        self._check(self.L.pflbm_checkpoint_bytes(self.h, ctypes.byref(n)), self.h)
+        return n.value
+
+    def save_state(self, buf=None):
+        if buf is None:
+            buf = torch.empty(self.checkpoint_bytes(), dtype=torch.uint8, device=self.device)
+        self._check(self.L.pflbm_save_state(self.h, _ptr(buf)), self.h)
+        return buf
+
+    def load_state(self, buf):
+        self._check(self.L.pflbm_load_state(self.h, _ptr(buf)), self.h)

@@ -1,0 +1,91 @@
+"""The C-ABI library loads and exports every symbol include/pflbm.h declares;
+host-side validation rejects invalid parameters (no GPU call is made)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2511_11360_amd import pflbm as P
+from paper_2511_11360_amd import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pflbm.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pflbm_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = P.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+        assert n in P.SIGNATURES, "binding lacks " + n
+
+
+def test_struct_layout_matches_header(tmp_path):
+    """ctypes structures have the C compiler's size and field offsets."""
+    prog = ["#include <stdio.h>", "#include <stddef.h>", '#include "pflbm.h"', "int main(void){"]
+    for S in (P.pflbm_params, P.pflbm_diag):
+        prog.append('printf("%%zu\\n", sizeof(%s));' % S.__name__)
+        for f, _ in S._fields_:
+            prog.append('printf("%%zu\\n", offsetof(%s, %s));' % (S.__name__, f))
+    prog.append("return 0;}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(prog))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    exp = []
+    for S in (P.pflbm_params, P.pflbm_diag):
+        exp.append(ctypes.sizeof(S))
+        exp.extend(getattr(S, f).offset for f, _ in S._fields_)
+    assert got == exp
+
+
+def _bytes(d, **kw):
+    p = P.make_params(d, **kw)
+    n = ctypes.c_size_t()
+    st = P.lib().pflbm_state_bytes(ctypes.byref(p), ctypes.byref(n))
+    return st, n.value
+
+
+def test_state_bytes_sizes():
+    d, _, _ = wl.static_droplet_2d()
+    st, n = _bytes(d)
+    assert st == 0
+    # g 9 + h 2 x 5 populations of 4096 nodes in float64, plus scratch
+    assert n >= (9 + 10) * 4096 * 8
+    st, n16 = _bytes(d, precision="mixed_fp16")
+    assert st == 0 and n16 < n
+    d3 = wl.base_params(lattice="D3Q19_D3Q7", nx=32, ny=32, nz=32)
+    st, n3 = _bytes(d3, precision="fp32")
+    # AC on D3Q7 stores 6 phase-field populations per buffer
+    assert st == 0 and n3 >= (19 + 12) * 32768 * 4
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nu_H=0.0), dict(nu_L=-1.0), dict(W=0.0), dict(M=0.0), dict(sigma=-1.0),
+    dict(rho_L=0.0), dict(s_other=2.0), dict(nx=0), dict(nz=2),
+    dict(bc=("wall", "wall", "periodic")),
+    dict(bc=("periodic", "wall", "periodic"), wall_u=((0.0, 0.1, 0.0), (0.0, 0.0, 0.0))),
+    dict(gravity=(0.0, 0.0, 1e-5)),
+    dict(normal_eps=-1.0),
+])
+def test_invalid_params_rejected(bad):
+    d = wl.base_params(**bad)
+    st, _ = _bytes(d)
+    assert st == P.PFLBM_EINVAL
+
+
+def test_strerror():
+    L = P.lib()
+    assert L.pflbm_strerror(P.PFLBM_EUNSTABLE).decode().startswith("numerical")
+    assert L.pflbm_create(None, None, None, 0, None) == P.PFLBM_EINVAL

@@ -1,0 +1,179 @@
+"""FP64 parity of the HIP path with the oracle: every distribution, element by
+element, on the same seeded inputs, max |difference| <= 1e-12.
+
+The two sides share no arithmetic; both start from the inputs of
+paper_2511_11360_amd.workloads. Sizes cover several 64 x 4 tiles, ragged
+x/y tails and a ragged last z block, walls, moving walls, gravity, the frozen
+phase field, both phase-field models, and odd and even in-place streaming
+parity of the stored g.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_helpers import (gpu_dists, gpu_run, hydrostatic_p0, max_abs_per_population,
+                         oracle_envelope, oracle_run, small_3d)
+from oracle import model as om
+from paper_2511_11360_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _parity(d, phi, u, steps, tag, p0=None):
+    _say("case", tag, "shape", (d["nx"], d["ny"], d["nz"]), "steps", steps)
+    s = gpu_run(d, phi, u, steps, p0=p0)
+    g, h = gpu_dists(s)
+    p, st = oracle_run(d, phi, u, steps, p0=p0)
+    eg = max_abs_per_population(g, st.g)
+    eh = max_abs_per_population(h, st.h)
+    _say("  max|dg| %.3e max|dh| %.3e" % (eg.max(), eh.max()))
+    assert np.all(np.isfinite(g)) and np.all(np.isfinite(h))
+    assert eg.max() <= TOL, eg
+    assert eh.max() <= TOL, eh
+    return s, p, st
+
+
+def test_static_droplet_2d_ac_1000():
+    d, phi, u = wl.static_droplet_2d()
+    _parity(d, phi, u, 1000, "static droplet 2-D AC")
+
+
+def test_static_droplet_2d_ch_1000():
+    d, phi, u = wl.static_droplet_2d()
+    d["model"] = "CH"
+    _parity(d, phi, u, 1000, "static droplet 2-D CH")
+
+
+def test_rayleigh_taylor_walls_ragged_ch():
+    d, phi, u = wl.rayleigh_taylor_2d(model="CH", nx=70, ny=90)
+    _parity(d, phi, u, 1001, "RT 2-D walls CH")
+
+
+def test_rayleigh_taylor_walls_ragged_ac_hydrostatic():
+    """AC with gravity: started in hydrostatic balance (pressure input path).
+    Still mildly ill-conditioned (a 1e-15 change reaches 3e-13 by step 300),
+    so the 1e-12 horizon is 101 steps; the 1001-step run is checked against
+    the oracle's rounding spread below."""
+    d, phi, u = wl.rayleigh_taylor_2d(model="AC", nx=70, ny=90)
+    _parity(d, phi, u, 101, "RT 2-D walls AC hydrostatic", p0=hydrostatic_p0(d, phi))
+
+
+def test_rayleigh_taylor_ac_within_oracle_rounding_envelope():
+    """RT with the AC model started at rest pressure is ill-conditioned: the
+    acoustic start-up moves phi off 1 in the heavy bulk where the gradient is
+    small, and the antidiffusion flux there amplifies any rounding difference
+    (a 1e-15 change grows to ~1e-4 in 1000 steps in the oracle itself). The HIP
+    result must lie within the oracle's own rounding spread."""
+    d, phi, u = wl.rayleigh_taylor_2d(model="AC", nx=70, ny=90)
+    steps = 1001
+    s = gpu_run(d, phi, u, steps)
+    g, h = gpu_dists(s)
+    eg_env, eh_env, st = oracle_envelope(d, phi, u, steps)
+    eg = max_abs_per_population(g, st.g)
+    eh = max_abs_per_population(h, st.h)
+    _say("  RT AC 1001: max|dg| %.3e (oracle spread %.3e) max|dh| %.3e (spread %.3e)"
+         % (eg.max(), eg_env.max(), eh.max(), eh_env.max()))
+    assert eg.max() <= 100 * eg_env.max() + TOL
+    assert eh.max() <= 100 * eh_env.max() + TOL
+
+
+def test_layered_poiseuille_frozen_phi():
+    d, phi, u = wl.layered_poiseuille()
+    _parity(d, phi, u, 1000, "layered Poiseuille")
+
+
+def test_droplet_vortex_3d_ragged_ac_1000():
+    d, phi, u = small_3d(model="AC")
+    _parity(d, phi, u, 1000, "3-D vortex droplet AC")
+
+
+def test_droplet_vortex_3d_ragged_ch():
+    d, phi, u = small_3d(model="CH")
+    _parity(d, phi, u, 301, "3-D vortex droplet CH")
+
+
+@pytest.mark.parametrize("model", ["AC", "CH"])
+def test_sheared_droplet_3d_moving_walls(model):
+    d, phi, u, _ = wl.sheared_droplet_3d(n=24, R=7.0, uw=0.02, W=2.5)
+    d["model"] = model
+    d["ny"] = 22
+    phi = wl.droplet_phi(d, (12.0, 10.5, 12.0), 7.0, periodic=False)
+    x, y, z = wl.grid(d)
+    u = wl.zero_velocity(d)
+    u[0] = -0.02 + 0.04 * (y + 0.5) / 22
+    _parity(d, phi, u, 301, "3-D sheared droplet " + model)
+
+
+def test_zblock_and_s_other_variants():
+    d, phi, u = small_3d(nx=30, ny=27, nz=23, s_other=1.2, visc_interp="nu", nu_H=0.03)
+    for zb in (1, 5, 23):
+        _say("zblock", zb)
+        s = gpu_run(d, phi, u, 120, zblock=zb)
+        g, h = gpu_dists(s)
+        p, st = oracle_run(d, phi, u, 120)
+        assert max_abs_per_population(g, st.g).max() <= TOL
+        assert max_abs_per_population(h, st.h).max() <= TOL
+
+
+def test_fields_and_diagnostics_match_oracle():
+    d, phi, u = wl.static_droplet_2d()
+    s = gpu_run(d, phi, u, 401)
+    p, st = oracle_run(d, phi, u, 401)
+    f_phi, f_u, f_p, f_rho = [t.cpu().numpy() for t in s.fields()]
+    o_phi, o_u, o_p, o_rho = om.fields(p, st)
+    assert np.max(np.abs(f_phi - o_phi)) < 1e-12
+    assert np.max(np.abs(f_u - o_u)) < 1e-13
+    assert np.max(np.abs(f_p - o_p)) < 1e-13
+    assert np.max(np.abs(f_rho - o_rho)) < 1e-11
+    dg = s.volume(centre=(32.0, 32.0), R=16.0)
+    do = om.diagnostics(p, st, centre=(32.0, 32.0), R=16.0)
+    for k in ("V_phi", "sum_phi"):
+        assert abs(dg[k] - do[k]) < 1e-10 * abs(do[k])
+    assert dg["V_count"] == do["V_count"]
+    assert abs(dg["phi_min"] - do["phi_min"]) < 1e-12
+    assert abs(dg["phi_max"] - do["phi_max"]) < 1e-12
+    assert abs(dg["umax"] - do["umax"]) < 1e-13
+    assert dg["n_in"] == do["n_in"] and dg["n_out"] == do["n_out"]
+    assert abs(dg["p_in"] - do["p_in"]) < 1e-12 and abs(dg["p_out"] - do["p_out"]) < 1e-12
+    assert dg["unstable"] == 0
+
+
+def test_checkpoint_and_set_distributions_roundtrip():
+    d, phi, u = small_3d(model="CH", nx=18, ny=9, nz=7)
+    s = gpu_run(d, phi, u, 7)          # odd parity
+    ck = s.save_state()
+    s.step(5)
+    g1, h1 = gpu_dists(s)
+    s.load_state(ck)
+    assert s.step_count() == 7
+    s.step(5)
+    g2, h2 = gpu_dists(s)
+    assert np.array_equal(g1, g2) and np.array_equal(h1, h2)
+    # canonical read-out and write-back are inverse at odd parity
+    s.load_state(ck)
+    g, h = gpu_dists(s)
+    s.set_distributions(g, h)
+    g3, h3 = gpu_dists(s)
+    assert np.array_equal(g, g3) and np.array_equal(h, h3)
+
+
+def test_oracle_state_injected_continues_in_parity():
+    """Load the oracle's state at step 50 through the canonical ABI and continue
+    (AC: the canonical distributions are the whole state)."""
+    d, phi, u = wl.static_droplet_2d(n=48, R=12.0)
+    p, st = oracle_run(d, phi, u, 51)
+    s = gpu_run(d, phi, u, 0)
+    s.set_distributions(st.g, st.h)
+    s.step(100)
+    g, h = gpu_dists(s)
+    st2 = om.run(p, st, 100)
+    assert max_abs_per_population(g, st2.g).max() <= TOL
+    assert max_abs_per_population(h, st2.h).max() <= TOL
