@@ -50,17 +50,20 @@ __host__ __device__ inline PhysT<float> to_float(const PhysT<T>& d) {
     return f;
 }
 
+// Device layout of every population array: plane-major [z][q][y][x], each
+// population plane padded to P elements, so plane z of an array with Q
+// populations starts at element z * Q * P.
 struct KArgs {
-    void* g;               // AA in-place hydrodynamic populations [Qg][N]
-    const void* hin;       // phase-field populations read this step [Qhs][N]
-    void* hout;            // phase-field populations written this step [Qhs][N]
-    void* phiu;            // CH (phi u) of the previous step [3][N], compute type
+    void* g;               // AA in-place hydrodynamic populations [z][Qg][P]
+    const void* hin;       // phase-field populations read this step [z][Qhs][P]
+    void* hout;            // phase-field populations written this step [z][Qhs][P]
+    void* phiu;            // CH (phi u) of the previous step [z][3][P], compute type
     double* f_phi;         // MODE_FIELDS outputs (canonical float64), may be null
     double* f_u;
     double* f_p;
     double* f_rho;
     double* partials;      // MODE_DIAG per-block partials [nblocks][NDIAG]
-    long long N;           // population stride in elements
+    int P;                 // elements per population plane (>= nx * ny)
     int nx, ny, nz;
     int ntx, nty, ntz, zb; // tiles per axis, z planes per tile
     int bc[3];             // 0 periodic, 1 wall
@@ -82,7 +85,7 @@ struct InitArgs {
     const double* phi0;
     const double* u0;      // may be null
     const double* p0;      // may be null
-    long long N;
+    int P;
     int nx, ny, nz;
     int bc[3];
     Phys ph;
@@ -93,7 +96,7 @@ struct IOArgs {
     void* h;               // current phase-field buffer
     double* cg;            // canonical float64 g [Qg][nodes]
     double* ch;            // canonical float64 h [Qh][nodes]
-    long long N;
+    int P;
     int nx, ny, nz;
     int bc[3];
     int wall_axis;

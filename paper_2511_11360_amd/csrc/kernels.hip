@@ -380,54 +380,63 @@ __device__ void block_reduce_diag(DiagAcc& d, double* out) {
 // ----------------------------------------------------------------------------
 // fused step kernel
 
-// Per-thread geometry of the column (x, y) a thread owns for the whole z march:
-// offsets to the x and y neighbours with the periodic wrap folded in, and wall
-// flags. Offsets are in nodes; the z part comes per plane as a uniform value.
+// Element index helpers for the plane-major layout [z][q][y][x].
+template <int Q>
+__device__ __forceinline__ size_t el(int z, int q, int inplane, int P) {
+    return ((size_t)z * Q + q) * (size_t)P + (unsigned)inplane;
+}
+
+// element inplane of population plane (z, q): a uniform plane base plus a
+// 32-bit byte offset, so loads and stores take the scalar-base addressing form
+template <int Q, class E>
+__device__ __forceinline__ E& at(E* arr, int z, int q, int P, int inplane) {
+    E* base = arr + ((size_t)z * Q + q) * (size_t)P;
+    return *(E*)((char*)base + (size_t)((unsigned)inplane * (unsigned)sizeof(E)));
+}
+template <int Q, class E>
+__device__ __forceinline__ const E& at(const E* arr, int z, int q, int P, int inplane) {
+    const E* base = arr + ((size_t)z * Q + q) * (size_t)P;
+    return *(const E*)((const char*)base + (size_t)((unsigned)inplane * (unsigned)sizeof(E)));
+}
+
+// Geometry of the column (x, y) a thread owns for the whole z march: in-plane
+// offsets of the 3 x 3 neighbourhood with the periodic wrap folded in (the
+// wall side keeps the node itself), and wall flags of the x and y neighbours.
 struct Column {
-    int ox[3];       // x offset for c_x = -1, 0, +1
-    int oy[3];       // y offset (nodes) for c_y = -1, 0, +1
+    int off[3][3];       // [dy + 1][dx + 1] -> (y + dy) * nx + (x + dx), wrapped
     bool wx[2], wy[2];   // the x / y neighbour at -1 / +1 lies beyond a wall
 };
 
-struct Plane {
-    int oz[3];       // z offset (nodes) for c_z = -1, 0, +1
-    bool wz[2];
-};
-
-__device__ __forceinline__ void axis_offsets(int v, int n, int bc, int stride, int* o, bool* w) {
+__device__ __forceinline__ void axis_nb(int v, int n, int bc, int* o, bool* w) {
     const bool lo = v == 0, hi = v == n - 1;
-    o[0] = (lo && bc == 0) ? (n - 1) * stride : -stride;
-    o[1] = 0;
-    o[2] = (hi && bc == 0) ? -(n - 1) * stride : stride;
+    o[0] = lo ? (bc == 0 ? n - 1 : 0) : v - 1;
+    o[1] = v;
+    o[2] = hi ? (bc == 0 ? 0 : n - 1) : v + 1;
     w[0] = lo && bc != 0;
     w[1] = hi && bc != 0;
 }
 
-// offset (nodes) of x + sgn c and whether that point lies beyond a wall
+// z planes of the neighbourhood of plane z (wrapped; clamped at a wall) and
+// wall flags, uniform over the workgroup
+struct ZPlanes {
+    int zk[3];
+    bool wz[2];
+};
+
+// does x + sgn c_i lie beyond a wall; which side
 template <class L, int i, int sgn>
-__device__ __forceinline__ int nb_offset(const Column& cl, const Plane& pl, bool& wall) {
+__device__ __forceinline__ bool beyond(const Column& cl, const ZPlanes& zp, int& side) {
     constexpr int cx = sgn * L::c(i, 0), cy = sgn * L::c(i, 1), cz = sgn * L::c(i, 2);
-    int off = cl.ox[cx + 1] + cl.oy[cy + 1] + pl.oz[cz + 1];
     bool w = false;
-    if constexpr (cx != 0) w = w || cl.wx[cx > 0];
-    if constexpr (cy != 0) w = w || cl.wy[cy > 0];
-    if constexpr (cz != 0) w = w || pl.wz[cz > 0];
-    wall = w;
-    return off;
+    side = 0;
+    if constexpr (cx != 0) { const bool f = cl.wx[cx > 0]; w = w || f; side = f ? (cx > 0) : side; }
+    if constexpr (cy != 0) { const bool f = cl.wy[cy > 0]; w = w || f; side = f ? (cy > 0) : side; }
+    if constexpr (cz != 0) { const bool f = zp.wz[cz > 0]; w = w || f; side = f ? (cz > 0) : side; }
+    return w;
 }
 
-// side (0 low, 1 high) of the wall crossed towards x + sgn c (single walled axis)
-template <class L, int i, int sgn>
-__device__ __forceinline__ int wall_side(const Column& cl, const Plane& pl) {
-    constexpr int cx = sgn * L::c(i, 0), cy = sgn * L::c(i, 1), cz = sgn * L::c(i, 2);
-    int side = 0;
-    if constexpr (cx != 0) side = cl.wx[cx > 0] ? (cx > 0) : side;
-    if constexpr (cy != 0) side = cl.wy[cy > 0] ? (cy > 0) : side;
-    if constexpr (cz != 0) side = pl.wz[cz > 0] ? (cz > 0) : side;
-    return side;
-}
-
-template <class PAIR, int MODEL, int PREC, int PARITY, int MODE>
+// WALLS = 0: every axis periodic (no bounce-back selects are compiled).
+template <class PAIR, int MODEL, int PREC, int PARITY, int MODE, int WALLS>
 __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
     using GL = typename PAIR::G;
     using HL = typename PAIR::H;
@@ -440,8 +449,8 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
     constexpr int HOFF = (MODEL == 0 && D3) ? 1 : 0;   // AC on D3Q7: rest population not stored
     constexpr int QHS = QH - HOFF;
     constexpr int PW = TILE_X + 2, PSZ = PW * (TILE_Y + 2);
+    constexpr int NRING = 2 * PW + 2 * TILE_Y;         // halo ring of the tile
     constexpr int NPL = D3 ? 3 : 1;
-    constexpr int NFILL = (PSZ + BLOCK - 1) / BLOCK;
     __shared__ T lphi[NPL * PSZ];
 
     const int b = xcd_remap(blockIdx.x, gridDim.x);
@@ -453,91 +462,114 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
     const int lx = threadIdx.x % TILE_X, ly = threadIdx.x / TILE_X;
     const int x = x0 + lx, y = y0 + ly;
     const bool active = x < a.nx && y < a.ny;
-    const int nx = a.nx, ny = a.ny, nz = a.nz, nxy = nx * ny;
-    const long long N = a.N;
-    const unsigned NU = (unsigned)a.N;
+    const int nx = a.nx, ny = a.ny, nz = a.nz, P = a.P;
     GS* __restrict__ G = (GS*)a.g;
     const HS* __restrict__ Hin = (const HS*)a.hin;
     HS* __restrict__ Hout = (HS*)a.hout;
     T* __restrict__ PU = (T*)a.phiu;
 
-    // halo positions this thread fills, fixed over the march (in-plane offsets)
-    int hoff[NFILL];
-    for (int r = 0; r < NFILL; ++r) {
-        const int k = threadIdx.x + r * BLOCK;
-        const int hx = k % PW - 1, hy = k / PW - 1;
-        hoff[r] = ghost_coord(y0 + hy, ny, a.bc[1]) * nx + ghost_coord(x0 + hx, nx, a.bc[0]);
-    }
-    Column cl;
-    axis_offsets(min(x, nx - 1), nx, a.bc[0], 1, cl.ox, cl.wx);
-    axis_offsets(min(y, ny - 1), ny, a.bc[1], nx, cl.oy, cl.wy);
-
     const PhysT<T>* php;
-    const double* gcd = &a.gcorr[0][0];
-    const float* gcf = &a.gcorrf[0][0];
     if constexpr (sizeof(T) == 8) php = &a.ph;
     else php = &a.phf;
     const PhysT<T>& ph = *php;
     auto gcorr = [&](int side, int i) -> T {
-        if constexpr (sizeof(T) == 8) return gcd[side * MAXQ + i];
-        else return gcf[side * MAXQ + i];
+        if constexpr (sizeof(T) == 8) return a.gcorr[side][i];
+        else return a.gcorrf[side][i];
     };
+
+    // the thread's own tile position, wrapped or clamped (inactive threads fill
+    // the halo of the domain edge with it)
+    const int own = ghost_coord(y, ny, a.bc[1]) * nx + ghost_coord(x, nx, a.bc[0]);
+    Column cl;
+    {
+        int ox[3], oy[3];
+        axis_nb(min(x, nx - 1), nx, a.bc[0], ox, cl.wx);
+        axis_nb(min(y, ny - 1), ny, a.bc[1], oy, cl.wy);
+        for (int dy = 0; dy < 3; ++dy)
+            for (int dx = 0; dx < 3; ++dx) cl.off[dy][dx] = oy[dy] * nx + ox[dx];
+    }
+    // halo ring position this thread fills (threads 0 .. NRING-1)
+    int ring_off = 0, ring_lds = 0;
+    const bool ring = threadIdx.x < NRING;
+    if (ring) {
+        const int r = threadIdx.x;
+        int hx, hy;
+        if (r < PW) { hx = r - 1; hy = -1; }
+        else if (r < 2 * PW) { hx = r - PW - 1; hy = TILE_Y; }
+        else if (r < 2 * PW + TILE_Y) { hx = -1; hy = r - 2 * PW; }
+        else { hx = TILE_X; hy = r - 2 * PW - TILE_Y; }
+        ring_off = ghost_coord(y0 + hy, ny, a.bc[1]) * nx + ghost_coord(x0 + hx, nx, a.bc[0]);
+        ring_lds = (hy + 1) * PW + (hx + 1);
+    }
+    const int own_lds = (ly + 1) * PW + (lx + 1);
 
     DiagAcc acc;
     if constexpr (MODE == MODE_DIAG) diag_init(acc);
 
+    // phi of plane zz into LDS slot; returns the thread's own h of that plane
+    T hn[QH];
     auto fill_plane = [&](int zz, int slot) {
         const int gz = D3 ? ghost_coord(zz, nz, a.bc[2]) : 0;
-        const int base = gz * nxy;
-        for (int r = 0; r < NFILL; ++r) {
-            const int k = threadIdx.x + r * BLOCK;
-            if (r + 1 < NFILL || k < PSZ) {
-                const unsigned idx = (unsigned)(base + hoff[r]);
-                T s = (T)0;
-                unroll<QHS>([&](auto J) {
-                    constexpr int jj = J;
-                    s += (T)Hin[(size_t)jj * N + idx];
-                });
-                lphi[slot * PSZ + k] = s;
-            }
+        hn[0] = (T)0;
+        T s = (T)0;
+        unroll<QHS>([&](auto J) {
+            constexpr int jj = J;
+            const T v = (T)at<QHS>(Hin, gz, jj, P, own);
+            hn[jj + HOFF] = v;
+            s += v;
+        });
+        lphi[slot * PSZ + own_lds] = s;
+        if (ring) {
+            T sr = (T)0;
+            unroll<QHS>([&](auto J) {
+                constexpr int jj = J;
+                sr += (T)at<QHS>(Hin, gz, jj, P, ring_off);
+            });
+            lphi[slot * PSZ + ring_lds] = sr;
         }
     };
 
-    auto do_node = [&](int z, const T* pm, const T* p0, const T* pp) {
-        Plane pl;
-        axis_offsets(z, nz, a.bc[2], nxy, pl.oz, pl.wz);
-        const unsigned idx = (unsigned)(z * nxy + y * nx + x);
+    auto do_node = [&](int z, const T* h, const T* pm, const T* p0, const T* pp) {
+        ZPlanes zp;
+        {
+            int oz[3];
+            axis_nb(z, nz, a.bc[2], oz, zp.wz);
+            zp.zk[0] = oz[0];
+            zp.zk[1] = oz[1];
+            zp.zk[2] = oz[2];
+        }
+        const int o11 = cl.off[1][1];
         // post-streaming g of this node
         T g[QG];
         unroll<QG>([&](auto I) {
             constexpr int i = I;
             if constexpr (PARITY == 0) {
-                g[i] = GC::template dec<GL, i, GS, T>(G[(size_t)i * N + idx]);
+                g[i] = GC::template dec<GL, i, GS, T>(at<QG>(G, z, i, P, o11));
             } else {
+                // written last step by the neighbour x - c_i into its slot opp(i)
                 constexpr int o = GL::opp(i);
-                constexpr int lo = i < o ? i : o;
-                bool wall;
-                const int off = nb_offset<GL, i, -1>(cl, pl, wall);
-                // beyond a wall the population left this node last step: slot i here;
-                // both candidates are addressed from the lower population's base
-                const unsigned e = wall ? (unsigned)(i - lo) * NU + idx
-                                        : (unsigned)(o - lo) * NU + (unsigned)((int)idx + off);
-                T v = GC::template dec<GL, o, GS, T>((G + (size_t)lo * N)[e]);
-                if (wall) v += gcorr(wall_side<GL, i, -1>(cl, pl), o);
-                g[i] = v;
+                constexpr int cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
+                const size_t enb = el<QG>(zp.zk[1 - cz], o, cl.off[1 - cy][1 - cx], P);
+                if constexpr (!WALLS) {
+                    g[i] = GC::template dec<GL, o, GS, T>(
+                        at<QG>(G, zp.zk[1 - cz], o, P, cl.off[1 - cy][1 - cx]));
+                } else {
+                    int side;
+                    // beyond a wall the population left this node last step: slot i here
+                    const bool w = beyond<GL, i, -1>(cl, zp, side);
+                    const size_t e = w ? el<QG>(z, i, o11, P) : enb;
+                    T v = GC::template dec<GL, o, GS, T>(G[e]);
+                    if (w) v += gcorr(side, o);
+                    g[i] = v;
+                }
             }
-        });
-        T h[QH];
-        h[0] = (T)0;
-        unroll<QHS>([&](auto J) {
-            constexpr int jj = J;
-            h[jj + HOFF] = (T)Hin[(size_t)jj * N + idx];
         });
         T pu_prev[3] = {(T)0, (T)0, (T)0};
         if constexpr (MODEL == 1) {
-            pu_prev[0] = PU[idx];
-            pu_prev[1] = PU[N + idx];
-            pu_prev[2] = PU[2 * N + idx];
+            unroll<3>([&](auto A) {
+                constexpr int c = A;
+                pu_prev[c] = at<3>(PU, z, c, P, o11);
+            });
         }
         // phi at the stencil points
         T phin[QG];
@@ -555,15 +587,20 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
                 constexpr int i = I;
                 constexpr int o = GL::opp(i);
                 if constexpr (PARITY == 0) {
-                    G[(size_t)o * N + idx] = GC::template enc<GL, o, GS, T>(v);
+                    at<QG>(G, z, o, P, o11) = GC::template enc<GL, o, GS, T>(v);
                 } else {
-                    constexpr int lo = i < o ? i : o;
-                    bool wall;
-                    const int off = nb_offset<GL, i, 1>(cl, pl, wall);
-                    if (wall) v += gcorr(wall_side<GL, i, 1>(cl, pl), i);
-                    const unsigned e = wall ? (unsigned)(o - lo) * NU + idx
-                                            : (unsigned)(i - lo) * NU + (unsigned)((int)idx + off);
-                    (G + (size_t)lo * N)[e] = GC::template enc<GL, i, GS, T>(v);
+                    constexpr int cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
+                    const size_t enb = el<QG>(zp.zk[1 + cz], i, cl.off[1 + cy][1 + cx], P);
+                    if constexpr (!WALLS) {
+                        at<QG>(G, zp.zk[1 + cz], i, P, cl.off[1 + cy][1 + cx]) =
+                            GC::template enc<GL, i, GS, T>(v);
+                    } else {
+                        int side;
+                        const bool w = beyond<GL, i, 1>(cl, zp, side);
+                        if (w) v += gcorr(side, i);
+                        const size_t e = w ? el<QG>(z, o, o11, P) : enb;
+                        G[e] = GC::template enc<GL, i, GS, T>(v);
+                    }
                 }
             };
             // h: push into the other buffer
@@ -572,32 +609,37 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
                 if constexpr (al >= HOFF) {
                     if (a.write_h) {
                         constexpr int o = HL::opp(al);
-                        constexpr int lo = al < o ? al : o;
-                        bool wall;
-                        const int off = nb_offset<HL, al, 1>(cl, pl, wall);
-                        const unsigned e = wall ? (unsigned)(o - lo) * NU + idx
-                                                : (unsigned)(al - lo) * NU + (unsigned)((int)idx + off);
-                        (Hout + (size_t)(lo - HOFF) * N)[e] = (HS)v;
+                        constexpr int ex = HL::c(al, 0), ey = HL::c(al, 1), ez = HL::c(al, 2);
+                        if constexpr (WALLS) {
+                            const size_t enb = el<QHS>(zp.zk[1 + ez], al - HOFF, cl.off[1 + ey][1 + ex], P);
+                            int side;
+                            const bool w = beyond<HL, al, 1>(cl, zp, side);
+                            Hout[w ? el<QHS>(z, o - HOFF, o11, P) : enb] = (HS)v;
+                        } else {
+                            at<QHS>(Hout, zp.zk[1 + ez], al - HOFF, P, cl.off[1 + ey][1 + ex]) = (HS)v;
+                        }
                     }
                 }
             };
             node_update<PAIR, MODEL, T, true>(ph, g, h, phin, pu_prev, pu_new, mo, gsink, hsink);
             if constexpr (MODEL == 1) {
                 if (a.write_h) {
-                    PU[idx] = pu_new[0];
-                    PU[N + idx] = pu_new[1];
-                    PU[2 * N + idx] = pu_new[2];
+                    unroll<3>([&](auto A) {
+                        constexpr int c = A;
+                        at<3>(PU, z, c, P, o11) = pu_new[c];
+                    });
                 }
             }
         } else {
             auto none = [](auto, T) {};
             node_update<PAIR, MODEL, T, false>(ph, g, h, phin, pu_prev, pu_new, mo, none, none);
+            const size_t idx = ((size_t)z * ny + y) * nx + x;    // canonical index
             if constexpr (MODE == MODE_FIELDS) {
                 if (a.f_phi) a.f_phi[idx] = (double)mo.phi;
                 if (a.f_rho) a.f_rho[idx] = (double)mo.rho;
                 if (a.f_p) a.f_p[idx] = (double)mo.p;
                 if (a.f_u) {
-                    const long long nn = (long long)nx * ny * nz;
+                    const size_t nn = (size_t)nx * ny * nz;
                     a.f_u[idx] = (double)mo.u[0];
                     a.f_u[nn + idx] = (double)mo.u[1];
                     if constexpr (D3) a.f_u[2 * nn + idx] = (double)mo.u[2];
@@ -632,21 +674,24 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
         }
     };
 
+    T hc[QH];
     if constexpr (D3) {
         fill_plane(zs - 1, 0);
         fill_plane(zs, 1);
+        unroll<QH>([&](auto J) { constexpr int al = J; hc[al] = hn[al]; });
         for (int z = zs; z < ze; ++z) {
             const int r = z - zs;
             fill_plane(z + 1, (r + 2) % 3);
             __syncthreads();
-            if (active) do_node(z, lphi + (r % 3) * PSZ, lphi + ((r + 1) % 3) * PSZ,
+            if (active) do_node(z, hc, lphi + (r % 3) * PSZ, lphi + ((r + 1) % 3) * PSZ,
                                 lphi + ((r + 2) % 3) * PSZ);
+            unroll<QH>([&](auto J) { constexpr int al = J; hc[al] = hn[al]; });
             __syncthreads();
         }
     } else {
         fill_plane(0, 0);
         __syncthreads();
-        if (active) do_node(0, lphi, lphi, lphi);
+        if (active) do_node(0, hn, lphi, lphi, lphi);
     }
     if constexpr (MODE == MODE_DIAG) {
         __syncthreads();
@@ -685,10 +730,12 @@ __global__ __launch_bounds__(256) void k_init(const InitArgs a) {
     using GC = GCodec<PREC>;
     constexpr bool D3 = PAIR::dim == 3;
     constexpr int HOFF = (MODEL == 0 && D3) ? 1 : 0;
+    constexpr int QHS = HL::Q - HOFF;
     const long long nn = (long long)a.nx * a.ny * a.nz;
     const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= nn) return;
     const int x = (int)(n % a.nx), y = (int)((n / a.nx) % a.ny), z = (int)(n / ((long long)a.nx * a.ny));
+    const int ip = y * a.nx + x;
     const Phys& ph = a.ph;
     const double phi = a.phi0[n];
     double u[3] = {0.0, 0.0, 0.0};
@@ -706,14 +753,14 @@ __global__ __launch_bounds__(256) void k_init(const InitArgs a) {
         constexpr int i = I;
         const double cu = GL::c(i, 0) * u[0] + GL::c(i, 1) * u[1] + GL::c(i, 2) * u[2];
         const double geq = GL::w(i) * (ps + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
-        G[(size_t)i * a.N + n] = GC::template enc<GL, i, GS, T>((T)geq);
+        G[el<GL::Q>(z, i, ip, a.P)] = GC::template enc<GL, i, GS, T>((T)geq);
     });
     if constexpr (MODEL == 0) {
-        unroll<HL::Q - HOFF>([&](auto J) {
+        unroll<QHS>([&](auto J) {
             constexpr int al = J + HOFF;
             const double eu = HL::c(al, 0) * u[0] + HL::c(al, 1) * u[1] + HL::c(al, 2) * u[2];
             const double heq = HL::w(al) * phi * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * usq);
-            H[(size_t)(al - HOFF) * a.N + n] = (HS)heq;
+            H[el<QHS>(z, al - HOFF, ip, a.P)] = (HS)heq;
         });
     } else {
         // mu_phi(phi0) with the same stencil and ghost rules as the step
@@ -738,12 +785,10 @@ __global__ __launch_bounds__(256) void k_init(const InitArgs a) {
                                   HL::c(al, 2) * phi * u[2];
                 heq = HL::w(al) * ph.eta * mu + 3.0 * HL::w(al) * ep;
             }
-            H[(size_t)al * a.N + n] = (HS)heq;
+            H[el<QHS>(z, al, ip, a.P)] = (HS)heq;
         });
         T* PU = (T*)a.phiu;
-        PU[n] = (T)(phi * u[0]);
-        PU[a.N + n] = (T)(phi * u[1]);
-        PU[2 * a.N + n] = (T)(phi * u[2]);
+        for (int c = 0; c < 3; ++c) PU[el<3>(z, c, ip, a.P)] = (T)(phi * u[c]);
     }
 }
 
@@ -760,25 +805,28 @@ __global__ __launch_bounds__(256) void k_get(const IOArgs a) {
     using GC = GCodec<PREC>;
     constexpr bool D3 = PAIR::dim == 3;
     constexpr int HOFF = (MODEL == 0 && D3) ? 1 : 0;
+    constexpr int QHS = HL::Q - HOFF;
     const long long nn = (long long)a.nx * a.ny * a.nz;
     const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= nn) return;
     const int x = (int)(n % a.nx), y = (int)((n / a.nx) % a.ny), z = (int)(n / ((long long)a.nx * a.ny));
+    const int ip = y * a.nx + x;
     const GS* G = (const GS*)a.g;
     const HS* H = (const HS*)a.h;
     unroll<GL::Q>([&](auto I) {
         constexpr int i = I;
         T v;
         if (a.parity == 0) {
-            v = GC::template dec<GL, i, GS, T>(G[(size_t)i * a.N + n]);
+            v = GC::template dec<GL, i, GS, T>(G[el<GL::Q>(z, i, ip, a.P)]);
         } else {
             int nb, side;
             if (shifted<GL, i, -1>(a.nx, a.ny, a.nz, a.bc, x, y, z, nb, side)) {
-                v = GC::template dec<GL, i, GS, T>(G[(size_t)i * a.N + n]) +
+                v = GC::template dec<GL, i, GS, T>(G[el<GL::Q>(z, i, ip, a.P)]) +
                     (T)a.gcorr[side][GL::opp(i)];
             } else {
                 constexpr int o = GL::opp(i);
-                v = GC::template dec<GL, o, GS, T>(G[(size_t)o * a.N + nb]);
+                const int zn = nb / (a.nx * a.ny), ipn = nb % (a.nx * a.ny);
+                v = GC::template dec<GL, o, GS, T>(G[el<GL::Q>(zn, o, ipn, a.P)]);
             }
         }
         a.cg[(size_t)i * nn + n] = (double)v;
@@ -786,7 +834,7 @@ __global__ __launch_bounds__(256) void k_get(const IOArgs a) {
     unroll<HL::Q>([&](auto J) {
         constexpr int al = J;
         if constexpr (al < HOFF) a.ch[(size_t)al * nn + n] = 0.0;
-        else a.ch[(size_t)al * nn + n] = (double)H[(size_t)(al - HOFF) * a.N + n];
+        else a.ch[(size_t)al * nn + n] = (double)H[el<QHS>(z, al - HOFF, ip, a.P)];
     });
 }
 
@@ -800,18 +848,21 @@ __global__ __launch_bounds__(256) void k_set(const IOArgs a) {
     using GC = GCodec<PREC>;
     constexpr bool D3 = PAIR::dim == 3;
     constexpr int HOFF = (MODEL == 0 && D3) ? 1 : 0;
+    constexpr int QHS = HL::Q - HOFF;
     const long long nn = (long long)a.nx * a.ny * a.nz;
     const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= nn) return;
+    const int x = (int)(n % a.nx), y = (int)((n / a.nx) % a.ny), z = (int)(n / ((long long)a.nx * a.ny));
+    const int ip = y * a.nx + x;
     GS* G = (GS*)a.g;
     HS* H = (HS*)a.h;
     unroll<GL::Q>([&](auto I) {
         constexpr int i = I;
-        G[(size_t)i * a.N + n] = GC::template enc<GL, i, GS, T>((T)a.cg[(size_t)i * nn + n]);
+        G[el<GL::Q>(z, i, ip, a.P)] = GC::template enc<GL, i, GS, T>((T)a.cg[(size_t)i * nn + n]);
     });
-    unroll<HL::Q - HOFF>([&](auto J) {
+    unroll<QHS>([&](auto J) {
         constexpr int al = J + HOFF;
-        H[(size_t)(al - HOFF) * a.N + n] = (HS)a.ch[(size_t)al * nn + n];
+        H[el<QHS>(z, al - HOFF, ip, a.P)] = (HS)a.ch[(size_t)al * nn + n];
     });
 }
 
@@ -821,15 +872,19 @@ __global__ __launch_bounds__(256) void k_set(const IOArgs a) {
 template <class PAIR, int MODEL, int PREC, int PARITY>
 static hipError_t step_mode(int mode, const KArgs& a, hipStream_t s) {
     const dim3 grid((unsigned)(a.ntx * a.nty * a.ntz)), block(BLOCK);
+    const bool walls = a.wall_axis >= 0;
     switch (mode) {
         case MODE_STEP:
-            hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, PARITY, MODE_STEP>), grid, block, 0, s, a);
+            if (walls)
+                hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, PARITY, MODE_STEP, 1>), grid, block, 0, s, a);
+            else
+                hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, PARITY, MODE_STEP, 0>), grid, block, 0, s, a);
             break;
         case MODE_FIELDS:
-            hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, PARITY, MODE_FIELDS>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, PARITY, MODE_FIELDS, 1>), grid, block, 0, s, a);
             break;
         default:
-            hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, PARITY, MODE_DIAG>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, PARITY, MODE_DIAG, 1>), grid, block, 0, s, a);
     }
     return hipGetLastError();
 }

@@ -23,10 +23,12 @@ namespace {
 struct Layout {
     int dim = 0, Qg = 0, Qh = 0, Qhs = 0;
     size_t sg = 0, sh = 0, sT = 0;   // bytes per stored g, h, compute value
-    long long nodes = 0, N = 0;      // nodes, population stride
+    long long nodes = 0;
+    int P = 0;                       // elements per population plane
     int ntx = 0, nty = 0, ntz = 0, zb = 0, nblocks = 0;
     size_t off_g = 0, off_h[2] = {0, 0}, off_pu = 0, off_part = 0, off_res = 0, total = 0;
     size_t ck_g = 0, ck_h = 0, ck_pu = 0, ck_total = 0;
+    size_t g_bytes = 0, h_bytes = 0, pu_bytes = 0;
 };
 
 constexpr size_t ALIGN = 4096;
@@ -43,11 +45,7 @@ std::string validate(const pflbm_params& p) {
     if (p.lattice == PFLBM_D2Q9_D2Q5 && p.nz != 1) return "2-D lattice requires nz == 1";
     const long long nodes = (long long)p.nx * p.ny * p.nz;
     if (nodes > 0x7fffffffLL) return "more than 2^31-1 nodes";
-    {
-        // kernels address a population pair through 32-bit byte offsets
-        const long long es = p.precision == PFLBM_FP64 ? 8 : 4;
-        if ((nodes + 128) * 3 * es >= 0xffffffffLL) return "too many nodes for this precision";
-    }
+    if ((long long)p.nx * p.ny > 0x7fff0000LL) return "more than 2^31 nodes per z plane";
     int walls = 0;
     for (int a = 0; a < 3; ++a) {
         if (p.bc[a] != PFLBM_PERIODIC && p.bc[a] != PFLBM_WALL) return "bc must be PFLBM_PERIODIC or PFLBM_WALL";
@@ -89,7 +87,8 @@ Layout make_layout(const pflbm_params& p) {
     L.sg = p.precision == PFLBM_FP64 ? 8 : (p.precision == PFLBM_FP32 ? 4 : 2);
     L.sh = p.precision == PFLBM_FP64 ? 8 : 4;
     L.nodes = (long long)p.nx * p.ny * p.nz;
-    L.N = (long long)align_up((size_t)L.nodes, 128);
+    L.P = (int)align_up((size_t)p.nx * p.ny, 64);
+    const size_t planes = (size_t)p.nz * L.P;
     L.ntx = (p.nx + TILE_X - 1) / TILE_X;
     L.nty = (p.ny + TILE_Y - 1) / TILE_Y;
     if (d3) {
@@ -102,13 +101,13 @@ Layout make_layout(const pflbm_params& p) {
     L.nblocks = L.ntx * L.nty * L.ntz;
     size_t off = 0;
     L.off_g = off;
-    off = align_up(off + (size_t)L.Qg * L.N * L.sg, ALIGN);
+    off = align_up(off + (size_t)L.Qg * planes * L.sg, ALIGN);
     for (int k = 0; k < 2; ++k) {
         L.off_h[k] = off;
-        off = align_up(off + (size_t)L.Qhs * L.N * L.sh, ALIGN);
+        off = align_up(off + (size_t)L.Qhs * planes * L.sh, ALIGN);
     }
     L.off_pu = off;
-    if (p.model == PFLBM_CH) off = align_up(off + 3 * (size_t)L.N * L.sT, ALIGN);
+    if (p.model == PFLBM_CH) off = align_up(off + 3 * planes * L.sT, ALIGN);
     L.off_part = off;
     off = align_up(off + (size_t)L.nblocks * NDIAG * sizeof(double), ALIGN);
     L.off_res = off;
@@ -116,9 +115,12 @@ Layout make_layout(const pflbm_params& p) {
     L.total = off;
     // checkpoint: 256-byte header, g, current h, (phi u)
     L.ck_g = 256;
-    L.ck_h = align_up(L.ck_g + (size_t)L.Qg * L.N * L.sg, 256);
-    L.ck_pu = align_up(L.ck_h + (size_t)L.Qhs * L.N * L.sh, 256);
-    L.ck_total = align_up(L.ck_pu + (p.model == PFLBM_CH ? 3 * (size_t)L.N * L.sT : 0), 256);
+    L.g_bytes = (size_t)L.Qg * planes * L.sg;
+    L.h_bytes = (size_t)L.Qhs * planes * L.sh;
+    L.pu_bytes = p.model == PFLBM_CH ? 3 * planes * L.sT : 0;
+    L.ck_h = align_up(L.ck_g + L.g_bytes, 256);
+    L.ck_pu = align_up(L.ck_h + L.h_bytes, 256);
+    L.ck_total = align_up(L.ck_pu + L.pu_bytes, 256);
     return L;
 }
 
@@ -189,7 +191,7 @@ void base_args(pflbm_t* h, KArgs& a) {
     a.hout = h->base + h->L.off_h[1 - h->hcur];
     a.phiu = h->base + h->L.off_pu;
     a.partials = (double*)(h->base + h->L.off_part);
-    a.N = h->L.N;
+    a.P = h->L.P;
     a.nx = h->p.nx;
     a.ny = h->p.ny;
     a.nz = h->p.nz;
@@ -309,7 +311,7 @@ int pflbm_init(pflbm_t* h, const double* phi0, const double* u0, const double* p
     a.phi0 = phi0;
     a.u0 = u0;
     a.p0 = p0;
-    a.N = h->L.N;
+    a.P = h->L.P;
     a.nx = h->p.nx;
     a.ny = h->p.ny;
     a.nz = h->p.nz;
@@ -390,7 +392,7 @@ static void io_args(pflbm_t* h, IOArgs& a) {
     std::memset(&a, 0, sizeof(a));
     a.g = h->base + h->L.off_g;
     a.h = h->base + h->L.off_h[h->hcur];
-    a.N = h->L.N;
+    a.P = h->L.P;
     a.nx = h->p.nx;
     a.ny = h->p.ny;
     a.nz = h->p.nz;
@@ -447,10 +449,10 @@ int pflbm_save_state(pflbm_t* h, void* dev_dst) {
     char* d = (char*)dev_dst;
     const Layout& L = h->L;
     HIPCHK(h, launch_header(d, h->steps, h->parity, 0, h->stream), "header kernel");
-    HIPCHK(h, hipMemcpyAsync(d + L.ck_g, h->base + L.off_g, (size_t)L.Qg * L.N * L.sg, hipMemcpyDeviceToDevice, h->stream), "save g");
-    HIPCHK(h, hipMemcpyAsync(d + L.ck_h, h->base + L.off_h[h->hcur], (size_t)L.Qhs * L.N * L.sh, hipMemcpyDeviceToDevice, h->stream), "save h");
+    HIPCHK(h, hipMemcpyAsync(d + L.ck_g, h->base + L.off_g, L.g_bytes, hipMemcpyDeviceToDevice, h->stream), "save g");
+    HIPCHK(h, hipMemcpyAsync(d + L.ck_h, h->base + L.off_h[h->hcur], L.h_bytes, hipMemcpyDeviceToDevice, h->stream), "save h");
     if (h->p.model == PFLBM_CH)
-        HIPCHK(h, hipMemcpyAsync(d + L.ck_pu, h->base + L.off_pu, 3 * (size_t)L.N * L.sT, hipMemcpyDeviceToDevice, h->stream), "save phiu");
+        HIPCHK(h, hipMemcpyAsync(d + L.ck_pu, h->base + L.off_pu, L.pu_bytes, hipMemcpyDeviceToDevice, h->stream), "save phiu");
     return PFLBM_OK;
 }
 
@@ -464,10 +466,10 @@ int pflbm_load_state(pflbm_t* h, const void* dev_src) {
     HIPCHK(h, hipMemcpyAsync(hdr, s, sizeof(hdr), hipMemcpyDeviceToHost, h->stream), "load header");
     HIPCHK(h, hipStreamSynchronize(h->stream), "load sync");
     if (hdr[0] != 0x70666c626dLL) return fail(h, PFLBM_EINVAL, "not a pflbm checkpoint");
-    HIPCHK(h, hipMemcpyAsync(h->base + L.off_g, s + L.ck_g, (size_t)L.Qg * L.N * L.sg, hipMemcpyDeviceToDevice, h->stream), "load g");
-    HIPCHK(h, hipMemcpyAsync(h->base + L.off_h[0], s + L.ck_h, (size_t)L.Qhs * L.N * L.sh, hipMemcpyDeviceToDevice, h->stream), "load h");
+    HIPCHK(h, hipMemcpyAsync(h->base + L.off_g, s + L.ck_g, L.g_bytes, hipMemcpyDeviceToDevice, h->stream), "load g");
+    HIPCHK(h, hipMemcpyAsync(h->base + L.off_h[0], s + L.ck_h, L.h_bytes, hipMemcpyDeviceToDevice, h->stream), "load h");
     if (h->p.model == PFLBM_CH)
-        HIPCHK(h, hipMemcpyAsync(h->base + L.off_pu, s + L.ck_pu, 3 * (size_t)L.N * L.sT, hipMemcpyDeviceToDevice, h->stream), "load phiu");
+        HIPCHK(h, hipMemcpyAsync(h->base + L.off_pu, s + L.ck_pu, L.pu_bytes, hipMemcpyDeviceToDevice, h->stream), "load phiu");
     h->steps = hdr[1];
     h->parity = (int)hdr[2];
     h->hcur = 0;
