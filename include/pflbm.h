@@ -179,6 +179,29 @@ int pflbm_checkpoint_bytes(const pflbm_t* h, size_t* bytes);
 int pflbm_save_state(pflbm_t* h, void* dev_dst);
 int pflbm_load_state(pflbm_t* h, const void* dev_src);
 
+/* Discrete adjoint (AC model). The adjoint of one time step X^n -> X^{n+1}
+   (X = canonical float64 post-streaming distributions, as returned by
+   pflbm_get_distributions) given lambda^{n+1} = dL/dX^{n+1}: writes
+   lambda^n = dL/dX^n and ADDS dL/d(sigma, M, W) of this step into dparams
+   (device float64[3], may be NULL). fwd_g/fwd_h hold X^n. All pointers are
+   device pointers in canonical layout ([Qg][z][y][x], [Qh][z][y][x]);
+   lam_*_out must not alias lam_*. work: caller-owned device workspace of
+   pflbm_adjoint_workspace_bytes(). Uses the handle's parameters; float64
+   arithmetic whatever the handle's precision. The method's reverse mode is
+   not in the paper: it is the exact transpose of the discrete step of
+   Sec. II.C.1 as implemented here. Returns PFLBM_EUNSUPPORTED for CH or a
+   frozen phase field. */
+int pflbm_adjoint_workspace_bytes(const pflbm_t* h, size_t* bytes);
+int pflbm_adjoint_step(pflbm_t* h, const double* fwd_g, const double* fwd_h,
+                       const double* lam_g, const double* lam_h,
+                       double* lam_g_out, double* lam_h_out, double* dparams, void* work);
+
+/* dL/dphi0 of the equilibrium initialisation (pflbm_init) given
+   lambda^0 = dL/dX^0: dphi0 [z][y][x] (device float64, overwritten). u0 and
+   p0 as passed to pflbm_init (NULL = zero). */
+int pflbm_adjoint_init(pflbm_t* h, const double* phi0, const double* u0, const double* p0,
+                       const double* lam_g, const double* lam_h, double* dphi0);
+
 void pflbm_destroy(pflbm_t* h);
 const char* pflbm_last_error(const pflbm_t* h);
 const char* pflbm_strerror(int status);

@@ -1,0 +1,79 @@
+"""Gradients of a phase-field run through the library's discrete adjoint.
+
+run_phase_field(phi0, sigma, M, W, params, u0, nsteps) returns phi after
+nsteps time steps as a differentiable function of the initial phase field and
+of sigma, M and W (0-d float64 tensors). The forward pass keeps a native
+checkpoint every k = ceil(sqrt(nsteps)) steps; the backward pass walks the
+segments in reverse, recomputes each segment's k states from its checkpoint
+and applies the adjoint step kernel to each, so memory is O(sqrt(nsteps))
+states. Every forward and adjoint step runs in libpflbm's kernels; this module
+only schedules them.
+"""
+import math
+
+import torch
+
+from .solver import Solver
+
+
+class PhaseFieldRun(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, phi0, sigma, M, W, params, u0, nsteps, precision, k):
+        d = dict(params)
+        d["sigma"], d["M"], d["W"] = float(sigma), float(M), float(W)
+        if d.get("model", "AC") != "AC":
+            raise ValueError("the adjoint is implemented for the AC model only")
+        s = Solver(d, precision=precision, device=phi0.device)
+        s.init(phi0, u0)
+        nsteps = int(nsteps)
+        if k is None or k <= 0:
+            k = max(1, int(math.ceil(math.sqrt(max(nsteps, 1)))))
+        cks = []
+        start = 0
+        while start < nsteps:
+            cks.append((start, s.save_state()))
+            n = min(k, nsteps - start)
+            s.step(n)
+            start += n
+        phiN, _, _, _ = s.fields()
+        ctx.solver = s
+        ctx.cks = cks
+        ctx.k = k
+        ctx.nsteps = nsteps
+        ctx.u0 = u0
+        ctx.save_for_backward(phi0)
+        return phiN.to(phi0.dtype)
+
+    @staticmethod
+    def backward(ctx, grad_phi):
+        s = ctx.solver
+        (phi0,) = ctx.saved_tensors
+        dev = s.device
+        shape = s.shape
+        lam_h = grad_phi.to(device=dev, dtype=torch.float64).reshape(shape)
+        lam_h = lam_h.unsqueeze(0).expand((s.Qh,) + shape).contiguous()   # phi = sum h
+        lam_g = torch.zeros((s.Qg,) + shape, dtype=torch.float64, device=dev)
+        out_g = torch.empty_like(lam_g)
+        out_h = torch.empty_like(lam_h)
+        dparams = torch.zeros(3, dtype=torch.float64, device=dev)
+        work = s.adjoint_workspace()
+        for start, buf in reversed(ctx.cks):
+            n = min(ctx.k, ctx.nsteps - start)
+            s.load_state(buf)
+            states = []
+            for _ in range(n):
+                states.append(s.get_distributions())
+                s.step(1)
+            for g, h in reversed(states):
+                s.adjoint_step(g, h, lam_g, lam_h, out_g, out_h, dparams, work)
+                lam_g, out_g = out_g, lam_g
+                lam_h, out_h = out_h, lam_h
+            del states
+        dphi0 = s.adjoint_init(phi0, ctx.u0, None, lam_g, lam_h)
+        return (dphi0.to(phi0.dtype).reshape(phi0.shape), dparams[0], dparams[1], dparams[2],
+                None, None, None, None, None)
+
+
+def run_phase_field(phi0, sigma, M, W, params, u0=None, nsteps=1, precision="fp64", k=None):
+    """phi after nsteps steps; differentiable in phi0, sigma, M, W."""
+    return PhaseFieldRun.apply(phi0, sigma, M, W, params, u0, nsteps, precision, k)

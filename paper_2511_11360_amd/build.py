@@ -14,7 +14,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpflbm.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["kernels.hip", "pflbm.cpp"]
+SOURCES = ["kernels.hip", "adjoint.hip", "pflbm.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -1,0 +1,502 @@
+// Discrete adjoint of one conservative Allen-Cahn time step (the fused step of
+// kernels.hip, Sec. II.C.1 of the paper), float64, on canonical arrays
+// [q][z][y][x].
+//
+// The forward step maps the post-streaming state X^n = (g, h) to X^{n+1}:
+//   phi = sum h;  grad phi, lap phi from phi at x + c_i (periodic image or wall
+//   mirror);  per node collision C(g, h, phi, grad phi, lap phi; sigma, M, W);
+//   streaming (a permutation, bounce-back at walls plus a constant).
+// Its adjoint maps lambda^{n+1} = dL/dX^{n+1} to lambda^n = dL/dX^n and adds
+// dL/d(sigma, M, W) of the step:
+//   pass 1  phi^n into the workspace;
+//   pass 2  per node: lambda* (stream transpose, a gather), the reverse sweep
+//           of C written out by hand (forward intermediates recomputed), giving
+//           dL/dg (the new lambda_g), dL/dh through h directly, dL/dphi
+//           directly, dL/dgrad phi, dL/dlap phi and the parameter terms
+//           (block partials in float64);
+//   pass 3  per node: transpose of the two stencils as a gather, added to every
+//           h population (phi = sum h).
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+#include "lattice.h"
+
+namespace pfk {
+
+namespace {
+
+__device__ __forceinline__ int gwrap(int v, int n, int bc) {
+    if (bc == 0) return v < 0 ? v + n : (v >= n ? v - n : v);
+    return v < 0 ? 0 : (v >= n ? n - 1 : v);
+}
+
+struct Node {
+    int x, y, z;
+};
+
+__device__ __forceinline__ Node node_of(long long n, const AdjArgs& a) {
+    Node d;
+    d.x = (int)(n % a.nx);
+    d.y = (int)((n / a.nx) % a.ny);
+    d.z = (int)(n / ((long long)a.nx * a.ny));
+    return d;
+}
+
+__device__ __forceinline__ long long lin(const AdjArgs& a, int x, int y, int z) {
+    return ((long long)z * a.ny + y) * a.nx + x;
+}
+
+// x + c: linear index, or -1 when it lies beyond a wall
+__device__ __forceinline__ long long step_to(const AdjArgs& a, Node p, int cx, int cy, int cz) {
+    int v[3] = {p.x + cx, p.y + cy, p.z + cz};
+    const int n[3] = {a.nx, a.ny, a.nz};
+    for (int k = 0; k < 3; ++k) {
+        if (v[k] < 0 || v[k] >= n[k]) {
+            if (a.bc[k] != 0) return -1;
+            v[k] = v[k] < 0 ? v[k] + n[k] : v[k] - n[k];
+        }
+    }
+    return lin(a, v[0], v[1], v[2]);
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(256) void k_adj_phi(const AdjArgs a) {
+    const long long nn = (long long)a.nx * a.ny * a.nz;
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    double s = a.fh[n];
+    for (int al = 1; al < a.qh; ++al) s += a.fh[(size_t)al * nn + n];
+    a.phi[n] = s;
+}
+
+// pass 2: local reverse sweep of the collision
+template <class PAIR>
+__global__ __launch_bounds__(256) void k_adj_local(const AdjArgs a) {
+    using GL = typename PAIR::G;
+    using HL = typename PAIR::H;
+    constexpr int Q = GL::Q, QH = HL::Q;
+    constexpr bool D3 = PAIR::dim == 3;
+    const long long nn = (long long)a.nx * a.ny * a.nz;
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double th[3] = {0.0, 0.0, 0.0};   // d sigma, d M, d W of this node
+    if (n < nn) {
+        const Node p = node_of(n, a);
+        const Phys& ph = a.ph;
+        double g[Q], h[QH], phin[Q];
+        for (int i = 0; i < Q; ++i) g[i] = a.fg[(size_t)i * nn + n];
+        for (int al = 0; al < QH; ++al) h[al] = a.fh[(size_t)al * nn + n];
+        unroll<Q>([&](auto I) {
+            constexpr int i = I;
+            const int gx = gwrap(p.x + GL::c(i, 0), a.nx, a.bc[0]);
+            const int gy = gwrap(p.y + GL::c(i, 1), a.ny, a.bc[1]);
+            const int gz = gwrap(p.z + GL::c(i, 2), a.nz, a.bc[2]);
+            phin[i] = a.phi[lin(a, gx, gy, gz)];
+        });
+        // lambda* : adjoint of the post-collision populations (stream transpose)
+        double lg[Q], lh[QH];
+        unroll<Q>([&](auto I) {
+            constexpr int i = I;
+            const long long t = step_to(a, p, GL::c(i, 0), GL::c(i, 1), GL::c(i, 2));
+            lg[i] = t >= 0 ? a.lg[(size_t)i * nn + t] : a.lg[(size_t)GL::opp(i) * nn + n];
+        });
+        unroll<QH>([&](auto J) {
+            constexpr int al = J;
+            const long long t = step_to(a, p, HL::c(al, 0), HL::c(al, 1), HL::c(al, 2));
+            lh[al] = t >= 0 ? a.lh[(size_t)al * nn + t] : a.lh[(size_t)HL::opp(al) * nn + n];
+        });
+
+        // ---------------- forward intermediates (as in the step kernel)
+        const double phi = phin[0];
+        double gr[3] = {0.0, 0.0, 0.0}, lap = 0.0;
+        unroll<Q>([&](auto I) {
+            constexpr int i = I;
+            if constexpr (i > 0) {
+                for (int k = 0; k < 3; ++k) gr[k] += 3.0 * GL::w(i) * GL::c(i, k) * phin[i];
+                lap += 6.0 * GL::w(i) * (phin[i] - phi);
+            }
+        });
+        const double dR = ph.dRho;
+        const double rho = ph.rhoL + phi * dR;
+        const double irho = 1.0 / rho;
+        const double numu = ph.muL + phi * ph.dMu;
+        const double nu = ph.visc_mu ? numu * irho : ph.nuL + phi * ph.dNu;
+        const double tau = 3.0 * nu + 0.5;
+        const double itau = 1.0 / tau;
+        const double cub = phi * (phi - 1.0) * (phi - 0.5);
+        const double mu = ph.beta4 * cub - ph.kappa * lap;
+        double ps = 0.0, j[3] = {0.0, 0.0, 0.0}, m2[3][3] = {{0.0}};
+        unroll<Q>([&](auto I) {
+            constexpr int i = I;
+            ps += g[i];
+            for (int k = 0; k < 3; ++k) {
+                j[k] += GL::c(i, k) * g[i];
+                for (int l = 0; l < 3; ++l) m2[k][l] += GL::c(i, k) * GL::c(i, l) * g[i];
+            }
+        });
+        const double sg = mu - ps * dR / 3.0;
+        double F0[3], us[3], S[3][3], F[3], u[3];
+        for (int k = 0; k < 3; ++k) F0[k] = sg * gr[k] + rho * ph.body[k] + ph.force[k];
+        for (int k = 0; k < 3; ++k) us[k] = j[k] + F0[k] * 0.5 * irho;
+        const double s3 = ps / 3.0;
+        const double sfac = -3.0 * itau;
+        const int dmax = D3 ? 3 : 2;
+        for (int k = 0; k < 3; ++k)
+            for (int l = 0; l < 3; ++l)
+                S[k][l] = (k < dmax && l < dmax)
+                              ? sfac * (m2[k][l] - (k == l ? s3 : 0.0) - us[k] * us[l]) : 0.0;
+        const double nr = nu * dR;
+        double Sg[3];
+        for (int k = 0; k < 3; ++k) Sg[k] = S[k][0] * gr[0] + S[k][1] * gr[1] + S[k][2] * gr[2];
+        for (int k = 0; k < 3; ++k) F[k] = F0[k] + nr * Sg[k];
+        for (int k = 0; k < 3; ++k) u[k] = j[k] + F[k] * 0.5 * irho;
+        const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        const double so = ph.s_o;
+        const double dS = itau - so;
+        const double ffac = (1.0 - 0.5 * so) * 3.0 * irho;
+        const double aeq = ps - 1.5 * usq;
+        double Pi[3][3];
+        for (int k = 0; k < 3; ++k)
+            for (int l = 0; l < 3; ++l)
+                Pi[k][l] = m2[k][l] - (k == l ? s3 : 0.0) - u[k] * u[l];
+        // stress-projection coefficients (linear in Pi)
+        double A[5];
+        if constexpr (D3) {
+            A[0] = (2.0 * Pi[0][0] - Pi[1][1] - Pi[2][2]) / 36.0;
+            A[1] = (Pi[1][1] - Pi[2][2]) / 12.0;
+            A[2] = Pi[0][1] / 4.0;
+            A[3] = Pi[1][2] / 4.0;
+            A[4] = Pi[0][2] / 4.0;
+        } else {
+            A[0] = (Pi[0][0] - Pi[1][1]) / 4.0;
+            A[1] = 0.0;
+            A[2] = Pi[0][1] / 4.0;
+            A[3] = 0.0;
+            A[4] = 0.0;
+        }
+        auto qrow = [&](int i, double* q) {   // stress rows evaluated at c_i
+            const int cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
+            if (D3) {
+                q[0] = 3 * cx * cx - (cx * cx + cy * cy + cz * cz);
+                q[1] = cy * cy - cz * cz;
+            } else {
+                q[0] = cx * cx - cy * cy;
+                q[1] = 0.0;
+            }
+            q[2] = cx * cy;
+            q[3] = cy * cz;
+            q[4] = cx * cz;
+        };
+        const double gg = gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2];
+        const double rn = 1.0 / sqrt(gg + ph.eps2);
+        const double pp = phi * (1.0 - phi);
+        const double coef = ph.anti * pp * rn;
+        const double itp = ph.inv_tau_phi, gfp = ph.g_fac_phi;
+
+        // ---------------- reverse sweep
+        double b_g[Q], b_h[QH];
+        double b_phi = 0.0, b_gr[3] = {0.0, 0.0, 0.0}, b_lap = 0.0;
+        double b_u[3] = {0.0, 0.0, 0.0}, b_F[3] = {0.0, 0.0, 0.0};
+        double b_ps = 0.0, b_irho = 0.0, b_itau = 0.0, b_usq = 0.0, b_aeq = 0.0;
+        double b_coef = 0.0, b_anti = 0.0, b_itp = 0.0, b_gfp = 0.0;
+        double b_Pi[3][3] = {{0.0}};
+
+        // h*_a = (1 - itp) h_a + itp heq_a + gfp w_a coef (e_a . gr)
+        for (int al = 0; al < QH; ++al) {
+            const double w = HL::w(al);
+            const double eu = HL::c(al, 0) * u[0] + HL::c(al, 1) * u[1] + HL::c(al, 2) * u[2];
+            const double eg = HL::c(al, 0) * gr[0] + HL::c(al, 1) * gr[1] + HL::c(al, 2) * gr[2];
+            const double base = 1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * usq;
+            const double heq = w * phi * base;
+            const double lb = lh[al];
+            b_h[al] = (1.0 - itp) * lb;
+            b_itp += (heq - h[al]) * lb;
+            b_gfp += w * coef * eg * lb;
+            b_coef += gfp * w * eg * lb;
+            for (int k = 0; k < 3; ++k) b_gr[k] += gfp * w * coef * HL::c(al, k) * lb;
+            const double bheq = itp * lb;
+            b_phi += bheq * w * base;
+            for (int k = 0; k < 3; ++k)
+                b_u[k] += bheq * w * phi * (3.0 * HL::c(al, k) + 9.0 * eu * HL::c(al, k));
+            b_usq += -1.5 * bheq * w * phi;
+        }
+        // coef = anti phi (1 - phi) (gg + eps^2)^(-1/2)
+        b_anti += b_coef * pp * rn;
+        b_phi += b_coef * ph.anti * (1.0 - 2.0 * phi) * rn;
+        {
+            const double b_rn = b_coef * ph.anti * pp;
+            const double b_gg = -0.5 * rn * rn * rn * b_rn;
+            for (int k = 0; k < 3; ++k) b_gr[k] += 2.0 * gr[k] * b_gg;
+        }
+        // g*_i = (1 - so) g_i + so geq_i - dS P_i + ffac w_i (c_i . F)
+        double b_A[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        double b_dS = 0.0, b_ffac = 0.0;
+        for (int i = 0; i < Q; ++i) {
+            const double w = GL::w(i);
+            const double cu = GL::c(i, 0) * u[0] + GL::c(i, 1) * u[1] + GL::c(i, 2) * u[2];
+            const double cf = GL::c(i, 0) * F[0] + GL::c(i, 1) * F[1] + GL::c(i, 2) * F[2];
+            double q[5];
+            qrow(i, q);
+            double P = 0.0;
+            for (int k = 0; k < 5; ++k) P += q[k] * A[k];
+            const double lb = lg[i];
+            b_g[i] = (1.0 - so) * lb;
+            const double bgeq = so * lb;
+            b_aeq += w * bgeq;
+            for (int k = 0; k < 3; ++k) b_u[k] += w * bgeq * (3.0 * GL::c(i, k) + 9.0 * cu * GL::c(i, k));
+            for (int k = 0; k < 5; ++k) b_A[k] += -dS * q[k] * lb;
+            b_dS += -P * lb;
+            b_ffac += w * cf * lb;
+            for (int k = 0; k < 3; ++k) b_F[k] += ffac * w * GL::c(i, k) * lb;
+        }
+        // A (linear in Pi)
+        if constexpr (D3) {
+            b_Pi[0][0] += 2.0 * b_A[0] / 36.0;
+            b_Pi[1][1] += -b_A[0] / 36.0 + b_A[1] / 12.0;
+            b_Pi[2][2] += -b_A[0] / 36.0 - b_A[1] / 12.0;
+            b_Pi[0][1] += b_A[2] / 4.0;
+            b_Pi[1][2] += b_A[3] / 4.0;
+            b_Pi[0][2] += b_A[4] / 4.0;
+        } else {
+            b_Pi[0][0] += b_A[0] / 4.0;
+            b_Pi[1][1] += -b_A[0] / 4.0;
+            b_Pi[0][1] += b_A[2] / 4.0;
+        }
+        // Pi_kl = m2_kl - delta s3 - u_k u_l (only k <= l entries carry adjoints)
+        double b_m2[3][3] = {{0.0}}, b_s3 = 0.0;
+        for (int k = 0; k < 3; ++k)
+            for (int l = k; l < 3; ++l) {
+                const double b = b_Pi[k][l];
+                b_m2[k][l] += b;
+                if (k == l) {
+                    b_s3 -= b;
+                    b_u[k] -= 2.0 * u[k] * b;
+                } else {
+                    b_u[k] -= u[l] * b;
+                    b_u[l] -= u[k] * b;
+                }
+            }
+        // aeq = ps - 1.5 usq ; usq = u.u ; dS = itau - so ; ffac = (1 - so/2) 3 irho
+        b_ps += b_aeq;
+        b_usq += -1.5 * b_aeq;
+        for (int k = 0; k < 3; ++k) b_u[k] += 2.0 * u[k] * b_usq;
+        b_itau += b_dS;
+        b_irho += (1.0 - 0.5 * so) * 3.0 * b_ffac;
+        // u = j + F irho / 2
+        double b_j[3];
+        for (int k = 0; k < 3; ++k) {
+            b_j[k] = b_u[k];
+            b_F[k] += 0.5 * irho * b_u[k];
+            b_irho += 0.5 * F[k] * b_u[k];
+        }
+        // F = F0 + nr S gr
+        double b_F0[3], b_S[3][3] = {{0.0}}, b_nr = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            b_F0[k] = b_F[k];
+            b_nr += b_F[k] * Sg[k];
+            for (int l = 0; l < 3; ++l) {
+                b_S[k][l] += nr * b_F[k] * gr[l];
+                b_gr[l] += nr * S[k][l] * b_F[k];
+            }
+        }
+        double b_nu = b_nr * dR;
+        // S_kl = sfac (m2_kl - delta s3 - us_k us_l)  (full symmetric 3 x 3)
+        double b_us[3] = {0.0, 0.0, 0.0}, b_sfac = 0.0;
+        for (int k = 0; k < dmax; ++k)
+            for (int l = 0; l < dmax; ++l) {
+                const double b = b_S[k][l];
+                b_sfac += b * (m2[k][l] - (k == l ? s3 : 0.0) - us[k] * us[l]);
+                const double bs = sfac * b;
+                if (k <= l) b_m2[k][l] += bs;
+                else b_m2[l][k] += bs;
+                if (k == l) b_s3 -= bs;
+                b_us[k] -= bs * us[l];
+                b_us[l] -= bs * us[k];
+            }
+        b_itau += -3.0 * b_sfac;
+        b_ps += b_s3 / 3.0;
+        // us = j + F0 irho / 2
+        for (int k = 0; k < 3; ++k) {
+            b_j[k] += b_us[k];
+            b_F0[k] += 0.5 * irho * b_us[k];
+            b_irho += 0.5 * F0[k] * b_us[k];
+        }
+        // F0 = sg gr + rho body + force
+        double b_sg = 0.0, b_rho = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            b_sg += b_F0[k] * gr[k];
+            b_gr[k] += sg * b_F0[k];
+            b_rho += ph.body[k] * b_F0[k];
+        }
+        // sg = mu - ps dR / 3
+        const double b_mu = b_sg;
+        b_ps += -b_sg * dR / 3.0;
+        // moments
+        for (int i = 0; i < Q; ++i) {
+            double b = b_ps;
+            for (int k = 0; k < 3; ++k) {
+                b += GL::c(i, k) * b_j[k];
+                for (int l = k; l < 3; ++l) b += GL::c(i, k) * GL::c(i, l) * b_m2[k][l];
+            }
+            b_g[i] += b;
+        }
+        // mu = beta4 phi (phi - 1)(phi - 1/2) - kappa lap
+        const double b_beta4 = b_mu * cub;
+        const double b_kappa = -b_mu * lap;
+        b_lap += -ph.kappa * b_mu;
+        b_phi += b_mu * ph.beta4 * (3.0 * phi * phi - 3.0 * phi + 0.5);
+        // itau = 1 / tau, tau = 3 nu + 1/2
+        b_nu += 3.0 * (-itau * itau * b_itau);
+        // nu
+        if (ph.visc_mu) {
+            b_phi += ph.dMu * irho * b_nu;
+            b_irho += numu * b_nu;
+        } else {
+            b_phi += ph.dNu * b_nu;
+        }
+        // irho = 1 / rho, rho = rhoL + phi dR
+        b_rho += -irho * irho * b_irho;
+        b_phi += dR * b_rho;
+
+        // parameters: beta4 = 48 sigma / W, kappa = 1.5 sigma W, anti = 4 / W,
+        // itp = 1 / (3 M + 1/2), gfp = 1 - itp / 2
+        const double sigma = a.sigma, W = a.W;
+        th[0] = b_beta4 * 48.0 / W + b_kappa * 1.5 * W;
+        const double b_itp_tot = b_itp - 0.5 * b_gfp;
+        th[1] = -3.0 * itp * itp * b_itp_tot;
+        th[2] = -b_beta4 * 48.0 * sigma / (W * W) + b_kappa * 1.5 * sigma - b_anti * 4.0 / (W * W);
+
+        for (int i = 0; i < Q; ++i) a.og[(size_t)i * nn + n] = b_g[i];
+        for (int al = 0; al < QH; ++al) a.oh[(size_t)al * nn + n] = b_h[al];
+        a.work[n] = b_phi;
+        a.work[nn + n] = b_gr[0];
+        a.work[2 * nn + n] = b_gr[1];
+        a.work[3 * nn + n] = b_gr[2];
+        a.work[4 * nn + n] = b_lap;
+    }
+    // block sums of the parameter adjoints, fixed order
+    __shared__ double red[3][256];
+    for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = th[k];
+    __syncthreads();
+    for (int s = 128; s >= 1; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 3; ++k) a.partials[(size_t)blockIdx.x * 3 + k] = red[k][0];
+}
+
+// pass 3: transpose of grad phi(x) = 3 sum w c phi(src(x, i)) and
+// lap phi(x) = 6 sum w (phi(src(x, i)) - phi(x)), src = periodic image or wall
+// mirror of x + c_i, as a gather at y over {x : src(x, i) = y}; then every h
+// population of y receives dL/dphi(y).
+template <class PAIR>
+__global__ __launch_bounds__(256) void k_adj_stencil(const AdjArgs a) {
+    using GL = typename PAIR::G;
+    using HL = typename PAIR::H;
+    constexpr int Q = GL::Q;
+    const long long nn = (long long)a.nx * a.ny * a.nz;
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    const Node p = node_of(n, a);
+    const double* bphi = a.work;
+    const double* bgr = a.work + nn;
+    const double* blap = a.work + 4 * nn;
+    double acc = bphi[n] - 6.0 * (1.0 - GL::w(0)) * blap[n];
+    auto contrib = [&](int i, long long x) {
+        acc += 3.0 * GL::w(i) * (GL::c(i, 0) * bgr[x] + GL::c(i, 1) * bgr[nn + x] +
+                                 GL::c(i, 2) * bgr[2 * nn + x]) +
+               6.0 * GL::w(i) * blap[x];
+    };
+    const int n3[3] = {a.nx, a.ny, a.nz};
+    const int co[3] = {p.x, p.y, p.z};
+    for (int i = 1; i < Q; ++i) {
+        const int c[3] = {GL::c(i, 0), GL::c(i, 1), GL::c(i, 2)};
+        // x = y - c_i (no wall crossed)
+        const long long t = step_to(a, p, -c[0], -c[1], -c[2]);
+        if (t >= 0) contrib(i, t);
+        // at a wall layer: x on the same layer whose x + c_i is mirrored onto y
+        for (int k = 0; k < 3; ++k) {
+            if (a.bc[k] == 0 || c[k] == 0) continue;
+            const bool edge = c[k] > 0 ? co[k] == n3[k] - 1 : co[k] == 0;
+            if (!edge) continue;
+            int cc[3] = {-c[0], -c[1], -c[2]};
+            cc[k] = 0;
+            const long long t2 = step_to(a, p, cc[0], cc[1], cc[2]);
+            if (t2 >= 0) contrib(i, t2);
+        }
+    }
+    for (int al = 0; al < HL::Q; ++al) a.oh[(size_t)al * nn + n] += acc;
+}
+
+__global__ __launch_bounds__(256) void k_adj_params(const double* part, int nb, double* out) {
+    __shared__ double red[3][256];
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nb; b += 256)
+        for (int k = 0; k < 3; ++k) s[k] += part[(size_t)b * 3 + k];
+    for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = s[k];
+    __syncthreads();
+    for (int st = 128; st >= 1; st >>= 1) {
+        if ((int)threadIdx.x < st)
+            for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 3; ++k) out[k] += red[k][0];
+}
+
+// dL/dphi0 through the equilibrium initialisation h = h_eq(phi0, u0),
+// g = g_eq(3 p0 / rho(phi0), u0)
+template <class PAIR>
+__global__ __launch_bounds__(256) void k_adj_init(const AdjInitArgs a) {
+    using GL = typename PAIR::G;
+    using HL = typename PAIR::H;
+    const long long nn = (long long)a.nx * a.ny * a.nz;
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    double u[3] = {0.0, 0.0, 0.0};
+    if (a.u0) {
+        u[0] = a.u0[n];
+        u[1] = a.u0[nn + n];
+        if (PAIR::dim == 3) u[2] = a.u0[2 * nn + n];
+    }
+    const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    double s = 0.0;
+    for (int al = 0; al < HL::Q; ++al) {
+        const double eu = HL::c(al, 0) * u[0] + HL::c(al, 1) * u[1] + HL::c(al, 2) * u[2];
+        s += a.lh[(size_t)al * nn + n] * HL::w(al) * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * usq);
+    }
+    if (a.p0) {
+        const double phi = a.phi0[n];
+        const double rho = a.ph.rhoL + phi * a.ph.dRho;
+        const double dps = -3.0 * a.p0[n] * a.ph.dRho / (rho * rho);
+        for (int i = 0; i < GL::Q; ++i) s += a.lg[(size_t)i * nn + n] * GL::w(i) * dps;
+    }
+    a.dphi0[n] = s;
+}
+
+hipError_t launch_adjoint(int lattice, const AdjArgs& a, double* dparams, hipStream_t st) {
+    const long long nn = (long long)a.nx * a.ny * a.nz;
+    const dim3 grid((unsigned)((nn + 255) / 256)), block(256);
+    hipLaunchKernelGGL(k_adj_phi, grid, block, 0, st, a);
+    if (lattice == 0) {
+        hipLaunchKernelGGL(k_adj_local<Pair2D>, grid, block, 0, st, a);
+        hipLaunchKernelGGL(k_adj_stencil<Pair2D>, grid, block, 0, st, a);
+    } else {
+        hipLaunchKernelGGL(k_adj_local<Pair3D>, grid, block, 0, st, a);
+        hipLaunchKernelGGL(k_adj_stencil<Pair3D>, grid, block, 0, st, a);
+    }
+    if (dparams) hipLaunchKernelGGL(k_adj_params, dim3(1), dim3(256), 0, st, a.partials, (int)grid.x, dparams);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_init(int lattice, const AdjInitArgs& a, hipStream_t st) {
+    const long long nn = (long long)a.nx * a.ny * a.nz;
+    const dim3 grid((unsigned)((nn + 255) / 256)), block(256);
+    if (lattice == 0) hipLaunchKernelGGL(k_adj_init<Pair2D>, grid, block, 0, st, a);
+    else hipLaunchKernelGGL(k_adj_init<Pair3D>, grid, block, 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace pfk

@@ -104,7 +104,38 @@ struct IOArgs {
     double gcorr[2][MAXQ];
 };
 
-// launchers (kernels.hip); return hipSuccess or the launch error
+// discrete adjoint of one AC step on canonical float64 arrays [q][z][y][x]
+struct AdjArgs {
+    const double* fg;      // forward state X^n (post-streaming)
+    const double* fh;
+    const double* lg;      // lambda^{n+1}
+    const double* lh;
+    double* og;            // lambda^n (must not alias lg / lh)
+    double* oh;
+    double* phi;           // workspace [nodes]
+    double* work;          // workspace [5][nodes]
+    double* partials;      // workspace [blocks][3]
+    int nx, ny, nz;
+    int bc[3];
+    int qh;
+    double sigma, W;
+    Phys ph;
+};
+
+struct AdjInitArgs {
+    const double* lg;
+    const double* lh;
+    const double* phi0;
+    const double* u0;      // may be null
+    const double* p0;      // may be null
+    double* dphi0;
+    int nx, ny, nz;
+    Phys ph;
+};
+
+// launchers (kernels.hip, adjoint.hip); return hipSuccess or the launch error
+hipError_t launch_adjoint(int lattice, const AdjArgs& a, double* dparams, hipStream_t s);
+hipError_t launch_adjoint_init(int lattice, const AdjInitArgs& a, hipStream_t s);
 hipError_t launch_step(int lattice, int model, int precision, int parity, int mode,
                        const KArgs& a, hipStream_t s);
 hipError_t launch_init(int lattice, int model, int precision, const InitArgs& a, hipStream_t s);

@@ -477,4 +477,71 @@ int pflbm_load_state(pflbm_t* h, const void* dev_src) {
     return PFLBM_OK;
 }
 
+static size_t adj_nodes(const pflbm_t* h) { return (size_t)h->p.nx * h->p.ny * h->p.nz; }
+
+int pflbm_adjoint_workspace_bytes(const pflbm_t* h, size_t* bytes) {
+    if (!h || !bytes) return PFLBM_EINVAL;
+    const size_t nn = adj_nodes(h);
+    const size_t blocks = (nn + 255) / 256;
+    *bytes = align_up(nn * 8, 256) + align_up(5 * nn * 8, 256) + align_up(blocks * 3 * 8, 256);
+    return PFLBM_OK;
+}
+
+int pflbm_adjoint_step(pflbm_t* h, const double* fwd_g, const double* fwd_h, const double* lam_g,
+                       const double* lam_h, double* lam_g_out, double* lam_h_out, double* dparams,
+                       void* work) {
+    int st = guard(h);
+    if (st) return st;
+    if (h->p.model != PFLBM_AC) return fail(h, PFLBM_EUNSUPPORTED, "adjoint implemented for the AC model only");
+    if (h->p.freeze_phi) return fail(h, PFLBM_EUNSUPPORTED, "adjoint of a frozen phase field is not implemented");
+    if (!fwd_g || !fwd_h || !lam_g || !lam_h || !lam_g_out || !lam_h_out || !work)
+        return fail(h, PFLBM_EINVAL, "null pointer");
+    if (lam_g_out == lam_g || lam_h_out == lam_h) return fail(h, PFLBM_EINVAL, "lambda in and out must not alias");
+    const size_t nn = adj_nodes(h);
+    AdjArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.fg = fwd_g;
+    a.fh = fwd_h;
+    a.lg = lam_g;
+    a.lh = lam_h;
+    a.og = lam_g_out;
+    a.oh = lam_h_out;
+    char* w = (char*)work;
+    a.phi = (double*)w;
+    a.work = (double*)(w + align_up(nn * 8, 256));
+    a.partials = (double*)(w + align_up(nn * 8, 256) + align_up(5 * nn * 8, 256));
+    a.nx = h->p.nx;
+    a.ny = h->p.ny;
+    a.nz = h->p.nz;
+    for (int k = 0; k < 3; ++k) a.bc[k] = h->p.bc[k];
+    a.qh = h->L.Qh;
+    a.sigma = h->p.sigma;
+    a.W = h->p.W;
+    a.ph = h->ph;
+    HIPCHK(h, launch_adjoint(h->p.lattice, a, dparams, h->stream), "adjoint kernels");
+    return PFLBM_OK;
+}
+
+int pflbm_adjoint_init(pflbm_t* h, const double* phi0, const double* u0, const double* p0,
+                       const double* lam_g, const double* lam_h, double* dphi0) {
+    int st = guard(h);
+    if (st) return st;
+    if (h->p.model != PFLBM_AC) return fail(h, PFLBM_EUNSUPPORTED, "adjoint implemented for the AC model only");
+    if (!phi0 || !lam_g || !lam_h || !dphi0) return fail(h, PFLBM_EINVAL, "null pointer");
+    AdjInitArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.lg = lam_g;
+    a.lh = lam_h;
+    a.phi0 = phi0;
+    a.u0 = u0;
+    a.p0 = p0;
+    a.dphi0 = dphi0;
+    a.nx = h->p.nx;
+    a.ny = h->p.ny;
+    a.nz = h->p.nz;
+    a.ph = h->ph;
+    HIPCHK(h, launch_adjoint_init(h->p.lattice, a, h->stream), "adjoint init kernel");
+    return PFLBM_OK;
+}
+
 }  // extern "C"

@@ -118,3 +118,25 @@ class Solver:
 
     def load_state(self, buf):
         self._check(self.L.pflbm_load_state(self.h, _ptr(buf)), self.h)
+
+    # ---- discrete adjoint (AC model)
+    def adjoint_workspace(self):
+        n = ctypes.c_size_t()
+        self._check(self.L.pflbm_adjoint_workspace_bytes(self.h, ctypes.byref(n)), self.h)
+        return torch.empty(n.value, dtype=torch.uint8, device=self.device)
+
+    def adjoint_step(self, fwd_g, fwd_h, lam_g, lam_h, out_g, out_h, dparams, work):
+        """lambda^n (out_g, out_h) from lambda^{n+1} (lam_g, lam_h) at the forward
+        state (fwd_g, fwd_h); adds dL/d(sigma, M, W) into dparams (float64 [3])."""
+        self._check(self.L.pflbm_adjoint_step(self.h, _ptr(fwd_g), _ptr(fwd_h), _ptr(lam_g),
+                                              _ptr(lam_h), _ptr(out_g), _ptr(out_h),
+                                              _ptr(dparams), _ptr(work)), self.h)
+
+    def adjoint_init(self, phi0, u0, p0, lam_g, lam_h):
+        phi = self._dev(phi0, self.shape)
+        u = self._dev(u0, (self.dim,) + self.shape)
+        pr = self._dev(p0, self.shape)
+        out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        self._check(self.L.pflbm_adjoint_init(self.h, _ptr(phi), _ptr(u), _ptr(pr), _ptr(lam_g),
+                                              _ptr(lam_h), _ptr(out)), self.h)
+        return out
