@@ -2,11 +2,13 @@
 
 Workload: 3-D droplet in a Taylor-Green vortex, D3Q19 + D3Q7, 256^3 periodic,
 conservative Allen-Cahn, u0 = 0.05, Re = 1000, R = 40, rho ratio 10, W = 4,
-M = 0.05, We = 10; g stored as fp16 of 4096 g_i / w_i, h in fp32, fp32
-arithmetic (the headline form), with the fp32 and fp64 forms timed beside it
-and the mixed and fp32 errors against the fp64 run stated.
+M = 0.05, We = 10. Headline form: g stored as fp16 of 4096 g_i / w_i, h in
+fp32, fp32 arithmetic; the fp64, fp32 and bf16-stored forms are timed beside
+it, and the per-field error of every reduced form against the fp64 form (whose
+parity with the oracle the test-suite establishes) is stated, on this workload
+and on a laminar one (a sheared droplet between moving walls).
 
-Prints ONE JSON line (see the repository's benchmark contract).
+Prints ONE JSON line.
 """
 import argparse
 import json
@@ -19,11 +21,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0   # MI355X HBM3E, GB/s
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_tgv256.json")
 
 
 def bytes_per_update(d, precision):
     """Algorithmic HBM bytes of one lattice update: every stored population
-    read once and written once (AC on D3Q7 stores 6 phase-field populations)."""
+    read once and written once (AC on D3Q7 stores 6 phase-field populations;
+    CH also carries the 3 components of (phi u))."""
     d3 = d["lattice"] == "D3Q19_D3Q7"
     qg = 19 if d3 else 9
     qh = (6 if d["model"] == "AC" else 7) if d3 else 5
@@ -48,19 +52,36 @@ def time_form(d, phi, u, precision, steps, warmup, zblock=0):
     ev1.record(s.stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms = ev0.elapsed_time(ev1)
-    return s, ms / steps, wall
+    return s, ev0.elapsed_time(ev1) / steps, wall
 
 
-def rel_l2(a, b):
+def field_errors(d, phi, u, steps, forms):
+    """Relative L2 error per field (phi, |u| vector, p) of each form against
+    the fp64 form after `steps` steps from the same initial state."""
     import torch
-    return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+    from paper_2511_11360_amd.solver import Solver
+    out = {}
+    ref = None
+    for prec in ["fp64"] + list(forms):
+        s = Solver(d, precision=prec)
+        s.init(phi, u)
+        s.step(steps)
+        f = s.fields()
+        if prec == "fp64":
+            ref = f
+        else:
+            e = {}
+            for name, a, b in (("phi", f[0], ref[0]), ("u", f[1], ref[1]), ("p", f[2], ref[2])):
+                e[name] = float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+            out[prec] = e
+        del s
+        torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(seconds=12.0):
     """Oracle (plain numpy, float64) on a bounded sample of the same workload:
     the 64^3 instance of the droplet-in-vortex case, single BLAS thread."""
-    import numpy as np
     from threadpoolctl import threadpool_limits
     from oracle import model as om
     from paper_2511_11360_amd import workloads as wl
@@ -79,8 +100,26 @@ def cpu_baseline(seconds=12.0):
                 break
     nodes = 64 ** 3
     return {"value": round(nodes * n / el / 1e6, 4), "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": "64^3 instance of the same workload, %d steps, %.1f s, numpy float64, "
-                      "1 thread" % (n, el)}
+            "sample": "64^3 instance of the same droplet-in-vortex workload (R scaled to 10), "
+                      "%d steps in %.1f s, numpy float64, one thread" % (n, el)}
+
+
+def measured_traffic(precision):
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None."""
+    from paper_2511_11360_amd import profiling
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        t = json.load(f)
+    if t.get("kernel_source_sha256") != profiling.kernel_source_hash():
+        return None
+    code = {"fp64": 0, "fp32": 1, "mixed_fp16": 2, "mixed_bf16": 3}[precision]
+    vals = [v["fetch"] + v["write"] for k, v in t["per_dispatch_bytes"].items()
+            if "Pair3D, 0, %d," % code in k and v["fetch"] is not None and v["write"] is not None]
+    if not vals:
+        return None
+    return sum(vals) / len(vals)
 
 
 def main():
@@ -95,6 +134,8 @@ def main():
     ap.add_argument("--err-steps", type=int, default=500)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a plain 1 GiB device copy first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -105,6 +146,13 @@ def main():
     from paper_2511_11360_amd import workloads as wl
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(2):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     d, phi, u = wl.taylor_green_droplet_3d(n=args.n, We=args.We)
     nodes = args.n ** 3
 
@@ -118,34 +166,34 @@ def main():
     torch.cuda.empty_cache()
 
     forms = {}
+    errors = {}
     if not args.no_forms:
-        ref = None
-        for prec in ("fp64", "fp32", args.precision):
+        for prec in ("fp64", "fp32", "mixed_fp16", "mixed_bf16"):
             print("bench: form %s" % prec, file=sys.stderr, flush=True)
-            sf, msf, _ = time_form(d, phi, u, prec, max(50, args.steps // 3), 10, args.zblock)
+            sf, msf, _ = time_form(d, phi, u, prec, max(60, args.steps // 3), 10, args.zblock)
             b = bytes_per_update(d, prec)
-            ent = {"MLUPS": round(nodes / (msf * 1e-3) / 1e6, 1),
-                   "ms_per_step": round(msf, 4), "bytes_per_update": b,
-                   "hbm_frac": round(b * nodes / (msf * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
-            # error after err_steps steps from the same initial state, against fp64
-            sf.init(phi, u)
-            sf.step(args.err_steps)
-            phi_f, u_f, _, _ = sf.fields()
-            if prec == "fp64":
-                ref = (phi_f, u_f)
-            else:
-                ent["rel_l2_phi_vs_fp64"] = rel_l2(phi_f, ref[0])
-                ent["rel_l2_u_vs_fp64"] = rel_l2(u_f, ref[1])
-                ent["err_steps"] = args.err_steps
-            forms[prec] = ent
+            forms[prec] = {"MLUPS": round(nodes / (msf * 1e-3) / 1e6, 1), "ms_per_step": round(msf, 4),
+                           "bytes_per_update": b,
+                           "hbm_frac": round(b * nodes / (msf * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
             del sf
             torch.cuda.empty_cache()
+        for k in ("fp32", "mixed_fp16", "mixed_bf16"):
+            forms[k]["speedup_vs_fp64"] = round(forms[k]["MLUPS"] / forms["fp64"]["MLUPS"], 3)
+            forms[k]["speedup_vs_fp32"] = round(forms[k]["MLUPS"] / forms["fp32"]["MLUPS"], 3)
+        print("bench: errors against fp64", file=sys.stderr, flush=True)
+        errors["this_workload"] = {"steps": args.err_steps,
+                                   "rel_l2": field_errors(d, phi, u, args.err_steps,
+                                                          ("fp32", "mixed_fp16", "mixed_bf16"))}
+        dl, phl, ul, _ = wl.sheared_droplet_3d(n=64, R=16.0, W=4.0)
+        errors["laminar_sheared_droplet_64"] = {
+            "steps": 1000, "rel_l2": field_errors(dl, phl, ul, 1000, ("fp32", "mixed_fp16", "mixed_bf16"))}
 
     cpu = None
     if not args.no_cpu:
         print("bench: oracle cpu baseline", file=sys.stderr, flush=True)
         cpu = cpu_baseline()
 
+    traffic = measured_traffic(args.precision)
     out = {
         "metric": "coupled PF-LB MLUPS + % HBM roofline; mixed-prec vs FP64/FP32 at stated error",
         "value": round(mlups, 1),
@@ -160,13 +208,21 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f32",
         "data": "synthetic",
         "config": {"workload": "3-D droplet in Taylor-Green vortex, D3Q19+D3Q7, %d^3 periodic, "
-                               "conservative AC, We=%g, rho ratio 10, R=40, W=4, M=0.05" % (args.n, args.We),
-                   "storage": args.precision, "nodes": nodes, "parallelism": "single GPU"},
+                               "conservative AC, u0=0.05, Re=1000, R=40, rho ratio 10, W=4, M=0.05, "
+                               "We=%g" % (args.n, args.We),
+                   "storage": {"mixed_fp16": "g fp16 (4096 g/w), h fp32",
+                               "mixed_bf16": "g bf16 (g/w), h fp32",
+                               "fp32": "g, h fp32", "fp64": "g, h fp64"}[args.precision],
+                   "nodes": nodes, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic),
+                     "traffic_unit": "bytes per launch",
+                     "algorithmic_bytes_per_launch": bpu * nodes,
                      "bytes_per_update": bpu},
         "cpu_baseline": cpu,
         "forms": forms,
+        "errors_vs_fp64": errors,
         "wall_s_timed": round(wall, 3),
     }
     print(json.dumps(out))
