@@ -450,7 +450,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
     constexpr int QHS = QH - HOFF;
     constexpr int PW = TILE_X + 2, PSZ = PW * (TILE_Y + 2);
     constexpr int NRING = 2 * PW + 2 * TILE_Y;         // halo ring of the tile
-    constexpr int NPL = D3 ? 3 : 1;
+    constexpr int NPL = D3 ? 4 : 1;
     __shared__ T lphi[NPL * PSZ];
 
     const int b = xcd_remap(blockIdx.x, gridDim.x);
@@ -488,18 +488,22 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
         for (int dy = 0; dy < 3; ++dy)
             for (int dx = 0; dx < 3; ++dx) cl.off[dy][dx] = oy[dy] * nx + ox[dx];
     }
-    // halo ring position this thread fills (threads 0 .. NRING-1)
-    int ring_off = 0, ring_lds = 0;
-    const bool ring = threadIdx.x < NRING;
-    if (ring) {
-        const int r = threadIdx.x;
-        int hx, hy;
+    // halo ring positions this thread fills (ring index threadIdx.x + k BLOCK)
+    static_assert(NRING <= 2 * BLOCK, "halo ring larger than two passes");
+    constexpr int NR = (NRING + BLOCK - 1) / BLOCK;
+    int ring_off[NR], ring_lds[NR];
+    bool ring[NR];
+    for (int k = 0; k < NR; ++k) {
+        const int r = threadIdx.x + k * BLOCK;
+        ring[k] = r < NRING;
+        int hx = 0, hy = 0;
         if (r < PW) { hx = r - 1; hy = -1; }
         else if (r < 2 * PW) { hx = r - PW - 1; hy = TILE_Y; }
         else if (r < 2 * PW + TILE_Y) { hx = -1; hy = r - 2 * PW; }
         else { hx = TILE_X; hy = r - 2 * PW - TILE_Y; }
-        ring_off = ghost_coord(y0 + hy, ny, a.bc[1]) * nx + ghost_coord(x0 + hx, nx, a.bc[0]);
-        ring_lds = (hy + 1) * PW + (hx + 1);
+        if (!ring[k]) { hx = 0; hy = 0; }
+        ring_off[k] = ghost_coord(y0 + hy, ny, a.bc[1]) * nx + ghost_coord(x0 + hx, nx, a.bc[0]);
+        ring_lds[k] = (hy + 1) * PW + (hx + 1);
     }
     const int own_lds = (ly + 1) * PW + (lx + 1);
 
@@ -519,13 +523,15 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
             s += v;
         });
         lphi[slot * PSZ + own_lds] = s;
-        if (ring) {
-            T sr = (T)0;
-            unroll<QHS>([&](auto J) {
-                constexpr int jj = J;
-                sr += (T)at<QHS>(Hin, gz, jj, P, ring_off);
-            });
-            lphi[slot * PSZ + ring_lds] = sr;
+        for (int k = 0; k < NR; ++k) {
+            if (ring[k]) {
+                T sr = (T)0;
+                unroll<QHS>([&](auto J) {
+                    constexpr int jj = J;
+                    sr += (T)at<QHS>(Hin, gz, jj, P, ring_off[k]);
+                });
+                lphi[slot * PSZ + ring_lds[k]] = sr;
+            }
         }
     };
 
@@ -582,18 +588,19 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
         NodeOut<T> mo;
         T pu_new[3];
         if constexpr (MODE == MODE_STEP) {
-            // g: AA in place
+            // g: AA in place; outputs are streamed (non-temporal stores): no
+            // workgroup reads them again within this step
             auto gsink = [&](auto I, T v) {
                 constexpr int i = I;
                 constexpr int o = GL::opp(i);
                 if constexpr (PARITY == 0) {
-                    at<QG>(G, z, o, P, o11) = GC::template enc<GL, o, GS, T>(v);
+                    __builtin_nontemporal_store(GC::template enc<GL, o, GS, T>(v), &at<QG>(G, z, o, P, o11));
                 } else {
                     constexpr int cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
                     const size_t enb = el<QG>(zp.zk[1 + cz], i, cl.off[1 + cy][1 + cx], P);
                     if constexpr (!WALLS) {
-                        at<QG>(G, zp.zk[1 + cz], i, P, cl.off[1 + cy][1 + cx]) =
-                            GC::template enc<GL, i, GS, T>(v);
+                        __builtin_nontemporal_store(GC::template enc<GL, i, GS, T>(v),
+                                                    &at<QG>(G, zp.zk[1 + cz], i, P, cl.off[1 + cy][1 + cx]));
                     } else {
                         int side;
                         const bool w = beyond<GL, i, 1>(cl, zp, side);
@@ -616,7 +623,8 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
                             const bool w = beyond<HL, al, 1>(cl, zp, side);
                             Hout[w ? el<QHS>(z, o - HOFF, o11, P) : enb] = (HS)v;
                         } else {
-                            at<QHS>(Hout, zp.zk[1 + ez], al - HOFF, P, cl.off[1 + ey][1 + ex]) = (HS)v;
+                            __builtin_nontemporal_store(
+                                (HS)v, &at<QHS>(Hout, zp.zk[1 + ez], al - HOFF, P, cl.off[1 + ey][1 + ex]));
                         }
                     }
                 }
@@ -676,17 +684,19 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
 
     T hc[QH];
     if constexpr (D3) {
+        // ring of 4 phi planes: plane zz lives in slot (zz - zs + 1) & 3. While a
+        // wave fills plane z + 2, the slowest wave may still read planes z - 1 ..
+        // z + 1, never slot (z + 2) & 3, so one barrier per plane suffices.
         fill_plane(zs - 1, 0);
         fill_plane(zs, 1);
         unroll<QH>([&](auto J) { constexpr int al = J; hc[al] = hn[al]; });
         for (int z = zs; z < ze; ++z) {
             const int r = z - zs;
-            fill_plane(z + 1, (r + 2) % 3);
+            fill_plane(z + 1, (r + 2) & 3);
             __syncthreads();
-            if (active) do_node(z, hc, lphi + (r % 3) * PSZ, lphi + ((r + 1) % 3) * PSZ,
-                                lphi + ((r + 2) % 3) * PSZ);
+            if (active) do_node(z, hc, lphi + (r & 3) * PSZ, lphi + ((r + 1) & 3) * PSZ,
+                                lphi + ((r + 2) & 3) * PSZ);
             unroll<QH>([&](auto J) { constexpr int al = J; hc[al] = hn[al]; });
-            __syncthreads();
         }
     } else {
         fill_plane(0, 0);

@@ -92,7 +92,7 @@ Layout make_layout(const pflbm_params& p) {
     L.ntx = (p.nx + TILE_X - 1) / TILE_X;
     L.nty = (p.ny + TILE_Y - 1) / TILE_Y;
     if (d3) {
-        L.zb = p.zblock > 0 ? p.zblock : 16;
+        L.zb = p.zblock > 0 ? p.zblock : 8;
         if (L.zb > p.nz) L.zb = p.nz;
     } else {
         L.zb = 1;
@@ -261,7 +261,7 @@ int pflbm_create(const pflbm_params* params, void* hip_stream, void* dev_state, 
     h->L = L;
     h->stream = (hipStream_t)hip_stream;
     h->base = (char*)dev_state;
-    hipGetDevice(&h->device);
+    if (hipGetDevice(&h->device) != hipSuccess) h->device = -1;
     const pflbm_params& p = h->p;
     for (int a = 0; a < 3; ++a)
         if (p.bc[a] == PFLBM_WALL) h->wall_axis = a;

@@ -191,7 +191,9 @@ def droplet_turbulence_3d(n=512, ndrop=64, R=16.0, We=5.0, W=4.0, M=0.05, ratio=
                           urms=0.04, k0=4.0, nu=None, seed_u=5, seed_pos=55):
     """Droplet-laden decaying isotropic turbulence: n^3 periodic, ndrop heavy
     droplets of radius R at seeded non-overlapping positions (minimum centre
-    distance 2R + 2W), We = rho_H urms^2 (2R) / sigma."""
+    distance 2R + 2W), We = rho_H urms^2 (2R) / sigma. Each droplet's tanh
+    profile is evaluated in a periodic box of half-width R + 6W around it
+    (beyond it the profile is below 1e-10); overlapping tails combine by max."""
     rho_L = 1.0
     rho_H = ratio
     sigma = rho_H * urms * urms * 2 * R / We
@@ -214,8 +216,14 @@ def droplet_turbulence_3d(n=512, ndrop=64, R=16.0, We=5.0, W=4.0, M=0.05, ratio=
         if ok:
             centres.append(c)
     phi = np.zeros((n, n, n))
+    h = int(np.ceil(R + 6 * W))
     for c in centres:
-        phi = np.maximum(phi, droplet_phi(p, c, R))
+        idx = [np.arange(int(np.floor(ci)) - h, int(np.floor(ci)) + h + 2) for ci in c]
+        dx = [(ix - ci) for ix, ci in zip(idx, c)]
+        r = np.sqrt(dx[2][:, None, None] ** 2 + dx[1][None, :, None] ** 2 + dx[0][None, None, :] ** 2)
+        local = 0.5 + 0.5 * np.tanh(2.0 * (R - r) / W)
+        sl = np.ix_(idx[2] % n, idx[1] % n, idx[0] % n)
+        phi[sl] = np.maximum(phi[sl], local)
     u = random_spectrum_velocity(n, k0=k0, urms=urms, seed=seed_u)
     return p, phi, u, np.array(centres)
 
