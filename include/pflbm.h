@@ -129,7 +129,12 @@ typedef struct pflbm_diag {
 
 typedef struct pflbm pflbm_t;
 
-/* Bytes of the device state buffer for these parameters. Host pointers. */
+/* Bytes of the device state buffer for these parameters. Host pointers.
+   The buffer holds two copies of each distribution in its storage form
+   (plane-major [z][q][y][x], planes padded to a multiple of 64 nodes): a step
+   reads the previous step's post-collision populations from one, pulling
+   population i of node x from node x - c_i, and writes its own post-collision
+   populations at x into the other. */
 int pflbm_state_bytes(const pflbm_params* params, size_t* bytes);
 
 /* Validate params and bind a handle to the caller's device buffer dev_state
@@ -159,7 +164,7 @@ int pflbm_fields(pflbm_t* h, double* phi, double* u, double* p, double* rho);
 int pflbm_volume(pflbm_t* h, const double* centre, double R, pflbm_diag* out);
 
 /* Copy the post-streaming distributions out as canonical float64 (decoding
-   the storage form and the in-place streaming layout). Device pointers
+   the storage form and applying the pending streaming). Device pointers
    g [Qg][z][y][x] and hd [Qh][z][y][x] (Qh = 5 or 7, rest included). */
 int pflbm_get_distributions(pflbm_t* h, double* g, double* hd);
 
@@ -173,7 +178,7 @@ int pflbm_set_distributions(pflbm_t* h, const double* g, const double* hd);
 int pflbm_step_count(const pflbm_t* h, long long* steps);
 
 /* Checkpoint: raw copy of the native state (distributions in their storage
-   form, layout parity, step counter, CH state) to/from a caller-owned device
+   form, step counter, CH state) to/from a caller-owned device
    buffer of pflbm_checkpoint_bytes() bytes. */
 int pflbm_checkpoint_bytes(const pflbm_t* h, size_t* bytes);
 int pflbm_save_state(pflbm_t* h, void* dev_dst);

@@ -53,8 +53,16 @@ __host__ __device__ inline PhysT<float> to_float(const PhysT<T>& d) {
 // Device layout of every population array: plane-major [z][q][y][x], each
 // population plane padded to P elements, so plane z of an array with Q
 // populations starts at element z * Q * P.
+//
+// Streaming is a pull between two buffers per distribution: a buffer holds the
+// post-collision populations of the previous step at their own node, slot i.
+// The step loads population i of node x from node x - c_i (a node beyond a
+// wall gives the bounce-back of slot opp(i) of x itself) and stores its
+// post-collision populations at x in the other buffer, so every store is
+// aligned to the node and only loads are shifted.
 struct KArgs {
-    void* g;               // AA in-place hydrodynamic populations [z][Qg][P]
+    const void* gin;       // hydrodynamic populations read this step [z][Qg][P]
+    void* gout;            // hydrodynamic populations written this step [z][Qg][P]
     const void* hin;       // phase-field populations read this step [z][Qhs][P]
     void* hout;            // phase-field populations written this step [z][Qhs][P]
     void* phiu;            // CH (phi u) of the previous step [z][3][P], compute type
@@ -79,7 +87,7 @@ struct KArgs {
 };
 
 struct InitArgs {
-    void* g;
+    void* g;               // the buffers the first step reads
     void* h;
     void* phiu;
     const double* phi0;
@@ -88,19 +96,19 @@ struct InitArgs {
     int P;
     int nx, ny, nz;
     int bc[3];
+    double gcorr[2][MAXQ]; // moving-wall terms (see KArgs)
     Phys ph;
 };
 
 struct IOArgs {
-    void* g;               // native state
+    void* g;               // current hydrodynamic buffer (post-collision, unstreamed)
     void* h;               // current phase-field buffer
-    double* cg;            // canonical float64 g [Qg][nodes]
+    double* cg;            // canonical float64 g [Qg][nodes] (post-streaming)
     double* ch;            // canonical float64 h [Qh][nodes]
     int P;
     int nx, ny, nz;
     int bc[3];
     int wall_axis;
-    int parity;            // layout parity of g (0: natural slots)
     double gcorr[2][MAXQ];
 };
 
@@ -136,12 +144,11 @@ struct AdjInitArgs {
 // launchers (kernels.hip, adjoint.hip); return hipSuccess or the launch error
 hipError_t launch_adjoint(int lattice, const AdjArgs& a, double* dparams, hipStream_t s);
 hipError_t launch_adjoint_init(int lattice, const AdjInitArgs& a, hipStream_t s);
-hipError_t launch_step(int lattice, int model, int precision, int parity, int mode,
-                       const KArgs& a, hipStream_t s);
+hipError_t launch_step(int lattice, int model, int precision, int mode, const KArgs& a, hipStream_t s);
 hipError_t launch_init(int lattice, int model, int precision, const InitArgs& a, hipStream_t s);
 hipError_t launch_get(int lattice, int model, int precision, const IOArgs& a, hipStream_t s);
 hipError_t launch_set(int lattice, int model, int precision, const IOArgs& a, hipStream_t s);
 hipError_t launch_reduce(const double* partials, int nblocks, double* out, hipStream_t s);
-hipError_t launch_header(void* dst, long long steps, int parity, int hcur, hipStream_t s);
+hipError_t launch_header(void* dst, long long steps, hipStream_t s);
 
 }  // namespace pfk

@@ -435,8 +435,63 @@ __device__ __forceinline__ bool beyond(const Column& cl, const ZPlanes& zp, int&
     return w;
 }
 
+// In-plane offset of a node and of its four axis neighbours (wrapped; the
+// node itself on a wall side), with the wall flags of those neighbours.
+struct Cross {
+    int c, xm, xp, ym, yp;
+    bool wxm, wxp, wym, wyp;
+};
+
+__device__ __forceinline__ Cross make_cross(int px, int py, int nx, int ny, const int* bc) {
+    int ox[3], oy[3];
+    bool wx[2], wy[2];
+    axis_nb(px, nx, bc[0], ox, wx);
+    axis_nb(py, ny, bc[1], oy, wy);
+    Cross X;
+    X.c = py * nx + px;
+    X.xm = py * nx + ox[0];
+    X.xp = py * nx + ox[2];
+    X.ym = oy[0] * nx + px;
+    X.yp = oy[2] * nx + px;
+    X.wxm = wx[0];
+    X.wxp = wx[1];
+    X.wym = wy[0];
+    X.wyp = wy[1];
+    return X;
+}
+
+__device__ __forceinline__ ZPlanes make_zplanes(int z, int nz, int bc) {
+    ZPlanes zp;
+    int oz[3];
+    axis_nb(z, nz, bc, oz, zp.wz);
+    zp.zk[0] = oz[0];
+    zp.zk[1] = oz[1];
+    zp.zk[2] = oz[2];
+    return zp;
+}
+
+// Post-streaming phase-field population al at the node of X in plane zp.zk[1]:
+// pulled from the node x - e_al of the previous step's post-collision buffer,
+// or, if that node lies beyond a wall, the bounce-back of slot opp(al) here.
+// D3Q7 / D2Q5 velocities are axis-aligned: one component at most is nonzero.
+template <class HL, int al, int HOFF, int WALLS, class T, class HS>
+__device__ __forceinline__ T pull_h(const HS* __restrict__ H, const Cross& X, const ZPlanes& zp, int P) {
+    constexpr int ex = HL::c(al, 0), ey = HL::c(al, 1), ez = HL::c(al, 2);
+    constexpr int QS = HL::Q - HOFF;
+    const int off = ex > 0 ? X.xm : (ex < 0 ? X.xp : (ey > 0 ? X.ym : (ey < 0 ? X.yp : X.c)));
+    if constexpr (WALLS) {
+        const bool w = (ex > 0 && X.wxm) || (ex < 0 && X.wxp) || (ey > 0 && X.wym) || (ey < 0 && X.wyp) ||
+                       (ez > 0 && zp.wz[0]) || (ez < 0 && zp.wz[1]);
+        constexpr int o = HL::opp(al);
+        const size_t e = w ? el<QS>(zp.zk[1], o - HOFF, X.c, P) : el<QS>(zp.zk[1 - ez], al - HOFF, off, P);
+        return (T)H[e];
+    } else {
+        return (T)at<QS>(H, zp.zk[1 - ez], al - HOFF, P, off);
+    }
+}
+
 // WALLS = 0: every axis periodic (no bounce-back selects are compiled).
-template <class PAIR, int MODEL, int PREC, int PARITY, int MODE, int WALLS>
+template <class PAIR, int MODEL, int PREC, int MODE, int WALLS>
 __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
     using GL = typename PAIR::G;
     using HL = typename PAIR::H;
@@ -463,7 +518,8 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
     const int x = x0 + lx, y = y0 + ly;
     const bool active = x < a.nx && y < a.ny;
     const int nx = a.nx, ny = a.ny, nz = a.nz, P = a.P;
-    GS* __restrict__ G = (GS*)a.g;
+    const GS* __restrict__ Gin = (const GS*)a.gin;
+    GS* __restrict__ Gout = (GS*)a.gout;
     const HS* __restrict__ Hin = (const HS*)a.hin;
     HS* __restrict__ Hout = (HS*)a.hout;
     T* __restrict__ PU = (T*)a.phiu;
@@ -479,7 +535,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
 
     // the thread's own tile position, wrapped or clamped (inactive threads fill
     // the halo of the domain edge with it)
-    const int own = ghost_coord(y, ny, a.bc[1]) * nx + ghost_coord(x, nx, a.bc[0]);
+    const Cross ocr = make_cross(ghost_coord(x, nx, a.bc[0]), ghost_coord(y, ny, a.bc[1]), nx, ny, a.bc);
     Column cl;
     {
         int ox[3], oy[3];
@@ -489,9 +545,9 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
             for (int dx = 0; dx < 3; ++dx) cl.off[dy][dx] = oy[dy] * nx + ox[dx];
     }
     // halo ring positions this thread fills (ring index threadIdx.x + k BLOCK)
-    static_assert(NRING <= 2 * BLOCK, "halo ring larger than two passes");
     constexpr int NR = (NRING + BLOCK - 1) / BLOCK;
-    int ring_off[NR], ring_lds[NR];
+    Cross rcr[NR];
+    int ring_lds[NR];
     bool ring[NR];
     for (int k = 0; k < NR; ++k) {
         const int r = threadIdx.x + k * BLOCK;
@@ -502,7 +558,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
         else if (r < 2 * PW + TILE_Y) { hx = -1; hy = r - 2 * PW; }
         else { hx = TILE_X; hy = r - 2 * PW - TILE_Y; }
         if (!ring[k]) { hx = 0; hy = 0; }
-        ring_off[k] = ghost_coord(y0 + hy, ny, a.bc[1]) * nx + ghost_coord(x0 + hx, nx, a.bc[0]);
+        rcr[k] = make_cross(ghost_coord(x0 + hx, nx, a.bc[0]), ghost_coord(y0 + hy, ny, a.bc[1]), nx, ny, a.bc);
         ring_lds[k] = (hy + 1) * PW + (hx + 1);
     }
     const int own_lds = (ly + 1) * PW + (lx + 1);
@@ -510,64 +566,58 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
     DiagAcc acc;
     if constexpr (MODE == MODE_DIAG) diag_init(acc);
 
-    // phi of plane zz into LDS slot; returns the thread's own h of that plane
+    // phi of plane zz into LDS slot; returns the thread's own h of that plane.
+    // phi = sum of the post-streaming h, pulled from the previous step's buffer.
     T hn[QH];
     auto fill_plane = [&](int zz, int slot) {
-        const int gz = D3 ? ghost_coord(zz, nz, a.bc[2]) : 0;
+        const int zu = __builtin_amdgcn_readfirstlane(zz);
+        const ZPlanes fz = make_zplanes(D3 ? ghost_coord(zu, nz, a.bc[2]) : 0, nz, a.bc[2]);
+        // every load of the plane first (ring loads unconditional: a thread with
+        // no ring position reads a valid in-tile node and discards it), then the
+        // sums, so the loads overlap instead of waiting on each other
+        T rv[NR][QHS];
         hn[0] = (T)0;
+        unroll<QHS>([&](auto J) {
+            constexpr int al = J + HOFF;
+            hn[al] = pull_h<HL, al, HOFF, WALLS, T>(Hin, ocr, fz, P);
+        });
+        for (int k = 0; k < NR; ++k)
+            unroll<QHS>([&](auto J) {
+                constexpr int al = J + HOFF;
+                rv[k][J] = pull_h<HL, al, HOFF, WALLS, T>(Hin, rcr[k], fz, P);
+            });
         T s = (T)0;
         unroll<QHS>([&](auto J) {
-            constexpr int jj = J;
-            const T v = (T)at<QHS>(Hin, gz, jj, P, own);
-            hn[jj + HOFF] = v;
-            s += v;
+            constexpr int al = J + HOFF;
+            s += hn[al];
         });
         lphi[slot * PSZ + own_lds] = s;
         for (int k = 0; k < NR; ++k) {
-            if (ring[k]) {
-                T sr = (T)0;
-                unroll<QHS>([&](auto J) {
-                    constexpr int jj = J;
-                    sr += (T)at<QHS>(Hin, gz, jj, P, ring_off[k]);
-                });
-                lphi[slot * PSZ + ring_lds[k]] = sr;
-            }
+            T sr = (T)0;
+            unroll<QHS>([&](auto J) { sr += rv[k][J]; });
+            if (ring[k]) lphi[slot * PSZ + ring_lds[k]] = sr;
         }
     };
 
     auto do_node = [&](int z, const T* h, const T* pm, const T* p0, const T* pp) {
-        ZPlanes zp;
-        {
-            int oz[3];
-            axis_nb(z, nz, a.bc[2], oz, zp.wz);
-            zp.zk[0] = oz[0];
-            zp.zk[1] = oz[1];
-            zp.zk[2] = oz[2];
-        }
+        const ZPlanes zp = make_zplanes(z, nz, a.bc[2]);
         const int o11 = cl.off[1][1];
-        // post-streaming g of this node
+        // post-streaming g of this node, pulled from x - c_i
         T g[QG];
         unroll<QG>([&](auto I) {
             constexpr int i = I;
-            if constexpr (PARITY == 0) {
-                g[i] = GC::template dec<GL, i, GS, T>(at<QG>(G, z, i, P, o11));
+            constexpr int o = GL::opp(i);
+            constexpr int cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
+            if constexpr (!WALLS) {
+                g[i] = GC::template dec<GL, i, GS, T>(at<QG>(Gin, zp.zk[1 - cz], i, P, cl.off[1 - cy][1 - cx]));
             } else {
-                // written last step by the neighbour x - c_i into its slot opp(i)
-                constexpr int o = GL::opp(i);
-                constexpr int cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
-                const size_t enb = el<QG>(zp.zk[1 - cz], o, cl.off[1 - cy][1 - cx], P);
-                if constexpr (!WALLS) {
-                    g[i] = GC::template dec<GL, o, GS, T>(
-                        at<QG>(G, zp.zk[1 - cz], o, P, cl.off[1 - cy][1 - cx]));
-                } else {
-                    int side;
-                    // beyond a wall the population left this node last step: slot i here
-                    const bool w = beyond<GL, i, -1>(cl, zp, side);
-                    const size_t e = w ? el<QG>(z, i, o11, P) : enb;
-                    T v = GC::template dec<GL, o, GS, T>(G[e]);
-                    if (w) v += gcorr(side, o);
-                    g[i] = v;
-                }
+                int side;
+                // beyond a wall: the bounce-back of what left this node, slot opp(i)
+                const bool w = beyond<GL, i, -1>(cl, zp, side);
+                const size_t e = w ? el<QG>(z, o, o11, P) : el<QG>(zp.zk[1 - cz], i, cl.off[1 - cy][1 - cx], P);
+                T v = GC::template dec<GL, i, GS, T>(Gin[e]);   // w_opp(i) = w_i: same codec
+                if (w) v += gcorr(side, o);
+                g[i] = v;
             }
         });
         T pu_prev[3] = {(T)0, (T)0, (T)0};
@@ -588,45 +638,16 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
         NodeOut<T> mo;
         T pu_new[3];
         if constexpr (MODE == MODE_STEP) {
-            // g: AA in place; outputs are streamed (non-temporal stores): no
-            // workgroup reads them again within this step
+            // post-collision populations at the node itself, in the other buffers;
+            // streamed (non-temporal stores): no workgroup reads them this step
             auto gsink = [&](auto I, T v) {
                 constexpr int i = I;
-                constexpr int o = GL::opp(i);
-                if constexpr (PARITY == 0) {
-                    __builtin_nontemporal_store(GC::template enc<GL, o, GS, T>(v), &at<QG>(G, z, o, P, o11));
-                } else {
-                    constexpr int cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
-                    const size_t enb = el<QG>(zp.zk[1 + cz], i, cl.off[1 + cy][1 + cx], P);
-                    if constexpr (!WALLS) {
-                        __builtin_nontemporal_store(GC::template enc<GL, i, GS, T>(v),
-                                                    &at<QG>(G, zp.zk[1 + cz], i, P, cl.off[1 + cy][1 + cx]));
-                    } else {
-                        int side;
-                        const bool w = beyond<GL, i, 1>(cl, zp, side);
-                        if (w) v += gcorr(side, i);
-                        const size_t e = w ? el<QG>(z, o, o11, P) : enb;
-                        G[e] = GC::template enc<GL, i, GS, T>(v);
-                    }
-                }
+                __builtin_nontemporal_store(GC::template enc<GL, i, GS, T>(v), &at<QG>(Gout, z, i, P, o11));
             };
-            // h: push into the other buffer
             auto hsink = [&](auto J, T v) {
                 constexpr int al = J;
                 if constexpr (al >= HOFF) {
-                    if (a.write_h) {
-                        constexpr int o = HL::opp(al);
-                        constexpr int ex = HL::c(al, 0), ey = HL::c(al, 1), ez = HL::c(al, 2);
-                        if constexpr (WALLS) {
-                            const size_t enb = el<QHS>(zp.zk[1 + ez], al - HOFF, cl.off[1 + ey][1 + ex], P);
-                            int side;
-                            const bool w = beyond<HL, al, 1>(cl, zp, side);
-                            Hout[w ? el<QHS>(z, o - HOFF, o11, P) : enb] = (HS)v;
-                        } else {
-                            __builtin_nontemporal_store(
-                                (HS)v, &at<QHS>(Hout, zp.zk[1 + ez], al - HOFF, P, cl.off[1 + ey][1 + ex]));
-                        }
-                    }
+                    if (a.write_h) __builtin_nontemporal_store((HS)v, &at<QHS>(Hout, z, al - HOFF, P, o11));
                 }
             };
             node_update<PAIR, MODEL, T, true>(ph, g, h, phin, pu_prev, pu_new, mo, gsink, hsink);
@@ -690,7 +711,11 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
         fill_plane(zs - 1, 0);
         fill_plane(zs, 1);
         unroll<QH>([&](auto J) { constexpr int al = J; hc[al] = hn[al]; });
-        for (int z = zs; z < ze; ++z) {
+        for (int zl = zs; zl < ze; ++zl) {
+            // the plane index is uniform; readfirstlane keeps the compiler from
+            // treating it as per-lane after the divergent node branch (which
+            // would move all plane and address arithmetic to 64-bit VALU)
+            const int z = __builtin_amdgcn_readfirstlane(zl);
             const int r = z - zs;
             fill_plane(z + 1, (r + 2) & 3);
             __syncthreads();
@@ -718,17 +743,35 @@ __global__ __launch_bounds__(BLOCK) void k_reduce(const double* __restrict__ par
     block_reduce_diag(d, out);
 }
 
-__global__ void k_header(long long* dst, long long steps, int parity, int hcur) {
+__global__ void k_header(long long* dst, long long steps) {
     if (threadIdx.x == 0) {
-        dst[0] = 0x70666c626dLL;   // tag
+        dst[0] = 0x70666c626eLL;   // tag (post-collision pull layout)
         dst[1] = steps;
-        dst[2] = parity;
-        dst[3] = hcur;
+        dst[2] = 0;
+        dst[3] = 0;
     }
 }
 
 // ----------------------------------------------------------------------------
-// initialisation: h = h_eq(phi0, u0), g = g_eq(p0 / (rho0 c_s^2), u0), natural slots
+// canonical (post-streaming) populations <-> stored (post-collision) buffers
+
+// Stored element that the pull of population i at node (x, y, z) reads: slot i
+// of node x - c_i, or, if that node lies beyond a wall, slot opp(i) of the node
+// itself (the pull then adds the wall term of opp(i)). The map is a bijection
+// of the stored elements, so canonical -> stored is its inverse scatter.
+template <class L, int i, int QS, int OFF>
+__device__ __forceinline__ size_t pull_source(int nx, int ny, int nz, const int* bc, int x, int y, int z, int P,
+                                              bool& wall, int& side) {
+    int nb;
+    wall = shifted<L, i, -1>(nx, ny, nz, bc, x, y, z, nb, side);
+    if (wall) return el<QS>(z, L::opp(i) - OFF, y * nx + x, P);
+    const int plane = nx * ny;
+    return el<QS>(nb / plane, i - OFF, nb % plane, P);
+}
+
+// ----------------------------------------------------------------------------
+// initialisation: h = h_eq(phi0, u0), g = g_eq(p0 / (rho0 c_s^2), u0), written
+// where the first step's pull reads them
 
 template <class PAIR, int MODEL, int PREC>
 __global__ __launch_bounds__(256) void k_init(const InitArgs a) {
@@ -762,15 +805,25 @@ __global__ __launch_bounds__(256) void k_init(const InitArgs a) {
     unroll<GL::Q>([&](auto I) {
         constexpr int i = I;
         const double cu = GL::c(i, 0) * u[0] + GL::c(i, 1) * u[1] + GL::c(i, 2) * u[2];
-        const double geq = GL::w(i) * (ps + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
-        G[el<GL::Q>(z, i, ip, a.P)] = GC::template enc<GL, i, GS, T>((T)geq);
+        double geq = GL::w(i) * (ps + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+        bool w;
+        int side;
+        const size_t e = pull_source<GL, i, GL::Q, 0>(a.nx, a.ny, a.nz, a.bc, x, y, z, a.P, w, side);
+        if (w) geq -= a.gcorr[side][GL::opp(i)];
+        G[e] = GC::template enc<GL, i, GS, T>((T)geq);
     });
+    auto put_h = [&](auto J, double v) {
+        constexpr int al = J;
+        bool w;
+        int side;
+        H[pull_source<HL, al, QHS, HOFF>(a.nx, a.ny, a.nz, a.bc, x, y, z, a.P, w, side)] = (HS)v;
+    };
     if constexpr (MODEL == 0) {
         unroll<QHS>([&](auto J) {
             constexpr int al = J + HOFF;
             const double eu = HL::c(al, 0) * u[0] + HL::c(al, 1) * u[1] + HL::c(al, 2) * u[2];
             const double heq = HL::w(al) * phi * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * usq);
-            H[el<QHS>(z, al - HOFF, ip, a.P)] = (HS)heq;
+            put_h(std::integral_constant<int, al>{}, heq);
         });
     } else {
         // mu_phi(phi0) with the same stencil and ghost rules as the step
@@ -795,7 +848,7 @@ __global__ __launch_bounds__(256) void k_init(const InitArgs a) {
                                   HL::c(al, 2) * phi * u[2];
                 heq = HL::w(al) * ph.eta * mu + 3.0 * HL::w(al) * ep;
             }
-            H[el<QHS>(z, al, ip, a.P)] = (HS)heq;
+            put_h(std::integral_constant<int, al>{}, heq);
         });
         T* PU = (T*)a.phiu;
         for (int c = 0; c < 3; ++c) PU[el<3>(z, c, ip, a.P)] = (T)(phi * u[c]);
@@ -825,26 +878,23 @@ __global__ __launch_bounds__(256) void k_get(const IOArgs a) {
     const HS* H = (const HS*)a.h;
     unroll<GL::Q>([&](auto I) {
         constexpr int i = I;
-        T v;
-        if (a.parity == 0) {
-            v = GC::template dec<GL, i, GS, T>(G[el<GL::Q>(z, i, ip, a.P)]);
-        } else {
-            int nb, side;
-            if (shifted<GL, i, -1>(a.nx, a.ny, a.nz, a.bc, x, y, z, nb, side)) {
-                v = GC::template dec<GL, i, GS, T>(G[el<GL::Q>(z, i, ip, a.P)]) +
-                    (T)a.gcorr[side][GL::opp(i)];
-            } else {
-                constexpr int o = GL::opp(i);
-                const int zn = nb / (a.nx * a.ny), ipn = nb % (a.nx * a.ny);
-                v = GC::template dec<GL, o, GS, T>(G[el<GL::Q>(zn, o, ipn, a.P)]);
-            }
-        }
+        bool w;
+        int side;
+        const size_t e = pull_source<GL, i, GL::Q, 0>(a.nx, a.ny, a.nz, a.bc, x, y, z, a.P, w, side);
+        T v = GC::template dec<GL, i, GS, T>(G[e]);
+        if (w) v += (T)a.gcorr[side][GL::opp(i)];
         a.cg[(size_t)i * nn + n] = (double)v;
     });
     unroll<HL::Q>([&](auto J) {
         constexpr int al = J;
-        if constexpr (al < HOFF) a.ch[(size_t)al * nn + n] = 0.0;
-        else a.ch[(size_t)al * nn + n] = (double)H[el<QHS>(z, al - HOFF, ip, a.P)];
+        if constexpr (al < HOFF) {
+            a.ch[(size_t)al * nn + n] = 0.0;
+        } else {
+            bool w;
+            int side;
+            a.ch[(size_t)al * nn + n] =
+                (double)H[pull_source<HL, al, QHS, HOFF>(a.nx, a.ny, a.nz, a.bc, x, y, z, a.P, w, side)];
+        }
     });
 }
 
@@ -868,60 +918,59 @@ __global__ __launch_bounds__(256) void k_set(const IOArgs a) {
     HS* H = (HS*)a.h;
     unroll<GL::Q>([&](auto I) {
         constexpr int i = I;
-        G[el<GL::Q>(z, i, ip, a.P)] = GC::template enc<GL, i, GS, T>((T)a.cg[(size_t)i * nn + n]);
+        bool w;
+        int side;
+        const size_t e = pull_source<GL, i, GL::Q, 0>(a.nx, a.ny, a.nz, a.bc, x, y, z, a.P, w, side);
+        double v = a.cg[(size_t)i * nn + n];
+        if (w) v -= a.gcorr[side][GL::opp(i)];
+        G[e] = GC::template enc<GL, i, GS, T>((T)v);
     });
     unroll<QHS>([&](auto J) {
         constexpr int al = J + HOFF;
-        H[el<QHS>(z, al - HOFF, ip, a.P)] = (HS)a.ch[(size_t)al * nn + n];
+        bool w;
+        int side;
+        H[pull_source<HL, al, QHS, HOFF>(a.nx, a.ny, a.nz, a.bc, x, y, z, a.P, w, side)] =
+            (HS)a.ch[(size_t)al * nn + n];
     });
 }
 
 // ----------------------------------------------------------------------------
 // dispatch
 
-template <class PAIR, int MODEL, int PREC, int PARITY>
+template <class PAIR, int MODEL, int PREC>
 static hipError_t step_mode(int mode, const KArgs& a, hipStream_t s) {
     const dim3 grid((unsigned)(a.ntx * a.nty * a.ntz)), block(BLOCK);
     const bool walls = a.wall_axis >= 0;
     switch (mode) {
         case MODE_STEP:
             if (walls)
-                hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, PARITY, MODE_STEP, 1>), grid, block, 0, s, a);
+                hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_STEP, 1>), grid, block, 0, s, a);
             else
-                hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, PARITY, MODE_STEP, 0>), grid, block, 0, s, a);
+                hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_STEP, 0>), grid, block, 0, s, a);
             break;
         case MODE_FIELDS:
-            hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, PARITY, MODE_FIELDS, 1>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_FIELDS, 1>), grid, block, 0, s, a);
             break;
         default:
-            hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, PARITY, MODE_DIAG, 1>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_DIAG, 1>), grid, block, 0, s, a);
     }
     return hipGetLastError();
 }
 
-template <class PAIR, int MODEL, int PREC>
-static hipError_t step_parity(int parity, int mode, const KArgs& a, hipStream_t s) {
-    return parity ? step_mode<PAIR, MODEL, PREC, 1>(mode, a, s)
-                  : step_mode<PAIR, MODEL, PREC, 0>(mode, a, s);
-}
-
 template <class PAIR, int MODEL>
-static hipError_t step_prec(int prec, int parity, int mode, const KArgs& a, hipStream_t s) {
+static hipError_t step_prec(int prec, int mode, const KArgs& a, hipStream_t s) {
     switch (prec) {
-        case 0: return step_parity<PAIR, MODEL, 0>(parity, mode, a, s);
-        case 1: return step_parity<PAIR, MODEL, 1>(parity, mode, a, s);
-        case 2: return step_parity<PAIR, MODEL, 2>(parity, mode, a, s);
-        default: return step_parity<PAIR, MODEL, 3>(parity, mode, a, s);
+        case 0: return step_mode<PAIR, MODEL, 0>(mode, a, s);
+        case 1: return step_mode<PAIR, MODEL, 1>(mode, a, s);
+        case 2: return step_mode<PAIR, MODEL, 2>(mode, a, s);
+        default: return step_mode<PAIR, MODEL, 3>(mode, a, s);
     }
 }
 
-hipError_t launch_step(int lattice, int model, int precision, int parity, int mode,
-                       const KArgs& a, hipStream_t s) {
+hipError_t launch_step(int lattice, int model, int precision, int mode, const KArgs& a, hipStream_t s) {
     if (lattice == 0)
-        return model ? step_prec<Pair2D, 1>(precision, parity, mode, a, s)
-                     : step_prec<Pair2D, 0>(precision, parity, mode, a, s);
-    return model ? step_prec<Pair3D, 1>(precision, parity, mode, a, s)
-                 : step_prec<Pair3D, 0>(precision, parity, mode, a, s);
+        return model ? step_prec<Pair2D, 1>(precision, mode, a, s) : step_prec<Pair2D, 0>(precision, mode, a, s);
+    return model ? step_prec<Pair3D, 1>(precision, mode, a, s) : step_prec<Pair3D, 0>(precision, mode, a, s);
 }
 
 #define PFLBM_NODE_DISPATCH(KERNEL, ARGS, NN)                                               \
@@ -971,8 +1020,8 @@ hipError_t launch_reduce(const double* partials, int nblocks, double* out, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_header(void* dst, long long steps, int parity, int hcur, hipStream_t s) {
-    hipLaunchKernelGGL(k_header, dim3(1), dim3(64), 0, s, (long long*)dst, steps, parity, hcur);
+hipError_t launch_header(void* dst, long long steps, hipStream_t s) {
+    hipLaunchKernelGGL(k_header, dim3(1), dim3(64), 0, s, (long long*)dst, steps);
     return hipGetLastError();
 }
 

@@ -1,6 +1,6 @@
 // C ABI of libpflbm (declared in include/pflbm.h): validation, device-state
-// layout inside the caller's buffer, in-place streaming parity bookkeeping and
-// kernel launch orchestration. All arithmetic of the method runs in the
+// layout inside the caller's buffer, double-buffer bookkeeping and kernel
+// launch orchestration. All arithmetic of the method runs in the
 // kernels (kernels.hip); this file only sets up their arguments.
 #include "pflbm.h"
 
@@ -26,7 +26,7 @@ struct Layout {
     long long nodes = 0;
     int P = 0;                       // elements per population plane
     int ntx = 0, nty = 0, ntz = 0, zb = 0, nblocks = 0;
-    size_t off_g = 0, off_h[2] = {0, 0}, off_pu = 0, off_part = 0, off_res = 0, total = 0;
+    size_t off_g[2] = {0, 0}, off_h[2] = {0, 0}, off_pu = 0, off_part = 0, off_res = 0, total = 0;
     size_t ck_g = 0, ck_h = 0, ck_pu = 0, ck_total = 0;
     size_t g_bytes = 0, h_bytes = 0, pu_bytes = 0;
 };
@@ -100,8 +100,10 @@ Layout make_layout(const pflbm_params& p) {
     L.ntz = (p.nz + L.zb - 1) / L.zb;
     L.nblocks = L.ntx * L.nty * L.ntz;
     size_t off = 0;
-    L.off_g = off;
-    off = align_up(off + (size_t)L.Qg * planes * L.sg, ALIGN);
+    for (int k = 0; k < 2; ++k) {
+        L.off_g[k] = off;
+        off = align_up(off + (size_t)L.Qg * planes * L.sg, ALIGN);
+    }
     for (int k = 0; k < 2; ++k) {
         L.off_h[k] = off;
         off = align_up(off + (size_t)L.Qhs * planes * L.sh, ALIGN);
@@ -113,7 +115,7 @@ Layout make_layout(const pflbm_params& p) {
     L.off_res = off;
     off = align_up(off + 64 * sizeof(double), ALIGN);
     L.total = off;
-    // checkpoint: 256-byte header, g, current h, (phi u)
+    // checkpoint: 256-byte header, current g, current h, (phi u)
     L.ck_g = 256;
     L.g_bytes = (size_t)L.Qg * planes * L.sg;
     L.h_bytes = (size_t)L.Qhs * planes * L.sh;
@@ -145,7 +147,7 @@ struct pflbm {
     hipStream_t stream = nullptr;
     char* base = nullptr;
     int device = 0;
-    int hcur = 0, parity = 0;
+    int gcur = 0, hcur = 0;   // buffers the next step reads
     long long steps = 0;
     bool initialised = false;
     int sticky = 0;
@@ -186,7 +188,8 @@ int guard(pflbm_t* h) {
 
 void base_args(pflbm_t* h, KArgs& a) {
     std::memset(&a, 0, sizeof(a));
-    a.g = h->base + h->L.off_g;
+    a.gin = h->base + h->L.off_g[h->gcur];
+    a.gout = h->base + h->L.off_g[1 - h->gcur];
     a.hin = h->base + h->L.off_h[h->hcur];
     a.hout = h->base + h->L.off_h[1 - h->hcur];
     a.phiu = h->base + h->L.off_pu;
@@ -217,7 +220,7 @@ int run_diag(pflbm_t* h, const double* centre, double R, double* res) {
         a.r_in = R - 2.0 * h->p.W;
         a.r_out = R + 2.0 * h->p.W;
     }
-    HIPCHK(h, launch_step(h->p.lattice, h->p.model, h->p.precision, h->parity, MODE_DIAG, a, h->stream), "diag kernel");
+    HIPCHK(h, launch_step(h->p.lattice, h->p.model, h->p.precision, MODE_DIAG, a, h->stream), "diag kernel");
     double* dres = (double*)(h->base + h->L.off_res);
     HIPCHK(h, launch_reduce(a.partials, h->L.nblocks, dres, h->stream), "reduce kernel");
     HIPCHK(h, hipMemcpyAsync(res, dres, NDIAG * sizeof(double), hipMemcpyDeviceToHost, h->stream), "diag copy");
@@ -305,7 +308,7 @@ int pflbm_init(pflbm_t* h, const double* phi0, const double* u0, const double* p
     if (!phi0) return fail(h, PFLBM_EINVAL, "phi0 is null");
     InitArgs a;
     std::memset(&a, 0, sizeof(a));
-    a.g = h->base + h->L.off_g;
+    a.g = h->base + h->L.off_g[0];
     a.h = h->base + h->L.off_h[0];
     a.phiu = h->base + h->L.off_pu;
     a.phi0 = phi0;
@@ -316,10 +319,11 @@ int pflbm_init(pflbm_t* h, const double* phi0, const double* u0, const double* p
     a.ny = h->p.ny;
     a.nz = h->p.nz;
     for (int k = 0; k < 3; ++k) a.bc[k] = h->p.bc[k];
+    std::memcpy(a.gcorr, h->gcorr, sizeof(a.gcorr));
     a.ph = h->ph;
     HIPCHK(h, launch_init(h->p.lattice, h->p.model, h->p.precision, a, h->stream), "init kernel");
+    h->gcur = 0;
     h->hcur = 0;
-    h->parity = 0;
     h->steps = 0;
     h->initialised = true;
     return PFLBM_OK;
@@ -333,11 +337,13 @@ int pflbm_step(pflbm_t* h, int nsteps) {
     KArgs a;
     base_args(h, a);
     for (int k = 0; k < nsteps; ++k) {
+        a.gin = h->base + h->L.off_g[h->gcur];
+        a.gout = h->base + h->L.off_g[1 - h->gcur];
         a.hin = h->base + h->L.off_h[h->hcur];
         a.hout = h->base + h->L.off_h[1 - h->hcur];
-        HIPCHK(h, launch_step(h->p.lattice, h->p.model, h->p.precision, h->parity, MODE_STEP, a, h->stream), "step kernel");
+        HIPCHK(h, launch_step(h->p.lattice, h->p.model, h->p.precision, MODE_STEP, a, h->stream), "step kernel");
         if (!h->p.freeze_phi) h->hcur ^= 1;
-        h->parity ^= 1;
+        h->gcur ^= 1;
         h->steps += 1;
         if (h->p.check_interval > 0 && h->steps % h->p.check_interval == 0) {
             st = run_diag(h, nullptr, 0.0, h->res_host);
@@ -362,7 +368,7 @@ int pflbm_fields(pflbm_t* h, double* phi, double* u, double* p, double* rho) {
     a.f_u = u;
     a.f_p = p;
     a.f_rho = rho;
-    HIPCHK(h, launch_step(h->p.lattice, h->p.model, h->p.precision, h->parity, MODE_FIELDS, a, h->stream), "fields kernel");
+    HIPCHK(h, launch_step(h->p.lattice, h->p.model, h->p.precision, MODE_FIELDS, a, h->stream), "fields kernel");
     return PFLBM_OK;
 }
 
@@ -390,7 +396,7 @@ int pflbm_volume(pflbm_t* h, const double* centre, double R, pflbm_diag* out) {
 
 static void io_args(pflbm_t* h, IOArgs& a) {
     std::memset(&a, 0, sizeof(a));
-    a.g = h->base + h->L.off_g;
+    a.g = h->base + h->L.off_g[h->gcur];
     a.h = h->base + h->L.off_h[h->hcur];
     a.P = h->L.P;
     a.nx = h->p.nx;
@@ -398,7 +404,6 @@ static void io_args(pflbm_t* h, IOArgs& a) {
     a.nz = h->p.nz;
     for (int k = 0; k < 3; ++k) a.bc[k] = h->p.bc[k];
     a.wall_axis = h->wall_axis;
-    a.parity = h->parity;
     std::memcpy(a.gcorr, h->gcorr, sizeof(a.gcorr));
 }
 
@@ -425,7 +430,6 @@ int pflbm_set_distributions(pflbm_t* h, const double* g, const double* hd) {
     a.cg = (double*)g;
     a.ch = (double*)hd;
     HIPCHK(h, launch_set(h->p.lattice, h->p.model, h->p.precision, a, h->stream), "set kernel");
-    h->parity = 0;
     return PFLBM_OK;
 }
 
@@ -448,8 +452,8 @@ int pflbm_save_state(pflbm_t* h, void* dev_dst) {
     if (!h->initialised) return fail(h, PFLBM_EINVAL, "pflbm_init not called");
     char* d = (char*)dev_dst;
     const Layout& L = h->L;
-    HIPCHK(h, launch_header(d, h->steps, h->parity, 0, h->stream), "header kernel");
-    HIPCHK(h, hipMemcpyAsync(d + L.ck_g, h->base + L.off_g, L.g_bytes, hipMemcpyDeviceToDevice, h->stream), "save g");
+    HIPCHK(h, launch_header(d, h->steps, h->stream), "header kernel");
+    HIPCHK(h, hipMemcpyAsync(d + L.ck_g, h->base + L.off_g[h->gcur], L.g_bytes, hipMemcpyDeviceToDevice, h->stream), "save g");
     HIPCHK(h, hipMemcpyAsync(d + L.ck_h, h->base + L.off_h[h->hcur], L.h_bytes, hipMemcpyDeviceToDevice, h->stream), "save h");
     if (h->p.model == PFLBM_CH)
         HIPCHK(h, hipMemcpyAsync(d + L.ck_pu, h->base + L.off_pu, L.pu_bytes, hipMemcpyDeviceToDevice, h->stream), "save phiu");
@@ -465,13 +469,13 @@ int pflbm_load_state(pflbm_t* h, const void* dev_src) {
     long long hdr[4];
     HIPCHK(h, hipMemcpyAsync(hdr, s, sizeof(hdr), hipMemcpyDeviceToHost, h->stream), "load header");
     HIPCHK(h, hipStreamSynchronize(h->stream), "load sync");
-    if (hdr[0] != 0x70666c626dLL) return fail(h, PFLBM_EINVAL, "not a pflbm checkpoint");
-    HIPCHK(h, hipMemcpyAsync(h->base + L.off_g, s + L.ck_g, L.g_bytes, hipMemcpyDeviceToDevice, h->stream), "load g");
+    if (hdr[0] != 0x70666c626eLL) return fail(h, PFLBM_EINVAL, "not a pflbm checkpoint");
+    HIPCHK(h, hipMemcpyAsync(h->base + L.off_g[0], s + L.ck_g, L.g_bytes, hipMemcpyDeviceToDevice, h->stream), "load g");
     HIPCHK(h, hipMemcpyAsync(h->base + L.off_h[0], s + L.ck_h, L.h_bytes, hipMemcpyDeviceToDevice, h->stream), "load h");
     if (h->p.model == PFLBM_CH)
         HIPCHK(h, hipMemcpyAsync(h->base + L.off_pu, s + L.ck_pu, L.pu_bytes, hipMemcpyDeviceToDevice, h->stream), "load phiu");
     h->steps = hdr[1];
-    h->parity = (int)hdr[2];
+    h->gcur = 0;
     h->hcur = 0;
     h->initialised = true;
     return PFLBM_OK;

@@ -45,7 +45,7 @@ def test_full_size_step_on_sampled_nodes(precision):
     d, phi, u = wl.taylor_green_droplet_3d(n=N, We=10.0)
     s = Solver(d, precision=precision)
     s.init(phi, u)
-    s.step(51)                       # the next step is an odd (neighbour-slot) step
+    s.step(51)
     g0, h0 = s.get_distributions()
     s.step(1)
     g1, h1 = s.get_distributions()
