@@ -77,6 +77,14 @@ extern "C" {
 #define PFLBM_MIXED_FP16  2  /* g stored as fp16 of 4096 g_i / w_i, h float32; float32 arithmetic */
 #define PFLBM_MIXED_BF16  3  /* g stored as bf16 of g_i / w_i, h float32; float32 arithmetic */
 
+/* step-kernel tile: x nodes by y rows per 256-thread workgroup (3-D; the
+   2-D lattice always uses 64 x 4) */
+#define PFLBM_TILE_AUTO   0  /* 64x4 for the fp16/bf16-stored forms, 256x1 for
+                                fp32, 128x2 for fp64 (narrower when nx is) */
+#define PFLBM_TILE_64x4   1  /* workgroups ordered so each XCD sweeps a contiguous run */
+#define PFLBM_TILE_128x2  2  /* hardware workgroup order */
+#define PFLBM_TILE_256x1  3  /* hardware workgroup order */
+
 /* boundary per axis */
 #define PFLBM_PERIODIC 0
 #define PFLBM_WALL     1    /* halfway bounce-back; at most one walled axis */
@@ -111,6 +119,8 @@ typedef struct pflbm_params {
     int check_interval;   /* every this many steps pflbm_step checks for NaN/Inf
                              or rho <= 0 (synchronising); 0 = never */
     int zblock;           /* z planes per workgroup, 0 = automatic (tuning only) */
+    int tile;             /* step-kernel tile, PFLBM_TILE_* (tuning only: results
+                             do not depend on it) */
 } pflbm_params;
 
 /* FP64 diagnostics of one state (Eq. volume_continuous; volume by counting

@@ -7,9 +7,10 @@
 
 namespace pfk {
 
-constexpr int TILE_X = 64;      // one wavefront per x row of a tile
-constexpr int TILE_Y = 4;       // rows per workgroup
-constexpr int BLOCK = TILE_X * TILE_Y;
+constexpr int BLOCK = 256;      // threads per step workgroup
+// step tiles (x nodes, y rows) by tile index; fields / diagnostics use tile 0
+constexpr int TILE_NX[3] = {64, 128, 256};
+constexpr int TILE_NY[3] = {4, 2, 1};
 constexpr int NDIAG = 12;       // per-block partial diagnostics (see kernels.hip)
 constexpr int MAXQ = 19;
 
@@ -74,6 +75,7 @@ struct KArgs {
     int P;                 // elements per population plane (>= nx * ny)
     int nx, ny, nz;
     int ntx, nty, ntz, zb; // tiles per axis, z planes per tile
+    int tile;              // tile index (TILE_NX / TILE_NY), 3-D step only
     int bc[3];             // 0 periodic, 1 wall
     int wall_axis;         // -1 none, else 0/1/2
     int write_h;           // 0 when phi is frozen

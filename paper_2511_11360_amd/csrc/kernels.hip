@@ -491,7 +491,10 @@ __device__ __forceinline__ T pull_h(const HS* __restrict__ H, const Cross& X, co
 }
 
 // WALLS = 0: every axis periodic (no bounce-back selects are compiled).
-template <class PAIR, int MODEL, int PREC, int MODE, int WALLS>
+// TS: tile shape, TX x TY nodes per workgroup: 0 = 64 x 4 with workgroups
+// ordered so each XCD sweeps a contiguous run of tiles, 1 = 128 x 2 and
+// 2 = 256 x 1 in hardware order.
+template <class PAIR, int MODEL, int PREC, int MODE, int WALLS, int TS>
 __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
     using GL = typename PAIR::G;
     using HL = typename PAIR::H;
@@ -503,18 +506,19 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
     constexpr bool D3 = PAIR::dim == 3;
     constexpr int HOFF = (MODEL == 0 && D3) ? 1 : 0;   // AC on D3Q7: rest population not stored
     constexpr int QHS = QH - HOFF;
-    constexpr int PW = TILE_X + 2, PSZ = PW * (TILE_Y + 2);
-    constexpr int NRING = 2 * PW + 2 * TILE_Y;         // halo ring of the tile
+    constexpr int TX = TS == 0 ? 64 : (TS == 1 ? 128 : 256), TY = BLOCK / TX;
+    constexpr int PW = TX + 2, PSZ = PW * (TY + 2);
+    constexpr int NRING = 2 * PW + 2 * TY;             // halo ring of the tile
     constexpr int NPL = D3 ? 4 : 1;
     __shared__ T lphi[NPL * PSZ];
 
-    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int b = TS == 0 ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int bx = b % a.ntx, byz = b / a.ntx;
     const int by = byz % a.nty, bz = byz / a.nty;
-    const int x0 = bx * TILE_X, y0 = by * TILE_Y;
+    const int x0 = bx * TX, y0 = by * TY;
     const int zs = bz * a.zb;
     const int ze = min(a.nz, zs + a.zb);
-    const int lx = threadIdx.x % TILE_X, ly = threadIdx.x / TILE_X;
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
     const int x = x0 + lx, y = y0 + ly;
     const bool active = x < a.nx && y < a.ny;
     const int nx = a.nx, ny = a.ny, nz = a.nz, P = a.P;
@@ -554,9 +558,9 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
         ring[k] = r < NRING;
         int hx = 0, hy = 0;
         if (r < PW) { hx = r - 1; hy = -1; }
-        else if (r < 2 * PW) { hx = r - PW - 1; hy = TILE_Y; }
-        else if (r < 2 * PW + TILE_Y) { hx = -1; hy = r - 2 * PW; }
-        else { hx = TILE_X; hy = r - 2 * PW - TILE_Y; }
+        else if (r < 2 * PW) { hx = r - PW - 1; hy = TY; }
+        else if (r < 2 * PW + TY) { hx = -1; hy = r - 2 * PW; }
+        else { hx = TX; hy = r - 2 * PW - TY; }
         if (!ring[k]) { hx = 0; hy = 0; }
         rcr[k] = make_cross(ghost_coord(x0 + hx, nx, a.bc[0]), ghost_coord(y0 + hy, ny, a.bc[1]), nx, ny, a.bc);
         ring_lds[k] = (hy + 1) * PW + (hx + 1);
@@ -943,16 +947,26 @@ static hipError_t step_mode(int mode, const KArgs& a, hipStream_t s) {
     const bool walls = a.wall_axis >= 0;
     switch (mode) {
         case MODE_STEP:
-            if (walls)
-                hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_STEP, 1>), grid, block, 0, s, a);
-            else
-                hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_STEP, 0>), grid, block, 0, s, a);
+            if constexpr (PAIR::dim == 3) {
+                if (a.tile == 1) {
+                    if (walls) hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_STEP, 1, 1>), grid, block, 0, s, a);
+                    else hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_STEP, 0, 1>), grid, block, 0, s, a);
+                    break;
+                }
+                if (a.tile == 2) {
+                    if (walls) hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_STEP, 1, 2>), grid, block, 0, s, a);
+                    else hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_STEP, 0, 2>), grid, block, 0, s, a);
+                    break;
+                }
+            }
+            if (walls) hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_STEP, 1, 0>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_STEP, 0, 0>), grid, block, 0, s, a);
             break;
         case MODE_FIELDS:
-            hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_FIELDS, 1>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_FIELDS, 1, 0>), grid, block, 0, s, a);
             break;
         default:
-            hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_DIAG, 1>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_DIAG, 1, 0>), grid, block, 0, s, a);
     }
     return hipGetLastError();
 }

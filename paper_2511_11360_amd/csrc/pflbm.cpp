@@ -25,7 +25,8 @@ struct Layout {
     size_t sg = 0, sh = 0, sT = 0;   // bytes per stored g, h, compute value
     long long nodes = 0;
     int P = 0;                       // elements per population plane
-    int ntx = 0, nty = 0, ntz = 0, zb = 0, nblocks = 0;
+    int ntx = 0, nty = 0, ntz = 0, zb = 0, nblocks = 0;   // 64 x 4 tiles (fields, diagnostics)
+    int tile_step = 0, ntx_step = 0, nty_step = 0;        // tiles of the step kernel
     size_t off_g[2] = {0, 0}, off_h[2] = {0, 0}, off_pu = 0, off_part = 0, off_res = 0, total = 0;
     size_t ck_g = 0, ck_h = 0, ck_pu = 0, ck_total = 0;
     size_t g_bytes = 0, h_bytes = 0, pu_bytes = 0;
@@ -73,6 +74,7 @@ std::string validate(const pflbm_params& p) {
     if (p.lattice == PFLBM_D2Q9_D2Q5 && (p.gravity[2] != 0.0 || p.force[2] != 0.0)) return "2-D body force has a z component";
     if (p.check_interval < 0) return "check_interval must be >= 0";
     if (p.zblock < 0) return "zblock must be >= 0";
+    if (p.tile < PFLBM_TILE_AUTO || p.tile > PFLBM_TILE_256x1) return "unknown tile";
     return "";
 }
 
@@ -89,8 +91,20 @@ Layout make_layout(const pflbm_params& p) {
     L.nodes = (long long)p.nx * p.ny * p.nz;
     L.P = (int)align_up((size_t)p.nx * p.ny, 64);
     const size_t planes = (size_t)p.nz * L.P;
-    L.ntx = (p.nx + TILE_X - 1) / TILE_X;
-    L.nty = (p.ny + TILE_Y - 1) / TILE_Y;
+    L.ntx = (p.nx + TILE_NX[0] - 1) / TILE_NX[0];
+    L.nty = (p.ny + TILE_NY[0] - 1) / TILE_NY[0];
+    // step tile: measured fastest per storage form on the 256^3 droplet case
+    // (fp16 / bf16-stored g: 64 x 4 in XCD runs; fp32: 256 x 1; fp64: 128 x 2);
+    // no wider than nx needs
+    int t = 0;
+    if (d3) {
+        if (p.tile != PFLBM_TILE_AUTO) t = p.tile - PFLBM_TILE_64x4;
+        else if (p.precision == PFLBM_FP32) t = p.nx >= 256 ? 2 : (p.nx > 64 ? 1 : 0);
+        else if (p.precision == PFLBM_FP64) t = p.nx > 64 ? 1 : 0;
+    }
+    L.tile_step = t;
+    L.ntx_step = (p.nx + TILE_NX[t] - 1) / TILE_NX[t];
+    L.nty_step = (p.ny + TILE_NY[t] - 1) / TILE_NY[t];
     if (d3) {
         L.zb = p.zblock > 0 ? p.zblock : 8;
         if (L.zb > p.nz) L.zb = p.nz;
@@ -341,6 +355,9 @@ int pflbm_step(pflbm_t* h, int nsteps) {
         a.gout = h->base + h->L.off_g[1 - h->gcur];
         a.hin = h->base + h->L.off_h[h->hcur];
         a.hout = h->base + h->L.off_h[1 - h->hcur];
+        a.tile = h->L.tile_step;
+        a.ntx = h->L.ntx_step;
+        a.nty = h->L.nty_step;
         HIPCHK(h, launch_step(h->p.lattice, h->p.model, h->p.precision, MODE_STEP, a, h->stream), "step kernel");
         if (!h->p.freeze_phi) h->hcur ^= 1;
         h->gcur ^= 1;

@@ -45,6 +45,7 @@ class pflbm_params(ctypes.Structure):
         ("gravity", ctypes.c_double * 3), ("force", ctypes.c_double * 3),
         ("s_other", ctypes.c_double), ("normal_eps", ctypes.c_double),
         ("freeze_phi", ctypes.c_int), ("check_interval", ctypes.c_int), ("zblock", ctypes.c_int),
+        ("tile", ctypes.c_int),
     ]
 
 
@@ -107,7 +108,10 @@ class PflbmError(RuntimeError):
         self.status = status
 
 
-def make_params(d, precision="fp64", check_interval=0, zblock=0):
+TILES = {"auto": 0, "64x4": 1, "128x2": 2, "256x1": 3}
+
+
+def make_params(d, precision="fp64", check_interval=0, zblock=0, tile="auto"):
     """pflbm_params from a workload dict (keys as in workloads.base_params)."""
     p = pflbm_params()
     p.lattice = PFLBM_D2Q9_D2Q5 if d["lattice"] == "D2Q9_D2Q5" else PFLBM_D3Q19_D3Q7
@@ -132,4 +136,5 @@ def make_params(d, precision="fp64", check_interval=0, zblock=0):
     p.freeze_phi = 1 if d.get("freeze_phi", False) else 0
     p.check_interval = int(check_interval)
     p.zblock = int(zblock)
+    p.tile = TILES[tile] if isinstance(tile, str) else int(tile)
     return p

@@ -19,13 +19,13 @@ class Solver:
     "fp32", "mixed_fp16" or "mixed_bf16"."""
 
     def __init__(self, params, precision="fp64", check_interval=0, zblock=0, device=None,
-                 stream=None):
+                 stream=None, tile="auto"):
         if not torch.cuda.is_available():
             raise RuntimeError("libpflbm needs a GPU; none is visible")
         self.d = dict(params)
         self.precision = precision
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
-        self.p = P.make_params(self.d, precision, check_interval, zblock)
+        self.p = P.make_params(self.d, precision, check_interval, zblock, tile)
         self.L = P.lib()
         nb = ctypes.c_size_t()
         self._check(self.L.pflbm_state_bytes(ctypes.byref(self.p), ctypes.byref(nb)), None)

@@ -61,14 +61,14 @@ def test_state_bytes_sizes():
     d, _, _ = wl.static_droplet_2d()
     st, n = _bytes(d)
     assert st == 0
-    # g 9 + h 2 x 5 populations of 4096 nodes in float64, plus scratch
-    assert n >= (9 + 10) * 4096 * 8
+    # g 2 x 9 + h 2 x 5 populations of 4096 nodes in float64 (two buffers each)
+    assert n >= (18 + 10) * 4096 * 8
     st, n16 = _bytes(d, precision="mixed_fp16")
     assert st == 0 and n16 < n
     d3 = wl.base_params(lattice="D3Q19_D3Q7", nx=32, ny=32, nz=32)
     st, n3 = _bytes(d3, precision="fp32")
     # AC on D3Q7 stores 6 phase-field populations per buffer
-    assert st == 0 and n3 >= (19 + 12) * 32768 * 4
+    assert st == 0 and n3 >= (38 + 12) * 32768 * 4
 
 
 @pytest.mark.parametrize("bad", [
@@ -83,6 +83,15 @@ def test_invalid_params_rejected(bad):
     d = wl.base_params(**bad)
     st, _ = _bytes(d)
     assert st == P.PFLBM_EINVAL
+
+
+def test_invalid_tile_rejected():
+    d = wl.base_params(lattice="D3Q19_D3Q7", nx=32, ny=32, nz=32)
+    for tile, ok in ((0, True), (3, True), (4, False), (-1, False)):
+        p = P.make_params(d, "fp32", tile=tile)
+        n = ctypes.c_size_t()
+        st = P.lib().pflbm_state_bytes(ctypes.byref(p), ctypes.byref(n))
+        assert (st == 0) == ok, tile
 
 
 def test_strerror():

@@ -124,6 +124,38 @@ def test_sheared_droplet_3d_moving_walls(model):
     _parity(d, phi, u, 301, "3-D sheared droplet " + model)
 
 
+_TILE_CASES = {}
+
+
+def _tile_cases():
+    """The two tile-test cases with their oracle results (computed once)."""
+    if not _TILE_CASES:
+        d, phi, u = small_3d(nx=150, ny=26, nz=25)
+        _TILE_CASES["periodic"] = (d, phi, u, 60, oracle_run(d, phi, u, 60)[1])
+        d, phi, u, _ = wl.sheared_droplet_3d(n=24, R=7.0, uw=0.02, W=2.5)
+        d["nx"], d["ny"] = 70, 22
+        phi = wl.droplet_phi(d, (35.0, 10.5, 12.0), 7.0, periodic=False)
+        x, y, z = wl.grid(d)
+        u = wl.zero_velocity(d)
+        u[0] = -0.02 + 0.04 * (y + 0.5) / 22
+        _TILE_CASES["walls"] = (d, phi, u, 40, oracle_run(d, phi, u, 40)[1])
+    return _TILE_CASES
+
+
+@pytest.mark.parametrize("tile", ["64x4", "128x2", "256x1"])
+def test_step_tiles(tile):
+    """Every step-kernel tile shape against the oracle, in float64: a ragged
+    periodic box (150 x 26 x 25: x and y tails in every shape, ragged last z
+    block) and moving walls (70 x 22 x 24)."""
+    for name, (d, phi, u, steps, st) in _tile_cases().items():
+        s = gpu_run(d, phi, u, steps, tile=tile, zblock=7)
+        g, h = gpu_dists(s)
+        eg = max_abs_per_population(g, st.g).max()
+        eh = max_abs_per_population(h, st.h).max()
+        _say("  tile %s %s: max|dg| %.3e max|dh| %.3e" % (tile, name, eg, eh))
+        assert eg <= TOL and eh <= TOL
+
+
 def test_zblock_and_s_other_variants():
     d, phi, u = small_3d(nx=30, ny=27, nz=23, s_other=1.2, visc_interp="nu", nu_H=0.03)
     for zb in (1, 5, 23):
