@@ -603,25 +603,36 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
         }
     };
 
-    auto do_node = [&](int z, const T* h, const T* pm, const T* p0, const T* pp) {
+    // stored g that the pull of plane z reads (storage form, not decoded)
+    auto pull_g = [&](int z, GS* gr) {
         const ZPlanes zp = make_zplanes(z, nz, a.bc[2]);
         const int o11 = cl.off[1][1];
-        // post-streaming g of this node, pulled from x - c_i
-        T g[QG];
         unroll<QG>([&](auto I) {
             constexpr int i = I;
             constexpr int o = GL::opp(i);
             constexpr int cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
             if constexpr (!WALLS) {
-                g[i] = GC::template dec<GL, i, GS, T>(at<QG>(Gin, zp.zk[1 - cz], i, P, cl.off[1 - cy][1 - cx]));
+                gr[i] = at<QG>(Gin, zp.zk[1 - cz], i, P, cl.off[1 - cy][1 - cx]);
             } else {
                 int side;
                 // beyond a wall: the bounce-back of what left this node, slot opp(i)
                 const bool w = beyond<GL, i, -1>(cl, zp, side);
-                const size_t e = w ? el<QG>(z, o, o11, P) : el<QG>(zp.zk[1 - cz], i, cl.off[1 - cy][1 - cx], P);
-                T v = GC::template dec<GL, i, GS, T>(Gin[e]);   // w_opp(i) = w_i: same codec
-                if (w) v += gcorr(side, o);
-                g[i] = v;
+                gr[i] = Gin[w ? el<QG>(z, o, o11, P) : el<QG>(zp.zk[1 - cz], i, cl.off[1 - cy][1 - cx], P)];
+            }
+        });
+    };
+
+    auto do_node = [&](int z, const GS* gr, const T* h, const T* pm, const T* p0, const T* pp) {
+        const ZPlanes zp = make_zplanes(z, nz, a.bc[2]);
+        const int o11 = cl.off[1][1];
+        // post-streaming g of this node (pulled from x - c_i), decoded
+        T g[QG];
+        unroll<QG>([&](auto I) {
+            constexpr int i = I;
+            g[i] = GC::template dec<GL, i, GS, T>(gr[i]);   // w_opp(i) = w_i: same codec
+            if constexpr (WALLS) {
+                int side;
+                if (beyond<GL, i, -1>(cl, zp, side)) g[i] += gcorr(side, GL::opp(i));
             }
         });
         T pu_prev[3] = {(T)0, (T)0, (T)0};
@@ -708,6 +719,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
     };
 
     T hc[QH];
+    GS gr[QG];
     if constexpr (D3) {
         // ring of 4 phi planes: plane zz lives in slot (zz - zs + 1) & 3. While a
         // wave fills plane z + 2, the slowest wave may still read planes z - 1 ..
@@ -723,14 +735,20 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
             const int r = z - zs;
             fill_plane(z + 1, (r + 2) & 3);
             __syncthreads();
-            if (active) do_node(z, hc, lphi + (r & 3) * PSZ, lphi + ((r + 1) & 3) * PSZ,
-                                lphi + ((r + 2) & 3) * PSZ);
+            if (active) {
+                pull_g(z, gr);
+                do_node(z, gr, hc, lphi + (r & 3) * PSZ, lphi + ((r + 1) & 3) * PSZ,
+                        lphi + ((r + 2) & 3) * PSZ);
+            }
             unroll<QH>([&](auto J) { constexpr int al = J; hc[al] = hn[al]; });
         }
     } else {
         fill_plane(0, 0);
         __syncthreads();
-        if (active) do_node(0, hn, lphi, lphi, lphi);
+        if (active) {
+            pull_g(0, gr);
+            do_node(0, gr, hn, lphi, lphi, lphi);
+        }
     }
     if constexpr (MODE == MODE_DIAG) {
         __syncthreads();
