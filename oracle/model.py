@@ -1,7 +1,9 @@
 """Oracle of one time step of the coupled phase-field lattice Boltzmann solver.
 
 Model (Sec. II.C.1, Fakhari2017 conservative Allen-Cahn) with the CH variant
-of Sec. II.D.1 (Liang2014 phase-field equation) as the second model. Notation
+of Sec. II.D.1 (Liang2014 phase-field equation) as the second model and the
+nonlocal / hybrid Allen-Cahn phase-field side of Sec. II.C (Chai2018, Hu2019
+with weight lam) as the third. Notation
 (see the package docstring): g = hydrodynamic distribution (paper's f_beta),
 h = phase-field distribution (paper's g_alpha), W = interface width xi,
 M = mobility M_phi.
@@ -17,6 +19,9 @@ x.x (no conjugation) and branches test real parts only.
 
 Order within one step, all node-local except the stencils and the streaming:
   O1  phi = sum_a h_a                               Eq. fakhari_phi_update
+      (nonlocal: phi = phi* + (1 - lam) R / 2 with phi* = sum_a h_a and the
+      source R of Eq. chai_G at phi*, gamma of Eq. lagrange_multiplier;
+      Eq. chai2018_phi_update)
   O2  ghost phi: periodic wrap, mirror at walls     (n . grad phi = 0, Sec. II.A)
   O3  grad phi, lap phi, isotropic central stencils  Sec. III, stencil equations
   O4  rho, nu, tau                                  Eqs. fakhari_rho_update,
@@ -30,7 +35,8 @@ Order within one step, all node-local except the stencils and the streaming:
   O9  u = sum c g + F / (2 rho)                     Eq. fakhari_velocity_update
   O10 h collision (BGK)                             Eqs. fakhari_g_simplified,
                                                     fakhari_geq, fakhari_G_modified
-                                                    (CH: liang2_geq, liang2_G)
+                                                    (CH: liang2_geq, liang2_G;
+                                                    nonlocal: Chai_geq, Hu_G)
   O11 g collision (MRT form of Eq. fakhari_f_simplified with Eqs. fakhari_feq,
       fakhari_F)
   O12 push streaming, halfway bounce-back at walls
@@ -53,7 +59,9 @@ WALL = "wall"
 @dataclass
 class Params:
     lattice: str = "D2Q9_D2Q5"       # or "D3Q19_D3Q7"
-    model: str = "AC"                 # "AC" (Fakhari2017) or "CH" (Liang2014 h-equation)
+    model: str = "AC"                 # "AC" (Fakhari2017), "CH" (Liang2014 h-equation)
+                                      # or "NL" (Chai2018 nonlocal AC, blended with the
+                                      # conservative flux by lam as in Hu2019)
     nx: int = 64
     ny: int = 64
     nz: int = 1
@@ -73,6 +81,7 @@ class Params:
     s_other: float = 1.0              # MRT rate of every non-stress moment
     freeze_phi: bool = False          # keep h (hence phi) fixed, Sec. III.D
     normal_eps: float = 1e-4          # regularisation of |grad phi| in the normal
+    lam: float = 0.0                  # NL: weight of the conservative flux (0: Chai2018)
 
     @property
     def shape(self):
@@ -201,6 +210,35 @@ def h_eq_ch(p, phi, mu_phi, u):
     return out
 
 
+def h_eq_nl(p, phi, u):
+    """Eq. Chai_geq: w phi (1 + e.u / c_s^2)."""
+    lat = p.lattices[1]
+    out = np.empty((lat.Q,) + phi.shape, dtype=np.result_type(phi, u))
+    for a in range(lat.Q):
+        out[a] = lat.w[a] * phi * (1 + _cdot(lat.c[a], u) / CS2)
+    return out
+
+
+def nonlocal_source(p, phi):
+    """Source of the nonlocal AC equation (Eqs. nonlocalAC, chai_G without the
+    weight w_a) at the field phi, and the Lagrange multiplier gamma of Eq.
+    lagrange_multiplier with the integrals taken as sums over all nodes:
+        R = M [ -(4 beta / kappa) (phi - phi_H)(phi - phi_L)(phi - phi_0)
+                + gamma (phi_H - phi)(phi - phi_L) ],
+        gamma = sum (4 beta / kappa)(phi - phi_H)(phi - phi_L)(phi - phi_0)
+                / sum (phi_H - phi)(phi - phi_L),
+    so that sum R = 0. 4 beta / kappa = 32 / (W^2 (phi_H - phi_L)^2): sigma
+    cancels (defined at sigma = 0). gamma = 0 when the denominator vanishes
+    (phi is phi_H or phi_L everywhere, where the gamma term is zero anyway)."""
+    c = 32.0 / (p.W * p.W * (PHI_H - PHI_L) ** 2)
+    bulk = c * (phi - PHI_H) * (phi - PHI_L) * (phi - PHI_0)
+    well = (PHI_H - phi) * (phi - PHI_L)
+    num = np.sum(bulk)
+    den = np.sum(well)
+    gamma = num / den if np.real(den) != 0 else 0.0 * num
+    return p.M * (-bulk + gamma * well), gamma
+
+
 def coefficients(p):
     """beta and kappa of Eqs. coefficient1 and coefficients."""
     dphi = PHI_H - PHI_L
@@ -270,6 +308,10 @@ def macroscopic(p, st):
     phi = st.h[0].copy()
     for a in range(1, hl.Q):
         phi = phi + st.h[a]
+    R = gamma = None
+    if p.model == "NL":
+        R, gamma = nonlocal_source(p, phi)
+        phi = phi + 0.5 * (1 - p.lam) * R
     # O2, O3
     grad = gradient(p, phi)
     lap = laplacian(p, phi)
@@ -314,7 +356,7 @@ def macroscopic(p, st):
     F = Fs + Fb + Fp + Fmu
     u = j + F / (2 * rho)
     return dict(phi=phi, grad=grad, lap=lap, rho=rho, nu=nu, tau=tau, mu_phi=mu_phi,
-                pstar=pstar, p=pres, F=F, u=u)
+                pstar=pstar, p=pres, F=F, u=u, R=R, gamma=gamma)
 
 
 # --------------------------------------------------------------------------
@@ -334,6 +376,13 @@ def collide_h(p, st, m):
         heq = h_eq_ch(p, m["phi"], m["mu_phi"], m["u"])
         phiu = m["phi"] * m["u"]
         G = G_ch(p, phiu - st.phiu_prev)       # backward Euler, delta t = 1
+    elif p.model == "NL":
+        # Eqs. Chai_geq and Hu_G (lam = 0: Eq. chai_G)
+        heq = h_eq_nl(p, m["phi"], m["u"])
+        w = p.lattices[1].w
+        G = p.lam * G_ac(p, m["phi"], m["grad"])
+        for a in range(p.lattices[1].Q):
+            G[a] = G[a] + (1 - p.lam) * w[a] * m["R"]
     else:
         heq = h_eq_ac(p, m["phi"], m["u"])
         G = G_ac(p, m["phi"], m["grad"])
@@ -420,7 +469,9 @@ def run(p, st, nsteps):
 
 
 def init(p, phi0, u0=None, p0=None):
-    """h = h_eq(phi0, u0), g = g_eq(p0 / (rho0 c_s^2), u0); CH also stores phi0 u0."""
+    """h = h_eq(phi0, u0), g = g_eq(p0 / (rho0 c_s^2), u0); CH also stores phi0 u0.
+    For NL this makes sum_a h_a = phi0 (the corrected phi of the first step then
+    adds (1 - lam) R(phi0) / 2)."""
     phi0 = np.asarray(phi0)
     dt = np.result_type(phi0, 1.0)
     if u0 is None:
@@ -438,6 +489,8 @@ def init(p, phi0, u0=None, p0=None):
         mu0 = chemical_potential(p, phi0, laplacian(p, phi0))
         h = h_eq_ch(p, phi0, mu0, u0)
         return State(g, h, phi0 * u0)
+    if p.model == "NL":
+        return State(g, h_eq_nl(p, phi0, u0), None)
     return State(g, h_eq_ac(p, phi0, u0), None)
 
 
