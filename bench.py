@@ -26,14 +26,18 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_tgv256.json")
 
 def bytes_per_update(d, precision):
     """Algorithmic HBM bytes of one lattice update: every stored population
-    read once and written once (AC on D3Q7 stores 6 phase-field populations;
-    CH also carries the 3 components of (phi u))."""
+    read once and written once (AC and the nonlocal model on D3Q7 store 6
+    phase-field populations; CH also carries the 3 components of (phi u); the
+    nonlocal model reads the phase-field populations once more for the global
+    sums of its multiplier)."""
     d3 = d["lattice"] == "D3Q19_D3Q7"
     qg = 19 if d3 else 9
-    qh = (6 if d["model"] == "AC" else 7) if d3 else 5
+    qh = (7 if d["model"] == "CH" else 6) if d3 else 5
     sg = {"fp64": 8, "fp32": 4, "mixed_fp16": 2, "mixed_bf16": 2}[precision]
     sh = 8 if precision == "fp64" else 4
     extra = 2 * 3 * (8 if precision == "fp64" else 4) if d["model"] == "CH" else 0
+    if d["model"] == "NL":
+        extra += qh * sh
     return 2 * (qg * sg + qh * sh) + extra
 
 
@@ -134,6 +138,7 @@ def main():
     ap.add_argument("--err-steps", type=int, default=500)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--no-models", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy first (counter calibration)")
     args = ap.parse_args()
@@ -188,6 +193,21 @@ def main():
         errors["laminar_sheared_droplet_64"] = {
             "steps": 1000, "rel_l2": field_errors(dl, phl, ul, 1000, ("fp32", "mixed_fp16", "mixed_bf16"))}
 
+    # the other phase-field models on the same workload and storage form
+    models = {}
+    if not args.no_models:
+        for model, extra in (("CH", {}), ("NL", {"lam": 0.0}), ("NL", {"lam": 0.9})):
+            dm = dict(d, model=model, **extra)
+            key = model if model != "NL" else "NL_lam%g" % extra["lam"]
+            print("bench: model %s" % key, file=sys.stderr, flush=True)
+            sm, msm, _ = time_form(dm, phi, u, args.precision, max(60, args.steps // 3), 10, args.zblock)
+            b = bytes_per_update(dm, args.precision)
+            models[key] = {"MLUPS": round(nodes / (msm * 1e-3) / 1e6, 1), "ms_per_step": round(msm, 4),
+                           "bytes_per_update": b,
+                           "hbm_frac": round(b * nodes / (msm * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+            del sm
+            torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu:
         print("bench: oracle cpu baseline", file=sys.stderr, flush=True)
@@ -222,6 +242,7 @@ def main():
                      "bytes_per_update": bpu},
         "cpu_baseline": cpu,
         "forms": forms,
+        "models": models,
         "errors_vs_fp64": errors,
         "wall_s_timed": round(wall, 3),
     }

@@ -70,6 +70,11 @@ extern "C" {
 /* phase-field model */
 #define PFLBM_AC 0   /* conservative Allen-Cahn, Eqs. fakhari_geq, fakhari_G_modified */
 #define PFLBM_CH 1   /* Cahn-Hilliard, Eqs. liang2_geq, liang2_G */
+#define PFLBM_NL 2   /* nonlocal Allen-Cahn, Eqs. Chai_geq, chai_G (Chai2018), the source
+                        blended with the conservative flux by lam as in Eq. Hu_G (Hu2019);
+                        phi = sum h + (1 - lam) R / 2 (Eq. chai2018_phi_update), with the
+                        multiplier gamma of Eq. lagrange_multiplier reduced over the whole
+                        box in float64 before every step */
 
 /* storage / arithmetic form */
 #define PFLBM_FP64        0  /* g, h float64; float64 arithmetic */
@@ -95,7 +100,7 @@ extern "C" {
 
 typedef struct pflbm_params {
     int lattice;          /* PFLBM_D2Q9_D2Q5 or PFLBM_D3Q19_D3Q7 */
-    int model;            /* PFLBM_AC or PFLBM_CH */
+    int model;            /* PFLBM_AC, PFLBM_CH or PFLBM_NL */
     int precision;        /* PFLBM_FP64 ... PFLBM_MIXED_BF16 */
     int nx, ny, nz;       /* nodes per axis, each >= 1; nz == 1 for 2-D */
     int bc[3];            /* PFLBM_PERIODIC or PFLBM_WALL per axis x, y, z */
@@ -115,6 +120,8 @@ typedef struct pflbm_params {
     double force[3];      /* uniform force density added to F_b (Sec. III.D drive) */
     double s_other;       /* MRT rate of every non-stress moment, in (0, 2) */
     double normal_eps;    /* interface normal n = grad phi / sqrt(|grad phi|^2 + eps^2), >= 0 */
+    double lam;           /* PFLBM_NL: weight of the conservative flux in [0, 1]
+                             (0 = Chai2018, Hu2019 uses 0.9); ignored otherwise */
     int freeze_phi;       /* nonzero: h (hence phi) is not updated (Sec. III.D) */
     int check_interval;   /* every this many steps pflbm_step checks for NaN/Inf
                              or rho <= 0 (synchronising); 0 = never */

@@ -32,6 +32,9 @@ struct PhysT {
     T g_fac_phi;       // 1 - 1 / (2 tau_phi)
     T eta;             // CH mobility parameter
     T s_o;             // MRT rate of the non-stress moments
+    T lam;             // nonlocal model: weight of the conservative flux
+    T mob;             // mobility M (nonlocal source)
+    T w32;             // 4 beta / kappa = 32 / W^2
     T body[3];         // gravity (F_b = rho body + force)
     T force[3];
 };
@@ -47,6 +50,7 @@ __host__ __device__ inline PhysT<float> to_float(const PhysT<T>& d) {
     f.beta4 = (float)d.beta4; f.kappa = (float)d.kappa; f.anti = (float)d.anti;
     f.eps2 = (float)d.eps2; f.inv_tau_phi = (float)d.inv_tau_phi; f.g_fac_phi = (float)d.g_fac_phi;
     f.eta = (float)d.eta; f.s_o = (float)d.s_o;
+    f.lam = (float)d.lam; f.mob = (float)d.mob; f.w32 = (float)d.w32;
     for (int k = 0; k < 3; ++k) { f.body[k] = (float)d.body[k]; f.force[k] = (float)d.force[k]; }
     return f;
 }
@@ -72,6 +76,7 @@ struct KArgs {
     double* f_p;
     double* f_rho;
     double* partials;      // MODE_DIAG per-block partials [nblocks][NDIAG]
+    const double* gamma;   // nonlocal model: multiplier of this step (device)
     int P;                 // elements per population plane (>= nx * ny)
     int nx, ny, nz;
     int ntx, nty, ntz, zb; // tiles per axis, z planes per tile
@@ -114,6 +119,17 @@ struct IOArgs {
     double gcorr[2][MAXQ];
 };
 
+// float64 sums of the nonlocal multiplier over the current phase-field buffer
+struct GammaArgs {
+    const void* h;         // current (post-collision) phase-field buffer
+    double* partials;      // [blocks][2]
+    double* gamma;         // result
+    int P;
+    int nx, ny, nz;
+    int bc[3];
+    double w32;            // 4 beta / kappa
+};
+
 // discrete adjoint of one AC step on canonical float64 arrays [q][z][y][x]
 struct AdjArgs {
     const double* fg;      // forward state X^n (post-streaming)
@@ -151,6 +167,7 @@ hipError_t launch_init(int lattice, int model, int precision, const InitArgs& a,
 hipError_t launch_get(int lattice, int model, int precision, const IOArgs& a, hipStream_t s);
 hipError_t launch_set(int lattice, int model, int precision, const IOArgs& a, hipStream_t s);
 hipError_t launch_reduce(const double* partials, int nblocks, double* out, hipStream_t s);
+hipError_t launch_gamma(int lattice, int precision, const GammaArgs& a, hipStream_t s);
 hipError_t launch_header(void* dst, long long steps, hipStream_t s);
 
 }  // namespace pfk

@@ -150,9 +150,22 @@ template <> __device__ __forceinline__ double rsqrt_<double>(double x) { return 
 // is formed (so that no array of outputs stays live). Populations are treated
 // in opposite pairs (c, -c): equilibria and sources split into a part even in
 // c, shared by the pair, and an odd part that changes sign.
+// Nonlocal model: source R of the nonlocal AC equation at phi* = sum h (Eq.
+// chai_G without its weight) and the phase field phi = phi* + (1 - lam) R / 2
+// (Eq. chai2018_phi_update, sum_a G_a = (1 - lam) R). The halo fill and the
+// node update evaluate both with these same expressions, so they agree bitwise.
+template <class T>
+__device__ __forceinline__ T nl_source(const PhysT<T>& ph, T phis, T gam) {
+    return ph.mob * (gam * phis * ((T)1 - phis) - ph.w32 * (phis - (T)1) * phis * (phis - (T)0.5));
+}
+template <class T>
+__device__ __forceinline__ T nl_phi(const PhysT<T>& ph, T phis, T gam) {
+    return phis + (T)0.5 * ((T)1 - ph.lam) * nl_source(ph, phis, gam);
+}
+
 template <class PAIR, int MODEL, class T, bool COLLIDE, class GSink, class HSink>
 __device__ __forceinline__ void node_update(const PhysT<T>& ph, const T* g, const T* h, const T* phin,
-                                            const T* pu_prev, T* pu_new, NodeOut<T>& mo,
+                                            const T* pu_prev, T* pu_new, NodeOut<T>& mo, const T gam,
                                             GSink&& gsink, HSink&& hsink) {
     using GL = typename PAIR::G;
     using HL = typename PAIR::H;
@@ -291,12 +304,32 @@ __device__ __forceinline__ void node_update(const PhysT<T>& ph, const T* g, cons
     // ---- h collision (BGK): h* = (1 - 1/tau_phi) h + h_eq / tau_phi + (1 - 1/(2 tau_phi)) G
     const T itp = ph.inv_tau_phi, gfp = ph.g_fac_phi;
     const T itp1 = (T)1 - itp;
+    // phi* = sum h, in the order of the halo fill
+    constexpr int HOFF = (MODEL != 1 && D3) ? 1 : 0;
+    T phis = (T)0;
+    unroll<HL::Q - HOFF>([&](auto J) { phis += h[J + HOFF]; });
+    // Float forms: the rounded weights do not sum to one (6 fl(1/6) = 1 + 3e-8),
+    // which would add a fixed fraction of phi to the phase-field mass every
+    // step. There the last population closes the node's exact balance instead:
+    // sum_a h*_a = phi* + (1/(2 tau_phi) + 1 - 1/(2 tau_phi)) sum_a G_a, where
+    // sum_a G_a = (1 - lam) R for the nonlocal model and 0 otherwise.
+    constexpr bool CLOSE = sizeof(T) == 4;
+    T hacc = (T)0, htarget = phis;
+    auto put = [&](auto J, T v) {
+        if constexpr (CLOSE) hacc += v;
+        hsink(J, v);
+    };
+    auto put_pair = [&](auto K, auto A, auto O, T va, T vo) {
+        put(A, va);
+        if constexpr (CLOSE && decltype(K)::value == HL::NP - 1) hsink(O, htarget - hacc);
+        else put(O, vo);
+    };
     if constexpr (MODEL == 0) {
         const T gg = gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2];
         const T coef = ph.anti * phi * ((T)1 - phi) * rsqrt_(gg + ph.eps2);
         const T e0 = phi * ((T)1 - (T)1.5 * usq);
         if constexpr (HL::w(0) != 0.0)
-            hsink(std::integral_constant<int, 0>{}, itp1 * h[0] + itp * (T)HL::w(0) * e0);
+            put(std::integral_constant<int, 0>{}, itp1 * h[0] + itp * (T)HL::w(0) * e0);
         unroll<HL::NP>([&](auto K) {
             constexpr int al = HL::pf(K), o = HL::opp(al);
             constexpr T w = (T)HL::w(al);
@@ -307,8 +340,33 @@ __device__ __forceinline__ void node_update(const PhysT<T>& ph, const T* g, cons
             if constexpr (ez != 0) { eu += (T)ez * u[2]; eg += (T)ez * gr[2]; }
             const T base = itp * w * (e0 + (T)4.5 * phi * eu * eu);
             const T t = itp * ((T)3 * w * phi * eu) + gfp * w * coef * eg;
-            hsink(std::integral_constant<int, al>{}, itp1 * h[al] + base + t);
-            hsink(std::integral_constant<int, o>{}, itp1 * h[o] + base - t);
+            put_pair(K, std::integral_constant<int, al>{}, std::integral_constant<int, o>{},
+                     itp1 * h[al] + base + t, itp1 * h[o] + base - t);
+        });
+    } else if constexpr (MODEL == 2) {
+        // Eqs. Chai_geq, Hu_G: h_eq = w phi (1 + e.u / c_s^2),
+        // G = lam w e.[(4/W) phi (1 - phi) n] + (1 - lam) w R, R at phi* = sum h
+        const T R = nl_source(ph, phis, gam);
+        htarget = phis + ((T)1 - ph.lam) * ((T)0.5 * itp + gfp) * R;
+        const T gg = gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2];
+        const T coef = ph.anti * phi * ((T)1 - phi) * rsqrt_(gg + ph.eps2);
+        const T gcon = gfp * ph.lam * coef;
+        const T giso = gfp * ((T)1 - ph.lam) * R;
+        const T e0 = itp * phi + giso;
+        if constexpr (HL::w(0) != 0.0)
+            put(std::integral_constant<int, 0>{}, itp1 * h[0] + (T)HL::w(0) * e0);
+        unroll<HL::NP>([&](auto K) {
+            constexpr int al = HL::pf(K), o = HL::opp(al);
+            constexpr T w = (T)HL::w(al);
+            constexpr int ex = HL::c(al, 0), ey = HL::c(al, 1), ez = HL::c(al, 2);
+            T eu = (T)0, eg = (T)0;
+            if constexpr (ex != 0) { eu += (T)ex * u[0]; eg += (T)ex * gr[0]; }
+            if constexpr (ey != 0) { eu += (T)ey * u[1]; eg += (T)ey * gr[1]; }
+            if constexpr (ez != 0) { eu += (T)ez * u[2]; eg += (T)ez * gr[2]; }
+            const T base = w * e0;
+            const T t = itp * ((T)3 * w * phi * eu) + gcon * w * eg;
+            put_pair(K, std::integral_constant<int, al>{}, std::integral_constant<int, o>{},
+                     itp1 * h[al] + base + t, itp1 * h[o] + base - t);
         });
     } else {
         const T eta = ph.eta;
@@ -320,7 +378,7 @@ __device__ __forceinline__ void node_update(const PhysT<T>& ph, const T* g, cons
             pu_new[a] = pu[a];
         });
         const T emu = eta * mu_phi;
-        hsink(std::integral_constant<int, 0>{}, itp1 * h[0] + itp * (phi + ((T)HL::w(0) - (T)1) * emu));
+        put(std::integral_constant<int, 0>{}, itp1 * h[0] + itp * (phi + ((T)HL::w(0) - (T)1) * emu));
         unroll<HL::NP>([&](auto K) {
             constexpr int al = HL::pf(K), o = HL::opp(al);
             constexpr T w = (T)HL::w(al);
@@ -331,8 +389,8 @@ __device__ __forceinline__ void node_update(const PhysT<T>& ph, const T* g, cons
             if constexpr (ez != 0) { ep += (T)ez * pu[2]; ed += (T)ez * dpu[2]; }
             const T base = itp * w * emu;
             const T t = itp * ((T)3 * w * ep) + gfp * (T)3 * w * ed;
-            hsink(std::integral_constant<int, al>{}, itp1 * h[al] + base + t);
-            hsink(std::integral_constant<int, o>{}, itp1 * h[o] + base - t);
+            put_pair(K, std::integral_constant<int, al>{}, std::integral_constant<int, o>{},
+                     itp1 * h[al] + base + t, itp1 * h[o] + base - t);
         });
     }
 }
@@ -504,7 +562,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
     using GC = GCodec<PREC>;
     constexpr int QG = GL::Q, QH = HL::Q;
     constexpr bool D3 = PAIR::dim == 3;
-    constexpr int HOFF = (MODEL == 0 && D3) ? 1 : 0;   // AC on D3Q7: rest population not stored
+    constexpr int HOFF = (MODEL != 1 && D3) ? 1 : 0;   // AC / NL on D3Q7: zero-weight rest population not stored
     constexpr int QHS = QH - HOFF;
     constexpr int TX = TS == 0 ? 64 : (TS == 1 ? 128 : 256), TY = BLOCK / TX;
     constexpr int PW = TX + 2, PSZ = PW * (TY + 2);
@@ -532,6 +590,8 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
     if constexpr (sizeof(T) == 8) php = &a.ph;
     else php = &a.phf;
     const PhysT<T>& ph = *php;
+    T gam = (T)0;                    // nonlocal multiplier of this step
+    if constexpr (MODEL == 2) gam = (T)*a.gamma;
     auto gcorr = [&](int side, int i) -> T {
         if constexpr (sizeof(T) == 8) return a.gcorr[side][i];
         else return a.gcorrf[side][i];
@@ -595,10 +655,12 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
             constexpr int al = J + HOFF;
             s += hn[al];
         });
+        if constexpr (MODEL == 2) s = nl_phi(ph, s, gam);
         lphi[slot * PSZ + own_lds] = s;
         for (int k = 0; k < NR; ++k) {
             T sr = (T)0;
             unroll<QHS>([&](auto J) { sr += rv[k][J]; });
+            if constexpr (MODEL == 2) sr = nl_phi(ph, sr, gam);
             if (ring[k]) lphi[slot * PSZ + ring_lds[k]] = sr;
         }
     };
@@ -665,7 +727,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
                     if (a.write_h) __builtin_nontemporal_store((HS)v, &at<QHS>(Hout, z, al - HOFF, P, o11));
                 }
             };
-            node_update<PAIR, MODEL, T, true>(ph, g, h, phin, pu_prev, pu_new, mo, gsink, hsink);
+            node_update<PAIR, MODEL, T, true>(ph, g, h, phin, pu_prev, pu_new, mo, gam, gsink, hsink);
             if constexpr (MODEL == 1) {
                 if (a.write_h) {
                     unroll<3>([&](auto A) {
@@ -676,7 +738,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
             }
         } else {
             auto none = [](auto, T) {};
-            node_update<PAIR, MODEL, T, false>(ph, g, h, phin, pu_prev, pu_new, mo, none, none);
+            node_update<PAIR, MODEL, T, false>(ph, g, h, phin, pu_prev, pu_new, mo, gam, none, none);
             const size_t idx = ((size_t)z * ny + y) * nx + x;    // canonical index
             if constexpr (MODE == MODE_FIELDS) {
                 if (a.f_phi) a.f_phi[idx] = (double)mo.phi;
@@ -804,7 +866,7 @@ __global__ __launch_bounds__(256) void k_init(const InitArgs a) {
     using HS = typename Types<PREC>::HS;
     using GC = GCodec<PREC>;
     constexpr bool D3 = PAIR::dim == 3;
-    constexpr int HOFF = (MODEL == 0 && D3) ? 1 : 0;
+    constexpr int HOFF = (MODEL != 1 && D3) ? 1 : 0;
     constexpr int QHS = HL::Q - HOFF;
     const long long nn = (long long)a.nx * a.ny * a.nz;
     const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -846,6 +908,12 @@ __global__ __launch_bounds__(256) void k_init(const InitArgs a) {
             const double eu = HL::c(al, 0) * u[0] + HL::c(al, 1) * u[1] + HL::c(al, 2) * u[2];
             const double heq = HL::w(al) * phi * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * usq);
             put_h(std::integral_constant<int, al>{}, heq);
+        });
+    } else if constexpr (MODEL == 2) {
+        unroll<QHS>([&](auto J) {
+            constexpr int al = J + HOFF;
+            const double eu = HL::c(al, 0) * u[0] + HL::c(al, 1) * u[1] + HL::c(al, 2) * u[2];
+            put_h(std::integral_constant<int, al>{}, HL::w(al) * phi * (1.0 + 3.0 * eu));
         });
     } else {
         // mu_phi(phi0) with the same stencil and ghost rules as the step
@@ -889,7 +957,7 @@ __global__ __launch_bounds__(256) void k_get(const IOArgs a) {
     using HS = typename Types<PREC>::HS;
     using GC = GCodec<PREC>;
     constexpr bool D3 = PAIR::dim == 3;
-    constexpr int HOFF = (MODEL == 0 && D3) ? 1 : 0;
+    constexpr int HOFF = (MODEL != 1 && D3) ? 1 : 0;
     constexpr int QHS = HL::Q - HOFF;
     const long long nn = (long long)a.nx * a.ny * a.nz;
     const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -929,7 +997,7 @@ __global__ __launch_bounds__(256) void k_set(const IOArgs a) {
     using HS = typename Types<PREC>::HS;
     using GC = GCodec<PREC>;
     constexpr bool D3 = PAIR::dim == 3;
-    constexpr int HOFF = (MODEL == 0 && D3) ? 1 : 0;
+    constexpr int HOFF = (MODEL != 1 && D3) ? 1 : 0;
     constexpr int QHS = HL::Q - HOFF;
     const long long nn = (long long)a.nx * a.ny * a.nz;
     const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -954,6 +1022,86 @@ __global__ __launch_bounds__(256) void k_set(const IOArgs a) {
         H[pull_source<HL, al, QHS, HOFF>(a.nx, a.ny, a.nz, a.bc, x, y, z, a.P, w, side)] =
             (HS)a.ch[(size_t)al * nn + n];
     });
+}
+
+// ----------------------------------------------------------------------------
+// nonlocal multiplier: gamma = sum (4 beta/kappa)(phi* - 1) phi* (phi* - 1/2)
+// / sum (1 - phi*) phi* over all nodes (Eq. lagrange_multiplier), phi* the
+// post-streaming sum of h pulled from the current buffer; float64 sums in a
+// fixed order (bit-reproducible)
+
+template <class PAIR, int PREC>
+__global__ __launch_bounds__(256) void k_gamma_part(const GammaArgs a) {
+    using HL = typename PAIR::H;
+    using T = typename Types<PREC>::T;
+    using HS = typename Types<PREC>::HS;
+    constexpr int HOFF = PAIR::dim == 3 ? 1 : 0;
+    constexpr int QHS = HL::Q - HOFF;
+    __shared__ double red[2][256 / 64];
+    const long long nn = (long long)a.nx * a.ny * a.nz;
+    const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
+    double num = 0.0, den = 0.0;
+    if (n < nn) {
+        const int x = (int)(n % a.nx), y = (int)((n / a.nx) % a.ny), z = (int)(n / ((long long)a.nx * a.ny));
+        const HS* H = (const HS*)a.h;
+        T s = (T)0;                  // same summation order as the step's halo fill
+        unroll<QHS>([&](auto J) {
+            constexpr int al = J + HOFF;
+            bool w;
+            int side;
+            s += (T)H[pull_source<HL, al, QHS, HOFF>(a.nx, a.ny, a.nz, a.bc, x, y, z, a.P, w, side)];
+        });
+        const double phi = (double)s;
+        num = a.w32 * (phi - 1.0) * phi * (phi - 0.5);
+        den = (1.0 - phi) * phi;
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        num += __shfl_xor(num, off, 64);
+        den += __shfl_xor(den, off, 64);
+    }
+    const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+    if (lane == 0) {
+        red[0][wv] = num;
+        red[1][wv] = den;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sn = red[0][0], sd = red[1][0];
+        for (int k = 1; k < 256 / 64; ++k) {
+            sn += red[0][k];
+            sd += red[1][k];
+        }
+        a.partials[2 * (size_t)blockIdx.x] = sn;
+        a.partials[2 * (size_t)blockIdx.x + 1] = sd;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gamma_final(const double* __restrict__ part, long long nb,
+                                                     double* __restrict__ gamma) {
+    __shared__ double red[2][256 / 64];
+    double num = 0.0, den = 0.0;
+    for (long long b = threadIdx.x; b < nb; b += 256) {
+        num += part[2 * b];
+        den += part[2 * b + 1];
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        num += __shfl_xor(num, off, 64);
+        den += __shfl_xor(den, off, 64);
+    }
+    const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+    if (lane == 0) {
+        red[0][wv] = num;
+        red[1][wv] = den;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sn = red[0][0], sd = red[1][0];
+        for (int k = 1; k < 256 / 64; ++k) {
+            sn += red[0][k];
+            sd += red[1][k];
+        }
+        gamma[0] = sd != 0.0 ? sn / sd : 0.0;
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -1001,8 +1149,12 @@ static hipError_t step_prec(int prec, int mode, const KArgs& a, hipStream_t s) {
 
 hipError_t launch_step(int lattice, int model, int precision, int mode, const KArgs& a, hipStream_t s) {
     if (lattice == 0)
-        return model ? step_prec<Pair2D, 1>(precision, mode, a, s) : step_prec<Pair2D, 0>(precision, mode, a, s);
-    return model ? step_prec<Pair3D, 1>(precision, mode, a, s) : step_prec<Pair3D, 0>(precision, mode, a, s);
+        return model == 2 ? step_prec<Pair2D, 2>(precision, mode, a, s)
+             : model == 1 ? step_prec<Pair2D, 1>(precision, mode, a, s)
+                          : step_prec<Pair2D, 0>(precision, mode, a, s);
+    return model == 2 ? step_prec<Pair3D, 2>(precision, mode, a, s)
+         : model == 1 ? step_prec<Pair3D, 1>(precision, mode, a, s)
+                      : step_prec<Pair3D, 0>(precision, mode, a, s);
 }
 
 #define PFLBM_NODE_DISPATCH(KERNEL, ARGS, NN)                                               \
@@ -1022,7 +1174,8 @@ hipError_t launch_step(int lattice, int model, int precision, int mode, const KA
             }                                                                                \
         };                                                                                   \
         auto mdl = [&](auto pair) {                                                          \
-            if (model) prec(pair, std::integral_constant<int, 1>{});                         \
+            if (model == 2) prec(pair, std::integral_constant<int, 2>{});                    \
+            else if (model == 1) prec(pair, std::integral_constant<int, 1>{});               \
             else prec(pair, std::integral_constant<int, 0>{});                               \
         };                                                                                   \
         if (lattice == 0) mdl(Pair2D{});                                                     \
@@ -1044,6 +1197,27 @@ hipError_t launch_get(int lattice, int model, int precision, const IOArgs& a, hi
 hipError_t launch_set(int lattice, int model, int precision, const IOArgs& a, hipStream_t s) {
     const long long nn = (long long)a.nx * a.ny * a.nz;
     PFLBM_NODE_DISPATCH(k_set, a, nn);
+    return hipGetLastError();
+}
+
+hipError_t launch_gamma(int lattice, int precision, const GammaArgs& a, hipStream_t s) {
+    const long long nn = (long long)a.nx * a.ny * a.nz;
+    const long long nb = (nn + 255) / 256;
+    const dim3 grid((unsigned)nb), block(256);
+    auto go = [&](auto pair) {
+        using P_ = decltype(pair);
+        switch (precision) {
+            case 0: hipLaunchKernelGGL((k_gamma_part<P_, 0>), grid, block, 0, s, a); break;
+            case 1: hipLaunchKernelGGL((k_gamma_part<P_, 1>), grid, block, 0, s, a); break;
+            case 2: hipLaunchKernelGGL((k_gamma_part<P_, 2>), grid, block, 0, s, a); break;
+            default: hipLaunchKernelGGL((k_gamma_part<P_, 3>), grid, block, 0, s, a);
+        }
+    };
+    if (lattice == 0) go(Pair2D{});
+    else go(Pair3D{});
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gamma_final, dim3(1), dim3(256), 0, s, (const double*)a.partials, nb, a.gamma);
     return hipGetLastError();
 }
 

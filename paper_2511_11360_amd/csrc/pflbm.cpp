@@ -27,7 +27,7 @@ struct Layout {
     int P = 0;                       // elements per population plane
     int ntx = 0, nty = 0, ntz = 0, zb = 0, nblocks = 0;   // 64 x 4 tiles (fields, diagnostics)
     int tile_step = 0, ntx_step = 0, nty_step = 0;        // tiles of the step kernel
-    size_t off_g[2] = {0, 0}, off_h[2] = {0, 0}, off_pu = 0, off_part = 0, off_res = 0, total = 0;
+    size_t off_g[2] = {0, 0}, off_h[2] = {0, 0}, off_pu = 0, off_part = 0, off_gpart = 0, off_res = 0, total = 0;
     size_t ck_g = 0, ck_h = 0, ck_pu = 0, ck_total = 0;
     size_t g_bytes = 0, h_bytes = 0, pu_bytes = 0;
 };
@@ -40,7 +40,8 @@ bool finite(double v) { return std::isfinite(v); }
 // validate; returns an error message or empty string
 std::string validate(const pflbm_params& p) {
     if (p.lattice != PFLBM_D2Q9_D2Q5 && p.lattice != PFLBM_D3Q19_D3Q7) return "lattice must be PFLBM_D2Q9_D2Q5 or PFLBM_D3Q19_D3Q7";
-    if (p.model != PFLBM_AC && p.model != PFLBM_CH) return "model must be PFLBM_AC or PFLBM_CH";
+    if (p.model != PFLBM_AC && p.model != PFLBM_CH && p.model != PFLBM_NL)
+        return "model must be PFLBM_AC, PFLBM_CH or PFLBM_NL";
     if (p.precision < PFLBM_FP64 || p.precision > PFLBM_MIXED_BF16) return "unknown precision";
     if (p.nx < 1 || p.ny < 1 || p.nz < 1) return "nx, ny, nz must be >= 1";
     if (p.lattice == PFLBM_D2Q9_D2Q5 && p.nz != 1) return "2-D lattice requires nz == 1";
@@ -69,6 +70,7 @@ std::string validate(const pflbm_params& p) {
     if (!(p.eta > 0) || !finite(p.eta)) return "eta must be > 0";
     if (!(p.s_other > 0 && p.s_other < 2)) return "s_other must be in (0, 2)";
     if (!(p.normal_eps >= 0) || !finite(p.normal_eps)) return "normal_eps must be >= 0";
+    if (!(p.lam >= 0 && p.lam <= 1)) return "lam must be in [0, 1]";
     for (int a = 0; a < 3; ++a)
         if (!finite(p.gravity[a]) || !finite(p.force[a])) return "body force not finite";
     if (p.lattice == PFLBM_D2Q9_D2Q5 && (p.gravity[2] != 0.0 || p.force[2] != 0.0)) return "2-D body force has a z component";
@@ -84,7 +86,7 @@ Layout make_layout(const pflbm_params& p) {
     L.dim = d3 ? 3 : 2;
     L.Qg = d3 ? 19 : 9;
     L.Qh = d3 ? 7 : 5;
-    L.Qhs = (d3 && p.model == PFLBM_AC) ? 6 : L.Qh;   // AC on D3Q7: rest population is zero
+    L.Qhs = (d3 && p.model != PFLBM_CH) ? 6 : L.Qh;   // AC / NL on D3Q7: rest population is zero
     L.sT = p.precision == PFLBM_FP64 ? 8 : 4;
     L.sg = p.precision == PFLBM_FP64 ? 8 : (p.precision == PFLBM_FP32 ? 4 : 2);
     L.sh = p.precision == PFLBM_FP64 ? 8 : 4;
@@ -126,6 +128,8 @@ Layout make_layout(const pflbm_params& p) {
     if (p.model == PFLBM_CH) off = align_up(off + 3 * planes * L.sT, ALIGN);
     L.off_part = off;
     off = align_up(off + (size_t)L.nblocks * NDIAG * sizeof(double), ALIGN);
+    L.off_gpart = off;   // nonlocal multiplier: per-256-node partial sums
+    if (p.model == PFLBM_NL) off = align_up(off + (size_t)((L.nodes + 255) / 256) * 2 * sizeof(double), ALIGN);
     L.off_res = off;
     off = align_up(off + 64 * sizeof(double), ALIGN);
     L.total = off;
@@ -225,9 +229,31 @@ void base_args(pflbm_t* h, KArgs& a) {
     a.phf = h->phf;
 }
 
+// nonlocal model: the multiplier of the current state into its device slot
+constexpr int RES_GAMMA = 32;   // index in the result area
+
+int run_gamma(pflbm_t* h, KArgs& a) {
+    if (h->p.model != PFLBM_NL) return PFLBM_OK;
+    GammaArgs ga;
+    std::memset(&ga, 0, sizeof(ga));
+    ga.h = h->base + h->L.off_h[h->hcur];
+    ga.partials = (double*)(h->base + h->L.off_gpart);
+    ga.gamma = (double*)(h->base + h->L.off_res) + RES_GAMMA;
+    ga.P = h->L.P;
+    ga.nx = h->p.nx;
+    ga.ny = h->p.ny;
+    ga.nz = h->p.nz;
+    for (int k = 0; k < 3; ++k) ga.bc[k] = h->p.bc[k];
+    ga.w32 = h->ph.w32;
+    HIPCHK(h, launch_gamma(h->p.lattice, h->p.precision, ga, h->stream), "nonlocal multiplier kernels");
+    a.gamma = ga.gamma;
+    return PFLBM_OK;
+}
+
 int run_diag(pflbm_t* h, const double* centre, double R, double* res) {
     KArgs a;
     base_args(h, a);
+    if (int st = run_gamma(h, a)) return st;
     if (centre) {
         a.has_centre = 1;
         for (int k = 0; k < h->L.dim; ++k) a.centre[k] = centre[k];
@@ -301,6 +327,9 @@ int pflbm_create(const pflbm_params* params, void* hip_stream, void* dev_state, 
     ph.g_fac_phi = 1.0 - 0.5 / tau_phi;
     ph.eta = p.eta;
     ph.s_o = p.s_other;
+    ph.lam = p.lam;
+    ph.mob = p.M;
+    ph.w32 = 32.0 / (p.W * p.W);              // 4 beta / kappa
     for (int a = 0; a < 3; ++a) {
         ph.body[a] = p.gravity[a];
         ph.force[a] = p.force[a];
@@ -358,6 +387,7 @@ int pflbm_step(pflbm_t* h, int nsteps) {
         a.tile = h->L.tile_step;
         a.ntx = h->L.ntx_step;
         a.nty = h->L.nty_step;
+        if ((st = run_gamma(h, a))) return st;
         HIPCHK(h, launch_step(h->p.lattice, h->p.model, h->p.precision, MODE_STEP, a, h->stream), "step kernel");
         if (!h->p.freeze_phi) h->hcur ^= 1;
         h->gcur ^= 1;
@@ -385,6 +415,7 @@ int pflbm_fields(pflbm_t* h, double* phi, double* u, double* p, double* rho) {
     a.f_u = u;
     a.f_p = p;
     a.f_rho = rho;
+    if ((st = run_gamma(h, a))) return st;
     HIPCHK(h, launch_step(h->p.lattice, h->p.model, h->p.precision, MODE_FIELDS, a, h->stream), "fields kernel");
     return PFLBM_OK;
 }

@@ -18,6 +18,8 @@ PFLBM_D2Q9_D2Q5 = 0
 PFLBM_D3Q19_D3Q7 = 1
 PFLBM_AC = 0
 PFLBM_CH = 1
+PFLBM_NL = 2
+MODELS = {"AC": PFLBM_AC, "CH": PFLBM_CH, "NL": PFLBM_NL}
 PFLBM_FP64 = 0
 PFLBM_FP32 = 1
 PFLBM_MIXED_FP16 = 2
@@ -43,7 +45,7 @@ class pflbm_params(ctypes.Structure):
         ("M", ctypes.c_double), ("W", ctypes.c_double), ("sigma", ctypes.c_double),
         ("eta", ctypes.c_double),
         ("gravity", ctypes.c_double * 3), ("force", ctypes.c_double * 3),
-        ("s_other", ctypes.c_double), ("normal_eps", ctypes.c_double),
+        ("s_other", ctypes.c_double), ("normal_eps", ctypes.c_double), ("lam", ctypes.c_double),
         ("freeze_phi", ctypes.c_int), ("check_interval", ctypes.c_int), ("zblock", ctypes.c_int),
         ("tile", ctypes.c_int),
     ]
@@ -115,7 +117,7 @@ def make_params(d, precision="fp64", check_interval=0, zblock=0, tile="auto"):
     """pflbm_params from a workload dict (keys as in workloads.base_params)."""
     p = pflbm_params()
     p.lattice = PFLBM_D2Q9_D2Q5 if d["lattice"] == "D2Q9_D2Q5" else PFLBM_D3Q19_D3Q7
-    p.model = PFLBM_AC if d["model"] == "AC" else PFLBM_CH
+    p.model = MODELS[d["model"]]
     p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     p.nx, p.ny, p.nz = int(d["nx"]), int(d["ny"]), int(d["nz"])
     for a in range(3):
@@ -133,6 +135,7 @@ def make_params(d, precision="fp64", check_interval=0, zblock=0, tile="auto"):
         p.force[a] = float(d["force"][a])
     p.s_other = float(d.get("s_other", 1.0))
     p.normal_eps = float(d.get("normal_eps", 1e-4))
+    p.lam = float(d.get("lam", 0.0))
     p.freeze_phi = 1 if d.get("freeze_phi", False) else 0
     p.check_interval = int(check_interval)
     p.zblock = int(zblock)

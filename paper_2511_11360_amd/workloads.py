@@ -8,7 +8,7 @@ groups. Both the HIP path's tests and the oracle's tests take their inputs from
 here; parameters come back as a plain dict whose keys name the physical
 quantities (lattice, model, nx, ny, nz, bc, wall_u, rho_H, rho_L, nu_H, nu_L,
 visc_interp, M, W, sigma, eta, gravity, force, s_other, freeze_phi,
-normal_eps).
+normal_eps, lam).
 
 Arrays are float64, scalars (nz, ny, nx), vectors (dim, nz, ny, nx), x fastest;
 node (i, j, k) sits at (x, y, z) = (i, j, k).
@@ -25,7 +25,7 @@ def base_params(**kw):
              rho_H=1.0, rho_L=1.0, nu_H=0.1, nu_L=0.1, visc_interp="mu",
              M=0.02, W=4.0, sigma=0.01, eta=1.0,
              gravity=(0.0, 0.0, 0.0), force=(0.0, 0.0, 0.0),
-             s_other=1.0, freeze_phi=False, normal_eps=1e-4)
+             s_other=1.0, freeze_phi=False, normal_eps=1e-4, lam=0.0)
     p.update(kw)
     return p
 
