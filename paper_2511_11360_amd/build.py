@@ -14,7 +14,13 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpflbm.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["kernels.hip", "adjoint.hip", "pflbm.cpp"]
+# (source, object name, extra defines); the step kernel is instantiated once per
+# lattice pair and phase-field model, each in its own compilation (in parallel)
+PAIRS = (0, 1)
+MODELS = (0, 1, 2)
+SOURCES = ([("kernels.hip", "kernels", []), ("adjoint.hip", "adjoint", []), ("pflbm.cpp", "pflbm", [])]
+           + [("step_inst.hip", "step_p%d_m%d" % (p, m), ["-DPFK_PAIR=%d" % p, "-DPFK_MODEL=%d" % m])
+              for p in PAIRS for m in MODELS])
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -26,10 +32,10 @@ FLAGS = [
 ]
 
 
-def _compile(src):
-    obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
-    lang = ["-x", "hip"] if src.endswith(".hip") else ["-x", "hip"]
-    cmd = [HIPCC] + lang + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(item):
+    src, name, defines = item
+    obj = os.path.join(OBJDIR, name + ".o")
+    cmd = [HIPCC, "-x", "hip"] + FLAGS + defines + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, " ".join(cmd), r.stderr[-8000:]))
@@ -38,7 +44,7 @@ def _compile(src):
 
 def build(verbose=True):
     os.makedirs(OBJDIR, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+    with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 4)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs

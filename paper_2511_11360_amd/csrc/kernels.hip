@@ -1,821 +1,19 @@
-// HIP kernels of the fused phase-field lattice Boltzmann time step (gfx950).
-//
-// One launch = one time step of the coupled solver of the paper's Sec. II.C.1
-// (Fakhari2017 conservative Allen-Cahn; Cahn-Hilliard h-equation of Sec. II.D.1
-// as the second model). Per node, in this order:
-//   phi = sum_a h_a                                   (Eq. fakhari_phi_update)
-//   grad phi, lap phi from the isotropic central stencils of Sec. III on the
-//   hydrodynamic lattice, ghost phi = periodic image or wall mirror
-//   rho, nu, tau, mu_phi, p* = sum g, F_s, F_b, F_p   (Eqs. fakhari_rho_update,
-//   mu_linear, fakhari_tau_model, chemical_potential, fakhari_p_update, total force)
-//   F_mu = nu (grad u + grad u^T) . grad rho with the strain rate from the
-//   non-equilibrium second moment of g at u* = sum c g + (F_s+F_b+F_p)/(2 rho)
-//   u = sum c g + F/(2 rho)                           (Eq. fakhari_velocity_update)
-//   h: BGK with Eqs. fakhari_geq + fakhari_G_modified (AC) or liang2_geq +
-//   liang2_G with a backward-Euler d(phi u)/dt (CH)
-//   g: MRT with the stress moments at 1/tau and the rest at s_o, Eqs. fakhari_feq
-//   and fakhari_F; in moment space m* = m - S(m - m_eq) + (I - S/2) m_F, which for
-//   an orthogonal basis and two rates is
-//     g* = g - s_o (g - g_eq) - (1/tau - s_o) P (g - g_eq) + (1 - s_o/2) F_i
-//   with P the orthogonal projector on the stress rows (P F_i = 0: F_i is odd
-//   in c). P (g - g_eq) needs only the non-equilibrium second moment.
-//   streaming: g in place (AA pattern: even steps read and write the node's own
-//   slots swapped, odd steps gather from and scatter to the neighbours); h
-//   push-streamed from one buffer into the other. Halfway bounce-back at walls.
-//
-// Layout in HBM: structure of arrays, population-major, x fastest; population
-// stride N elements. g storage: float64, float32, or fp16/bf16 of g_i / w_i.
-//
-// Work decomposition: a workgroup owns a 64 x 4 (x, y) column tile and marches
-// over zb planes in z. phi of three planes (tile plus a one-node halo) is
-// rebuilt from h in LDS as a ring; the h buffer read this step is never written
-// during the step, so halo reads of other tiles' nodes are race-free.
-#include <hip/hip_runtime.h>
-#include <stdint.h>
-
-#include "internal.h"
-#include "lattice.h"
+// HIP kernels around the fused step (gfx950): initialisation, canonical
+// float64 I/O, the float64 reductions (diagnostics, nonlocal multiplier) and
+// the dispatch of the step kernel to its per-pair, per-model instantiations
+// (step_inst.hip). The device code of the step itself is in step.h.
+#include "step.h"
 
 namespace pfk {
 
-// ----------------------------------------------------------------------------
-// storage forms
-
-template <int P> struct Types;
-template <> struct Types<0> { using T = double; using GS = double;   using HS = double; };
-template <> struct Types<1> { using T = float;  using GS = float;    using HS = float;  };
-template <> struct Types<2> { using T = float;  using GS = _Float16; using HS = float;  };
-template <> struct Types<3> { using T = float;  using GS = uint16_t; using HS = float;  };
-
-// g codec: the scaled forms store s_i = K g_i / w_i (fp16, K = 4096) or g_i / w_i
-// (bf16), rounded to nearest even.
-template <int P> struct GCodec {
-    template <class L, int i, class GS, class T>
-    static __device__ __forceinline__ T dec(GS v) { return (T)v; }
-    template <class L, int i, class GS, class T>
-    static __device__ __forceinline__ GS enc(T v) { return (GS)v; }
-};
-template <> struct GCodec<2> {
-    template <class L, int i, class GS, class T>
-    static __device__ __forceinline__ float dec(_Float16 v) {
-        constexpr float s = (float)(L::w(i) / 4096.0);
-        return (float)v * s;
-    }
-    template <class L, int i, class GS, class T>
-    static __device__ __forceinline__ _Float16 enc(float v) {
-        constexpr float s = (float)(4096.0 / L::w(i));
-        return (_Float16)(v * s);
-    }
-};
-template <> struct GCodec<3> {
-    template <class L, int i, class GS, class T>
-    static __device__ __forceinline__ float dec(uint16_t v) {
-        constexpr float s = (float)L::w(i);
-        return __uint_as_float(((uint32_t)v) << 16) * s;
-    }
-    template <class L, int i, class GS, class T>
-    static __device__ __forceinline__ uint16_t enc(float v) {
-        constexpr float s = (float)(1.0 / L::w(i));
-        uint32_t u = __float_as_uint(v * s);
-        u += 0x7FFFu + ((u >> 16) & 1u);
-        return (uint16_t)(u >> 16);
-    }
-};
-
-// ----------------------------------------------------------------------------
-// index helpers
-
-__device__ __forceinline__ int ghost_coord(int v, int n, int bc) {
-    if (bc == 0) {
-        v %= n;
-        return v < 0 ? v + n : v;
-    }
-    return v < 0 ? 0 : (v >= n ? n - 1 : v);
-}
-
-// neighbour x + sgn c_i: linear index, or wall crossing (side 0 low, 1 high)
-template <class L, int i, int sgn>
-__device__ __forceinline__ bool shifted(int nx, int ny, int nz, const int* bc, int x, int y, int z,
-                                        int& idx, int& side) {
-    int co[3] = {x, y, z};
-    const int n[3] = {nx, ny, nz};
-    bool wall = false;
-    side = 0;
-    unroll<3>([&](auto A) {
-        constexpr int ax = A;
-        constexpr int d = sgn * L::c(i, ax);
-        if constexpr (d != 0) {
-            int v = co[ax] + d;
-            if (v < 0 || v >= n[ax]) {
-                if (bc[ax] == 0) {
-                    v = v < 0 ? v + n[ax] : v - n[ax];
-                } else {
-                    wall = true;
-                    side = v < 0 ? 0 : 1;
-                }
-            }
-            co[ax] = v;
-        }
-    });
-    idx = (co[2] * ny + co[1]) * nx + co[0];
-    return wall;
-}
-
-__device__ __forceinline__ int xcd_remap(int bid, int nb) {
-    // consecutive workgroup ids go to different XCDs (round robin over 8);
-    // give each XCD a contiguous run of tiles so halo rows stay in its L2
-    const int per = nb / 8;
-    if (bid >= per * 8) return bid;
-    return (bid % 8) * per + bid / 8;
-}
-
-// ----------------------------------------------------------------------------
-// the node update
-
-template <class T>
-struct NodeOut {
-    T phi, rho, p;
-    T u[3];
-};
-
-template <class T> __device__ __forceinline__ T rcp(T x);
-template <> __device__ __forceinline__ float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
-template <> __device__ __forceinline__ double rcp<double>(double x) { return 1.0 / x; }
-template <class T> __device__ __forceinline__ T rsqrt_(T x);
-template <> __device__ __forceinline__ float rsqrt_<float>(float x) { return __builtin_amdgcn_rsqf(x); }
-template <> __device__ __forceinline__ double rsqrt_<double>(double x) { return 1.0 / sqrt(x); }
-
-// Computes the macroscopic state of one node and, when COLLIDE, hands every
-// post-collision population to gsink(i, value) / hsink(a, value) as soon as it
-// is formed (so that no array of outputs stays live). Populations are treated
-// in opposite pairs (c, -c): equilibria and sources split into a part even in
-// c, shared by the pair, and an odd part that changes sign.
-// Nonlocal model: source R of the nonlocal AC equation at phi* = sum h (Eq.
-// chai_G without its weight) and the phase field phi = phi* + (1 - lam) R / 2
-// (Eq. chai2018_phi_update, sum_a G_a = (1 - lam) R). The halo fill and the
-// node update evaluate both with these same expressions, so they agree bitwise.
-template <class T>
-__device__ __forceinline__ T nl_source(const PhysT<T>& ph, T phis, T gam) {
-    return ph.mob * (gam * phis * ((T)1 - phis) - ph.w32 * (phis - (T)1) * phis * (phis - (T)0.5));
-}
-template <class T>
-__device__ __forceinline__ T nl_phi(const PhysT<T>& ph, T phis, T gam) {
-    return phis + (T)0.5 * ((T)1 - ph.lam) * nl_source(ph, phis, gam);
-}
-
-template <class PAIR, int MODEL, class T, bool COLLIDE, class GSink, class HSink>
-__device__ __forceinline__ void node_update(const PhysT<T>& ph, const T* g, const T* h, const T* phin,
-                                            const T* pu_prev, T* pu_new, NodeOut<T>& mo, const T gam,
-                                            GSink&& gsink, HSink&& hsink) {
-    using GL = typename PAIR::G;
-    using HL = typename PAIR::H;
-    constexpr bool D3 = PAIR::dim == 3;
-
-    const T phi = phin[0];
-    // isotropic stencils: grad = 3 sum w c phi(x+c), lap = 6 sum w (phi(x+c) - phi)
-    T gr[3] = {(T)0, (T)0, (T)0};
-    T lap = (T)0;
-    unroll<GL::NP>([&](auto K) {
-        constexpr int i = GL::pf(K), o = GL::opp(i);
-        const T dp = phin[i] - phin[o];
-        unroll<3>([&](auto A) {
-            constexpr int a = A;
-            if constexpr (GL::c(i, a) != 0) gr[a] += (T)(3.0 * GL::w(i) * GL::c(i, a)) * dp;
-        });
-        lap += (T)(6.0 * GL::w(i)) * ((phin[i] - phi) + (phin[o] - phi));
-    });
-
-    const T dRho = ph.dRho;
-    const T rho = ph.rhoL + phi * dRho;
-    const T irho = rcp(rho);
-    const T nu = ph.visc_mu ? (ph.muL + phi * ph.dMu) * irho : ph.nuL + phi * ph.dNu;
-    const T itau = rcp((T)3 * nu + (T)0.5);
-    const T mu_phi = ph.beta4 * phi * (phi - (T)1) * (phi - (T)0.5) - ph.kappa * lap;
-
-    // moments of g: p*, j, second moment (xx yy zz xy yz xz)
-    T ps = g[0];
-    T j[3] = {(T)0, (T)0, (T)0};
-    T m2[6] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
-    unroll<GL::NP>([&](auto K) {
-        constexpr int i = GL::pf(K), o = GL::opp(i);
-        constexpr int cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
-        const T s = g[i] + g[o], d = g[i] - g[o];
-        ps += s;
-        if constexpr (cx != 0) { j[0] += (T)cx * d; m2[0] += s; }
-        if constexpr (cy != 0) { j[1] += (T)cy * d; m2[1] += s; }
-        if constexpr (cz != 0) { j[2] += (T)cz * d; m2[2] += s; }
-        if constexpr (cx * cy != 0) m2[3] += (T)(cx * cy) * s;
-        if constexpr (cy * cz != 0) m2[4] += (T)(cy * cz) * s;
-        if constexpr (cx * cz != 0) m2[5] += (T)(cx * cz) * s;
-    });
-
-    // forces: F_s + F_b + F_p, with F_p = -(p/rho) grad rho = -c_s^2 p* dRho grad phi
-    const T inv2rho = (T)0.5 * irho;
-    const T sg = mu_phi - ps * dRho * (T)(1.0 / 3.0);
-    T F[3];
-    unroll<3>([&](auto A) {
-        constexpr int a = A;
-        F[a] = sg * gr[a] + rho * ph.body[a] + ph.force[a];
-    });
-    // strain from the non-equilibrium second moment at u* (sum c c g_eq = p*/3 I + u u)
-    T us[3];
-    unroll<3>([&](auto A) { constexpr int a = A; us[a] = j[a] + F[a] * inv2rho; });
-    const T s3 = ps * (T)(1.0 / 3.0);
-    const T sfac = (T)(-3.0) * itau;            // S = -Pi / (tau c_s^2)
-    T S[6];
-    S[0] = sfac * (m2[0] - s3 - us[0] * us[0]);
-    S[1] = sfac * (m2[1] - s3 - us[1] * us[1]);
-    S[2] = D3 ? sfac * (m2[2] - s3 - us[2] * us[2]) : (T)0;
-    S[3] = sfac * (m2[3] - us[0] * us[1]);
-    S[4] = D3 ? sfac * (m2[4] - us[1] * us[2]) : (T)0;
-    S[5] = D3 ? sfac * (m2[5] - us[0] * us[2]) : (T)0;
-    const T nr = nu * dRho;                     // F_mu = nu S . grad rho
-    F[0] += nr * (S[0] * gr[0] + S[3] * gr[1] + S[5] * gr[2]);
-    F[1] += nr * (S[3] * gr[0] + S[1] * gr[1] + S[4] * gr[2]);
-    F[2] += nr * (S[5] * gr[0] + S[4] * gr[1] + S[2] * gr[2]);
-    T u[3];
-    unroll<3>([&](auto A) { constexpr int a = A; u[a] = j[a] + F[a] * inv2rho; });
-
-    mo.phi = phi;
-    mo.rho = rho;
-    mo.p = rho * s3;
-    mo.u[0] = u[0];
-    mo.u[1] = u[1];
-    mo.u[2] = u[2];
-    if constexpr (!COLLIDE) return;
-
-    // ---- g collision (two-rate MRT, projector form)
-    const T usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    const T so = ph.s_o;
-    const T so1 = (T)1 - so;
-    const T dS = itau - so;
-    const T ffac = ((T)1 - (T)0.5 * so) * (T)3 * irho;
-    const T aeq = ps - (T)1.5 * usq;
-    // non-equilibrium second moment at the final u
-    const T pxx = m2[0] - s3 - u[0] * u[0], pyy = m2[1] - s3 - u[1] * u[1];
-    const T pzz = m2[2] - s3 - u[2] * u[2];
-    const T pxy = m2[3] - u[0] * u[1], pyz = m2[4] - u[1] * u[2], pxz = m2[5] - u[0] * u[2];
-    T A0, A1, Axy, Ayz, Axz;
-    if constexpr (D3) {
-        A0 = ((T)2 * pxx - pyy - pzz) * (T)(1.0 / 36.0);   // row 3cx^2 - c^2, norm^2 36
-        A1 = (pyy - pzz) * (T)(1.0 / 12.0);                // row cy^2 - cz^2, norm^2 12
-        Axy = pxy * (T)0.25;
-        Ayz = pyz * (T)0.25;
-        Axz = pxz * (T)0.25;
-    } else {
-        A0 = (pxx - pyy) * (T)0.25;                        // row cx^2 - cy^2, norm^2 4
-        A1 = (T)0;
-        Axy = pxy * (T)0.25;
-        Ayz = (T)0;
-        Axz = (T)0;
-    }
-    // rest population: no odd part, no stress projection
-    gsink(std::integral_constant<int, 0>{}, so1 * g[0] + so * (T)GL::w(0) * aeq);
-    unroll<GL::NP>([&](auto K) {
-        constexpr int i = GL::pf(K), o = GL::opp(i);
-        constexpr int cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
-        constexpr T w = (T)GL::w(i);
-        T cu = (T)0, cf = (T)0;
-        if constexpr (cx != 0) { cu += (T)cx * u[0]; cf += (T)cx * F[0]; }
-        if constexpr (cy != 0) { cu += (T)cy * u[1]; cf += (T)cy * F[1]; }
-        if constexpr (cz != 0) { cu += (T)cz * u[2]; cf += (T)cz * F[2]; }
-        T P = (T)0;
-        if constexpr (D3) {
-            constexpr int q0 = 3 * cx * cx - (cx * cx + cy * cy + cz * cz);
-            constexpr int q1 = cy * cy - cz * cz;
-            if constexpr (q0 != 0) P += (T)q0 * A0;
-            if constexpr (q1 != 0) P += (T)q1 * A1;
-            if constexpr (cx * cy != 0) P += (T)(cx * cy) * Axy;
-            if constexpr (cy * cz != 0) P += (T)(cy * cz) * Ayz;
-            if constexpr (cx * cz != 0) P += (T)(cx * cz) * Axz;
-        } else {
-            constexpr int q0 = cx * cx - cy * cy;
-            if constexpr (q0 != 0) P += (T)q0 * A0;
-            if constexpr (cx * cy != 0) P += (T)(cx * cy) * Axy;
-        }
-        // g_eq = E +/- O with E = w (aeq + 4.5 (c.u)^2), O = 3 w c.u; F_i = +/- w c.F ...
-        const T E = w * (aeq + (T)4.5 * cu * cu);
-        const T base = so * E - dS * P;
-        const T t = so * ((T)3 * w * cu) + ffac * w * cf;
-        gsink(std::integral_constant<int, i>{}, so1 * g[i] + base + t);
-        gsink(std::integral_constant<int, o>{}, so1 * g[o] + base - t);
-    });
-
-    // ---- h collision (BGK): h* = (1 - 1/tau_phi) h + h_eq / tau_phi + (1 - 1/(2 tau_phi)) G
-    const T itp = ph.inv_tau_phi, gfp = ph.g_fac_phi;
-    const T itp1 = (T)1 - itp;
-    // phi* = sum h, in the order of the halo fill
-    constexpr int HOFF = (MODEL != 1 && D3) ? 1 : 0;
-    T phis = (T)0;
-    unroll<HL::Q - HOFF>([&](auto J) { phis += h[J + HOFF]; });
-    // Float forms: the rounded weights do not sum to one (6 fl(1/6) = 1 + 3e-8),
-    // which would add a fixed fraction of phi to the phase-field mass every
-    // step. There the last population closes the node's exact balance instead:
-    // sum_a h*_a = phi* + (1/(2 tau_phi) + 1 - 1/(2 tau_phi)) sum_a G_a, where
-    // sum_a G_a = (1 - lam) R for the nonlocal model and 0 otherwise.
-    constexpr bool CLOSE = sizeof(T) == 4;
-    T hacc = (T)0, htarget = phis;
-    auto put = [&](auto J, T v) {
-        if constexpr (CLOSE) hacc += v;
-        hsink(J, v);
-    };
-    auto put_pair = [&](auto K, auto A, auto O, T va, T vo) {
-        put(A, va);
-        if constexpr (CLOSE && decltype(K)::value == HL::NP - 1) hsink(O, htarget - hacc);
-        else put(O, vo);
-    };
-    if constexpr (MODEL == 0) {
-        const T gg = gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2];
-        const T coef = ph.anti * phi * ((T)1 - phi) * rsqrt_(gg + ph.eps2);
-        const T e0 = phi * ((T)1 - (T)1.5 * usq);
-        if constexpr (HL::w(0) != 0.0)
-            put(std::integral_constant<int, 0>{}, itp1 * h[0] + itp * (T)HL::w(0) * e0);
-        unroll<HL::NP>([&](auto K) {
-            constexpr int al = HL::pf(K), o = HL::opp(al);
-            constexpr T w = (T)HL::w(al);
-            constexpr int ex = HL::c(al, 0), ey = HL::c(al, 1), ez = HL::c(al, 2);
-            T eu = (T)0, eg = (T)0;
-            if constexpr (ex != 0) { eu += (T)ex * u[0]; eg += (T)ex * gr[0]; }
-            if constexpr (ey != 0) { eu += (T)ey * u[1]; eg += (T)ey * gr[1]; }
-            if constexpr (ez != 0) { eu += (T)ez * u[2]; eg += (T)ez * gr[2]; }
-            const T base = itp * w * (e0 + (T)4.5 * phi * eu * eu);
-            const T t = itp * ((T)3 * w * phi * eu) + gfp * w * coef * eg;
-            put_pair(K, std::integral_constant<int, al>{}, std::integral_constant<int, o>{},
-                     itp1 * h[al] + base + t, itp1 * h[o] + base - t);
-        });
-    } else if constexpr (MODEL == 2) {
-        // Eqs. Chai_geq, Hu_G: h_eq = w phi (1 + e.u / c_s^2),
-        // G = lam w e.[(4/W) phi (1 - phi) n] + (1 - lam) w R, R at phi* = sum h
-        const T R = nl_source(ph, phis, gam);
-        htarget = phis + ((T)1 - ph.lam) * ((T)0.5 * itp + gfp) * R;
-        const T gg = gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2];
-        const T coef = ph.anti * phi * ((T)1 - phi) * rsqrt_(gg + ph.eps2);
-        const T gcon = gfp * ph.lam * coef;
-        const T giso = gfp * ((T)1 - ph.lam) * R;
-        const T e0 = itp * phi + giso;
-        if constexpr (HL::w(0) != 0.0)
-            put(std::integral_constant<int, 0>{}, itp1 * h[0] + (T)HL::w(0) * e0);
-        unroll<HL::NP>([&](auto K) {
-            constexpr int al = HL::pf(K), o = HL::opp(al);
-            constexpr T w = (T)HL::w(al);
-            constexpr int ex = HL::c(al, 0), ey = HL::c(al, 1), ez = HL::c(al, 2);
-            T eu = (T)0, eg = (T)0;
-            if constexpr (ex != 0) { eu += (T)ex * u[0]; eg += (T)ex * gr[0]; }
-            if constexpr (ey != 0) { eu += (T)ey * u[1]; eg += (T)ey * gr[1]; }
-            if constexpr (ez != 0) { eu += (T)ez * u[2]; eg += (T)ez * gr[2]; }
-            const T base = w * e0;
-            const T t = itp * ((T)3 * w * phi * eu) + gcon * w * eg;
-            put_pair(K, std::integral_constant<int, al>{}, std::integral_constant<int, o>{},
-                     itp1 * h[al] + base + t, itp1 * h[o] + base - t);
-        });
-    } else {
-        const T eta = ph.eta;
-        T pu[3], dpu[3];
-        unroll<3>([&](auto A) {
-            constexpr int a = A;
-            pu[a] = phi * u[a];
-            dpu[a] = pu[a] - pu_prev[a];
-            pu_new[a] = pu[a];
-        });
-        const T emu = eta * mu_phi;
-        put(std::integral_constant<int, 0>{}, itp1 * h[0] + itp * (phi + ((T)HL::w(0) - (T)1) * emu));
-        unroll<HL::NP>([&](auto K) {
-            constexpr int al = HL::pf(K), o = HL::opp(al);
-            constexpr T w = (T)HL::w(al);
-            constexpr int ex = HL::c(al, 0), ey = HL::c(al, 1), ez = HL::c(al, 2);
-            T ep = (T)0, ed = (T)0;
-            if constexpr (ex != 0) { ep += (T)ex * pu[0]; ed += (T)ex * dpu[0]; }
-            if constexpr (ey != 0) { ep += (T)ey * pu[1]; ed += (T)ey * dpu[1]; }
-            if constexpr (ez != 0) { ep += (T)ez * pu[2]; ed += (T)ez * dpu[2]; }
-            const T base = itp * w * emu;
-            const T t = itp * ((T)3 * w * ep) + gfp * (T)3 * w * ed;
-            put_pair(K, std::integral_constant<int, al>{}, std::integral_constant<int, o>{},
-                     itp1 * h[al] + base + t, itp1 * h[o] + base - t);
-        });
-    }
-}
-
-// ----------------------------------------------------------------------------
-// block reduction of the diagnostics (fixed order, deterministic)
-
-struct DiagAcc {
-    double v[NDIAG];
-};
-
-__device__ __forceinline__ void diag_init(DiagAcc& d) {
-    for (int k = 0; k < NDIAG; ++k) d.v[k] = 0.0;
-    d.v[3] = 1e300;    // phi_min
-    d.v[4] = -1e300;   // phi_max
-}
-
-__device__ __forceinline__ void diag_combine(double* a, const double* b) {
-    for (int k = 0; k < NDIAG; ++k) {
-        if (k == 3) a[k] = fmin(a[k], b[k]);
-        else if (k == 4 || k == 5 || k == 10) a[k] = fmax(a[k], b[k]);
-        else a[k] += b[k];
-    }
-}
-
-__device__ void block_reduce_diag(DiagAcc& d, double* out) {
-    __shared__ double red[BLOCK / 64][NDIAG];
-    for (int off = 32; off >= 1; off >>= 1) {
-        double o[NDIAG];
-        for (int k = 0; k < NDIAG; ++k) o[k] = __shfl_xor(d.v[k], off, 64);
-        diag_combine(d.v, o);
-    }
-    const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
-    if (lane == 0)
-        for (int k = 0; k < NDIAG; ++k) red[wv][k] = d.v[k];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double acc[NDIAG];
-        for (int k = 0; k < NDIAG; ++k) acc[k] = red[0][k];
-        for (int w = 1; w < BLOCK / 64; ++w) diag_combine(acc, red[w]);
-        for (int k = 0; k < NDIAG; ++k) out[k] = acc[k];
-    }
-}
-
-// ----------------------------------------------------------------------------
-// fused step kernel
-
-// Element index helpers for the plane-major layout [z][q][y][x].
-template <int Q>
-__device__ __forceinline__ size_t el(int z, int q, int inplane, int P) {
-    return ((size_t)z * Q + q) * (size_t)P + (unsigned)inplane;
-}
-
-// element inplane of population plane (z, q): a uniform plane base plus a
-// 32-bit byte offset, so loads and stores take the scalar-base addressing form
-template <int Q, class E>
-__device__ __forceinline__ E& at(E* arr, int z, int q, int P, int inplane) {
-    E* base = arr + ((size_t)z * Q + q) * (size_t)P;
-    return *(E*)((char*)base + (size_t)((unsigned)inplane * (unsigned)sizeof(E)));
-}
-template <int Q, class E>
-__device__ __forceinline__ const E& at(const E* arr, int z, int q, int P, int inplane) {
-    const E* base = arr + ((size_t)z * Q + q) * (size_t)P;
-    return *(const E*)((const char*)base + (size_t)((unsigned)inplane * (unsigned)sizeof(E)));
-}
-
-// Geometry of the column (x, y) a thread owns for the whole z march: in-plane
-// offsets of the 3 x 3 neighbourhood with the periodic wrap folded in (the
-// wall side keeps the node itself), and wall flags of the x and y neighbours.
-struct Column {
-    int off[3][3];       // [dy + 1][dx + 1] -> (y + dy) * nx + (x + dx), wrapped
-    bool wx[2], wy[2];   // the x / y neighbour at -1 / +1 lies beyond a wall
-};
-
-__device__ __forceinline__ void axis_nb(int v, int n, int bc, int* o, bool* w) {
-    const bool lo = v == 0, hi = v == n - 1;
-    o[0] = lo ? (bc == 0 ? n - 1 : 0) : v - 1;
-    o[1] = v;
-    o[2] = hi ? (bc == 0 ? 0 : n - 1) : v + 1;
-    w[0] = lo && bc != 0;
-    w[1] = hi && bc != 0;
-}
-
-// z planes of the neighbourhood of plane z (wrapped; clamped at a wall) and
-// wall flags, uniform over the workgroup
-struct ZPlanes {
-    int zk[3];
-    bool wz[2];
-};
-
-// does x + sgn c_i lie beyond a wall; which side
-template <class L, int i, int sgn>
-__device__ __forceinline__ bool beyond(const Column& cl, const ZPlanes& zp, int& side) {
-    constexpr int cx = sgn * L::c(i, 0), cy = sgn * L::c(i, 1), cz = sgn * L::c(i, 2);
-    bool w = false;
-    side = 0;
-    if constexpr (cx != 0) { const bool f = cl.wx[cx > 0]; w = w || f; side = f ? (cx > 0) : side; }
-    if constexpr (cy != 0) { const bool f = cl.wy[cy > 0]; w = w || f; side = f ? (cy > 0) : side; }
-    if constexpr (cz != 0) { const bool f = zp.wz[cz > 0]; w = w || f; side = f ? (cz > 0) : side; }
-    return w;
-}
-
-// In-plane offset of a node and of its four axis neighbours (wrapped; the
-// node itself on a wall side), with the wall flags of those neighbours.
-struct Cross {
-    int c, xm, xp, ym, yp;
-    bool wxm, wxp, wym, wyp;
-};
-
-__device__ __forceinline__ Cross make_cross(int px, int py, int nx, int ny, const int* bc) {
-    int ox[3], oy[3];
-    bool wx[2], wy[2];
-    axis_nb(px, nx, bc[0], ox, wx);
-    axis_nb(py, ny, bc[1], oy, wy);
-    Cross X;
-    X.c = py * nx + px;
-    X.xm = py * nx + ox[0];
-    X.xp = py * nx + ox[2];
-    X.ym = oy[0] * nx + px;
-    X.yp = oy[2] * nx + px;
-    X.wxm = wx[0];
-    X.wxp = wx[1];
-    X.wym = wy[0];
-    X.wyp = wy[1];
-    return X;
-}
-
-__device__ __forceinline__ ZPlanes make_zplanes(int z, int nz, int bc) {
-    ZPlanes zp;
-    int oz[3];
-    axis_nb(z, nz, bc, oz, zp.wz);
-    zp.zk[0] = oz[0];
-    zp.zk[1] = oz[1];
-    zp.zk[2] = oz[2];
-    return zp;
-}
-
-// Post-streaming phase-field population al at the node of X in plane zp.zk[1]:
-// pulled from the node x - e_al of the previous step's post-collision buffer,
-// or, if that node lies beyond a wall, the bounce-back of slot opp(al) here.
-// D3Q7 / D2Q5 velocities are axis-aligned: one component at most is nonzero.
-template <class HL, int al, int HOFF, int WALLS, class T, class HS>
-__device__ __forceinline__ T pull_h(const HS* __restrict__ H, const Cross& X, const ZPlanes& zp, int P) {
-    constexpr int ex = HL::c(al, 0), ey = HL::c(al, 1), ez = HL::c(al, 2);
-    constexpr int QS = HL::Q - HOFF;
-    const int off = ex > 0 ? X.xm : (ex < 0 ? X.xp : (ey > 0 ? X.ym : (ey < 0 ? X.yp : X.c)));
-    if constexpr (WALLS) {
-        const bool w = (ex > 0 && X.wxm) || (ex < 0 && X.wxp) || (ey > 0 && X.wym) || (ey < 0 && X.wyp) ||
-                       (ez > 0 && zp.wz[0]) || (ez < 0 && zp.wz[1]);
-        constexpr int o = HL::opp(al);
-        const size_t e = w ? el<QS>(zp.zk[1], o - HOFF, X.c, P) : el<QS>(zp.zk[1 - ez], al - HOFF, off, P);
-        return (T)H[e];
-    } else {
-        return (T)at<QS>(H, zp.zk[1 - ez], al - HOFF, P, off);
-    }
-}
-
-// WALLS = 0: every axis periodic (no bounce-back selects are compiled).
-// TS: tile shape, TX x TY nodes per workgroup: 0 = 64 x 4 with workgroups
-// ordered so each XCD sweeps a contiguous run of tiles, 1 = 128 x 2 and
-// 2 = 256 x 1 in hardware order.
-template <class PAIR, int MODEL, int PREC, int MODE, int WALLS, int TS>
-__global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
-    using GL = typename PAIR::G;
-    using HL = typename PAIR::H;
-    using T = typename Types<PREC>::T;
-    using GS = typename Types<PREC>::GS;
-    using HS = typename Types<PREC>::HS;
-    using GC = GCodec<PREC>;
-    constexpr int QG = GL::Q, QH = HL::Q;
-    constexpr bool D3 = PAIR::dim == 3;
-    constexpr int HOFF = (MODEL != 1 && D3) ? 1 : 0;   // AC / NL on D3Q7: zero-weight rest population not stored
-    constexpr int QHS = QH - HOFF;
-    constexpr int TX = TS == 0 ? 64 : (TS == 1 ? 128 : 256), TY = BLOCK / TX;
-    constexpr int PW = TX + 2, PSZ = PW * (TY + 2);
-    constexpr int NRING = 2 * PW + 2 * TY;             // halo ring of the tile
-    constexpr int NPL = D3 ? 4 : 1;
-    __shared__ T lphi[NPL * PSZ];
-
-    const int b = TS == 0 ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    const int bx = b % a.ntx, byz = b / a.ntx;
-    const int by = byz % a.nty, bz = byz / a.nty;
-    const int x0 = bx * TX, y0 = by * TY;
-    const int zs = bz * a.zb;
-    const int ze = min(a.nz, zs + a.zb);
-    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
-    const int x = x0 + lx, y = y0 + ly;
-    const bool active = x < a.nx && y < a.ny;
-    const int nx = a.nx, ny = a.ny, nz = a.nz, P = a.P;
-    const GS* __restrict__ Gin = (const GS*)a.gin;
-    GS* __restrict__ Gout = (GS*)a.gout;
-    const HS* __restrict__ Hin = (const HS*)a.hin;
-    HS* __restrict__ Hout = (HS*)a.hout;
-    T* __restrict__ PU = (T*)a.phiu;
-
-    const PhysT<T>* php;
-    if constexpr (sizeof(T) == 8) php = &a.ph;
-    else php = &a.phf;
-    const PhysT<T>& ph = *php;
-    T gam = (T)0;                    // nonlocal multiplier of this step
-    if constexpr (MODEL == 2) gam = (T)*a.gamma;
-    auto gcorr = [&](int side, int i) -> T {
-        if constexpr (sizeof(T) == 8) return a.gcorr[side][i];
-        else return a.gcorrf[side][i];
-    };
-
-    // the thread's own tile position, wrapped or clamped (inactive threads fill
-    // the halo of the domain edge with it)
-    const Cross ocr = make_cross(ghost_coord(x, nx, a.bc[0]), ghost_coord(y, ny, a.bc[1]), nx, ny, a.bc);
-    Column cl;
-    {
-        int ox[3], oy[3];
-        axis_nb(min(x, nx - 1), nx, a.bc[0], ox, cl.wx);
-        axis_nb(min(y, ny - 1), ny, a.bc[1], oy, cl.wy);
-        for (int dy = 0; dy < 3; ++dy)
-            for (int dx = 0; dx < 3; ++dx) cl.off[dy][dx] = oy[dy] * nx + ox[dx];
-    }
-    // halo ring positions this thread fills (ring index threadIdx.x + k BLOCK)
-    constexpr int NR = (NRING + BLOCK - 1) / BLOCK;
-    Cross rcr[NR];
-    int ring_lds[NR];
-    bool ring[NR];
-    for (int k = 0; k < NR; ++k) {
-        const int r = threadIdx.x + k * BLOCK;
-        ring[k] = r < NRING;
-        int hx = 0, hy = 0;
-        if (r < PW) { hx = r - 1; hy = -1; }
-        else if (r < 2 * PW) { hx = r - PW - 1; hy = TY; }
-        else if (r < 2 * PW + TY) { hx = -1; hy = r - 2 * PW; }
-        else { hx = TX; hy = r - 2 * PW - TY; }
-        if (!ring[k]) { hx = 0; hy = 0; }
-        rcr[k] = make_cross(ghost_coord(x0 + hx, nx, a.bc[0]), ghost_coord(y0 + hy, ny, a.bc[1]), nx, ny, a.bc);
-        ring_lds[k] = (hy + 1) * PW + (hx + 1);
-    }
-    const int own_lds = (ly + 1) * PW + (lx + 1);
-
-    DiagAcc acc;
-    if constexpr (MODE == MODE_DIAG) diag_init(acc);
-
-    // phi of plane zz into LDS slot; returns the thread's own h of that plane.
-    // phi = sum of the post-streaming h, pulled from the previous step's buffer.
-    T hn[QH];
-    auto fill_plane = [&](int zz, int slot) {
-        const int zu = __builtin_amdgcn_readfirstlane(zz);
-        const ZPlanes fz = make_zplanes(D3 ? ghost_coord(zu, nz, a.bc[2]) : 0, nz, a.bc[2]);
-        // every load of the plane first (ring loads unconditional: a thread with
-        // no ring position reads a valid in-tile node and discards it), then the
-        // sums, so the loads overlap instead of waiting on each other
-        T rv[NR][QHS];
-        hn[0] = (T)0;
-        unroll<QHS>([&](auto J) {
-            constexpr int al = J + HOFF;
-            hn[al] = pull_h<HL, al, HOFF, WALLS, T>(Hin, ocr, fz, P);
-        });
-        for (int k = 0; k < NR; ++k)
-            unroll<QHS>([&](auto J) {
-                constexpr int al = J + HOFF;
-                rv[k][J] = pull_h<HL, al, HOFF, WALLS, T>(Hin, rcr[k], fz, P);
-            });
-        T s = (T)0;
-        unroll<QHS>([&](auto J) {
-            constexpr int al = J + HOFF;
-            s += hn[al];
-        });
-        if constexpr (MODEL == 2) s = nl_phi(ph, s, gam);
-        lphi[slot * PSZ + own_lds] = s;
-        for (int k = 0; k < NR; ++k) {
-            T sr = (T)0;
-            unroll<QHS>([&](auto J) { sr += rv[k][J]; });
-            if constexpr (MODEL == 2) sr = nl_phi(ph, sr, gam);
-            if (ring[k]) lphi[slot * PSZ + ring_lds[k]] = sr;
-        }
-    };
-
-    // stored g that the pull of plane z reads (storage form, not decoded)
-    auto pull_g = [&](int z, GS* gr) {
-        const ZPlanes zp = make_zplanes(z, nz, a.bc[2]);
-        const int o11 = cl.off[1][1];
-        unroll<QG>([&](auto I) {
-            constexpr int i = I;
-            constexpr int o = GL::opp(i);
-            constexpr int cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
-            if constexpr (!WALLS) {
-                gr[i] = at<QG>(Gin, zp.zk[1 - cz], i, P, cl.off[1 - cy][1 - cx]);
-            } else {
-                int side;
-                // beyond a wall: the bounce-back of what left this node, slot opp(i)
-                const bool w = beyond<GL, i, -1>(cl, zp, side);
-                gr[i] = Gin[w ? el<QG>(z, o, o11, P) : el<QG>(zp.zk[1 - cz], i, cl.off[1 - cy][1 - cx], P)];
-            }
-        });
-    };
-
-    auto do_node = [&](int z, const GS* gr, const T* h, const T* pm, const T* p0, const T* pp) {
-        const ZPlanes zp = make_zplanes(z, nz, a.bc[2]);
-        const int o11 = cl.off[1][1];
-        // post-streaming g of this node (pulled from x - c_i), decoded
-        T g[QG];
-        unroll<QG>([&](auto I) {
-            constexpr int i = I;
-            g[i] = GC::template dec<GL, i, GS, T>(gr[i]);   // w_opp(i) = w_i: same codec
-            if constexpr (WALLS) {
-                int side;
-                if (beyond<GL, i, -1>(cl, zp, side)) g[i] += gcorr(side, GL::opp(i));
-            }
-        });
-        T pu_prev[3] = {(T)0, (T)0, (T)0};
-        if constexpr (MODEL == 1) {
-            unroll<3>([&](auto A) {
-                constexpr int c = A;
-                pu_prev[c] = at<3>(PU, z, c, P, o11);
-            });
-        }
-        // phi at the stencil points
-        T phin[QG];
-        unroll<QG>([&](auto I) {
-            constexpr int i = I;
-            constexpr int cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
-            const T* pl_ = cz < 0 ? pm : (cz > 0 ? pp : p0);
-            phin[i] = pl_[(ly + 1 + cy) * PW + (lx + 1 + cx)];
-        });
-        NodeOut<T> mo;
-        T pu_new[3];
-        if constexpr (MODE == MODE_STEP) {
-            // post-collision populations at the node itself, in the other buffers;
-            // streamed (non-temporal stores): no workgroup reads them this step
-            auto gsink = [&](auto I, T v) {
-                constexpr int i = I;
-                __builtin_nontemporal_store(GC::template enc<GL, i, GS, T>(v), &at<QG>(Gout, z, i, P, o11));
-            };
-            auto hsink = [&](auto J, T v) {
-                constexpr int al = J;
-                if constexpr (al >= HOFF) {
-                    if (a.write_h) __builtin_nontemporal_store((HS)v, &at<QHS>(Hout, z, al - HOFF, P, o11));
-                }
-            };
-            node_update<PAIR, MODEL, T, true>(ph, g, h, phin, pu_prev, pu_new, mo, gam, gsink, hsink);
-            if constexpr (MODEL == 1) {
-                if (a.write_h) {
-                    unroll<3>([&](auto A) {
-                        constexpr int c = A;
-                        at<3>(PU, z, c, P, o11) = pu_new[c];
-                    });
-                }
-            }
-        } else {
-            auto none = [](auto, T) {};
-            node_update<PAIR, MODEL, T, false>(ph, g, h, phin, pu_prev, pu_new, mo, gam, none, none);
-            const size_t idx = ((size_t)z * ny + y) * nx + x;    // canonical index
-            if constexpr (MODE == MODE_FIELDS) {
-                if (a.f_phi) a.f_phi[idx] = (double)mo.phi;
-                if (a.f_rho) a.f_rho[idx] = (double)mo.rho;
-                if (a.f_p) a.f_p[idx] = (double)mo.p;
-                if (a.f_u) {
-                    const size_t nn = (size_t)nx * ny * nz;
-                    a.f_u[idx] = (double)mo.u[0];
-                    a.f_u[nn + idx] = (double)mo.u[1];
-                    if constexpr (D3) a.f_u[2 * nn + idx] = (double)mo.u[2];
-                }
-            } else {
-                const double phi = (double)mo.phi;
-                const double u2 = (double)mo.u[0] * (double)mo.u[0] +
-                                  (double)mo.u[1] * (double)mo.u[1] +
-                                  (double)mo.u[2] * (double)mo.u[2];
-                acc.v[0] += phi;
-                acc.v[1] += phi > 0.5 ? 1.0 : 0.0;
-                acc.v[2] += phi;
-                acc.v[3] = fmin(acc.v[3], phi);
-                acc.v[4] = fmax(acc.v[4], phi);
-                acc.v[5] = fmax(acc.v[5], u2);
-                const bool bad = !isfinite(phi) || !isfinite(u2) || !((double)mo.rho > 0.0);
-                acc.v[10] = fmax(acc.v[10], bad ? 1.0 : 0.0);
-                if (a.has_centre) {
-                    const double co[3] = {(double)x, (double)y, (double)z};
-                    const int n[3] = {nx, ny, nz};
-                    double r2 = 0.0;
-                    for (int ax = 0; ax < PAIR::dim; ++ax) {
-                        double d = co[ax] - a.centre[ax];
-                        if (a.bc[ax] == 0) d -= n[ax] * rint(d / n[ax]);
-                        r2 += d * d;
-                    }
-                    const double r = sqrt(r2);
-                    if (r < a.r_in) { acc.v[6] += (double)mo.p; acc.v[7] += 1.0; }
-                    if (r > a.r_out) { acc.v[8] += (double)mo.p; acc.v[9] += 1.0; }
-                }
-            }
-        }
-    };
-
-    T hc[QH];
-    GS gr[QG];
-    if constexpr (D3) {
-        // ring of 4 phi planes: plane zz lives in slot (zz - zs + 1) & 3. While a
-        // wave fills plane z + 2, the slowest wave may still read planes z - 1 ..
-        // z + 1, never slot (z + 2) & 3, so one barrier per plane suffices.
-        fill_plane(zs - 1, 0);
-        fill_plane(zs, 1);
-        unroll<QH>([&](auto J) { constexpr int al = J; hc[al] = hn[al]; });
-        for (int zl = zs; zl < ze; ++zl) {
-            // the plane index is uniform; readfirstlane keeps the compiler from
-            // treating it as per-lane after the divergent node branch (which
-            // would move all plane and address arithmetic to 64-bit VALU)
-            const int z = __builtin_amdgcn_readfirstlane(zl);
-            const int r = z - zs;
-            fill_plane(z + 1, (r + 2) & 3);
-            __syncthreads();
-            if (active) {
-                pull_g(z, gr);
-                do_node(z, gr, hc, lphi + (r & 3) * PSZ, lphi + ((r + 1) & 3) * PSZ,
-                        lphi + ((r + 2) & 3) * PSZ);
-            }
-            unroll<QH>([&](auto J) { constexpr int al = J; hc[al] = hn[al]; });
-        }
-    } else {
-        fill_plane(0, 0);
-        __syncthreads();
-        if (active) {
-            pull_g(0, gr);
-            do_node(0, gr, hn, lphi, lphi, lphi);
-        }
-    }
-    if constexpr (MODE == MODE_DIAG) {
-        __syncthreads();
-        block_reduce_diag(acc, a.partials + (size_t)blockIdx.x * NDIAG);
-    }
+hipError_t launch_step(int lattice, int model, int precision, int mode, const KArgs& a, hipStream_t s) {
+    if (lattice == 0)
+        return model == 2 ? launch_step_p0_m2(precision, mode, a, s)
+             : model == 1 ? launch_step_p0_m1(precision, mode, a, s)
+                          : launch_step_p0_m0(precision, mode, a, s);
+    return model == 2 ? launch_step_p1_m2(precision, mode, a, s)
+         : model == 1 ? launch_step_p1_m1(precision, mode, a, s)
+                      : launch_step_p1_m0(precision, mode, a, s);
 }
 
 // final reduction over the per-block partials, one workgroup, fixed order
@@ -1038,22 +236,25 @@ __global__ __launch_bounds__(256) void k_gamma_part(const GammaArgs a) {
     constexpr int HOFF = PAIR::dim == 3 ? 1 : 0;
     constexpr int QHS = HL::Q - HOFF;
     __shared__ double red[2][256 / 64];
-    const long long nn = (long long)a.nx * a.ny * a.nz;
-    const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
+    // workgroup (bx, bz): 256 consecutive in-plane nodes over GAMMA_ZB planes
+    const int ip = blockIdx.x * 256 + threadIdx.x;
+    const int z0 = blockIdx.y * GAMMA_ZB, z1 = min(a.nz, z0 + GAMMA_ZB);
     double num = 0.0, den = 0.0;
-    if (n < nn) {
-        const int x = (int)(n % a.nx), y = (int)((n / a.nx) % a.ny), z = (int)(n / ((long long)a.nx * a.ny));
+    if (ip < a.nx * a.ny) {
+        const int x = ip % a.nx, y = ip / a.nx;
         const HS* H = (const HS*)a.h;
-        T s = (T)0;                  // same summation order as the step's halo fill
-        unroll<QHS>([&](auto J) {
-            constexpr int al = J + HOFF;
-            bool w;
-            int side;
-            s += (T)H[pull_source<HL, al, QHS, HOFF>(a.nx, a.ny, a.nz, a.bc, x, y, z, a.P, w, side)];
-        });
-        const double phi = (double)s;
-        num = a.w32 * (phi - 1.0) * phi * (phi - 0.5);
-        den = (1.0 - phi) * phi;
+        for (int z = z0; z < z1; ++z) {
+            T s = (T)0;              // same summation order as the step's halo fill
+            unroll<QHS>([&](auto J) {
+                constexpr int al = J + HOFF;
+                bool w;
+                int side;
+                s += (T)H[pull_source<HL, al, QHS, HOFF>(a.nx, a.ny, a.nz, a.bc, x, y, z, a.P, w, side)];
+            });
+            const double phi = (double)s;
+            num += a.w32 * (phi - 1.0) * phi * (phi - 0.5);
+            den += (1.0 - phi) * phi;
+        }
     }
     for (int off = 32; off >= 1; off >>= 1) {
         num += __shfl_xor(num, off, 64);
@@ -1071,8 +272,9 @@ __global__ __launch_bounds__(256) void k_gamma_part(const GammaArgs a) {
             sn += red[0][k];
             sd += red[1][k];
         }
-        a.partials[2 * (size_t)blockIdx.x] = sn;
-        a.partials[2 * (size_t)blockIdx.x + 1] = sd;
+        const size_t b = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+        a.partials[2 * b] = sn;
+        a.partials[2 * b + 1] = sd;
     }
 }
 
@@ -1106,56 +308,6 @@ __global__ __launch_bounds__(256) void k_gamma_final(const double* __restrict__ 
 
 // ----------------------------------------------------------------------------
 // dispatch
-
-template <class PAIR, int MODEL, int PREC>
-static hipError_t step_mode(int mode, const KArgs& a, hipStream_t s) {
-    const dim3 grid((unsigned)(a.ntx * a.nty * a.ntz)), block(BLOCK);
-    const bool walls = a.wall_axis >= 0;
-    switch (mode) {
-        case MODE_STEP:
-            if constexpr (PAIR::dim == 3) {
-                if (a.tile == 1) {
-                    if (walls) hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_STEP, 1, 1>), grid, block, 0, s, a);
-                    else hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_STEP, 0, 1>), grid, block, 0, s, a);
-                    break;
-                }
-                if (a.tile == 2) {
-                    if (walls) hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_STEP, 1, 2>), grid, block, 0, s, a);
-                    else hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_STEP, 0, 2>), grid, block, 0, s, a);
-                    break;
-                }
-            }
-            if (walls) hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_STEP, 1, 0>), grid, block, 0, s, a);
-            else hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_STEP, 0, 0>), grid, block, 0, s, a);
-            break;
-        case MODE_FIELDS:
-            hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_FIELDS, 1, 0>), grid, block, 0, s, a);
-            break;
-        default:
-            hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_DIAG, 1, 0>), grid, block, 0, s, a);
-    }
-    return hipGetLastError();
-}
-
-template <class PAIR, int MODEL>
-static hipError_t step_prec(int prec, int mode, const KArgs& a, hipStream_t s) {
-    switch (prec) {
-        case 0: return step_mode<PAIR, MODEL, 0>(mode, a, s);
-        case 1: return step_mode<PAIR, MODEL, 1>(mode, a, s);
-        case 2: return step_mode<PAIR, MODEL, 2>(mode, a, s);
-        default: return step_mode<PAIR, MODEL, 3>(mode, a, s);
-    }
-}
-
-hipError_t launch_step(int lattice, int model, int precision, int mode, const KArgs& a, hipStream_t s) {
-    if (lattice == 0)
-        return model == 2 ? step_prec<Pair2D, 2>(precision, mode, a, s)
-             : model == 1 ? step_prec<Pair2D, 1>(precision, mode, a, s)
-                          : step_prec<Pair2D, 0>(precision, mode, a, s);
-    return model == 2 ? step_prec<Pair3D, 2>(precision, mode, a, s)
-         : model == 1 ? step_prec<Pair3D, 1>(precision, mode, a, s)
-                      : step_prec<Pair3D, 0>(precision, mode, a, s);
-}
 
 #define PFLBM_NODE_DISPATCH(KERNEL, ARGS, NN)                                               \
     do {                                                                                     \
@@ -1201,9 +353,9 @@ hipError_t launch_set(int lattice, int model, int precision, const IOArgs& a, hi
 }
 
 hipError_t launch_gamma(int lattice, int precision, const GammaArgs& a, hipStream_t s) {
-    const long long nn = (long long)a.nx * a.ny * a.nz;
-    const long long nb = (nn + 255) / 256;
-    const dim3 grid((unsigned)nb), block(256);
+    const int nbx = (a.nx * a.ny + 255) / 256, nbz = (a.nz + GAMMA_ZB - 1) / GAMMA_ZB;
+    const long long nb = (long long)nbx * nbz;
+    const dim3 grid((unsigned)nbx, (unsigned)nbz), block(256);
     auto go = [&](auto pair) {
         using P_ = decltype(pair);
         switch (precision) {

@@ -129,7 +129,10 @@ Layout make_layout(const pflbm_params& p) {
     L.off_part = off;
     off = align_up(off + (size_t)L.nblocks * NDIAG * sizeof(double), ALIGN);
     L.off_gpart = off;   // nonlocal multiplier: per-256-node partial sums
-    if (p.model == PFLBM_NL) off = align_up(off + (size_t)((L.nodes + 255) / 256) * 2 * sizeof(double), ALIGN);
+    if (p.model == PFLBM_NL) {
+        const size_t nbg = (size_t)((p.nx * p.ny + 255) / 256) * ((p.nz + GAMMA_ZB - 1) / GAMMA_ZB);
+        off = align_up(off + nbg * 2 * sizeof(double), ALIGN);
+    }
     L.off_res = off;
     off = align_up(off + 64 * sizeof(double), ALIGN);
     L.total = off;

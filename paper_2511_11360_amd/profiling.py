@@ -16,8 +16,8 @@ import os
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = [os.path.join(HERE, "csrc", "kernels.hip"), os.path.join(HERE, "csrc", "lattice.h"),
-                  os.path.join(HERE, "csrc", "internal.h")]
+KERNEL_SOURCES = [os.path.join(HERE, "csrc", f) for f in
+                  ("step.h", "step_inst.hip", "kernels.hip", "lattice.h", "internal.h")]
 COPY_BYTES = 1 << 30
 
 
