@@ -2,7 +2,8 @@
 
 Sec. III (2-D tests) uses D2Q9; Sec. IV uses a D3Q7 phase-field lattice with
 c_s^2 = 1/3 for both lattices. The hydrodynamic 3-D lattice here is D3Q19 and
-the 2-D phase-field lattice D2Q5 (readings listed in the design notes).
+the 2-D phase-field lattice D2Q5 (readings listed in the design notes); the
+paper's own 3-D hydrodynamic lattice, D3Q27 (Sec. IV), is the alternative.
 
 Canonical population order (shared with the library's canonical I/O, since it
 is an interface format):
@@ -13,11 +14,14 @@ is an interface format):
          vectors in opposite pairs (+x+y,-x-y), (+x-y,-x+y), (+x+z,-x-z),
          (+x-z,-x+z), (+y+z,-y-z), (+y-z,-y+z)
   D3Q7 : the first seven D3Q19 vectors
+  D3Q27: the nineteen D3Q19 vectors, then the eight corners in opposite pairs
+         (+x+y+z,-x-y-z), (+x+y-z,-x-y+z), (+x-y+z,-x+y-z), (-x+y+z,+x-y-z)
 
 Weights. D2Q9: 4/9, 1/9, 1/36. D2Q5 with c_s^2 = 1/3: 1/3, 1/6.
-D3Q19: 1/3, 1/18, 1/36. D3Q7 with c_s^2 = 1/3 (Sec. IV states c_s^2 = 1/3 for
-both lattices): the second-moment condition sum w e e = c_s^2 I forces 1/6 on
-the six faces and therefore 0 on the rest vector.
+D3Q19: 1/3, 1/18, 1/36. D3Q27: 8/27, 2/27, 1/54, 1/216. D3Q7 with
+c_s^2 = 1/3 (Sec. IV states c_s^2 = 1/3 for both lattices): the second-moment
+condition sum w e e = c_s^2 I forces 1/6 on the six faces and therefore 0 on
+the rest vector.
 """
 from dataclasses import dataclass
 from fractions import Fraction
@@ -78,8 +82,15 @@ D3Q7 = Lattice(
               [0, 0, 1], [0, 0, -1]]),
     (_F(0),) + (_F(1, 6),) * 6)
 
+D3Q27 = Lattice(
+    "D3Q27", 3,
+    np.concatenate([D3Q19.c, np.array([[1, 1, 1], [-1, -1, -1], [1, 1, -1], [-1, -1, 1],
+                                       [1, -1, 1], [-1, 1, -1], [-1, 1, 1], [1, -1, -1]])]),
+    (_F(8, 27),) + (_F(2, 27),) * 6 + (_F(1, 54),) * 12 + (_F(1, 216),) * 8)
+
 # lattice pair id -> (hydrodynamic lattice of g, phase-field lattice of h)
 PAIRS = {
     "D2Q9_D2Q5": (D2Q9, D2Q5),
     "D3Q19_D3Q7": (D3Q19, D3Q7),
+    "D3Q27_D3Q7": (D3Q27, D3Q7),
 }

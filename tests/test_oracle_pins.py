@@ -18,7 +18,7 @@ from oracle import mrt
 from oracle import poiseuille as pz
 from paper_2511_11360_amd import workloads as wl
 
-ALL = [L.D2Q9, L.D2Q5, L.D3Q19, L.D3Q7]
+ALL = [L.D2Q9, L.D2Q5, L.D3Q19, L.D3Q7, L.D3Q27]
 
 
 # ---------------------------------------------------------------- lattices
@@ -36,7 +36,7 @@ def test_lattice_moments_exact(lat):
             assert s == exp, (lat.name, a, b, s)
 
 
-@pytest.mark.parametrize("lat", [L.D2Q9, L.D3Q19], ids=lambda l: l.name)
+@pytest.mark.parametrize("lat", [L.D2Q9, L.D3Q19, L.D3Q27], ids=lambda l: l.name)
 def test_fourth_order_isotropy(lat):
     """sum w c_a c_b c_c c_d = c_s^4 (d_ab d_cd + d_ac d_bd + d_ad d_bc) on the
     hydrodynamic lattices (needed for the u^2 terms of Eq. fakhari_feq)."""
@@ -58,7 +58,7 @@ def test_opposites(lat):
 
 
 # ---------------------------------------------------------------- MRT basis
-@pytest.mark.parametrize("lat", [L.D2Q9, L.D3Q19], ids=lambda l: l.name)
+@pytest.mark.parametrize("lat", [L.D2Q9, L.D3Q19, L.D3Q27], ids=lambda l: l.name)
 def test_mrt_basis_orthogonal_and_stress_rows(lat):
     """The moment rows are mutually orthogonal and the stress rows span the
     traceless symmetric quadratic forms of c (dimension 2 in 2-D, 5 in 3-D)."""
@@ -95,7 +95,7 @@ def _random_node_state(p, seed, amp=0.02):
     return st
 
 
-@pytest.mark.parametrize("lat", ["D2Q9_D2Q5", "D3Q19_D3Q7"])
+@pytest.mark.parametrize("lat", ["D2Q9_D2Q5", "D3Q19_D3Q7", "D3Q27_D3Q7"])
 def test_mrt_uniform_rates_is_bgk(lat):
     """With every moment relaxed at 1/tau the MRT operator is the BGK update of
     Eq. fakhari_f_simplified: g - (g - g_eq)/tau + (1 - 1/(2 tau)) F_i."""
@@ -114,7 +114,7 @@ def test_mrt_uniform_rates_is_bgk(lat):
     assert np.max(np.abs(mrt_post - bgk)) < 1e-15
 
 
-@pytest.mark.parametrize("lat", ["D2Q9_D2Q5", "D3Q19_D3Q7"])
+@pytest.mark.parametrize("lat", ["D2Q9_D2Q5", "D3Q19_D3Q7", "D3Q27_D3Q7"])
 def test_mrt_conserves_mass_and_adds_force_momentum(lat):
     """The collision leaves p* = sum g unchanged and raises sum c g by F/rho
     exactly, whatever the non-stress rate (conserved-moment identities)."""
@@ -140,7 +140,7 @@ def test_stencils_exact_on_polynomials():
     and lap of a quadratic exactly (second-order schemes); checked on interior
     nodes away from the periodic seam, 2-D and 3-D."""
     rng = np.random.default_rng(3)
-    for lat, shape in (("D2Q9_D2Q5", (1, 9, 11)), ("D3Q19_D3Q7", (7, 8, 9))):
+    for lat, shape in (("D2Q9_D2Q5", (1, 9, 11)), ("D3Q19_D3Q7", (7, 8, 9)), ("D3Q27_D3Q7", (7, 8, 9))):
         nz, ny, nx = shape
         p = om.Params(lattice=lat, nx=nx, ny=ny, nz=nz)
         d = p.dim
@@ -174,7 +174,7 @@ def test_wall_ghost_is_mirror():
 
 
 # ---------------------------------------------------------------- equilibria
-@pytest.mark.parametrize("lat", ["D2Q9_D2Q5", "D3Q19_D3Q7"])
+@pytest.mark.parametrize("lat", ["D2Q9_D2Q5", "D3Q19_D3Q7", "D3Q27_D3Q7"])
 def test_equilibrium_and_source_moments(lat):
     """Moments fixed by construction (Eqs. fakhari_geq, fakhari_feq,
     fakhari_G_modified, fakhari_F, liang2_geq):
@@ -301,7 +301,7 @@ def test_phase_conservation_walls_and_gravity():
 
 def test_fixed_point_uniform_phase_at_rest():
     """Uniform phi, u = 0, p = 0 is a fixed point (no gradient, no force)."""
-    for lat, shape in (("D2Q9_D2Q5", (1, 6, 7)), ("D3Q19_D3Q7", (4, 5, 6))):
+    for lat, shape in (("D2Q9_D2Q5", (1, 6, 7)), ("D3Q19_D3Q7", (4, 5, 6)), ("D3Q27_D3Q7", (4, 5, 6))):
         for model in ("AC", "CH"):
             p = om.Params(lattice=lat, model=model, nz=shape[0], ny=shape[1], nx=shape[2])
             st = om.init(p, np.full(shape, 0.8))
@@ -365,6 +365,35 @@ def test_shear_wave_viscosity():
     _, uu, _, _ = om.fields(p, st)
     amp = np.sum(uu[0][0, :, 0] * np.sin(k * np.arange(L_))) / (L_ / 2)
     rate = -np.log(amp / 1e-3) / T
+    assert abs(rate / (nu * k * k) - 1) < 0.01
+
+
+@pytest.mark.parametrize("lat", ["D3Q19_D3Q7", "D3Q27_D3Q7"])
+@pytest.mark.parametrize("axes", [(0, 1), (1, 2), (2, 0)])
+def test_shear_wave_viscosity_3d_two_rates(lat, axes):
+    """3-D shear wave u_a = U sin(k x_b) with the non-stress moments at
+    s_o = 1 far from 1/tau = 1.61: the decay rate is still nu k^2,
+    nu = c_s^2 (tau - 1/2), so the stress rows (including the off-diagonal one
+    of this orientation) are the ones relaxed at 1/tau (relaxed at s_o the
+    rate would be four times larger)."""
+    a, b = axes
+    L_ = 32
+    nu = 0.04
+    shape = [4, 4, 4]
+    shape[b] = L_
+    p = om.Params(lattice=lat, nx=shape[0], ny=shape[1], nz=shape[2], nu_H=nu, nu_L=nu, s_other=1.0)
+    k = 2 * np.pi / L_
+    x = np.arange(L_)
+    prof = np.sin(k * x)
+    sh = [1, 1, 1]
+    sh[2 - b] = L_
+    u = np.zeros((3,) + p.shape)
+    u[a] = 1e-3 * prof.reshape(sh) * np.ones(p.shape)
+    st = om.run(p, om.init(p, np.full(p.shape, 1.0), u), 300)
+    uu = om.fields(p, st)[1]
+    line = np.moveaxis(uu[a], 2 - b, 0).reshape(L_, -1)[:, 0]
+    amp = np.sum(line * prof) / (L_ / 2)
+    rate = -np.log(amp / 1e-3) / 300
     assert abs(rate / (nu * k * k) - 1) < 0.01
 
 
