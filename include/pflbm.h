@@ -42,6 +42,9 @@
  *  D3Q19: 0 rest, 1 +x, 2 -x, 3 +y, 4 -y, 5 +z, 6 -z, 7 (+x+y), 8 (-x-y),
  *         9 (+x-y), 10 (-x+y), 11 (+x+z), 12 (-x-z), 13 (+x-z), 14 (-x+z),
  *         15 (+y+z), 16 (-y-z), 17 (+y-z), 18 (-y+z)
+ *  D3Q27: the nineteen D3Q19 vectors, then the corners 19 (+x+y+z), 20 (-x-y-z),
+ *         21 (+x+y-z), 22 (-x-y+z), 23 (+x-y+z), 24 (-x+y-z), 25 (-x+y+z),
+ *         26 (+x-y-z); weights 8/27, 2/27, 1/54, 1/216
  *  D3Q7 : the first seven D3Q19 vectors; with c_s^2 = 1/3 (Sec. IV) the rest
  *         weight is 0 and the face weights 1/6, so for the AC model the rest
  *         population of h is identically zero and is not stored.
@@ -66,6 +69,7 @@ extern "C" {
 /* lattice pair: hydrodynamic g + phase-field h */
 #define PFLBM_D2Q9_D2Q5   0
 #define PFLBM_D3Q19_D3Q7  1
+#define PFLBM_D3Q27_D3Q7  2   /* the paper's 3-D hydrodynamic lattice (Sec. IV) */
 
 /* phase-field model */
 #define PFLBM_AC 0   /* conservative Allen-Cahn, Eqs. fakhari_geq, fakhari_G_modified */
@@ -99,7 +103,7 @@ extern "C" {
 #define PFLBM_VISC_LINEAR_NU 1   /* Eq. fakhari_mu_update: nu linear in phi */
 
 typedef struct pflbm_params {
-    int lattice;          /* PFLBM_D2Q9_D2Q5 or PFLBM_D3Q19_D3Q7 */
+    int lattice;          /* PFLBM_D2Q9_D2Q5, PFLBM_D3Q19_D3Q7 or PFLBM_D3Q27_D3Q7 */
     int model;            /* PFLBM_AC, PFLBM_CH or PFLBM_NL */
     int precision;        /* PFLBM_FP64 ... PFLBM_MIXED_BF16 */
     int nx, ny, nz;       /* nodes per axis, each >= 1; nz == 1 for 2-D */

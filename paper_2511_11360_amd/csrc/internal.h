@@ -13,7 +13,7 @@ constexpr int TILE_NX[3] = {64, 128, 256};
 constexpr int TILE_NY[3] = {4, 2, 1};
 constexpr int NDIAG = 12;       // per-block partial diagnostics (see kernels.hip)
 constexpr int GAMMA_ZB = 16;    // z planes per workgroup of the nonlocal multiplier sums
-constexpr int MAXQ = 19;
+constexpr int MAXQ = 27;
 
 enum Mode { MODE_STEP = 0, MODE_FIELDS = 1, MODE_DIAG = 2 };
 
@@ -171,6 +171,9 @@ hipError_t launch_step_p0_m2(int precision, int mode, const KArgs& a, hipStream_
 hipError_t launch_step_p1_m0(int precision, int mode, const KArgs& a, hipStream_t s);
 hipError_t launch_step_p1_m1(int precision, int mode, const KArgs& a, hipStream_t s);
 hipError_t launch_step_p1_m2(int precision, int mode, const KArgs& a, hipStream_t s);
+hipError_t launch_step_p2_m0(int precision, int mode, const KArgs& a, hipStream_t s);
+hipError_t launch_step_p2_m1(int precision, int mode, const KArgs& a, hipStream_t s);
+hipError_t launch_step_p2_m2(int precision, int mode, const KArgs& a, hipStream_t s);
 hipError_t launch_init(int lattice, int model, int precision, const InitArgs& a, hipStream_t s);
 hipError_t launch_get(int lattice, int model, int precision, const IOArgs& a, hipStream_t s);
 hipError_t launch_set(int lattice, int model, int precision, const IOArgs& a, hipStream_t s);

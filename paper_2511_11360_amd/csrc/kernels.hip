@@ -11,9 +11,13 @@ hipError_t launch_step(int lattice, int model, int precision, int mode, const KA
         return model == 2 ? launch_step_p0_m2(precision, mode, a, s)
              : model == 1 ? launch_step_p0_m1(precision, mode, a, s)
                           : launch_step_p0_m0(precision, mode, a, s);
-    return model == 2 ? launch_step_p1_m2(precision, mode, a, s)
-         : model == 1 ? launch_step_p1_m1(precision, mode, a, s)
-                      : launch_step_p1_m0(precision, mode, a, s);
+    if (lattice == 1)
+        return model == 2 ? launch_step_p1_m2(precision, mode, a, s)
+             : model == 1 ? launch_step_p1_m1(precision, mode, a, s)
+                          : launch_step_p1_m0(precision, mode, a, s);
+    return model == 2 ? launch_step_p2_m2(precision, mode, a, s)
+         : model == 1 ? launch_step_p2_m1(precision, mode, a, s)
+                      : launch_step_p2_m0(precision, mode, a, s);
 }
 
 // final reduction over the per-block partials, one workgroup, fixed order
@@ -331,7 +335,8 @@ __global__ __launch_bounds__(256) void k_gamma_final(const double* __restrict__ 
             else prec(pair, std::integral_constant<int, 0>{});                               \
         };                                                                                   \
         if (lattice == 0) mdl(Pair2D{});                                                     \
-        else mdl(Pair3D{});                                                                  \
+        else if (lattice == 1) mdl(Pair3D{});                                                \
+        else mdl(Pair3D27{});                                                                \
     } while (0)
 
 hipError_t launch_init(int lattice, int model, int precision, const InitArgs& a, hipStream_t s) {
@@ -366,7 +371,8 @@ hipError_t launch_gamma(int lattice, int precision, const GammaArgs& a, hipStrea
         }
     };
     if (lattice == 0) go(Pair2D{});
-    else go(Pair3D{});
+    else if (lattice == 1) go(Pair3D{});
+    else go(Pair3D27{});
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_gamma_final, dim3(1), dim3(256), 0, s, (const double*)a.partials, nb, a.gamma);

@@ -1,8 +1,9 @@
 // Velocity sets of the GPU path (its own tables, compile-time only).
 //
 // c_s^2 = 1/3 on every lattice (Sec. IV of the paper). D2Q9 for the 2-D
-// hydrodynamics (Sec. III), D3Q19 for the 3-D hydrodynamics, D2Q5 and D3Q7
-// for the phase field; with c_s^2 = 1/3 the D3Q7 rest weight is 0.
+// hydrodynamics (Sec. III), D3Q19 or D3Q27 (the paper's own 3-D lattice) for
+// the 3-D hydrodynamics, D2Q5 and D3Q7 for the phase field; with c_s^2 = 1/3
+// the D3Q7 rest weight is 0.
 // The population order is the canonical order of the C ABI (pflbm.h).
 #pragma once
 
@@ -73,6 +74,59 @@ struct D3Q19 {
     __host__ __device__ static constexpr int pf(int k) { return 2 * k + 1; }
 };
 
+struct D3Q27 {
+    static constexpr int Q = 27;
+    __host__ __device__ static constexpr int c(int i, int a) {
+        constexpr int t[8][3] = {{1, 1, 1}, {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1},
+                                 {1, -1, 1}, {-1, 1, -1}, {-1, 1, 1}, {1, -1, -1}};
+        return i < 19 ? D3Q19::c(i, a) : t[i - 19][a];
+    }
+    __host__ __device__ static constexpr double w(int i) {
+        return i == 0 ? 8.0 / 27.0 : (i < 7 ? 2.0 / 27.0 : (i < 19 ? 1.0 / 54.0 : 1.0 / 216.0));
+    }
+    __host__ __device__ static constexpr int opp(int i) {
+        return i == 0 ? 0 : (i % 2 == 1 ? i + 1 : i - 1);
+    }
+    static constexpr int NP = 13;
+    __host__ __device__ static constexpr int pf(int k) { return 2 * k + 1; }
+};
+
+// Squared norms (sum over the velocities) of the stress rows of the moment
+// basis: 3 c_x^2 - c^2 and c_y^2 - c_z^2 in 3-D, c_x^2 - c_y^2 in 2-D, and
+// c_x c_y (the same for the other off-diagonal rows by symmetry).
+template <class L, int DIM>
+__host__ __device__ constexpr double stress_norm_diag0() {
+    double s = 0.0;
+    for (int i = 0; i < L::Q; ++i) {
+        const int x2 = L::c(i, 0) * L::c(i, 0), y2 = L::c(i, 1) * L::c(i, 1), z2 = L::c(i, 2) * L::c(i, 2);
+        const int v = DIM == 2 ? x2 - y2 : 3 * x2 - (x2 + y2 + z2);
+        s += (double)(v * v);
+    }
+    return s;
+}
+template <class L>
+__host__ __device__ constexpr double stress_norm_diag1() {
+    double s = 0.0;
+    for (int i = 0; i < L::Q; ++i) {
+        const int v = L::c(i, 1) * L::c(i, 1) - L::c(i, 2) * L::c(i, 2);
+        s += (double)(v * v);
+    }
+    return s;
+}
+template <class L>
+__host__ __device__ constexpr double stress_norm_off() {
+    double s = 0.0;
+    for (int i = 0; i < L::Q; ++i) {
+        const int v = L::c(i, 0) * L::c(i, 1);
+        s += (double)(v * v);
+    }
+    return s;
+}
+static_assert(stress_norm_diag0<D3Q19, 3>() == 36.0 && stress_norm_diag1<D3Q19>() == 12.0 &&
+              stress_norm_off<D3Q19>() == 4.0, "D3Q19 stress norms");
+static_assert(stress_norm_off<D3Q27>() == 12.0, "D3Q27 stress norm");
+static_assert(stress_norm_diag0<D2Q9, 2>() == 4.0 && stress_norm_off<D2Q9>() == 4.0, "D2Q9 stress norms");
+
 struct D3Q7 {
     static constexpr int Q = 7;
     __host__ __device__ static constexpr int c(int i, int a) { return D3Q19::c(i, a); }
@@ -90,6 +144,11 @@ struct Pair2D {
 };
 struct Pair3D {
     using G = D3Q19;
+    using H = D3Q7;
+    static constexpr int dim = 3;
+};
+struct Pair3D27 {
+    using G = D3Q27;
     using H = D3Q7;
     static constexpr int dim = 3;
 };

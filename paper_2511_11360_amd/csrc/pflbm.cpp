@@ -39,7 +39,8 @@ bool finite(double v) { return std::isfinite(v); }
 
 // validate; returns an error message or empty string
 std::string validate(const pflbm_params& p) {
-    if (p.lattice != PFLBM_D2Q9_D2Q5 && p.lattice != PFLBM_D3Q19_D3Q7) return "lattice must be PFLBM_D2Q9_D2Q5 or PFLBM_D3Q19_D3Q7";
+    if (p.lattice != PFLBM_D2Q9_D2Q5 && p.lattice != PFLBM_D3Q19_D3Q7 && p.lattice != PFLBM_D3Q27_D3Q7)
+        return "lattice must be PFLBM_D2Q9_D2Q5, PFLBM_D3Q19_D3Q7 or PFLBM_D3Q27_D3Q7";
     if (p.model != PFLBM_AC && p.model != PFLBM_CH && p.model != PFLBM_NL)
         return "model must be PFLBM_AC, PFLBM_CH or PFLBM_NL";
     if (p.precision < PFLBM_FP64 || p.precision > PFLBM_MIXED_BF16) return "unknown precision";
@@ -82,9 +83,9 @@ std::string validate(const pflbm_params& p) {
 
 Layout make_layout(const pflbm_params& p) {
     Layout L;
-    const bool d3 = p.lattice == PFLBM_D3Q19_D3Q7;
+    const bool d3 = p.lattice != PFLBM_D2Q9_D2Q5;
     L.dim = d3 ? 3 : 2;
-    L.Qg = d3 ? 19 : 9;
+    L.Qg = p.lattice == PFLBM_D3Q27_D3Q7 ? 27 : (d3 ? 19 : 9);
     L.Qh = d3 ? 7 : 5;
     L.Qhs = (d3 && p.model != PFLBM_CH) ? 6 : L.Qh;   // AC / NL on D3Q7: rest population is zero
     L.sT = p.precision == PFLBM_FP64 ? 8 : 4;
@@ -312,7 +313,8 @@ int pflbm_create(const pflbm_params* params, void* hip_stream, void* dev_state, 
     for (int a = 0; a < 3; ++a)
         if (p.bc[a] == PFLBM_WALL) h->wall_axis = a;
     if (p.lattice == PFLBM_D2Q9_D2Q5) wall_terms<D2Q9>(p, h->gcorr);
-    else wall_terms<D3Q19>(p, h->gcorr);
+    else if (p.lattice == PFLBM_D3Q19_D3Q7) wall_terms<D3Q19>(p, h->gcorr);
+    else wall_terms<D3Q27>(p, h->gcorr);
     Phys& ph = h->ph;
     ph.rhoL = p.rho_L;
     ph.dRho = p.rho_H - p.rho_L;
@@ -548,6 +550,7 @@ int pflbm_adjoint_step(pflbm_t* h, const double* fwd_g, const double* fwd_h, con
     int st = guard(h);
     if (st) return st;
     if (h->p.model != PFLBM_AC) return fail(h, PFLBM_EUNSUPPORTED, "adjoint implemented for the AC model only");
+    if (h->p.lattice == PFLBM_D3Q27_D3Q7) return fail(h, PFLBM_EUNSUPPORTED, "adjoint implemented for D2Q9 and D3Q19 only");
     if (h->p.freeze_phi) return fail(h, PFLBM_EUNSUPPORTED, "adjoint of a frozen phase field is not implemented");
     if (!fwd_g || !fwd_h || !lam_g || !lam_h || !lam_g_out || !lam_h_out || !work)
         return fail(h, PFLBM_EINVAL, "null pointer");
@@ -582,6 +585,7 @@ int pflbm_adjoint_init(pflbm_t* h, const double* phi0, const double* u0, const d
     int st = guard(h);
     if (st) return st;
     if (h->p.model != PFLBM_AC) return fail(h, PFLBM_EUNSUPPORTED, "adjoint implemented for the AC model only");
+    if (h->p.lattice == PFLBM_D3Q27_D3Q7) return fail(h, PFLBM_EUNSUPPORTED, "adjoint implemented for D2Q9 and D3Q19 only");
     if (!phi0 || !lam_g || !lam_h || !dphi0) return fail(h, PFLBM_EINVAL, "null pointer");
     AdjInitArgs a;
     std::memset(&a, 0, sizeof(a));

@@ -266,15 +266,17 @@ __device__ __forceinline__ void node_update(const PhysT<T>& ph, const T* g, cons
     const T pxy = m2[3] - u[0] * u[1], pyz = m2[4] - u[1] * u[2], pxz = m2[5] - u[0] * u[2];
     T A0, A1, Axy, Ayz, Axz;
     if constexpr (D3) {
-        A0 = ((T)2 * pxx - pyy - pzz) * (T)(1.0 / 36.0);   // row 3cx^2 - c^2, norm^2 36
-        A1 = (pyy - pzz) * (T)(1.0 / 12.0);                // row cy^2 - cz^2, norm^2 12
-        Axy = pxy * (T)0.25;
-        Ayz = pyz * (T)0.25;
-        Axz = pxz * (T)0.25;
+        // projections on the stress rows 3cx^2 - c^2, cy^2 - cz^2, cx cy, cy cz, cx cz
+        A0 = ((T)2 * pxx - pyy - pzz) * (T)(1.0 / stress_norm_diag0<GL, 3>());
+        A1 = (pyy - pzz) * (T)(1.0 / stress_norm_diag1<GL>());
+        Axy = pxy * (T)(1.0 / stress_norm_off<GL>());
+        Ayz = pyz * (T)(1.0 / stress_norm_off<GL>());
+        Axz = pxz * (T)(1.0 / stress_norm_off<GL>());
     } else {
-        A0 = (pxx - pyy) * (T)0.25;                        // row cx^2 - cy^2, norm^2 4
+        // stress rows cx^2 - cy^2 and cx cy
+        A0 = (pxx - pyy) * (T)(1.0 / stress_norm_diag0<GL, 2>());
         A1 = (T)0;
-        Axy = pxy * (T)0.25;
+        Axy = pxy * (T)(1.0 / stress_norm_off<GL>());
         Ayz = (T)0;
         Axz = (T)0;
     }

@@ -1,5 +1,5 @@
 // One instantiation set of the step kernel: lattice pair PFK_PAIR (0: D2Q9 +
-// D2Q5, 1: D3Q19 + D3Q7) and phase-field model PFK_MODEL (0: AC, 1: CH, 2:
+// D2Q5, 1: D3Q19 + D3Q7, 2: D3Q27 + D3Q7) and phase-field model PFK_MODEL (0: AC, 1: CH, 2:
 // nonlocal), every storage form, mode and tile. The build compiles this file
 // once per pair and model, in parallel.
 #include "step.h"
@@ -11,8 +11,10 @@ namespace pfk {
 
 #if PFK_PAIR == 0
 using InstPair = Pair2D;
-#else
+#elif PFK_PAIR == 1
 using InstPair = Pair3D;
+#else
+using InstPair = Pair3D27;
 #endif
 
 hipError_t PFK_CAT(launch_step_p, PFK_PAIR, _m, PFK_MODEL)(int precision, int mode, const KArgs& a, hipStream_t s) {

@@ -16,6 +16,8 @@ PFLBM_ESTATE = -5
 
 PFLBM_D2Q9_D2Q5 = 0
 PFLBM_D3Q19_D3Q7 = 1
+PFLBM_D3Q27_D3Q7 = 2
+LATTICES = {"D2Q9_D2Q5": PFLBM_D2Q9_D2Q5, "D3Q19_D3Q7": PFLBM_D3Q19_D3Q7, "D3Q27_D3Q7": PFLBM_D3Q27_D3Q7}
 PFLBM_AC = 0
 PFLBM_CH = 1
 PFLBM_NL = 2
@@ -116,7 +118,7 @@ TILES = {"auto": 0, "64x4": 1, "128x2": 2, "256x1": 3}
 def make_params(d, precision="fp64", check_interval=0, zblock=0, tile="auto"):
     """pflbm_params from a workload dict (keys as in workloads.base_params)."""
     p = pflbm_params()
-    p.lattice = PFLBM_D2Q9_D2Q5 if d["lattice"] == "D2Q9_D2Q5" else PFLBM_D3Q19_D3Q7
+    p.lattice = LATTICES[d["lattice"]]
     p.model = MODELS[d["model"]]
     p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     p.nx, p.ny, p.nz = int(d["nx"]), int(d["ny"]), int(d["nz"])

@@ -37,7 +37,7 @@ class Solver:
         self.h = h
         self.dim = 2 if self.d["lattice"] == "D2Q9_D2Q5" else 3
         self.shape = (int(self.d["nz"]), int(self.d["ny"]), int(self.d["nx"]))
-        self.Qg, self.Qh = (9, 5) if self.dim == 2 else (19, 7)
+        self.Qg, self.Qh = {"D2Q9_D2Q5": (9, 5), "D3Q19_D3Q7": (19, 7), "D3Q27_D3Q7": (27, 7)}[self.d["lattice"]]
 
     def _check(self, st, h):
         if st != P.PFLBM_OK:

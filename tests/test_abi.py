@@ -85,6 +85,17 @@ def test_invalid_params_rejected(bad):
     assert st == P.PFLBM_EINVAL
 
 
+def test_d3q27_state_bytes_and_invalid_lattice():
+    d = wl.base_params(lattice="D3Q27_D3Q7", nx=16, ny=16, nz=16)
+    st, n = _bytes(d, precision="fp32")
+    # g 2 x 27 and h 2 x 6 populations of 4096 nodes in float32
+    assert st == 0 and n >= (54 + 12) * 4096 * 4
+    p = P.make_params(d, "fp32")
+    p.lattice = 3
+    m = ctypes.c_size_t()
+    assert P.lib().pflbm_state_bytes(ctypes.byref(p), ctypes.byref(m)) == P.PFLBM_EINVAL
+
+
 def test_invalid_tile_rejected():
     d = wl.base_params(lattice="D3Q19_D3Q7", nx=32, ny=32, nz=32)
     for tile, ok in ((0, True), (3, True), (4, False), (-1, False)):
