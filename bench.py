@@ -30,8 +30,8 @@ def bytes_per_update(d, precision):
     phase-field populations; CH also carries the 3 components of (phi u); the
     nonlocal model reads the phase-field populations once more for the global
     sums of its multiplier)."""
-    d3 = d["lattice"] == "D3Q19_D3Q7"
-    qg = 19 if d3 else 9
+    d3 = d["lattice"] != "D2Q9_D2Q5"
+    qg = {"D2Q9_D2Q5": 9, "D3Q19_D3Q7": 19, "D3Q27_D3Q7": 27}[d["lattice"]]
     qh = (7 if d["model"] == "CH" else 6) if d3 else 5
     sg = {"fp64": 8, "fp32": 4, "mixed_fp16": 2, "mixed_bf16": 2}[precision]
     sh = 8 if precision == "fp64" else 4
@@ -193,12 +193,13 @@ def main():
         errors["laminar_sheared_droplet_64"] = {
             "steps": 1000, "rel_l2": field_errors(dl, phl, ul, 1000, ("fp32", "mixed_fp16", "mixed_bf16"))}
 
-    # the other phase-field models on the same workload and storage form
+    # the other phase-field models and the D3Q27 lattice, same workload and storage form
     models = {}
     if not args.no_models:
-        for model, extra in (("CH", {}), ("NL", {"lam": 0.0}), ("NL", {"lam": 0.9})):
-            dm = dict(d, model=model, **extra)
-            key = model if model != "NL" else "NL_lam%g" % extra["lam"]
+        for key, extra in (("CH", {"model": "CH"}), ("NL_lam0", {"model": "NL", "lam": 0.0}),
+                           ("NL_lam0.9", {"model": "NL", "lam": 0.9}),
+                           ("AC_D3Q27", {"lattice": "D3Q27_D3Q7"})):
+            dm = dict(d, **extra)
             print("bench: model %s" % key, file=sys.stderr, flush=True)
             sm, msm, _ = time_form(dm, phi, u, args.precision, max(60, args.steps // 3), 10, args.zblock)
             b = bytes_per_update(dm, args.precision)
