@@ -3,7 +3,8 @@
 Model (Sec. II.C.1, Fakhari2017 conservative Allen-Cahn) with the CH variant
 of Sec. II.D.1 (Liang2014 phase-field equation) as the second model and the
 nonlocal / hybrid Allen-Cahn phase-field side of Sec. II.C (Chai2018, Hu2019
-with weight lam) as the third. Notation
+with weight lam) as the third, and Liang2018 (Sec. II.C, conservative AC with
+its own conservative-form hydrodynamics) as the fourth. Notation
 (see the package docstring): g = hydrodynamic distribution (paper's f_beta),
 h = phase-field distribution (paper's g_alpha), W = interface width xi,
 M = mobility M_phi.
@@ -60,8 +61,9 @@ WALL = "wall"
 class Params:
     lattice: str = "D2Q9_D2Q5"       # or "D3Q19_D3Q7"
     model: str = "AC"                 # "AC" (Fakhari2017), "CH" (Liang2014 h-equation)
-                                      # or "NL" (Chai2018 nonlocal AC, blended with the
-                                      # conservative flux by lam as in Hu2019)
+                                      # "NL" (Chai2018 nonlocal AC, blended with the
+                                      # conservative flux by lam as in Hu2019) or "L18"
+                                      # (Liang2018: phase field and hydrodynamics)
     nx: int = 64
     ny: int = 64
     nz: int = 1
@@ -183,6 +185,34 @@ def g_eq(p, pstar, u):
     for i in range(lat.Q):
         cu = _cdot(lat.c[i], u)
         out[i] = lat.w[i] * (pstar + cu / CS2 + cu * cu / (2 * CS2 * CS2) - uu / (2 * CS2))
+    return out
+
+
+def f_eq_liang(p, rho, pres, u):
+    """Eq. liang_feq (also Eq. liang2_feq): rest (p/c_s^2)(w_0 - 1) + rho w_0 [...],
+    others (p/c_s^2) w + rho w [e.u/c_s^2 + (e.u)^2/(2 c_s^4) - u.u/(2 c_s^2)]."""
+    lat = p.lattices[0]
+    uu = _vdot(u, u)
+    out = np.empty((lat.Q,) + rho.shape, dtype=np.result_type(rho, pres, u))
+    for i in range(lat.Q):
+        cu = _cdot(lat.c[i], u)
+        kin = rho * lat.w[i] * (cu / CS2 + cu * cu / (2 * CS2 * CS2) - uu / (2 * CS2))
+        out[i] = pres / CS2 * (lat.w[i] - 1 if i == 0 else lat.w[i]) + kin
+    return out
+
+
+def force_liang(p, F, u, grad_rho):
+    """Eq. liang_F_final: w [u.grad rho + e.F/c_s^2 + u grad rho : (e e - c_s^2 I)/c_s^2]."""
+    lat = p.lattices[0]
+    udr = _vdot(u, grad_rho)
+    out = np.empty((lat.Q,) + udr.shape, dtype=np.result_type(F, u, grad_rho))
+    for i in range(lat.Q):
+        c = lat.c[i]
+        tens = 0.0 * udr
+        for a in range(3):
+            for b in range(3):
+                tens = tens + u[a] * grad_rho[b] * (c[a] * c[b] - CS2 * (a == b))
+        out[i] = lat.w[i] * (udr + _cdot(c, F) / CS2 + tens / CS2)
     return out
 
 
@@ -326,6 +356,8 @@ def macroscopic(p, st):
     tau = nu / CS2 + 0.5
     # O5
     mu_phi = chemical_potential(p, phi, lap)
+    if p.model == "L18":
+        return _macroscopic_liang(p, st, phi, grad, lap, rho, grad_rho, nu, tau, mu_phi)
     # O6
     pstar = st.g[0].copy()
     for i in range(1, gl.Q):
@@ -359,6 +391,30 @@ def macroscopic(p, st):
                 pstar=pstar, p=pres, F=F, u=u, R=R, gamma=gamma)
 
 
+def _macroscopic_liang(p, st, phi, grad, lap, rho, grad_rho, nu, tau, mu_phi):
+    """Liang2018 hydrodynamics (Sec. II.C): F = F_s + F_b (no pressure or viscous
+    force term), rho u = sum e f + F/2 (Eq. liang_velocity_update) and
+    p = c_s^2 / (1 - w_0) [sum_{beta != 0} f + u.grad rho / 2
+    + rho w_0 (-u.u / (2 c_s^2))] (Eq. liang_p_update)."""
+    gl = p.lattices[0]
+    Fs = mu_phi * grad
+    Fb = np.array([rho * p.gravity[a] + p.force[a] for a in range(3)])
+    F = Fs + Fb
+    j = np.zeros((3,) + phi.shape, dtype=st.g.dtype)
+    for i in range(gl.Q):
+        for a in range(3):
+            if gl.c[i][a] != 0:
+                j[a] = j[a] + gl.c[i][a] * st.g[i]
+    u = (j + 0.5 * F) / rho
+    moving = st.g[1].copy()
+    for i in range(2, gl.Q):
+        moving = moving + st.g[i]
+    w0 = gl.w[0]
+    pres = CS2 / (1 - w0) * (moving + 0.5 * _vdot(u, grad_rho) + rho * w0 * (-_vdot(u, u) / (2 * CS2)))
+    return dict(phi=phi, grad=grad, lap=lap, rho=rho, nu=nu, tau=tau, mu_phi=mu_phi,
+                pstar=pres / (rho * CS2), p=pres, F=F, u=u, grad_rho=grad_rho, R=None, gamma=None)
+
+
 # --------------------------------------------------------------------------
 # collisions (O10, O11)
 
@@ -376,6 +432,10 @@ def collide_h(p, st, m):
         heq = h_eq_ch(p, m["phi"], m["mu_phi"], m["u"])
         phiu = m["phi"] * m["u"]
         G = G_ch(p, phiu - st.phiu_prev)       # backward Euler, delta t = 1
+    elif p.model == "L18":
+        # Eqs. liang_geq and liang_G_final, d(phi u)/dt by backward Euler
+        heq = h_eq_nl(p, m["phi"], m["u"])
+        G = G_ch(p, m["phi"] * m["u"] - st.phiu_prev) + G_ac(p, m["phi"], m["grad"])
     elif p.model == "NL":
         # Eqs. Chai_geq and Hu_G (lam = 0: Eq. chai_G)
         heq = h_eq_nl(p, m["phi"], m["u"])
@@ -394,8 +454,12 @@ def collide_g(p, st, m):
     gl = p.lattices[0]
     Mmat, stress = mrt.basis(gl)
     Minv = np.linalg.inv(Mmat)
-    geq = g_eq(p, m["pstar"], m["u"])
-    Fi = force_populations(p, m["F"], m["rho"])
+    if p.model == "L18":
+        geq = f_eq_liang(p, m["rho"], m["p"], m["u"])
+        Fi = force_liang(p, m["F"], m["u"], m["grad_rho"])
+    else:
+        geq = g_eq(p, m["pstar"], m["u"])
+        Fi = force_populations(p, m["F"], m["rho"])
     mom = np.tensordot(Mmat, st.g, axes=(1, 0))
     mom_eq = np.tensordot(Mmat, geq, axes=(1, 0))
     mom_F = np.tensordot(Mmat, Fi, axes=(1, 0))
@@ -458,7 +522,7 @@ def step(p, st):
     else:
         h_post = collide_h(p, st, m)
         h_new = stream(p, p.lattices[1], h_post, "h")
-    phiu = m["phi"] * m["u"] if p.model == "CH" else None
+    phiu = m["phi"] * m["u"] if p.model in ("CH", "L18") else None
     return State(g_new, h_new, phiu)
 
 
@@ -491,6 +555,8 @@ def init(p, phi0, u0=None, p0=None):
         return State(g, h, phi0 * u0)
     if p.model == "NL":
         return State(g, h_eq_nl(p, phi0, u0), None)
+    if p.model == "L18":
+        return State(f_eq_liang(p, rho0, p0, u0), h_eq_nl(p, phi0, u0), phi0 * u0)
     return State(g, h_eq_ac(p, phi0, u0), None)
 
 
