@@ -74,6 +74,11 @@ extern "C" {
 /* phase-field model */
 #define PFLBM_AC 0   /* conservative Allen-Cahn, Eqs. fakhari_geq, fakhari_G_modified */
 #define PFLBM_CH 1   /* Cahn-Hilliard, Eqs. liang2_geq, liang2_G */
+#define PFLBM_L18 3  /* Liang2018 (Sec. II.C): conservative AC with Eqs. liang_geq and
+                        liang_G_final (backward-Euler d(phi u)/dt) and its conservative-form
+                        hydrodynamics, Eqs. liang_feq, liang_F_final, liang_velocity_update,
+                        liang_p_update. Stationary walls only; with fp16-stored g,
+                        rho_H and rho_L <= 16 (f / w must fit the fp16 range) */
 #define PFLBM_NL 2   /* nonlocal Allen-Cahn, Eqs. Chai_geq, chai_G (Chai2018), the source
                         blended with the conservative flux by lam as in Eq. Hu_G (Hu2019);
                         phi = sum h + (1 - lam) R / 2 (Eq. chai2018_phi_update), with the
@@ -104,7 +109,7 @@ extern "C" {
 
 typedef struct pflbm_params {
     int lattice;          /* PFLBM_D2Q9_D2Q5, PFLBM_D3Q19_D3Q7 or PFLBM_D3Q27_D3Q7 */
-    int model;            /* PFLBM_AC, PFLBM_CH or PFLBM_NL */
+    int model;            /* PFLBM_AC, PFLBM_CH, PFLBM_NL or PFLBM_L18 */
     int precision;        /* PFLBM_FP64 ... PFLBM_MIXED_BF16 */
     int nx, ny, nz;       /* nodes per axis, each >= 1; nz == 1 for 2-D */
     int bc[3];            /* PFLBM_PERIODIC or PFLBM_WALL per axis x, y, z */

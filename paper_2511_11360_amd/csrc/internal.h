@@ -71,7 +71,7 @@ struct KArgs {
     void* gout;            // hydrodynamic populations written this step [z][Qg][P]
     const void* hin;       // phase-field populations read this step [z][Qhs][P]
     void* hout;            // phase-field populations written this step [z][Qhs][P]
-    void* phiu;            // CH (phi u) of the previous step [z][3][P], compute type
+    void* phiu;            // CH / Liang2018: (phi u) of the previous step [z][3][P], compute type
     double* f_phi;         // MODE_FIELDS outputs (canonical float64), may be null
     double* f_u;
     double* f_p;
@@ -174,6 +174,9 @@ hipError_t launch_step_p1_m2(int precision, int mode, const KArgs& a, hipStream_
 hipError_t launch_step_p2_m0(int precision, int mode, const KArgs& a, hipStream_t s);
 hipError_t launch_step_p2_m1(int precision, int mode, const KArgs& a, hipStream_t s);
 hipError_t launch_step_p2_m2(int precision, int mode, const KArgs& a, hipStream_t s);
+hipError_t launch_step_p0_m3(int precision, int mode, const KArgs& a, hipStream_t s);
+hipError_t launch_step_p1_m3(int precision, int mode, const KArgs& a, hipStream_t s);
+hipError_t launch_step_p2_m3(int precision, int mode, const KArgs& a, hipStream_t s);
 hipError_t launch_init(int lattice, int model, int precision, const InitArgs& a, hipStream_t s);
 hipError_t launch_get(int lattice, int model, int precision, const IOArgs& a, hipStream_t s);
 hipError_t launch_set(int lattice, int model, int precision, const IOArgs& a, hipStream_t s);

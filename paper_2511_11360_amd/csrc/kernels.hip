@@ -7,17 +7,12 @@
 namespace pfk {
 
 hipError_t launch_step(int lattice, int model, int precision, int mode, const KArgs& a, hipStream_t s) {
-    if (lattice == 0)
-        return model == 2 ? launch_step_p0_m2(precision, mode, a, s)
-             : model == 1 ? launch_step_p0_m1(precision, mode, a, s)
-                          : launch_step_p0_m0(precision, mode, a, s);
-    if (lattice == 1)
-        return model == 2 ? launch_step_p1_m2(precision, mode, a, s)
-             : model == 1 ? launch_step_p1_m1(precision, mode, a, s)
-                          : launch_step_p1_m0(precision, mode, a, s);
-    return model == 2 ? launch_step_p2_m2(precision, mode, a, s)
-         : model == 1 ? launch_step_p2_m1(precision, mode, a, s)
-                      : launch_step_p2_m0(precision, mode, a, s);
+    using StepFn = hipError_t (*)(int, int, const KArgs&, hipStream_t);
+    static const StepFn fn[3][4] = {
+        {launch_step_p0_m0, launch_step_p0_m1, launch_step_p0_m2, launch_step_p0_m3},
+        {launch_step_p1_m0, launch_step_p1_m1, launch_step_p1_m2, launch_step_p1_m3},
+        {launch_step_p2_m0, launch_step_p2_m1, launch_step_p2_m2, launch_step_p2_m3}};
+    return fn[lattice][model](precision, mode, a, s);
 }
 
 // final reduction over the per-block partials, one workgroup, fixed order
@@ -91,7 +86,15 @@ __global__ __launch_bounds__(256) void k_init(const InitArgs a) {
     unroll<GL::Q>([&](auto I) {
         constexpr int i = I;
         const double cu = GL::c(i, 0) * u[0] + GL::c(i, 1) * u[1] + GL::c(i, 2) * u[2];
-        double geq = GL::w(i) * (ps + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+        double geq;
+        if constexpr (MODEL == 3) {
+            // Eq. liang_feq: (p/c_s^2)(w - [i = 0]) + rho w (3 c.u + 4.5 (c.u)^2 - 1.5 u.u)
+            const double p0 = a.p0 ? a.p0[n] : 0.0;
+            geq = 3.0 * p0 * (GL::w(i) - (i == 0 ? 1.0 : 0.0)) +
+                  rho * GL::w(i) * (3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+        } else {
+            geq = GL::w(i) * (ps + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+        }
         bool w;
         int side;
         const size_t e = pull_source<GL, i, GL::Q, 0>(a.nx, a.ny, a.nz, a.bc, x, y, z, a.P, w, side);
@@ -111,12 +114,16 @@ __global__ __launch_bounds__(256) void k_init(const InitArgs a) {
             const double heq = HL::w(al) * phi * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * usq);
             put_h(std::integral_constant<int, al>{}, heq);
         });
-    } else if constexpr (MODEL == 2) {
+    } else if constexpr (MODEL == 2 || MODEL == 3) {
         unroll<QHS>([&](auto J) {
             constexpr int al = J + HOFF;
             const double eu = HL::c(al, 0) * u[0] + HL::c(al, 1) * u[1] + HL::c(al, 2) * u[2];
             put_h(std::integral_constant<int, al>{}, HL::w(al) * phi * (1.0 + 3.0 * eu));
         });
+        if constexpr (MODEL == 3) {
+            T* PU = (T*)a.phiu;
+            for (int c = 0; c < 3; ++c) PU[el<3>(z, c, ip, a.P)] = (T)(phi * u[c]);
+        }
     } else {
         // mu_phi(phi0) with the same stencil and ghost rules as the step
         double lap = 0.0;
@@ -330,7 +337,8 @@ __global__ __launch_bounds__(256) void k_gamma_final(const double* __restrict__ 
             }                                                                                \
         };                                                                                   \
         auto mdl = [&](auto pair) {                                                          \
-            if (model == 2) prec(pair, std::integral_constant<int, 2>{});                    \
+            if (model == 3) prec(pair, std::integral_constant<int, 3>{});                    \
+            else if (model == 2) prec(pair, std::integral_constant<int, 2>{});               \
             else if (model == 1) prec(pair, std::integral_constant<int, 1>{});               \
             else prec(pair, std::integral_constant<int, 0>{});                               \
         };                                                                                   \

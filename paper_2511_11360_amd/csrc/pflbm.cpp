@@ -41,8 +41,8 @@ bool finite(double v) { return std::isfinite(v); }
 std::string validate(const pflbm_params& p) {
     if (p.lattice != PFLBM_D2Q9_D2Q5 && p.lattice != PFLBM_D3Q19_D3Q7 && p.lattice != PFLBM_D3Q27_D3Q7)
         return "lattice must be PFLBM_D2Q9_D2Q5, PFLBM_D3Q19_D3Q7 or PFLBM_D3Q27_D3Q7";
-    if (p.model != PFLBM_AC && p.model != PFLBM_CH && p.model != PFLBM_NL)
-        return "model must be PFLBM_AC, PFLBM_CH or PFLBM_NL";
+    if (p.model != PFLBM_AC && p.model != PFLBM_CH && p.model != PFLBM_NL && p.model != PFLBM_L18)
+        return "model must be PFLBM_AC, PFLBM_CH, PFLBM_NL or PFLBM_L18";
     if (p.precision < PFLBM_FP64 || p.precision > PFLBM_MIXED_BF16) return "unknown precision";
     if (p.nx < 1 || p.ny < 1 || p.nz < 1) return "nx, ny, nz must be >= 1";
     if (p.lattice == PFLBM_D2Q9_D2Q5 && p.nz != 1) return "2-D lattice requires nz == 1";
@@ -72,6 +72,13 @@ std::string validate(const pflbm_params& p) {
     if (!(p.s_other > 0 && p.s_other < 2)) return "s_other must be in (0, 2)";
     if (!(p.normal_eps >= 0) || !finite(p.normal_eps)) return "normal_eps must be >= 0";
     if (!(p.lam >= 0 && p.lam <= 1)) return "lam must be in [0, 1]";
+    if (p.model == PFLBM_L18) {
+        for (int s = 0; s < 2; ++s)
+            for (int a = 0; a < 3; ++a)
+                if (p.wall_u[s][a] != 0.0) return "PFLBM_L18 supports stationary walls only";
+        if (p.precision == PFLBM_MIXED_FP16 && (p.rho_H > 16.0 || p.rho_L > 16.0))
+            return "PFLBM_L18 with fp16-stored g needs rho_H, rho_L <= 16";
+    }
     for (int a = 0; a < 3; ++a)
         if (!finite(p.gravity[a]) || !finite(p.force[a])) return "body force not finite";
     if (p.lattice == PFLBM_D2Q9_D2Q5 && (p.gravity[2] != 0.0 || p.force[2] != 0.0)) return "2-D body force has a z component";
@@ -87,7 +94,7 @@ Layout make_layout(const pflbm_params& p) {
     L.dim = d3 ? 3 : 2;
     L.Qg = p.lattice == PFLBM_D3Q27_D3Q7 ? 27 : (d3 ? 19 : 9);
     L.Qh = d3 ? 7 : 5;
-    L.Qhs = (d3 && p.model != PFLBM_CH) ? 6 : L.Qh;   // AC / NL on D3Q7: rest population is zero
+    L.Qhs = (d3 && p.model != PFLBM_CH) ? 6 : L.Qh;   // AC / NL / L18 on D3Q7: rest population is zero
     L.sT = p.precision == PFLBM_FP64 ? 8 : 4;
     L.sg = p.precision == PFLBM_FP64 ? 8 : (p.precision == PFLBM_FP32 ? 4 : 2);
     L.sh = p.precision == PFLBM_FP64 ? 8 : 4;
@@ -126,7 +133,7 @@ Layout make_layout(const pflbm_params& p) {
         off = align_up(off + (size_t)L.Qhs * planes * L.sh, ALIGN);
     }
     L.off_pu = off;
-    if (p.model == PFLBM_CH) off = align_up(off + 3 * planes * L.sT, ALIGN);
+    if (p.model == PFLBM_CH || p.model == PFLBM_L18) off = align_up(off + 3 * planes * L.sT, ALIGN);
     L.off_part = off;
     off = align_up(off + (size_t)L.nblocks * NDIAG * sizeof(double), ALIGN);
     L.off_gpart = off;   // nonlocal multiplier: per-256-node partial sums
@@ -141,7 +148,7 @@ Layout make_layout(const pflbm_params& p) {
     L.ck_g = 256;
     L.g_bytes = (size_t)L.Qg * planes * L.sg;
     L.h_bytes = (size_t)L.Qhs * planes * L.sh;
-    L.pu_bytes = p.model == PFLBM_CH ? 3 * planes * L.sT : 0;
+    L.pu_bytes = (p.model == PFLBM_CH || p.model == PFLBM_L18) ? 3 * planes * L.sT : 0;
     L.ck_h = align_up(L.ck_g + L.g_bytes, 256);
     L.ck_pu = align_up(L.ck_h + L.h_bytes, 256);
     L.ck_total = align_up(L.ck_pu + L.pu_bytes, 256);
@@ -508,7 +515,7 @@ int pflbm_save_state(pflbm_t* h, void* dev_dst) {
     HIPCHK(h, launch_header(d, h->steps, h->stream), "header kernel");
     HIPCHK(h, hipMemcpyAsync(d + L.ck_g, h->base + L.off_g[h->gcur], L.g_bytes, hipMemcpyDeviceToDevice, h->stream), "save g");
     HIPCHK(h, hipMemcpyAsync(d + L.ck_h, h->base + L.off_h[h->hcur], L.h_bytes, hipMemcpyDeviceToDevice, h->stream), "save h");
-    if (h->p.model == PFLBM_CH)
+    if (L.pu_bytes)
         HIPCHK(h, hipMemcpyAsync(d + L.ck_pu, h->base + L.off_pu, L.pu_bytes, hipMemcpyDeviceToDevice, h->stream), "save phiu");
     return PFLBM_OK;
 }
@@ -525,7 +532,7 @@ int pflbm_load_state(pflbm_t* h, const void* dev_src) {
     if (hdr[0] != 0x70666c626eLL) return fail(h, PFLBM_EINVAL, "not a pflbm checkpoint");
     HIPCHK(h, hipMemcpyAsync(h->base + L.off_g[0], s + L.ck_g, L.g_bytes, hipMemcpyDeviceToDevice, h->stream), "load g");
     HIPCHK(h, hipMemcpyAsync(h->base + L.off_h[0], s + L.ck_h, L.h_bytes, hipMemcpyDeviceToDevice, h->stream), "load h");
-    if (h->p.model == PFLBM_CH)
+    if (L.pu_bytes)
         HIPCHK(h, hipMemcpyAsync(h->base + L.off_pu, s + L.ck_pu, L.pu_bytes, hipMemcpyDeviceToDevice, h->stream), "load phiu");
     h->steps = hdr[1];
     h->gcur = 0;

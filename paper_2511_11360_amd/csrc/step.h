@@ -218,6 +218,142 @@ __device__ __forceinline__ void node_update(const PhysT<T>& ph, const T* g, cons
         if constexpr (cx * cz != 0) m2[5] += (T)(cx * cz) * s;
     });
 
+    if constexpr (MODEL == 3) {
+        // ---- Liang2018 (Sec. II.C): conservative-form hydrodynamics, F = F_s + F_b,
+        // rho u = sum e f + F/2 (Eq. liang_velocity_update),
+        // p = c_s^2/(1 - w_0) [sum_{b != 0} f + u.grad rho / 2 - rho w_0 u.u/(2 c_s^2)]
+        // (Eq. liang_p_update)
+        const T irho3 = irho;
+        T F[3], u[3], grho[3];
+        unroll<3>([&](auto A) {
+            constexpr int a = A;
+            F[a] = mu_phi * gr[a] + rho * ph.body[a] + ph.force[a];
+            u[a] = (j[a] + (T)0.5 * F[a]) * irho3;
+            grho[a] = dRho * gr[a];
+        });
+        const T udr = u[0] * grho[0] + u[1] * grho[1] + u[2] * grho[2];
+        const T usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        constexpr T w0 = (T)GL::w(0);
+        const T pres = (T)(1.0 / (3.0 * (1.0 - GL::w(0)))) *
+                       ((ps - g[0]) + (T)0.5 * udr - rho * w0 * (T)1.5 * usq);
+        mo.phi = phi;
+        mo.rho = rho;
+        mo.p = pres;
+        mo.u[0] = u[0];
+        mo.u[1] = u[1];
+        mo.u[2] = u[2];
+        if constexpr (!COLLIDE) return;
+
+        // ---- f collision: two-rate MRT with f_eq of Eq. liang_feq and
+        // F_b = 3 w [c.F + (c.u)(c.grad rho)] (Eq. liang_F_final, its u.grad rho
+        // terms cancel); F has a stress part, so P acts on (f - f_eq) + F / 2:
+        // f* = (1 - s_o) f + s_o f_eq + (1 - s_o/2) F - (1/tau - s_o) P (f - f_eq + F/2)
+        const T so = ph.s_o;
+        const T so1 = (T)1 - so;
+        const T dS = itau - so;
+        const T fh = (T)1 - (T)0.5 * so;
+        const T p3 = (T)3 * pres;                          // p / c_s^2
+        // traceless parts of sum c c (f - f_eq) + sum c c F / 2, with
+        // sum c c f_eq = p I + rho u u and sum c c F = (u grad rho + grad rho u + (u.grad rho) I) / 3
+        auto pi = [&](int a, int b, T m) {
+            return m - rho * u[a] * u[b] + (T)(1.0 / 6.0) * (u[a] * grho[b] + u[b] * grho[a]);
+        };
+        const T pxx = pi(0, 0, m2[0]), pyy = pi(1, 1, m2[1]), pzz = pi(2, 2, m2[2]);
+        const T pxy = pi(0, 1, m2[3]), pyz = pi(1, 2, m2[4]), pxz = pi(0, 2, m2[5]);
+        T A0, A1, Axy, Ayz, Axz;
+        if constexpr (D3) {
+            A0 = ((T)2 * pxx - pyy - pzz) * (T)(1.0 / stress_norm_diag0<GL, 3>());
+            A1 = (pyy - pzz) * (T)(1.0 / stress_norm_diag1<GL>());
+            Axy = pxy * (T)(1.0 / stress_norm_off<GL>());
+            Ayz = pyz * (T)(1.0 / stress_norm_off<GL>());
+            Axz = pxz * (T)(1.0 / stress_norm_off<GL>());
+        } else {
+            A0 = (pxx - pyy) * (T)(1.0 / stress_norm_diag0<GL, 2>());
+            A1 = (T)0;
+            Axy = pxy * (T)(1.0 / stress_norm_off<GL>());
+            Ayz = (T)0;
+            Axz = (T)0;
+        }
+        const T kin0 = rho * (T)(-1.5) * usq;
+        gsink(std::integral_constant<int, 0>{}, so1 * g[0] + so * (p3 * (w0 - (T)1) + w0 * kin0));
+        unroll<GL::NP>([&](auto K) {
+            constexpr int i = GL::pf(K), o = GL::opp(i);
+            constexpr int cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
+            constexpr T w = (T)GL::w(i);
+            T cu = (T)0, cf = (T)0, cr = (T)0;
+            if constexpr (cx != 0) { cu += (T)cx * u[0]; cf += (T)cx * F[0]; cr += (T)cx * grho[0]; }
+            if constexpr (cy != 0) { cu += (T)cy * u[1]; cf += (T)cy * F[1]; cr += (T)cy * grho[1]; }
+            if constexpr (cz != 0) { cu += (T)cz * u[2]; cf += (T)cz * F[2]; cr += (T)cz * grho[2]; }
+            T P = (T)0;
+            if constexpr (D3) {
+                constexpr int q0 = 3 * cx * cx - (cx * cx + cy * cy + cz * cz);
+                constexpr int q1 = cy * cy - cz * cz;
+                if constexpr (q0 != 0) P += (T)q0 * A0;
+                if constexpr (q1 != 0) P += (T)q1 * A1;
+                if constexpr (cx * cy != 0) P += (T)(cx * cy) * Axy;
+                if constexpr (cy * cz != 0) P += (T)(cy * cz) * Ayz;
+                if constexpr (cx * cz != 0) P += (T)(cx * cz) * Axz;
+            } else {
+                constexpr int q0 = cx * cx - cy * cy;
+                if constexpr (q0 != 0) P += (T)q0 * A0;
+                if constexpr (cx * cy != 0) P += (T)(cx * cy) * Axy;
+            }
+            const T E = w * (p3 + kin0 + rho * (T)4.5 * cu * cu);   // even part of f_eq
+            const T O = w * (T)3 * rho * cu;                         // odd part
+            const T Fe = (T)3 * w * cu * cr, Fo = (T)3 * w * cf;     // even / odd parts of F
+            const T base = so * E + fh * Fe - dS * P;
+            const T t = so * O + fh * Fo;
+            gsink(std::integral_constant<int, i>{}, so1 * g[i] + base + t);
+            gsink(std::integral_constant<int, o>{}, so1 * g[o] + base - t);
+        });
+
+        // ---- h collision: Eqs. liang_geq, liang_G_final,
+        // h_eq = w phi (1 + 3 e.u), G = w e.[3 d(phi u)/dt + (4/W) phi (1 - phi) n]
+        const T itp = ph.inv_tau_phi, gfp = ph.g_fac_phi;
+        const T itp1 = (T)1 - itp;
+        constexpr int HOFF = D3 ? 1 : 0;
+        T phis = (T)0;
+        unroll<HL::Q - HOFF>([&](auto J) { phis += h[J + HOFF]; });
+        T pu[3], dpu[3];
+        unroll<3>([&](auto A) {
+            constexpr int a = A;
+            pu[a] = phi * u[a];
+            dpu[a] = pu[a] - pu_prev[a];
+            pu_new[a] = pu[a];
+        });
+        const T gg = gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2];
+        const T coef = ph.anti * phi * ((T)1 - phi) * rsqrt_(gg + ph.eps2);
+        // float forms close each node's balance on its last population (see below)
+        constexpr bool CLOSE = sizeof(T) == 4;
+        T hacc = (T)0;
+        if constexpr (HL::w(0) != 0.0) {
+            const T v = itp1 * h[0] + itp * (T)HL::w(0) * phi;
+            if constexpr (CLOSE) hacc += v;
+            hsink(std::integral_constant<int, 0>{}, v);
+        }
+        unroll<HL::NP>([&](auto K) {
+            constexpr int al = HL::pf(K), o = HL::opp(al);
+            constexpr T w = (T)HL::w(al);
+            constexpr int ex = HL::c(al, 0), ey = HL::c(al, 1), ez = HL::c(al, 2);
+            T eu = (T)0, eg = (T)0, ed = (T)0;
+            if constexpr (ex != 0) { eu += (T)ex * u[0]; eg += (T)ex * gr[0]; ed += (T)ex * dpu[0]; }
+            if constexpr (ey != 0) { eu += (T)ey * u[1]; eg += (T)ey * gr[1]; ed += (T)ey * dpu[1]; }
+            if constexpr (ez != 0) { eu += (T)ez * u[2]; eg += (T)ez * gr[2]; ed += (T)ez * dpu[2]; }
+            const T base = itp * w * phi;
+            const T t = itp * ((T)3 * w * phi * eu) + gfp * w * ((T)3 * ed + coef * eg);
+            const T va = itp1 * h[al] + base + t, vo = itp1 * h[o] + base - t;
+            if constexpr (CLOSE) hacc += va;
+            hsink(std::integral_constant<int, al>{}, va);
+            if constexpr (CLOSE && decltype(K)::value == HL::NP - 1) {
+                hsink(std::integral_constant<int, o>{}, phis - hacc);
+            } else {
+                if constexpr (CLOSE) hacc += vo;
+                hsink(std::integral_constant<int, o>{}, vo);
+            }
+        });
+        return;
+    }
+
     // forces: F_s + F_b + F_p, with F_p = -(p/rho) grad rho = -c_s^2 p* dRho grad phi
     const T inv2rho = (T)0.5 * irho;
     const T sg = mu_phi - ps * dRho * (T)(1.0 / 3.0);
@@ -709,7 +845,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
             }
         });
         T pu_prev[3] = {(T)0, (T)0, (T)0};
-        if constexpr (MODEL == 1) {
+        if constexpr (MODEL == 1 || MODEL == 3) {
             unroll<3>([&](auto A) {
                 constexpr int c = A;
                 pu_prev[c] = at<3>(PU, z, c, P, o11);
@@ -739,7 +875,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
                 }
             };
             node_update<PAIR, MODEL, T, true>(ph, g, h, phin, pu_prev, pu_new, mo, gam, gsink, hsink);
-            if constexpr (MODEL == 1) {
+            if constexpr (MODEL == 1 || MODEL == 3) {
                 if (a.write_h) {
                     unroll<3>([&](auto A) {
                         constexpr int c = A;

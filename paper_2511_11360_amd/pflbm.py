@@ -21,7 +21,8 @@ LATTICES = {"D2Q9_D2Q5": PFLBM_D2Q9_D2Q5, "D3Q19_D3Q7": PFLBM_D3Q19_D3Q7, "D3Q27
 PFLBM_AC = 0
 PFLBM_CH = 1
 PFLBM_NL = 2
-MODELS = {"AC": PFLBM_AC, "CH": PFLBM_CH, "NL": PFLBM_NL}
+PFLBM_L18 = 3
+MODELS = {"AC": PFLBM_AC, "CH": PFLBM_CH, "NL": PFLBM_NL, "L18": PFLBM_L18}
 PFLBM_FP64 = 0
 PFLBM_FP32 = 1
 PFLBM_MIXED_FP16 = 2
