@@ -3,8 +3,10 @@
 Model (Sec. II.C.1, Fakhari2017 conservative Allen-Cahn) with the CH variant
 of Sec. II.D.1 (Liang2014 phase-field equation) as the second model and the
 nonlocal / hybrid Allen-Cahn phase-field side of Sec. II.C (Chai2018, Hu2019
-with weight lam) as the third, and Liang2018 (Sec. II.C, conservative AC with
-its own conservative-form hydrodynamics) as the fourth. Notation
+with weight lam) as the third, Liang2018 (Sec. II.C, conservative AC with
+its own conservative-form hydrodynamics) as the fourth, and Liang2014 with its
+full hydrodynamic coupling (Sec. II.D.1: CH phase field, Eqs. liang2_feq,
+liang2_F, the F_a force and the modified velocity update) as the fifth. Notation
 (see the package docstring): g = hydrodynamic distribution (paper's f_beta),
 h = phase-field distribution (paper's g_alpha), W = interface width xi,
 M = mobility M_phi.
@@ -62,8 +64,9 @@ class Params:
     lattice: str = "D2Q9_D2Q5"       # or "D3Q19_D3Q7"
     model: str = "AC"                 # "AC" (Fakhari2017), "CH" (Liang2014 h-equation)
                                       # "NL" (Chai2018 nonlocal AC, blended with the
-                                      # conservative flux by lam as in Hu2019) or "L18"
-                                      # (Liang2018: phase field and hydrodynamics)
+                                      # conservative flux by lam as in Hu2019), "L18"
+                                      # (Liang2018: phase field and hydrodynamics) or
+                                      # "L14" (Liang2014 CH with its own hydrodynamics)
     nx: int = 64
     ny: int = 64
     nz: int = 1
@@ -216,6 +219,23 @@ def force_liang(p, F, u, grad_rho):
     return out
 
 
+def force_liang14(p, Fp, u, rho, grad_rho):
+    """Eq. liang2_F: (e - u)/c_s^2 . [Gamma(u) grad(rho c_s^2) + F' s(u)] with
+    Gamma, s of Eq. Gamma_beta and F' = F_s + F_a + F_b."""
+    lat = p.lattices[0]
+    uu = _vdot(u, u)
+    A = CS2 * grad_rho
+    out = np.empty((lat.Q,) + rho.shape, dtype=np.result_type(Fp, u, grad_rho))
+    for i in range(lat.Q):
+        c = lat.c[i]
+        cu = _cdot(c, u)
+        gam = lat.w[i] * (cu / CS2 + cu * cu / (2 * CS2 * CS2) - uu / (2 * CS2))
+        s_ = lat.w[i] + gam
+        emu = [c[a] - u[a] for a in range(3)]
+        out[i] = (sum(emu[a] * (gam * A[a] + Fp[a] * s_) for a in range(3))) / CS2
+    return out
+
+
 def h_eq_ac(p, phi, u):
     """Eq. fakhari_geq: w phi [1 + e.u/c_s^2 + (e.u)^2/(2c_s^4) - u.u/(2c_s^2)]."""
     lat = p.lattices[1]
@@ -358,6 +378,8 @@ def macroscopic(p, st):
     mu_phi = chemical_potential(p, phi, lap)
     if p.model == "L18":
         return _macroscopic_liang(p, st, phi, grad, lap, rho, grad_rho, nu, tau, mu_phi)
+    if p.model == "L14":
+        return _macroscopic_liang14(p, st, phi, grad, lap, rho, grad_rho, nu, tau, mu_phi)
     # O6
     pstar = st.g[0].copy()
     for i in range(1, gl.Q):
@@ -415,12 +437,40 @@ def _macroscopic_liang(p, st, phi, grad, lap, rho, grad_rho, nu, tau, mu_phi):
                 pstar=pres / (rho * CS2), p=pres, F=F, u=u, grad_rho=grad_rho, R=None, gamma=None)
 
 
+def _macroscopic_liang14(p, st, phi, grad, lap, rho, grad_rho, nu, tau, mu_phi):
+    """Liang2014 hydrodynamics (Sec. II.D.1): lap mu_phi with the same stencil
+    and ghost rules as phi (so div(M grad mu_phi) = M lap mu_phi, M constant),
+    u = (sum e f + (F_s + F_b)/2) / (rho - (rho_H - rho_L) M lap mu_phi / 2)
+    (Eq. liang2014_velocity_update), F_a = (rho_H - rho_L) M lap mu_phi u, and
+    p as in Eq. liang_p_update."""
+    gl = p.lattices[0]
+    lap_mu = laplacian(p, mu_phi)
+    drho = (p.rho_H - p.rho_L) / (PHI_H - PHI_L)
+    Fs = mu_phi * grad
+    Fb = np.array([rho * p.gravity[a] + p.force[a] for a in range(3)])
+    j = np.zeros((3,) + phi.shape, dtype=st.g.dtype)
+    for i in range(gl.Q):
+        for a in range(3):
+            if gl.c[i][a] != 0:
+                j[a] = j[a] + gl.c[i][a] * st.g[i]
+    u = (j + 0.5 * (Fs + Fb)) / (rho - 0.5 * drho * p.M * lap_mu)
+    Fa = drho * p.M * lap_mu * u
+    moving = st.g[1].copy()
+    for i in range(2, gl.Q):
+        moving = moving + st.g[i]
+    w0 = gl.w[0]
+    pres = CS2 / (1 - w0) * (moving + 0.5 * _vdot(u, grad_rho) + rho * w0 * (-_vdot(u, u) / (2 * CS2)))
+    return dict(phi=phi, grad=grad, lap=lap, rho=rho, nu=nu, tau=tau, mu_phi=mu_phi,
+                pstar=pres / (rho * CS2), p=pres, F=Fs + Fa + Fb, u=u, grad_rho=grad_rho,
+                lap_mu=lap_mu, R=None, gamma=None)
+
+
 # --------------------------------------------------------------------------
 # collisions (O10, O11)
 
 def tau_phi(p):
     """Eq. fakhari_tau_model (AC) and its CH form of Sec. II.D.1."""
-    if p.model == "CH":
+    if p.model in ("CH", "L14"):
         return p.M / (p.eta * CS2) + 0.5
     return p.M / CS2 + 0.5
 
@@ -428,7 +478,7 @@ def tau_phi(p):
 def collide_h(p, st, m):
     """Eq. fakhari_g_simplified (BGK) for the phase-field populations."""
     tp = tau_phi(p)
-    if p.model == "CH":
+    if p.model in ("CH", "L14"):
         heq = h_eq_ch(p, m["phi"], m["mu_phi"], m["u"])
         phiu = m["phi"] * m["u"]
         G = G_ch(p, phiu - st.phiu_prev)       # backward Euler, delta t = 1
@@ -457,6 +507,9 @@ def collide_g(p, st, m):
     if p.model == "L18":
         geq = f_eq_liang(p, m["rho"], m["p"], m["u"])
         Fi = force_liang(p, m["F"], m["u"], m["grad_rho"])
+    elif p.model == "L14":
+        geq = f_eq_liang(p, m["rho"], m["p"], m["u"])
+        Fi = force_liang14(p, m["F"], m["u"], m["rho"], m["grad_rho"])
     else:
         geq = g_eq(p, m["pstar"], m["u"])
         Fi = force_populations(p, m["F"], m["rho"])
@@ -522,7 +575,7 @@ def step(p, st):
     else:
         h_post = collide_h(p, st, m)
         h_new = stream(p, p.lattices[1], h_post, "h")
-    phiu = m["phi"] * m["u"] if p.model in ("CH", "L18") else None
+    phiu = m["phi"] * m["u"] if p.model in ("CH", "L18", "L14") else None
     return State(g_new, h_new, phiu)
 
 
@@ -557,6 +610,9 @@ def init(p, phi0, u0=None, p0=None):
         return State(g, h_eq_nl(p, phi0, u0), None)
     if p.model == "L18":
         return State(f_eq_liang(p, rho0, p0, u0), h_eq_nl(p, phi0, u0), phi0 * u0)
+    if p.model == "L14":
+        mu0 = chemical_potential(p, phi0, laplacian(p, phi0))
+        return State(f_eq_liang(p, rho0, p0, u0), h_eq_ch(p, phi0, mu0, u0), phi0 * u0)
     return State(g, h_eq_ac(p, phi0, u0), None)
 
 
