@@ -130,22 +130,6 @@ def test_phase_conservation_droplet():
     assert abs(st.h.sum() - phi.sum()) < 1e-12 * phi.sum()
 
 
-def test_laplace_law_static_droplet():
-    """dp R / sigma converges to 0.946 (R = 10) and 0.938 (R = 14) within
-    4000 steps (the AC model gives 0.968); a surface force off by a factor
-    moves it by that factor."""
-    out = []
-    for R in (10.0, 14.0):
-        p = _p(nx=64, ny=64)
-        x, y = np.meshgrid(np.arange(64), np.arange(64))
-        phi = (0.5 + 0.5 * np.tanh(2 * (R - np.sqrt((x - 32) ** 2 + (y - 32) ** 2)) / p.W))[None]
-        st = om.run(p, om.init(p, phi), 4000)
-        d = om.diagnostics(p, st, centre=(32.0, 32.0), R=R)
-        out.append((d["p_in"] - d["p_out"]) * R / p.sigma)
-    for v in out:
-        assert abs(v - 1) < 0.08, out
-
-
 # ---------------------------------------------------------------- Liang2014 with its hydrodynamics
 @pytest.mark.parametrize("lat", ["D2Q9_D2Q5", "D3Q19_D3Q7", "D3Q27_D3Q7"])
 def test_liang14_force_moments(lat):
@@ -215,16 +199,16 @@ def test_liang14_fixed_point_and_shear_wave(lat):
     assert abs(-np.log(amp / 1e-3) / 300 / (nu * k * k) - 1) < 0.01
 
 
-def test_liang14_phase_conservation_and_laplace():
-    p = _p(model="L14", nx=64, ny=64)
+@pytest.mark.parametrize("model,expect", [("L18", 0.945), ("L14", 0.992)])
+def test_laplace_law_and_conservation(model, expect):
+    """Static droplet R = 10 (rho ratio 10), 2500 steps: dp R / sigma measured
+    0.945 (Liang2018) and 0.992 (Liang2014), converging to 0.946 and 0.996; a
+    surface force off by a factor moves it by that factor. sum phi kept."""
+    p = _p(model=model, nx=64, ny=64)
     x, y = np.meshgrid(np.arange(64), np.arange(64))
-    out = []
-    for R in (10.0, 14.0):
-        phi = (0.5 + 0.5 * np.tanh(2 * (R - np.sqrt((x - 32) ** 2 + (y - 32) ** 2)) / p.W))[None]
-        st = om.run(p, om.init(p, phi), 4000)
-        assert abs(st.h.sum() - phi.sum()) < 1e-11 * phi.sum()
-        d = om.diagnostics(p, st, centre=(32.0, 32.0), R=R)
-        out.append((d["p_in"] - d["p_out"]) * R / p.sigma)
-    # measured 0.996 (R = 10) and 0.998 (R = 14)
-    for v in out:
-        assert abs(v - 1) < 0.03, out
+    phi = (0.5 + 0.5 * np.tanh(2 * (10 - np.sqrt((x - 32) ** 2 + (y - 32) ** 2)) / p.W))[None]
+    st = om.run(p, om.init(p, phi), 2500)
+    assert abs(st.h.sum() - phi.sum()) < 1e-11 * phi.sum()
+    d = om.diagnostics(p, st, centre=(32.0, 32.0), R=10.0)
+    v = (d["p_in"] - d["p_out"]) * 10.0 / p.sigma
+    assert abs(v - expect) < 0.01 and abs(v - 1) < 0.08, v
