@@ -79,6 +79,12 @@ extern "C" {
                         hydrodynamics, Eqs. liang_feq, liang_F_final, liang_velocity_update,
                         liang_p_update. Stationary walls only; with fp16-stored g,
                         rho_H and rho_L <= 16 (f / w must fit the fp16 range) */
+#define PFLBM_L14 4  /* Liang2014 with its hydrodynamics (Sec. II.D.1): the CH phase field of
+                        PFLBM_CH with Eqs. liang2_feq, liang2_F (Gamma, s of Eq. Gamma_beta),
+                        F_a = (rho_H - rho_L) M lap(mu_phi) u, the velocity update of
+                        Eq. liang2014_velocity_update and the pressure of Eq. liang_p_update;
+                        a pass before each step stores mu_phi for its Laplacian. Same wall
+                        and fp16 limits as PFLBM_L18 */
 #define PFLBM_NL 2   /* nonlocal Allen-Cahn, Eqs. Chai_geq, chai_G (Chai2018), the source
                         blended with the conservative flux by lam as in Eq. Hu_G (Hu2019);
                         phi = sum h + (1 - lam) R / 2 (Eq. chai2018_phi_update), with the
@@ -109,7 +115,7 @@ extern "C" {
 
 typedef struct pflbm_params {
     int lattice;          /* PFLBM_D2Q9_D2Q5, PFLBM_D3Q19_D3Q7 or PFLBM_D3Q27_D3Q7 */
-    int model;            /* PFLBM_AC, PFLBM_CH, PFLBM_NL or PFLBM_L18 */
+    int model;            /* PFLBM_AC, PFLBM_CH, PFLBM_NL, PFLBM_L18 or PFLBM_L14 */
     int precision;        /* PFLBM_FP64 ... PFLBM_MIXED_BF16 */
     int nx, ny, nz;       /* nodes per axis, each >= 1; nz == 1 for 2-D */
     int bc[3];            /* PFLBM_PERIODIC or PFLBM_WALL per axis x, y, z */

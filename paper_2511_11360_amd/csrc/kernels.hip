@@ -8,10 +8,10 @@ namespace pfk {
 
 hipError_t launch_step(int lattice, int model, int precision, int mode, const KArgs& a, hipStream_t s) {
     using StepFn = hipError_t (*)(int, int, const KArgs&, hipStream_t);
-    static const StepFn fn[3][4] = {
-        {launch_step_p0_m0, launch_step_p0_m1, launch_step_p0_m2, launch_step_p0_m3},
-        {launch_step_p1_m0, launch_step_p1_m1, launch_step_p1_m2, launch_step_p1_m3},
-        {launch_step_p2_m0, launch_step_p2_m1, launch_step_p2_m2, launch_step_p2_m3}};
+    static const StepFn fn[3][5] = {
+        {launch_step_p0_m0, launch_step_p0_m1, launch_step_p0_m2, launch_step_p0_m3, launch_step_p0_m4},
+        {launch_step_p1_m0, launch_step_p1_m1, launch_step_p1_m2, launch_step_p1_m3, launch_step_p1_m4},
+        {launch_step_p2_m0, launch_step_p2_m1, launch_step_p2_m2, launch_step_p2_m3, launch_step_p2_m4}};
     return fn[lattice][model](precision, mode, a, s);
 }
 
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) void k_init(const InitArgs a) {
     using HS = typename Types<PREC>::HS;
     using GC = GCodec<PREC>;
     constexpr bool D3 = PAIR::dim == 3;
-    constexpr int HOFF = (MODEL != 1 && D3) ? 1 : 0;
+    constexpr int HOFF = rest_offset(MODEL, D3);
     constexpr int QHS = HL::Q - HOFF;
     const long long nn = (long long)a.nx * a.ny * a.nz;
     const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -87,8 +87,8 @@ __global__ __launch_bounds__(256) void k_init(const InitArgs a) {
         constexpr int i = I;
         const double cu = GL::c(i, 0) * u[0] + GL::c(i, 1) * u[1] + GL::c(i, 2) * u[2];
         double geq;
-        if constexpr (MODEL == 3) {
-            // Eq. liang_feq: (p/c_s^2)(w - [i = 0]) + rho w (3 c.u + 4.5 (c.u)^2 - 1.5 u.u)
+        if constexpr (MODEL == 3 || MODEL == 4) {
+            // Eqs. liang_feq / liang2_feq: (p/c_s^2)(w - [i = 0]) + rho w (3 c.u + 4.5 (c.u)^2 - 1.5 u.u)
             const double p0 = a.p0 ? a.p0[n] : 0.0;
             geq = 3.0 * p0 * (GL::w(i) - (i == 0 ? 1.0 : 0.0)) +
                   rho * GL::w(i) * (3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
@@ -166,7 +166,7 @@ __global__ __launch_bounds__(256) void k_get(const IOArgs a) {
     using HS = typename Types<PREC>::HS;
     using GC = GCodec<PREC>;
     constexpr bool D3 = PAIR::dim == 3;
-    constexpr int HOFF = (MODEL != 1 && D3) ? 1 : 0;
+    constexpr int HOFF = rest_offset(MODEL, D3);
     constexpr int QHS = HL::Q - HOFF;
     const long long nn = (long long)a.nx * a.ny * a.nz;
     const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(256) void k_set(const IOArgs a) {
     using HS = typename Types<PREC>::HS;
     using GC = GCodec<PREC>;
     constexpr bool D3 = PAIR::dim == 3;
-    constexpr int HOFF = (MODEL != 1 && D3) ? 1 : 0;
+    constexpr int HOFF = rest_offset(MODEL, D3);
     constexpr int QHS = HL::Q - HOFF;
     const long long nn = (long long)a.nx * a.ny * a.nz;
     const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -337,7 +337,8 @@ __global__ __launch_bounds__(256) void k_gamma_final(const double* __restrict__ 
             }                                                                                \
         };                                                                                   \
         auto mdl = [&](auto pair) {                                                          \
-            if (model == 3) prec(pair, std::integral_constant<int, 3>{});                    \
+            if (model == 4) prec(pair, std::integral_constant<int, 4>{});                    \
+            else if (model == 3) prec(pair, std::integral_constant<int, 3>{});               \
             else if (model == 2) prec(pair, std::integral_constant<int, 2>{});               \
             else if (model == 1) prec(pair, std::integral_constant<int, 1>{});               \
             else prec(pair, std::integral_constant<int, 0>{});                               \

@@ -27,7 +27,8 @@ struct Layout {
     int P = 0;                       // elements per population plane
     int ntx = 0, nty = 0, ntz = 0, zb = 0, nblocks = 0;   // 64 x 4 tiles (fields, diagnostics)
     int tile_step = 0, ntx_step = 0, nty_step = 0;        // tiles of the step kernel
-    size_t off_g[2] = {0, 0}, off_h[2] = {0, 0}, off_pu = 0, off_part = 0, off_gpart = 0, off_res = 0, total = 0;
+    size_t off_g[2] = {0, 0}, off_h[2] = {0, 0}, off_pu = 0, off_mu = 0, off_part = 0, off_gpart = 0, off_res = 0,
+           total = 0;
     size_t ck_g = 0, ck_h = 0, ck_pu = 0, ck_total = 0;
     size_t g_bytes = 0, h_bytes = 0, pu_bytes = 0;
 };
@@ -41,8 +42,9 @@ bool finite(double v) { return std::isfinite(v); }
 std::string validate(const pflbm_params& p) {
     if (p.lattice != PFLBM_D2Q9_D2Q5 && p.lattice != PFLBM_D3Q19_D3Q7 && p.lattice != PFLBM_D3Q27_D3Q7)
         return "lattice must be PFLBM_D2Q9_D2Q5, PFLBM_D3Q19_D3Q7 or PFLBM_D3Q27_D3Q7";
-    if (p.model != PFLBM_AC && p.model != PFLBM_CH && p.model != PFLBM_NL && p.model != PFLBM_L18)
-        return "model must be PFLBM_AC, PFLBM_CH, PFLBM_NL or PFLBM_L18";
+    if (p.model != PFLBM_AC && p.model != PFLBM_CH && p.model != PFLBM_NL && p.model != PFLBM_L18 &&
+        p.model != PFLBM_L14)
+        return "model must be PFLBM_AC, PFLBM_CH, PFLBM_NL, PFLBM_L18 or PFLBM_L14";
     if (p.precision < PFLBM_FP64 || p.precision > PFLBM_MIXED_BF16) return "unknown precision";
     if (p.nx < 1 || p.ny < 1 || p.nz < 1) return "nx, ny, nz must be >= 1";
     if (p.lattice == PFLBM_D2Q9_D2Q5 && p.nz != 1) return "2-D lattice requires nz == 1";
@@ -72,12 +74,12 @@ std::string validate(const pflbm_params& p) {
     if (!(p.s_other > 0 && p.s_other < 2)) return "s_other must be in (0, 2)";
     if (!(p.normal_eps >= 0) || !finite(p.normal_eps)) return "normal_eps must be >= 0";
     if (!(p.lam >= 0 && p.lam <= 1)) return "lam must be in [0, 1]";
-    if (p.model == PFLBM_L18) {
+    if (p.model == PFLBM_L18 || p.model == PFLBM_L14) {
         for (int s = 0; s < 2; ++s)
             for (int a = 0; a < 3; ++a)
-                if (p.wall_u[s][a] != 0.0) return "PFLBM_L18 supports stationary walls only";
+                if (p.wall_u[s][a] != 0.0) return "the Liang models support stationary walls only";
         if (p.precision == PFLBM_MIXED_FP16 && (p.rho_H > 16.0 || p.rho_L > 16.0))
-            return "PFLBM_L18 with fp16-stored g needs rho_H, rho_L <= 16";
+            return "the Liang models with fp16-stored g need rho_H, rho_L <= 16";
     }
     for (int a = 0; a < 3; ++a)
         if (!finite(p.gravity[a]) || !finite(p.force[a])) return "body force not finite";
@@ -94,7 +96,7 @@ Layout make_layout(const pflbm_params& p) {
     L.dim = d3 ? 3 : 2;
     L.Qg = p.lattice == PFLBM_D3Q27_D3Q7 ? 27 : (d3 ? 19 : 9);
     L.Qh = d3 ? 7 : 5;
-    L.Qhs = (d3 && p.model != PFLBM_CH) ? 6 : L.Qh;   // AC / NL / L18 on D3Q7: rest population is zero
+    L.Qhs = rest_offset(p.model, d3) ? 6 : L.Qh;   // D3Q7 rest population of weight 0 not stored
     L.sT = p.precision == PFLBM_FP64 ? 8 : 4;
     L.sg = p.precision == PFLBM_FP64 ? 8 : (p.precision == PFLBM_FP32 ? 4 : 2);
     L.sh = p.precision == PFLBM_FP64 ? 8 : 4;
@@ -133,7 +135,10 @@ Layout make_layout(const pflbm_params& p) {
         off = align_up(off + (size_t)L.Qhs * planes * L.sh, ALIGN);
     }
     L.off_pu = off;
-    if (p.model == PFLBM_CH || p.model == PFLBM_L18) off = align_up(off + 3 * planes * L.sT, ALIGN);
+    const bool has_pu = p.model == PFLBM_CH || p.model == PFLBM_L18 || p.model == PFLBM_L14;
+    if (has_pu) off = align_up(off + 3 * planes * L.sT, ALIGN);
+    L.off_mu = off;
+    if (p.model == PFLBM_L14) off = align_up(off + planes * L.sT, ALIGN);
     L.off_part = off;
     off = align_up(off + (size_t)L.nblocks * NDIAG * sizeof(double), ALIGN);
     L.off_gpart = off;   // nonlocal multiplier: per-256-node partial sums
@@ -148,7 +153,7 @@ Layout make_layout(const pflbm_params& p) {
     L.ck_g = 256;
     L.g_bytes = (size_t)L.Qg * planes * L.sg;
     L.h_bytes = (size_t)L.Qhs * planes * L.sh;
-    L.pu_bytes = (p.model == PFLBM_CH || p.model == PFLBM_L18) ? 3 * planes * L.sT : 0;
+    L.pu_bytes = has_pu ? 3 * planes * L.sT : 0;
     L.ck_h = align_up(L.ck_g + L.g_bytes, 256);
     L.ck_pu = align_up(L.ck_h + L.h_bytes, 256);
     L.ck_total = align_up(L.ck_pu + L.pu_bytes, 256);
@@ -222,6 +227,7 @@ void base_args(pflbm_t* h, KArgs& a) {
     a.hin = h->base + h->L.off_h[h->hcur];
     a.hout = h->base + h->L.off_h[1 - h->hcur];
     a.phiu = h->base + h->L.off_pu;
+    a.mu = h->base + h->L.off_mu;
     a.partials = (double*)(h->base + h->L.off_part);
     a.P = h->L.P;
     a.nx = h->p.nx;
@@ -261,10 +267,22 @@ int run_gamma(pflbm_t* h, KArgs& a) {
     return PFLBM_OK;
 }
 
+// Liang2014: mu_phi of the current state, for the Laplacian in the next launch
+int run_mu(pflbm_t* h, const KArgs& a) {
+    if (h->p.model != PFLBM_L14) return PFLBM_OK;
+    KArgs m = a;
+    m.tile = 0;
+    m.ntx = h->L.ntx;
+    m.nty = h->L.nty;
+    HIPCHK(h, launch_step(h->p.lattice, h->p.model, h->p.precision, MODE_MU, m, h->stream), "mu kernel");
+    return PFLBM_OK;
+}
+
 int run_diag(pflbm_t* h, const double* centre, double R, double* res) {
     KArgs a;
     base_args(h, a);
     if (int st = run_gamma(h, a)) return st;
+    if (int st = run_mu(h, a)) return st;
     if (centre) {
         a.has_centre = 1;
         for (int k = 0; k < h->L.dim; ++k) a.centre[k] = centre[k];
@@ -334,7 +352,8 @@ int pflbm_create(const pflbm_params* params, void* hip_stream, void* dev_state, 
     ph.kappa = 1.5 * p.sigma * p.W;          // kappa = 3 sigma W / 2
     ph.anti = 4.0 / p.W;                     // sqrt(2 beta / kappa)
     ph.eps2 = p.normal_eps * p.normal_eps;
-    const double tau_phi = p.model == PFLBM_CH ? 3.0 * p.M / p.eta + 0.5 : 3.0 * p.M + 0.5;
+    const bool ch_phase = p.model == PFLBM_CH || p.model == PFLBM_L14;
+    const double tau_phi = ch_phase ? 3.0 * p.M / p.eta + 0.5 : 3.0 * p.M + 0.5;
     ph.inv_tau_phi = 1.0 / tau_phi;
     ph.g_fac_phi = 1.0 - 0.5 / tau_phi;
     ph.eta = p.eta;
@@ -400,6 +419,7 @@ int pflbm_step(pflbm_t* h, int nsteps) {
         a.ntx = h->L.ntx_step;
         a.nty = h->L.nty_step;
         if ((st = run_gamma(h, a))) return st;
+        if ((st = run_mu(h, a))) return st;
         HIPCHK(h, launch_step(h->p.lattice, h->p.model, h->p.precision, MODE_STEP, a, h->stream), "step kernel");
         if (!h->p.freeze_phi) h->hcur ^= 1;
         h->gcur ^= 1;
@@ -428,6 +448,7 @@ int pflbm_fields(pflbm_t* h, double* phi, double* u, double* p, double* rho) {
     a.f_p = p;
     a.f_rho = rho;
     if ((st = run_gamma(h, a))) return st;
+    if ((st = run_mu(h, a))) return st;
     HIPCHK(h, launch_step(h->p.lattice, h->p.model, h->p.precision, MODE_FIELDS, a, h->stream), "fields kernel");
     return PFLBM_OK;
 }

@@ -172,10 +172,71 @@ __device__ __forceinline__ T nl_phi(const PhysT<T>& ph, T phis, T gam) {
     return phis + (T)0.5 * ((T)1 - ph.lam) * nl_source(ph, phis, gam);
 }
 
+// CH phase-field collision (Eqs. liang2_geq, liang2_G, backward-Euler
+// d(phi u)/dt): h* = (1 - 1/tau_phi) h + h_eq / tau_phi + (1 - 1/(2 tau_phi)) G.
+// Float forms close each node's phase-field mass balance (sum h* = sum h) on
+// the last population: the rounded weights do not sum to one.
+template <class HL, class T, class HSink>
+__device__ __forceinline__ void ch_collide(const PhysT<T>& ph, const T* h, T phi, const T* u, T mu_phi,
+                                           const T* pu_prev, T* pu_new, HSink&& hsink) {
+    const T itp = ph.inv_tau_phi, gfp = ph.g_fac_phi;
+    const T itp1 = (T)1 - itp;
+    T phis = (T)0;
+    unroll<HL::Q>([&](auto J) { phis += h[J]; });
+    constexpr bool CLOSE = sizeof(T) == 4;
+    T hacc = (T)0;
+    T pu[3], dpu[3];
+    unroll<3>([&](auto A) {
+        constexpr int a = A;
+        pu[a] = phi * u[a];
+        dpu[a] = pu[a] - pu_prev[a];
+        pu_new[a] = pu[a];
+    });
+    const T emu = ph.eta * mu_phi;
+    const T v0 = itp1 * h[0] + itp * (phi + ((T)HL::w(0) - (T)1) * emu);
+    if constexpr (CLOSE) hacc += v0;
+    hsink(std::integral_constant<int, 0>{}, v0);
+    unroll<HL::NP>([&](auto K) {
+        constexpr int al = HL::pf(K), o = HL::opp(al);
+        constexpr T w = (T)HL::w(al);
+        constexpr int ex = HL::c(al, 0), ey = HL::c(al, 1), ez = HL::c(al, 2);
+        T ep = (T)0, ed = (T)0;
+        if constexpr (ex != 0) { ep += (T)ex * pu[0]; ed += (T)ex * dpu[0]; }
+        if constexpr (ey != 0) { ep += (T)ey * pu[1]; ed += (T)ey * dpu[1]; }
+        if constexpr (ez != 0) { ep += (T)ez * pu[2]; ed += (T)ez * dpu[2]; }
+        const T base = itp * w * emu;
+        const T t = itp * ((T)3 * w * ep) + gfp * (T)3 * w * ed;
+        const T va = itp1 * h[al] + base + t, vo = itp1 * h[o] + base - t;
+        if constexpr (CLOSE) hacc += va;
+        hsink(std::integral_constant<int, al>{}, va);
+        if constexpr (CLOSE && decltype(K)::value == HL::NP - 1) {
+            hsink(std::integral_constant<int, o>{}, phis - hacc);
+        } else {
+            if constexpr (CLOSE) hacc += vo;
+            hsink(std::integral_constant<int, o>{}, vo);
+        }
+    });
+}
+
+// lap phi = 6 sum_i w_i (phi(x + c_i) - phi(x)) over opposite pairs (the same
+// order as the node update)
+template <class GL, class T>
+__device__ __forceinline__ T stencil_lap(const T* phin) {
+    const T phi = phin[0];
+    T lap = (T)0;
+    unroll<GL::NP>([&](auto K) {
+        constexpr int i = GL::pf(K), o = GL::opp(i);
+        lap += (T)(6.0 * GL::w(i)) * ((phin[i] - phi) + (phin[o] - phi));
+    });
+    return lap;
+}
+
+// muin: mu_phi at the stencil points (Liang2014 only; the model's MODE_MU pass
+// wrote it for every node), else unused.
 template <class PAIR, int MODEL, class T, bool COLLIDE, class GSink, class HSink>
 __device__ __forceinline__ void node_update(const PhysT<T>& ph, const T* g, const T* h, const T* phin,
-                                            const T* pu_prev, T* pu_new, NodeOut<T>& mo, const T gam,
-                                            GSink&& gsink, HSink&& hsink) {
+                                            const T* muin, const T* pu_prev, T* pu_new, NodeOut<T>& mo,
+                                            const T gam, GSink&& gsink, HSink&& hsink) {
     using GL = typename PAIR::G;
     using HL = typename PAIR::H;
     constexpr bool D3 = PAIR::dim == 3;
@@ -199,7 +260,9 @@ __device__ __forceinline__ void node_update(const PhysT<T>& ph, const T* g, cons
     const T irho = rcp(rho);
     const T nu = ph.visc_mu ? (ph.muL + phi * ph.dMu) * irho : ph.nuL + phi * ph.dNu;
     const T itau = rcp((T)3 * nu + (T)0.5);
-    const T mu_phi = ph.beta4 * phi * (phi - (T)1) * (phi - (T)0.5) - ph.kappa * lap;
+    T mu_phi;
+    if constexpr (MODEL == 4) mu_phi = muin[0];
+    else mu_phi = ph.beta4 * phi * (phi - (T)1) * (phi - (T)0.5) - ph.kappa * lap;
 
     // moments of g: p*, j, second moment (xx yy zz xy yz xz)
     T ps = g[0];
@@ -217,6 +280,107 @@ __device__ __forceinline__ void node_update(const PhysT<T>& ph, const T* g, cons
         if constexpr (cy * cz != 0) m2[4] += (T)(cy * cz) * s;
         if constexpr (cx * cz != 0) m2[5] += (T)(cx * cz) * s;
     });
+
+    if constexpr (MODEL == 4) {
+        // ---- Liang2014 hydrodynamics (Sec. II.D.1): F' = F_s + F_a + F_b with
+        // F_a = (rho_H - rho_L) M lap(mu_phi) u, u = (sum e f + (F_s + F_b)/2) /
+        // (rho - (rho_H - rho_L) M lap(mu_phi) / 2) (Eq. liang2014_velocity_update),
+        // p as Eq. liang_p_update; lap(mu_phi) from the mu ring (same stencil as phi)
+        const T lapmu = stencil_lap<GL>(muin);
+        const T dM = dRho * ph.mob * lapmu;
+        const T iden = rcp(rho - (T)0.5 * dM);
+        T Fp[3], u[3], grho[3], A[3];
+        unroll<3>([&](auto K) {
+            constexpr int a = K;
+            const T fsb = mu_phi * gr[a] + rho * ph.body[a] + ph.force[a];
+            u[a] = (j[a] + (T)0.5 * fsb) * iden;
+            Fp[a] = fsb + dM * u[a];
+            grho[a] = dRho * gr[a];
+            A[a] = (T)(1.0 / 3.0) * grho[a];          // grad(rho c_s^2)
+        });
+        const T udr = u[0] * grho[0] + u[1] * grho[1] + u[2] * grho[2];
+        const T usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        constexpr T w0 = (T)GL::w(0);
+        const T pres = (T)(1.0 / (3.0 * (1.0 - GL::w(0)))) *
+                       ((ps - g[0]) + (T)0.5 * udr - rho * w0 * (T)1.5 * usq);
+        mo.phi = phi;
+        mo.rho = rho;
+        mo.p = pres;
+        mo.u[0] = u[0];
+        mo.u[1] = u[1];
+        mo.u[2] = u[2];
+        if constexpr (!COLLIDE) return;
+
+        // ---- f collision: two-rate MRT, f_eq of Eq. liang2_feq, forcing of
+        // Eq. liang2_F, F_b = 3 (e - u).[Gamma grad(rho c_s^2) + F' s] with
+        // Gamma, s of Eq. Gamma_beta; its traceless second moment is that of
+        // B u + u B - 3 (u.B) u u with B = grad(rho c_s^2) + F'
+        const T so = ph.s_o;
+        const T so1 = (T)1 - so;
+        const T dS = itau - so;
+        const T fh = (T)1 - (T)0.5 * so;
+        const T p3 = (T)3 * pres;
+        T B[3];
+        unroll<3>([&](auto K) { constexpr int a = K; B[a] = A[a] + Fp[a]; });
+        const T uB = u[0] * B[0] + u[1] * B[1] + u[2] * B[2];
+        const T uA = u[0] * A[0] + u[1] * A[1] + u[2] * A[2];
+        const T uF = u[0] * Fp[0] + u[1] * Fp[1] + u[2] * Fp[2];
+        auto pi = [&](int a, int b, T m) {
+            return m - rho * u[a] * u[b] + (T)0.5 * (B[a] * u[b] + B[b] * u[a] - (T)3 * uB * u[a] * u[b]);
+        };
+        const T pxx = pi(0, 0, m2[0]), pyy = pi(1, 1, m2[1]), pzz = pi(2, 2, m2[2]);
+        const T pxy = pi(0, 1, m2[3]), pyz = pi(1, 2, m2[4]), pxz = pi(0, 2, m2[5]);
+        T A0, A1, Axy, Ayz, Axz;
+        if constexpr (D3) {
+            A0 = ((T)2 * pxx - pyy - pzz) * (T)(1.0 / stress_norm_diag0<GL, 3>());
+            A1 = (pyy - pzz) * (T)(1.0 / stress_norm_diag1<GL>());
+            Axy = pxy * (T)(1.0 / stress_norm_off<GL>());
+            Ayz = pyz * (T)(1.0 / stress_norm_off<GL>());
+            Axz = pxz * (T)(1.0 / stress_norm_off<GL>());
+        } else {
+            A0 = (pxx - pyy) * (T)(1.0 / stress_norm_diag0<GL, 2>());
+            A1 = (T)0;
+            Axy = pxy * (T)(1.0 / stress_norm_off<GL>());
+            Ayz = (T)0;
+            Axz = (T)0;
+        }
+        const T kin0 = rho * (T)(-1.5) * usq;
+        const T gam0 = w0 * (T)(-1.5) * usq;
+        const T F0 = (T)3 * (-uA * gam0 - uF * (w0 + gam0));
+        gsink(std::integral_constant<int, 0>{}, so1 * g[0] + so * (p3 * (w0 - (T)1) + w0 * kin0) + fh * F0);
+        unroll<GL::NP>([&](auto K) {
+            constexpr int i = GL::pf(K), o = GL::opp(i);
+            constexpr int cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
+            constexpr T w = (T)GL::w(i);
+            T cu = (T)0, cF = (T)0, cA = (T)0;
+            if constexpr (cx != 0) { cu += (T)cx * u[0]; cF += (T)cx * Fp[0]; cA += (T)cx * A[0]; }
+            if constexpr (cy != 0) { cu += (T)cy * u[1]; cF += (T)cy * Fp[1]; cA += (T)cy * A[1]; }
+            if constexpr (cz != 0) { cu += (T)cz * u[2]; cF += (T)cz * Fp[2]; cA += (T)cz * A[2]; }
+            T P = (T)0;
+            if constexpr (D3) {
+                constexpr int q0 = 3 * cx * cx - (cx * cx + cy * cy + cz * cz);
+                constexpr int q1 = cy * cy - cz * cz;
+                if constexpr (q0 != 0) P += (T)q0 * A0;
+                if constexpr (q1 != 0) P += (T)q1 * A1;
+                if constexpr (cx * cy != 0) P += (T)(cx * cy) * Axy;
+                if constexpr (cy * cz != 0) P += (T)(cy * cz) * Ayz;
+                if constexpr (cx * cz != 0) P += (T)(cx * cz) * Axz;
+            } else {
+                constexpr int q0 = cx * cx - cy * cy;
+                if constexpr (q0 != 0) P += (T)q0 * A0;
+                if constexpr (cx * cy != 0) P += (T)(cx * cy) * Axy;
+            }
+            const T E = w * (p3 + kin0 + rho * (T)4.5 * cu * cu);
+            const T O = w * (T)3 * rho * cu;
+            const T Ge = w * ((T)4.5 * cu * cu - (T)1.5 * usq), Go = w * (T)3 * cu;   // Gamma = Ge +/- Go
+            const T Fpl = (T)3 * ((cA - uA) * (Ge + Go) + (cF - uF) * (w + Ge + Go));
+            const T Fmi = (T)3 * ((-cA - uA) * (Ge - Go) + (-cF - uF) * (w + Ge - Go));
+            gsink(std::integral_constant<int, i>{}, so1 * g[i] + so * (E + O) + fh * Fpl - dS * P);
+            gsink(std::integral_constant<int, o>{}, so1 * g[o] + so * (E - O) + fh * Fmi - dS * P);
+        });
+        ch_collide<HL>(ph, h, phi, u, mu_phi, pu_prev, pu_new, hsink);
+        return;
+    }
 
     if constexpr (MODEL == 3) {
         // ---- Liang2018 (Sec. II.C): conservative-form hydrodynamics, F = F_s + F_b,
@@ -452,7 +616,7 @@ __device__ __forceinline__ void node_update(const PhysT<T>& ph, const T* g, cons
     const T itp = ph.inv_tau_phi, gfp = ph.g_fac_phi;
     const T itp1 = (T)1 - itp;
     // phi* = sum h, in the order of the halo fill
-    constexpr int HOFF = (MODEL != 1 && D3) ? 1 : 0;
+    constexpr int HOFF = rest_offset(MODEL, D3);
     T phis = (T)0;
     unroll<HL::Q - HOFF>([&](auto J) { phis += h[J + HOFF]; });
     // Float forms: the rounded weights do not sum to one (6 fl(1/6) = 1 + 3e-8),
@@ -516,29 +680,7 @@ __device__ __forceinline__ void node_update(const PhysT<T>& ph, const T* g, cons
                      itp1 * h[al] + base + t, itp1 * h[o] + base - t);
         });
     } else {
-        const T eta = ph.eta;
-        T pu[3], dpu[3];
-        unroll<3>([&](auto A) {
-            constexpr int a = A;
-            pu[a] = phi * u[a];
-            dpu[a] = pu[a] - pu_prev[a];
-            pu_new[a] = pu[a];
-        });
-        const T emu = eta * mu_phi;
-        put(std::integral_constant<int, 0>{}, itp1 * h[0] + itp * (phi + ((T)HL::w(0) - (T)1) * emu));
-        unroll<HL::NP>([&](auto K) {
-            constexpr int al = HL::pf(K), o = HL::opp(al);
-            constexpr T w = (T)HL::w(al);
-            constexpr int ex = HL::c(al, 0), ey = HL::c(al, 1), ez = HL::c(al, 2);
-            T ep = (T)0, ed = (T)0;
-            if constexpr (ex != 0) { ep += (T)ex * pu[0]; ed += (T)ex * dpu[0]; }
-            if constexpr (ey != 0) { ep += (T)ey * pu[1]; ed += (T)ey * dpu[1]; }
-            if constexpr (ez != 0) { ep += (T)ez * pu[2]; ed += (T)ez * dpu[2]; }
-            const T base = itp * w * emu;
-            const T t = itp * ((T)3 * w * ep) + gfp * (T)3 * w * ed;
-            put_pair(K, std::integral_constant<int, al>{}, std::integral_constant<int, o>{},
-                     itp1 * h[al] + base + t, itp1 * h[o] + base - t);
-        });
+        ch_collide<HL>(ph, h, phi, u, mu_phi, pu_prev, pu_new, hsink);
     }
 }
 
@@ -709,13 +851,16 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
     using GC = GCodec<PREC>;
     constexpr int QG = GL::Q, QH = HL::Q;
     constexpr bool D3 = PAIR::dim == 3;
-    constexpr int HOFF = (MODEL != 1 && D3) ? 1 : 0;   // AC / NL on D3Q7: zero-weight rest population not stored
+    constexpr int HOFF = rest_offset(MODEL, D3);        // zero-weight D3Q7 rest population not stored
     constexpr int QHS = QH - HOFF;
     constexpr int TX = TS == 0 ? 64 : (TS == 1 ? 128 : 256), TY = BLOCK / TX;
     constexpr int PW = TX + 2, PSZ = PW * (TY + 2);
     constexpr int NRING = 2 * PW + 2 * TY;             // halo ring of the tile
     constexpr int NPL = D3 ? 4 : 1;
     __shared__ T lphi[NPL * PSZ];
+    constexpr bool MUR = MODEL == 4 && MODE != MODE_MU;   // Liang2014: mu_phi ring beside phi
+    __shared__ T lmu[MUR ? NPL * PSZ : 1];
+    const T* __restrict__ MU = (const T*)a.mu;
 
     const int b = TS == 0 ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int bx = b % a.ntx, byz = b / a.ntx;
@@ -810,6 +955,15 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
             if constexpr (MODEL == 2) sr = nl_phi(ph, sr, gam);
             if (ring[k]) lphi[slot * PSZ + ring_lds[k]] = sr;
         }
+        if constexpr (MUR) {
+            // mu_phi of the same positions (ghosts: periodic image or wall mirror)
+            const size_t pb = (size_t)fz.zk[1] * P;
+            lmu[slot * PSZ + own_lds] = MU[pb + (unsigned)ocr.c];
+            for (int k = 0; k < NR; ++k) {
+                const T m = MU[pb + (unsigned)rcr[k].c];
+                if (ring[k]) lmu[slot * PSZ + ring_lds[k]] = m;
+            }
+        }
     };
 
     // stored g that the pull of plane z reads (storage form, not decoded)
@@ -831,9 +985,28 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
         });
     };
 
-    auto do_node = [&](int z, const GS* gr, const T* h, const T* pm, const T* p0, const T* pp) {
-        const ZPlanes zp = make_zplanes(z, nz, a.bc[2]);
+    // node update of plane z: slots sm, s0, sp hold planes z - 1, z, z + 1
+    auto do_node = [&](int z, const GS* gr, const T* h, int sm, int s0, int sp) {
+        const T* pm = lphi + sm * PSZ;
+        const T* p0 = lphi + s0 * PSZ;
+        const T* pp = lphi + sp * PSZ;
         const int o11 = cl.off[1][1];
+        if constexpr (MODE == MODE_MU) {
+            // Liang2014: mu_phi of this node for the step's halo (same stencil)
+            T phin[QG];
+            unroll<QG>([&](auto I) {
+                constexpr int i = I;
+                constexpr int cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
+                const T* pl_ = cz < 0 ? pm : (cz > 0 ? pp : p0);
+                phin[i] = pl_[(ly + 1 + cy) * PW + (lx + 1 + cx)];
+            });
+            const T phi = phin[0];
+            const T lap = stencil_lap<GL>(phin);
+            ((T*)a.mu)[(size_t)z * P + (unsigned)o11] =
+                ph.beta4 * phi * (phi - (T)1) * (phi - (T)0.5) - ph.kappa * lap;
+            return;
+        }
+        const ZPlanes zp = make_zplanes(z, nz, a.bc[2]);
         // post-streaming g of this node (pulled from x - c_i), decoded
         T g[QG];
         unroll<QG>([&](auto I) {
@@ -845,19 +1018,22 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
             }
         });
         T pu_prev[3] = {(T)0, (T)0, (T)0};
-        if constexpr (MODEL == 1 || MODEL == 3) {
+        if constexpr (MODEL == 1 || MODEL == 3 || MODEL == 4) {
             unroll<3>([&](auto A) {
                 constexpr int c = A;
                 pu_prev[c] = at<3>(PU, z, c, P, o11);
             });
         }
-        // phi at the stencil points
+        // phi (and, for Liang2014, mu_phi) at the stencil points
         T phin[QG];
+        T muin[MUR ? QG : 1];
         unroll<QG>([&](auto I) {
             constexpr int i = I;
             constexpr int cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
-            const T* pl_ = cz < 0 ? pm : (cz > 0 ? pp : p0);
-            phin[i] = pl_[(ly + 1 + cy) * PW + (lx + 1 + cx)];
+            const int sl = cz < 0 ? sm : (cz > 0 ? sp : s0);
+            const int off = (ly + 1 + cy) * PW + (lx + 1 + cx);
+            phin[i] = lphi[sl * PSZ + off];
+            if constexpr (MUR) muin[i] = lmu[sl * PSZ + off];
         });
         NodeOut<T> mo;
         T pu_new[3];
@@ -874,8 +1050,8 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
                     if (a.write_h) __builtin_nontemporal_store((HS)v, &at<QHS>(Hout, z, al - HOFF, P, o11));
                 }
             };
-            node_update<PAIR, MODEL, T, true>(ph, g, h, phin, pu_prev, pu_new, mo, gam, gsink, hsink);
-            if constexpr (MODEL == 1 || MODEL == 3) {
+            node_update<PAIR, MODEL, T, true>(ph, g, h, phin, muin, pu_prev, pu_new, mo, gam, gsink, hsink);
+            if constexpr (MODEL == 1 || MODEL == 3 || MODEL == 4) {
                 if (a.write_h) {
                     unroll<3>([&](auto A) {
                         constexpr int c = A;
@@ -885,7 +1061,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
             }
         } else {
             auto none = [](auto, T) {};
-            node_update<PAIR, MODEL, T, false>(ph, g, h, phin, pu_prev, pu_new, mo, gam, none, none);
+            node_update<PAIR, MODEL, T, false>(ph, g, h, phin, muin, pu_prev, pu_new, mo, gam, none, none);
             const size_t idx = ((size_t)z * ny + y) * nx + x;    // canonical index
             if constexpr (MODE == MODE_FIELDS) {
                 if (a.f_phi) a.f_phi[idx] = (double)mo.phi;
@@ -945,9 +1121,8 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
             fill_plane(z + 1, (r + 2) & 3);
             __syncthreads();
             if (active) {
-                pull_g(z, gr);
-                do_node(z, gr, hc, lphi + (r & 3) * PSZ, lphi + ((r + 1) & 3) * PSZ,
-                        lphi + ((r + 2) & 3) * PSZ);
+                if constexpr (MODE != MODE_MU) pull_g(z, gr);
+                do_node(z, gr, hc, r & 3, (r + 1) & 3, (r + 2) & 3);
             }
             unroll<QH>([&](auto J) { constexpr int al = J; hc[al] = hn[al]; });
         }
@@ -955,8 +1130,8 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
         fill_plane(0, 0);
         __syncthreads();
         if (active) {
-            pull_g(0, gr);
-            do_node(0, gr, hn, lphi, lphi, lphi);
+            if constexpr (MODE != MODE_MU) pull_g(0, gr);
+            do_node(0, gr, hn, 0, 0, 0);
         }
     }
     if constexpr (MODE == MODE_DIAG) {
@@ -988,6 +1163,12 @@ inline hipError_t step_mode(int mode, const KArgs& a, hipStream_t s) {
             break;
         case MODE_FIELDS:
             hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_FIELDS, 1, 0>), grid, block, 0, s, a);
+            break;
+        case MODE_MU:
+            if constexpr (MODEL == 4)
+                hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_MU, 1, 0>), grid, block, 0, s, a);
+            else
+                return hipErrorInvalidValue;
             break;
         default:
             hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_DIAG, 1, 0>), grid, block, 0, s, a);

@@ -1,6 +1,7 @@
 // One instantiation set of the step kernel: lattice pair PFK_PAIR (0: D2Q9 +
 // D2Q5, 1: D3Q19 + D3Q7, 2: D3Q27 + D3Q7) and model PFK_MODEL (0: AC, 1: CH, 2:
-// nonlocal, 3: Liang2018), every storage form, mode and tile. The build compiles this file
+// nonlocal, 3: Liang2018, 4: Liang2014 with its hydrodynamics), every storage
+// form, mode and tile. The build compiles this file
 // once per pair and model, in parallel.
 #include "step.h"
 

@@ -22,7 +22,8 @@ PFLBM_AC = 0
 PFLBM_CH = 1
 PFLBM_NL = 2
 PFLBM_L18 = 3
-MODELS = {"AC": PFLBM_AC, "CH": PFLBM_CH, "NL": PFLBM_NL, "L18": PFLBM_L18}
+PFLBM_L14 = 4
+MODELS = {"AC": PFLBM_AC, "CH": PFLBM_CH, "NL": PFLBM_NL, "L18": PFLBM_L18, "L14": PFLBM_L14}
 PFLBM_FP64 = 0
 PFLBM_FP32 = 1
 PFLBM_MIXED_FP16 = 2

@@ -113,3 +113,43 @@ def test_liang_rejects_moving_walls_and_fp16_range():
     d2 = wl.base_params(model="L18", rho_H=100.0)
     assert P.lib().pflbm_state_bytes(ctypes.byref(P.make_params(d2, "mixed_fp16")), ctypes.byref(n)) == P.PFLBM_EINVAL
     assert P.lib().pflbm_state_bytes(ctypes.byref(P.make_params(d2, "mixed_bf16")), ctypes.byref(n)) == 0
+
+
+# ---------------------------------------------------------------- Liang2014 with its hydrodynamics
+def test_liang14_static_droplet_2d_1000_fields():
+    d, phi, u = wl.static_droplet_2d()
+    d["model"] = "L14"
+    s, p, st = _check(d, phi, u, 1000, "static droplet 2-D Liang2014")
+    f_phi, f_u, f_p, f_rho = [a.cpu().numpy() for a in s.fields()]
+    o_phi, o_u, o_p, o_rho = om.fields(p, st)
+    assert np.abs(f_phi - o_phi).max() <= TOL and np.abs(f_u - o_u).max() <= TOL
+    assert np.abs(f_p - o_p).max() <= TOL
+    dg, do = s.volume(centre=(32.0, 32.0), R=16.0), om.diagnostics(p, st, centre=(32.0, 32.0), R=16.0)
+    assert abs(dg["p_in"] - do["p_in"]) <= TOL and abs(dg["p_out"] - do["p_out"]) <= TOL
+
+
+def test_liang14_rayleigh_taylor_walls():
+    d, phi, u = wl.rayleigh_taylor_2d(model="L14", nx=70, ny=90)
+    _check(d, phi, u, 501, "RT 2-D walls Liang2014")
+
+
+@pytest.mark.parametrize("lattice,tile,steps", [("D3Q19_D3Q7", "auto", 300), ("D3Q19_D3Q7", "256x1", 300),
+                                                ("D3Q27_D3Q7", "128x2", 200)])
+def test_liang14_3d_vortex_droplet(lattice, tile, steps):
+    d, phi, u = small_3d(model="L14", lattice=lattice, s_other=1.3)
+    _check(d, phi, u, steps, "3-D vortex droplet Liang2014 " + lattice, tile=tile, zblock=5)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "mixed_fp16"])
+def test_liang14_reduced_forms(precision):
+    d, phi, u = small_3d(model="L14")
+    ref = gpu_run(d, phi, u, 400)
+    s = gpu_run(d, phi, u, 400, precision=precision)
+    fr = [a.cpu().numpy() for a in ref.fields()]
+    fs = [a.cpu().numpy() for a in s.fields()]
+    e_phi = np.linalg.norm(fs[0] - fr[0]) / np.linalg.norm(fr[0])
+    e_u = np.linalg.norm(fs[1] - fr[1]) / np.linalg.norm(fr[1])
+    drift = abs(fs[0].sum() - phi.sum()) / phi.sum()
+    _say("  Liang2014 %s: rel L2 phi %.2e u %.2e, sum phi drift %.2e" % (precision, e_phi, e_u, drift))
+    assert drift < 2e-6
+    assert e_phi < 1e-4 and e_u < (1e-4 if precision == "fp32" else 2e-3)
