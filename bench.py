@@ -29,13 +29,18 @@ def bytes_per_update(d, precision):
     read once and written once (AC, the nonlocal model and Liang2018 on D3Q7
     store 6 phase-field populations; CH and Liang2018 also carry the 3
     components of (phi u); the nonlocal model reads the phase-field
-    populations once more for the global sums of its multiplier)."""
+    populations once more for the global sums of its multiplier; Liang2014
+    also carries (phi u) and reads h once more in its mu_phi pass, which
+    writes mu_phi for the step to read)."""
     d3 = d["lattice"] != "D2Q9_D2Q5"
     qg = {"D2Q9_D2Q5": 9, "D3Q19_D3Q7": 19, "D3Q27_D3Q7": 27}[d["lattice"]]
-    qh = (7 if d["model"] == "CH" else 6) if d3 else 5
+    qh = (7 if d["model"] in ("CH", "L14") else 6) if d3 else 5
     sg = {"fp64": 8, "fp32": 4, "mixed_fp16": 2, "mixed_bf16": 2}[precision]
     sh = 8 if precision == "fp64" else 4
-    extra = 2 * 3 * (8 if precision == "fp64" else 4) if d["model"] in ("CH", "L18") else 0
+    st = 8 if precision == "fp64" else 4
+    extra = 2 * 3 * st if d["model"] in ("CH", "L18", "L14") else 0
+    if d["model"] == "L14":
+        extra += qh * sh + 2 * st        # mu_phi pass: h read, mu written; the step reads mu
     if d["model"] == "NL":
         extra += qh * sh
     return 2 * (qg * sg + qh * sh) + extra
@@ -198,6 +203,7 @@ def main():
     if not args.no_models:
         for key, extra in (("CH", {"model": "CH"}), ("NL_lam0", {"model": "NL", "lam": 0.0}),
                            ("NL_lam0.9", {"model": "NL", "lam": 0.9}), ("L18", {"model": "L18"}),
+                           ("L14", {"model": "L14"}),
                            ("AC_D3Q27", {"lattice": "D3Q27_D3Q7"})):
             dm = dict(d, **extra)
             print("bench: model %s" % key, file=sys.stderr, flush=True)
