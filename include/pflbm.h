@@ -99,11 +99,12 @@ extern "C" {
 
 /* step-kernel tile: x nodes by y rows per 256-thread workgroup (3-D; the
    2-D lattice always uses 64 x 4) */
-#define PFLBM_TILE_AUTO   0  /* 64x4 for the fp16/bf16-stored forms, 256x1 for
+#define PFLBM_TILE_AUTO   0  /* 256x4 for the fp16/bf16-stored forms, 256x1 for
                                 fp32, 128x2 for fp64 (narrower when nx is) */
 #define PFLBM_TILE_64x4   1  /* workgroups ordered so each XCD sweeps a contiguous run */
 #define PFLBM_TILE_128x2  2  /* hardware workgroup order */
 #define PFLBM_TILE_256x1  3  /* hardware workgroup order */
+#define PFLBM_TILE_256x4  4  /* 1024-thread workgroups, ordered as 64x4 */
 
 /* boundary per axis */
 #define PFLBM_PERIODIC 0

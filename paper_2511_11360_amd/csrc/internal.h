@@ -7,10 +7,13 @@
 
 namespace pfk {
 
-constexpr int BLOCK = 256;      // threads per step workgroup
-// step tiles (x nodes, y rows) by tile index; fields / diagnostics use tile 0
-constexpr int TILE_NX[3] = {64, 128, 256};
-constexpr int TILE_NY[3] = {4, 2, 1};
+constexpr int BLOCK = 256;      // threads per workgroup (step tiles 0-2, reductions)
+// step tiles (x nodes, y rows, threads) by tile index; fields / diagnostics
+// use tile 0; tile 3 is a 1024-thread workgroup
+constexpr int NTILES = 4;
+constexpr int TILE_NX[NTILES] = {64, 128, 256, 256};
+constexpr int TILE_NY[NTILES] = {4, 2, 1, 4};
+constexpr int TILE_THREADS[NTILES] = {256, 256, 256, 1024};
 constexpr int NDIAG = 12;       // per-block partial diagnostics (see kernels.hip)
 constexpr int GAMMA_ZB = 16;    // z planes per workgroup of the nonlocal multiplier sums
 constexpr int MAXQ = 27;

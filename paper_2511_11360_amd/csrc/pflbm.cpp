@@ -86,7 +86,7 @@ std::string validate(const pflbm_params& p) {
     if (p.lattice == PFLBM_D2Q9_D2Q5 && (p.gravity[2] != 0.0 || p.force[2] != 0.0)) return "2-D body force has a z component";
     if (p.check_interval < 0) return "check_interval must be >= 0";
     if (p.zblock < 0) return "zblock must be >= 0";
-    if (p.tile < PFLBM_TILE_AUTO || p.tile > PFLBM_TILE_256x1) return "unknown tile";
+    if (p.tile < PFLBM_TILE_AUTO || p.tile > PFLBM_TILE_256x4) return "unknown tile";
     return "";
 }
 
@@ -106,13 +106,14 @@ Layout make_layout(const pflbm_params& p) {
     L.ntx = (p.nx + TILE_NX[0] - 1) / TILE_NX[0];
     L.nty = (p.ny + TILE_NY[0] - 1) / TILE_NY[0];
     // step tile: measured fastest per storage form on the 256^3 droplet case
-    // (fp16 / bf16-stored g: 64 x 4 in XCD runs; fp32: 256 x 1; fp64: 128 x 2);
+    // (fp16 / bf16-stored g: 256 x 4 in XCD runs; fp32: 256 x 1; fp64: 128 x 2);
     // no wider than nx needs
     int t = 0;
     if (d3) {
         if (p.tile != PFLBM_TILE_AUTO) t = p.tile - PFLBM_TILE_64x4;
         else if (p.precision == PFLBM_FP32) t = p.nx >= 256 ? 2 : (p.nx > 64 ? 1 : 0);
         else if (p.precision == PFLBM_FP64) t = p.nx > 64 ? 1 : 0;
+        else t = p.nx >= 256 ? 3 : 0;
     }
     L.tile_step = t;
     L.ntx_step = (p.nx + TILE_NX[t] - 1) / TILE_NX[t];

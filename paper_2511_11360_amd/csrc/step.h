@@ -838,11 +838,12 @@ __device__ __forceinline__ T pull_h(const HS* __restrict__ H, const Cross& X, co
 }
 
 // WALLS = 0: every axis periodic (no bounce-back selects are compiled).
-// TS: tile shape, TX x TY nodes per workgroup: 0 = 64 x 4 with workgroups
-// ordered so each XCD sweeps a contiguous run of tiles, 1 = 128 x 2 and
-// 2 = 256 x 1 in hardware order.
+// TS: tile shape, TX x TY nodes per workgroup of NT threads (one node each):
+// 0 = 64 x 4 and 3 = 256 x 4 (1024 threads) with workgroups ordered so each
+// XCD sweeps a contiguous run of tiles, 1 = 128 x 2 and 2 = 256 x 1 in
+// hardware order.
 template <class PAIR, int MODEL, int PREC, int MODE, int WALLS, int TS>
-__global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
+__global__ __launch_bounds__(TILE_THREADS[TS]) void k_step(const KArgs a) {
     using GL = typename PAIR::G;
     using HL = typename PAIR::H;
     using T = typename Types<PREC>::T;
@@ -853,7 +854,9 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
     constexpr bool D3 = PAIR::dim == 3;
     constexpr int HOFF = rest_offset(MODEL, D3);        // zero-weight D3Q7 rest population not stored
     constexpr int QHS = QH - HOFF;
-    constexpr int TX = TS == 0 ? 64 : (TS == 1 ? 128 : 256), TY = BLOCK / TX;
+    constexpr int NT = TILE_THREADS[TS];
+    constexpr int TX = TILE_NX[TS], TY = TILE_NY[TS];
+    static_assert(TX * TY == NT, "one node per thread");
     constexpr int PW = TX + 2, PSZ = PW * (TY + 2);
     constexpr int NRING = 2 * PW + 2 * TY;             // halo ring of the tile
     constexpr int NPL = D3 ? 4 : 1;
@@ -862,7 +865,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
     __shared__ T lmu[MUR ? NPL * PSZ : 1];
     const T* __restrict__ MU = (const T*)a.mu;
 
-    const int b = TS == 0 ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int b = (TS == 0 || TS == 3) ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int bx = b % a.ntx, byz = b / a.ntx;
     const int by = byz % a.nty, bz = byz / a.nty;
     const int x0 = bx * TX, y0 = by * TY;
@@ -900,13 +903,13 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
         for (int dy = 0; dy < 3; ++dy)
             for (int dx = 0; dx < 3; ++dx) cl.off[dy][dx] = oy[dy] * nx + ox[dx];
     }
-    // halo ring positions this thread fills (ring index threadIdx.x + k BLOCK)
-    constexpr int NR = (NRING + BLOCK - 1) / BLOCK;
+    // halo ring positions this thread fills (ring index threadIdx.x + k NT)
+    constexpr int NR = (NRING + NT - 1) / NT;
     Cross rcr[NR];
     int ring_lds[NR];
     bool ring[NR];
     for (int k = 0; k < NR; ++k) {
-        const int r = threadIdx.x + k * BLOCK;
+        const int r = threadIdx.x + k * NT;
         ring[k] = r < NRING;
         int hx = 0, hy = 0;
         if (r < PW) { hx = r - 1; hy = -1; }
@@ -1142,7 +1145,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(const KArgs a) {
 
 template <class PAIR, int MODEL, int PREC>
 inline hipError_t step_mode(int mode, const KArgs& a, hipStream_t s) {
-    const dim3 grid((unsigned)(a.ntx * a.nty * a.ntz)), block(BLOCK);
+    const dim3 grid((unsigned)(a.ntx * a.nty * a.ntz)), block(TILE_THREADS[a.tile]);
     const bool walls = a.wall_axis >= 0;
     switch (mode) {
         case MODE_STEP:
@@ -1155,6 +1158,11 @@ inline hipError_t step_mode(int mode, const KArgs& a, hipStream_t s) {
                 if (a.tile == 2) {
                     if (walls) hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_STEP, 1, 2>), grid, block, 0, s, a);
                     else hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_STEP, 0, 2>), grid, block, 0, s, a);
+                    break;
+                }
+                if (a.tile == 3) {
+                    if (walls) hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_STEP, 1, 3>), grid, block, 0, s, a);
+                    else hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_STEP, 0, 3>), grid, block, 0, s, a);
                     break;
                 }
             }
