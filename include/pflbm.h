@@ -99,8 +99,9 @@ extern "C" {
 
 /* step-kernel tile: x nodes by y rows per 256-thread workgroup (3-D; the
    2-D lattice always uses 64 x 4) */
-#define PFLBM_TILE_AUTO   0  /* 256x4 for the fp16/bf16-stored forms, 256x1 for
-                                fp32, 128x2 for fp64 (narrower when nx is) */
+#define PFLBM_TILE_AUTO   0  /* 256x4 for the fp16/bf16-stored forms on D3Q19
+                                (64x4 for D3Q27 and PFLBM_L14), 256x1 for fp32,
+                                128x2 for fp64 (narrower when nx is) */
 #define PFLBM_TILE_64x4   1  /* workgroups ordered so each XCD sweeps a contiguous run */
 #define PFLBM_TILE_128x2  2  /* hardware workgroup order */
 #define PFLBM_TILE_256x1  3  /* hardware workgroup order */

@@ -106,14 +106,16 @@ Layout make_layout(const pflbm_params& p) {
     L.ntx = (p.nx + TILE_NX[0] - 1) / TILE_NX[0];
     L.nty = (p.ny + TILE_NY[0] - 1) / TILE_NY[0];
     // step tile: measured fastest per storage form on the 256^3 droplet case
-    // (fp16 / bf16-stored g: 256 x 4 in XCD runs; fp32: 256 x 1; fp64: 128 x 2);
-    // no wider than nx needs
+    // (fp16 / bf16-stored g: 256 x 4 in XCD runs on D3Q19, else 64 x 4;
+    // fp32: 256 x 1; fp64: 128 x 2); no wider than nx needs
     int t = 0;
     if (d3) {
         if (p.tile != PFLBM_TILE_AUTO) t = p.tile - PFLBM_TILE_64x4;
         else if (p.precision == PFLBM_FP32) t = p.nx >= 256 ? 2 : (p.nx > 64 ? 1 : 0);
         else if (p.precision == PFLBM_FP64) t = p.nx > 64 ? 1 : 0;
-        else t = p.nx >= 256 ? 3 : 0;
+        // 256 x 4 (1024 threads) allows 128 registers per thread: the D3Q27 and
+        // Liang2014 kernels need more and run faster in 64 x 4
+        else t = (p.nx >= 256 && p.lattice == PFLBM_D3Q19_D3Q7 && p.model != PFLBM_L14) ? 3 : 0;
     }
     L.tile_step = t;
     L.ntx_step = (p.nx + TILE_NX[t] - 1) / TILE_NX[t];
