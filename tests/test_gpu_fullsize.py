@@ -90,3 +90,39 @@ def test_full_size_phase_conservation_fp64():
     _say("  sum phi 256^3, 100 steps: rel change %.3e" % rel)
     assert rel < 1e-12
     assert v1["unstable"] == 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed_fp16"])
+def test_full_size_d3q27_step_on_sampled_nodes(precision):
+    """The same sampled check on D3Q27 hydrodynamics at 256^3 (the bench's
+    D3Q27 line): a 5^3 periodic block around each sampled node, stepped by the
+    oracle, against the HIP step there."""
+    from paper_2511_11360_amd.solver import Solver
+    d, phi, u = wl.taylor_green_droplet_3d(n=N, We=10.0)
+    d["lattice"] = "D3Q27_D3Q7"
+    s = Solver(d, precision=precision)
+    s.init(phi, u)
+    s.step(20)
+    g0, h0 = s.get_distributions()
+    s.step(1)
+    g1, h1 = s.get_distributions()
+    p = om.Params(**dict(d, nx=5, ny=5, nz=5))
+    rng = np.random.default_rng(27)
+    w = p.lattices[0].w
+    worst = 0.0
+    for (x, y, z) in _samples(rng, 30):
+        st = om.State(_block(g0, z, y, x), _block(h0, z, y, x))
+        out = om.step(p, st)
+        got_g = g1[:, z, y, x].cpu().numpy()
+        got_h = h1[:, z, y, x].cpu().numpy()
+        if precision == "fp64":
+            e = max(np.max(np.abs(got_g - out.g[:, 2, 2, 2])), np.max(np.abs(got_h - out.h[:, 2, 2, 2])))
+            assert e <= 1e-14, ((x, y, z), e)
+        else:
+            eg = np.max(np.abs(got_g - out.g[:, 2, 2, 2]) / w / (2.0 ** -10 * np.abs(out.g[:, 2, 2, 2] / w)
+                                                               + 2.0 ** -24 + 1e-6))
+            eh = np.max(np.abs(got_h - out.h[:, 2, 2, 2]) / (2e-6 * np.abs(out.h[:, 2, 2, 2]) + 1e-7))
+            e = max(eg, eh)
+            assert e <= 1.0, ((x, y, z), eg, eh)
+        worst = max(worst, e)
+    _say("  D3Q27 %s 256^3 sampled step: worst %.3e" % (precision, worst))
