@@ -142,7 +142,9 @@ typedef struct pflbm_params {
     int freeze_phi;       /* nonzero: h (hence phi) is not updated (Sec. III.D) */
     int check_interval;   /* every this many steps pflbm_step checks for NaN/Inf
                              or rho <= 0 (synchronising); 0 = never */
-    int zblock;           /* z planes per workgroup, 0 = automatic (tuning only) */
+    int zblock;           /* z planes per workgroup, 0 = automatic: the step kernel
+                             then sizes its grid from the device occupancy
+                             (tuning only) */
     int tile;             /* step-kernel tile, PFLBM_TILE_* (tuning only: results
                              do not depend on it) */
 } pflbm_params;

@@ -27,6 +27,7 @@ struct Layout {
     int P = 0;                       // elements per population plane
     int ntx = 0, nty = 0, ntz = 0, zb = 0, nblocks = 0;   // 64 x 4 tiles (fields, diagnostics)
     int tile_step = 0, ntx_step = 0, nty_step = 0;        // tiles of the step kernel
+    int zb_step = 0, ntz_step = 0;                        // z blocks of the step kernel
     size_t off_g[2] = {0, 0}, off_h[2] = {0, 0}, off_pu = 0, off_mu = 0, off_part = 0, off_gpart = 0, off_res = 0,
            total = 0;
     size_t ck_g = 0, ck_h = 0, ck_pu = 0, ck_total = 0;
@@ -128,6 +129,8 @@ Layout make_layout(const pflbm_params& p) {
     }
     L.ntz = (p.nz + L.zb - 1) / L.zb;
     L.nblocks = L.ntx * L.nty * L.ntz;
+    L.zb_step = L.zb;   // refined at create time when zblock is automatic
+    L.ntz_step = L.ntz;
     size_t off = 0;
     for (int k = 0; k < 2; ++k) {
         L.off_g[k] = off;
@@ -223,6 +226,37 @@ int guard(pflbm_t* h) {
     return PFLBM_OK;
 }
 
+// z planes per step workgroup when the caller leaves zblock at 0. A workgroup
+// marches its column plane by plane and first loads the halo planes of its
+// phi ring; with one resident workgroup per compute unit (the 1024-thread
+// tile) nothing hides that start, so the grid is sized to fill every unit
+// once. With several resident workgroups: 32 planes while that still leaves
+// two rounds of work, else halving down to 8. The fields and diagnostics
+// kernels keep the layout's depth (their partial sums are sized by it).
+void choose_step_zblock(pflbm_t* h) {
+    Layout& L = h->L;
+    if (L.dim != 3 || h->p.zblock != 0 || h->device < 0) return;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess) return;
+    const int occ = occupancy_step(h->p.lattice, h->p.model, h->p.precision, L.tile_step, h->wall_axis >= 0);
+    if (cus <= 0 || occ <= 0) return;
+    const long long slots = (long long)cus * occ;
+    const long long tiles = (long long)L.ntx_step * L.nty_step;
+    const int nz = h->p.nz;
+    int zb;
+    if (occ == 1) {
+        const long long nzb = slots / tiles > 1 ? slots / tiles : 1;
+        zb = (int)((nz + nzb - 1) / nzb);
+        if (zb < 4) zb = 4;
+    } else {
+        zb = 32;
+        while (zb > 8 && tiles * ((nz + zb - 1) / zb) < 2 * slots) zb /= 2;
+    }
+    if (zb > nz) zb = nz;
+    L.zb_step = zb;
+    L.ntz_step = (nz + zb - 1) / zb;
+}
+
 void base_args(pflbm_t* h, KArgs& a) {
     std::memset(&a, 0, sizeof(a));
     a.gin = h->base + h->L.off_g[h->gcur];
@@ -277,6 +311,8 @@ int run_mu(pflbm_t* h, const KArgs& a) {
     m.tile = 0;
     m.ntx = h->L.ntx;
     m.nty = h->L.nty;
+    m.ntz = h->L.ntz;
+    m.zb = h->L.zb;
     HIPCHK(h, launch_step(h->p.lattice, h->p.model, h->p.precision, MODE_MU, m, h->stream), "mu kernel");
     return PFLBM_OK;
 }
@@ -340,6 +376,7 @@ int pflbm_create(const pflbm_params* params, void* hip_stream, void* dev_state, 
     const pflbm_params& p = h->p;
     for (int a = 0; a < 3; ++a)
         if (p.bc[a] == PFLBM_WALL) h->wall_axis = a;
+    choose_step_zblock(h);
     if (p.lattice == PFLBM_D2Q9_D2Q5) wall_terms<D2Q9>(p, h->gcorr);
     else if (p.lattice == PFLBM_D3Q19_D3Q7) wall_terms<D3Q19>(p, h->gcorr);
     else wall_terms<D3Q27>(p, h->gcorr);
@@ -421,6 +458,8 @@ int pflbm_step(pflbm_t* h, int nsteps) {
         a.tile = h->L.tile_step;
         a.ntx = h->L.ntx_step;
         a.nty = h->L.nty_step;
+        a.ntz = h->L.ntz_step;
+        a.zb = h->L.zb_step;
         if ((st = run_gamma(h, a))) return st;
         if ((st = run_mu(h, a))) return st;
         HIPCHK(h, launch_step(h->p.lattice, h->p.model, h->p.precision, MODE_STEP, a, h->stream), "step kernel");

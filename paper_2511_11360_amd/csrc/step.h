@@ -1184,6 +1184,35 @@ inline hipError_t step_mode(int mode, const KArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// resident workgroups per compute unit of the 3-D step kernel with this tile
+// (0 when the runtime cannot say)
+template <class PAIR, int MODEL, int PREC, int WALLS>
+inline int step_occupancy_walls(int tile) {
+    int n = 0;
+    hipError_t e = hipErrorInvalidValue;
+    const int bs = TILE_THREADS[tile];
+    if constexpr (PAIR::dim == 3) {
+        switch (tile) {
+            case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<PAIR, MODEL, PREC, MODE_STEP, WALLS, 0>, bs, 0); break;
+            case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<PAIR, MODEL, PREC, MODE_STEP, WALLS, 1>, bs, 0); break;
+            case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<PAIR, MODEL, PREC, MODE_STEP, WALLS, 2>, bs, 0); break;
+            case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<PAIR, MODEL, PREC, MODE_STEP, WALLS, 3>, bs, 0); break;
+            default: break;
+        }
+    }
+    return e == hipSuccess ? n : 0;
+}
+
+template <class PAIR, int MODEL>
+inline int step_occupancy(int prec, int tile, int walls) {
+    switch (prec) {
+        case 0: return walls ? step_occupancy_walls<PAIR, MODEL, 0, 1>(tile) : step_occupancy_walls<PAIR, MODEL, 0, 0>(tile);
+        case 1: return walls ? step_occupancy_walls<PAIR, MODEL, 1, 1>(tile) : step_occupancy_walls<PAIR, MODEL, 1, 0>(tile);
+        case 2: return walls ? step_occupancy_walls<PAIR, MODEL, 2, 1>(tile) : step_occupancy_walls<PAIR, MODEL, 2, 0>(tile);
+        default: return walls ? step_occupancy_walls<PAIR, MODEL, 3, 1>(tile) : step_occupancy_walls<PAIR, MODEL, 3, 0>(tile);
+    }
+}
+
 template <class PAIR, int MODEL>
 inline hipError_t step_prec(int prec, int mode, const KArgs& a, hipStream_t s) {
     switch (prec) {
