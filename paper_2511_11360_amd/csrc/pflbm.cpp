@@ -106,17 +106,19 @@ Layout make_layout(const pflbm_params& p) {
     const size_t planes = (size_t)p.nz * L.P;
     L.ntx = (p.nx + TILE_NX[0] - 1) / TILE_NX[0];
     L.nty = (p.ny + TILE_NY[0] - 1) / TILE_NY[0];
-    // step tile: measured fastest per storage form on the 256^3 droplet case
-    // (fp16 / bf16-stored g: 256 x 4 in XCD runs on D3Q19, else 64 x 4;
-    // fp32: 256 x 1; fp64: 128 x 2); no wider than nx needs
+    // step tile: measured fastest per storage form on the 256^3 droplet case;
+    // no wider than nx needs. 256 x 4 (1024 threads, XCD runs) allows 128
+    // registers per thread, so it serves only the kernels that fit them:
+    // float32 except Liang2014 (which takes 128 x 2), and fp16 / bf16-stored g
+    // on D3Q19 except Liang2014 (the D3Q27 and Liang2014 kernels of those
+    // forms run faster in 64 x 4). float64 needs about 200 registers: 128 x 2.
     int t = 0;
     if (d3) {
+        const bool wide = p.nx >= 256 && p.model != PFLBM_L14;
         if (p.tile != PFLBM_TILE_AUTO) t = p.tile - PFLBM_TILE_64x4;
-        else if (p.precision == PFLBM_FP32) t = p.nx >= 256 ? 2 : (p.nx > 64 ? 1 : 0);
+        else if (p.precision == PFLBM_FP32) t = wide ? 3 : (p.nx > 64 ? 1 : 0);
         else if (p.precision == PFLBM_FP64) t = p.nx > 64 ? 1 : 0;
-        // 256 x 4 (1024 threads) allows 128 registers per thread: the D3Q27 and
-        // Liang2014 kernels need more and run faster in 64 x 4
-        else t = (p.nx >= 256 && p.lattice == PFLBM_D3Q19_D3Q7 && p.model != PFLBM_L14) ? 3 : 0;
+        else t = (wide && p.lattice == PFLBM_D3Q19_D3Q7) ? 3 : 0;
     }
     L.tile_step = t;
     L.ntx_step = (p.nx + TILE_NX[t] - 1) / TILE_NX[t];

@@ -169,6 +169,24 @@ def test_zblock_and_s_other_variants():
         assert max_abs_per_population(h, st.h).max() <= TOL
 
 
+@pytest.mark.parametrize("model", ["AC", "NL", "L18"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "mixed_fp16"])
+def test_automatic_zblock_matches_fixed_depth(model, precision):
+    """The automatic z-block depth changes only the launch grid. On the
+    1024-thread 256 x 4 tile (one resident workgroup per compute unit) a
+    40 x 128 x 50 box gets z blocks sized to one round over the compute units
+    (7 planes on 256 units, the last block 1 plane); every population must
+    equal the run with 5-plane blocks bit for bit, since each node takes the
+    same arithmetic whatever block it falls in."""
+    d, phi, u = small_3d(nx=40, ny=128, nz=50, R=9.0, model=model)
+    out = []
+    for zb in (0, 5):
+        _say("  %s %s zblock %d" % (model, precision, zb))
+        out.append(gpu_dists(gpu_run(d, phi, u, 60, precision=precision, tile="256x4", zblock=zb)))
+    (g0, h0), (g1, h1) = out
+    assert np.array_equal(g0, g1) and np.array_equal(h0, h1)
+
+
 def test_fields_and_diagnostics_match_oracle():
     d, phi, u = wl.static_droplet_2d()
     s = gpu_run(d, phi, u, 401)
