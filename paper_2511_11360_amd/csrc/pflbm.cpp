@@ -108,17 +108,14 @@ Layout make_layout(const pflbm_params& p) {
     L.nty = (p.ny + TILE_NY[0] - 1) / TILE_NY[0];
     // step tile: measured fastest per storage form on the 256^3 droplet case;
     // no wider than nx needs. 256 x 4 (1024 threads, XCD runs) allows 128
-    // registers per thread, so it serves only the kernels that fit them:
-    // float32 except Liang2014 (which takes 128 x 2), and fp16 / bf16-stored g
-    // on D3Q19 except Liang2014 (the D3Q27 and Liang2014 kernels of those
-    // forms run faster in 64 x 4). float64 needs about 200 registers: 128 x 2.
+    // registers per thread: every float32 and fp16 / bf16-stored kernel fits
+    // (90-124), float64 needs 168-204 and takes 128 x 2.
     int t = 0;
     if (d3) {
-        const bool wide = p.nx >= 256 && p.model != PFLBM_L14;
         if (p.tile != PFLBM_TILE_AUTO) t = p.tile - PFLBM_TILE_64x4;
-        else if (p.precision == PFLBM_FP32) t = wide ? 3 : (p.nx > 64 ? 1 : 0);
         else if (p.precision == PFLBM_FP64) t = p.nx > 64 ? 1 : 0;
-        else t = (wide && p.lattice == PFLBM_D3Q19_D3Q7) ? 3 : 0;
+        else if (p.nx >= 256) t = 3;
+        else if (p.precision == PFLBM_FP32) t = p.nx > 64 ? 1 : 0;
     }
     L.tile_step = t;
     L.ntx_step = (p.nx + TILE_NX[t] - 1) / TILE_NX[t];

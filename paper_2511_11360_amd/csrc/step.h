@@ -746,6 +746,14 @@ __device__ __forceinline__ const E& at(const E* arr, int z, int q, int P, int in
     return *(const E*)((const char*)base + (size_t)((unsigned)inplane * (unsigned)sizeof(E)));
 }
 
+// Hide a per-lane offset from loop-invariant code motion. In the z march every
+// load and store addresses a uniform plane base (scalar registers) plus a
+// 32-bit lane offset that does not change along the column; seen as invariant,
+// base + offset is hoisted into a 64-bit per-lane pointer and every access
+// then pays a 64-bit vector add (and two registers per pointer). Marking the
+// offset as redefined each plane keeps the scalar-base addressing form.
+__device__ __forceinline__ void lane_opaque(int& v) { asm volatile("" : "+v"(v)); }
+
 // Geometry of the column (x, y) a thread owns for the whole z march: in-plane
 // offsets of the 3 x 3 neighbourhood with the periodic wrap folded in (the
 // wall side keeps the node itself), and wall flags of the x and y neighbours.
@@ -788,6 +796,14 @@ struct Cross {
     int c, xm, xp, ym, yp;
     bool wxm, wxp, wym, wyp;
 };
+
+__device__ __forceinline__ void lane_opaque(Cross& X) {
+    lane_opaque(X.c);
+    lane_opaque(X.xm);
+    lane_opaque(X.xp);
+    lane_opaque(X.ym);
+    lane_opaque(X.yp);
+}
 
 __device__ __forceinline__ Cross make_cross(int px, int py, int nx, int ny, const int* bc) {
     int ox[3], oy[3];
@@ -894,7 +910,7 @@ __global__ __launch_bounds__(TILE_THREADS[TS]) void k_step(const KArgs a) {
 
     // the thread's own tile position, wrapped or clamped (inactive threads fill
     // the halo of the domain edge with it)
-    const Cross ocr = make_cross(ghost_coord(x, nx, a.bc[0]), ghost_coord(y, ny, a.bc[1]), nx, ny, a.bc);
+    Cross ocr = make_cross(ghost_coord(x, nx, a.bc[0]), ghost_coord(y, ny, a.bc[1]), nx, ny, a.bc);
     Column cl;
     {
         int ox[3], oy[3];
@@ -1042,15 +1058,19 @@ __global__ __launch_bounds__(TILE_THREADS[TS]) void k_step(const KArgs a) {
         T pu_new[3];
         if constexpr (MODE == MODE_STEP) {
             // post-collision populations at the node itself, in the other buffers;
-            // streamed (non-temporal stores): no workgroup reads them this step
+            // streamed (non-temporal stores): no workgroup reads them this step.
+            // The store offset is opaque here too, or one 64-bit lane pointer is
+            // formed and every store adds its plane base to it in vector code.
+            int so = o11;
+            lane_opaque(so);
             auto gsink = [&](auto I, T v) {
                 constexpr int i = I;
-                __builtin_nontemporal_store(GC::template enc<GL, i, GS, T>(v), &at<QG>(Gout, z, i, P, o11));
+                __builtin_nontemporal_store(GC::template enc<GL, i, GS, T>(v), &at<QG>(Gout, z, i, P, so));
             };
             auto hsink = [&](auto J, T v) {
                 constexpr int al = J;
                 if constexpr (al >= HOFF) {
-                    if (a.write_h) __builtin_nontemporal_store((HS)v, &at<QHS>(Hout, z, al - HOFF, P, o11));
+                    if (a.write_h) __builtin_nontemporal_store((HS)v, &at<QHS>(Hout, z, al - HOFF, P, so));
                 }
             };
             node_update<PAIR, MODEL, T, true>(ph, g, h, phin, muin, pu_prev, pu_new, mo, gam, gsink, hsink);
@@ -1121,6 +1141,10 @@ __global__ __launch_bounds__(TILE_THREADS[TS]) void k_step(const KArgs a) {
             // would move all plane and address arithmetic to 64-bit VALU)
             const int z = __builtin_amdgcn_readfirstlane(zl);
             const int r = z - zs;
+            for (int dy = 0; dy < 3; ++dy)
+                for (int dx = 0; dx < 3; ++dx) lane_opaque(cl.off[dy][dx]);
+            lane_opaque(ocr);
+            for (int k = 0; k < NR; ++k) lane_opaque(rcr[k]);
             fill_plane(z + 1, (r + 2) & 3);
             __syncthreads();
             if (active) {

@@ -148,7 +148,7 @@ def test_step_tiles(tile):
     periodic box (150 x 26 x 25: x and y tails in every shape, ragged last z
     block) and moving walls (70 x 22 x 24)."""
     # 256x4 is 1024 threads: float64 at that size runs with spilled registers
-    # (slow, still exact); the automatic choice uses it for 16-bit g only
+    # (slow, still exact); the automatic choice uses it for float32 and 16-bit g
     for name, (d, phi, u, steps, st) in _tile_cases().items():
         s = gpu_run(d, phi, u, steps, tile=tile, zblock=7)
         g, h = gpu_dists(s)
