@@ -87,6 +87,9 @@ class Params:
     freeze_phi: bool = False          # keep h (hence phi) fixed, Sec. III.D
     normal_eps: float = 1e-4          # regularisation of |grad phi| in the normal
     lam: float = 0.0                  # NL: weight of the conservative flux (0: Chai2018)
+    gamma_given: float = None         # NL: multiplier to use instead of the sums over
+                                      # this box (for stepping a block cut out of a
+                                      # larger box, whose sums span the whole box)
 
     @property
     def shape(self):
@@ -283,9 +286,12 @@ def nonlocal_source(p, phi):
     c = 32.0 / (p.W * p.W * (PHI_H - PHI_L) ** 2)
     bulk = c * (phi - PHI_H) * (phi - PHI_L) * (phi - PHI_0)
     well = (PHI_H - phi) * (phi - PHI_L)
-    num = np.sum(bulk)
-    den = np.sum(well)
-    gamma = num / den if np.real(den) != 0 else 0.0 * num
+    if p.gamma_given is not None:
+        gamma = p.gamma_given
+    else:
+        num = np.sum(bulk)
+        den = np.sum(well)
+        gamma = num / den if np.real(den) != 0 else 0.0 * num
     return p.M * (-bulk + gamma * well), gamma
 
 

@@ -5,7 +5,10 @@ The next state at a node depends only on the current state within two nodes
 of it (streaming reaches one node, the phi stencil one more), so the oracle
 can produce sampled outputs one by one: it steps a periodic 5^3 block cut
 around each sampled node from the HIP state and the block's centre must match
-the HIP step there. Sum phi conservation is checked over the whole box."""
+the HIP step there (Liang2014 reaches one node further: 7^3 blocks; the
+nonlocal multiplier, a sum over the whole box, is computed by the oracle from
+the whole HIP phi and supplied to the block step). Sum phi conservation is
+checked over the whole box."""
 import sys
 
 import numpy as np
@@ -30,9 +33,9 @@ def _samples(rng, k):
     return pts
 
 
-def _block(t, z, y, x):
+def _block(t, z, y, x, r=2):
     import torch
-    idx = [(np.arange(c - 2, c + 3) % N) for c in (z, y, x)]
+    idx = [(np.arange(c - r, c + r + 1) % N) for c in (z, y, x)]
     iz = torch.as_tensor(idx[0], device=t.device)
     iy = torch.as_tensor(idx[1], device=t.device)
     ix = torch.as_tensor(idx[2], device=t.device)
@@ -126,3 +129,69 @@ def test_full_size_d3q27_step_on_sampled_nodes(precision):
             assert e <= 1.0, ((x, y, z), eg, eh)
         worst = max(worst, e)
     _say("  D3Q27 %s 256^3 sampled step: worst %.3e" % (precision, worst))
+
+
+def _fp16_fraction(got_g, ref_g, got_h, ref_h, w, floor):
+    """Worst error as a fraction of the fp16-stored tolerance: g is stored as
+    fp16 of 4096 g / w (2^-11 relative), h as float32, arithmetic float32; the
+    floor (in units of g / w) covers float32 rounding of the O(1) terms."""
+    eg = np.max(np.abs(got_g - ref_g) / w / (2.0 ** -10 * np.abs(ref_g / w) + 2.0 ** -24 + floor))
+    eh = np.max(np.abs(got_h - ref_h) / (2e-6 * np.abs(ref_h) + 1e-7))
+    return eg, eh
+
+
+@pytest.mark.parametrize("model", ["CH", "NL", "L18", "L14"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed_fp16"])
+def test_full_size_models_step_on_sampled_nodes(model, precision):
+    """The sampled check for the other models at 256^3, automatic tile and z
+    block (the bench's model lines; nonlocal with lam = 0.5). CH, Liang2018 and
+    Liang2014 carry (phi u) of the previous step in their state: taken as
+    phi u from fields() of that state."""
+    import torch
+    from paper_2511_11360_amd.solver import Solver
+    d, phi, u = wl.taylor_green_droplet_3d(n=N, We=10.0)
+    d["model"] = model
+    if model == "NL":
+        d["lam"] = 0.5
+    s = Solver(d, precision=precision)
+    s.init(phi, u)
+    s.step(19)
+    pu = None
+    if model in ("CH", "L18", "L14"):
+        f_phi, f_u, _, _ = s.fields()
+        pu = f_phi[None] * f_u
+        del f_u
+    s.step(1)
+    g0, h0 = s.get_distributions()
+    extra = {}
+    if model == "NL":
+        phi_all = h0.sum(dim=0).cpu().numpy()
+        extra["gamma_given"] = om.nonlocal_source(om.Params(**d), phi_all)[1]
+        _say("  oracle gamma over 256^3: %.17g" % extra["gamma_given"])
+    s.step(1)
+    g1, h1 = s.get_distributions()
+    r = 3 if model == "L14" else 2
+    B = 2 * r + 1
+    p = om.Params(**dict(d, nx=B, ny=B, nz=B, **extra))
+    w = p.lattices[0].w
+    rng = np.random.default_rng(11)
+    worst = 0.0
+    for (x, y, z) in _samples(rng, 30):
+        st = om.State(_block(g0, z, y, x, r), _block(h0, z, y, x, r),
+                      None if pu is None else _block(pu, z, y, x, r))
+        out = om.step(p, st)
+        ref_g, ref_h = out.g[:, r, r, r], out.h[:, r, r, r]
+        got_g = g1[:, z, y, x].cpu().numpy()
+        got_h = h1[:, z, y, x].cpu().numpy()
+        if precision == "fp64":
+            e = max(np.max(np.abs(got_g - ref_g)), np.max(np.abs(got_h - ref_h)))
+            assert e <= 1e-14, ((x, y, z), e)
+        else:
+            eg, eh = _fp16_fraction(got_g, ref_g, got_h, ref_h, w, 1e-6)
+            e = max(eg, eh)
+            assert e <= 1.0, ((x, y, z), eg, eh)
+        worst = max(worst, e)
+    _say("  %s %s 256^3 sampled step: worst %.3e (%s)"
+         % (model, precision, worst, "abs" if precision == "fp64" else "fraction of tolerance"))
+    del g0, h0, g1, h1, pu
+    torch.cuda.empty_cache()

@@ -115,3 +115,32 @@ def test_hybrid_source_moments(lam):
     assert np.abs(heq.sum(axis=0) - m["phi"]).max() < 1e-15
     for a in range(2):
         assert np.abs(sum(hl.c[k][a] * heq[k] for k in range(hl.Q)) - m["phi"] * m["u"][a]).max() < 1e-16
+
+
+def test_block_step_with_the_box_multiplier_matches_the_box():
+    """Locality with the multiplier supplied: apart from gamma, the next state
+    at a node depends on the state within two nodes (streaming one, the phi
+    stencil one more). A periodic 5^3 block cut around a node of a 3-D box and
+    stepped with the box's gamma must reproduce the box's step at its centre;
+    with the block's own sums in place of gamma it must not (the sums of Eq.
+    lagrange_multiplier span the whole box)."""
+    n = 12
+    p = om.Params(lattice="D3Q19_D3Q7", model="NL", nx=n, ny=n, nz=n, rho_H=5.0, rho_L=1.0,
+                  nu_H=0.05, nu_L=0.05, M=0.05, W=3.0, sigma=0.01, lam=0.5)
+    z, y, x = np.meshgrid(*(np.arange(n),) * 3, indexing="ij")
+    r = np.sqrt((x - 5.3) ** 2 + (y - 6.1) ** 2 + (z - 5.7) ** 2)
+    st = om.run(p, om.init(p, 0.5 + 0.5 * np.tanh(2 * (3.5 - r) / p.W)), 3)
+    gamma = om.macroscopic(p, st)["gamma"]
+    full = om.step(p, st)
+    pb = om.Params(**dict(p.__dict__, nx=5, ny=5, nz=5, gamma_given=gamma))
+    pb_own = om.Params(**dict(p.__dict__, nx=5, ny=5, nz=5))
+    own_err = 0.0
+    for (cz, cy, cx) in [(5, 6, 6), (0, 11, 3), (8, 2, 9)]:
+        idx = np.ix_(*(np.arange(c - 2, c + 3) % n for c in (cz, cy, cx)))
+        blk = om.State(st.g[(slice(None),) + idx], st.h[(slice(None),) + idx])
+        out = om.step(pb, blk)
+        assert np.abs(out.g[:, 2, 2, 2] - full.g[:, cz, cy, cx]).max() < 1e-15
+        assert np.abs(out.h[:, 2, 2, 2] - full.h[:, cz, cy, cx]).max() < 1e-15
+        own = om.step(pb_own, blk)
+        own_err = max(own_err, np.abs(own.h[:, 2, 2, 2] - full.h[:, cz, cy, cx]).max())
+    assert own_err > 1e-8
