@@ -193,23 +193,24 @@ hipError_t launch_step_p2_m3(int precision, int mode, const KArgs& a, hipStream_
 hipError_t launch_step_p0_m4(int precision, int mode, const KArgs& a, hipStream_t s);
 hipError_t launch_step_p1_m4(int precision, int mode, const KArgs& a, hipStream_t s);
 hipError_t launch_step_p2_m4(int precision, int mode, const KArgs& a, hipStream_t s);
-// resident workgroups per compute unit of the 3-D step kernel (0 if unknown)
-int occupancy_step(int lattice, int model, int precision, int tile, int walls);
-int occupancy_step_p0_m0(int precision, int tile, int walls);
-int occupancy_step_p0_m1(int precision, int tile, int walls);
-int occupancy_step_p0_m2(int precision, int tile, int walls);
-int occupancy_step_p0_m3(int precision, int tile, int walls);
-int occupancy_step_p0_m4(int precision, int tile, int walls);
-int occupancy_step_p1_m0(int precision, int tile, int walls);
-int occupancy_step_p1_m1(int precision, int tile, int walls);
-int occupancy_step_p1_m2(int precision, int tile, int walls);
-int occupancy_step_p1_m3(int precision, int tile, int walls);
-int occupancy_step_p1_m4(int precision, int tile, int walls);
-int occupancy_step_p2_m0(int precision, int tile, int walls);
-int occupancy_step_p2_m1(int precision, int tile, int walls);
-int occupancy_step_p2_m2(int precision, int tile, int walls);
-int occupancy_step_p2_m3(int precision, int tile, int walls);
-int occupancy_step_p2_m4(int precision, int tile, int walls);
+// resident workgroups per compute unit of the 3-D step kernel in mode MODE_STEP
+// or MODE_MU (0 if unknown)
+int occupancy_step(int lattice, int model, int precision, int tile, int walls, int mode);
+int occupancy_step_p0_m0(int precision, int tile, int walls, int mode);
+int occupancy_step_p0_m1(int precision, int tile, int walls, int mode);
+int occupancy_step_p0_m2(int precision, int tile, int walls, int mode);
+int occupancy_step_p0_m3(int precision, int tile, int walls, int mode);
+int occupancy_step_p0_m4(int precision, int tile, int walls, int mode);
+int occupancy_step_p1_m0(int precision, int tile, int walls, int mode);
+int occupancy_step_p1_m1(int precision, int tile, int walls, int mode);
+int occupancy_step_p1_m2(int precision, int tile, int walls, int mode);
+int occupancy_step_p1_m3(int precision, int tile, int walls, int mode);
+int occupancy_step_p1_m4(int precision, int tile, int walls, int mode);
+int occupancy_step_p2_m0(int precision, int tile, int walls, int mode);
+int occupancy_step_p2_m1(int precision, int tile, int walls, int mode);
+int occupancy_step_p2_m2(int precision, int tile, int walls, int mode);
+int occupancy_step_p2_m3(int precision, int tile, int walls, int mode);
+int occupancy_step_p2_m4(int precision, int tile, int walls, int mode);
 hipError_t launch_init(int lattice, int model, int precision, const InitArgs& a, hipStream_t s);
 hipError_t launch_get(int lattice, int model, int precision, const IOArgs& a, hipStream_t s);
 hipError_t launch_set(int lattice, int model, int precision, const IOArgs& a, hipStream_t s);

@@ -15,13 +15,13 @@ hipError_t launch_step(int lattice, int model, int precision, int mode, const KA
     return fn[lattice][model](precision, mode, a, s);
 }
 
-int occupancy_step(int lattice, int model, int precision, int tile, int walls) {
-    using OccFn = int (*)(int, int, int);
+int occupancy_step(int lattice, int model, int precision, int tile, int walls, int mode) {
+    using OccFn = int (*)(int, int, int, int);
     static const OccFn fn[3][5] = {
         {occupancy_step_p0_m0, occupancy_step_p0_m1, occupancy_step_p0_m2, occupancy_step_p0_m3, occupancy_step_p0_m4},
         {occupancy_step_p1_m0, occupancy_step_p1_m1, occupancy_step_p1_m2, occupancy_step_p1_m3, occupancy_step_p1_m4},
         {occupancy_step_p2_m0, occupancy_step_p2_m1, occupancy_step_p2_m2, occupancy_step_p2_m3, occupancy_step_p2_m4}};
-    return fn[lattice][model](precision, tile, walls);
+    return fn[lattice][model](precision, tile, walls, mode);
 }
 
 // final reduction over the per-block partials, one workgroup, fixed order
@@ -248,7 +248,7 @@ __global__ __launch_bounds__(256) void k_set(const IOArgs a) {
 // post-streaming sum of h pulled from the current buffer; float64 sums in a
 // fixed order (bit-reproducible)
 
-template <class PAIR, int PREC>
+template <class PAIR, int PREC, int WALLS>
 __global__ __launch_bounds__(256) void k_gamma_part(const GammaArgs a) {
     using HL = typename PAIR::H;
     using T = typename Types<PREC>::T;
@@ -256,20 +256,23 @@ __global__ __launch_bounds__(256) void k_gamma_part(const GammaArgs a) {
     constexpr int HOFF = PAIR::dim == 3 ? 1 : 0;
     constexpr int QHS = HL::Q - HOFF;
     __shared__ double red[2][256 / 64];
-    // workgroup (bx, bz): 256 consecutive in-plane nodes over GAMMA_ZB planes
+    // workgroup (bx, bz): 256 consecutive in-plane nodes over GAMMA_ZB planes;
+    // phi* pulled by the step's own helper in the step's summation order
     const int ip = blockIdx.x * 256 + threadIdx.x;
     const int z0 = blockIdx.y * GAMMA_ZB, z1 = min(a.nz, z0 + GAMMA_ZB);
     double num = 0.0, den = 0.0;
     if (ip < a.nx * a.ny) {
         const int x = ip % a.nx, y = ip / a.nx;
-        const HS* H = (const HS*)a.h;
-        for (int z = z0; z < z1; ++z) {
-            T s = (T)0;              // same summation order as the step's halo fill
+        const HS* __restrict__ H = (const HS*)a.h;
+        Cross X = make_cross(x, y, a.nx, a.ny, a.bc);
+        for (int zl = z0; zl < z1; ++zl) {
+            const int z = __builtin_amdgcn_readfirstlane(zl);
+            lane_opaque(X);
+            const ZPlanes zp = make_zplanes(z, a.nz, a.bc[2]);
+            T s = (T)0;
             unroll<QHS>([&](auto J) {
                 constexpr int al = J + HOFF;
-                bool w;
-                int side;
-                s += (T)H[pull_source<HL, al, QHS, HOFF>(a.nx, a.ny, a.nz, a.bc, x, y, z, a.P, w, side)];
+                s += pull_h<HL, al, HOFF, WALLS, T>(H, X, zp, a.P);
             });
             const double phi = (double)s;
             num += a.w32 * (phi - 1.0) * phi * (phi - 0.5);
@@ -379,14 +382,20 @@ hipError_t launch_gamma(int lattice, int precision, const GammaArgs& a, hipStrea
     const int nbx = (a.nx * a.ny + 255) / 256, nbz = (a.nz + GAMMA_ZB - 1) / GAMMA_ZB;
     const long long nb = (long long)nbx * nbz;
     const dim3 grid((unsigned)nbx, (unsigned)nbz), block(256);
-    auto go = [&](auto pair) {
+    const bool walls = a.bc[0] != 0 || a.bc[1] != 0 || a.bc[2] != 0;
+    auto go_w = [&](auto pair, auto w) {
         using P_ = decltype(pair);
+        constexpr int W = decltype(w)::value;
         switch (precision) {
-            case 0: hipLaunchKernelGGL((k_gamma_part<P_, 0>), grid, block, 0, s, a); break;
-            case 1: hipLaunchKernelGGL((k_gamma_part<P_, 1>), grid, block, 0, s, a); break;
-            case 2: hipLaunchKernelGGL((k_gamma_part<P_, 2>), grid, block, 0, s, a); break;
-            default: hipLaunchKernelGGL((k_gamma_part<P_, 3>), grid, block, 0, s, a);
+            case 0: hipLaunchKernelGGL((k_gamma_part<P_, 0, W>), grid, block, 0, s, a); break;
+            case 1: hipLaunchKernelGGL((k_gamma_part<P_, 1, W>), grid, block, 0, s, a); break;
+            case 2: hipLaunchKernelGGL((k_gamma_part<P_, 2, W>), grid, block, 0, s, a); break;
+            default: hipLaunchKernelGGL((k_gamma_part<P_, 3, W>), grid, block, 0, s, a);
         }
+    };
+    auto go = [&](auto pair) {
+        if (walls) go_w(pair, std::integral_constant<int, 1>{});
+        else go_w(pair, std::integral_constant<int, 0>{});
     };
     if (lattice == 0) go(Pair2D{});
     else if (lattice == 1) go(Pair3D{});

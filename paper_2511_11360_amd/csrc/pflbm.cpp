@@ -28,6 +28,7 @@ struct Layout {
     int ntx = 0, nty = 0, ntz = 0, zb = 0, nblocks = 0;   // 64 x 4 tiles (fields, diagnostics)
     int tile_step = 0, ntx_step = 0, nty_step = 0;        // tiles of the step kernel
     int zb_step = 0, ntz_step = 0;                        // z blocks of the step kernel
+    int zb_mu = 0, ntz_mu = 0;                            // z blocks of the Liang2014 mu pass
     size_t off_g[2] = {0, 0}, off_h[2] = {0, 0}, off_pu = 0, off_mu = 0, off_part = 0, off_gpart = 0, off_res = 0,
            total = 0;
     size_t ck_g = 0, ck_h = 0, ck_pu = 0, ck_total = 0;
@@ -130,6 +131,8 @@ Layout make_layout(const pflbm_params& p) {
     L.nblocks = L.ntx * L.nty * L.ntz;
     L.zb_step = L.zb;   // refined at create time when zblock is automatic
     L.ntz_step = L.ntz;
+    L.zb_mu = L.zb;
+    L.ntz_mu = L.ntz;
     size_t off = 0;
     for (int k = 0; k < 2; ++k) {
         L.off_g[k] = off;
@@ -225,22 +228,21 @@ int guard(pflbm_t* h) {
     return PFLBM_OK;
 }
 
-// z planes per step workgroup when the caller leaves zblock at 0. A workgroup
+// z planes per workgroup of a z-marching pass when the caller leaves zblock
+// at 0, from its tile and resident workgroups per compute unit. A workgroup
 // marches its column plane by plane and first loads the halo planes of its
 // phi ring; with one resident workgroup per compute unit (the 1024-thread
 // tile) nothing hides that start, so the grid is sized to fill every unit
 // once. With several resident workgroups: 32 planes while that still leaves
-// two rounds of work, else halving down to 8. The fields and diagnostics
-// kernels keep the layout's depth (their partial sums are sized by it).
-void choose_step_zblock(pflbm_t* h) {
-    Layout& L = h->L;
-    if (L.dim != 3 || h->p.zblock != 0 || h->device < 0) return;
+// two rounds of work, else halving down to 8. Returns 0 if the device cannot
+// be queried (the layout's depth stays).
+int auto_zblock(const pflbm_t* h, int tile, int occ) {
     int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess) return;
-    const int occ = occupancy_step(h->p.lattice, h->p.model, h->p.precision, L.tile_step, h->wall_axis >= 0);
-    if (cus <= 0 || occ <= 0) return;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess) return 0;
+    if (cus <= 0 || occ <= 0) return 0;
     const long long slots = (long long)cus * occ;
-    const long long tiles = (long long)L.ntx_step * L.nty_step;
+    const long long tiles = (long long)((h->p.nx + TILE_NX[tile] - 1) / TILE_NX[tile]) *
+                            ((h->p.ny + TILE_NY[tile] - 1) / TILE_NY[tile]);
     const int nz = h->p.nz;
     int zb;
     if (occ == 1) {
@@ -251,9 +253,28 @@ void choose_step_zblock(pflbm_t* h) {
         zb = 32;
         while (zb > 8 && tiles * ((nz + zb - 1) / zb) < 2 * slots) zb /= 2;
     }
-    if (zb > nz) zb = nz;
-    L.zb_step = zb;
-    L.ntz_step = (nz + zb - 1) / zb;
+    return zb > nz ? nz : zb;
+}
+
+// the step kernel's (and the Liang2014 mu pass's) depth; the fields and
+// diagnostics kernels keep the layout's depth (their partial sums are sized by it)
+void choose_zblocks(pflbm_t* h) {
+    Layout& L = h->L;
+    if (L.dim != 3 || h->p.zblock != 0 || h->device < 0) return;
+    const int walls = h->wall_axis >= 0;
+    int zb = auto_zblock(h, L.tile_step,
+                         occupancy_step(h->p.lattice, h->p.model, h->p.precision, L.tile_step, walls, MODE_STEP));
+    if (zb > 0) {
+        L.zb_step = zb;
+        L.ntz_step = (h->p.nz + zb - 1) / zb;
+    }
+    if (h->p.model == PFLBM_L14) {
+        zb = auto_zblock(h, 0, occupancy_step(h->p.lattice, h->p.model, h->p.precision, 0, walls, MODE_MU));
+        if (zb > 0) {
+            L.zb_mu = zb;
+            L.ntz_mu = (h->p.nz + zb - 1) / zb;
+        }
+    }
 }
 
 void base_args(pflbm_t* h, KArgs& a) {
@@ -310,8 +331,8 @@ int run_mu(pflbm_t* h, const KArgs& a) {
     m.tile = 0;
     m.ntx = h->L.ntx;
     m.nty = h->L.nty;
-    m.ntz = h->L.ntz;
-    m.zb = h->L.zb;
+    m.ntz = h->L.ntz_mu;
+    m.zb = h->L.zb_mu;
     HIPCHK(h, launch_step(h->p.lattice, h->p.model, h->p.precision, MODE_MU, m, h->stream), "mu kernel");
     return PFLBM_OK;
 }
@@ -375,7 +396,7 @@ int pflbm_create(const pflbm_params* params, void* hip_stream, void* dev_state, 
     const pflbm_params& p = h->p;
     for (int a = 0; a < 3; ++a)
         if (p.bc[a] == PFLBM_WALL) h->wall_axis = a;
-    choose_step_zblock(h);
+    choose_zblocks(h);
     if (p.lattice == PFLBM_D2Q9_D2Q5) wall_terms<D2Q9>(p, h->gcorr);
     else if (p.lattice == PFLBM_D3Q19_D3Q7) wall_terms<D3Q19>(p, h->gcorr);
     else wall_terms<D3Q27>(p, h->gcorr);

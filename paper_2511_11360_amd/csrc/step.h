@@ -1021,8 +1021,9 @@ __global__ __launch_bounds__(TILE_THREADS[TS]) void k_step(const KArgs a) {
             });
             const T phi = phin[0];
             const T lap = stencil_lap<GL>(phin);
-            ((T*)a.mu)[(size_t)z * P + (unsigned)o11] =
-                ph.beta4 * phi * (phi - (T)1) * (phi - (T)0.5) - ph.kappa * lap;
+            int so = o11;
+            lane_opaque(so);
+            at<1>((T*)a.mu, z, 0, P, so) = ph.beta4 * phi * (phi - (T)1) * (phi - (T)0.5) - ph.kappa * lap;
             return;
         }
         const ZPlanes zp = make_zplanes(z, nz, a.bc[2]);
@@ -1197,10 +1198,12 @@ inline hipError_t step_mode(int mode, const KArgs& a, hipStream_t s) {
             hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_FIELDS, 1, 0>), grid, block, 0, s, a);
             break;
         case MODE_MU:
-            if constexpr (MODEL == 4)
-                hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_MU, 1, 0>), grid, block, 0, s, a);
-            else
+            if constexpr (MODEL == 4) {
+                if (walls) hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_MU, 1, 0>), grid, block, 0, s, a);
+                else hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_MU, 0, 0>), grid, block, 0, s, a);
+            } else {
                 return hipErrorInvalidValue;
+            }
             break;
         default:
             hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_DIAG, 1, 0>), grid, block, 0, s, a);
@@ -1208,13 +1211,21 @@ inline hipError_t step_mode(int mode, const KArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-// resident workgroups per compute unit of the 3-D step kernel with this tile
-// (0 when the runtime cannot say)
+// resident workgroups per compute unit of the 3-D step kernel (mode MODE_STEP,
+// any tile) or of the Liang2014 mu pass (MODE_MU, tile 0); 0 when the runtime
+// cannot say or the kernel does not exist
 template <class PAIR, int MODEL, int PREC, int WALLS>
-inline int step_occupancy_walls(int tile) {
+inline int step_occupancy_walls(int tile, int mode) {
     int n = 0;
     hipError_t e = hipErrorInvalidValue;
     const int bs = TILE_THREADS[tile];
+    if constexpr (PAIR::dim == 3 && MODEL == 4) {
+        if (mode == MODE_MU) {
+            if (tile == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<PAIR, MODEL, PREC, MODE_MU, WALLS, 0>, bs, 0);
+            return e == hipSuccess ? n : 0;
+        }
+    }
+    if (mode != MODE_STEP) return 0;
     if constexpr (PAIR::dim == 3) {
         switch (tile) {
             case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<PAIR, MODEL, PREC, MODE_STEP, WALLS, 0>, bs, 0); break;
@@ -1228,12 +1239,12 @@ inline int step_occupancy_walls(int tile) {
 }
 
 template <class PAIR, int MODEL>
-inline int step_occupancy(int prec, int tile, int walls) {
+inline int step_occupancy(int prec, int tile, int walls, int mode) {
     switch (prec) {
-        case 0: return walls ? step_occupancy_walls<PAIR, MODEL, 0, 1>(tile) : step_occupancy_walls<PAIR, MODEL, 0, 0>(tile);
-        case 1: return walls ? step_occupancy_walls<PAIR, MODEL, 1, 1>(tile) : step_occupancy_walls<PAIR, MODEL, 1, 0>(tile);
-        case 2: return walls ? step_occupancy_walls<PAIR, MODEL, 2, 1>(tile) : step_occupancy_walls<PAIR, MODEL, 2, 0>(tile);
-        default: return walls ? step_occupancy_walls<PAIR, MODEL, 3, 1>(tile) : step_occupancy_walls<PAIR, MODEL, 3, 0>(tile);
+        case 0: return walls ? step_occupancy_walls<PAIR, MODEL, 0, 1>(tile, mode) : step_occupancy_walls<PAIR, MODEL, 0, 0>(tile, mode);
+        case 1: return walls ? step_occupancy_walls<PAIR, MODEL, 1, 1>(tile, mode) : step_occupancy_walls<PAIR, MODEL, 1, 0>(tile, mode);
+        case 2: return walls ? step_occupancy_walls<PAIR, MODEL, 2, 1>(tile, mode) : step_occupancy_walls<PAIR, MODEL, 2, 0>(tile, mode);
+        default: return walls ? step_occupancy_walls<PAIR, MODEL, 3, 1>(tile, mode) : step_occupancy_walls<PAIR, MODEL, 3, 0>(tile, mode);
     }
 }
 
