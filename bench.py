@@ -30,8 +30,7 @@ def bytes_per_update(d, precision):
     store 6 phase-field populations; CH and Liang2018 also carry the 3
     components of (phi u); the nonlocal model reads the phase-field
     populations once more for the global sums of its multiplier; Liang2014
-    also carries (phi u) and reads h once more in its mu_phi pass, which
-    writes mu_phi for the step to read)."""
+    also carries (phi u), its mu_phi is formed in the step kernel)."""
     d3 = d["lattice"] != "D2Q9_D2Q5"
     qg = {"D2Q9_D2Q5": 9, "D3Q19_D3Q7": 19, "D3Q27_D3Q7": 27}[d["lattice"]]
     qh = (7 if d["model"] in ("CH", "L14") else 6) if d3 else 5
@@ -39,8 +38,6 @@ def bytes_per_update(d, precision):
     sh = 8 if precision == "fp64" else 4
     st = 8 if precision == "fp64" else 4
     extra = 2 * 3 * st if d["model"] in ("CH", "L18", "L14") else 0
-    if d["model"] == "L14":
-        extra += qh * sh + 2 * st        # mu_phi pass: h read, mu written; the step reads mu
     if d["model"] == "NL":
         extra += qh * sh
     return 2 * (qg * sg + qh * sh) + extra

@@ -83,8 +83,8 @@ extern "C" {
                         PFLBM_CH with Eqs. liang2_feq, liang2_F (Gamma, s of Eq. Gamma_beta),
                         F_a = (rho_H - rho_L) M lap(mu_phi) u, the velocity update of
                         Eq. liang2014_velocity_update and the pressure of Eq. liang_p_update;
-                        a pass before each step stores mu_phi for its Laplacian. Same wall
-                        and fp16 limits as PFLBM_L18 */
+                        the step kernel forms mu_phi itself around each tile for its
+                        Laplacian. Same wall and fp16 limits as PFLBM_L18 */
 #define PFLBM_NL 2   /* nonlocal Allen-Cahn, Eqs. Chai_geq, chai_G (Chai2018), the source
                         blended with the conservative flux by lam as in Eq. Hu_G (Hu2019);
                         phi = sum h + (1 - lam) R / 2 (Eq. chai2018_phi_update), with the

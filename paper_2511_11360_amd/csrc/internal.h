@@ -18,7 +18,7 @@ constexpr int NDIAG = 12;       // per-block partial diagnostics (see kernels.hi
 constexpr int GAMMA_ZB = 16;    // z planes per workgroup of the nonlocal multiplier sums
 constexpr int MAXQ = 27;
 
-enum Mode { MODE_STEP = 0, MODE_FIELDS = 1, MODE_DIAG = 2, MODE_MU = 3 };
+enum Mode { MODE_STEP = 0, MODE_FIELDS = 1, MODE_DIAG = 2 };
 
 // Models: 0 conservative AC, 1 CH, 2 nonlocal / hybrid AC, 3 Liang2018,
 // 4 Liang2014 with its hydrodynamics. The CH phase field (1, 4) stores the
@@ -83,8 +83,6 @@ struct KArgs {
     const void* hin;       // phase-field populations read this step [z][Qhs][P]
     void* hout;            // phase-field populations written this step [z][Qhs][P]
     void* phiu;            // CH / Liang: (phi u) of the previous step [z][3][P], compute type
-    void* mu;              // Liang2014: mu_phi of the current state [z][P], compute type
-                           // (written by the MODE_MU pass, read with its halo by the step)
     double* f_phi;         // MODE_FIELDS outputs (canonical float64), may be null
     double* f_u;
     double* f_p;
@@ -193,24 +191,23 @@ hipError_t launch_step_p2_m3(int precision, int mode, const KArgs& a, hipStream_
 hipError_t launch_step_p0_m4(int precision, int mode, const KArgs& a, hipStream_t s);
 hipError_t launch_step_p1_m4(int precision, int mode, const KArgs& a, hipStream_t s);
 hipError_t launch_step_p2_m4(int precision, int mode, const KArgs& a, hipStream_t s);
-// resident workgroups per compute unit of the 3-D step kernel in mode MODE_STEP
-// or MODE_MU (0 if unknown)
-int occupancy_step(int lattice, int model, int precision, int tile, int walls, int mode);
-int occupancy_step_p0_m0(int precision, int tile, int walls, int mode);
-int occupancy_step_p0_m1(int precision, int tile, int walls, int mode);
-int occupancy_step_p0_m2(int precision, int tile, int walls, int mode);
-int occupancy_step_p0_m3(int precision, int tile, int walls, int mode);
-int occupancy_step_p0_m4(int precision, int tile, int walls, int mode);
-int occupancy_step_p1_m0(int precision, int tile, int walls, int mode);
-int occupancy_step_p1_m1(int precision, int tile, int walls, int mode);
-int occupancy_step_p1_m2(int precision, int tile, int walls, int mode);
-int occupancy_step_p1_m3(int precision, int tile, int walls, int mode);
-int occupancy_step_p1_m4(int precision, int tile, int walls, int mode);
-int occupancy_step_p2_m0(int precision, int tile, int walls, int mode);
-int occupancy_step_p2_m1(int precision, int tile, int walls, int mode);
-int occupancy_step_p2_m2(int precision, int tile, int walls, int mode);
-int occupancy_step_p2_m3(int precision, int tile, int walls, int mode);
-int occupancy_step_p2_m4(int precision, int tile, int walls, int mode);
+// resident workgroups per compute unit of the 3-D step kernel (0 if unknown)
+int occupancy_step(int lattice, int model, int precision, int tile, int walls);
+int occupancy_step_p0_m0(int precision, int tile, int walls);
+int occupancy_step_p0_m1(int precision, int tile, int walls);
+int occupancy_step_p0_m2(int precision, int tile, int walls);
+int occupancy_step_p0_m3(int precision, int tile, int walls);
+int occupancy_step_p0_m4(int precision, int tile, int walls);
+int occupancy_step_p1_m0(int precision, int tile, int walls);
+int occupancy_step_p1_m1(int precision, int tile, int walls);
+int occupancy_step_p1_m2(int precision, int tile, int walls);
+int occupancy_step_p1_m3(int precision, int tile, int walls);
+int occupancy_step_p1_m4(int precision, int tile, int walls);
+int occupancy_step_p2_m0(int precision, int tile, int walls);
+int occupancy_step_p2_m1(int precision, int tile, int walls);
+int occupancy_step_p2_m2(int precision, int tile, int walls);
+int occupancy_step_p2_m3(int precision, int tile, int walls);
+int occupancy_step_p2_m4(int precision, int tile, int walls);
 hipError_t launch_init(int lattice, int model, int precision, const InitArgs& a, hipStream_t s);
 hipError_t launch_get(int lattice, int model, int precision, const IOArgs& a, hipStream_t s);
 hipError_t launch_set(int lattice, int model, int precision, const IOArgs& a, hipStream_t s);

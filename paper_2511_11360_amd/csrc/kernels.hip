@@ -15,13 +15,13 @@ hipError_t launch_step(int lattice, int model, int precision, int mode, const KA
     return fn[lattice][model](precision, mode, a, s);
 }
 
-int occupancy_step(int lattice, int model, int precision, int tile, int walls, int mode) {
-    using OccFn = int (*)(int, int, int, int);
+int occupancy_step(int lattice, int model, int precision, int tile, int walls) {
+    using OccFn = int (*)(int, int, int);
     static const OccFn fn[3][5] = {
         {occupancy_step_p0_m0, occupancy_step_p0_m1, occupancy_step_p0_m2, occupancy_step_p0_m3, occupancy_step_p0_m4},
         {occupancy_step_p1_m0, occupancy_step_p1_m1, occupancy_step_p1_m2, occupancy_step_p1_m3, occupancy_step_p1_m4},
         {occupancy_step_p2_m0, occupancy_step_p2_m1, occupancy_step_p2_m2, occupancy_step_p2_m3, occupancy_step_p2_m4}};
-    return fn[lattice][model](precision, tile, walls, mode);
+    return fn[lattice][model](precision, tile, walls);
 }
 
 // final reduction over the per-block partials, one workgroup, fixed order

@@ -28,8 +28,7 @@ struct Layout {
     int ntx = 0, nty = 0, ntz = 0, zb = 0, nblocks = 0;   // 64 x 4 tiles (fields, diagnostics)
     int tile_step = 0, ntx_step = 0, nty_step = 0;        // tiles of the step kernel
     int zb_step = 0, ntz_step = 0;                        // z blocks of the step kernel
-    int zb_mu = 0, ntz_mu = 0;                            // z blocks of the Liang2014 mu pass
-    size_t off_g[2] = {0, 0}, off_h[2] = {0, 0}, off_pu = 0, off_mu = 0, off_part = 0, off_gpart = 0, off_res = 0,
+    size_t off_g[2] = {0, 0}, off_h[2] = {0, 0}, off_pu = 0, off_part = 0, off_gpart = 0, off_res = 0,
            total = 0;
     size_t ck_g = 0, ck_h = 0, ck_pu = 0, ck_total = 0;
     size_t g_bytes = 0, h_bytes = 0, pu_bytes = 0;
@@ -109,14 +108,16 @@ Layout make_layout(const pflbm_params& p) {
     L.nty = (p.ny + TILE_NY[0] - 1) / TILE_NY[0];
     // step tile: measured fastest per storage form on the 256^3 droplet case;
     // no wider than nx needs. 256 x 4 (1024 threads, XCD runs) allows 128
-    // registers per thread: every float32 and fp16 / bf16-stored kernel fits
-    // (90-124), float64 needs 168-204 and takes 128 x 2.
+    // registers per thread: the float32 and fp16 / bf16-stored kernels fit
+    // (90-128) except Liang2014 on D3Q27 (its mu frame spills: 64 x 4);
+    // float64 needs 168-227 and takes 128 x 2.
     int t = 0;
     if (d3) {
+        const bool fits = !(p.model == PFLBM_L14 && p.lattice == PFLBM_D3Q27_D3Q7);
         if (p.tile != PFLBM_TILE_AUTO) t = p.tile - PFLBM_TILE_64x4;
         else if (p.precision == PFLBM_FP64) t = p.nx > 64 ? 1 : 0;
-        else if (p.nx >= 256) t = 3;
-        else if (p.precision == PFLBM_FP32) t = p.nx > 64 ? 1 : 0;
+        else if (p.nx >= 256 && fits) t = 3;
+        else if (p.precision == PFLBM_FP32 && fits) t = p.nx > 64 ? 1 : 0;
     }
     L.tile_step = t;
     L.ntx_step = (p.nx + TILE_NX[t] - 1) / TILE_NX[t];
@@ -131,8 +132,6 @@ Layout make_layout(const pflbm_params& p) {
     L.nblocks = L.ntx * L.nty * L.ntz;
     L.zb_step = L.zb;   // refined at create time when zblock is automatic
     L.ntz_step = L.ntz;
-    L.zb_mu = L.zb;
-    L.ntz_mu = L.ntz;
     size_t off = 0;
     for (int k = 0; k < 2; ++k) {
         L.off_g[k] = off;
@@ -145,8 +144,6 @@ Layout make_layout(const pflbm_params& p) {
     L.off_pu = off;
     const bool has_pu = p.model == PFLBM_CH || p.model == PFLBM_L18 || p.model == PFLBM_L14;
     if (has_pu) off = align_up(off + 3 * planes * L.sT, ALIGN);
-    L.off_mu = off;
-    if (p.model == PFLBM_L14) off = align_up(off + planes * L.sT, ALIGN);
     L.off_part = off;
     off = align_up(off + (size_t)L.nblocks * NDIAG * sizeof(double), ALIGN);
     L.off_gpart = off;   // nonlocal multiplier: per-256-node partial sums
@@ -256,24 +253,17 @@ int auto_zblock(const pflbm_t* h, int tile, int occ) {
     return zb > nz ? nz : zb;
 }
 
-// the step kernel's (and the Liang2014 mu pass's) depth; the fields and
-// diagnostics kernels keep the layout's depth (their partial sums are sized by it)
+// the step kernel's depth; the fields and diagnostics kernels keep the layout's
+// depth (their partial sums are sized by it)
 void choose_zblocks(pflbm_t* h) {
     Layout& L = h->L;
     if (L.dim != 3 || h->p.zblock != 0 || h->device < 0) return;
     const int walls = h->wall_axis >= 0;
-    int zb = auto_zblock(h, L.tile_step,
-                         occupancy_step(h->p.lattice, h->p.model, h->p.precision, L.tile_step, walls, MODE_STEP));
+    const int zb = auto_zblock(h, L.tile_step,
+                               occupancy_step(h->p.lattice, h->p.model, h->p.precision, L.tile_step, walls));
     if (zb > 0) {
         L.zb_step = zb;
         L.ntz_step = (h->p.nz + zb - 1) / zb;
-    }
-    if (h->p.model == PFLBM_L14) {
-        zb = auto_zblock(h, 0, occupancy_step(h->p.lattice, h->p.model, h->p.precision, 0, walls, MODE_MU));
-        if (zb > 0) {
-            L.zb_mu = zb;
-            L.ntz_mu = (h->p.nz + zb - 1) / zb;
-        }
     }
 }
 
@@ -284,7 +274,6 @@ void base_args(pflbm_t* h, KArgs& a) {
     a.hin = h->base + h->L.off_h[h->hcur];
     a.hout = h->base + h->L.off_h[1 - h->hcur];
     a.phiu = h->base + h->L.off_pu;
-    a.mu = h->base + h->L.off_mu;
     a.partials = (double*)(h->base + h->L.off_part);
     a.P = h->L.P;
     a.nx = h->p.nx;
@@ -324,24 +313,10 @@ int run_gamma(pflbm_t* h, KArgs& a) {
     return PFLBM_OK;
 }
 
-// Liang2014: mu_phi of the current state, for the Laplacian in the next launch
-int run_mu(pflbm_t* h, const KArgs& a) {
-    if (h->p.model != PFLBM_L14) return PFLBM_OK;
-    KArgs m = a;
-    m.tile = 0;
-    m.ntx = h->L.ntx;
-    m.nty = h->L.nty;
-    m.ntz = h->L.ntz_mu;
-    m.zb = h->L.zb_mu;
-    HIPCHK(h, launch_step(h->p.lattice, h->p.model, h->p.precision, MODE_MU, m, h->stream), "mu kernel");
-    return PFLBM_OK;
-}
-
 int run_diag(pflbm_t* h, const double* centre, double R, double* res) {
     KArgs a;
     base_args(h, a);
     if (int st = run_gamma(h, a)) return st;
-    if (int st = run_mu(h, a)) return st;
     if (centre) {
         a.has_centre = 1;
         for (int k = 0; k < h->L.dim; ++k) a.centre[k] = centre[k];
@@ -481,7 +456,6 @@ int pflbm_step(pflbm_t* h, int nsteps) {
         a.ntz = h->L.ntz_step;
         a.zb = h->L.zb_step;
         if ((st = run_gamma(h, a))) return st;
-        if ((st = run_mu(h, a))) return st;
         HIPCHK(h, launch_step(h->p.lattice, h->p.model, h->p.precision, MODE_STEP, a, h->stream), "step kernel");
         if (!h->p.freeze_phi) h->hcur ^= 1;
         h->gcur ^= 1;
@@ -510,7 +484,6 @@ int pflbm_fields(pflbm_t* h, double* phi, double* u, double* p, double* rho) {
     a.f_p = p;
     a.f_rho = rho;
     if ((st = run_gamma(h, a))) return st;
-    if ((st = run_mu(h, a))) return st;
     HIPCHK(h, launch_step(h->p.lattice, h->p.model, h->p.precision, MODE_FIELDS, a, h->stream), "fields kernel");
     return PFLBM_OK;
 }

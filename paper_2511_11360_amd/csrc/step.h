@@ -231,8 +231,8 @@ __device__ __forceinline__ T stencil_lap(const T* phin) {
     return lap;
 }
 
-// muin: mu_phi at the stencil points (Liang2014 only; the model's MODE_MU pass
-// wrote it for every node), else unused.
+// muin: mu_phi at the stencil points (Liang2014 only; the step kernel computes
+// it from its phi frame), else unused.
 template <class PAIR, int MODEL, class T, bool COLLIDE, class GSink, class HSink>
 __device__ __forceinline__ void node_update(const PhysT<T>& ph, const T* g, const T* h, const T* phin,
                                             const T* muin, const T* pu_prev, T* pu_new, NodeOut<T>& mo,
@@ -873,13 +873,18 @@ __global__ __launch_bounds__(TILE_THREADS[TS]) void k_step(const KArgs a) {
     constexpr int NT = TILE_THREADS[TS];
     constexpr int TX = TILE_NX[TS], TY = TILE_NY[TS];
     static_assert(TX * TY == NT, "one node per thread");
-    constexpr int PW = TX + 2, PSZ = PW * (TY + 2);
-    constexpr int NRING = 2 * PW + 2 * TY;             // halo ring of the tile
-    constexpr int NPL = D3 ? 4 : 1;
+    // Liang2014 needs mu_phi at the stencil points: computed here from phi, on
+    // the tile and a halo of one, so its phi frame reaches two nodes out
+    constexpr bool MUF = MODEL == 4;
+    constexpr int RH = MUF ? 2 : 1;                    // halo of the phi frame
+    constexpr int PW = TX + 2 * RH, PSZ = PW * (TY + 2 * RH);
+    constexpr int NRING = PSZ - TX * TY;               // halo positions of the frame
+    constexpr int ZL = MUF ? 2 : 1;                    // phi planes filled ahead of the node plane
+    constexpr int NPL = D3 ? (MUF ? 5 : 4) : 1;        // phi planes held (ring)
     __shared__ T lphi[NPL * PSZ];
-    constexpr bool MUR = MODEL == 4 && MODE != MODE_MU;   // Liang2014: mu_phi ring beside phi
-    __shared__ T lmu[MUR ? NPL * PSZ : 1];
-    const T* __restrict__ MU = (const T*)a.mu;
+    constexpr int MW = TX + 2, MSZ = MW * (TY + 2);    // mu frame
+    constexpr int NMU = MUF ? (MSZ + NT - 1) / NT : 1; // mu positions per thread
+    __shared__ T lmu[MUF ? (D3 ? 4 : 1) * MSZ : 1];
 
     const int b = (TS == 0 || TS == 3) ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int bx = b % a.ntx, byz = b / a.ntx;
@@ -928,15 +933,36 @@ __global__ __launch_bounds__(TILE_THREADS[TS]) void k_step(const KArgs a) {
         const int r = threadIdx.x + k * NT;
         ring[k] = r < NRING;
         int hx = 0, hy = 0;
-        if (r < PW) { hx = r - 1; hy = -1; }
-        else if (r < 2 * PW) { hx = r - PW - 1; hy = TY; }
-        else if (r < 2 * PW + TY) { hx = -1; hy = r - 2 * PW; }
-        else { hx = TX; hy = r - 2 * PW - TY; }
+        // RH rows above, RH rows below, then RH columns left and right
+        if (r < RH * PW) { hy = r / PW - RH; hx = r % PW - RH; }
+        else if (r < 2 * RH * PW) { const int q = r - RH * PW; hy = TY + q / PW; hx = q % PW - RH; }
+        else if (r < 2 * RH * PW + RH * TY) { const int q = r - 2 * RH * PW; hx = q / TY - RH; hy = q % TY; }
+        else { const int q = r - 2 * RH * PW - RH * TY; hx = TX + q / TY; hy = q % TY; }
         if (!ring[k]) { hx = 0; hy = 0; }
         rcr[k] = make_cross(ghost_coord(x0 + hx, nx, a.bc[0]), ghost_coord(y0 + hy, ny, a.bc[1]), nx, ny, a.bc);
-        ring_lds[k] = (hy + 1) * PW + (hx + 1);
+        ring_lds[k] = (hy + RH) * PW + (hx + RH);
     }
-    const int own_lds = (ly + 1) * PW + (lx + 1);
+    const int own_lds = (ly + RH) * PW + (lx + RH);
+    // phi ring slot of plane zz (zz >= zs - ZL) and mu ring slot (zz >= zs - 1)
+    auto phi_slot = [&](int zz) { return D3 ? (zz - zs + ZL) % NPL : 0; };
+    auto mu_slot = [&](int zz) { return D3 ? (zz - zs + 1) & 3 : 0; };
+    // mu positions this thread computes (mu-frame index threadIdx.x + m NT) and
+    // the phi-frame position of each one's stencil centre: the position itself,
+    // or beyond an x / y wall the clamped node inside (a ghost takes the mu_phi
+    // of the node it mirrors, as a ghost phi takes its phi)
+    int mu_c[NMU];
+    bool mu_on[NMU];
+    if constexpr (MUF) {
+        for (int m = 0; m < NMU; ++m) {
+            const int q = threadIdx.x + m * NT;
+            mu_on[m] = q < MSZ;
+            const int mx = (mu_on[m] ? q % MW : 1) - 1, my = (mu_on[m] ? q / MW : 1) - 1;
+            int cxp = mx, cyp = my;
+            if (a.bc[0] != 0) cxp = min(max(x0 + mx, 0), nx - 1) - x0;
+            if (a.bc[1] != 0) cyp = min(max(y0 + my, 0), ny - 1) - y0;
+            mu_c[m] = (cyp + RH) * PW + (cxp + RH);
+        }
+    }
 
     DiagAcc acc;
     if constexpr (MODE == MODE_DIAG) diag_init(acc);
@@ -974,14 +1000,32 @@ __global__ __launch_bounds__(TILE_THREADS[TS]) void k_step(const KArgs a) {
             if constexpr (MODEL == 2) sr = nl_phi(ph, sr, gam);
             if (ring[k]) lphi[slot * PSZ + ring_lds[k]] = sr;
         }
-        if constexpr (MUR) {
-            // mu_phi of the same positions (ghosts: periodic image or wall mirror)
-            const size_t pb = (size_t)fz.zk[1] * P;
-            lmu[slot * PSZ + own_lds] = MU[pb + (unsigned)ocr.c];
-            for (int k = 0; k < NR; ++k) {
-                const T m = MU[pb + (unsigned)rcr[k].c];
-                if (ring[k]) lmu[slot * PSZ + ring_lds[k]] = m;
-            }
+    };
+
+    // Liang2014: mu_phi of plane zz on the mu frame, from the phi ring, with the
+    // stencil and expression of the chemical potential at a node; beyond a z
+    // wall the stencil is centred on the plane inside
+    auto fill_mu = [&](int zz) {
+        int zc = zz;
+        if constexpr (D3) {
+            if (a.bc[2] != 0) zc = min(max(zz, 0), nz - 1);
+        }
+        const T* pm = lphi + phi_slot(zc - 1) * PSZ;
+        const T* p0 = lphi + phi_slot(zc) * PSZ;
+        const T* pp = lphi + phi_slot(zc + 1) * PSZ;
+        T* mo_ = lmu + mu_slot(zz) * MSZ;
+        for (int m = 0; m < NMU; ++m) {
+            T phin[QG];
+            unroll<QG>([&](auto I) {
+                constexpr int i = I;
+                constexpr int cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
+                const T* pl_ = cz < 0 ? pm : (cz > 0 ? pp : p0);
+                phin[i] = pl_[mu_c[m] + cy * PW + cx];
+            });
+            const T phi = phin[0];
+            const T lap = stencil_lap<GL>(phin);
+            if (mu_on[m])
+                mo_[threadIdx.x + m * NT] = ph.beta4 * phi * (phi - (T)1) * (phi - (T)0.5) - ph.kappa * lap;
         }
     };
 
@@ -1010,22 +1054,6 @@ __global__ __launch_bounds__(TILE_THREADS[TS]) void k_step(const KArgs a) {
         const T* p0 = lphi + s0 * PSZ;
         const T* pp = lphi + sp * PSZ;
         const int o11 = cl.off[1][1];
-        if constexpr (MODE == MODE_MU) {
-            // Liang2014: mu_phi of this node for the step's halo (same stencil)
-            T phin[QG];
-            unroll<QG>([&](auto I) {
-                constexpr int i = I;
-                constexpr int cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
-                const T* pl_ = cz < 0 ? pm : (cz > 0 ? pp : p0);
-                phin[i] = pl_[(ly + 1 + cy) * PW + (lx + 1 + cx)];
-            });
-            const T phi = phin[0];
-            const T lap = stencil_lap<GL>(phin);
-            int so = o11;
-            lane_opaque(so);
-            at<1>((T*)a.mu, z, 0, P, so) = ph.beta4 * phi * (phi - (T)1) * (phi - (T)0.5) - ph.kappa * lap;
-            return;
-        }
         const ZPlanes zp = make_zplanes(z, nz, a.bc[2]);
         // post-streaming g of this node (pulled from x - c_i), decoded
         T g[QG];
@@ -1046,14 +1074,13 @@ __global__ __launch_bounds__(TILE_THREADS[TS]) void k_step(const KArgs a) {
         }
         // phi (and, for Liang2014, mu_phi) at the stencil points
         T phin[QG];
-        T muin[MUR ? QG : 1];
+        T muin[MUF ? QG : 1];
         unroll<QG>([&](auto I) {
             constexpr int i = I;
             constexpr int cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
             const int sl = cz < 0 ? sm : (cz > 0 ? sp : s0);
-            const int off = (ly + 1 + cy) * PW + (lx + 1 + cx);
-            phin[i] = lphi[sl * PSZ + off];
-            if constexpr (MUR) muin[i] = lmu[sl * PSZ + off];
+            phin[i] = lphi[sl * PSZ + (ly + RH + cy) * PW + (lx + RH + cx)];
+            if constexpr (MUF) muin[i] = lmu[mu_slot(z + cz) * MSZ + (ly + 1 + cy) * MW + (lx + 1 + cx)];
         });
         NodeOut<T> mo;
         T pu_new[3];
@@ -1128,37 +1155,61 @@ __global__ __launch_bounds__(TILE_THREADS[TS]) void k_step(const KArgs a) {
     };
 
     T hc[QH];
+    T hq[MUF ? QH : 1];   // own h of plane z + 1 (Liang2014 fills two planes ahead)
     GS gr[QG];
     if constexpr (D3) {
-        // ring of 4 phi planes: plane zz lives in slot (zz - zs + 1) & 3. While a
-        // wave fills plane z + 2, the slowest wave may still read planes z - 1 ..
-        // z + 1, never slot (z + 2) & 3, so one barrier per plane suffices.
-        fill_plane(zs - 1, 0);
-        fill_plane(zs, 1);
-        unroll<QH>([&](auto J) { constexpr int al = J; hc[al] = hn[al]; });
+        // ring of phi planes: plane zz lives in slot phi_slot(zz), filled ZL
+        // planes ahead of the node plane. With 4 slots (ZL = 1): while a wave
+        // fills plane z + 2 the slowest may still read planes z - 1 .. z + 1,
+        // so one barrier per plane suffices. Liang2014 (ZL = 2, 5 slots, a
+        // mu ring of 4): fill phi of z + 2, barrier, mu of z + 1 from phi
+        // z .. z + 2, barrier, node update of z from phi and mu of z - 1 .. z + 1;
+        // the fill of z + 3 then overwrites only phi of z - 2 and the mu pass
+        // of z + 2 only mu of z - 2, which no wave still reads.
+        for (int k = 0; k < 2 * ZL; ++k) {
+            fill_plane(zs - ZL + k, phi_slot(zs - ZL + k));
+            if (k == ZL) unroll<QH>([&](auto J) { constexpr int al = J; hc[al] = hn[al]; });
+        }
+        if constexpr (MUF) {
+            unroll<QH>([&](auto J) { constexpr int al = J; hq[al] = hn[al]; });
+            __syncthreads();
+            fill_mu(zs - 1);
+            fill_mu(zs);
+        }
         for (int zl = zs; zl < ze; ++zl) {
             // the plane index is uniform; readfirstlane keeps the compiler from
             // treating it as per-lane after the divergent node branch (which
             // would move all plane and address arithmetic to 64-bit VALU)
             const int z = __builtin_amdgcn_readfirstlane(zl);
-            const int r = z - zs;
             for (int dy = 0; dy < 3; ++dy)
                 for (int dx = 0; dx < 3; ++dx) lane_opaque(cl.off[dy][dx]);
             lane_opaque(ocr);
             for (int k = 0; k < NR; ++k) lane_opaque(rcr[k]);
-            fill_plane(z + 1, (r + 2) & 3);
+            fill_plane(z + ZL, phi_slot(z + ZL));
             __syncthreads();
-            if (active) {
-                if constexpr (MODE != MODE_MU) pull_g(z, gr);
-                do_node(z, gr, hc, r & 3, (r + 1) & 3, (r + 2) & 3);
+            if constexpr (MUF) {
+                fill_mu(z + 1);
+                __syncthreads();
             }
-            unroll<QH>([&](auto J) { constexpr int al = J; hc[al] = hn[al]; });
+            if (active) {
+                pull_g(z, gr);
+                do_node(z, gr, hc, phi_slot(z - 1), phi_slot(z), phi_slot(z + 1));
+            }
+            if constexpr (MUF) {
+                unroll<QH>([&](auto J) { constexpr int al = J; hc[al] = hq[al]; hq[al] = hn[al]; });
+            } else {
+                unroll<QH>([&](auto J) { constexpr int al = J; hc[al] = hn[al]; });
+            }
         }
     } else {
         fill_plane(0, 0);
         __syncthreads();
+        if constexpr (MUF) {
+            fill_mu(0);
+            __syncthreads();
+        }
         if (active) {
-            if constexpr (MODE != MODE_MU) pull_g(0, gr);
+            pull_g(0, gr);
             do_node(0, gr, hn, 0, 0, 0);
         }
     }
@@ -1197,35 +1248,19 @@ inline hipError_t step_mode(int mode, const KArgs& a, hipStream_t s) {
         case MODE_FIELDS:
             hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_FIELDS, 1, 0>), grid, block, 0, s, a);
             break;
-        case MODE_MU:
-            if constexpr (MODEL == 4) {
-                if (walls) hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_MU, 1, 0>), grid, block, 0, s, a);
-                else hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_MU, 0, 0>), grid, block, 0, s, a);
-            } else {
-                return hipErrorInvalidValue;
-            }
-            break;
         default:
             hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_DIAG, 1, 0>), grid, block, 0, s, a);
     }
     return hipGetLastError();
 }
 
-// resident workgroups per compute unit of the 3-D step kernel (mode MODE_STEP,
-// any tile) or of the Liang2014 mu pass (MODE_MU, tile 0); 0 when the runtime
-// cannot say or the kernel does not exist
+// resident workgroups per compute unit of the 3-D step kernel with this tile
+// (0 when the runtime cannot say)
 template <class PAIR, int MODEL, int PREC, int WALLS>
-inline int step_occupancy_walls(int tile, int mode) {
+inline int step_occupancy_walls(int tile) {
     int n = 0;
     hipError_t e = hipErrorInvalidValue;
     const int bs = TILE_THREADS[tile];
-    if constexpr (PAIR::dim == 3 && MODEL == 4) {
-        if (mode == MODE_MU) {
-            if (tile == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<PAIR, MODEL, PREC, MODE_MU, WALLS, 0>, bs, 0);
-            return e == hipSuccess ? n : 0;
-        }
-    }
-    if (mode != MODE_STEP) return 0;
     if constexpr (PAIR::dim == 3) {
         switch (tile) {
             case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<PAIR, MODEL, PREC, MODE_STEP, WALLS, 0>, bs, 0); break;
@@ -1239,12 +1274,12 @@ inline int step_occupancy_walls(int tile, int mode) {
 }
 
 template <class PAIR, int MODEL>
-inline int step_occupancy(int prec, int tile, int walls, int mode) {
+inline int step_occupancy(int prec, int tile, int walls) {
     switch (prec) {
-        case 0: return walls ? step_occupancy_walls<PAIR, MODEL, 0, 1>(tile, mode) : step_occupancy_walls<PAIR, MODEL, 0, 0>(tile, mode);
-        case 1: return walls ? step_occupancy_walls<PAIR, MODEL, 1, 1>(tile, mode) : step_occupancy_walls<PAIR, MODEL, 1, 0>(tile, mode);
-        case 2: return walls ? step_occupancy_walls<PAIR, MODEL, 2, 1>(tile, mode) : step_occupancy_walls<PAIR, MODEL, 2, 0>(tile, mode);
-        default: return walls ? step_occupancy_walls<PAIR, MODEL, 3, 1>(tile, mode) : step_occupancy_walls<PAIR, MODEL, 3, 0>(tile, mode);
+        case 0: return walls ? step_occupancy_walls<PAIR, MODEL, 0, 1>(tile) : step_occupancy_walls<PAIR, MODEL, 0, 0>(tile);
+        case 1: return walls ? step_occupancy_walls<PAIR, MODEL, 1, 1>(tile) : step_occupancy_walls<PAIR, MODEL, 1, 0>(tile);
+        case 2: return walls ? step_occupancy_walls<PAIR, MODEL, 2, 1>(tile) : step_occupancy_walls<PAIR, MODEL, 2, 0>(tile);
+        default: return walls ? step_occupancy_walls<PAIR, MODEL, 3, 1>(tile) : step_occupancy_walls<PAIR, MODEL, 3, 0>(tile);
     }
 }
 

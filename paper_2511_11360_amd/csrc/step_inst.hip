@@ -22,8 +22,8 @@ hipError_t PFK_CAT(launch_step_p, PFK_PAIR, _m, PFK_MODEL)(int precision, int mo
     return step_prec<InstPair, PFK_MODEL>(precision, mode, a, s);
 }
 
-int PFK_CAT(occupancy_step_p, PFK_PAIR, _m, PFK_MODEL)(int precision, int tile, int walls, int mode) {
-    return step_occupancy<InstPair, PFK_MODEL>(precision, tile, walls, mode);
+int PFK_CAT(occupancy_step_p, PFK_PAIR, _m, PFK_MODEL)(int precision, int tile, int walls) {
+    return step_occupancy<InstPair, PFK_MODEL>(precision, tile, walls);
 }
 
 }  // namespace pfk
