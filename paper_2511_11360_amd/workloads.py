@@ -161,29 +161,33 @@ def sheared_droplet_3d(n=128, R=24.0, uw=0.02, Ca=0.2, W=4.0, M=0.05, nu=1.0 / 6
 
 def random_spectrum_velocity(n, k0=4.0, urms=0.04, seed=5):
     """Random-phase solenoidal field with E(k) ~ k^4 exp(-2 (k/k0)^2), scaled to
-    a per-component rms of urms (numpy FFT, seeded)."""
+    a per-component rms of urms (seeded). Phases are drawn on the modes with
+    |k_x|, |k_y|, |k_z| <= kmax = min(n/2 - 1, ceil(8 k0)) only (beyond 8 k0,
+    E(k) is below 1e-40 of its peak), then each component is the real part of
+    its zero-padded inverse FFT (multi-threaded)."""
+    import os
+    import scipy.fft as sfft
     rng = np.random.default_rng(seed)
-    kf = np.fft.fftfreq(n, d=1.0 / n)
-    KX, KY, KZ = np.meshgrid(kf, kf, kf, indexing="ij")
+    km = int(min(n // 2 - 1, math.ceil(8 * k0)))
+    kb = np.arange(-km, km + 1, dtype=float)
+    KX, KY, KZ = kb[:, None, None], kb[None, :, None], kb[None, None, :]
     K2 = KX ** 2 + KY ** 2 + KZ ** 2
-    K = np.sqrt(K2)
-    amp = np.zeros_like(K)
-    nz_ = K > 0
+    nz_ = K2 > 0
+    amp = np.zeros_like(K2)
     # shell energy E(k) spread over 4 pi k^2 modes -> |u_k| ~ sqrt(E / k^2)
-    amp[nz_] = np.sqrt(K[nz_] ** 4 * np.exp(-2 * (K[nz_] / k0) ** 2) / K2[nz_])
-    comps = []
-    for _ in range(3):
-        ph = rng.uniform(0, 2 * np.pi, size=K.shape)
-        comps.append(amp * np.exp(1j * ph))
-    comps = np.array(comps)
+    amp[nz_] = np.sqrt(K2[nz_] ** 2 * np.exp(-2 * K2[nz_] / (k0 * k0)) / K2[nz_])
+    comps = np.array([amp * np.exp(1j * rng.uniform(0, 2 * np.pi, size=K2.shape)) for _ in range(3)])
     # project out the compressive part: u_k <- u_k - k (k . u_k) / k^2
-    kvec = np.array([KX, KY, KZ])
-    with np.errstate(invalid="ignore", divide="ignore"):
-        kd = (kvec * comps).sum(axis=0) / np.where(nz_, K2, 1.0)
-    comps = comps - kvec * kd
-    u = np.real(np.fft.ifftn(comps, axes=(1, 2, 3)))
+    kd = (KX * comps[0] + KY * comps[1] + KZ * comps[2]) / np.where(nz_, K2, 1.0)
+    comps = comps - np.array([KX * kd, KY * kd, KZ * kd])
+    idx = np.arange(-km, km + 1) % n
+    u = np.empty((3, n, n, n))
+    full = np.zeros((n, n, n), dtype=np.complex128)
+    for c in range(3):
+        full[np.ix_(idx, idx, idx)] = comps[c]
+        u[c] = sfft.ifftn(full, workers=os.cpu_count() or 1).real
     u *= urms / np.sqrt((u * u).mean(axis=(1, 2, 3)).mean())
-    # arrays are (k, j, i) -> (z, y, x) for the (x, y, z) meshgrid above
+    # arrays are (k_x, k_y, k_z) -> (z, y, x)
     return np.ascontiguousarray(np.transpose(u, (0, 3, 2, 1)))
 
 
