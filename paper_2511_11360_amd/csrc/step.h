@@ -1164,8 +1164,8 @@ __global__ __launch_bounds__(TILE_THREADS[TS]) void k_step(const KArgs a) {
         // so one barrier per plane suffices. Liang2014 (ZL = 2, 5 slots, a
         // mu ring of 4): fill phi of z + 2, barrier, mu of z + 1 from phi
         // z .. z + 2, barrier, node update of z from phi and mu of z - 1 .. z + 1;
-        // the fill of z + 3 then overwrites only phi of z - 2 and the mu pass
-        // of z + 2 only mu of z - 2, which no wave still reads.
+        // the fill of z + 3 then overwrites only phi of z - 2 and mu of z + 2
+        // only mu of z - 2, which no wave still reads.
         for (int k = 0; k < 2 * ZL; ++k) {
             fill_plane(zs - ZL + k, phi_slot(zs - ZL + k));
             if (k == ZL) unroll<QH>([&](auto J) { constexpr int al = J; hc[al] = hn[al]; });

@@ -177,8 +177,8 @@ def test_automatic_zblock_matches_fixed_depth(model, precision):
     40 x 128 x 50 box gets z blocks sized to one round over the compute units
     (7 planes on 256 units, the last block 1 plane); every population must
     equal the run with 5-plane blocks bit for bit, since each node takes the
-    same arithmetic whatever block it falls in (Liang2014: the mu pass takes
-    its own automatic depth too)."""
+    same arithmetic whatever block it falls in (Liang2014 included: its
+    kernel forms mu_phi on each block's own halo)."""
     d, phi, u = small_3d(nx=40, ny=128, nz=50, R=9.0, model=model)
     out = []
     for zb in (0, 5):
