@@ -97,15 +97,16 @@ extern "C" {
 #define PFLBM_MIXED_FP16  2  /* g stored as fp16 of 4096 g_i / w_i, h float32; float32 arithmetic */
 #define PFLBM_MIXED_BF16  3  /* g stored as bf16 of g_i / w_i, h float32; float32 arithmetic */
 
-/* step-kernel tile: x nodes by y rows per 256-thread workgroup (3-D; the
-   2-D lattice always uses 64 x 4) */
-#define PFLBM_TILE_AUTO   0  /* 256x4 for the fp16/bf16-stored forms on D3Q19
-                                (64x4 for D3Q27 and PFLBM_L14), 256x1 for fp32,
-                                128x2 for fp64 (narrower when nx is) */
-#define PFLBM_TILE_64x4   1  /* workgroups ordered so each XCD sweeps a contiguous run */
-#define PFLBM_TILE_128x2  2  /* hardware workgroup order */
-#define PFLBM_TILE_256x1  3  /* hardware workgroup order */
-#define PFLBM_TILE_256x4  4  /* 1024-thread workgroups, ordered as 64x4 */
+/* step-kernel tile: x nodes by y rows per workgroup, one node per thread
+   (3-D; the 2-D lattice always uses 64 x 4). Results do not depend on it. */
+#define PFLBM_TILE_AUTO   0  /* 256x4 for float32 and the fp16/bf16-stored forms
+                                at nx >= 256 (64x4 for PFLBM_L14 on D3Q27),
+                                128x2 for float64; narrower when nx is */
+#define PFLBM_TILE_64x4   1  /* 256 threads; workgroups ordered so each XCD
+                                sweeps a contiguous run */
+#define PFLBM_TILE_128x2  2  /* 256 threads, hardware workgroup order */
+#define PFLBM_TILE_256x1  3  /* 256 threads, hardware workgroup order */
+#define PFLBM_TILE_256x4  4  /* 1024 threads, ordered as 64x4 */
 
 /* boundary per axis */
 #define PFLBM_PERIODIC 0
