@@ -52,6 +52,13 @@ std::string validate(const pflbm_params& p) {
     const long long nodes = (long long)p.nx * p.ny * p.nz;
     if (nodes > 0x7fffffffLL) return "more than 2^31-1 nodes";
     if ((long long)p.nx * p.ny > 0x7fff0000LL) return "more than 2^31 nodes per z plane";
+    {
+        // kernels address a population plane as a scalar base plus a 32-bit
+        // byte offset: one plane (padded to 64 nodes) must stay below 4 GiB
+        const long long esz = p.precision == PFLBM_FP64 ? 8 : 4;
+        const long long padded = ((long long)p.nx * p.ny + 63) / 64 * 64;
+        if (padded * esz > 0xffffffffLL) return "one z plane of a population spans 4 GiB or more";
+    }
     int walls = 0;
     for (int a = 0; a < 3; ++a) {
         if (p.bc[a] != PFLBM_PERIODIC && p.bc[a] != PFLBM_WALL) return "bc must be PFLBM_PERIODIC or PFLBM_WALL";

@@ -105,6 +105,24 @@ def test_invalid_tile_rejected():
         assert (st == 0) == ok, tile
 
 
+def test_size_limits():
+    """Limits of the addressing: fewer than 2^31 nodes, and one z plane of a
+    population (padded to 64 nodes) below 4 GiB, since kernels address it as a
+    scalar base plus a 32-bit byte offset (float64: 2^29 nodes per plane)."""
+    cases = [
+        (dict(nx=23168, ny=23168), "fp64", True),      # 536 739 840 nodes, padded x 8 < 2^32
+        (dict(nx=23171, ny=23171), "fp64", False),     # 536 895 241 x 8 > 2^32
+        (dict(nx=32767, ny=32768), "fp32", True),      # 1 073 709 056 x 4 < 2^32
+        (dict(nx=32768, ny=32768), "fp32", False),     # 2^30 x 4 = 2^32
+        (dict(nx=32768, ny=32768), "mixed_fp16", False),
+        (dict(lattice="D3Q19_D3Q7", nx=1290, ny=1290, nz=1290), "fp32", True),   # 2.147e9 < 2^31 nodes
+        (dict(lattice="D3Q19_D3Q7", nx=1291, ny=1291, nz=1291), "fp32", False),  # over 2^31 - 1 nodes
+    ]
+    for kw, prec, ok in cases:
+        st, _ = _bytes(wl.base_params(**kw), precision=prec)
+        assert (st == 0) == ok, (kw, prec)
+
+
 def test_strerror():
     L = P.lib()
     assert L.pflbm_strerror(P.PFLBM_EUNSTABLE).decode().startswith("numerical")
