@@ -10,10 +10,10 @@ namespace pfk {
 constexpr int BLOCK = 256;      // threads per workgroup (step tiles 0-2, reductions)
 // step tiles (x nodes, y rows, threads) by tile index; fields / diagnostics
 // use tile 0; tile 3 is a 1024-thread workgroup
-constexpr int NTILES = 4;
-constexpr int TILE_NX[NTILES] = {64, 128, 256, 256};
-constexpr int TILE_NY[NTILES] = {4, 2, 1, 4};
-constexpr int TILE_THREADS[NTILES] = {256, 256, 256, 1024};
+constexpr int NTILES = 5;
+constexpr int TILE_NX[NTILES] = {64, 128, 256, 256, 128};
+constexpr int TILE_NY[NTILES] = {4, 2, 1, 4, 8};
+constexpr int TILE_THREADS[NTILES] = {256, 256, 256, 1024, 1024};
 constexpr int NDIAG = 12;       // per-block partial diagnostics (see kernels.hip)
 constexpr int GAMMA_ZB = 16;    // z planes per workgroup of the nonlocal multiplier sums
 constexpr int MAXQ = 27;

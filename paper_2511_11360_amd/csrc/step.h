@@ -886,7 +886,7 @@ __global__ __launch_bounds__(TILE_THREADS[TS]) void k_step(const KArgs a) {
     constexpr int NMU = MUF ? (MSZ + NT - 1) / NT : 1; // mu positions per thread
     __shared__ T lmu[MUF ? (D3 ? 4 : 1) * MSZ : 1];
 
-    const int b = (TS == 0 || TS == 3) ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int b = (TS == 0 || TS >= 3) ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int bx = b % a.ntx, byz = b / a.ntx;
     const int by = byz % a.nty, bz = byz / a.nty;
     const int x0 = bx * TX, y0 = by * TY;
@@ -1241,6 +1241,11 @@ inline hipError_t step_mode(int mode, const KArgs& a, hipStream_t s) {
                     else hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_STEP, 0, 3>), grid, block, 0, s, a);
                     break;
                 }
+                if (a.tile == 4) {
+                    if (walls) hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_STEP, 1, 4>), grid, block, 0, s, a);
+                    else hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_STEP, 0, 4>), grid, block, 0, s, a);
+                    break;
+                }
             }
             if (walls) hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_STEP, 1, 0>), grid, block, 0, s, a);
             else hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_STEP, 0, 0>), grid, block, 0, s, a);
@@ -1267,6 +1272,7 @@ inline int step_occupancy_walls(int tile) {
             case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<PAIR, MODEL, PREC, MODE_STEP, WALLS, 1>, bs, 0); break;
             case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<PAIR, MODEL, PREC, MODE_STEP, WALLS, 2>, bs, 0); break;
             case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<PAIR, MODEL, PREC, MODE_STEP, WALLS, 3>, bs, 0); break;
+            case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<PAIR, MODEL, PREC, MODE_STEP, WALLS, 4>, bs, 0); break;
             default: break;
         }
     }

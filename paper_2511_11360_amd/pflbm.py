@@ -114,7 +114,7 @@ class PflbmError(RuntimeError):
         self.status = status
 
 
-TILES = {"auto": 0, "64x4": 1, "128x2": 2, "256x1": 3, "256x4": 4}
+TILES = {"auto": 0, "64x4": 1, "128x2": 2, "256x1": 3, "256x4": 4, "128x8": 5}
 
 
 def make_params(d, precision="fp64", check_interval=0, zblock=0, tile="auto"):

@@ -98,7 +98,7 @@ def test_d3q27_state_bytes_and_invalid_lattice():
 
 def test_invalid_tile_rejected():
     d = wl.base_params(lattice="D3Q19_D3Q7", nx=32, ny=32, nz=32)
-    for tile, ok in ((0, True), (3, True), (4, True), (5, False), (-1, False)):
+    for tile, ok in ((0, True), (3, True), (4, True), (5, True), (6, False), (-1, False)):
         p = P.make_params(d, "fp32", tile=tile)
         n = ctypes.c_size_t()
         st = P.lib().pflbm_state_bytes(ctypes.byref(p), ctypes.byref(n))

@@ -134,6 +134,7 @@ def test_liang14_rayleigh_taylor_walls():
 
 
 @pytest.mark.parametrize("lattice,tile,steps", [("D3Q19_D3Q7", "auto", 300), ("D3Q19_D3Q7", "256x1", 300),
+                                                ("D3Q19_D3Q7", "256x4", 300), ("D3Q19_D3Q7", "128x8", 300),
                                                 ("D3Q27_D3Q7", "128x2", 200)])
 def test_liang14_3d_vortex_droplet(lattice, tile, steps):
     d, phi, u = small_3d(model="L14", lattice=lattice, s_other=1.3)

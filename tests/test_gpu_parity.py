@@ -142,13 +142,14 @@ def _tile_cases():
     return _TILE_CASES
 
 
-@pytest.mark.parametrize("tile", ["64x4", "128x2", "256x1", "256x4"])
+@pytest.mark.parametrize("tile", ["64x4", "128x2", "256x1", "256x4", "128x8"])
 def test_step_tiles(tile):
     """Every step-kernel tile shape against the oracle, in float64: a ragged
     periodic box (150 x 26 x 25: x and y tails in every shape, ragged last z
     block) and moving walls (70 x 22 x 24)."""
-    # 256x4 is 1024 threads: float64 at that size runs with spilled registers
-    # (slow, still exact); the automatic choice uses it for float32 and 16-bit g
+    # 256x4 and 128x8 are 1024 threads: float64 there runs with spilled
+    # registers (slow, still exact); the automatic choice uses 256x4 for float32
+    # and 16-bit g, 128x8 for Liang2014 with 16-bit g
     for name, (d, phi, u, steps, st) in _tile_cases().items():
         s = gpu_run(d, phi, u, steps, tile=tile, zblock=7)
         g, h = gpu_dists(s)
