@@ -218,6 +218,50 @@ __device__ __forceinline__ void ch_collide(const PhysT<T>& ph, const T* h, T phi
     });
 }
 
+// Sums below start from their first term, not from zero: 0 + x is not folded
+// to x (it differs for x = -0), so a zero start costs one add per sum.
+template <bool FIRST, class T>
+__device__ __forceinline__ void add_term(T& s, T x) {
+    if constexpr (FIRST) s = x;
+    else s += x;
+}
+
+// first opposite pair (index into L::pf) whose velocity has c_a != 0, or
+// c_a c_b != 0 for a != b; -1 if there is none
+template <class L>
+__host__ __device__ constexpr int first_pair(int a, int b) {
+    for (int k = 0; k < L::NP; ++k)
+        if ((a == b ? L::c(L::pf(k), a) : L::c(L::pf(k), a) * L::c(L::pf(k), b)) != 0) return k;
+    return -1;
+}
+
+// c . v for a compile-time velocity c (its nonzero components only)
+template <int cx, int cy, int cz, class T>
+__device__ __forceinline__ T cdot(const T* v) {
+    T r = (T)0;
+    if constexpr (cx != 0) r = (T)cx * v[0];
+    if constexpr (cy != 0) add_term<cx == 0>(r, (T)cy * v[1]);
+    if constexpr (cz != 0) add_term<cx == 0 && cy == 0>(r, (T)cz * v[2]);
+    return r;
+}
+
+// projection of velocity c on the stress rows, weighted by the row amplitudes:
+// 3-D rows 3 c_x^2 - c^2, c_y^2 - c_z^2, c_x c_y, c_y c_z, c_x c_z; 2-D rows
+// c_x^2 - c_y^2, c_x c_y
+template <int cx, int cy, int cz, bool D3, class T>
+__device__ __forceinline__ T stress_proj(T A0, T A1, T Axy, T Ayz, T Axz) {
+    constexpr int q0 = D3 ? 3 * cx * cx - (cx * cx + cy * cy + cz * cz) : cx * cx - cy * cy;
+    constexpr int q1 = D3 ? cy * cy - cz * cz : 0;
+    constexpr int qxy = cx * cy, qyz = D3 ? cy * cz : 0, qxz = D3 ? cx * cz : 0;
+    T r = (T)0;
+    if constexpr (q0 != 0) r = (T)q0 * A0;
+    if constexpr (q1 != 0) add_term<q0 == 0>(r, (T)q1 * A1);
+    if constexpr (qxy != 0) add_term<q0 == 0 && q1 == 0>(r, (T)qxy * Axy);
+    if constexpr (qyz != 0) add_term<q0 == 0 && q1 == 0 && qxy == 0>(r, (T)qyz * Ayz);
+    if constexpr (qxz != 0) add_term<q0 == 0 && q1 == 0 && qxy == 0 && qyz == 0>(r, (T)qxz * Axz);
+    return r;
+}
+
 // lap phi = 6 sum_i w_i (phi(x + c_i) - phi(x)) over opposite pairs (the same
 // order as the node update)
 template <class GL, class T>
@@ -225,8 +269,9 @@ __device__ __forceinline__ T stencil_lap(const T* phin) {
     const T phi = phin[0];
     T lap = (T)0;
     unroll<GL::NP>([&](auto K) {
-        constexpr int i = GL::pf(K), o = GL::opp(i);
-        lap += (T)(6.0 * GL::w(i)) * ((phin[i] - phi) + (phin[o] - phi));
+        constexpr int k = K;
+        constexpr int i = GL::pf(k), o = GL::opp(i);
+        add_term<k == 0>(lap, (T)(6.0 * GL::w(i)) * ((phin[i] - phi) + (phin[o] - phi)));
     });
     return lap;
 }
@@ -246,13 +291,15 @@ __device__ __forceinline__ void node_update(const PhysT<T>& ph, const T* g, cons
     T gr[3] = {(T)0, (T)0, (T)0};
     T lap = (T)0;
     unroll<GL::NP>([&](auto K) {
-        constexpr int i = GL::pf(K), o = GL::opp(i);
+        constexpr int k = K;
+        constexpr int i = GL::pf(k), o = GL::opp(i);
         const T dp = phin[i] - phin[o];
         unroll<3>([&](auto A) {
             constexpr int a = A;
-            if constexpr (GL::c(i, a) != 0) gr[a] += (T)(3.0 * GL::w(i) * GL::c(i, a)) * dp;
+            if constexpr (GL::c(i, a) != 0)
+                add_term<k == first_pair<GL>(a, a)>(gr[a], (T)(3.0 * GL::w(i) * GL::c(i, a)) * dp);
         });
-        lap += (T)(6.0 * GL::w(i)) * ((phin[i] - phi) + (phin[o] - phi));
+        add_term<k == 0>(lap, (T)(6.0 * GL::w(i)) * ((phin[i] - phi) + (phin[o] - phi)));
     });
 
     const T dRho = ph.dRho;
@@ -269,16 +316,17 @@ __device__ __forceinline__ void node_update(const PhysT<T>& ph, const T* g, cons
     T j[3] = {(T)0, (T)0, (T)0};
     T m2[6] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
     unroll<GL::NP>([&](auto K) {
-        constexpr int i = GL::pf(K), o = GL::opp(i);
+        constexpr int k = K;
+        constexpr int i = GL::pf(k), o = GL::opp(i);
         constexpr int cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
         const T s = g[i] + g[o], d = g[i] - g[o];
         ps += s;
-        if constexpr (cx != 0) { j[0] += (T)cx * d; m2[0] += s; }
-        if constexpr (cy != 0) { j[1] += (T)cy * d; m2[1] += s; }
-        if constexpr (cz != 0) { j[2] += (T)cz * d; m2[2] += s; }
-        if constexpr (cx * cy != 0) m2[3] += (T)(cx * cy) * s;
-        if constexpr (cy * cz != 0) m2[4] += (T)(cy * cz) * s;
-        if constexpr (cx * cz != 0) m2[5] += (T)(cx * cz) * s;
+        if constexpr (cx != 0) { add_term<k == first_pair<GL>(0, 0)>(j[0], (T)cx * d); add_term<k == first_pair<GL>(0, 0)>(m2[0], s); }
+        if constexpr (cy != 0) { add_term<k == first_pair<GL>(1, 1)>(j[1], (T)cy * d); add_term<k == first_pair<GL>(1, 1)>(m2[1], s); }
+        if constexpr (cz != 0) { add_term<k == first_pair<GL>(2, 2)>(j[2], (T)cz * d); add_term<k == first_pair<GL>(2, 2)>(m2[2], s); }
+        if constexpr (cx * cy != 0) add_term<k == first_pair<GL>(0, 1)>(m2[3], (T)(cx * cy) * s);
+        if constexpr (cy * cz != 0) add_term<k == first_pair<GL>(1, 2)>(m2[4], (T)(cy * cz) * s);
+        if constexpr (cx * cz != 0) add_term<k == first_pair<GL>(0, 2)>(m2[5], (T)(cx * cz) * s);
     });
 
     if constexpr (MODEL == 4) {
@@ -352,24 +400,8 @@ __device__ __forceinline__ void node_update(const PhysT<T>& ph, const T* g, cons
             constexpr int i = GL::pf(K), o = GL::opp(i);
             constexpr int cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
             constexpr T w = (T)GL::w(i);
-            T cu = (T)0, cF = (T)0, cA = (T)0;
-            if constexpr (cx != 0) { cu += (T)cx * u[0]; cF += (T)cx * Fp[0]; cA += (T)cx * A[0]; }
-            if constexpr (cy != 0) { cu += (T)cy * u[1]; cF += (T)cy * Fp[1]; cA += (T)cy * A[1]; }
-            if constexpr (cz != 0) { cu += (T)cz * u[2]; cF += (T)cz * Fp[2]; cA += (T)cz * A[2]; }
-            T P = (T)0;
-            if constexpr (D3) {
-                constexpr int q0 = 3 * cx * cx - (cx * cx + cy * cy + cz * cz);
-                constexpr int q1 = cy * cy - cz * cz;
-                if constexpr (q0 != 0) P += (T)q0 * A0;
-                if constexpr (q1 != 0) P += (T)q1 * A1;
-                if constexpr (cx * cy != 0) P += (T)(cx * cy) * Axy;
-                if constexpr (cy * cz != 0) P += (T)(cy * cz) * Ayz;
-                if constexpr (cx * cz != 0) P += (T)(cx * cz) * Axz;
-            } else {
-                constexpr int q0 = cx * cx - cy * cy;
-                if constexpr (q0 != 0) P += (T)q0 * A0;
-                if constexpr (cx * cy != 0) P += (T)(cx * cy) * Axy;
-            }
+            const T cu = cdot<cx, cy, cz>(u), cF = cdot<cx, cy, cz>(Fp), cA = cdot<cx, cy, cz>(A);
+            const T P = stress_proj<cx, cy, cz, D3>(A0, A1, Axy, Ayz, Axz);
             const T E = w * (p3 + kin0 + rho * (T)4.5 * cu * cu);
             const T O = w * (T)3 * rho * cu;
             const T Ge = w * ((T)4.5 * cu * cu - (T)1.5 * usq), Go = w * (T)3 * cu;   // Gamma = Ge +/- Go
@@ -444,24 +476,8 @@ __device__ __forceinline__ void node_update(const PhysT<T>& ph, const T* g, cons
             constexpr int i = GL::pf(K), o = GL::opp(i);
             constexpr int cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
             constexpr T w = (T)GL::w(i);
-            T cu = (T)0, cf = (T)0, cr = (T)0;
-            if constexpr (cx != 0) { cu += (T)cx * u[0]; cf += (T)cx * F[0]; cr += (T)cx * grho[0]; }
-            if constexpr (cy != 0) { cu += (T)cy * u[1]; cf += (T)cy * F[1]; cr += (T)cy * grho[1]; }
-            if constexpr (cz != 0) { cu += (T)cz * u[2]; cf += (T)cz * F[2]; cr += (T)cz * grho[2]; }
-            T P = (T)0;
-            if constexpr (D3) {
-                constexpr int q0 = 3 * cx * cx - (cx * cx + cy * cy + cz * cz);
-                constexpr int q1 = cy * cy - cz * cz;
-                if constexpr (q0 != 0) P += (T)q0 * A0;
-                if constexpr (q1 != 0) P += (T)q1 * A1;
-                if constexpr (cx * cy != 0) P += (T)(cx * cy) * Axy;
-                if constexpr (cy * cz != 0) P += (T)(cy * cz) * Ayz;
-                if constexpr (cx * cz != 0) P += (T)(cx * cz) * Axz;
-            } else {
-                constexpr int q0 = cx * cx - cy * cy;
-                if constexpr (q0 != 0) P += (T)q0 * A0;
-                if constexpr (cx * cy != 0) P += (T)(cx * cy) * Axy;
-            }
+            const T cu = cdot<cx, cy, cz>(u), cf = cdot<cx, cy, cz>(F), cr = cdot<cx, cy, cz>(grho);
+            const T P = stress_proj<cx, cy, cz, D3>(A0, A1, Axy, Ayz, Axz);
             const T E = w * (p3 + kin0 + rho * (T)4.5 * cu * cu);   // even part of f_eq
             const T O = w * (T)3 * rho * cu;                         // odd part
             const T Fe = (T)3 * w * cu * cr, Fo = (T)3 * w * cf;     // even / odd parts of F
@@ -586,24 +602,8 @@ __device__ __forceinline__ void node_update(const PhysT<T>& ph, const T* g, cons
         constexpr int i = GL::pf(K), o = GL::opp(i);
         constexpr int cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
         constexpr T w = (T)GL::w(i);
-        T cu = (T)0, cf = (T)0;
-        if constexpr (cx != 0) { cu += (T)cx * u[0]; cf += (T)cx * F[0]; }
-        if constexpr (cy != 0) { cu += (T)cy * u[1]; cf += (T)cy * F[1]; }
-        if constexpr (cz != 0) { cu += (T)cz * u[2]; cf += (T)cz * F[2]; }
-        T P = (T)0;
-        if constexpr (D3) {
-            constexpr int q0 = 3 * cx * cx - (cx * cx + cy * cy + cz * cz);
-            constexpr int q1 = cy * cy - cz * cz;
-            if constexpr (q0 != 0) P += (T)q0 * A0;
-            if constexpr (q1 != 0) P += (T)q1 * A1;
-            if constexpr (cx * cy != 0) P += (T)(cx * cy) * Axy;
-            if constexpr (cy * cz != 0) P += (T)(cy * cz) * Ayz;
-            if constexpr (cx * cz != 0) P += (T)(cx * cz) * Axz;
-        } else {
-            constexpr int q0 = cx * cx - cy * cy;
-            if constexpr (q0 != 0) P += (T)q0 * A0;
-            if constexpr (cx * cy != 0) P += (T)(cx * cy) * Axy;
-        }
+        const T cu = cdot<cx, cy, cz>(u), cf = cdot<cx, cy, cz>(F);
+        const T P = stress_proj<cx, cy, cz, D3>(A0, A1, Axy, Ayz, Axz);
         // g_eq = E +/- O with E = w (aeq + 4.5 (c.u)^2), O = 3 w c.u; F_i = +/- w c.F ...
         const T E = w * (aeq + (T)4.5 * cu * cu);
         const T base = so * E - dS * P;
