@@ -100,9 +100,9 @@ extern "C" {
 /* step-kernel tile: x nodes by y rows per workgroup, one node per thread
    (3-D; the 2-D lattice always uses 64 x 4). Results do not depend on it. */
 #define PFLBM_TILE_AUTO   0  /* 256x4 for float32 and the fp16/bf16-stored forms
-                                at nx >= 256 (128x8 for PFLBM_L14 with 16-bit g
-                                on D3Q19, 64x4 for PFLBM_L14 on D3Q27), 128x2
-                                for float64; narrower when nx is */
+                                at nx >= 256 (PFLBM_L14 with 16-bit g: 128x8 on
+                                D3Q19, 64x4 on D3Q27), 128x2 for float64;
+                                narrower when nx is */
 #define PFLBM_TILE_64x4   1  /* 256 threads; workgroups ordered so each XCD
                                 sweeps a contiguous run */
 #define PFLBM_TILE_128x2  2  /* 256 threads, hardware workgroup order */

@@ -122,6 +122,15 @@ __host__ __device__ constexpr double stress_norm_off() {
     }
     return s;
 }
+// Their inverses as compile-time constants: the norm functions loop over the
+// velocity table, and used in ordinary expressions they are not always folded
+// (on D3Q27 the loop stayed in the kernel, run for every plane).
+template <class L, int DIM>
+struct StressNorms {
+    static constexpr double inv_d0 = 1.0 / stress_norm_diag0<L, DIM>();
+    static constexpr double inv_d1 = 1.0 / stress_norm_diag1<L>();
+    static constexpr double inv_off = 1.0 / stress_norm_off<L>();
+};
 static_assert(stress_norm_diag0<D3Q19, 3>() == 36.0 && stress_norm_diag1<D3Q19>() == 12.0 &&
               stress_norm_off<D3Q19>() == 4.0, "D3Q19 stress norms");
 static_assert(stress_norm_off<D3Q27>() == 12.0, "D3Q27 stress norm");

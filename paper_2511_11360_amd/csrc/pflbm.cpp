@@ -116,14 +116,14 @@ Layout make_layout(const pflbm_params& p) {
     // step tile: measured fastest per storage form on the 256^3 droplet case;
     // no wider than nx needs. 256 x 4 (1024 threads, XCD runs) allows 128
     // registers per thread: the float32 and fp16 / bf16-stored kernels fit
-    // (90-128) except Liang2014 on D3Q27 (its mu frame spills: 64 x 4);
-    // float64 needs 168-227 and takes 128 x 2. Liang2014 with 16-bit g on
-    // D3Q19 takes 128 x 8: its phi frame reaches two nodes out, and the
+    // (90-128) except Liang2014 on D3Q27, whose 16-bit form runs faster in
+    // 64 x 4; float64 needs 168-227 and takes 128 x 2. Liang2014 with 16-bit
+    // g on D3Q19 takes 128 x 8: its phi frame reaches two nodes out, and the
     // taller tile has a quarter less frame per node (6 % faster).
     int t = 0;
     if (d3) {
-        const bool fits = !(p.model == PFLBM_L14 && p.lattice == PFLBM_D3Q27_D3Q7);
         const bool half = p.precision == PFLBM_MIXED_FP16 || p.precision == PFLBM_MIXED_BF16;
+        const bool fits = !(p.model == PFLBM_L14 && p.lattice == PFLBM_D3Q27_D3Q7 && half);
         if (p.tile != PFLBM_TILE_AUTO) t = p.tile - PFLBM_TILE_64x4;
         else if (p.precision == PFLBM_FP64) t = p.nx > 64 ? 1 : 0;
         else if (half && p.model == PFLBM_L14 && p.lattice == PFLBM_D3Q19_D3Q7 && p.nx >= 128) t = 4;

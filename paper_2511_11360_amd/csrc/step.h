@@ -380,15 +380,15 @@ __device__ __forceinline__ void node_update(const PhysT<T>& ph, const T* g, cons
         const T pxy = pi(0, 1, m2[3]), pyz = pi(1, 2, m2[4]), pxz = pi(0, 2, m2[5]);
         T A0, A1, Axy, Ayz, Axz;
         if constexpr (D3) {
-            A0 = ((T)2 * pxx - pyy - pzz) * (T)(1.0 / stress_norm_diag0<GL, 3>());
-            A1 = (pyy - pzz) * (T)(1.0 / stress_norm_diag1<GL>());
-            Axy = pxy * (T)(1.0 / stress_norm_off<GL>());
-            Ayz = pyz * (T)(1.0 / stress_norm_off<GL>());
-            Axz = pxz * (T)(1.0 / stress_norm_off<GL>());
+            A0 = ((T)2 * pxx - pyy - pzz) * (T)StressNorms<GL, 3>::inv_d0;
+            A1 = (pyy - pzz) * (T)StressNorms<GL, 3>::inv_d1;
+            Axy = pxy * (T)StressNorms<GL, PAIR::dim>::inv_off;
+            Ayz = pyz * (T)StressNorms<GL, PAIR::dim>::inv_off;
+            Axz = pxz * (T)StressNorms<GL, PAIR::dim>::inv_off;
         } else {
-            A0 = (pxx - pyy) * (T)(1.0 / stress_norm_diag0<GL, 2>());
+            A0 = (pxx - pyy) * (T)StressNorms<GL, 2>::inv_d0;
             A1 = (T)0;
-            Axy = pxy * (T)(1.0 / stress_norm_off<GL>());
+            Axy = pxy * (T)StressNorms<GL, PAIR::dim>::inv_off;
             Ayz = (T)0;
             Axz = (T)0;
         }
@@ -458,15 +458,15 @@ __device__ __forceinline__ void node_update(const PhysT<T>& ph, const T* g, cons
         const T pxy = pi(0, 1, m2[3]), pyz = pi(1, 2, m2[4]), pxz = pi(0, 2, m2[5]);
         T A0, A1, Axy, Ayz, Axz;
         if constexpr (D3) {
-            A0 = ((T)2 * pxx - pyy - pzz) * (T)(1.0 / stress_norm_diag0<GL, 3>());
-            A1 = (pyy - pzz) * (T)(1.0 / stress_norm_diag1<GL>());
-            Axy = pxy * (T)(1.0 / stress_norm_off<GL>());
-            Ayz = pyz * (T)(1.0 / stress_norm_off<GL>());
-            Axz = pxz * (T)(1.0 / stress_norm_off<GL>());
+            A0 = ((T)2 * pxx - pyy - pzz) * (T)StressNorms<GL, 3>::inv_d0;
+            A1 = (pyy - pzz) * (T)StressNorms<GL, 3>::inv_d1;
+            Axy = pxy * (T)StressNorms<GL, PAIR::dim>::inv_off;
+            Ayz = pyz * (T)StressNorms<GL, PAIR::dim>::inv_off;
+            Axz = pxz * (T)StressNorms<GL, PAIR::dim>::inv_off;
         } else {
-            A0 = (pxx - pyy) * (T)(1.0 / stress_norm_diag0<GL, 2>());
+            A0 = (pxx - pyy) * (T)StressNorms<GL, 2>::inv_d0;
             A1 = (T)0;
-            Axy = pxy * (T)(1.0 / stress_norm_off<GL>());
+            Axy = pxy * (T)StressNorms<GL, PAIR::dim>::inv_off;
             Ayz = (T)0;
             Axz = (T)0;
         }
@@ -583,16 +583,16 @@ __device__ __forceinline__ void node_update(const PhysT<T>& ph, const T* g, cons
     T A0, A1, Axy, Ayz, Axz;
     if constexpr (D3) {
         // projections on the stress rows 3cx^2 - c^2, cy^2 - cz^2, cx cy, cy cz, cx cz
-        A0 = ((T)2 * pxx - pyy - pzz) * (T)(1.0 / stress_norm_diag0<GL, 3>());
-        A1 = (pyy - pzz) * (T)(1.0 / stress_norm_diag1<GL>());
-        Axy = pxy * (T)(1.0 / stress_norm_off<GL>());
-        Ayz = pyz * (T)(1.0 / stress_norm_off<GL>());
-        Axz = pxz * (T)(1.0 / stress_norm_off<GL>());
+        A0 = ((T)2 * pxx - pyy - pzz) * (T)StressNorms<GL, 3>::inv_d0;
+        A1 = (pyy - pzz) * (T)StressNorms<GL, 3>::inv_d1;
+        Axy = pxy * (T)StressNorms<GL, PAIR::dim>::inv_off;
+        Ayz = pyz * (T)StressNorms<GL, PAIR::dim>::inv_off;
+        Axz = pxz * (T)StressNorms<GL, PAIR::dim>::inv_off;
     } else {
         // stress rows cx^2 - cy^2 and cx cy
-        A0 = (pxx - pyy) * (T)(1.0 / stress_norm_diag0<GL, 2>());
+        A0 = (pxx - pyy) * (T)StressNorms<GL, 2>::inv_d0;
         A1 = (T)0;
-        Axy = pxy * (T)(1.0 / stress_norm_off<GL>());
+        Axy = pxy * (T)StressNorms<GL, PAIR::dim>::inv_off;
         Ayz = (T)0;
         Axz = (T)0;
     }
