@@ -233,8 +233,9 @@ int pflbm_load_state(pflbm_t* h, const void* dev_src);
    pflbm_adjoint_workspace_bytes(). Uses the handle's parameters; float64
    arithmetic whatever the handle's precision. The method's reverse mode is
    not in the paper: it is the exact transpose of the discrete step of
-   Sec. II.C.1 as implemented here. Returns PFLBM_EUNSUPPORTED for CH or a
-   frozen phase field. */
+   Sec. II.C.1 as implemented here. Returns PFLBM_EUNSUPPORTED for any other
+   model (CH, nonlocal, Liang2018, Liang2014), for D3Q27 and for a frozen
+   phase field. */
 int pflbm_adjoint_workspace_bytes(const pflbm_t* h, size_t* bytes);
 int pflbm_adjoint_step(pflbm_t* h, const double* fwd_g, const double* fwd_h,
                        const double* lam_g, const double* lam_h,
