@@ -61,6 +61,51 @@ def time_form(d, phi, u, precision, steps, warmup, zblock=0):
     return s, ev0.elapsed_time(ev1) / steps, wall
 
 
+ADJ_BYTES = 2 * (19 + 7) * 8 + 26 * 8 + 2 * 6 * 8   # lambda in + out, forward g, h, workspace
+
+
+def time_adjoint(steps):
+    """The discrete adjoint step (float64, canonical layout) on the 128^3
+    sheared droplet between moving walls, at the forward state after 20 steps,
+    chaining lambda through two buffers. Algorithmic bytes per node: lambda
+    read and written (2 x 26 x 8), the forward state read (26 x 8), six
+    workspace values written and read (2 x 6 x 8)."""
+    import torch
+    from paper_2511_11360_amd import workloads as wl
+    from paper_2511_11360_amd.solver import Solver
+    d, phi, u, _ = wl.sheared_droplet_3d()
+    s = Solver(d, precision="fp64")
+    s.init(phi, u)
+    s.step(20)
+    fg, fh = s.get_distributions()
+    gen = torch.Generator(device=fg.device).manual_seed(5)
+    lam = [(torch.randn(fg.shape, dtype=torch.float64, device=fg.device, generator=gen),
+            torch.randn(fh.shape, dtype=torch.float64, device=fg.device, generator=gen)),
+           (torch.empty_like(fg), torch.empty_like(fh))]
+    dparams = torch.zeros(3, dtype=torch.float64, device=fg.device)
+    work = s.adjoint_workspace()
+
+    def run(k, first):
+        for i in range(k):
+            a, b = lam[(first + i) % 2], lam[(first + i + 1) % 2]
+            s.adjoint_step(fg, fh, a[0], a[1], b[0], b[1], dparams, work)
+    run(4, 0)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(s.stream)
+    run(steps, 0)
+    ev1.record(s.stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    nodes = d["nx"] * d["ny"] * d["nz"]
+    return {"workload": "3-D sheared droplet, D3Q19+D3Q7, 128^3, walls moving at -+0.02 (adjoint "
+                        "of the AC step, float64)",
+            "ms_per_step": round(ms, 4), "MLUPS": round(nodes / (ms * 1e-3) / 1e6, 1),
+            "bytes_per_update": ADJ_BYTES,
+            "hbm_frac": round(ADJ_BYTES * nodes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+
+
 def field_errors(d, phi, u, steps, forms):
     """Relative L2 error per field (phi, |u| vector, p) of each form against
     the fp64 form after `steps` steps from the same initial state."""
@@ -141,6 +186,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-models", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy first (counter calibration)")
     args = ap.parse_args()
@@ -212,6 +258,12 @@ def main():
             del sm
             torch.cuda.empty_cache()
 
+    adjoint = None
+    if not args.no_adjoint:
+        print("bench: adjoint", file=sys.stderr, flush=True)
+        adjoint = time_adjoint(100)
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu:
         print("bench: oracle cpu baseline", file=sys.stderr, flush=True)
@@ -247,6 +299,7 @@ def main():
         "cpu_baseline": cpu,
         "forms": forms,
         "models": models,
+        "adjoint": adjoint,
         "errors_vs_fp64": errors,
         "wall_s_timed": round(wall, 3),
     }

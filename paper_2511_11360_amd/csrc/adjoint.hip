@@ -72,7 +72,7 @@ __global__ __launch_bounds__(256) void k_adj_phi(const AdjArgs a) {
 
 // pass 2: local reverse sweep of the collision
 template <class PAIR>
-__global__ __launch_bounds__(256) void k_adj_local(const AdjArgs a) {
+__global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
     using GL = typename PAIR::G;
     using HL = typename PAIR::H;
     constexpr int Q = GL::Q, QH = HL::Q;
