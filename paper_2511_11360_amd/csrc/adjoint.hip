@@ -34,11 +34,15 @@ struct Node {
     int x, y, z;
 };
 
+// node coordinates of linear index n (boxes hold fewer than 2^31 nodes, so
+// 32-bit division suffices)
 __device__ __forceinline__ Node node_of(long long n, const AdjArgs& a) {
+    const int m = (int)n;
+    const int q = m / a.nx;
     Node d;
-    d.x = (int)(n % a.nx);
-    d.y = (int)((n / a.nx) % a.ny);
-    d.z = (int)(n / ((long long)a.nx * a.ny));
+    d.x = m - q * a.nx;
+    d.y = q % a.ny;
+    d.z = q / a.ny;
     return d;
 }
 
@@ -404,29 +408,35 @@ __global__ __launch_bounds__(256) void k_adj_stencil(const AdjArgs a) {
     const double* bgr = a.work + nn;
     const double* blap = a.work + 4 * nn;
     double acc = bphi[n] - 6.0 * (1.0 - GL::w(0)) * blap[n];
-    auto contrib = [&](int i, long long x) {
-        acc += 3.0 * GL::w(i) * (GL::c(i, 0) * bgr[x] + GL::c(i, 1) * bgr[nn + x] +
-                                 GL::c(i, 2) * bgr[2 * nn + x]) +
-               6.0 * GL::w(i) * blap[x];
-    };
     const int n3[3] = {a.nx, a.ny, a.nz};
     const int co[3] = {p.x, p.y, p.z};
-    for (int i = 1; i < Q; ++i) {
-        const int c[3] = {GL::c(i, 0), GL::c(i, 1), GL::c(i, 2)};
+    unroll<Q - 1>([&](auto I) {
+        constexpr int i = I + 1;
+        constexpr int c0 = GL::c(i, 0), c1 = GL::c(i, 1), c2 = GL::c(i, 2);
+        constexpr double w3 = 3.0 * GL::w(i), w6 = 6.0 * GL::w(i);
+        // the terms of x's stencil that reach y (zero components skipped)
+        auto contrib = [&](long long x) {
+            double t = w6 * blap[x];
+            if constexpr (c0 != 0) t += (w3 * c0) * bgr[x];
+            if constexpr (c1 != 0) t += (w3 * c1) * bgr[nn + x];
+            if constexpr (c2 != 0) t += (w3 * c2) * bgr[2 * nn + x];
+            acc += t;
+        };
         // x = y - c_i (no wall crossed)
-        const long long t = step_to(a, p, -c[0], -c[1], -c[2]);
-        if (t >= 0) contrib(i, t);
+        const long long t = step_to(a, p, -c0, -c1, -c2);
+        if (t >= 0) contrib(t);
         // at a wall layer: x on the same layer whose x + c_i is mirrored onto y
-        for (int k = 0; k < 3; ++k) {
-            if (a.bc[k] == 0 || c[k] == 0) continue;
-            const bool edge = c[k] > 0 ? co[k] == n3[k] - 1 : co[k] == 0;
-            if (!edge) continue;
-            int cc[3] = {-c[0], -c[1], -c[2]};
-            cc[k] = 0;
-            const long long t2 = step_to(a, p, cc[0], cc[1], cc[2]);
-            if (t2 >= 0) contrib(i, t2);
-        }
-    }
+        unroll<3>([&](auto K) {
+            constexpr int k = K;
+            constexpr int ck = k == 0 ? c0 : (k == 1 ? c1 : c2);
+            if constexpr (ck != 0) {
+                if (a.bc[k] != 0 && (ck > 0 ? co[k] == n3[k] - 1 : co[k] == 0)) {
+                    const long long t2 = step_to(a, p, k == 0 ? 0 : -c0, k == 1 ? 0 : -c1, k == 2 ? 0 : -c2);
+                    if (t2 >= 0) contrib(t2);
+                }
+            }
+        });
+    });
     for (int al = 0; al < HL::Q; ++al) a.oh[(size_t)al * nn + n] += acc;
 }
 
