@@ -440,14 +440,17 @@ __global__ __launch_bounds__(256) void k_adj_stencil(const AdjArgs a) {
     for (int al = 0; al < HL::Q; ++al) a.oh[(size_t)al * nn + n] += acc;
 }
 
-__global__ __launch_bounds__(256) void k_adj_params(const double* part, int nb, double* out) {
-    __shared__ double red[3][256];
+// one workgroup, fixed summation order (bit-reproducible); 1024 threads so the
+// per-thread strided sums are short
+constexpr int PARAMS_THREADS = 1024;
+__global__ __launch_bounds__(PARAMS_THREADS) void k_adj_params(const double* part, int nb, double* out) {
+    __shared__ double red[3][PARAMS_THREADS];
     double s[3] = {0.0, 0.0, 0.0};
-    for (int b = threadIdx.x; b < nb; b += 256)
+    for (int b = threadIdx.x; b < nb; b += PARAMS_THREADS)
         for (int k = 0; k < 3; ++k) s[k] += part[(size_t)b * 3 + k];
     for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = s[k];
     __syncthreads();
-    for (int st = 128; st >= 1; st >>= 1) {
+    for (int st = PARAMS_THREADS / 2; st >= 1; st >>= 1) {
         if ((int)threadIdx.x < st)
             for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + st];
         __syncthreads();
@@ -497,7 +500,7 @@ hipError_t launch_adjoint(int lattice, const AdjArgs& a, double* dparams, hipStr
         hipLaunchKernelGGL(k_adj_local<Pair3D>, grid, block, 0, st, a);
         hipLaunchKernelGGL(k_adj_stencil<Pair3D>, grid, block, 0, st, a);
     }
-    if (dparams) hipLaunchKernelGGL(k_adj_params, dim3(1), dim3(256), 0, st, a.partials, (int)grid.x, dparams);
+    if (dparams) hipLaunchKernelGGL(k_adj_params, dim3(1), dim3(PARAMS_THREADS), 0, st, a.partials, (int)grid.x, dparams);
     return hipGetLastError();
 }
 
