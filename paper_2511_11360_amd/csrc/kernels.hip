@@ -301,11 +301,13 @@ __global__ __launch_bounds__(256) void k_gamma_part(const GammaArgs a) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_gamma_final(const double* __restrict__ part, long long nb,
-                                                     double* __restrict__ gamma) {
-    __shared__ double red[2][256 / 64];
+// one workgroup of GAMMA_FINAL_THREADS, fixed summation order (bit-reproducible)
+constexpr int GAMMA_FINAL_THREADS = 1024;
+__global__ __launch_bounds__(GAMMA_FINAL_THREADS) void k_gamma_final(const double* __restrict__ part, long long nb,
+                                                                     double* __restrict__ gamma) {
+    __shared__ double red[2][GAMMA_FINAL_THREADS / 64];
     double num = 0.0, den = 0.0;
-    for (long long b = threadIdx.x; b < nb; b += 256) {
+    for (long long b = threadIdx.x; b < nb; b += GAMMA_FINAL_THREADS) {
         num += part[2 * b];
         den += part[2 * b + 1];
     }
@@ -321,7 +323,7 @@ __global__ __launch_bounds__(256) void k_gamma_final(const double* __restrict__ 
     __syncthreads();
     if (threadIdx.x == 0) {
         double sn = red[0][0], sd = red[1][0];
-        for (int k = 1; k < 256 / 64; ++k) {
+        for (int k = 1; k < GAMMA_FINAL_THREADS / 64; ++k) {
             sn += red[0][k];
             sd += red[1][k];
         }
@@ -402,7 +404,8 @@ hipError_t launch_gamma(int lattice, int precision, const GammaArgs& a, hipStrea
     else go(Pair3D27{});
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_gamma_final, dim3(1), dim3(256), 0, s, (const double*)a.partials, nb, a.gamma);
+    hipLaunchKernelGGL(k_gamma_final, dim3(1), dim3(GAMMA_FINAL_THREADS), 0, s, (const double*)a.partials, nb,
+                       a.gamma);
     return hipGetLastError();
 }
 
