@@ -25,11 +25,6 @@ namespace pfk {
 
 namespace {
 
-__device__ __forceinline__ int gwrap(int v, int n, int bc) {
-    if (bc == 0) return v < 0 ? v + n : (v >= n ? v - n : v);
-    return v < 0 ? 0 : (v >= n ? n - 1 : v);
-}
-
 struct Node {
     int x, y, z;
 };
@@ -46,22 +41,41 @@ __device__ __forceinline__ Node node_of(long long n, const AdjArgs& a) {
     return d;
 }
 
-__device__ __forceinline__ long long lin(const AdjArgs& a, int x, int y, int z) {
-    return ((long long)z * a.ny + y) * a.nx + x;
-}
+// neighbours of one node, formed once: along each axis the coordinates v - 1,
+// v, v + 1 (periodic image, or clamped to the wall layer with the "beyond"
+// flag set when the node lies beyond a wall); the linear index of x + c is a
+// plane offset plus a row offset plus a column
+struct Nbr {
+    long long zo[3];
+    int yo[3], xo[3];
+    bool bnd[3][3];
 
-// x + c: linear index, or -1 when it lies beyond a wall
-__device__ __forceinline__ long long step_to(const AdjArgs& a, Node p, int cx, int cy, int cz) {
-    int v[3] = {p.x + cx, p.y + cy, p.z + cz};
-    const int n[3] = {a.nx, a.ny, a.nz};
-    for (int k = 0; k < 3; ++k) {
-        if (v[k] < 0 || v[k] >= n[k]) {
-            if (a.bc[k] != 0) return -1;
-            v[k] = v[k] < 0 ? v[k] + n[k] : v[k] - n[k];
+    __device__ __forceinline__ Nbr(const AdjArgs& a, Node p) {
+        const int v[3] = {p.x, p.y, p.z};
+        const int n3[3] = {a.nx, a.ny, a.nz};
+        int o[3][3];
+        for (int d = 0; d < 3; ++d)
+            for (int k = 0; k < 3; ++k) {
+                const int w = v[d] - 1 + k, n = n3[d];
+                const bool out = w < 0 || w >= n;
+                bnd[d][k] = out && a.bc[d] != 0;
+                o[d][k] = !out ? w : (a.bc[d] == 0 ? (w < 0 ? w + n : w - n) : (w < 0 ? 0 : n - 1));
+            }
+        for (int k = 0; k < 3; ++k) {
+            xo[k] = o[0][k];
+            yo[k] = o[1][k] * a.nx;
+            zo[k] = (long long)o[2][k] * a.nx * a.ny;
         }
     }
-    return lin(a, v[0], v[1], v[2]);
-}
+    // x + c, wrapped, or clamped onto the wall layer
+    __device__ __forceinline__ long long index(int cx, int cy, int cz) const {
+        return zo[cz + 1] + yo[cy + 1] + xo[cx + 1];
+    }
+    // whether x + c lies beyond a wall
+    __device__ __forceinline__ bool beyond(int cx, int cy, int cz) const {
+        return (cx != 0 && bnd[0][cx + 1]) || (cy != 0 && bnd[1][cy + 1]) || (cz != 0 && bnd[2][cz + 1]);
+    }
+};
 
 }  // namespace
 
@@ -90,24 +104,27 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
         double g[Q], h[QH], phin[Q];
         for (int i = 0; i < Q; ++i) g[i] = a.fg[(size_t)i * nn + n];
         for (int al = 0; al < QH; ++al) h[al] = a.fh[(size_t)al * nn + n];
+        const Nbr nb(a, p);
         unroll<Q>([&](auto I) {
             constexpr int i = I;
-            const int gx = gwrap(p.x + GL::c(i, 0), a.nx, a.bc[0]);
-            const int gy = gwrap(p.y + GL::c(i, 1), a.ny, a.bc[1]);
-            const int gz = gwrap(p.z + GL::c(i, 2), a.nz, a.bc[2]);
-            phin[i] = a.phi[lin(a, gx, gy, gz)];
+            phin[i] = a.phi[nb.index(GL::c(i, 0), GL::c(i, 1), GL::c(i, 2))];
         });
-        // lambda* : adjoint of the post-collision populations (stream transpose)
+        // lambda* : adjoint of the post-collision populations (stream transpose);
+        // beyond a wall, the bounce-back slot opp(i) of the node itself
         double lg[Q], lh[QH];
         unroll<Q>([&](auto I) {
             constexpr int i = I;
-            const long long t = step_to(a, p, GL::c(i, 0), GL::c(i, 1), GL::c(i, 2));
-            lg[i] = t >= 0 ? a.lg[(size_t)i * nn + t] : a.lg[(size_t)GL::opp(i) * nn + n];
+            constexpr int cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
+            const size_t e = nb.beyond(cx, cy, cz) ? (size_t)GL::opp(i) * nn + n
+                                                    : (size_t)i * nn + nb.index(cx, cy, cz);
+            lg[i] = a.lg[e];
         });
         unroll<QH>([&](auto J) {
             constexpr int al = J;
-            const long long t = step_to(a, p, HL::c(al, 0), HL::c(al, 1), HL::c(al, 2));
-            lh[al] = t >= 0 ? a.lh[(size_t)al * nn + t] : a.lh[(size_t)HL::opp(al) * nn + n];
+            constexpr int cx = HL::c(al, 0), cy = HL::c(al, 1), cz = HL::c(al, 2);
+            const size_t e = nb.beyond(cx, cy, cz) ? (size_t)HL::opp(al) * nn + n
+                                                    : (size_t)al * nn + nb.index(cx, cy, cz);
+            lh[al] = a.lh[e];
         });
 
         // ---------------- forward intermediates (as in the step kernel)
@@ -408,8 +425,7 @@ __global__ __launch_bounds__(256) void k_adj_stencil(const AdjArgs a) {
     const double* bgr = a.work + nn;
     const double* blap = a.work + 4 * nn;
     double acc = bphi[n] - 6.0 * (1.0 - GL::w(0)) * blap[n];
-    const int n3[3] = {a.nx, a.ny, a.nz};
-    const int co[3] = {p.x, p.y, p.z};
+    const Nbr nb(a, p);
     unroll<Q - 1>([&](auto I) {
         constexpr int i = I + 1;
         constexpr int c0 = GL::c(i, 0), c1 = GL::c(i, 1), c2 = GL::c(i, 2);
@@ -423,16 +439,16 @@ __global__ __launch_bounds__(256) void k_adj_stencil(const AdjArgs a) {
             acc += t;
         };
         // x = y - c_i (no wall crossed)
-        const long long t = step_to(a, p, -c0, -c1, -c2);
-        if (t >= 0) contrib(t);
-        // at a wall layer: x on the same layer whose x + c_i is mirrored onto y
+        if (!nb.beyond(-c0, -c1, -c2)) contrib(nb.index(-c0, -c1, -c2));
+        // at a wall layer (y + c_i beyond the wall along axis k): x on the same
+        // layer whose x + c_i is mirrored onto y
         unroll<3>([&](auto K) {
             constexpr int k = K;
             constexpr int ck = k == 0 ? c0 : (k == 1 ? c1 : c2);
             if constexpr (ck != 0) {
-                if (a.bc[k] != 0 && (ck > 0 ? co[k] == n3[k] - 1 : co[k] == 0)) {
-                    const long long t2 = step_to(a, p, k == 0 ? 0 : -c0, k == 1 ? 0 : -c1, k == 2 ? 0 : -c2);
-                    if (t2 >= 0) contrib(t2);
+                if (nb.bnd[k][ck + 1]) {
+                    constexpr int dx = k == 0 ? 0 : -c0, dy = k == 1 ? 0 : -c1, dz = k == 2 ? 0 : -c2;
+                    if (!nb.beyond(dx, dy, dz)) contrib(nb.index(dx, dy, dz));
                 }
             }
         });
