@@ -41,6 +41,15 @@ __device__ __forceinline__ Node node_of(long long n, const AdjArgs& a) {
     return d;
 }
 
+// workgroup index in row order: consecutive hardware indices go round-robin
+// to the eight XCDs, so the first 8 * (nb / 8) are regrouped so that each XCD
+// takes a contiguous run of rows (the y neighbours of a row then sit in the
+// same L2); the remainder keeps its index
+__device__ __forceinline__ int xcd_block() {
+    const int b = blockIdx.x, per = gridDim.x / 8;
+    return b < 8 * per ? (b % 8) * per + b / 8 : b;
+}
+
 // neighbours of one node, formed once: along each axis the coordinates v - 1,
 // v, v + 1 (periodic image, or clamped to the wall layer with the "beyond"
 // flag set when the node lies beyond a wall); the linear index of x + c is a
@@ -96,7 +105,8 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
     constexpr int Q = GL::Q, QH = HL::Q;
     constexpr bool D3 = PAIR::dim == 3;
     const long long nn = (long long)a.nx * a.ny * a.nz;
-    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int wg = xcd_block();
+    const long long n = (long long)wg * blockDim.x + threadIdx.x;
     double th[3] = {0.0, 0.0, 0.0};   // d sigma, d M, d W of this node
     if (n < nn) {
         const Node p = node_of(n, a);
@@ -405,7 +415,7 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
         __syncthreads();
     }
     if (threadIdx.x == 0)
-        for (int k = 0; k < 3; ++k) a.partials[(size_t)blockIdx.x * 3 + k] = red[k][0];
+        for (int k = 0; k < 3; ++k) a.partials[(size_t)wg * 3 + k] = red[k][0];
 }
 
 // pass 3: transpose of grad phi(x) = 3 sum w c phi(src(x, i)) and
@@ -418,7 +428,8 @@ __global__ __launch_bounds__(256) void k_adj_stencil(const AdjArgs a) {
     using HL = typename PAIR::H;
     constexpr int Q = GL::Q;
     const long long nn = (long long)a.nx * a.ny * a.nz;
-    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int wg = xcd_block();
+    const long long n = (long long)wg * blockDim.x + threadIdx.x;
     if (n >= nn) return;
     const Node p = node_of(n, a);
     const double* bphi = a.work;
