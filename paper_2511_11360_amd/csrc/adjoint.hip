@@ -119,24 +119,6 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
             constexpr int i = I;
             phin[i] = a.phi[nb.index(GL::c(i, 0), GL::c(i, 1), GL::c(i, 2))];
         });
-        // lambda* : adjoint of the post-collision populations (stream transpose);
-        // beyond a wall, the bounce-back slot opp(i) of the node itself
-        double lg[Q], lh[QH];
-        unroll<Q>([&](auto I) {
-            constexpr int i = I;
-            constexpr int cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
-            const size_t e = nb.beyond(cx, cy, cz) ? (size_t)GL::opp(i) * nn + n
-                                                    : (size_t)i * nn + nb.index(cx, cy, cz);
-            lg[i] = a.lg[e];
-        });
-        unroll<QH>([&](auto J) {
-            constexpr int al = J;
-            constexpr int cx = HL::c(al, 0), cy = HL::c(al, 1), cz = HL::c(al, 2);
-            const size_t e = nb.beyond(cx, cy, cz) ? (size_t)HL::opp(al) * nn + n
-                                                    : (size_t)al * nn + nb.index(cx, cy, cz);
-            lh[al] = a.lh[e];
-        });
-
         // ---------------- forward intermediates (as in the step kernel)
         const double phi = phin[0];
         double gr[3] = {0.0, 0.0, 0.0}, lap = 0.0;
@@ -225,6 +207,24 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
         const double itp = ph.inv_tau_phi, gfp = ph.g_fac_phi;
 
         // ---------------- reverse sweep
+        // lambda* : adjoint of the post-collision populations (stream transpose),
+        // gathered here, where the sweep first needs it;
+        // beyond a wall, the bounce-back slot opp(i) of the node itself
+        double lg[Q], lh[QH];
+        unroll<Q>([&](auto I) {
+            constexpr int i = I;
+            constexpr int cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
+            const size_t e = nb.beyond(cx, cy, cz) ? (size_t)GL::opp(i) * nn + n
+                                                    : (size_t)i * nn + nb.index(cx, cy, cz);
+            lg[i] = a.lg[e];
+        });
+        unroll<QH>([&](auto J) {
+            constexpr int al = J;
+            constexpr int cx = HL::c(al, 0), cy = HL::c(al, 1), cz = HL::c(al, 2);
+            const size_t e = nb.beyond(cx, cy, cz) ? (size_t)HL::opp(al) * nn + n
+                                                    : (size_t)al * nn + nb.index(cx, cy, cz);
+            lh[al] = a.lh[e];
+        });
         double b_g[Q], b_h[QH];
         double b_phi = 0.0, b_gr[3] = {0.0, 0.0, 0.0}, b_lap = 0.0;
         double b_u[3] = {0.0, 0.0, 0.0}, b_F[3] = {0.0, 0.0, 0.0};
