@@ -20,8 +20,11 @@
  *  - Every function returns an int status: PFLBM_OK (0) or a negative
  *    PFLBM_E* code. Nothing throws or aborts across the ABI. After an error on
  *    a handle, pflbm_last_error() returns a message owned by the handle.
- *    Errors other than PFLBM_EINVAL are sticky: later calls return
- *    PFLBM_ESTATE until the handle is destroyed.
+ *    PFLBM_EINVAL leaves the handle as it was. After PFLBM_EHIP every later
+ *    call returns PFLBM_ESTATE until the handle is destroyed. After
+ *    PFLBM_EUNSTABLE every later call returns PFLBM_ESTATE until
+ *    pflbm_init() or pflbm_load_state() replaces the state (recovery from a
+ *    checkpoint).
  *  - Field pointers are DEVICE pointers to float64 arrays in canonical
  *    layout, x fastest: scalars [z][y][x], vectors [d][z][y][x] with
  *    d = 2 (2-D) or 3, distributions [q][z][y][x] in the canonical population
@@ -139,7 +142,9 @@ typedef struct pflbm_params {
     double gravity[3];    /* body acceleration: F_b = rho * gravity */
     double force[3];      /* uniform force density added to F_b (Sec. III.D drive) */
     double s_other;       /* MRT rate of every non-stress moment, in (0, 2) */
-    double normal_eps;    /* interface normal n = grad phi / sqrt(|grad phi|^2 + eps^2), >= 0 */
+    double normal_eps;    /* interface normal n = grad phi / sqrt(|grad phi|^2 + eps^2), >= 0;
+                             0 is the paper's n = grad phi / |grad phi| of
+                             Eq. fakhari_G_modified with n = 0 where grad phi = 0 */
     double lam;           /* PFLBM_NL: weight of the conservative flux in [0, 1]
                              (0 = Chai2018, Hu2019 uses 0.9); ignored otherwise */
     int freeze_phi;       /* nonzero: h (hence phi) is not updated (Sec. III.D) */
@@ -189,7 +194,8 @@ int pflbm_create(const pflbm_params* params, void* hip_stream, void* dev_state,
 int pflbm_init(pflbm_t* h, const double* phi0, const double* u0, const double* p0);
 
 /* Advance nsteps >= 0 fused time steps (one kernel launch each). Returns
-   PFLBM_EUNSTABLE (and stops) when a check due under check_interval fails. */
+   PFLBM_EUNSTABLE (and stops, with the failing state current) when a check
+   due under check_interval finds NaN/Inf in phi or u, or rho <= 0. */
 int pflbm_step(pflbm_t* h, int nsteps);
 
 /* Macroscopic fields of the current state (the values the next step uses):
@@ -218,7 +224,12 @@ int pflbm_step_count(const pflbm_t* h, long long* steps);
 
 /* Checkpoint: raw copy of the native state (distributions in their storage
    form, step counter, CH state) to/from a caller-owned device
-   buffer of pflbm_checkpoint_bytes() bytes. */
+   buffer of pflbm_checkpoint_bytes() bytes. Its 256-byte header records the
+   checkpoint size and the layout it was written with (lattice, model,
+   precision, frozen phase field, nx, ny, nz); pflbm_load_state reads the
+   header first (synchronising the stream) and returns PFLBM_EINVAL, copying
+   nothing, when any of them differs from the handle's. The physical
+   parameters (sigma, M, W, ...) may differ. */
 int pflbm_checkpoint_bytes(const pflbm_t* h, size_t* bytes);
 int pflbm_save_state(pflbm_t* h, void* dev_dst);
 int pflbm_load_state(pflbm_t* h, const void* dev_src);
@@ -240,6 +251,13 @@ int pflbm_adjoint_workspace_bytes(const pflbm_t* h, size_t* bytes);
 int pflbm_adjoint_step(pflbm_t* h, const double* fwd_g, const double* fwd_h,
                        const double* lam_g, const double* lam_h,
                        double* lam_g_out, double* lam_h_out, double* dparams, void* work);
+
+/* Seed of the adjoint from a loss on the phase field of a state: given
+   dL/dphi [z][y][x] (device float64), writes lambda = dL/dX for that state,
+   lam_g [Qg][z][y][x] = 0 and lam_h [Qh][z][y][x] = dL/dphi for every
+   population, the transpose of phi = sum_a h_a (Eq. fakhari_phi_update).
+   AC model (PFLBM_EUNSUPPORTED otherwise). Asynchronous. */
+int pflbm_adjoint_seed_phi(pflbm_t* h, const double* dphi, double* lam_g, double* lam_h);
 
 /* dL/dphi0 of the equilibrium initialisation (pflbm_init) given
    lambda^0 = dL/dX^0: dphi0 [z][y][x] (device float64, overwritten). u0 and

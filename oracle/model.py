@@ -320,11 +320,15 @@ def G_ac(p, phi, grad):
     antidiffusion flux is anti-diffusive for gradients below (4/W) phi (1 - phi),
     so an unregularised normal amplifies round-off inside a droplet (two exact
     implementations drift apart). With eps = 1e-4 the flux differs from the
-    paper's by (eps/|grad phi|)^2/2 < 2e-7 relative at the interface centre."""
+    paper's by (eps/|grad phi|)^2/2 < 2e-7 relative at the interface centre.
+    eps = 0 is the paper's normal with the guard n = 0 where
+    grad phi . grad phi = 0 (there the flux vanishes with the gradient)."""
     lat = p.lattices[1]
     gg = _vdot(grad, grad)
-    coef = 4.0 / (p.W * (PHI_H - PHI_L)) * (PHI_H - phi) * (phi - PHI_L) \
-        / np.sqrt(gg + p.normal_eps * p.normal_eps)
+    s = gg + p.normal_eps * p.normal_eps
+    pos = np.real(s) > 0
+    inv = np.where(pos, 1.0 / np.sqrt(np.where(pos, s, 1.0)), 0.0)
+    coef = 4.0 / (p.W * (PHI_H - PHI_L)) * (PHI_H - phi) * (phi - PHI_L) * inv
     out = np.empty((lat.Q,) + phi.shape, dtype=np.result_type(coef, grad))
     for a in range(lat.Q):
         out[a] = lat.w[a] * coef * _cdot(lat.c[a], grad)

@@ -50,9 +50,7 @@ class PhaseFieldRun(torch.autograd.Function):
         (phi0,) = ctx.saved_tensors
         dev = s.device
         shape = s.shape
-        lam_h = grad_phi.to(device=dev, dtype=torch.float64).reshape(shape)
-        lam_h = lam_h.unsqueeze(0).expand((s.Qh,) + shape).contiguous()   # phi = sum h
-        lam_g = torch.zeros((s.Qg,) + shape, dtype=torch.float64, device=dev)
+        lam_g, lam_h = s.adjoint_seed_phi(grad_phi.to(device=dev, dtype=torch.float64).reshape(shape))
         out_g = torch.empty_like(lam_g)
         out_h = torch.empty_like(lam_h)
         dparams = torch.zeros(3, dtype=torch.float64, device=dev)

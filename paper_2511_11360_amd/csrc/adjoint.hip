@@ -201,7 +201,8 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
             q[4] = cx * cz;
         };
         const double gg = gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2];
-        const double rn = 1.0 / sqrt(gg + ph.eps2);
+        const double sn = gg + ph.eps2;
+        const double rn = sn > 0.0 ? 1.0 / sqrt(sn) : 0.0;   // guarded normal at eps = 0
         const double pp = phi * (1.0 - phi);
         const double coef = ph.anti * pp * rn;
         const double itp = ph.inv_tau_phi, gfp = ph.g_fac_phi;
@@ -514,6 +515,24 @@ __global__ __launch_bounds__(256) void k_adj_init(const AdjInitArgs a) {
         for (int i = 0; i < GL::Q; ++i) s += a.lg[(size_t)i * nn + n] * GL::w(i) * dps;
     }
     a.dphi0[n] = s;
+}
+
+// seed of the adjoint from dL/dphi of a state: phi = sum_a h_a (Eq.
+// fakhari_phi_update) gives dL/dh_a = dL/dphi for every a, and dL/dg = 0
+__global__ __launch_bounds__(256) void k_adj_seed(const double* dphi, double* lg, double* lh, long long nn,
+                                                  int qg, int qh) {
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    const double v = dphi[n];
+    for (int i = 0; i < qg; ++i) lg[(size_t)i * nn + n] = 0.0;
+    for (int a = 0; a < qh; ++a) lh[(size_t)a * nn + n] = v;
+}
+
+hipError_t launch_adjoint_seed(const double* dphi, double* lg, double* lh, long long nn, int qg, int qh,
+                               hipStream_t st) {
+    const dim3 grid((unsigned)((nn + 255) / 256)), block(256);
+    hipLaunchKernelGGL(k_adj_seed, grid, block, 0, st, dphi, lg, lh, nn, qg, qh);
+    return hipGetLastError();
 }
 
 hipError_t launch_adjoint(int lattice, const AdjArgs& a, double* dparams, hipStream_t st) {

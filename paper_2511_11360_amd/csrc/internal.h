@@ -172,6 +172,8 @@ struct AdjInitArgs {
 };
 
 // launchers (kernels.hip, adjoint.hip); return hipSuccess or the launch error
+hipError_t launch_adjoint_seed(const double* dphi, double* lg, double* lh, long long nn, int qg, int qh,
+                               hipStream_t st);
 hipError_t launch_adjoint(int lattice, const AdjArgs& a, double* dparams, hipStream_t s);
 hipError_t launch_adjoint_init(int lattice, const AdjInitArgs& a, hipStream_t s);
 hipError_t launch_step(int lattice, int model, int precision, int mode, const KArgs& a, hipStream_t s);
@@ -213,6 +215,13 @@ hipError_t launch_get(int lattice, int model, int precision, const IOArgs& a, hi
 hipError_t launch_set(int lattice, int model, int precision, const IOArgs& a, hipStream_t s);
 hipError_t launch_reduce(const double* partials, int nblocks, double* out, hipStream_t s);
 hipError_t launch_gamma(int lattice, int precision, const GammaArgs& a, hipStream_t s);
-hipError_t launch_header(void* dst, long long steps, hipStream_t s);
+// checkpoint header (the first 256 bytes of a checkpoint): tag, step counter,
+// checkpoint size and the layout it was written with (lattice, model,
+// precision, nx, ny, nz), compared on the host before a load copies anything
+struct CkHeader {
+    static constexpr int N = 8;
+    long long v[N];
+};
+hipError_t launch_header(void* dst, const CkHeader& hd, hipStream_t s);
 
 }  // namespace pfk

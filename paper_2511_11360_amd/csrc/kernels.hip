@@ -33,13 +33,8 @@ __global__ __launch_bounds__(BLOCK) void k_reduce(const double* __restrict__ par
     block_reduce_diag(d, out);
 }
 
-__global__ void k_header(long long* dst, long long steps) {
-    if (threadIdx.x == 0) {
-        dst[0] = 0x70666c626eLL;   // tag (post-collision pull layout)
-        dst[1] = steps;
-        dst[2] = 0;
-        dst[3] = 0;
-    }
+__global__ void k_header(long long* dst, CkHeader hd) {
+    if (threadIdx.x < CkHeader::N) dst[threadIdx.x] = hd.v[threadIdx.x];
 }
 
 // ----------------------------------------------------------------------------
@@ -414,8 +409,8 @@ hipError_t launch_reduce(const double* partials, int nblocks, double* out, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_header(void* dst, long long steps, hipStream_t s) {
-    hipLaunchKernelGGL(k_header, dim3(1), dim3(64), 0, s, (long long*)dst, steps);
+hipError_t launch_header(void* dst, const CkHeader& hd, hipStream_t s) {
+    hipLaunchKernelGGL(k_header, dim3(1), dim3(64), 0, s, (long long*)dst, hd);
     return hipGetLastError();
 }
 

@@ -200,7 +200,8 @@ struct pflbm {
     int gcur = 0, hcur = 0;   // buffers the next step reads
     long long steps = 0;
     bool initialised = false;
-    int sticky = 0;
+    int sticky = 0;        // PFLBM_EHIP: every later call returns PFLBM_ESTATE
+    bool unstable = false; // after PFLBM_EUNSTABLE, until pflbm_init / pflbm_load_state
     std::string err;
     Phys ph;
     PhysT<float> phf;
@@ -215,7 +216,8 @@ namespace {
 int fail(pflbm_t* h, int code, const std::string& msg) {
     if (h) {
         h->err = msg;
-        if (code != PFLBM_EINVAL && code != PFLBM_EUNSTABLE) h->sticky = code;
+        if (code == PFLBM_EUNSTABLE) h->unstable = true;
+        else if (code != PFLBM_EINVAL) h->sticky = code;
     }
     return code;
 }
@@ -231,6 +233,14 @@ int hip_fail(pflbm_t* h, hipError_t e, const char* where) {
     } while (0)
 
 int guard(pflbm_t* h) {
+    if (!h) return PFLBM_EINVAL;
+    if (h->sticky || h->unstable) return PFLBM_ESTATE;
+    return PFLBM_OK;
+}
+
+// calls that replace the whole state (init, load_state) are allowed after an
+// instability and clear it when they succeed
+int guard_replace(pflbm_t* h) {
     if (!h) return PFLBM_EINVAL;
     if (h->sticky) return PFLBM_ESTATE;
     return PFLBM_OK;
@@ -423,7 +433,7 @@ void pflbm_destroy(pflbm_t* h) { delete h; }
 const char* pflbm_last_error(const pflbm_t* h) { return h ? h->err.c_str() : "null handle"; }
 
 int pflbm_init(pflbm_t* h, const double* phi0, const double* u0, const double* p0) {
-    int st = guard(h);
+    int st = guard_replace(h);
     if (st) return st;
     if (!phi0) return fail(h, PFLBM_EINVAL, "phi0 is null");
     InitArgs a;
@@ -446,6 +456,7 @@ int pflbm_init(pflbm_t* h, const double* phi0, const double* u0, const double* p
     h->hcur = 0;
     h->steps = 0;
     h->initialised = true;
+    h->unstable = false;
     return PFLBM_OK;
 }
 
@@ -566,6 +577,19 @@ int pflbm_step_count(const pflbm_t* h, long long* steps) {
     return PFLBM_OK;
 }
 
+static CkHeader ck_header(const pflbm_t* h, long long steps) {
+    CkHeader hd;
+    hd.v[0] = 0x70666c626eLL;   // tag (post-collision pull layout)
+    hd.v[1] = steps;
+    hd.v[2] = (long long)h->L.ck_total;
+    hd.v[3] = h->p.lattice + 16LL * h->p.model + 256LL * h->p.precision + 4096LL * (h->p.freeze_phi != 0);
+    hd.v[4] = h->p.nx;
+    hd.v[5] = h->p.ny;
+    hd.v[6] = h->p.nz;
+    hd.v[7] = 0;
+    return hd;
+}
+
 int pflbm_checkpoint_bytes(const pflbm_t* h, size_t* bytes) {
     if (!h || !bytes) return PFLBM_EINVAL;
     *bytes = h->L.ck_total;
@@ -579,7 +603,7 @@ int pflbm_save_state(pflbm_t* h, void* dev_dst) {
     if (!h->initialised) return fail(h, PFLBM_EINVAL, "pflbm_init not called");
     char* d = (char*)dev_dst;
     const Layout& L = h->L;
-    HIPCHK(h, launch_header(d, h->steps, h->stream), "header kernel");
+    HIPCHK(h, launch_header(d, ck_header(h, h->steps), h->stream), "header kernel");
     HIPCHK(h, hipMemcpyAsync(d + L.ck_g, h->base + L.off_g[h->gcur], L.g_bytes, hipMemcpyDeviceToDevice, h->stream), "save g");
     HIPCHK(h, hipMemcpyAsync(d + L.ck_h, h->base + L.off_h[h->hcur], L.h_bytes, hipMemcpyDeviceToDevice, h->stream), "save h");
     if (L.pu_bytes)
@@ -588,23 +612,30 @@ int pflbm_save_state(pflbm_t* h, void* dev_dst) {
 }
 
 int pflbm_load_state(pflbm_t* h, const void* dev_src) {
-    int st = guard(h);
+    int st = guard_replace(h);
     if (st) return st;
     if (!dev_src) return fail(h, PFLBM_EINVAL, "null source");
     const char* s = (const char*)dev_src;
     const Layout& L = h->L;
-    long long hdr[4];
-    HIPCHK(h, hipMemcpyAsync(hdr, s, sizeof(hdr), hipMemcpyDeviceToHost, h->stream), "load header");
+    CkHeader hdr;
+    HIPCHK(h, hipMemcpyAsync(hdr.v, s, sizeof(hdr.v), hipMemcpyDeviceToHost, h->stream), "load header");
     HIPCHK(h, hipStreamSynchronize(h->stream), "load sync");
-    if (hdr[0] != 0x70666c626eLL) return fail(h, PFLBM_EINVAL, "not a pflbm checkpoint");
+    const CkHeader want = ck_header(h, hdr.v[1]);
+    if (hdr.v[0] != want.v[0]) return fail(h, PFLBM_EINVAL, "not a pflbm checkpoint");
+    if (hdr.v[2] != want.v[2]) return fail(h, PFLBM_EINVAL, "checkpoint size differs from this handle's");
+    for (int k = 3; k < CkHeader::N; ++k)
+        if (hdr.v[k] != want.v[k])
+            return fail(h, PFLBM_EINVAL, "checkpoint written with another lattice, model, precision or box");
+    if (hdr.v[1] < 0) return fail(h, PFLBM_EINVAL, "checkpoint step counter is negative");
     HIPCHK(h, hipMemcpyAsync(h->base + L.off_g[0], s + L.ck_g, L.g_bytes, hipMemcpyDeviceToDevice, h->stream), "load g");
     HIPCHK(h, hipMemcpyAsync(h->base + L.off_h[0], s + L.ck_h, L.h_bytes, hipMemcpyDeviceToDevice, h->stream), "load h");
     if (L.pu_bytes)
         HIPCHK(h, hipMemcpyAsync(h->base + L.off_pu, s + L.ck_pu, L.pu_bytes, hipMemcpyDeviceToDevice, h->stream), "load phiu");
-    h->steps = hdr[1];
+    h->steps = hdr.v[1];
     h->gcur = 0;
     h->hcur = 0;
     h->initialised = true;
+    h->unstable = false;
     return PFLBM_OK;
 }
 
@@ -651,6 +682,16 @@ int pflbm_adjoint_step(pflbm_t* h, const double* fwd_g, const double* fwd_h, con
     a.W = h->p.W;
     a.ph = h->ph;
     HIPCHK(h, launch_adjoint(h->p.lattice, a, dparams, h->stream), "adjoint kernels");
+    return PFLBM_OK;
+}
+
+int pflbm_adjoint_seed_phi(pflbm_t* h, const double* dphi, double* lam_g, double* lam_h) {
+    int st = guard(h);
+    if (st) return st;
+    if (h->p.model != PFLBM_AC) return fail(h, PFLBM_EUNSUPPORTED, "adjoint implemented for the AC model only");
+    if (!dphi || !lam_g || !lam_h) return fail(h, PFLBM_EINVAL, "null pointer");
+    HIPCHK(h, launch_adjoint_seed(dphi, lam_g, lam_h, (long long)adj_nodes(h), h->L.Qg, h->L.Qh, h->stream),
+           "adjoint seed kernel");
     return PFLBM_OK;
 }
 

@@ -153,6 +153,10 @@ template <> __device__ __forceinline__ double rcp<double>(double x) { return 1.0
 template <class T> __device__ __forceinline__ T rsqrt_(T x);
 template <> __device__ __forceinline__ float rsqrt_<float>(float x) { return __builtin_amdgcn_rsqf(x); }
 template <> __device__ __forceinline__ double rsqrt_<double>(double x) { return 1.0 / sqrt(x); }
+// 1 / |grad phi| of the interface normal, from s = grad phi . grad phi + eps^2;
+// with eps = 0 the guard n = 0 where the gradient vanishes (the antidiffusion
+// flux of Eq. fakhari_G_modified then vanishes with it)
+template <class T> __device__ __forceinline__ T inv_norm(T s) { return s > (T)0 ? rsqrt_(s) : (T)0; }
 
 // Computes the macroscopic state of one node and, when COLLIDE, hands every
 // post-collision population to gsink(i, value) / hsink(a, value) as soon as it
@@ -502,7 +506,7 @@ __device__ __forceinline__ void node_update(const PhysT<T>& ph, const T* g, cons
             pu_new[a] = pu[a];
         });
         const T gg = gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2];
-        const T coef = ph.anti * phi * ((T)1 - phi) * rsqrt_(gg + ph.eps2);
+        const T coef = ph.anti * phi * ((T)1 - phi) * inv_norm(gg + ph.eps2);
         // float forms close each node's balance on its last population (see below)
         constexpr bool CLOSE = sizeof(T) == 4;
         T hacc = (T)0;
@@ -637,7 +641,7 @@ __device__ __forceinline__ void node_update(const PhysT<T>& ph, const T* g, cons
     };
     if constexpr (MODEL == 0) {
         const T gg = gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2];
-        const T coef = ph.anti * phi * ((T)1 - phi) * rsqrt_(gg + ph.eps2);
+        const T coef = ph.anti * phi * ((T)1 - phi) * inv_norm(gg + ph.eps2);
         const T e0 = phi * ((T)1 - (T)1.5 * usq);
         if constexpr (HL::w(0) != 0.0)
             put(std::integral_constant<int, 0>{}, itp1 * h[0] + itp * (T)HL::w(0) * e0);
@@ -660,7 +664,7 @@ __device__ __forceinline__ void node_update(const PhysT<T>& ph, const T* g, cons
         const T R = nl_source(ph, phis, gam);
         htarget = phis + ((T)1 - ph.lam) * ((T)0.5 * itp + gfp) * R;
         const T gg = gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2];
-        const T coef = ph.anti * phi * ((T)1 - phi) * rsqrt_(gg + ph.eps2);
+        const T coef = ph.anti * phi * ((T)1 - phi) * inv_norm(gg + ph.eps2);
         const T gcon = gfp * ph.lam * coef;
         const T giso = gfp * ((T)1 - ph.lam) * R;
         const T e0 = itp * phi + giso;

@@ -84,6 +84,7 @@ SIGNATURES = {
     "pflbm_adjoint_workspace_bytes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),
     "pflbm_adjoint_step": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "pflbm_adjoint_init": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    "pflbm_adjoint_seed_phi": (ctypes.c_int, [_P, _P, _P, _P]),
     "pflbm_destroy": (None, [_P]),
     "pflbm_last_error": (ctypes.c_char_p, [_P]),
     "pflbm_strerror": (ctypes.c_char_p, [ctypes.c_int]),

@@ -132,6 +132,16 @@ class Solver:
                                               _ptr(lam_h), _ptr(out_g), _ptr(out_h),
                                               _ptr(dparams), _ptr(work)), self.h)
 
+    def adjoint_seed_phi(self, dphi):
+        """(lambda_g, lambda_h) of a loss with gradient dphi with respect to the
+        phase field of a state (pflbm_adjoint_seed_phi)."""
+        dphi = self._dev(dphi, self.shape)
+        lam_g = torch.empty((self.Qg,) + self.shape, dtype=torch.float64, device=self.device)
+        lam_h = torch.empty((self.Qh,) + self.shape, dtype=torch.float64, device=self.device)
+        self._keep = (dphi,)
+        self._check(self.L.pflbm_adjoint_seed_phi(self.h, _ptr(dphi), _ptr(lam_g), _ptr(lam_h)), self.h)
+        return lam_g, lam_h
+
     def adjoint_init(self, phi0, u0, p0, lam_g, lam_h):
         phi = self._dev(phi0, self.shape)
         u = self._dev(u0, (self.dim,) + self.shape)
