@@ -1,12 +1,23 @@
 """Benchmark of the fused PF-LB step on one MI355X.
 
-Workload: 3-D droplet in a Taylor-Green vortex, D3Q19 + D3Q7, 256^3 periodic,
-conservative Allen-Cahn, u0 = 0.05, Re = 1000, R = 40, rho ratio 10, W = 4,
-M = 0.05, We = 10. Headline form: g stored as fp16 of 4096 g_i / w_i, h in
-fp32, fp32 arithmetic; the fp64, fp32 and bf16-stored forms are timed beside
-it, and the per-field error of every reduced form against the fp64 form (whose
-parity with the oracle the test-suite establishes) is stated, on this workload
-and on a laminar one (a sheared droplet between moving walls).
+Headline workload: 3-D droplet-laden decaying isotropic turbulence, D3Q19 +
+D3Q7, 512^3 periodic, conservative Allen-Cahn, 64 droplets of radius 16 at
+seeded non-overlapping positions, seeded random-phase velocity with
+E(k) ~ k^4 exp(-2 (k/4)^2), u_rms = 0.04, rho ratio 10, We = 5, W = 4,
+M = 0.05. Headline form: g stored as fp16 of 4096 g_i / w_i, h in fp32, fp32
+arithmetic. Beside it: the fp64, fp32 and bf16-stored forms on the same
+workload; the other phase-field models and the D3Q27 lattice; the 256^3
+droplet in a Taylor-Green vortex as a secondary workload; memory-pattern
+probes of the step's HBM streams (the bandwidth ceiling of its access
+pattern); the per-field error of every reduced form against the fp64 form;
+the discrete adjoint step and a full backward step; the oracle's CPU rate on
+a bounded sample of the headline workload.
+
+Before the timed window of every line, a clock pre-warm runs steps from a
+checkpoint of the initial state for about a quarter of a second and reloads
+the checkpoint, so that the warm-up and timed steps are the workload's own
+first steps: the GPU's clocks ramp up over the first ~15 ms after an idle
+gap, which otherwise lands in a short timed window.
 
 Prints ONE JSON line.
 """
@@ -21,7 +32,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0   # MI355X HBM3E, GB/s
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_tgv256.json")
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_FILES = {"turb512": os.path.join(PROFILES, "traffic_step_turb512.json"),
+                 "tgv256": os.path.join(PROFILES, "traffic_step_tgv256.json")}
+PREWARM_MS = 250.0
+
+
+def log(*a):
+    print("bench:", *a, file=sys.stderr, flush=True)
 
 
 def bytes_per_update(d, precision):
@@ -43,22 +61,117 @@ def bytes_per_update(d, precision):
     return 2 * (qg * sg + qh * sh) + extra
 
 
+def workload(name):
+    from paper_2511_11360_amd import workloads as wl
+    if name == "turb512":
+        d, phi, u, _ = wl.droplet_turbulence_3d(n=512, We=5.0)
+        desc = ("3-D droplet-laden decaying isotropic turbulence, D3Q19+D3Q7, 512^3 periodic, "
+                "conservative AC, 64 droplets R=16, E(k)~k^4 exp(-2(k/4)^2), u_rms=0.04, "
+                "rho ratio 10, We=5, W=4, M=0.05")
+    else:
+        d, phi, u = wl.taylor_green_droplet_3d(n=256, We=10.0)
+        desc = ("3-D droplet in Taylor-Green vortex, D3Q19+D3Q7, 256^3 periodic, conservative AC, "
+                "u0=0.05, Re=1000, R=40, rho ratio 10, W=4, M=0.05, We=10")
+    return d, phi, u, desc
+
+
+def _events(s):
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def prewarm(s):
+    """Steps from a checkpoint of the current state for PREWARM_MS of GPU time,
+    then the checkpoint is reloaded (the state is exactly the initial one)."""
+    import torch
+    ck = s.save_state()
+    e0, e1 = _events(s)
+    n = 0
+    e0.record(s.stream)
+    while True:
+        s.step(8)
+        n += 8
+        e1.record(s.stream)
+        e1.synchronize()
+        if e0.elapsed_time(e1) >= PREWARM_MS or n >= 4000:
+            break
+    s.load_state(ck)
+    torch.cuda.synchronize()
+    del ck
+    return n
+
+
 def time_form(d, phi, u, precision, steps, warmup, zblock=0):
+    """Milliseconds per step (HIP events on the solver's stream) over `steps`
+    steps after `warmup` steps, from the initial state."""
     import torch
     from paper_2511_11360_amd.solver import Solver
     s = Solver(d, precision=precision, zblock=zblock)
     s.init(phi, u)
+    prewarm(s)
     s.step(warmup)
     torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(s.stream)
+    e0, e1 = _events(s)
+    e0.record(s.stream)
     t0 = time.perf_counter()
     s.step(steps)
-    ev1.record(s.stream)
+    e1.record(s.stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return s, ev0.elapsed_time(ev1) / steps, wall
+    return s, e0.elapsed_time(e1) / steps, wall
+
+
+def line(d, precision, ms, nodes):
+    b = bytes_per_update(d, precision)
+    return {"MLUPS": round(nodes / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4),
+            "bytes_per_update": b, "hbm_frac": round(b * nodes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+
+
+def auto_zblock(n, tiles_x, tiles_y):
+    """z planes per workgroup of the step kernel's automatic launch with the
+    1024-thread 256 x 4 tile (one resident workgroup per compute unit): the
+    grid fills every compute unit once."""
+    import torch
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    nzb = max(1, cus // (tiles_x * tiles_y))
+    return max(4, -(-n // nzb))
+
+
+def probes(n, reps=20):
+    """The step's HBM streams (19 fp16 + 6 fp32 populations per node, read and
+    written) with no arithmetic, in four access patterns, at n^3 in the step
+    kernel's grid: ms per pass and TB/s of the 124 bytes per node."""
+    import ctypes
+    import torch
+    from paper_2511_11360_amd import pflbm as P
+    L = P.lib()
+    gb, hb = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.pflbm_probe_bytes(n, n, n, ctypes.byref(gb), ctypes.byref(hb)) == 0
+    bufs = [torch.zeros(v.value, dtype=torch.uint8, device="cuda") for v in (gb, gb, hb, hb)]
+    zb = auto_zblock(n, -(-n // 256), -(-n // 4))
+    st = torch.cuda.current_stream()
+    out = {"zblock": zb}
+    names = {P.PFLBM_PROBE_CHUNKS: "contiguous_chunks", P.PFLBM_PROBE_TILES: "tiles_256x4_aligned",
+             P.PFLBM_PROBE_SHIFT_LD: "tiles_shifted_loads", P.PFLBM_PROBE_SHIFT_ST: "tiles_shifted_stores"}
+    for pat, name in names.items():
+        def go():
+            rc = L.pflbm_probe_stream(*(ctypes.c_void_p(b.data_ptr()) for b in bufs), n, n, n, pat, zb,
+                                      ctypes.c_void_p(st.cuda_stream))
+            assert rc == 0, rc
+        for _ in range(max(3, int(PREWARM_MS / 3))):
+            go()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            go()
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"ms": round(ms, 4), "TB_s": round(124 * n ** 3 / (ms * 1e-3) / 1e12, 3)}
+    del bufs
+    torch.cuda.empty_cache()
+    return out
 
 
 ADJ_BYTES = 2 * (19 + 7) * 8 + 26 * 8 + 2 * 6 * 8   # lambda in + out, forward g, h, workspace
@@ -85,19 +198,18 @@ def time_adjoint(steps):
     dparams = torch.zeros(3, dtype=torch.float64, device=fg.device)
     work = s.adjoint_workspace()
 
-    def run(k, first):
+    def run(k):
         for i in range(k):
-            a, b = lam[(first + i) % 2], lam[(first + i + 1) % 2]
+            a, b = lam[i % 2], lam[(i + 1) % 2]
             s.adjoint_step(fg, fh, a[0], a[1], b[0], b[1], dparams, work)
-    run(4, 0)
+    run(max(4, int(PREWARM_MS / 0.45)))
     torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(s.stream)
-    run(steps, 0)
-    ev1.record(s.stream)
+    e0, e1 = _events(s)
+    e0.record(s.stream)
+    run(steps)
+    e1.record(s.stream)
     torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / steps
+    ms = e0.elapsed_time(e1) / steps
     nodes = d["nx"] * d["ny"] * d["nz"]
     return {"workload": "3-D sheared droplet, D3Q19+D3Q7, 128^3, walls moving at -+0.02 (adjoint "
                         "of the AC step, float64)",
@@ -125,22 +237,34 @@ def field_errors(d, phi, u, steps, forms):
             for name, a, b in (("phi", f[0], ref[0]), ("u", f[1], ref[1]), ("p", f[2], ref[2])):
                 e[name] = float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
             out[prec] = e
-        del s
+        del s, f
         torch.cuda.empty_cache()
     return out
 
 
-def cpu_baseline(seconds=12.0):
-    """Oracle (plain numpy, float64) on a bounded sample of the same workload:
-    the 64^3 instance of the droplet-in-vortex case, single BLAS thread."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(d, phi, u, block=128, seconds=12.0):
+    """The oracle (plain numpy, float64, one thread) on a bounded sample of the
+    headline workload: the block^3 corner of its initial state with the same
+    parameters, as a periodic box, stepped for about `seconds`."""
     from threadpoolctl import threadpool_limits
     from oracle import model as om
-    from paper_2511_11360_amd import workloads as wl
-    d, phi, u = wl.taylor_green_droplet_3d(n=64)
+    db = dict(d, nx=block, ny=block, nz=block)
+    pb = phi[:block, :block, :block].copy()
+    ub = u[:, :block, :block, :block].copy()
     with threadpool_limits(limits=1):
-        p = om.Params(**d)
-        st = om.init(p, phi, u)
-        st = om.step(p, st)
+        p = om.Params(**db)
+        st = om.init(p, pb, ub)
         n = 0
         t0 = time.perf_counter()
         while True:
@@ -149,19 +273,22 @@ def cpu_baseline(seconds=12.0):
             el = time.perf_counter() - t0
             if el > seconds or n >= 200:
                 break
-    nodes = 64 ** 3
+    nodes = block ** 3
     return {"value": round(nodes * n / el / 1e6, 4), "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": "64^3 instance of the same droplet-in-vortex workload (R scaled to 10), "
-                      "%d steps in %.1f s, numpy float64, one thread" % (n, el)}
+            "cpu_model": cpu_model(),
+            "sample": "%d^3 corner block of the 512^3 turbulence workload's initial state (same "
+                      "parameters, periodic), %d steps in %.1f s, numpy float64, one thread"
+                      % (block, n, el)}
 
 
-def measured_traffic(precision):
+def measured_traffic(name, precision):
     """HBM bytes per step-kernel launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source; else None."""
+    summary of this workload, if it was taken on the current kernel source."""
     from paper_2511_11360_amd import profiling
-    if not os.path.exists(TRAFFIC_FILE):
+    path = TRAFFIC_FILES[name]
+    if not os.path.exists(path):
         return None
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         t = json.load(f)
     if t.get("kernel_source_sha256") != profiling.kernel_source_hash():
         return None
@@ -173,20 +300,26 @@ def measured_traffic(precision):
     return sum(vals) / len(vals)
 
 
+STORAGE = {"mixed_fp16": "g fp16 (4096 g/w), h fp32", "mixed_bf16": "g bf16 (g/w), h fp32",
+           "fp32": "g, h fp32", "fp64": "g, h fp64"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=300)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--We", type=float, default=10.0)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="turb512", choices=["turb512", "tgv256"])
     ap.add_argument("--precision", default="mixed_fp16")
     ap.add_argument("--zblock", type=int, default=0)
-    ap.add_argument("--err-steps", type=int, default=500)
+    ap.add_argument("--err-steps", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-models", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-probes", action="store_true")
+    ap.add_argument("--no-errors", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy first (counter calibration)")
     args = ap.parse_args()
@@ -206,11 +339,13 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    d, phi, u = wl.taylor_green_droplet_3d(n=args.n, We=args.We)
-    nodes = args.n ** 3
+    t0 = time.perf_counter()
+    d, phi, u, desc = workload(args.workload)
+    n = d["nx"]
+    nodes = n ** 3
+    log("inputs %s in %.1f s" % (args.workload, time.perf_counter() - t0))
 
-    print("bench: headline %s %d^3, %d warmup + %d timed steps" % (args.precision, args.n, args.warmup,
-                                                                  args.steps), file=sys.stderr, flush=True)
+    log("headline %s %s, %d warmup + %d timed steps" % (args.workload, args.precision, args.warmup, args.steps))
     s, ms, wall = time_form(d, phi, u, args.precision, args.steps, args.warmup, args.zblock)
     mlups = nodes / (ms * 1e-3) / 1e6
     bpu = bytes_per_update(d, args.precision)
@@ -219,57 +354,74 @@ def main():
     torch.cuda.empty_cache()
 
     forms = {}
-    errors = {}
     if not args.no_forms:
         for prec in ("fp64", "fp32", "mixed_fp16", "mixed_bf16"):
-            print("bench: form %s" % prec, file=sys.stderr, flush=True)
-            sf, msf, _ = time_form(d, phi, u, prec, max(60, args.steps // 3), 10, args.zblock)
-            b = bytes_per_update(d, prec)
-            forms[prec] = {"MLUPS": round(nodes / (msf * 1e-3) / 1e6, 1), "ms_per_step": round(msf, 4),
-                           "bytes_per_update": b,
-                           "hbm_frac": round(b * nodes / (msf * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+            log("form %s" % prec)
+            sf, msf, _ = time_form(d, phi, u, prec, 40, 5, args.zblock)
+            forms[prec] = line(d, prec, msf, nodes)
             del sf
             torch.cuda.empty_cache()
         for k in ("fp32", "mixed_fp16", "mixed_bf16"):
             forms[k]["speedup_vs_fp64"] = round(forms[k]["MLUPS"] / forms["fp64"]["MLUPS"], 3)
             forms[k]["speedup_vs_fp32"] = round(forms[k]["MLUPS"] / forms["fp32"]["MLUPS"], 3)
-        print("bench: errors against fp64", file=sys.stderr, flush=True)
-        errors["this_workload"] = {"steps": args.err_steps,
-                                   "rel_l2": field_errors(d, phi, u, args.err_steps,
-                                                          ("fp32", "mixed_fp16", "mixed_bf16"))}
-        dl, phl, ul, _ = wl.sheared_droplet_3d(n=64, R=16.0, W=4.0)
-        errors["laminar_sheared_droplet_64"] = {
-            "steps": 1000, "rel_l2": field_errors(dl, phl, ul, 1000, ("fp32", "mixed_fp16", "mixed_bf16"))}
 
     # the other phase-field models and the D3Q27 lattice, same workload and storage form
     models = {}
     if not args.no_models:
         for key, extra in (("CH", {"model": "CH"}), ("NL_lam0", {"model": "NL", "lam": 0.0}),
                            ("NL_lam0.9", {"model": "NL", "lam": 0.9}), ("L18", {"model": "L18"}),
-                           ("L14", {"model": "L14"}),
-                           ("AC_D3Q27", {"lattice": "D3Q27_D3Q7"})):
+                           ("L14", {"model": "L14"}), ("AC_D3Q27", {"lattice": "D3Q27_D3Q7"})):
             dm = dict(d, **extra)
-            print("bench: model %s" % key, file=sys.stderr, flush=True)
-            sm, msm, _ = time_form(dm, phi, u, args.precision, max(60, args.steps // 3), 10, args.zblock)
-            b = bytes_per_update(dm, args.precision)
-            models[key] = {"MLUPS": round(nodes / (msm * 1e-3) / 1e6, 1), "ms_per_step": round(msm, 4),
-                           "bytes_per_update": b,
-                           "hbm_frac": round(b * nodes / (msm * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+            log("model %s" % key)
+            sm, msm, _ = time_form(dm, phi, u, args.precision, 40, 5, args.zblock)
+            models[key] = line(dm, args.precision, msm, nodes)
             del sm
             torch.cuda.empty_cache()
 
+    errors = {}
+    if not args.no_errors:
+        log("errors against fp64")
+        errors[args.workload] = {"steps": args.err_steps,
+                                 "rel_l2": field_errors(d, phi, u, args.err_steps,
+                                                        ("fp32", "mixed_fp16", "mixed_bf16"))}
+        dl, phl, ul, _ = wl.sheared_droplet_3d(n=64, R=16.0, W=4.0)
+        errors["laminar_sheared_droplet_64"] = {
+            "steps": 1000, "rel_l2": field_errors(dl, phl, ul, 1000, ("fp32", "mixed_fp16", "mixed_bf16"))}
+
+    probe = None
+    if not args.no_probes:
+        log("memory-pattern probes %d^3" % n)
+        probe = probes(n)
+        probe["step_kernel"] = {"ms": round(ms, 4), "TB_s": round(124 * nodes / (ms * 1e-3) / 1e12, 3)}
+
+    cpu = None
+    if not args.no_cpu and args.workload == "turb512":
+        log("oracle cpu baseline")
+        cpu = cpu_baseline(d, phi, u)
+    del phi, u
+
+    secondary = None
+    if not args.no_secondary and args.workload == "turb512":
+        d2, phi2, u2, desc2 = workload("tgv256")
+        secondary = {"workload": desc2, "forms": {}}
+        for prec in ("mixed_fp16", "fp32", "fp64", "mixed_bf16"):
+            log("secondary tgv256 %s" % prec)
+            s2, ms2, _ = time_form(d2, phi2, u2, prec, 100, 10, args.zblock)
+            secondary["forms"][prec] = line(d2, prec, ms2, 256 ** 3)
+            del s2
+            torch.cuda.empty_cache()
+        if not args.no_probes:
+            log("memory-pattern probes 256^3")
+            secondary["probes"] = probes(256)
+        del phi2, u2
+
     adjoint = None
     if not args.no_adjoint:
-        print("bench: adjoint", file=sys.stderr, flush=True)
+        log("adjoint")
         adjoint = time_adjoint(100)
         torch.cuda.empty_cache()
 
-    cpu = None
-    if not args.no_cpu:
-        print("bench: oracle cpu baseline", file=sys.stderr, flush=True)
-        cpu = cpu_baseline()
-
-    traffic = measured_traffic(args.precision)
+    traffic = measured_traffic(args.workload, args.precision)
     out = {
         "metric": "coupled PF-LB MLUPS + % HBM roofline; mixed-prec vs FP64/FP32 at stated error",
         "value": round(mlups, 1),
@@ -283,13 +435,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32",
         "data": "synthetic",
-        "config": {"workload": "3-D droplet in Taylor-Green vortex, D3Q19+D3Q7, %d^3 periodic, "
-                               "conservative AC, u0=0.05, Re=1000, R=40, rho ratio 10, W=4, M=0.05, "
-                               "We=%g" % (args.n, args.We),
-                   "storage": {"mixed_fp16": "g fp16 (4096 g/w), h fp32",
-                               "mixed_bf16": "g bf16 (g/w), h fp32",
-                               "fp32": "g, h fp32", "fp64": "g, h fp64"}[args.precision],
-                   "nodes": nodes, "parallelism": "single GPU"},
+        "config": {"workload": desc, "storage": STORAGE[args.precision], "nodes": nodes,
+                   "parallelism": "single GPU",
+                   "prewarm": "%.0f ms of steps from a checkpoint of the initial state, reloaded "
+                              "before the warm-up" % PREWARM_MS},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": None if traffic is None else round(traffic),
@@ -299,6 +448,8 @@ def main():
         "cpu_baseline": cpu,
         "forms": forms,
         "models": models,
+        "probes": probe,
+        "secondary": secondary,
         "adjoint": adjoint,
         "errors_vs_fp64": errors,
         "wall_s_timed": round(wall, 3),

@@ -265,6 +265,26 @@ int pflbm_adjoint_seed_phi(pflbm_t* h, const double* dphi, double* lam_g, double
 int pflbm_adjoint_init(pflbm_t* h, const double* phi0, const double* u0, const double* p0,
                        const double* lam_g, const double* lam_h, double* dphi0);
 
+/* Measurement only (no part of the method): memory-pattern probes of the
+   mixed-precision D3Q19 + D3Q7 step's HBM streams, 19 fp16 g and 6 fp32 h
+   populations per node read once and written once in the step's plane-major
+   layout [z][q][plane] (plane = nx ny rounded up to 64 nodes), with no
+   arithmetic. They give the bandwidth ceiling of the step kernel's access
+   pattern on the device at hand. g_src / g_dst hold g_bytes, h_src / h_dst
+   h_bytes of device memory (pflbm_probe_bytes); one launch per call on
+   hip_stream (hipStream_t), asynchronous; zblock = z planes per workgroup
+   (the step kernel's automatic depth reproduces its grid). Returns
+   PFLBM_EINVAL for bad sizes or pattern, PFLBM_EHIP if the launch fails. */
+#define PFLBM_PROBE_CHUNKS    0  /* contiguous 1024-node chunks of every population plane */
+#define PFLBM_PROBE_TILES     1  /* 256 x 4 tiles in XCD runs, z blocks marched, aligned */
+#define PFLBM_PROBE_SHIFT_LD  2  /* PFLBM_PROBE_TILES, g populations with c_x != 0 loaded
+                                    from x - c_x (the pull streaming of the step) */
+#define PFLBM_PROBE_SHIFT_ST  3  /* PFLBM_PROBE_TILES, those populations stored at x + c_x
+                                    (the shifted stores of in-place streaming) */
+int pflbm_probe_bytes(int nx, int ny, int nz, size_t* g_bytes, size_t* h_bytes);
+int pflbm_probe_stream(const void* g_src, void* g_dst, const void* h_src, void* h_dst, int nx,
+                       int ny, int nz, int pattern, int zblock, void* hip_stream);
+
 void pflbm_destroy(pflbm_t* h);
 const char* pflbm_last_error(const pflbm_t* h);
 const char* pflbm_strerror(int status);

@@ -18,7 +18,8 @@ OBJDIR = os.path.join(HERE, "_build")
 # lattice pair and phase-field model, each in its own compilation (in parallel)
 PAIRS = (0, 1, 2)
 MODELS = (0, 1, 2, 3, 4)
-SOURCES = ([("kernels.hip", "kernels", []), ("adjoint.hip", "adjoint", []), ("pflbm.cpp", "pflbm", [])]
+SOURCES = ([("kernels.hip", "kernels", []), ("adjoint.hip", "adjoint", []), ("pflbm.cpp", "pflbm", []),
+            ("probe.hip", "probe", [])]
            + [("step_inst.hip", "step_p%d_m%d" % (p, m), ["-DPFK_PAIR=%d" % p, "-DPFK_MODEL=%d" % m])
               for p in PAIRS for m in MODELS])
 

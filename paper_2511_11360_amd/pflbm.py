@@ -85,6 +85,10 @@ SIGNATURES = {
     "pflbm_adjoint_step": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "pflbm_adjoint_init": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "pflbm_adjoint_seed_phi": (ctypes.c_int, [_P, _P, _P, _P]),
+    "pflbm_probe_bytes": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
+    "pflbm_probe_stream": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_int, ctypes.c_int, _P]),
     "pflbm_destroy": (None, [_P]),
     "pflbm_last_error": (ctypes.c_char_p, [_P]),
     "pflbm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
