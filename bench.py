@@ -84,6 +84,8 @@ def prewarm(s):
     """Steps from a checkpoint of the current state for PREWARM_MS of GPU time,
     then the checkpoint is reloaded (the state is exactly the initial one)."""
     import torch
+    if PREWARM_MS <= 0:
+        return 0
     ck = s.save_state()
     e0, e1 = _events(s)
     n = 0
@@ -158,10 +160,15 @@ def probes(n, reps=20):
             rc = L.pflbm_probe_stream(*(ctypes.c_void_p(b.data_ptr()) for b in bufs), n, n, n, pat, zb,
                                       ctypes.c_void_p(st.cuda_stream))
             assert rc == 0, rc
-        for _ in range(max(3, int(PREWARM_MS / 3))):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(3):
+            go()
+        e1.record(st)
+        torch.cuda.synchronize()
+        for _ in range(int(PREWARM_MS / max(e0.elapsed_time(e1) / 3, 1e-3))):
             go()
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(st)
         for _ in range(reps):
             go()
@@ -305,6 +312,7 @@ STORAGE = {"mixed_fp16": "g fp16 (4096 g/w), h fp32", "mixed_bf16": "g bf16 (g/w
 
 
 def main():
+    global PREWARM_MS
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
@@ -320,9 +328,12 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-probes", action="store_true")
     ap.add_argument("--no-errors", action="store_true")
+    ap.add_argument("--prewarm-ms", type=float, default=PREWARM_MS,
+                    help="GPU time of the clock pre-warm before each timed line (0: none)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy first (counter calibration)")
     args = ap.parse_args()
+    PREWARM_MS = args.prewarm_ms
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)

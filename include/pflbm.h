@@ -281,6 +281,8 @@ int pflbm_adjoint_init(pflbm_t* h, const double* phi0, const double* u0, const d
                                     from x - c_x (the pull streaming of the step) */
 #define PFLBM_PROBE_SHIFT_ST  3  /* PFLBM_PROBE_TILES, those populations stored at x + c_x
                                     (the shifted stores of in-place streaming) */
+#define PFLBM_PROBE_ZSKEW     4  /* PFLBM_PROBE_SHIFT_LD; when one z block spans the box,
+                                    each workgroup starts at its own plane and wraps */
 int pflbm_probe_bytes(int nx, int ny, int nz, size_t* g_bytes, size_t* h_bytes);
 int pflbm_probe_stream(const void* g_src, void* g_dst, const void* h_src, void* h_dst, int nx,
                        int ny, int nz, int pattern, int zblock, void* hip_stream);

@@ -12,6 +12,9 @@
 //                         pull of the step kernel)
 //   PFLBM_PROBE_SHIFT_ST  PFLBM_PROBE_TILES with those populations stored at
 //                         x + c_x (the in-place schemes' shifted stores)
+//   PFLBM_PROBE_ZSKEW     PFLBM_PROBE_SHIFT_LD with, when one z block spans
+//                         the box, each workgroup starting its march at its
+//                         own plane (spread evenly over nz) and wrapping
 // Loads are ordinary and stores non-temporal, as in the step kernel.
 // Every index is wrapped into the box, so the probes stay inside the buffers
 // for any box.
@@ -65,16 +68,24 @@ __global__ __launch_bounds__(PNT) void k_probe(const ProbeArgs a) {
         zs = bz * a.zb;
     }
     if (!active) return;
-    const int ze = min(a.nz, zs + a.zb);
+    int ze = min(a.nz, zs + a.zb);
+    if constexpr (PATTERN == PFLBM_PROBE_ZSKEW) {
+        if (a.zb >= a.nz) {
+            const int nb = gridDim.x, b = remap_xcd(blockIdx.x, gridDim.x);
+            zs = (int)(((long long)b * a.nz) / nb);
+            ze = zs + a.nz;
+        }
+    }
     const int own = y * a.nx + x;
-    for (int z = zs; z < ze; ++z) {
+    for (int zv = zs; zv < ze; ++zv) {
+        const int z = zv < a.nz ? zv : zv - a.nz;
         const size_t gb = (size_t)z * PQG * a.P, hb = (size_t)z * PQH * a.P;
         uint16_t gv[PQG];
         unroll<PQG>([&](auto I) {
             constexpr int i = I;
             constexpr int cx = D3Q19::c(i, 0);
             int src = own;
-            if constexpr (PATTERN == PFLBM_PROBE_SHIFT_LD && cx != 0) {
+            if constexpr ((PATTERN == PFLBM_PROBE_SHIFT_LD || PATTERN == PFLBM_PROBE_ZSKEW) && cx != 0) {
                 int xs = x - cx;
                 xs = xs < 0 ? xs + a.nx : (xs >= a.nx ? xs - a.nx : xs);
                 src = y * a.nx + xs;
@@ -127,7 +138,7 @@ int pflbm_probe_stream(const void* g_src, void* g_dst, const void* h_src, void* 
     if (!g_src || !g_dst || !h_src || !h_dst) return PFLBM_EINVAL;
     if (nx < 1 || ny < 1 || nz < 1 || zblock < 1) return PFLBM_EINVAL;
     if ((long long)nx * ny * nz > 0x7fffffffLL) return PFLBM_EINVAL;
-    if (pattern < PFLBM_PROBE_CHUNKS || pattern > PFLBM_PROBE_SHIFT_ST) return PFLBM_EINVAL;
+    if (pattern < PFLBM_PROBE_CHUNKS || pattern > PFLBM_PROBE_ZSKEW) return PFLBM_EINVAL;
     ProbeArgs a;
     a.gs = (const uint16_t*)g_src;
     a.gd = (uint16_t*)g_dst;
@@ -149,7 +160,8 @@ int pflbm_probe_stream(const void* g_src, void* g_dst, const void* h_src, void* 
         const dim3 grid(a.ntx * a.nty * nzb);
         if (pattern == PFLBM_PROBE_TILES) hipLaunchKernelGGL(k_probe<PFLBM_PROBE_TILES>, grid, dim3(PNT), 0, st, a);
         else if (pattern == PFLBM_PROBE_SHIFT_LD) hipLaunchKernelGGL(k_probe<PFLBM_PROBE_SHIFT_LD>, grid, dim3(PNT), 0, st, a);
-        else hipLaunchKernelGGL(k_probe<PFLBM_PROBE_SHIFT_ST>, grid, dim3(PNT), 0, st, a);
+        else if (pattern == PFLBM_PROBE_SHIFT_ST) hipLaunchKernelGGL(k_probe<PFLBM_PROBE_SHIFT_ST>, grid, dim3(PNT), 0, st, a);
+        else hipLaunchKernelGGL(k_probe<PFLBM_PROBE_ZSKEW>, grid, dim3(PNT), 0, st, a);
     }
     return hipGetLastError() == hipSuccess ? PFLBM_OK : PFLBM_EHIP;
 }

@@ -32,6 +32,11 @@ PFLBM_PERIODIC = 0
 PFLBM_WALL = 1
 PFLBM_VISC_LINEAR_MU = 0
 PFLBM_VISC_LINEAR_NU = 1
+PFLBM_PROBE_CHUNKS = 0
+PFLBM_PROBE_TILES = 1
+PFLBM_PROBE_SHIFT_LD = 2
+PFLBM_PROBE_SHIFT_ST = 3
+PFLBM_PROBE_ZSKEW = 4
 
 PRECISIONS = {"fp64": PFLBM_FP64, "fp32": PFLBM_FP32, "mixed_fp16": PFLBM_MIXED_FP16,
               "mixed_bf16": PFLBM_MIXED_BF16}
