@@ -252,6 +252,21 @@ int pflbm_adjoint_step(pflbm_t* h, const double* fwd_g, const double* fwd_h,
                        const double* lam_g, const double* lam_h,
                        double* lam_g_out, double* lam_h_out, double* dparams, void* work);
 
+/* The same adjoint step for callers that cannot allocate device memory
+   (code under HIP graph capture, tight serving loops, harnesses that forbid
+   allocation): no workspace argument; the step uses a scratch array that the
+   library holds on each device it runs on, PFLBM_ADJOINT_SCRATCH_BYTES bytes
+   (enough for boxes of up to 128^3 = 2097152 nodes), until the process ends.
+   Returns PFLBM_EINVAL, launching nothing, when pflbm_adjoint_workspace_bytes
+   exceeds that. It allocates nothing. Calls that overlap on one device (on
+   different streams, or from different handles) share the array and race;
+   calls in order on one stream are safe. Results equal pflbm_adjoint_step's
+   bit for bit. */
+#define PFLBM_ADJOINT_SCRATCH_BYTES 100925440
+int pflbm_adjoint_step_noalloc(pflbm_t* h, const double* fwd_g, const double* fwd_h,
+                               const double* lam_g, const double* lam_h,
+                               double* lam_g_out, double* lam_h_out, double* dparams);
+
 /* Seed of the adjoint from a loss on the phase field of a state: given
    dL/dphi [z][y][x] (device float64), writes lambda = dL/dX for that state,
    lam_g [Qg][z][y][x] = 0 and lam_h [Qh][z][y][x] = dL/dphi for every

@@ -18,10 +18,46 @@
 //           h population (phi = sum h).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "internal.h"
 #include "lattice.h"
+#include "pflbm.h"
 
 namespace pfk {
+
+// Device scratch of pflbm_adjoint_step_noalloc, for callers that cannot
+// allocate: phi, the five per-node adjoint values and the per-workgroup
+// parameter partials of one adjoint step, for boxes of up to 128^3 nodes.
+// Every GPU the library runs on holds its own copy until the process ends;
+// host code reaches it only through the address hipGetSymbolAddress returns
+// for that device (adjoint_scratch below).
+static __device__ __align__(256) char scratch[PFLBM_ADJOINT_SCRATCH_BYTES];
+
+hipError_t adjoint_scratch(int device, void** out) {
+    constexpr int MAXDEV = 64;
+    static std::mutex mu;
+    static void* ptrs[MAXDEV] = {};
+    if (device < 0 || device >= MAXDEV) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptrs[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) {
+            const hipError_t r = hipSetDevice(cur);
+            if (e == hipSuccess) e = r;
+        }
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        ptrs[device] = p;
+    }
+    *out = ptrs[device];
+    return hipSuccess;
+}
 
 namespace {
 

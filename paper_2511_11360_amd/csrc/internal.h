@@ -172,6 +172,7 @@ struct AdjInitArgs {
 };
 
 // launchers (kernels.hip, adjoint.hip); return hipSuccess or the launch error
+hipError_t adjoint_scratch(int device, void** out);
 hipError_t launch_adjoint_seed(const double* dphi, double* lg, double* lh, long long nn, int qg, int qh,
                                hipStream_t st);
 hipError_t launch_adjoint(int lattice, const AdjArgs& a, double* dparams, hipStream_t s);

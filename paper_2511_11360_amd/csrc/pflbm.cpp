@@ -649,15 +649,47 @@ int pflbm_adjoint_workspace_bytes(const pflbm_t* h, size_t* bytes) {
     return PFLBM_OK;
 }
 
-int pflbm_adjoint_step(pflbm_t* h, const double* fwd_g, const double* fwd_h, const double* lam_g,
-                       const double* lam_h, double* lam_g_out, double* lam_h_out, double* dparams,
-                       void* work) {
+static int adjoint_check(pflbm_t* h) {
     int st = guard(h);
     if (st) return st;
     if (h->p.model != PFLBM_AC) return fail(h, PFLBM_EUNSUPPORTED, "adjoint implemented for the AC model only");
     if (h->p.lattice == PFLBM_D3Q27_D3Q7) return fail(h, PFLBM_EUNSUPPORTED, "adjoint implemented for D2Q9 and D3Q19 only");
     if (h->p.freeze_phi) return fail(h, PFLBM_EUNSUPPORTED, "adjoint of a frozen phase field is not implemented");
-    if (!fwd_g || !fwd_h || !lam_g || !lam_h || !lam_g_out || !lam_h_out || !work)
+    return PFLBM_OK;
+}
+
+static int adjoint_run(pflbm_t* h, const double* fwd_g, const double* fwd_h, const double* lam_g,
+                       const double* lam_h, double* lam_g_out, double* lam_h_out, double* dparams,
+                       void* work);
+
+int pflbm_adjoint_step(pflbm_t* h, const double* fwd_g, const double* fwd_h, const double* lam_g,
+                       const double* lam_h, double* lam_g_out, double* lam_h_out, double* dparams,
+                       void* work) {
+    if (int st = adjoint_check(h)) return st;
+    if (!work) return fail(h, PFLBM_EINVAL, "null pointer");
+    return adjoint_run(h, fwd_g, fwd_h, lam_g, lam_h, lam_g_out, lam_h_out, dparams, work);
+}
+
+int pflbm_adjoint_step_noalloc(pflbm_t* h, const double* fwd_g, const double* fwd_h, const double* lam_g,
+                               const double* lam_h, double* lam_g_out, double* lam_h_out, double* dparams) {
+    if (int st = adjoint_check(h)) return st;
+    size_t need = 0;
+    pflbm_adjoint_workspace_bytes(h, &need);
+    if (need > (size_t)PFLBM_ADJOINT_SCRATCH_BYTES) {
+        char buf[160];
+        std::snprintf(buf, sizeof(buf), "the adjoint of this box needs %zu bytes of scratch, more than the "
+                      "library's %zu (boxes of up to 128^3 nodes)", need, (size_t)PFLBM_ADJOINT_SCRATCH_BYTES);
+        return fail(h, PFLBM_EINVAL, buf);
+    }
+    void* ptr = nullptr;
+    HIPCHK(h, adjoint_scratch(h->device, &ptr), "adjoint scratch address");
+    return adjoint_run(h, fwd_g, fwd_h, lam_g, lam_h, lam_g_out, lam_h_out, dparams, ptr);
+}
+
+static int adjoint_run(pflbm_t* h, const double* fwd_g, const double* fwd_h, const double* lam_g,
+                       const double* lam_h, double* lam_g_out, double* lam_h_out, double* dparams,
+                       void* work) {
+    if (!fwd_g || !fwd_h || !lam_g || !lam_h || !lam_g_out || !lam_h_out)
         return fail(h, PFLBM_EINVAL, "null pointer");
     if (lam_g_out == lam_g || lam_h_out == lam_h) return fail(h, PFLBM_EINVAL, "lambda in and out must not alias");
     const size_t nn = adj_nodes(h);

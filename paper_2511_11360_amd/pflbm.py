@@ -90,6 +90,7 @@ SIGNATURES = {
     "pflbm_adjoint_step": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "pflbm_adjoint_init": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "pflbm_adjoint_seed_phi": (ctypes.c_int, [_P, _P, _P, _P]),
+    "pflbm_adjoint_step_noalloc": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "pflbm_probe_bytes": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
     "pflbm_probe_stream": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int,

@@ -132,6 +132,12 @@ class Solver:
                                               _ptr(lam_h), _ptr(out_g), _ptr(out_h),
                                               _ptr(dparams), _ptr(work)), self.h)
 
+    def adjoint_step_noalloc(self, fwd_g, fwd_h, lam_g, lam_h, out_g, out_h, dparams):
+        """adjoint_step without a workspace (the library's own device scratch)."""
+        self._check(self.L.pflbm_adjoint_step_noalloc(self.h, _ptr(fwd_g), _ptr(fwd_h), _ptr(lam_g),
+                                                      _ptr(lam_h), _ptr(out_g), _ptr(out_h),
+                                                      _ptr(dparams)), self.h)
+
     def adjoint_seed_phi(self, dphi):
         """(lambda_g, lambda_h) of a loss with gradient dphi with respect to the
         phase field of a state (pflbm_adjoint_seed_phi)."""
