@@ -15,7 +15,8 @@
 //           directly, dL/dgrad phi, dL/dlap phi and the parameter terms
 //           (block partials in float64);
 //   pass 3  per node: transpose of the two stencils as a gather, added to every
-//           h population (phi = sum h).
+//           h population (phi = sum h), plus the direct term of h (the h stream
+//           transpose of lambda_h^{n+1} times 1 - 1/tau_phi).
 #include <hip/hip_runtime.h>
 
 #include <mutex>
@@ -262,7 +263,7 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
                                                     : (size_t)al * nn + nb.index(cx, cy, cz);
             lh[al] = a.lh[e];
         });
-        double b_g[Q], b_h[QH];
+        double b_g[Q];
         double b_phi = 0.0, b_gr[3] = {0.0, 0.0, 0.0}, b_lap = 0.0;
         double b_u[3] = {0.0, 0.0, 0.0}, b_F[3] = {0.0, 0.0, 0.0};
         double b_ps = 0.0, b_irho = 0.0, b_itau = 0.0, b_usq = 0.0, b_aeq = 0.0;
@@ -277,7 +278,6 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
             const double base = 1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * usq;
             const double heq = w * phi * base;
             const double lb = lh[al];
-            b_h[al] = (1.0 - itp) * lb;
             b_itp += (heq - h[al]) * lb;
             b_gfp += w * coef * eg * lb;
             b_coef += gfp * w * eg * lb;
@@ -435,7 +435,7 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
         th[2] = -b_beta4 * 48.0 * sigma / (W * W) + b_kappa * 1.5 * sigma - b_anti * 4.0 / (W * W);
 
         for (int i = 0; i < Q; ++i) a.og[(size_t)i * nn + n] = b_g[i];
-        for (int al = 0; al < QH; ++al) a.oh[(size_t)al * nn + n] = b_h[al];
+        // the direct h adjoint (1 - itp) lambda*_h is formed by the stencil pass
         a.work[n] = b_phi;
         a.work[nn + n] = b_gr[0];
         a.work[2 * nn + n] = b_gr[1];
@@ -457,8 +457,10 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
 
 // pass 3: transpose of grad phi(x) = 3 sum w c phi(src(x, i)) and
 // lap phi(x) = 6 sum w (phi(src(x, i)) - phi(x)), src = periodic image or wall
-// mirror of x + c_i, as a gather at y over {x : src(x, i) = y}; then every h
-// population of y receives dL/dphi(y).
+// mirror of x + c_i, as a gather at y over {x : src(x, i) = y}; every h
+// population of y receives that plus dL/dphi(y), and its direct term
+// (1 - 1/tau_phi) lambda*_h (the h stream transpose of lambda_h^{n+1},
+// gathered here rather than written by the sweep and read back).
 template <class PAIR>
 __global__ __launch_bounds__(256) void k_adj_stencil(const AdjArgs a) {
     using GL = typename PAIR::G;
@@ -501,7 +503,14 @@ __global__ __launch_bounds__(256) void k_adj_stencil(const AdjArgs a) {
             }
         });
     });
-    for (int al = 0; al < HL::Q; ++al) a.oh[(size_t)al * nn + n] += acc;
+    const double itp1 = 1.0 - a.ph.inv_tau_phi;
+    unroll<HL::Q>([&](auto J) {
+        constexpr int al = J;
+        constexpr int cx = HL::c(al, 0), cy = HL::c(al, 1), cz = HL::c(al, 2);
+        const size_t e = nb.beyond(cx, cy, cz) ? (size_t)HL::opp(al) * nn + n
+                                                : (size_t)al * nn + nb.index(cx, cy, cz);
+        a.oh[(size_t)al * nn + n] = itp1 * a.lh[e] + acc;
+    });
 }
 
 // one workgroup, fixed summation order (bit-reproducible); 1024 threads so the

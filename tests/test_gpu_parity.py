@@ -58,11 +58,32 @@ def test_rayleigh_taylor_walls_ragged_ch():
 
 
 def test_rayleigh_taylor_walls_ragged_ac_hydrostatic():
-    """AC with gravity: started in hydrostatic balance (pressure input path).
-    Still mildly ill-conditioned: two oracle runs whose initial populations
-    differ by one ulp already differ by 5e-13 to 8e-13 in h at step 101 (g:
-    1e-15). g must match to 1e-12, h to 1e-12 plus ten times that spread; the
-    1001-step run is checked against the oracle's rounding spread below."""
+    """AC with gravity from a hydrostatic start (pressure input path), 1001
+    steps, every distribution within 1e-12. With normal_eps = 1e-3 the layout
+    is well conditioned: two oracle runs whose initial populations differ by
+    one ulp stay within 1e-15 of each other over the 1001 steps."""
+    d, phi, u = wl.rayleigh_taylor_2d(model="AC", nx=70, ny=90)
+    d["normal_eps"] = 1e-3
+    _parity(d, phi, u, 1001, "RT 2-D walls AC hydrostatic, normal_eps 1e-3", p0=hydrostatic_p0(d, phi))
+
+
+def test_rayleigh_taylor_walls_ragged_ac_rest_start():
+    """The Rayleigh-Taylor layout's own start (zero velocity, zero pressure),
+    AC, 1001 steps, every distribution within 1e-12. With normal_eps = 1e-2 the
+    acoustic start-up no longer amplifies rounding (oracle one-ulp spread
+    7.5e-16 after 1001 steps)."""
+    d, phi, u = wl.rayleigh_taylor_2d(model="AC", nx=70, ny=90)
+    d["normal_eps"] = 1e-2
+    _parity(d, phi, u, 1001, "RT 2-D walls AC rest start, normal_eps 1e-2")
+
+
+def test_rayleigh_taylor_ac_default_normal_within_twice_the_oracle_spread():
+    """With the default normal_eps = 1e-4 the RT layout is ill conditioned even
+    from a hydrostatic start: phi overshoots 1 by 2e-5 in the heavy bulk, where
+    the gradient is far below eps, and the antidiffusion flux there amplifies
+    rounding (two oracle runs one ulp apart: 7e-13 in h after 101 steps, 5e-12
+    after 301, 1e-7 after 1001). After 101 steps g must match to 1e-12 and h
+    within 1e-12 plus twice that oracle-vs-oracle spread."""
     d, phi, u = wl.rayleigh_taylor_2d(model="AC", nx=70, ny=90)
     p0 = hydrostatic_p0(d, phi)
     steps = 101
@@ -75,26 +96,7 @@ def test_rayleigh_taylor_walls_ragged_ac_hydrostatic():
          % (eg.max(), eh.max(), eh_env.max()))
     assert np.all(np.isfinite(g)) and np.all(np.isfinite(h))
     assert eg.max() <= TOL
-    assert eh.max() <= TOL + 10 * eh_env.max()
-
-
-def test_rayleigh_taylor_ac_within_oracle_rounding_envelope():
-    """RT with the AC model started at rest pressure is ill-conditioned: the
-    acoustic start-up moves phi off 1 in the heavy bulk where the gradient is
-    small, and the antidiffusion flux there amplifies any rounding difference
-    (a 1e-15 change grows to ~1e-4 in 1000 steps in the oracle itself). The HIP
-    result must lie within the oracle's own rounding spread."""
-    d, phi, u = wl.rayleigh_taylor_2d(model="AC", nx=70, ny=90)
-    steps = 1001
-    s = gpu_run(d, phi, u, steps)
-    g, h = gpu_dists(s)
-    eg_env, eh_env, st = oracle_envelope(d, phi, u, steps)
-    eg = max_abs_per_population(g, st.g)
-    eh = max_abs_per_population(h, st.h)
-    _say("  RT AC 1001: max|dg| %.3e (oracle spread %.3e) max|dh| %.3e (spread %.3e)"
-         % (eg.max(), eg_env.max(), eh.max(), eh_env.max()))
-    assert eg.max() <= 100 * eg_env.max() + TOL
-    assert eh.max() <= 100 * eh_env.max() + TOL
+    assert eh.max() <= TOL + 2 * eh_env.max()
 
 
 def test_layered_poiseuille_frozen_phi():
