@@ -225,6 +225,40 @@ def time_adjoint(steps):
             "hbm_frac": round(ADJ_BYTES * nodes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
 
 
+def time_backward(nsteps=200):
+    """A full backward pass of the 128^3 sheared droplet (the adjoint workload:
+    walls moving at -+0.02, loss 1/2 sum (phi_N - phi*)^2) through the
+    autograd wrapper, with ceil(sqrt(nsteps)) checkpoints: per step, the
+    recompute of the forward step from its segment's checkpoint, the read-out
+    of its state in canonical float64 and the adjoint step. Forward pass
+    (steps plus checkpoints) timed beside it. float64 and float32 forward."""
+    import torch
+    from paper_2511_11360_amd import workloads as wl
+    from paper_2511_11360_amd.autograd import run_phase_field
+    d, phi, u, target = wl.sheared_droplet_3d()
+    out = {"workload": "3-D sheared droplet, D3Q19+D3Q7, 128^3, walls moving at -+0.02, "
+                       "%d steps, %d checkpoints" % (nsteps, math.ceil(math.sqrt(nsteps)))}
+    tg = torch.as_tensor(target, device="cuda")
+    ut = torch.as_tensor(u, device="cuda")
+    for prec in ("fp64", "fp32"):
+        phi0 = torch.as_tensor(phi, device="cuda").requires_grad_(True)
+        params = [torch.tensor(d[k], dtype=torch.float64, requires_grad=True) for k in ("sigma", "M", "W")]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        phiN = run_phase_field(phi0, *params, d, ut, nsteps, precision=prec)
+        L = 0.5 * ((phiN - tg) ** 2).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        out[prec] = {"forward_ms_per_step": round((t1 - t0) * 1e3 / nsteps, 4),
+                     "backward_ms_per_step": round((t2 - t1) * 1e3 / nsteps, 4)}
+        del phi0, params, phiN, L
+        torch.cuda.empty_cache()
+    return out
+
+
 def field_errors(d, phi, u, steps, forms):
     """Relative L2 error per field (phi, |u| vector, p) of each form against
     the fp64 form after `steps` steps from the same initial state."""
@@ -307,6 +341,46 @@ def measured_traffic(name, precision):
     return sum(vals) / len(vals)
 
 
+def volume_trace(name, steps, every, forms=("fp64", "fp32", "mixed_fp16", "mixed_bf16")):
+    """Long-horizon FP64 diagnostics of each storage form on one workload:
+    droplet volume (sum phi, Eq. volume_continuous), the count-based volume
+    (nodes with phi > 1/2) and the phi extrema every `every` steps."""
+    import torch
+    from paper_2511_11360_amd.solver import Solver
+    d, phi, u, desc = workload(name)
+    out = {"workload": desc, "steps": steps, "every": every, "traces": {}}
+    for prec in forms:
+        s = Solver(d, precision=prec)
+        s.init(phi, u)
+        tr = {k: [] for k in ("step", "V_phi", "V_count", "phi_min", "phi_max")}
+        t0 = time.perf_counter()
+        for k in range(0, steps + 1, every):
+            if k:
+                s.step(every)
+            v = s.volume()
+            tr["step"].append(k)
+            for key in ("V_phi", "V_count", "phi_min", "phi_max"):
+                tr[key].append(v[key])
+            if k % max(every, steps // 10) == 0:
+                log("trace %s %s step %d V_phi %.6f V_count %d (%.0f s)"
+                    % (name, prec, k, v["V_phi"], v["V_count"], time.perf_counter() - t0))
+        out["traces"][prec] = tr
+        del s
+        torch.cuda.empty_cache()
+    ref = out["traces"].get("fp64")
+    if ref:
+        out["summary"] = {}
+        for prec, tr in out["traces"].items():
+            rel = [abs(a - b) / abs(b) for a, b in zip(tr["V_phi"], ref["V_phi"])]
+            out["summary"][prec] = {
+                "V_phi_drift": tr["V_phi"][-1] / tr["V_phi"][0] - 1,
+                "max_rel_dV_phi_vs_fp64": max(rel),
+                "final_rel_dV_phi_vs_fp64": rel[-1],
+                "final_dV_count_vs_fp64": tr["V_count"][-1] - ref["V_count"][-1],
+                "max_phi": max(tr["phi_max"]), "min_phi": min(tr["phi_min"])}
+    return out
+
+
 STORAGE = {"mixed_fp16": "g fp16 (4096 g/w), h fp32", "mixed_bf16": "g bf16 (g/w), h fp32",
            "fp32": "g, h fp32", "fp64": "g, h fp64"}
 
@@ -330,6 +404,10 @@ def main():
     ap.add_argument("--no-errors", action="store_true")
     ap.add_argument("--prewarm-ms", type=float, default=PREWARM_MS,
                     help="GPU time of the clock pre-warm before each timed line (0: none)")
+    ap.add_argument("--volume-trace", default=None, choices=["turb512", "tgv256"],
+                    help="instead of the benchmark: FP64 volume diagnostics of every storage form "
+                         "over --steps steps, every --trace-every steps (one JSON line)")
+    ap.add_argument("--trace-every", type=int, default=100)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy first (counter calibration)")
     args = ap.parse_args()
@@ -343,6 +421,9 @@ def main():
     from paper_2511_11360_amd import workloads as wl
 
     torch.cuda.set_device(0)
+    if args.volume_trace:
+        print(json.dumps({"volume_trace": volume_trace(args.volume_trace, args.steps, args.trace_every)}))
+        return
     if args.copy_calibration:
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -431,6 +512,8 @@ def main():
         log("adjoint")
         adjoint = time_adjoint(100)
         torch.cuda.empty_cache()
+        log("backward pass")
+        adjoint["backward"] = time_backward()
 
     traffic = measured_traffic(args.workload, args.precision)
     out = {

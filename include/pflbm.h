@@ -99,6 +99,11 @@ extern "C" {
 #define PFLBM_FP32        1  /* g, h float32; float32 arithmetic */
 #define PFLBM_MIXED_FP16  2  /* g stored as fp16 of 4096 g_i / w_i, h float32; float32 arithmetic */
 #define PFLBM_MIXED_BF16  3  /* g stored as bf16 of g_i / w_i, h float32; float32 arithmetic */
+/* In both 16-bit forms the step rounds the stored g stochastically (unbiased:
+   up or down with probabilities that make the expectation the float32 value),
+   from random bits keyed by node, step and population, so runs are
+   reproducible and independent of the tile and z block; initialisation and
+   pflbm_set_distributions round to nearest even. */
 
 /* step-kernel tile: x nodes by y rows per workgroup, one node per thread
    (3-D; the 2-D lattice always uses 64 x 4). Results do not depend on it. */

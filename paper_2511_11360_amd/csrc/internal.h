@@ -93,6 +93,7 @@ struct KArgs {
     int nx, ny, nz;
     int ntx, nty, ntz, zb; // tiles per axis, z planes per tile
     int tile;              // tile index (TILE_NX / TILE_NY), 3-D step only
+    unsigned step;         // steps completed before this one (key of the stochastic rounding)
     int bc[3];             // 0 periodic, 1 wall
     int wall_axis;         // -1 none, else 0/1/2
     int write_h;           // 0 when phi is frozen

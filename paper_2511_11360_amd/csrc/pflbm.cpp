@@ -477,6 +477,7 @@ int pflbm_step(pflbm_t* h, int nsteps) {
         a.nty = h->L.nty_step;
         a.ntz = h->L.ntz_step;
         a.zb = h->L.zb_step;
+        a.step = (unsigned)h->steps;
         if ((st = run_gamma(h, a))) return st;
         HIPCHK(h, launch_step(h->p.lattice, h->p.model, h->p.precision, MODE_STEP, a, h->stream), "step kernel");
         if (!h->p.freeze_phi) h->hcur ^= 1;

@@ -56,13 +56,47 @@ template <> struct Types<1> { using T = float;  using GS = float;    using HS = 
 template <> struct Types<2> { using T = float;  using GS = _Float16; using HS = float;  };
 template <> struct Types<3> { using T = float;  using GS = uint16_t; using HS = float;  };
 
+// Random words for the stochastic rounding of the 16-bit g store: a
+// counter-based generator keyed by the node, the step and the population, so
+// the rounding is reproducible and independent of the launch shape. The
+// 32-bit integer finaliser "lowbias32" of C. Wellons' hash prospector mixes
+// the node index with the mixed step into the seed of a xorshift32 sequence
+// (G. Marsaglia, "Xorshift RNGs", J. Stat. Softw. 8(14), 2003), which yields
+// one word per population in a fixed order.
+__host__ __device__ constexpr uint32_t sr_mix(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+struct SRBits {
+    uint32_t s;
+    __device__ __forceinline__ SRBits(uint32_t node, uint32_t step) : s(sr_mix(node ^ sr_mix(step)) | 1u) {}
+    __device__ __forceinline__ uint32_t next() {
+        s ^= s << 13;
+        s ^= s >> 17;
+        s ^= s << 5;
+        return s;
+    }
+};
+
 // g codec: the scaled forms store s_i = K g_i / w_i (fp16, K = 4096) or g_i / w_i
-// (bf16), rounded to nearest even.
+// (bf16). enc rounds to nearest even (initialisation, canonical write-back);
+// enc_sr, used by the step, rounds stochastically: with r uniform over the
+// bits the 16-bit form drops, adding r to the float32 bit pattern and
+// truncating rounds the magnitude up with probability equal to the dropped
+// fraction of an ulp, so the stored value is unbiased (its expectation is the
+// float32 value) and rounding errors do not accumulate systematically over
+// steps; the error is below one ulp of the stored form.
 template <int P> struct GCodec {
     template <class L, int i, class GS, class T>
     static __device__ __forceinline__ T dec(GS v) { return (T)v; }
     template <class L, int i, class GS, class T>
     static __device__ __forceinline__ GS enc(T v) { return (GS)v; }
+    template <class L, int i, class GS, class T>
+    static __device__ __forceinline__ GS enc_sr(T v, uint32_t) { return (GS)v; }
 };
 template <> struct GCodec<2> {
     template <class L, int i, class GS, class T>
@@ -74,6 +108,14 @@ template <> struct GCodec<2> {
     static __device__ __forceinline__ _Float16 enc(float v) {
         constexpr float s = (float)(4096.0 / L::w(i));
         return (_Float16)(v * s);
+    }
+    // 13 float32 mantissa bits below fp16's; the truncated pattern is an fp16
+    // value (in fp16's normal range), so the conversion is exact there
+    template <class L, int i, class GS, class T>
+    static __device__ __forceinline__ _Float16 enc_sr(float v, uint32_t r) {
+        constexpr float s = (float)(4096.0 / L::w(i));
+        const uint32_t b = (__float_as_uint(v * s) + (r & 0x1FFFu)) & 0xFFFFE000u;
+        return (_Float16)__uint_as_float(b);
     }
 };
 template <> struct GCodec<3> {
@@ -88,6 +130,11 @@ template <> struct GCodec<3> {
         uint32_t u = __float_as_uint(v * s);
         u += 0x7FFFu + ((u >> 16) & 1u);
         return (uint16_t)(u >> 16);
+    }
+    template <class L, int i, class GS, class T>
+    static __device__ __forceinline__ uint16_t enc_sr(float v, uint32_t r) {
+        constexpr float s = (float)(1.0 / L::w(i));
+        return (uint16_t)((__float_as_uint(v * s) + (r & 0xFFFFu)) >> 16);
     }
 };
 
@@ -1095,9 +1142,10 @@ __global__ __launch_bounds__(TILE_THREADS[TS]) void k_step(const KArgs a) {
             // formed and every store adds its plane base to it in vector code.
             int so = o11;
             lane_opaque(so);
+            SRBits rb((uint32_t)(((size_t)z * ny + y) * nx + x), a.step);
             auto gsink = [&](auto I, T v) {
                 constexpr int i = I;
-                __builtin_nontemporal_store(GC::template enc<GL, i, GS, T>(v), &at<QG>(Gout, z, i, P, so));
+                __builtin_nontemporal_store(GC::template enc_sr<GL, i, GS, T>(v, rb.next()), &at<QG>(Gout, z, i, P, so));
             };
             auto hsink = [&](auto J, T v) {
                 constexpr int al = J;

@@ -162,8 +162,9 @@ def test_turbulence_512_sampled_nodes(precision):
         if precision == "fp32":
             eg, eh = _float_fraction(got_g[:, None], ref_g[:, None], got_h, ref_h, w, 2e-6, 2e-6)
         else:
-            # fp16 of 4096 g / w: 2^-11 relative rounding, float32 arithmetic
-            eg, eh = _float_fraction(got_g[:, None], ref_g[:, None], got_h, ref_h, w, 2.0 ** -10, 1e-6)
+            # fp16 of 4096 g / w, stochastically rounded: below one ulp (2^-10
+            # relative), tolerance twice that; float32 arithmetic
+            eg, eh = _float_fraction(got_g[:, None], ref_g[:, None], got_h, ref_h, w, 2.0 ** -9, 1e-6)
         e = max(eg, eh)
         assert e <= 1.0, ((x, y, z), eg, eh)
         worst = max(worst, e)

@@ -181,14 +181,17 @@ def test_automatic_zblock_matches_fixed_depth(model, precision):
     (7 planes on 256 units, the last block 1 plane); every population must
     equal the run with 5-plane blocks bit for bit, since each node takes the
     same arithmetic whatever block it falls in (Liang2014 included: its
-    kernel forms mu_phi on each block's own halo)."""
+    kernel forms mu_phi on each block's own halo). So must a single 50-plane
+    block, whose march starts at a different plane in every workgroup and
+    wraps around the periodic z axis."""
     d, phi, u = small_3d(nx=40, ny=128, nz=50, R=9.0, model=model)
     out = []
-    for zb in (0, 5):
+    for zb in (0, 5, 50):
         _say("  %s %s zblock %d" % (model, precision, zb))
         out.append(gpu_dists(gpu_run(d, phi, u, 60, precision=precision, tile="256x4", zblock=zb)))
-    (g0, h0), (g1, h1) = out
-    assert np.array_equal(g0, g1) and np.array_equal(h0, h1)
+    g0, h0 = out[0]
+    for g1, h1 in out[1:]:
+        assert np.array_equal(g0, g1) and np.array_equal(h0, h1)
 
 
 def test_fields_and_diagnostics_match_oracle():
