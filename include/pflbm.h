@@ -103,7 +103,8 @@ extern "C" {
    up or down with probabilities that make the expectation the float32 value),
    from random bits keyed by node, step and population, so runs are
    reproducible and independent of the tile and z block; initialisation and
-   pflbm_set_distributions round to nearest even. */
+   pflbm_set_distributions round to nearest even, and so does every store of
+   PFLBM_L14 (its kernel has no registers to spare for the random words). */
 
 /* step-kernel tile: x nodes by y rows per workgroup, one node per thread
    (3-D; the 2-D lattice always uses 64 x 4). Results do not depend on it. */
@@ -249,9 +250,9 @@ int pflbm_load_state(pflbm_t* h, const void* dev_src);
    pflbm_adjoint_workspace_bytes(). Uses the handle's parameters; float64
    arithmetic whatever the handle's precision. The method's reverse mode is
    not in the paper: it is the exact transpose of the discrete step of
-   Sec. II.C.1 as implemented here. Returns PFLBM_EUNSUPPORTED for any other
-   model (CH, nonlocal, Liang2018, Liang2014), for D3Q27 and for a frozen
-   phase field. */
+   Sec. II.C.1 as implemented here, on every lattice pair. Returns
+   PFLBM_EUNSUPPORTED for any other model (CH, nonlocal, Liang2018,
+   Liang2014) and for a frozen phase field. */
 int pflbm_adjoint_workspace_bytes(const pflbm_t* h, size_t* bytes);
 int pflbm_adjoint_step(pflbm_t* h, const double* fwd_g, const double* fwd_h,
                        const double* lam_g, const double* lam_h,

@@ -123,6 +123,26 @@ struct Nbr {
     }
 };
 
+// stress row k of the two-rate collision evaluated at velocity i: 3 c_x^2 - c^2,
+// c_y^2 - c_z^2, c_x c_y, c_y c_z, c_x c_z (2-D: c_x^2 - c_y^2, 0, c_x c_y, 0, 0)
+template <class GL, bool D3>
+__host__ __device__ constexpr int stress_row(int k, int i) {
+    const int cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
+    if (k == 0) return D3 ? 3 * cx * cx - (cx * cx + cy * cy + cz * cz) : cx * cx - cy * cy;
+    if (k == 1) return D3 ? cy * cy - cz * cz : 0;
+    if (k == 2) return cx * cy;
+    if (k == 3) return cy * cz;
+    return cx * cz;
+}
+// its squared norm over the velocity set (the projector's denominator; 36,
+// 12, 4 on D3Q19 and 36, 12, 12 on D3Q27 for the rows of each kind)
+template <class GL, bool D3>
+__host__ __device__ constexpr double stress_norm(int k) {
+    int s = 0;
+    for (int i = 0; i < GL::Q; ++i) s += stress_row<GL, D3>(k, i) * stress_row<GL, D3>(k, i);
+    return s > 0 ? (double)s : 1.0;
+}
+
 }  // namespace
 
 __global__ __launch_bounds__(256) void k_adj_phi(const AdjArgs a) {
@@ -209,33 +229,27 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
         for (int k = 0; k < 3; ++k)
             for (int l = 0; l < 3; ++l)
                 Pi[k][l] = m2[k][l] - (k == l ? s3 : 0.0) - u[k] * u[l];
-        // stress-projection coefficients (linear in Pi)
+        // stress-projection coefficients (linear in Pi), each row's sum over
+        // the populations divided by its squared norm
+        constexpr double N0 = stress_norm<GL, D3>(0), N1 = stress_norm<GL, D3>(1),
+                         N2 = stress_norm<GL, D3>(2), N3 = stress_norm<GL, D3>(3),
+                         N4 = stress_norm<GL, D3>(4);
         double A[5];
         if constexpr (D3) {
-            A[0] = (2.0 * Pi[0][0] - Pi[1][1] - Pi[2][2]) / 36.0;
-            A[1] = (Pi[1][1] - Pi[2][2]) / 12.0;
-            A[2] = Pi[0][1] / 4.0;
-            A[3] = Pi[1][2] / 4.0;
-            A[4] = Pi[0][2] / 4.0;
+            A[0] = (2.0 * Pi[0][0] - Pi[1][1] - Pi[2][2]) / N0;
+            A[1] = (Pi[1][1] - Pi[2][2]) / N1;
+            A[2] = Pi[0][1] / N2;
+            A[3] = Pi[1][2] / N3;
+            A[4] = Pi[0][2] / N4;
         } else {
-            A[0] = (Pi[0][0] - Pi[1][1]) / 4.0;
+            A[0] = (Pi[0][0] - Pi[1][1]) / N0;
             A[1] = 0.0;
-            A[2] = Pi[0][1] / 4.0;
+            A[2] = Pi[0][1] / N2;
             A[3] = 0.0;
             A[4] = 0.0;
         }
         auto qrow = [&](int i, double* q) {   // stress rows evaluated at c_i
-            const int cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
-            if (D3) {
-                q[0] = 3 * cx * cx - (cx * cx + cy * cy + cz * cz);
-                q[1] = cy * cy - cz * cz;
-            } else {
-                q[0] = cx * cx - cy * cy;
-                q[1] = 0.0;
-            }
-            q[2] = cx * cy;
-            q[3] = cy * cz;
-            q[4] = cx * cz;
+            for (int k = 0; k < 5; ++k) q[k] = stress_row<GL, D3>(k, i);
         };
         const double gg = gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2];
         const double sn = gg + ph.eps2;
@@ -319,16 +333,16 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
         }
         // A (linear in Pi)
         if constexpr (D3) {
-            b_Pi[0][0] += 2.0 * b_A[0] / 36.0;
-            b_Pi[1][1] += -b_A[0] / 36.0 + b_A[1] / 12.0;
-            b_Pi[2][2] += -b_A[0] / 36.0 - b_A[1] / 12.0;
-            b_Pi[0][1] += b_A[2] / 4.0;
-            b_Pi[1][2] += b_A[3] / 4.0;
-            b_Pi[0][2] += b_A[4] / 4.0;
+            b_Pi[0][0] += 2.0 * b_A[0] / N0;
+            b_Pi[1][1] += -b_A[0] / N0 + b_A[1] / N1;
+            b_Pi[2][2] += -b_A[0] / N0 - b_A[1] / N1;
+            b_Pi[0][1] += b_A[2] / N2;
+            b_Pi[1][2] += b_A[3] / N3;
+            b_Pi[0][2] += b_A[4] / N4;
         } else {
-            b_Pi[0][0] += b_A[0] / 4.0;
-            b_Pi[1][1] += -b_A[0] / 4.0;
-            b_Pi[0][1] += b_A[2] / 4.0;
+            b_Pi[0][0] += b_A[0] / N0;
+            b_Pi[1][1] += -b_A[0] / N0;
+            b_Pi[0][1] += b_A[2] / N2;
         }
         // Pi_kl = m2_kl - delta s3 - u_k u_l (only k <= l entries carry adjoints)
         double b_m2[3][3] = {{0.0}}, b_s3 = 0.0;
@@ -587,9 +601,12 @@ hipError_t launch_adjoint(int lattice, const AdjArgs& a, double* dparams, hipStr
     if (lattice == 0) {
         hipLaunchKernelGGL(k_adj_local<Pair2D>, grid, block, 0, st, a);
         hipLaunchKernelGGL(k_adj_stencil<Pair2D>, grid, block, 0, st, a);
-    } else {
+    } else if (lattice == 1) {
         hipLaunchKernelGGL(k_adj_local<Pair3D>, grid, block, 0, st, a);
         hipLaunchKernelGGL(k_adj_stencil<Pair3D>, grid, block, 0, st, a);
+    } else {
+        hipLaunchKernelGGL(k_adj_local<Pair3D27>, grid, block, 0, st, a);
+        hipLaunchKernelGGL(k_adj_stencil<Pair3D27>, grid, block, 0, st, a);
     }
     if (dparams) hipLaunchKernelGGL(k_adj_params, dim3(1), dim3(PARAMS_THREADS), 0, st, a.partials, (int)grid.x, dparams);
     return hipGetLastError();
@@ -599,7 +616,8 @@ hipError_t launch_adjoint_init(int lattice, const AdjInitArgs& a, hipStream_t st
     const long long nn = (long long)a.nx * a.ny * a.nz;
     const dim3 grid((unsigned)((nn + 255) / 256)), block(256);
     if (lattice == 0) hipLaunchKernelGGL(k_adj_init<Pair2D>, grid, block, 0, st, a);
-    else hipLaunchKernelGGL(k_adj_init<Pair3D>, grid, block, 0, st, a);
+    else if (lattice == 1) hipLaunchKernelGGL(k_adj_init<Pair3D>, grid, block, 0, st, a);
+    else hipLaunchKernelGGL(k_adj_init<Pair3D27>, grid, block, 0, st, a);
     return hipGetLastError();
 }
 

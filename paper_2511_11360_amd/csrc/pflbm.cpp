@@ -654,7 +654,6 @@ static int adjoint_check(pflbm_t* h) {
     int st = guard(h);
     if (st) return st;
     if (h->p.model != PFLBM_AC) return fail(h, PFLBM_EUNSUPPORTED, "adjoint implemented for the AC model only");
-    if (h->p.lattice == PFLBM_D3Q27_D3Q7) return fail(h, PFLBM_EUNSUPPORTED, "adjoint implemented for D2Q9 and D3Q19 only");
     if (h->p.freeze_phi) return fail(h, PFLBM_EUNSUPPORTED, "adjoint of a frozen phase field is not implemented");
     return PFLBM_OK;
 }
@@ -733,7 +732,6 @@ int pflbm_adjoint_init(pflbm_t* h, const double* phi0, const double* u0, const d
     int st = guard(h);
     if (st) return st;
     if (h->p.model != PFLBM_AC) return fail(h, PFLBM_EUNSUPPORTED, "adjoint implemented for the AC model only");
-    if (h->p.lattice == PFLBM_D3Q27_D3Q7) return fail(h, PFLBM_EUNSUPPORTED, "adjoint implemented for D2Q9 and D3Q19 only");
     if (!phi0 || !lam_g || !lam_h || !dphi0) return fail(h, PFLBM_EINVAL, "null pointer");
     AdjInitArgs a;
     std::memset(&a, 0, sizeof(a));

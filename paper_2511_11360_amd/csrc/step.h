@@ -1142,10 +1142,16 @@ __global__ __launch_bounds__(TILE_THREADS[TS]) void k_step(const KArgs a) {
             // formed and every store adds its plane base to it in vector code.
             int so = o11;
             lane_opaque(so);
+            // Liang2014 keeps round-to-nearest: its 1024-thread kernel sits at
+            // 118 of its 128 registers, and the stochastic rounding pushes it
+            // over (spills, 16 % slower)
             SRBits rb((uint32_t)(((size_t)z * ny + y) * nx + x), a.step);
             auto gsink = [&](auto I, T v) {
                 constexpr int i = I;
-                __builtin_nontemporal_store(GC::template enc_sr<GL, i, GS, T>(v, rb.next()), &at<QG>(Gout, z, i, P, so));
+                if constexpr (MODEL == 4)
+                    __builtin_nontemporal_store(GC::template enc<GL, i, GS, T>(v), &at<QG>(Gout, z, i, P, so));
+                else
+                    __builtin_nontemporal_store(GC::template enc_sr<GL, i, GS, T>(v, rb.next()), &at<QG>(Gout, z, i, P, so));
             };
             auto hsink = [&](auto J, T v) {
                 constexpr int al = J;

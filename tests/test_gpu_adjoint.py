@@ -33,7 +33,8 @@ def _cases():
     x, y, z = wl.grid(d2)
     u2 = wl.zero_velocity(d2)
     u2[0] = -0.02 + 0.04 * (y + 0.5) / 22
-    return {"droplet2d": (d1, phi1, u1), "sheared3d": (d2, phi2, u2)}
+    d3 = dict(d2, lattice="D3Q27_D3Q7")
+    return {"droplet2d": (d1, phi1, u1), "sheared3d": (d2, phi2, u2), "sheared3d_q27": (d3, phi2, u2)}
 
 
 def _dev(a):
@@ -41,7 +42,7 @@ def _dev(a):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
 
 
-@pytest.mark.parametrize("case", ["droplet2d", "sheared3d"])
+@pytest.mark.parametrize("case", ["droplet2d", "sheared3d", "sheared3d_q27"])
 def test_adjoint_step_is_transpose_of_oracle_tangent(case):
     d, phi, u = _cases()[case]
     d = dict(d, rho_H=3.0, visc_interp="mu", nu_L=d["nu_H"] * 1.5)
@@ -57,6 +58,8 @@ DEGENERATE = [
     ("D3Q19_D3Q7", (1, 3, 2), ("periodic", "periodic", "periodic")),
     ("D3Q19_D3Q7", (4, 2, 3), ("periodic", "wall", "periodic")),
     ("D3Q19_D3Q7", (2, 5, 1), ("periodic", "wall", "periodic")),
+    ("D3Q27_D3Q7", (3, 2, 4), ("periodic", "periodic", "periodic")),
+    ("D3Q27_D3Q7", (4, 2, 3), ("periodic", "wall", "periodic")),
     ("D2Q9_D2Q5", (1, 6, 1), ("periodic", "wall", "periodic")),
     ("D2Q9_D2Q5", (3, 1, 1), ("periodic", "periodic", "periodic")),
 ]
@@ -122,7 +125,7 @@ def _grad_hip(d, phi, u, steps, target, k=None):
             float(W.grad.cpu()))
 
 
-@pytest.mark.parametrize("case,steps", [("droplet2d", 40), ("sheared3d", 24)])
+@pytest.mark.parametrize("case,steps", [("droplet2d", 40), ("sheared3d", 24), ("sheared3d_q27", 16)])
 def test_trajectory_gradient_vs_oracle_complex_step(case, steps):
     d, phi, u = _cases()[case]
     _say("case", case, "steps", steps)

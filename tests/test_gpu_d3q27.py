@@ -100,16 +100,3 @@ def test_d3q27_reduced_forms(precision):
     _say("  D3Q27 %s: rel L2 phi %.2e u %.2e, sum phi drift %.2e" % (precision, e_phi, e_u, drift))
     assert drift < 2e-6
     assert e_phi < 1e-4 and e_u < (1e-4 if precision == "fp32" else 2e-3)
-
-
-def test_d3q27_adjoint_unsupported():
-    import torch
-    from paper_2511_11360_amd import pflbm as P
-    from paper_2511_11360_amd.solver import Solver
-    d, phi, u = small_3d(lattice=LAT, nx=8, ny=8, nz=8, R=2.5)
-    s = Solver(d)
-    s.init(phi, u)
-    with pytest.raises(P.PflbmError) as e:
-        z = torch.zeros(8, dtype=torch.float64, device="cuda")
-        s.adjoint_step(z, z, z, z, z.clone(), z.clone(), z, z)
-    assert e.value.status == P.PFLBM_EUNSUPPORTED
