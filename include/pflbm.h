@@ -225,6 +225,15 @@ int pflbm_get_distributions(pflbm_t* h, double* g, double* hd);
    state. */
 int pflbm_set_distributions(pflbm_t* h, const double* g, const double* hd);
 
+/* The (phi u) of the previous step that the CH, Liang2018 and Liang2014
+   models keep for their backward-Euler d(phi u)/dt (Eq. liang2_G): copied
+   out to, or overwritten from, canonical float64 pu [3][z][y][x] (device
+   pointer; the third component of a 2-D box is zero). Set rounds to the
+   compute type (float32 for the reduced forms). PFLBM_EUNSUPPORTED for the
+   AC and nonlocal models. Asynchronous. */
+int pflbm_get_phiu(pflbm_t* h, double* pu);
+int pflbm_set_phiu(pflbm_t* h, const double* pu);
+
 /* Number of completed steps since pflbm_init. */
 int pflbm_step_count(const pflbm_t* h, long long* steps);
 
@@ -240,7 +249,7 @@ int pflbm_checkpoint_bytes(const pflbm_t* h, size_t* bytes);
 int pflbm_save_state(pflbm_t* h, void* dev_dst);
 int pflbm_load_state(pflbm_t* h, const void* dev_src);
 
-/* Discrete adjoint (AC model). The adjoint of one time step X^n -> X^{n+1}
+/* Discrete adjoint (AC and CH models). The adjoint of one time step X^n -> X^{n+1}
    (X = canonical float64 post-streaming distributions, as returned by
    pflbm_get_distributions) given lambda^{n+1} = dL/dX^{n+1}: writes
    lambda^n = dL/dX^n and ADDS dL/d(sigma, M, W) of this step into dparams
@@ -250,13 +259,28 @@ int pflbm_load_state(pflbm_t* h, const void* dev_src);
    pflbm_adjoint_workspace_bytes(). Uses the handle's parameters; float64
    arithmetic whatever the handle's precision. The method's reverse mode is
    not in the paper: it is the exact transpose of the discrete step of
-   Sec. II.C.1 as implemented here, on every lattice pair. Returns
-   PFLBM_EUNSUPPORTED for any other model (CH, nonlocal, Liang2018,
-   Liang2014) and for a frozen phase field. */
+   Sec. II.C.1 (AC) or Sec. II.D.1 (CH) as implemented here, on every lattice
+   pair. The CH state also holds (phi u) of the previous step, so the CH model
+   goes through pflbm_adjoint_step_pu; pflbm_adjoint_step returns
+   PFLBM_EUNSUPPORTED for it, and both return PFLBM_EUNSUPPORTED for the
+   other models (nonlocal, Liang2018, Liang2014) and for a frozen phase
+   field. */
 int pflbm_adjoint_workspace_bytes(const pflbm_t* h, size_t* bytes);
 int pflbm_adjoint_step(pflbm_t* h, const double* fwd_g, const double* fwd_h,
                        const double* lam_g, const double* lam_h,
                        double* lam_g_out, double* lam_h_out, double* dparams, void* work);
+
+/* The adjoint step with the (phi u) part of the state X = (g, h, pu) of the
+   CH model (Eqs. liang2_geq, liang2_G with the backward-Euler d(phi u)/dt):
+   fwd_pu holds (phi u) of the step before X^n (pflbm_get_phiu), lam_pu its
+   adjoint dL/dpu^{n+1}, lam_pu_out receives dL/dpu^n; all [3][z][y][x]
+   device float64, lam_pu_out not aliasing lam_pu. For the AC model the three
+   pu pointers are ignored (may be NULL) and the call equals
+   pflbm_adjoint_step. */
+int pflbm_adjoint_step_pu(pflbm_t* h, const double* fwd_g, const double* fwd_h, const double* fwd_pu,
+                          const double* lam_g, const double* lam_h, const double* lam_pu,
+                          double* lam_g_out, double* lam_h_out, double* lam_pu_out,
+                          double* dparams, void* work);
 
 /* The same adjoint step for callers that cannot allocate device memory
    (code under HIP graph capture, tight serving loops, harnesses that forbid
@@ -277,14 +301,28 @@ int pflbm_adjoint_step_noalloc(pflbm_t* h, const double* fwd_g, const double* fw
    dL/dphi [z][y][x] (device float64), writes lambda = dL/dX for that state,
    lam_g [Qg][z][y][x] = 0 and lam_h [Qh][z][y][x] = dL/dphi for every
    population, the transpose of phi = sum_a h_a (Eq. fakhari_phi_update).
-   AC model (PFLBM_EUNSUPPORTED otherwise). Asynchronous. */
+   AC and CH models (PFLBM_EUNSUPPORTED otherwise); for CH the loss does not
+   depend on pu, so lam_pu of that state is zero (the caller's buffer).
+   Asynchronous. */
 int pflbm_adjoint_seed_phi(pflbm_t* h, const double* dphi, double* lam_g, double* lam_h);
 
 /* dL/dphi0 of the equilibrium initialisation (pflbm_init) given
    lambda^0 = dL/dX^0: dphi0 [z][y][x] (device float64, overwritten). u0 and
-   p0 as passed to pflbm_init (NULL = zero). */
+   p0 as passed to pflbm_init (NULL = zero). AC model (the CH model goes
+   through pflbm_adjoint_init_pu). */
 int pflbm_adjoint_init(pflbm_t* h, const double* phi0, const double* u0, const double* p0,
                        const double* lam_g, const double* lam_h, double* dphi0);
+
+/* The same with the (phi u) part: lam_pu = dL/dpu^0 [3][z][y][x]. The CH
+   initialisation h = h_eq(phi0, mu_phi(phi0), u0) (Eq. liang2_geq, mu_phi of
+   Eq. chemical_potential, on the step's Laplacian stencil), pu^0 = phi0 u0,
+   depends on sigma and W through mu_phi: their terms are ADDED into dparams
+   (device float64[3], may be NULL). work: workspace of
+   pflbm_adjoint_workspace_bytes(). For the AC model lam_pu, dparams and work
+   are ignored and the call equals pflbm_adjoint_init. */
+int pflbm_adjoint_init_pu(pflbm_t* h, const double* phi0, const double* u0, const double* p0,
+                          const double* lam_g, const double* lam_h, const double* lam_pu,
+                          double* dphi0, double* dparams, void* work);
 
 /* Measurement only (no part of the method): memory-pattern probes of the
    mixed-precision D3Q19 + D3Q7 step's HBM streams, 19 fp16 g and 6 fp32 h

@@ -47,16 +47,38 @@ def fd_param(p, name, phi0, u0, steps, target, rel=1e-5):
     return float((lp - lm) / (2 * dh))
 
 
-def step_jvp(p, st, vg, vh, h=1e-30):
-    """Tangent of one step at state st along (vg, vh): (J v)_g, (J v)_h."""
-    sc = om.State(st.g + 1j * h * vg, st.h + 1j * h * vh)
-    out = om.step(p, sc)
-    return np.imag(out.g) / h, np.imag(out.h) / h
+def step_jvp(p, st, vg, vh, vpu=None, h=1e-30):
+    """Tangent of one step at state st along (vg, vh): (J v)_g, (J v)_h. A state
+    that carries (phi u) of the previous step (the CH model) is perturbed along
+    vpu too (zero if None) and its tangent (J v)_pu is returned third."""
+    pu = None
+    if st.phiu_prev is not None:
+        pu = st.phiu_prev + (1j * h * vpu if vpu is not None else 0j)
+    out = om.step(p, om.State(st.g + 1j * h * vg, st.h + 1j * h * vh, pu))
+    if pu is None:
+        return np.imag(out.g) / h, np.imag(out.h) / h
+    return np.imag(out.g) / h, np.imag(out.h) / h, np.imag(out.phiu_prev) / h
 
 
 def step_param_tangent(p, st, name, h=1e-30):
-    """d(step output)/d(name) at state st."""
+    """d(step output)/d(name) at state st (with the (phi u) part third when the
+    state carries it)."""
     pc = _with(p, **{name: complex(getattr(p, name), h)})
-    sc = om.State(st.g.astype(complex), st.h.astype(complex))
-    out = om.step(pc, sc)
-    return np.imag(out.g) / h, np.imag(out.h) / h
+    pu = None if st.phiu_prev is None else st.phiu_prev.astype(complex)
+    out = om.step(pc, om.State(st.g.astype(complex), st.h.astype(complex), pu))
+    if pu is None:
+        return np.imag(out.g) / h, np.imag(out.h) / h
+    return np.imag(out.g) / h, np.imag(out.h) / h, np.imag(out.phiu_prev) / h
+
+
+def init_jvp(p, phi0, v, u0=None, p0=None, name=None, h=1e-30):
+    """Tangent of the initial state (g, h[, phi u]) along v in phi0, or, with
+    name given, with respect to that parameter (v unused)."""
+    if name is None:
+        st = om.init(p, phi0 + 1j * h * v, u0, p0)
+    else:
+        st = om.init(_with(p, **{name: complex(getattr(p, name), h)}), phi0.astype(complex), u0, p0)
+    out = [np.imag(st.g) / h, np.imag(st.h) / h]
+    if st.phiu_prev is not None:
+        out.append(np.imag(st.phiu_prev) / h)
+    return tuple(out)

@@ -21,8 +21,8 @@ class PhaseFieldRun(torch.autograd.Function):
     def forward(ctx, phi0, sigma, M, W, params, u0, nsteps, precision, k):
         d = dict(params)
         d["sigma"], d["M"], d["W"] = float(sigma), float(M), float(W)
-        if d.get("model", "AC") != "AC":
-            raise ValueError("the adjoint is implemented for the AC model only")
+        if d.get("model", "AC") not in ("AC", "CH"):
+            raise ValueError("the adjoint is implemented for the AC and CH models only")
         s = Solver(d, precision=precision, device=phi0.device)
         s.init(phi0, u0)
         nsteps = int(nsteps)
@@ -50,9 +50,14 @@ class PhaseFieldRun(torch.autograd.Function):
         (phi0,) = ctx.saved_tensors
         dev = s.device
         shape = s.shape
+        # the CH state also holds (phi u) of the previous step; L depends on
+        # phi alone, so its adjoint starts at zero
+        ch = s.d.get("model", "AC") == "CH"
         lam_g, lam_h = s.adjoint_seed_phi(grad_phi.to(device=dev, dtype=torch.float64).reshape(shape))
         out_g = torch.empty_like(lam_g)
         out_h = torch.empty_like(lam_h)
+        lam_pu = torch.zeros((3,) + shape, dtype=torch.float64, device=dev) if ch else None
+        out_pu = torch.empty_like(lam_pu) if ch else None
         dparams = torch.zeros(3, dtype=torch.float64, device=dev)
         work = s.adjoint_workspace()
         for start, buf in reversed(ctx.cks):
@@ -60,14 +65,22 @@ class PhaseFieldRun(torch.autograd.Function):
             s.load_state(buf)
             states = []
             for _ in range(n):
-                states.append(s.get_distributions())
+                g, h = s.get_distributions()
+                states.append((g, h, s.get_phiu() if ch else None))
                 s.step(1)
-            for g, h in reversed(states):
-                s.adjoint_step(g, h, lam_g, lam_h, out_g, out_h, dparams, work)
+            for g, h, pu in reversed(states):
+                if ch:
+                    s.adjoint_step_pu(g, h, pu, lam_g, lam_h, lam_pu, out_g, out_h, out_pu, dparams, work)
+                    lam_pu, out_pu = out_pu, lam_pu
+                else:
+                    s.adjoint_step(g, h, lam_g, lam_h, out_g, out_h, dparams, work)
                 lam_g, out_g = out_g, lam_g
                 lam_h, out_h = out_h, lam_h
             del states
-        dphi0 = s.adjoint_init(phi0, ctx.u0, None, lam_g, lam_h)
+        if ch:
+            dphi0 = s.adjoint_init_pu(phi0, ctx.u0, None, lam_g, lam_h, lam_pu, dparams, work)
+        else:
+            dphi0 = s.adjoint_init(phi0, ctx.u0, None, lam_g, lam_h)
         return (dphi0.to(phi0.dtype).reshape(phi0.shape), dparams[0], dparams[1], dparams[2],
                 None, None, None, None, None)
 

@@ -154,8 +154,11 @@ __global__ __launch_bounds__(256) void k_adj_phi(const AdjArgs a) {
     a.phi[n] = s;
 }
 
-// pass 2: local reverse sweep of the collision
-template <class PAIR>
+// pass 2: local reverse sweep of the collision. MODEL 0: conservative AC
+// (Eqs. fakhari_geq, fakhari_G_modified); MODEL 1: the Cahn-Hilliard phase
+// field (Eqs. liang2_geq, liang2_G with the backward-Euler d(phi u)/dt, whose
+// (phi u) of the previous step is part of the state)
+template <class PAIR, int MODEL>
 __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
     using GL = typename PAIR::G;
     using HL = typename PAIR::H;
@@ -257,6 +260,14 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
         const double pp = phi * (1.0 - phi);
         const double coef = ph.anti * pp * rn;
         const double itp = ph.inv_tau_phi, gfp = ph.g_fac_phi;
+        // CH: (phi u) of this step and of the previous one (state)
+        double puc[3] = {0.0, 0.0, 0.0}, pup[3] = {0.0, 0.0, 0.0};
+        if constexpr (MODEL == 1) {
+            for (int k = 0; k < 3; ++k) {
+                puc[k] = phi * u[k];
+                pup[k] = a.fpu[(size_t)k * nn + n];
+            }
+        }
 
         // ---------------- reverse sweep
         // lambda* : adjoint of the post-collision populations (stream transpose),
@@ -283,7 +294,51 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
         double b_ps = 0.0, b_irho = 0.0, b_itau = 0.0, b_usq = 0.0, b_aeq = 0.0;
         double b_coef = 0.0, b_anti = 0.0, b_itp = 0.0, b_gfp = 0.0;
         double b_Pi[3][3] = {{0.0}};
+        double b_muh = 0.0;   // CH: mu_phi through h_eq
 
+        if constexpr (MODEL == 1) {
+            // h*_a = (1 - itp) h_a + itp heq_a + gfp G_a with
+            // heq_0 = phi + (w_0 - 1) eta mu, heq_a = w_a eta mu + 3 w_a e_a . (phi u),
+            // G_a = 3 w_a e_a . ((phi u) - (phi u)_prev); (phi u) is also stored
+            // for the next step, whose adjoint lambda_pu^{n+1} arrives at the node
+            double b_puc[3], b_pup[3] = {0.0, 0.0, 0.0};
+            for (int k = 0; k < 3; ++k) b_puc[k] = a.lpu[(size_t)k * nn + n];
+            unroll<QH>([&](auto J) {
+                constexpr int al = J;
+                constexpr double w = HL::w(al);
+                constexpr int ex = HL::c(al, 0), ey = HL::c(al, 1), ez = HL::c(al, 2);
+                const double lb = lh[al];
+                const double bheq = itp * lb;
+                double heq, G = 0.0;
+                if constexpr (al == 0) {
+                    heq = phi + (w - 1.0) * ph.eta * mu;
+                    b_phi += bheq;
+                    b_muh += (w - 1.0) * ph.eta * bheq;
+                } else {
+                    const double ep = ex * puc[0] + ey * puc[1] + ez * puc[2];
+                    const double eq = ex * pup[0] + ey * pup[1] + ez * pup[2];
+                    heq = w * ph.eta * mu + 3.0 * w * ep;
+                    G = 3.0 * w * (ep - eq);
+                    b_muh += w * ph.eta * bheq;
+                    const double t = 3.0 * w * (bheq + gfp * lb);
+                    const double tp = 3.0 * w * gfp * lb;
+                    b_puc[0] += ex * t;
+                    b_puc[1] += ey * t;
+                    b_puc[2] += ez * t;
+                    b_pup[0] -= ex * tp;
+                    b_pup[1] -= ey * tp;
+                    b_pup[2] -= ez * tp;
+                }
+                b_itp += (heq - h[al]) * lb;
+                b_gfp += G * lb;
+            });
+            // (phi u) = phi u
+            for (int k = 0; k < 3; ++k) {
+                b_phi += u[k] * b_puc[k];
+                b_u[k] += phi * b_puc[k];
+                a.opu[(size_t)k * nn + n] = b_pup[k];
+            }
+        } else {
         // h*_a = (1 - itp) h_a + itp heq_a + gfp w_a coef (e_a . gr)
         for (int al = 0; al < QH; ++al) {
             const double w = HL::w(al);
@@ -309,6 +364,7 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
             const double b_rn = b_coef * ph.anti * pp;
             const double b_gg = -0.5 * rn * rn * rn * b_rn;
             for (int k = 0; k < 3; ++k) b_gr[k] += 2.0 * gr[k] * b_gg;
+        }
         }
         // g*_i = (1 - so) g_i + so geq_i - dS P_i + ffac w_i (c_i . F)
         double b_A[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -411,7 +467,7 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
             b_rho += ph.body[k] * b_F0[k];
         }
         // sg = mu - ps dR / 3
-        const double b_mu = b_sg;
+        const double b_mu = b_sg + b_muh;
         b_ps += -b_sg * dR / 3.0;
         // moments
         for (int i = 0; i < Q; ++i) {
@@ -445,7 +501,7 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
         const double sigma = a.sigma, W = a.W;
         th[0] = b_beta4 * 48.0 / W + b_kappa * 1.5 * W;
         const double b_itp_tot = b_itp - 0.5 * b_gfp;
-        th[1] = -3.0 * itp * itp * b_itp_tot;
+        th[1] = -(MODEL == 1 ? 3.0 / ph.eta : 3.0) * itp * itp * b_itp_tot;   // tau_phi = 3 M (/ eta) + 1/2
         th[2] = -b_beta4 * 48.0 * sigma / (W * W) + b_kappa * 1.5 * sigma - b_anti * 4.0 / (W * W);
 
         for (int i = 0; i < Q; ++i) a.og[(size_t)i * nn + n] = b_g[i];
@@ -475,7 +531,9 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
 // population of y receives that plus dL/dphi(y), and its direct term
 // (1 - 1/tau_phi) lambda*_h (the h stream transpose of lambda_h^{n+1},
 // gathered here rather than written by the sweep and read back).
-template <class PAIR>
+// INIT: the transpose of the Laplacian alone, for the adjoint of the CH
+// initialisation (mu_phi(phi0) in h_eq): dL/dphi0 = work[0] + lap^T(work[4])
+template <class PAIR, bool INIT>
 __global__ __launch_bounds__(256) void k_adj_stencil(const AdjArgs a) {
     using GL = typename PAIR::G;
     using HL = typename PAIR::H;
@@ -497,9 +555,9 @@ __global__ __launch_bounds__(256) void k_adj_stencil(const AdjArgs a) {
         // the terms of x's stencil that reach y (zero components skipped)
         auto contrib = [&](long long x) {
             double t = w6 * blap[x];
-            if constexpr (c0 != 0) t += (w3 * c0) * bgr[x];
-            if constexpr (c1 != 0) t += (w3 * c1) * bgr[nn + x];
-            if constexpr (c2 != 0) t += (w3 * c2) * bgr[2 * nn + x];
+            if constexpr (!INIT && c0 != 0) t += (w3 * c0) * bgr[x];
+            if constexpr (!INIT && c1 != 0) t += (w3 * c1) * bgr[nn + x];
+            if constexpr (!INIT && c2 != 0) t += (w3 * c2) * bgr[2 * nn + x];
             acc += t;
         };
         // x = y - c_i (no wall crossed)
@@ -517,6 +575,10 @@ __global__ __launch_bounds__(256) void k_adj_stencil(const AdjArgs a) {
             }
         });
     });
+    if constexpr (INIT) {
+        a.dphi0[n] = acc;
+        return;
+    }
     const double itp1 = 1.0 - a.ph.inv_tau_phi;
     unroll<HL::Q>([&](auto J) {
         constexpr int al = J;
@@ -576,6 +638,74 @@ __global__ __launch_bounds__(256) void k_adj_init(const AdjInitArgs a) {
     a.dphi0[n] = s;
 }
 
+// adjoint of the CH initialisation h = h_eq(phi0, mu_phi(phi0), u0) (Eq.
+// liang2_geq with mu_phi of Eq. chemical_potential), g = g_eq(3 p0 / rho(phi0),
+// u0), (phi u) = phi0 u0: the local part of dL/dphi0 into work[0],
+// dL/d(lap phi0) into work[4] (the stencil pass in init mode adds its
+// transpose), and the sigma and W terms of mu_phi into the block partials
+template <class PAIR>
+__global__ __launch_bounds__(256) void k_adj_init_ch(const AdjArgs a, const double* phi0, const double* u0,
+                                                     const double* p0) {
+    using GL = typename PAIR::G;
+    using HL = typename PAIR::H;
+    const long long nn = (long long)a.nx * a.ny * a.nz;
+    const int wg = xcd_block();
+    const long long n = (long long)wg * blockDim.x + threadIdx.x;
+    double th[3] = {0.0, 0.0, 0.0};
+    if (n < nn) {
+        const Phys& ph = a.ph;
+        const Nbr nb(a, node_of(n, a));
+        const double phi = phi0[n];
+        double lap = 0.0;
+        unroll<GL::Q - 1>([&](auto I) {
+            constexpr int i = I + 1;
+            lap += 6.0 * GL::w(i) * (phi0[nb.index(GL::c(i, 0), GL::c(i, 1), GL::c(i, 2))] - phi);
+        });
+        double u[3] = {0.0, 0.0, 0.0};
+        if (u0) {
+            u[0] = u0[n];
+            u[1] = u0[nn + n];
+            if (PAIR::dim == 3) u[2] = u0[2 * nn + n];
+        }
+        const double cub = phi * (phi - 1.0) * (phi - 0.5);
+        // heq_0 = phi + (w_0 - 1) eta mu, heq_a = w_a eta mu + 3 w_a e_a . (phi u)
+        double s = a.lh[n], cmu = -a.lh[n];
+        unroll<HL::Q>([&](auto J) {
+            constexpr int al = J;
+            const double lb = a.lh[(size_t)al * nn + n];
+            cmu += HL::w(al) * lb;
+            if constexpr (al > 0) {
+                constexpr int ex = HL::c(al, 0), ey = HL::c(al, 1), ez = HL::c(al, 2);
+                s += 3.0 * HL::w(al) * (ex * u[0] + ey * u[1] + ez * u[2]) * lb;
+            }
+        });
+        cmu *= ph.eta;   // dL/dmu_phi
+        for (int k = 0; k < 3; ++k) s += a.lpu[(size_t)k * nn + n] * u[k];
+        s += cmu * ph.beta4 * (3.0 * phi * phi - 3.0 * phi + 0.5);
+        if (p0) {
+            const double rho = ph.rhoL + phi * ph.dRho;
+            const double dps = -3.0 * p0[n] * ph.dRho / (rho * rho);
+            for (int i = 0; i < GL::Q; ++i) s += a.lg[(size_t)i * nn + n] * GL::w(i) * dps;
+        }
+        a.work[n] = s;
+        a.work[4 * nn + n] = -ph.kappa * cmu;
+        // beta4 = 48 sigma / W, kappa = 1.5 sigma W
+        const double sigma = a.sigma, W = a.W;
+        th[0] = cmu * (cub * 48.0 / W - lap * 1.5 * W);
+        th[2] = -cmu * (cub * 48.0 * sigma / (W * W) + lap * 1.5 * sigma);
+    }
+    __shared__ double red[3][256];
+    for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = th[k];
+    __syncthreads();
+    for (int s = 128; s >= 1; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 3; ++k) a.partials[(size_t)wg * 3 + k] = red[k][0];
+}
+
 // seed of the adjoint from dL/dphi of a state: phi = sum_a h_a (Eq.
 // fakhari_phi_update) gives dL/dh_a = dL/dphi for every a, and dL/dg = 0
 __global__ __launch_bounds__(256) void k_adj_seed(const double* dphi, double* lg, double* lh, long long nn,
@@ -594,20 +724,19 @@ hipError_t launch_adjoint_seed(const double* dphi, double* lg, double* lh, long 
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint(int lattice, const AdjArgs& a, double* dparams, hipStream_t st) {
+hipError_t launch_adjoint(int lattice, int model, const AdjArgs& a, double* dparams, hipStream_t st) {
     const long long nn = (long long)a.nx * a.ny * a.nz;
     const dim3 grid((unsigned)((nn + 255) / 256)), block(256);
     hipLaunchKernelGGL(k_adj_phi, grid, block, 0, st, a);
-    if (lattice == 0) {
-        hipLaunchKernelGGL(k_adj_local<Pair2D>, grid, block, 0, st, a);
-        hipLaunchKernelGGL(k_adj_stencil<Pair2D>, grid, block, 0, st, a);
-    } else if (lattice == 1) {
-        hipLaunchKernelGGL(k_adj_local<Pair3D>, grid, block, 0, st, a);
-        hipLaunchKernelGGL(k_adj_stencil<Pair3D>, grid, block, 0, st, a);
-    } else {
-        hipLaunchKernelGGL(k_adj_local<Pair3D27>, grid, block, 0, st, a);
-        hipLaunchKernelGGL(k_adj_stencil<Pair3D27>, grid, block, 0, st, a);
-    }
+    auto go = [&](auto pair) {
+        using P_ = decltype(pair);
+        if (model == 1) hipLaunchKernelGGL((k_adj_local<P_, 1>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_adj_local<P_, 0>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((k_adj_stencil<P_, false>), grid, block, 0, st, a);
+    };
+    if (lattice == 0) go(Pair2D{});
+    else if (lattice == 1) go(Pair3D{});
+    else go(Pair3D27{});
     if (dparams) hipLaunchKernelGGL(k_adj_params, dim3(1), dim3(PARAMS_THREADS), 0, st, a.partials, (int)grid.x, dparams);
     return hipGetLastError();
 }
@@ -618,6 +747,22 @@ hipError_t launch_adjoint_init(int lattice, const AdjInitArgs& a, hipStream_t st
     if (lattice == 0) hipLaunchKernelGGL(k_adj_init<Pair2D>, grid, block, 0, st, a);
     else if (lattice == 1) hipLaunchKernelGGL(k_adj_init<Pair3D>, grid, block, 0, st, a);
     else hipLaunchKernelGGL(k_adj_init<Pair3D27>, grid, block, 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_init_ch(int lattice, const AdjArgs& a, const double* phi0, const double* u0,
+                                  const double* p0, double* dparams, hipStream_t st) {
+    const long long nn = (long long)a.nx * a.ny * a.nz;
+    const dim3 grid((unsigned)((nn + 255) / 256)), block(256);
+    auto go = [&](auto pair) {
+        using P_ = decltype(pair);
+        hipLaunchKernelGGL((k_adj_init_ch<P_>), grid, block, 0, st, a, phi0, u0, p0);
+        hipLaunchKernelGGL((k_adj_stencil<P_, true>), grid, block, 0, st, a);
+    };
+    if (lattice == 0) go(Pair2D{});
+    else if (lattice == 1) go(Pair3D{});
+    else go(Pair3D27{});
+    if (dparams) hipLaunchKernelGGL(k_adj_params, dim3(1), dim3(PARAMS_THREADS), 0, st, a.partials, (int)grid.x, dparams);
     return hipGetLastError();
 }
 

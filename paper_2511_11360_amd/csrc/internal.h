@@ -151,6 +151,10 @@ struct AdjArgs {
     const double* lh;
     double* og;            // lambda^n (must not alias lg / lh)
     double* oh;
+    const double* fpu;     // CH: (phi u) of the step before X^n [3][nodes]
+    const double* lpu;     // CH: its adjoint lambda_pu^{n+1}
+    double* opu;           // CH: lambda_pu^n
+    double* dphi0;         // adjoint of the initialisation: dL/dphi0 (stencil pass, init mode)
     double* phi;           // workspace [nodes]
     double* work;          // workspace [5][nodes]
     double* partials;      // workspace [blocks][3]
@@ -176,8 +180,12 @@ struct AdjInitArgs {
 hipError_t adjoint_scratch(int device, void** out);
 hipError_t launch_adjoint_seed(const double* dphi, double* lg, double* lh, long long nn, int qg, int qh,
                                hipStream_t st);
-hipError_t launch_adjoint(int lattice, const AdjArgs& a, double* dparams, hipStream_t s);
+hipError_t launch_adjoint(int lattice, int model, const AdjArgs& a, double* dparams, hipStream_t s);
 hipError_t launch_adjoint_init(int lattice, const AdjInitArgs& a, hipStream_t s);
+hipError_t launch_adjoint_init_ch(int lattice, const AdjArgs& a, const double* phi0, const double* u0,
+                                  const double* p0, double* dparams, hipStream_t s);
+hipError_t launch_phiu_io(int precision, bool get, void* pu, double* canon, int P, int nx, int ny, int nz,
+                          hipStream_t s);
 hipError_t launch_step(int lattice, int model, int precision, int mode, const KArgs& a, hipStream_t s);
 // per lattice pair (p) and model (m) instantiations (step_inst.hip)
 hipError_t launch_step_p0_m0(int precision, int mode, const KArgs& a, hipStream_t s);

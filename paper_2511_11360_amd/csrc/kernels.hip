@@ -237,6 +237,22 @@ __global__ __launch_bounds__(256) void k_set(const IOArgs a) {
     });
 }
 
+// (phi u) of the previous step, native [z][3][P] of the compute type, to or
+// from canonical float64 [3][z][y][x]
+template <class T, bool GET>
+__global__ __launch_bounds__(256) void k_phiu_io(T* pu, double* c, int P, int nx, int ny, int nz) {
+    const long long nn = (long long)nx * ny * nz;
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    const int pl = nx * ny;
+    const int z = (int)(n / pl), ip = (int)(n - (long long)z * pl);
+    for (int k = 0; k < 3; ++k) {
+        const size_t e = ((size_t)z * 3 + k) * (size_t)P + ip;
+        if constexpr (GET) c[(size_t)k * nn + n] = (double)pu[e];
+        else pu[e] = (T)c[(size_t)k * nn + n];
+    }
+}
+
 // ----------------------------------------------------------------------------
 // nonlocal multiplier: gamma = sum (4 beta/kappa)(phi* - 1) phi* (phi* - 1/2)
 // / sum (1 - phi*) phi* over all nodes (Eq. lagrange_multiplier), phi* the
@@ -372,6 +388,20 @@ hipError_t launch_get(int lattice, int model, int precision, const IOArgs& a, hi
 hipError_t launch_set(int lattice, int model, int precision, const IOArgs& a, hipStream_t s) {
     const long long nn = (long long)a.nx * a.ny * a.nz;
     PFLBM_NODE_DISPATCH(k_set, a, nn);
+    return hipGetLastError();
+}
+
+hipError_t launch_phiu_io(int precision, bool get, void* pu, double* canon, int P, int nx, int ny, int nz,
+                          hipStream_t s) {
+    const long long nn = (long long)nx * ny * nz;
+    const dim3 grid((unsigned)((nn + 255) / 256)), block(256);
+    if (precision == 0) {
+        if (get) hipLaunchKernelGGL((k_phiu_io<double, true>), grid, block, 0, s, (double*)pu, canon, P, nx, ny, nz);
+        else hipLaunchKernelGGL((k_phiu_io<double, false>), grid, block, 0, s, (double*)pu, canon, P, nx, ny, nz);
+    } else {
+        if (get) hipLaunchKernelGGL((k_phiu_io<float, true>), grid, block, 0, s, (float*)pu, canon, P, nx, ny, nz);
+        else hipLaunchKernelGGL((k_phiu_io<float, false>), grid, block, 0, s, (float*)pu, canon, P, nx, ny, nz);
+    }
     return hipGetLastError();
 }
 

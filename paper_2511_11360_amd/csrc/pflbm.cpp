@@ -650,29 +650,50 @@ int pflbm_adjoint_workspace_bytes(const pflbm_t* h, size_t* bytes) {
     return PFLBM_OK;
 }
 
-static int adjoint_check(pflbm_t* h) {
+// with_pu: the entry point carries the (phi u) state of the CH model
+static int adjoint_check(pflbm_t* h, bool with_pu) {
     int st = guard(h);
     if (st) return st;
-    if (h->p.model != PFLBM_AC) return fail(h, PFLBM_EUNSUPPORTED, "adjoint implemented for the AC model only");
+    if (h->p.model != PFLBM_AC && h->p.model != PFLBM_CH)
+        return fail(h, PFLBM_EUNSUPPORTED, "adjoint implemented for the AC and CH models only");
+    if (h->p.model == PFLBM_CH && !with_pu)
+        return fail(h, PFLBM_EUNSUPPORTED, "the CH adjoint carries (phi u): use the _pu entry points");
     if (h->p.freeze_phi) return fail(h, PFLBM_EUNSUPPORTED, "adjoint of a frozen phase field is not implemented");
     return PFLBM_OK;
 }
 
-static int adjoint_run(pflbm_t* h, const double* fwd_g, const double* fwd_h, const double* lam_g,
-                       const double* lam_h, double* lam_g_out, double* lam_h_out, double* dparams,
-                       void* work);
+static int adjoint_run(pflbm_t* h, const double* fwd_g, const double* fwd_h, const double* fwd_pu,
+                       const double* lam_g, const double* lam_h, const double* lam_pu, double* lam_g_out,
+                       double* lam_h_out, double* lam_pu_out, double* dparams, void* work);
 
 int pflbm_adjoint_step(pflbm_t* h, const double* fwd_g, const double* fwd_h, const double* lam_g,
                        const double* lam_h, double* lam_g_out, double* lam_h_out, double* dparams,
                        void* work) {
-    if (int st = adjoint_check(h)) return st;
+    if (int st = adjoint_check(h, false)) return st;
     if (!work) return fail(h, PFLBM_EINVAL, "null pointer");
-    return adjoint_run(h, fwd_g, fwd_h, lam_g, lam_h, lam_g_out, lam_h_out, dparams, work);
+    return adjoint_run(h, fwd_g, fwd_h, nullptr, lam_g, lam_h, nullptr, lam_g_out, lam_h_out, nullptr, dparams,
+                       work);
+}
+
+int pflbm_adjoint_step_pu(pflbm_t* h, const double* fwd_g, const double* fwd_h, const double* fwd_pu,
+                          const double* lam_g, const double* lam_h, const double* lam_pu, double* lam_g_out,
+                          double* lam_h_out, double* lam_pu_out, double* dparams, void* work) {
+    if (int st = adjoint_check(h, true)) return st;
+    if (!work) return fail(h, PFLBM_EINVAL, "null pointer");
+    if (h->p.model != PFLBM_CH) {
+        fwd_pu = lam_pu = nullptr;
+        lam_pu_out = nullptr;
+    } else {
+        if (!fwd_pu || !lam_pu || !lam_pu_out) return fail(h, PFLBM_EINVAL, "null pointer");
+        if (lam_pu_out == lam_pu) return fail(h, PFLBM_EINVAL, "lambda in and out must not alias");
+    }
+    return adjoint_run(h, fwd_g, fwd_h, fwd_pu, lam_g, lam_h, lam_pu, lam_g_out, lam_h_out, lam_pu_out, dparams,
+                       work);
 }
 
 int pflbm_adjoint_step_noalloc(pflbm_t* h, const double* fwd_g, const double* fwd_h, const double* lam_g,
                                const double* lam_h, double* lam_g_out, double* lam_h_out, double* dparams) {
-    if (int st = adjoint_check(h)) return st;
+    if (int st = adjoint_check(h, false)) return st;
     size_t need = 0;
     pflbm_adjoint_workspace_bytes(h, &need);
     if (need > (size_t)PFLBM_ADJOINT_SCRATCH_BYTES) {
@@ -683,24 +704,14 @@ int pflbm_adjoint_step_noalloc(pflbm_t* h, const double* fwd_g, const double* fw
     }
     void* ptr = nullptr;
     HIPCHK(h, adjoint_scratch(h->device, &ptr), "adjoint scratch address");
-    return adjoint_run(h, fwd_g, fwd_h, lam_g, lam_h, lam_g_out, lam_h_out, dparams, ptr);
+    return adjoint_run(h, fwd_g, fwd_h, nullptr, lam_g, lam_h, nullptr, lam_g_out, lam_h_out, nullptr, dparams,
+                       ptr);
 }
 
-static int adjoint_run(pflbm_t* h, const double* fwd_g, const double* fwd_h, const double* lam_g,
-                       const double* lam_h, double* lam_g_out, double* lam_h_out, double* dparams,
-                       void* work) {
-    if (!fwd_g || !fwd_h || !lam_g || !lam_h || !lam_g_out || !lam_h_out)
-        return fail(h, PFLBM_EINVAL, "null pointer");
-    if (lam_g_out == lam_g || lam_h_out == lam_h) return fail(h, PFLBM_EINVAL, "lambda in and out must not alias");
+// the workspace: phi [nodes], five adjoint values [5][nodes], block partials
+static void adjoint_args(pflbm_t* h, void* work, AdjArgs& a) {
     const size_t nn = adj_nodes(h);
-    AdjArgs a;
     std::memset(&a, 0, sizeof(a));
-    a.fg = fwd_g;
-    a.fh = fwd_h;
-    a.lg = lam_g;
-    a.lh = lam_h;
-    a.og = lam_g_out;
-    a.oh = lam_h_out;
     char* w = (char*)work;
     a.phi = (double*)w;
     a.work = (double*)(w + align_up(nn * 8, 256));
@@ -713,14 +724,31 @@ static int adjoint_run(pflbm_t* h, const double* fwd_g, const double* fwd_h, con
     a.sigma = h->p.sigma;
     a.W = h->p.W;
     a.ph = h->ph;
-    HIPCHK(h, launch_adjoint(h->p.lattice, a, dparams, h->stream), "adjoint kernels");
+}
+
+static int adjoint_run(pflbm_t* h, const double* fwd_g, const double* fwd_h, const double* fwd_pu,
+                       const double* lam_g, const double* lam_h, const double* lam_pu, double* lam_g_out,
+                       double* lam_h_out, double* lam_pu_out, double* dparams, void* work) {
+    if (!fwd_g || !fwd_h || !lam_g || !lam_h || !lam_g_out || !lam_h_out)
+        return fail(h, PFLBM_EINVAL, "null pointer");
+    if (lam_g_out == lam_g || lam_h_out == lam_h) return fail(h, PFLBM_EINVAL, "lambda in and out must not alias");
+    AdjArgs a;
+    adjoint_args(h, work, a);
+    a.fg = fwd_g;
+    a.fh = fwd_h;
+    a.lg = lam_g;
+    a.lh = lam_h;
+    a.og = lam_g_out;
+    a.oh = lam_h_out;
+    a.fpu = fwd_pu;
+    a.lpu = lam_pu;
+    a.opu = lam_pu_out;
+    HIPCHK(h, launch_adjoint(h->p.lattice, h->p.model, a, dparams, h->stream), "adjoint kernels");
     return PFLBM_OK;
 }
 
 int pflbm_adjoint_seed_phi(pflbm_t* h, const double* dphi, double* lam_g, double* lam_h) {
-    int st = guard(h);
-    if (st) return st;
-    if (h->p.model != PFLBM_AC) return fail(h, PFLBM_EUNSUPPORTED, "adjoint implemented for the AC model only");
+    if (int st = adjoint_check(h, true)) return st;
     if (!dphi || !lam_g || !lam_h) return fail(h, PFLBM_EINVAL, "null pointer");
     HIPCHK(h, launch_adjoint_seed(dphi, lam_g, lam_h, (long long)adj_nodes(h), h->L.Qg, h->L.Qh, h->stream),
            "adjoint seed kernel");
@@ -729,9 +757,7 @@ int pflbm_adjoint_seed_phi(pflbm_t* h, const double* dphi, double* lam_g, double
 
 int pflbm_adjoint_init(pflbm_t* h, const double* phi0, const double* u0, const double* p0,
                        const double* lam_g, const double* lam_h, double* dphi0) {
-    int st = guard(h);
-    if (st) return st;
-    if (h->p.model != PFLBM_AC) return fail(h, PFLBM_EUNSUPPORTED, "adjoint implemented for the AC model only");
+    if (int st = adjoint_check(h, false)) return st;
     if (!phi0 || !lam_g || !lam_h || !dphi0) return fail(h, PFLBM_EINVAL, "null pointer");
     AdjInitArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -746,6 +772,45 @@ int pflbm_adjoint_init(pflbm_t* h, const double* phi0, const double* u0, const d
     a.nz = h->p.nz;
     a.ph = h->ph;
     HIPCHK(h, launch_adjoint_init(h->p.lattice, a, h->stream), "adjoint init kernel");
+    return PFLBM_OK;
+}
+
+int pflbm_adjoint_init_pu(pflbm_t* h, const double* phi0, const double* u0, const double* p0,
+                          const double* lam_g, const double* lam_h, const double* lam_pu, double* dphi0,
+                          double* dparams, void* work) {
+    if (int st = adjoint_check(h, true)) return st;
+    if (h->p.model != PFLBM_CH) return pflbm_adjoint_init(h, phi0, u0, p0, lam_g, lam_h, dphi0);
+    if (!phi0 || !lam_g || !lam_h || !lam_pu || !dphi0 || !work) return fail(h, PFLBM_EINVAL, "null pointer");
+    AdjArgs a;
+    adjoint_args(h, work, a);
+    a.lg = lam_g;
+    a.lh = lam_h;
+    a.lpu = lam_pu;
+    a.dphi0 = dphi0;
+    HIPCHK(h, launch_adjoint_init_ch(h->p.lattice, a, phi0, u0, p0, dparams, h->stream), "adjoint init kernels");
+    return PFLBM_OK;
+}
+
+static int phiu_check(pflbm_t* h, const void* buf) {
+    int st = guard(h);
+    if (st) return st;
+    if (!h->L.pu_bytes) return fail(h, PFLBM_EUNSUPPORTED, "this model keeps no (phi u) state");
+    if (!buf) return fail(h, PFLBM_EINVAL, "null pointer");
+    if (!h->initialised) return fail(h, PFLBM_EINVAL, "pflbm_init not called");
+    return PFLBM_OK;
+}
+
+int pflbm_get_phiu(pflbm_t* h, double* pu) {
+    if (int st = phiu_check(h, pu)) return st;
+    HIPCHK(h, launch_phiu_io(h->p.precision, true, h->base + h->L.off_pu, pu, h->L.P, h->p.nx, h->p.ny, h->p.nz,
+                             h->stream), "phiu get kernel");
+    return PFLBM_OK;
+}
+
+int pflbm_set_phiu(pflbm_t* h, const double* pu) {
+    if (int st = phiu_check(h, pu)) return st;
+    HIPCHK(h, launch_phiu_io(h->p.precision, false, h->base + h->L.off_pu, (double*)pu, h->L.P, h->p.nx, h->p.ny,
+                             h->p.nz, h->stream), "phiu set kernel");
     return PFLBM_OK;
 }
 

@@ -91,6 +91,10 @@ SIGNATURES = {
     "pflbm_adjoint_init": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "pflbm_adjoint_seed_phi": (ctypes.c_int, [_P, _P, _P, _P]),
     "pflbm_adjoint_step_noalloc": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
+    "pflbm_adjoint_step_pu": (ctypes.c_int, [_P] * 12),
+    "pflbm_adjoint_init_pu": (ctypes.c_int, [_P] * 10),
+    "pflbm_get_phiu": (ctypes.c_int, [_P, _P]),
+    "pflbm_set_phiu": (ctypes.c_int, [_P, _P]),
     "pflbm_probe_bytes": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
     "pflbm_probe_stream": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int,

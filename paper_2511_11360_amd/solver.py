@@ -100,6 +100,18 @@ class Solver:
         self._keep = (g, h)
         self._check(self.L.pflbm_set_distributions(self.h, _ptr(g), _ptr(h)), self.h)
 
+    def get_phiu(self):
+        """(phi u) of the previous step, canonical float64 [3][z][y][x] (CH,
+        Liang2018, Liang2014)."""
+        pu = torch.empty((3,) + self.shape, dtype=torch.float64, device=self.device)
+        self._check(self.L.pflbm_get_phiu(self.h, _ptr(pu)), self.h)
+        return pu
+
+    def set_phiu(self, pu):
+        pu = self._dev(pu, (3,) + self.shape)
+        self._keep = (pu,)
+        self._check(self.L.pflbm_set_phiu(self.h, _ptr(pu)), self.h)
+
     def step_count(self):
         n = ctypes.c_longlong()
         self._check(self.L.pflbm_step_count(self.h, ctypes.byref(n)), self.h)
@@ -119,7 +131,7 @@ class Solver:
     def load_state(self, buf):
         self._check(self.L.pflbm_load_state(self.h, _ptr(buf)), self.h)
 
-    # ---- discrete adjoint (AC model)
+    # ---- discrete adjoint (AC and CH models)
     def adjoint_workspace(self):
         n = ctypes.c_size_t()
         self._check(self.L.pflbm_adjoint_workspace_bytes(self.h, ctypes.byref(n)), self.h)
@@ -131,6 +143,14 @@ class Solver:
         self._check(self.L.pflbm_adjoint_step(self.h, _ptr(fwd_g), _ptr(fwd_h), _ptr(lam_g),
                                               _ptr(lam_h), _ptr(out_g), _ptr(out_h),
                                               _ptr(dparams), _ptr(work)), self.h)
+
+    def adjoint_step_pu(self, fwd_g, fwd_h, fwd_pu, lam_g, lam_h, lam_pu, out_g, out_h, out_pu, dparams,
+                        work):
+        """adjoint_step with the (phi u) state of the CH model
+        (pflbm_adjoint_step_pu)."""
+        self._check(self.L.pflbm_adjoint_step_pu(self.h, _ptr(fwd_g), _ptr(fwd_h), _ptr(fwd_pu), _ptr(lam_g),
+                                                 _ptr(lam_h), _ptr(lam_pu), _ptr(out_g), _ptr(out_h),
+                                                 _ptr(out_pu), _ptr(dparams), _ptr(work)), self.h)
 
     def adjoint_step_noalloc(self, fwd_g, fwd_h, lam_g, lam_h, out_g, out_h, dparams):
         """adjoint_step without a workspace (the library's own device scratch)."""
@@ -155,4 +175,16 @@ class Solver:
         out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
         self._check(self.L.pflbm_adjoint_init(self.h, _ptr(phi), _ptr(u), _ptr(pr), _ptr(lam_g),
                                               _ptr(lam_h), _ptr(out)), self.h)
+        return out
+
+    def adjoint_init_pu(self, phi0, u0, p0, lam_g, lam_h, lam_pu, dparams, work):
+        """dL/dphi0 of the initialisation with the (phi u) part; adds the sigma
+        and W terms of the CH initialisation into dparams."""
+        phi = self._dev(phi0, self.shape)
+        u = self._dev(u0, (self.dim,) + self.shape)
+        pr = self._dev(p0, self.shape)
+        out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        self._check(self.L.pflbm_adjoint_init_pu(self.h, _ptr(phi), _ptr(u), _ptr(pr), _ptr(lam_g),
+                                                 _ptr(lam_h), _ptr(lam_pu), _ptr(out), _ptr(dparams),
+                                                 _ptr(work)), self.h)
         return out

@@ -46,3 +46,73 @@ def test_step_tangent_is_linear():
     c = dv.step_jvp(p, st, v1[0] + 2 * v2[0], v1[1] + 2 * v2[1])
     for k in range(2):
         assert np.allclose(c[k], a[k] + 2 * b[k], rtol=1e-12, atol=1e-12)
+
+
+def _small_ch():
+    """The resolved droplet with the Cahn-Hilliard phase field (Sec. II.D.1),
+    whose state also holds (phi u) of the previous step, in a shear flow so
+    that (phi u) and its tangent are not zero."""
+    p, phi, u, target = _small()
+    p = om.Params(**dict(p.__dict__, model="CH", eta=1.0, M=0.05))
+    u = u.copy()
+    y = np.arange(phi.shape[1])[None, :, None]
+    u[0] = 0.01 * np.sin(2 * np.pi * (y + 0.5) / phi.shape[1])
+    return p, phi, u, target
+
+
+def test_ch_complex_step_matches_central_differences():
+    p, phi, u, target = _small_ch()
+    for name in ("sigma", "M", "W"):
+        cs = dv.cs_param(p, name, phi, u, 8, target)
+        fd = dv.fd_param(p, name, phi, u, 8, target, rel=1e-5)
+        assert abs(cs - fd) <= 1e-6 * abs(cs), (name, cs, fd)
+    v = wl.seeded_field(phi.shape, 7, -1.0, 1.0)
+    cs = dv.cs_phi0(p, v, phi, u, 8, target)
+    h = 1e-5
+    fd = (dv.loss_l2(p, phi + h * v, u, 8, target) - dv.loss_l2(p, phi - h * v, u, 8, target)) / (2 * h)
+    assert abs(cs - fd) <= 1e-6 * abs(cs)
+
+
+def test_ch_step_tangent_matches_central_differences_with_phiu():
+    """The step's tangent along (g, h, phi u) of the previous step: a dropped
+    (phi u) term (G of Eq. liang2_G, or the stored phi u) fails this."""
+    p, phi, u, _ = _small_ch()
+    st = om.run(p, om.init(p, phi, u), 3)
+    rng = np.random.default_rng(5)
+    vg = rng.standard_normal(st.g.shape) * 1e-3
+    vh = rng.standard_normal(st.h.shape) * 1e-3
+    vpu = rng.standard_normal(st.phiu_prev.shape)
+    J = dv.step_jvp(p, st, vg, vh, vpu)
+    assert len(J) == 3
+    e = 1e-6
+    a = om.step(p, om.State(st.g + e * vg, st.h + e * vh, st.phiu_prev + e * vpu))
+    b = om.step(p, om.State(st.g - e * vg, st.h - e * vh, st.phiu_prev - e * vpu))
+    for k, (x, y) in enumerate(((a.g, b.g), (a.h, b.h), (a.phiu_prev, b.phiu_prev))):
+        fd = (x - y) / (2 * e)
+        assert np.max(np.abs(J[k] - fd)) <= 1e-7 * (np.max(np.abs(fd)) + 1e-12), k
+    # the previous (phi u) enters h through G alone, with weight -3 w_a e_a (1 - 1/(2 tau_phi))
+    Jpu = dv.step_jvp(p, st, 0 * vg, 0 * vh, vpu)
+    assert np.max(np.abs(Jpu[0])) == 0.0 and np.max(np.abs(Jpu[2])) == 0.0
+    assert np.max(np.abs(Jpu[1])) > 0.0
+
+
+def test_ch_init_tangent_matches_central_differences():
+    p, phi, u, _ = _small_ch()
+    v = wl.seeded_field(phi.shape, 9, -1.0, 1.0)
+    p0 = 1e-3 * wl.seeded_field(phi.shape, 10, -1.0, 1.0)
+    J = dv.init_jvp(p, phi, v, u, p0)
+    assert len(J) == 3
+    e = 1e-6
+    a = om.init(p, phi + e * v, u, p0)
+    b = om.init(p, phi - e * v, u, p0)
+    for k, (x, y) in enumerate(((a.g, b.g), (a.h, b.h), (a.phiu_prev, b.phiu_prev))):
+        fd = (x - y) / (2 * e)
+        assert np.max(np.abs(J[k] - fd)) <= 1e-7 * (np.max(np.abs(fd)) + 1e-12), k
+    for name in ("sigma", "W"):
+        T = dv.init_jvp(p, phi, None, u, p0, name=name)
+        dh = 1e-6 * getattr(p, name)
+        a = om.init(om.Params(**dict(p.__dict__, **{name: getattr(p, name) + dh})), phi, u, p0)
+        b = om.init(om.Params(**dict(p.__dict__, **{name: getattr(p, name) - dh})), phi, u, p0)
+        fd = (a.h - b.h) / (2 * dh)
+        assert np.max(np.abs(T[1] - fd)) <= 1e-6 * np.max(np.abs(fd)), name
+        assert np.max(np.abs(T[0])) == 0.0
