@@ -189,31 +189,40 @@ def probes(n, reps=20):
 ADJ_BYTES = 2 * (19 + 7) * 8 + 26 * 8 + 2 * 6 * 8   # lambda in + out, forward g, h, workspace
 
 
-def time_adjoint(steps):
+def time_adjoint(steps, model="AC"):
     """The discrete adjoint step (float64, canonical layout) on the 128^3
     sheared droplet between moving walls, at the forward state after 20 steps,
     chaining lambda through two buffers. Algorithmic bytes per node: lambda
     read and written (2 x 26 x 8), the forward state read (26 x 8), six
-    workspace values written and read (2 x 6 x 8)."""
+    workspace values written and read (2 x 6 x 8); the CH model adds (phi u)
+    to the state (3 x 8 more in each of the three)."""
     import torch
     from paper_2511_11360_amd import workloads as wl
     from paper_2511_11360_amd.solver import Solver
     d, phi, u, _ = wl.sheared_droplet_3d()
+    d = dict(d, model=model)
+    ch = model == "CH"
     s = Solver(d, precision="fp64")
     s.init(phi, u)
     s.step(20)
     fg, fh = s.get_distributions()
+    fpu = s.get_phiu() if ch else None
     gen = torch.Generator(device=fg.device).manual_seed(5)
-    lam = [(torch.randn(fg.shape, dtype=torch.float64, device=fg.device, generator=gen),
-            torch.randn(fh.shape, dtype=torch.float64, device=fg.device, generator=gen)),
-           (torch.empty_like(fg), torch.empty_like(fh))]
+
+    def rnd(t):
+        return torch.randn(t.shape, dtype=torch.float64, device=fg.device, generator=gen)
+    lam = [(rnd(fg), rnd(fh), rnd(fpu) if ch else None),
+           (torch.empty_like(fg), torch.empty_like(fh), torch.empty_like(fpu) if ch else None)]
     dparams = torch.zeros(3, dtype=torch.float64, device=fg.device)
     work = s.adjoint_workspace()
 
     def run(k):
         for i in range(k):
             a, b = lam[i % 2], lam[(i + 1) % 2]
-            s.adjoint_step(fg, fh, a[0], a[1], b[0], b[1], dparams, work)
+            if ch:
+                s.adjoint_step_pu(fg, fh, fpu, a[0], a[1], a[2], b[0], b[1], b[2], dparams, work)
+            else:
+                s.adjoint_step(fg, fh, a[0], a[1], b[0], b[1], dparams, work)
     run(max(4, int(PREWARM_MS / 0.45)))
     torch.cuda.synchronize()
     e0, e1 = _events(s)
@@ -223,11 +232,12 @@ def time_adjoint(steps):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     nodes = d["nx"] * d["ny"] * d["nz"]
+    nb = ADJ_BYTES + (3 * 3 * 8 if ch else 0)
     return {"workload": "3-D sheared droplet, D3Q19+D3Q7, 128^3, walls moving at -+0.02 (adjoint "
-                        "of the AC step, float64)",
+                        "of the %s step, float64)" % model,
             "ms_per_step": round(ms, 4), "MLUPS": round(nodes / (ms * 1e-3) / 1e6, 1),
-            "bytes_per_update": ADJ_BYTES,
-            "hbm_frac": round(ADJ_BYTES * nodes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+            "bytes_per_update": nb,
+            "hbm_frac": round(nb * nodes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
 
 
 def time_backward(nsteps=200):
@@ -408,6 +418,8 @@ def main():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-probes", action="store_true")
+    ap.add_argument("--no-backward", action="store_true",
+                    help="adjoint line without the full backward pass (counter runs)")
     ap.add_argument("--no-errors", action="store_true")
     ap.add_argument("--prewarm-ms", type=float, default=PREWARM_MS,
                     help="GPU time of the clock pre-warm before each timed line (0: none)")
@@ -529,8 +541,12 @@ def main():
         log("adjoint")
         adjoint = time_adjoint(100)
         torch.cuda.empty_cache()
-        log("backward pass")
-        adjoint["backward"] = time_backward()
+        log("adjoint, CH")
+        adjoint["ch"] = time_adjoint(100, "CH")
+        torch.cuda.empty_cache()
+        if not args.no_backward:
+            log("backward pass")
+            adjoint["backward"] = time_backward()
 
     traffic = measured_traffic(args.workload, args.precision)
     out = {
