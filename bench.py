@@ -404,8 +404,8 @@ def main():
     global PREWARM_MS
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="turb512", choices=["turb512", "tgv256"])
     ap.add_argument("--precision", default="mixed_fp16")
     ap.add_argument("--zblock", type=int, default=0)
