@@ -249,7 +249,7 @@ int pflbm_checkpoint_bytes(const pflbm_t* h, size_t* bytes);
 int pflbm_save_state(pflbm_t* h, void* dev_dst);
 int pflbm_load_state(pflbm_t* h, const void* dev_src);
 
-/* Discrete adjoint (AC and CH models). The adjoint of one time step X^n -> X^{n+1}
+/* Discrete adjoint (AC, CH and nonlocal models). The adjoint of one time step X^n -> X^{n+1}
    (X = canonical float64 post-streaming distributions, as returned by
    pflbm_get_distributions) given lambda^{n+1} = dL/dX^{n+1}: writes
    lambda^n = dL/dX^n and ADDS dL/d(sigma, M, W) of this step into dparams
@@ -259,12 +259,14 @@ int pflbm_load_state(pflbm_t* h, const void* dev_src);
    pflbm_adjoint_workspace_bytes(). Uses the handle's parameters; float64
    arithmetic whatever the handle's precision. The method's reverse mode is
    not in the paper: it is the exact transpose of the discrete step of
-   Sec. II.C.1 (AC) or Sec. II.D.1 (CH) as implemented here, on every lattice
-   pair. The CH state also holds (phi u) of the previous step, so the CH model
-   goes through pflbm_adjoint_step_pu; pflbm_adjoint_step returns
-   PFLBM_EUNSUPPORTED for it, and both return PFLBM_EUNSUPPORTED for the
-   other models (nonlocal, Liang2018, Liang2014) and for a frozen phase
-   field. */
+   Sec. II.C.1 (AC), Sec. II.D.1 (CH) or Secs. II.C.3-4 (nonlocal AC, Eqs.
+   nonlocalAC, lagrange_multiplier, Chai_geq, Hu_G, with its global
+   multiplier) as implemented here, on every lattice pair. The CH state also
+   holds (phi u) of the previous step, so the CH model goes through
+   pflbm_adjoint_step_pu; pflbm_adjoint_step returns PFLBM_EUNSUPPORTED for
+   it, and both return PFLBM_EUNSUPPORTED for the Liang2018 and Liang2014
+   models and for a frozen phase field. The nonlocal model's workspace is
+   larger (two more per-node arrays). */
 int pflbm_adjoint_workspace_bytes(const pflbm_t* h, size_t* bytes);
 int pflbm_adjoint_step(pflbm_t* h, const double* fwd_g, const double* fwd_h,
                        const double* lam_g, const double* lam_h,
@@ -291,7 +293,7 @@ int pflbm_adjoint_step_pu(pflbm_t* h, const double* fwd_g, const double* fwd_h, 
    exceeds that. It allocates nothing. Calls that overlap on one device (on
    different streams, or from different handles) share the array and race;
    calls in order on one stream are safe. Results equal pflbm_adjoint_step's
-   bit for bit. */
+   bit for bit. AC model (PFLBM_EUNSUPPORTED otherwise). */
 #define PFLBM_ADJOINT_SCRATCH_BYTES 100925440
 int pflbm_adjoint_step_noalloc(pflbm_t* h, const double* fwd_g, const double* fwd_h,
                                const double* lam_g, const double* lam_h,
@@ -306,10 +308,22 @@ int pflbm_adjoint_step_noalloc(pflbm_t* h, const double* fwd_g, const double* fw
    Asynchronous. */
 int pflbm_adjoint_seed_phi(pflbm_t* h, const double* dphi, double* lam_g, double* lam_h);
 
+/* The seed for every model with an adjoint: dphi = dL/dphi of the phase field
+   that pflbm_fields returns for the state whose canonical h is fwd_h. For the
+   nonlocal model that field is phi* = sum h + (1 - lam) R / 2 (the corrected
+   phi of Sec. II.C.3), which depends on every node through the multiplier
+   gamma of Eq. lagrange_multiplier and on M and W through the source R: the
+   seed applies its transpose and ADDS the M and W terms into dparams (device
+   float64[3], may be NULL); work: workspace of
+   pflbm_adjoint_workspace_bytes(). For the AC and CH models it equals
+   pflbm_adjoint_seed_phi (fwd_h, dparams and work unused). */
+int pflbm_adjoint_seed(pflbm_t* h, const double* fwd_h, const double* dphi, double* lam_g, double* lam_h,
+                       double* dparams, void* work);
+
 /* dL/dphi0 of the equilibrium initialisation (pflbm_init) given
    lambda^0 = dL/dX^0: dphi0 [z][y][x] (device float64, overwritten). u0 and
-   p0 as passed to pflbm_init (NULL = zero). AC model (the CH model goes
-   through pflbm_adjoint_init_pu). */
+   p0 as passed to pflbm_init (NULL = zero). AC and nonlocal models (the CH
+   model goes through pflbm_adjoint_init_pu). */
 int pflbm_adjoint_init(pflbm_t* h, const double* phi0, const double* u0, const double* p0,
                        const double* lam_g, const double* lam_h, double* dphi0);
 

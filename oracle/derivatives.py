@@ -82,3 +82,17 @@ def init_jvp(p, phi0, v, u0=None, p0=None, name=None, h=1e-30):
     if st.phiu_prev is not None:
         out.append(np.imag(st.phiu_prev) / h)
     return tuple(out)
+
+
+def fields_phi_tangent(p, st, vh=None, name=None, h=1e-30):
+    """Tangent of the phase field the state reports (om.fields: for the
+    nonlocal model the corrected phi*) along vh in h, or, with name given,
+    with respect to that parameter."""
+    if name is None:
+        sc = om.State(st.g.astype(complex), st.h + 1j * h * vh,
+                      None if st.phiu_prev is None else st.phiu_prev.astype(complex))
+        return np.imag(om.fields(p, sc)[0]) / h
+    pc = _with(p, **{name: complex(getattr(p, name), h)})
+    sc = om.State(st.g.astype(complex), st.h.astype(complex),
+                  None if st.phiu_prev is None else st.phiu_prev.astype(complex))
+    return np.imag(om.fields(pc, sc)[0]) / h

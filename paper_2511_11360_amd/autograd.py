@@ -21,8 +21,8 @@ class PhaseFieldRun(torch.autograd.Function):
     def forward(ctx, phi0, sigma, M, W, params, u0, nsteps, precision, k):
         d = dict(params)
         d["sigma"], d["M"], d["W"] = float(sigma), float(M), float(W)
-        if d.get("model", "AC") not in ("AC", "CH"):
-            raise ValueError("the adjoint is implemented for the AC and CH models only")
+        if d.get("model", "AC") not in ("AC", "CH", "NL"):
+            raise ValueError("the adjoint is implemented for the AC, CH and nonlocal models only")
         s = Solver(d, precision=precision, device=phi0.device)
         s.init(phi0, u0)
         nsteps = int(nsteps)
@@ -53,13 +53,18 @@ class PhaseFieldRun(torch.autograd.Function):
         # the CH state also holds (phi u) of the previous step; L depends on
         # phi alone, so its adjoint starts at zero
         ch = s.d.get("model", "AC") == "CH"
-        lam_g, lam_h = s.adjoint_seed_phi(grad_phi.to(device=dev, dtype=torch.float64).reshape(shape))
-        out_g = torch.empty_like(lam_g)
-        out_h = torch.empty_like(lam_h)
         lam_pu = torch.zeros((3,) + shape, dtype=torch.float64, device=dev) if ch else None
         out_pu = torch.empty_like(lam_pu) if ch else None
         dparams = torch.zeros(3, dtype=torch.float64, device=dev)
         work = s.adjoint_workspace()
+        # the nonlocal model's phase field is a corrected sum h, so its seed
+        # reads h of the final state, which the solver still holds
+        h_final = s.get_distributions()[1] if s.d.get("model", "AC") == "NL" else None
+        lam_g, lam_h = s.adjoint_seed(h_final, grad_phi.to(device=dev, dtype=torch.float64).reshape(shape),
+                                      dparams, work)
+        del h_final
+        out_g = torch.empty_like(lam_g)
+        out_h = torch.empty_like(lam_h)
         for start, buf in reversed(ctx.cks):
             n = min(ctx.k, ctx.nsteps - start)
             s.load_state(buf)

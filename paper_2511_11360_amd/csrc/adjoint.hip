@@ -157,7 +157,9 @@ __global__ __launch_bounds__(256) void k_adj_phi(const AdjArgs a) {
 // pass 2: local reverse sweep of the collision. MODEL 0: conservative AC
 // (Eqs. fakhari_geq, fakhari_G_modified); MODEL 1: the Cahn-Hilliard phase
 // field (Eqs. liang2_geq, liang2_G with the backward-Euler d(phi u)/dt, whose
-// (phi u) of the previous step is part of the state)
+// (phi u) of the previous step is part of the state); MODEL 2: the nonlocal
+// AC (Eqs. Chai_geq, Hu_G; phi here is the corrected phi* of the phase-field
+// pass, the nonlocal source R is formed from sum h of the node)
 template <class PAIR, int MODEL>
 __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
     using GL = typename PAIR::G;
@@ -295,6 +297,7 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
         double b_coef = 0.0, b_anti = 0.0, b_itp = 0.0, b_gfp = 0.0;
         double b_Pi[3][3] = {{0.0}};
         double b_muh = 0.0;   // CH: mu_phi through h_eq
+        double b_R = 0.0;     // nonlocal: the source R through G
 
         if constexpr (MODEL == 1) {
             // h*_a = (1 - itp) h_a + itp heq_a + gfp G_a with
@@ -338,6 +341,36 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
                 b_u[k] += phi * b_puc[k];
                 a.opu[(size_t)k * nn + n] = b_pup[k];
             }
+        } else if constexpr (MODEL == 2) {
+            // h*_a = (1 - itp) h_a + itp heq_a + gfp G_a with heq_a = w_a phi
+            // (1 + 3 e_a . u), G_a = lam w_a coef (e_a . gr) + (1 - lam) w_a R,
+            // R = M (gamma phi_s (1 - phi_s) - (32 / W^2) phi_s (phi_s - 1)
+            // (phi_s - 1/2)) at phi_s = sum h (summed in the phi pass's order)
+            double hs = h[0];
+            for (int al = 1; al < QH; ++al) hs += h[al];
+            const double gam = a.nls[0];
+            const double R = ph.mob * (gam * hs * (1.0 - hs) - ph.w32 * (hs - 1.0) * hs * (hs - 0.5));
+            const double lam = ph.lam;
+            for (int al = 0; al < QH; ++al) {
+                const double w = HL::w(al);
+                const double eu = HL::c(al, 0) * u[0] + HL::c(al, 1) * u[1] + HL::c(al, 2) * u[2];
+                const double eg = HL::c(al, 0) * gr[0] + HL::c(al, 1) * gr[1] + HL::c(al, 2) * gr[2];
+                const double heq = w * phi * (1.0 + 3.0 * eu);
+                const double lb = lh[al];
+                b_itp += (heq - h[al]) * lb;
+                b_gfp += (lam * w * coef * eg + (1.0 - lam) * w * R) * lb;
+                b_coef += gfp * lam * w * eg * lb;
+                for (int k = 0; k < 3; ++k) b_gr[k] += gfp * lam * w * coef * HL::c(al, k) * lb;
+                b_R += gfp * (1.0 - lam) * w * lb;
+                const double bheq = itp * lb;
+                b_phi += bheq * w * (1.0 + 3.0 * eu);
+                for (int k = 0; k < 3; ++k) b_u[k] += bheq * w * phi * 3.0 * HL::c(al, k);
+            }
+            b_anti += b_coef * pp * rn;
+            b_phi += b_coef * ph.anti * (1.0 - 2.0 * phi) * rn;
+            const double b_rn = b_coef * ph.anti * pp;
+            const double b_gg = -0.5 * rn * rn * rn * b_rn;
+            for (int k = 0; k < 3; ++k) b_gr[k] += 2.0 * gr[k] * b_gg;
         } else {
         // h*_a = (1 - itp) h_a + itp heq_a + gfp w_a coef (e_a . gr)
         for (int al = 0; al < QH; ++al) {
@@ -497,7 +530,8 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
         b_phi += dR * b_rho;
 
         // parameters: beta4 = 48 sigma / W, kappa = 1.5 sigma W, anti = 4 / W,
-        // itp = 1 / (3 M + 1/2), gfp = 1 - itp / 2
+        // itp = 1 / (3 M + 1/2), gfp = 1 - itp / 2 (the nonlocal source's M and
+        // W terms are formed with its total adjoint, after the stencil pass)
         const double sigma = a.sigma, W = a.W;
         th[0] = b_beta4 * 48.0 / W + b_kappa * 1.5 * W;
         const double b_itp_tot = b_itp - 0.5 * b_gfp;
@@ -511,6 +545,7 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
         a.work[2 * nn + n] = b_gr[1];
         a.work[3 * nn + n] = b_gr[2];
         a.work[4 * nn + n] = b_lap;
+        if constexpr (MODEL == 2) a.work[5 * nn + n] = b_R;
     }
     // block sums of the parameter adjoints, fixed order
     __shared__ double red[3][256];
@@ -531,10 +566,15 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
 // population of y receives that plus dL/dphi(y), and its direct term
 // (1 - 1/tau_phi) lambda*_h (the h stream transpose of lambda_h^{n+1},
 // gathered here rather than written by the sweep and read back).
-// INIT: the transpose of the Laplacian alone, for the adjoint of the CH
-// initialisation (mu_phi(phi0) in h_eq): dL/dphi0 = work[0] + lap^T(work[4])
-template <class PAIR, bool INIT>
+// MODE 0: that, into lambda_h^n (AC, CH). MODE 1: the transpose of the
+// Laplacian alone, for the adjoint of the CH initialisation (mu_phi(phi0) in
+// h_eq): dL/dphi0 = work[0] + lap^T(work[4]). MODE 2 (nonlocal model): the
+// total dL/dphi* into work[0] (in place: only this node reads it), the
+// nonlocal correction's transpose and the h populations follow.
+constexpr int ST_STEP = 0, ST_INIT = 1, ST_NL = 2;
+template <class PAIR, int MODE>
 __global__ __launch_bounds__(256) void k_adj_stencil(const AdjArgs a) {
+    constexpr bool INIT = MODE == ST_INIT;
     using GL = typename PAIR::G;
     using HL = typename PAIR::H;
     constexpr int Q = GL::Q;
@@ -579,6 +619,10 @@ __global__ __launch_bounds__(256) void k_adj_stencil(const AdjArgs a) {
         a.dphi0[n] = acc;
         return;
     }
+    if constexpr (MODE == ST_NL) {
+        a.work[n] = acc;
+        return;
+    }
     const double itp1 = 1.0 - a.ph.inv_tau_phi;
     unroll<HL::Q>([&](auto J) {
         constexpr int al = J;
@@ -608,9 +652,150 @@ __global__ __launch_bounds__(PARAMS_THREADS) void k_adj_params(const double* par
         for (int k = 0; k < 3; ++k) out[k] += red[k][0];
 }
 
+// ---------------------------------------------------------------------------
+// nonlocal model (Eqs. nonlocalAC, lagrange_multiplier, chai_G, Hu_G): the
+// step uses phi* = phi + (1 - lam) R(phi, gamma) / 2 in place of phi = sum h,
+// R = M (gamma phi (1 - phi) - (32 / W^2) phi (phi - 1)(phi - 1/2)), gamma =
+// sum (32 / W^2) phi (phi - 1)(phi - 1/2) / sum phi (1 - phi) over all nodes
+// (0 when that denominator vanishes). Its transpose needs two global sums:
+// gamma of the state, and dL/dgamma = sum_x dL/dR(x) M phi(x) (1 - phi(x)).
+
+// 256-thread fixed-order block sum of K values per thread into part[wg][4]
+template <int K>
+__device__ __forceinline__ void block_sums(const double (&v)[K], double* part, int wg) {
+    __shared__ double red[K][256];
+    for (int k = 0; k < K; ++k) red[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int s = 128; s >= 1; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < K; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < K; ++k) part[(size_t)wg * 4 + k] = red[k][0];
+}
+
+// phi = sum h into work[6], partial sums of gamma's numerator and denominator
+__global__ __launch_bounds__(256) void k_adj_phi_nl(const AdjArgs a) {
+    const long long nn = (long long)a.nx * a.ny * a.nz;
+    const int wg = xcd_block();
+    const long long n = (long long)wg * blockDim.x + threadIdx.x;
+    double v[2] = {0.0, 0.0};
+    if (n < nn) {
+        double s = a.fh[n];
+        for (int al = 1; al < a.qh; ++al) s += a.fh[(size_t)al * nn + n];
+        a.work[6 * nn + n] = s;
+        v[0] = a.ph.w32 * (s - 1.0) * s * (s - 0.5);
+        v[1] = s * (1.0 - s);
+    }
+    block_sums<2>(v, a.nlpart, wg);
+}
+
+// one workgroup, fixed order. MODE 0: gamma = num / den (0 if den = 0) and
+// den into nls[0], nls[1]. MODE 1: dL/dgamma into nls[2]; the source's M and
+// W terms added into dparams[1], dparams[2] (if given)
+__global__ __launch_bounds__(1024) void k_adj_nlred(const double* part, int nb, int mode, double* nls,
+                                                    double* dparams) {
+    __shared__ double red[3][1024];
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nb; b += 1024)
+        for (int k = 0; k < 3; ++k) s[k] += part[(size_t)b * 4 + k];
+    for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = s[k];
+    __syncthreads();
+    for (int st = 512; st >= 1; st >>= 1) {
+        if ((int)threadIdx.x < st)
+            for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (mode == 0) {
+            nls[0] = red[1][0] != 0.0 ? red[0][0] / red[1][0] : 0.0;
+            nls[1] = red[1][0];
+        } else {
+            nls[2] = red[0][0];
+            if (dparams) {
+                dparams[1] += red[1][0];
+                dparams[2] += red[2][0];
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ double nl_R(const Phys& ph, double p, double gam) {
+    return ph.mob * (gam * p * (1.0 - p) - ph.w32 * (p - 1.0) * p * (p - 0.5));
+}
+
+// phi* of every node into the workspace's phi
+__global__ __launch_bounds__(256) void k_adj_phistar(const AdjArgs a) {
+    const long long nn = (long long)a.nx * a.ny * a.nz;
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    const double p = a.work[6 * nn + n];
+    a.phi[n] = p + 0.5 * (1.0 - a.ph.lam) * nl_R(a.ph, p, a.nls[0]);
+}
+
+// transpose of phi* = phi + (1 - lam) R / 2 at each node, without gamma's
+// global term: from dL/dphi* (work[0], or the seed dphi) and the collision's
+// direct dL/dR (work[5], or none for the seed), dL/dR = direct + (1 - lam)
+// dL/dphi* / 2 and dL/dphi = dL/dphi* + dL/dR dR/dphi into work[0]; block
+// partials of dL/dgamma, dL/dM = sum dL/dR R / M and dL/dW = sum dL/dR
+// (-2 R / W) (R scales with 32 / W^2, gamma included)
+__global__ __launch_bounds__(256) void k_adj_nl_map(const AdjArgs a, const double* dphis, const double* bRd) {
+    const long long nn = (long long)a.nx * a.ny * a.nz;
+    const int wg = xcd_block();
+    const long long n = (long long)wg * blockDim.x + threadIdx.x;
+    double v[3] = {0.0, 0.0, 0.0};
+    if (n < nn) {
+        const Phys& ph = a.ph;
+        const double p = a.work[6 * nn + n], gam = a.nls[0];
+        const double acc = dphis[n];
+        const double bR = (bRd ? bRd[n] : 0.0) + 0.5 * (1.0 - ph.lam) * acc;
+        const double well = p * (1.0 - p);
+        const double Rm = gam * well - ph.w32 * (p - 1.0) * p * (p - 0.5);   // R / M
+        const double dR = ph.mob * (gam * (1.0 - 2.0 * p) - ph.w32 * (3.0 * p * p - 3.0 * p + 0.5));
+        a.work[n] = acc + bR * dR;
+        v[0] = bR * ph.mob * well;
+        v[1] = bR * Rm;
+        v[2] = bR * (-2.0 * ph.mob * Rm / a.W);
+    }
+    block_sums<3>(v, a.nlpart, wg);
+}
+
+// dL/dphi = work[0] + dL/dgamma dgamma/dphi, dgamma/dphi = ((32 / W^2)
+// (3 phi^2 - 3 phi + 1/2) - gamma (1 - 2 phi)) / den, into every h population:
+// SEED: lam_h = that (lam_g = 0); otherwise oh = that plus the direct term
+// (1 - 1/tau_phi) lambda*_h (the h stream transpose of lambda_h^{n+1})
+template <class PAIR, bool SEED>
+__global__ __launch_bounds__(256) void k_adj_nl_final(const AdjArgs a, double* lam_g, double* lam_h) {
+    using GL = typename PAIR::G;
+    using HL = typename PAIR::H;
+    const long long nn = (long long)a.nx * a.ny * a.nz;
+    const int wg = xcd_block();
+    const long long n = (long long)wg * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    const Phys& ph = a.ph;
+    const double p = a.work[6 * nn + n], gam = a.nls[0], den = a.nls[1];
+    const double dgam = den != 0.0 ? (ph.w32 * (3.0 * p * p - 3.0 * p + 0.5) - gam * (1.0 - 2.0 * p)) / den : 0.0;
+    const double t = a.work[n] + a.nls[2] * dgam;
+    if constexpr (SEED) {
+        for (int i = 0; i < GL::Q; ++i) lam_g[(size_t)i * nn + n] = 0.0;
+        for (int al = 0; al < HL::Q; ++al) lam_h[(size_t)al * nn + n] = t;
+    } else {
+        const Nbr nb(a, node_of(n, a));
+        const double itp1 = 1.0 - ph.inv_tau_phi;
+        unroll<HL::Q>([&](auto J) {
+            constexpr int al = J;
+            constexpr int cx = HL::c(al, 0), cy = HL::c(al, 1), cz = HL::c(al, 2);
+            const size_t e = nb.beyond(cx, cy, cz) ? (size_t)HL::opp(al) * nn + n
+                                                    : (size_t)al * nn + nb.index(cx, cy, cz);
+            a.oh[(size_t)al * nn + n] = itp1 * a.lh[e] + t;
+        });
+    }
+}
+
 // dL/dphi0 through the equilibrium initialisation h = h_eq(phi0, u0),
-// g = g_eq(3 p0 / rho(phi0), u0)
-template <class PAIR>
+// g = g_eq(3 p0 / rho(phi0), u0); MODEL 0 AC, 2 nonlocal
+template <class PAIR, int MODEL>
 __global__ __launch_bounds__(256) void k_adj_init(const AdjInitArgs a) {
     using GL = typename PAIR::G;
     using HL = typename PAIR::H;
@@ -627,7 +812,9 @@ __global__ __launch_bounds__(256) void k_adj_init(const AdjInitArgs a) {
     double s = 0.0;
     for (int al = 0; al < HL::Q; ++al) {
         const double eu = HL::c(al, 0) * u[0] + HL::c(al, 1) * u[1] + HL::c(al, 2) * u[2];
-        s += a.lh[(size_t)al * nn + n] * HL::w(al) * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * usq);
+        // Eq. fakhari_geq (AC) or Eq. Chai_geq (nonlocal: first order in u)
+        const double dh = MODEL == 2 ? 1.0 + 3.0 * eu : 1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * usq;
+        s += a.lh[(size_t)al * nn + n] * HL::w(al) * dh;
     }
     if (a.p0) {
         const double phi = a.phi0[n];
@@ -727,12 +914,31 @@ hipError_t launch_adjoint_seed(const double* dphi, double* lg, double* lh, long 
 hipError_t launch_adjoint(int lattice, int model, const AdjArgs& a, double* dparams, hipStream_t st) {
     const long long nn = (long long)a.nx * a.ny * a.nz;
     const dim3 grid((unsigned)((nn + 255) / 256)), block(256);
-    hipLaunchKernelGGL(k_adj_phi, grid, block, 0, st, a);
+    if (model == 2) {
+        // phi = sum h, gamma, phi*
+        hipLaunchKernelGGL(k_adj_phi_nl, grid, block, 0, st, a);
+        hipLaunchKernelGGL(k_adj_nlred, dim3(1), dim3(1024), 0, st, (const double*)a.nlpart, (int)grid.x, 0, a.nls,
+                           (double*)nullptr);
+        hipLaunchKernelGGL(k_adj_phistar, grid, block, 0, st, a);
+    } else {
+        hipLaunchKernelGGL(k_adj_phi, grid, block, 0, st, a);
+    }
     auto go = [&](auto pair) {
         using P_ = decltype(pair);
+        if (model == 2) {
+            hipLaunchKernelGGL((k_adj_local<P_, 2>), grid, block, 0, st, a);
+            hipLaunchKernelGGL((k_adj_stencil<P_, ST_NL>), grid, block, 0, st, a);
+            hipLaunchKernelGGL(k_adj_nl_map, grid, block, 0, st, a, (const double*)a.work,
+                               (const double*)(a.work + 5 * nn));
+            hipLaunchKernelGGL(k_adj_nlred, dim3(1), dim3(1024), 0, st, (const double*)a.nlpart, (int)grid.x, 1,
+                               a.nls, dparams);
+            hipLaunchKernelGGL((k_adj_nl_final<P_, false>), grid, block, 0, st, a, (double*)nullptr,
+                               (double*)nullptr);
+            return;
+        }
         if (model == 1) hipLaunchKernelGGL((k_adj_local<P_, 1>), grid, block, 0, st, a);
         else hipLaunchKernelGGL((k_adj_local<P_, 0>), grid, block, 0, st, a);
-        hipLaunchKernelGGL((k_adj_stencil<P_, false>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((k_adj_stencil<P_, ST_STEP>), grid, block, 0, st, a);
     };
     if (lattice == 0) go(Pair2D{});
     else if (lattice == 1) go(Pair3D{});
@@ -741,12 +947,37 @@ hipError_t launch_adjoint(int lattice, int model, const AdjArgs& a, double* dpar
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint_init(int lattice, const AdjInitArgs& a, hipStream_t st) {
+hipError_t launch_adjoint_init(int lattice, int model, const AdjInitArgs& a, hipStream_t st) {
     const long long nn = (long long)a.nx * a.ny * a.nz;
     const dim3 grid((unsigned)((nn + 255) / 256)), block(256);
-    if (lattice == 0) hipLaunchKernelGGL(k_adj_init<Pair2D>, grid, block, 0, st, a);
-    else if (lattice == 1) hipLaunchKernelGGL(k_adj_init<Pair3D>, grid, block, 0, st, a);
-    else hipLaunchKernelGGL(k_adj_init<Pair3D27>, grid, block, 0, st, a);
+    auto go = [&](auto pair) {
+        using P_ = decltype(pair);
+        if (model == 2) hipLaunchKernelGGL((k_adj_init<P_, 2>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_adj_init<P_, 0>), grid, block, 0, st, a);
+    };
+    if (lattice == 0) go(Pair2D{});
+    else if (lattice == 1) go(Pair3D{});
+    else go(Pair3D27{});
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_seed_nl(int lattice, const AdjArgs& a, const double* dphi, double* lam_g, double* lam_h,
+                                  double* dparams, hipStream_t st) {
+    const long long nn = (long long)a.nx * a.ny * a.nz;
+    const dim3 grid((unsigned)((nn + 255) / 256)), block(256);
+    hipLaunchKernelGGL(k_adj_phi_nl, grid, block, 0, st, a);
+    hipLaunchKernelGGL(k_adj_nlred, dim3(1), dim3(1024), 0, st, (const double*)a.nlpart, (int)grid.x, 0, a.nls,
+                       (double*)nullptr);
+    hipLaunchKernelGGL(k_adj_nl_map, grid, block, 0, st, a, dphi, (const double*)nullptr);
+    hipLaunchKernelGGL(k_adj_nlred, dim3(1), dim3(1024), 0, st, (const double*)a.nlpart, (int)grid.x, 1, a.nls,
+                       dparams);
+    auto go = [&](auto pair) {
+        using P_ = decltype(pair);
+        hipLaunchKernelGGL((k_adj_nl_final<P_, true>), grid, block, 0, st, a, lam_g, lam_h);
+    };
+    if (lattice == 0) go(Pair2D{});
+    else if (lattice == 1) go(Pair3D{});
+    else go(Pair3D27{});
     return hipGetLastError();
 }
 
@@ -757,7 +988,7 @@ hipError_t launch_adjoint_init_ch(int lattice, const AdjArgs& a, const double* p
     auto go = [&](auto pair) {
         using P_ = decltype(pair);
         hipLaunchKernelGGL((k_adj_init_ch<P_>), grid, block, 0, st, a, phi0, u0, p0);
-        hipLaunchKernelGGL((k_adj_stencil<P_, true>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((k_adj_stencil<P_, ST_INIT>), grid, block, 0, st, a);
     };
     if (lattice == 0) go(Pair2D{});
     else if (lattice == 1) go(Pair3D{});

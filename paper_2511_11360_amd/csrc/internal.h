@@ -158,6 +158,8 @@ struct AdjArgs {
     double* phi;           // workspace [nodes]
     double* work;          // workspace [5][nodes]
     double* partials;      // workspace [blocks][3]
+    double* nlpart;        // nonlocal model: workspace [blocks][4] of partial sums
+    double* nls;           // nonlocal model: workspace [4]: gamma, its denominator, dL/dgamma
     int nx, ny, nz;
     int bc[3];
     int qh;
@@ -181,7 +183,9 @@ hipError_t adjoint_scratch(int device, void** out);
 hipError_t launch_adjoint_seed(const double* dphi, double* lg, double* lh, long long nn, int qg, int qh,
                                hipStream_t st);
 hipError_t launch_adjoint(int lattice, int model, const AdjArgs& a, double* dparams, hipStream_t s);
-hipError_t launch_adjoint_init(int lattice, const AdjInitArgs& a, hipStream_t s);
+hipError_t launch_adjoint_init(int lattice, int model, const AdjInitArgs& a, hipStream_t s);
+hipError_t launch_adjoint_seed_nl(int lattice, const AdjArgs& a, const double* dphi, double* lam_g, double* lam_h,
+                                  double* dparams, hipStream_t s);
 hipError_t launch_adjoint_init_ch(int lattice, const AdjArgs& a, const double* phi0, const double* u0,
                                   const double* p0, double* dparams, hipStream_t s);
 hipError_t launch_phiu_io(int precision, bool get, void* pu, double* canon, int P, int nx, int ny, int nz,

@@ -642,11 +642,17 @@ int pflbm_load_state(pflbm_t* h, const void* dev_src) {
 
 static size_t adj_nodes(const pflbm_t* h) { return (size_t)h->p.nx * h->p.ny * h->p.nz; }
 
+// per-node adjoint values of the workspace: dL/dphi, dL/dgrad phi, dL/dlap phi;
+// the nonlocal model adds dL/dR and phi = sum h
+static size_t adj_nwork(const pflbm_t* h) { return h->p.model == PFLBM_NL ? 7 : 5; }
+
 int pflbm_adjoint_workspace_bytes(const pflbm_t* h, size_t* bytes) {
     if (!h || !bytes) return PFLBM_EINVAL;
     const size_t nn = adj_nodes(h);
     const size_t blocks = (nn + 255) / 256;
-    *bytes = align_up(nn * 8, 256) + align_up(5 * nn * 8, 256) + align_up(blocks * 3 * 8, 256);
+    size_t b = align_up(nn * 8, 256) + align_up(adj_nwork(h) * nn * 8, 256) + align_up(blocks * 3 * 8, 256);
+    if (h->p.model == PFLBM_NL) b += align_up(blocks * 4 * 8, 256) + 256;
+    *bytes = b;
     return PFLBM_OK;
 }
 
@@ -654,8 +660,8 @@ int pflbm_adjoint_workspace_bytes(const pflbm_t* h, size_t* bytes) {
 static int adjoint_check(pflbm_t* h, bool with_pu) {
     int st = guard(h);
     if (st) return st;
-    if (h->p.model != PFLBM_AC && h->p.model != PFLBM_CH)
-        return fail(h, PFLBM_EUNSUPPORTED, "adjoint implemented for the AC and CH models only");
+    if (h->p.model != PFLBM_AC && h->p.model != PFLBM_CH && h->p.model != PFLBM_NL)
+        return fail(h, PFLBM_EUNSUPPORTED, "adjoint implemented for the AC, CH and nonlocal models only");
     if (h->p.model == PFLBM_CH && !with_pu)
         return fail(h, PFLBM_EUNSUPPORTED, "the CH adjoint carries (phi u): use the _pu entry points");
     if (h->p.freeze_phi) return fail(h, PFLBM_EUNSUPPORTED, "adjoint of a frozen phase field is not implemented");
@@ -694,6 +700,7 @@ int pflbm_adjoint_step_pu(pflbm_t* h, const double* fwd_g, const double* fwd_h, 
 int pflbm_adjoint_step_noalloc(pflbm_t* h, const double* fwd_g, const double* fwd_h, const double* lam_g,
                                const double* lam_h, double* lam_g_out, double* lam_h_out, double* dparams) {
     if (int st = adjoint_check(h, false)) return st;
+    if (h->p.model != PFLBM_AC) return fail(h, PFLBM_EUNSUPPORTED, "the allocation-free adjoint covers the AC model");
     size_t need = 0;
     pflbm_adjoint_workspace_bytes(h, &need);
     if (need > (size_t)PFLBM_ADJOINT_SCRATCH_BYTES) {
@@ -712,10 +719,20 @@ int pflbm_adjoint_step_noalloc(pflbm_t* h, const double* fwd_g, const double* fw
 static void adjoint_args(pflbm_t* h, void* work, AdjArgs& a) {
     const size_t nn = adj_nodes(h);
     std::memset(&a, 0, sizeof(a));
+    const size_t blocks = (nn + 255) / 256;
     char* w = (char*)work;
-    a.phi = (double*)w;
-    a.work = (double*)(w + align_up(nn * 8, 256));
-    a.partials = (double*)(w + align_up(nn * 8, 256) + align_up(5 * nn * 8, 256));
+    size_t off = 0;
+    a.phi = (double*)(w + off);
+    off += align_up(nn * 8, 256);
+    a.work = (double*)(w + off);
+    off += align_up(adj_nwork(h) * nn * 8, 256);
+    a.partials = (double*)(w + off);
+    off += align_up(blocks * 3 * 8, 256);
+    if (h->p.model == PFLBM_NL) {
+        a.nlpart = (double*)(w + off);
+        off += align_up(blocks * 4 * 8, 256);
+        a.nls = (double*)(w + off);
+    }
     a.nx = h->p.nx;
     a.ny = h->p.ny;
     a.nz = h->p.nz;
@@ -749,9 +766,23 @@ static int adjoint_run(pflbm_t* h, const double* fwd_g, const double* fwd_h, con
 
 int pflbm_adjoint_seed_phi(pflbm_t* h, const double* dphi, double* lam_g, double* lam_h) {
     if (int st = adjoint_check(h, true)) return st;
+    if (h->p.model == PFLBM_NL)
+        return fail(h, PFLBM_EUNSUPPORTED, "the nonlocal phase field is corrected: use pflbm_adjoint_seed");
     if (!dphi || !lam_g || !lam_h) return fail(h, PFLBM_EINVAL, "null pointer");
     HIPCHK(h, launch_adjoint_seed(dphi, lam_g, lam_h, (long long)adj_nodes(h), h->L.Qg, h->L.Qh, h->stream),
            "adjoint seed kernel");
+    return PFLBM_OK;
+}
+
+int pflbm_adjoint_seed(pflbm_t* h, const double* fwd_h, const double* dphi, double* lam_g, double* lam_h,
+                       double* dparams, void* work) {
+    if (int st = adjoint_check(h, true)) return st;
+    if (h->p.model != PFLBM_NL) return pflbm_adjoint_seed_phi(h, dphi, lam_g, lam_h);
+    if (!fwd_h || !dphi || !lam_g || !lam_h || !work) return fail(h, PFLBM_EINVAL, "null pointer");
+    AdjArgs a;
+    adjoint_args(h, work, a);
+    a.fh = fwd_h;
+    HIPCHK(h, launch_adjoint_seed_nl(h->p.lattice, a, dphi, lam_g, lam_h, dparams, h->stream), "adjoint seed kernels");
     return PFLBM_OK;
 }
 
@@ -771,7 +802,7 @@ int pflbm_adjoint_init(pflbm_t* h, const double* phi0, const double* u0, const d
     a.ny = h->p.ny;
     a.nz = h->p.nz;
     a.ph = h->ph;
-    HIPCHK(h, launch_adjoint_init(h->p.lattice, a, h->stream), "adjoint init kernel");
+    HIPCHK(h, launch_adjoint_init(h->p.lattice, h->p.model, a, h->stream), "adjoint init kernel");
     return PFLBM_OK;
 }
 

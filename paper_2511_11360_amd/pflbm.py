@@ -92,6 +92,7 @@ SIGNATURES = {
     "pflbm_adjoint_seed_phi": (ctypes.c_int, [_P, _P, _P, _P]),
     "pflbm_adjoint_step_noalloc": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "pflbm_adjoint_step_pu": (ctypes.c_int, [_P] * 12),
+    "pflbm_adjoint_seed": (ctypes.c_int, [_P] * 7),
     "pflbm_adjoint_init_pu": (ctypes.c_int, [_P] * 10),
     "pflbm_get_phiu": (ctypes.c_int, [_P, _P]),
     "pflbm_set_phiu": (ctypes.c_int, [_P, _P]),

@@ -131,7 +131,7 @@ class Solver:
     def load_state(self, buf):
         self._check(self.L.pflbm_load_state(self.h, _ptr(buf)), self.h)
 
-    # ---- discrete adjoint (AC and CH models)
+    # ---- discrete adjoint (AC, CH and nonlocal models)
     def adjoint_workspace(self):
         n = ctypes.c_size_t()
         self._check(self.L.pflbm_adjoint_workspace_bytes(self.h, ctypes.byref(n)), self.h)
@@ -166,6 +166,18 @@ class Solver:
         lam_h = torch.empty((self.Qh,) + self.shape, dtype=torch.float64, device=self.device)
         self._keep = (dphi,)
         self._check(self.L.pflbm_adjoint_seed_phi(self.h, _ptr(dphi), _ptr(lam_g), _ptr(lam_h)), self.h)
+        return lam_g, lam_h
+
+    def adjoint_seed(self, fwd_h, dphi, dparams, work):
+        """(lambda_g, lambda_h) of a loss with gradient dphi with respect to the
+        phase field pflbm_fields returns for the state with h = fwd_h; adds the
+        nonlocal correction's M and W terms into dparams (pflbm_adjoint_seed)."""
+        dphi = self._dev(dphi, self.shape)
+        lam_g = torch.empty((self.Qg,) + self.shape, dtype=torch.float64, device=self.device)
+        lam_h = torch.empty((self.Qh,) + self.shape, dtype=torch.float64, device=self.device)
+        self._keep = (dphi,)
+        self._check(self.L.pflbm_adjoint_seed(self.h, _ptr(fwd_h), _ptr(dphi), _ptr(lam_g), _ptr(lam_h),
+                                              _ptr(dparams), _ptr(work)), self.h)
         return lam_g, lam_h
 
     def adjoint_init(self, phi0, u0, p0, lam_g, lam_h):

@@ -116,3 +116,50 @@ def test_ch_init_tangent_matches_central_differences():
         fd = (a.h - b.h) / (2 * dh)
         assert np.max(np.abs(T[1] - fd)) <= 1e-6 * np.max(np.abs(fd)), name
         assert np.max(np.abs(T[0])) == 0.0
+
+
+def _small_nl(lam):
+    """The resolved droplet with the nonlocal phase field (Secs. II.C.3-4):
+    its corrected phi depends on every node through the multiplier gamma."""
+    p, phi, u, target = _small()
+    p = om.Params(**dict(p.__dict__, model="NL", lam=lam))
+    u = u.copy()
+    y = np.arange(phi.shape[1])[None, :, None]
+    u[0] = 0.01 * np.sin(2 * np.pi * (y + 0.5) / phi.shape[1])
+    return p, phi, u, target
+
+
+def test_nl_complex_step_matches_central_differences():
+    for lam in (0.0, 0.9):
+        p, phi, u, target = _small_nl(lam)
+        for name in ("sigma", "M", "W"):
+            cs = dv.cs_param(p, name, phi, u, 8, target)
+            fd = dv.fd_param(p, name, phi, u, 8, target, rel=1e-5)
+            assert abs(cs - fd) <= 1e-6 * abs(cs), (lam, name, cs, fd)
+        v = wl.seeded_field(phi.shape, 7, -1.0, 1.0)
+        cs = dv.cs_phi0(p, v, phi, u, 8, target)
+        h = 1e-5
+        fd = (dv.loss_l2(p, phi + h * v, u, 8, target) - dv.loss_l2(p, phi - h * v, u, 8, target)) / (2 * h)
+        assert abs(cs - fd) <= 1e-6 * abs(cs), lam
+
+
+def test_nl_corrected_phi_tangent_matches_central_differences():
+    """Tangent of the corrected phi* (through gamma, a sum over every node)
+    along h and in M and W."""
+    p, phi, u, _ = _small_nl(0.0)
+    st = om.run(p, om.init(p, phi, u), 3)
+    vh = np.random.default_rng(6).standard_normal(st.h.shape) * 1e-2
+    t = dv.fields_phi_tangent(p, st, vh)
+    e = 1e-6
+    a = om.fields(p, om.State(st.g, st.h + e * vh))[0]
+    b = om.fields(p, om.State(st.g, st.h - e * vh))[0]
+    fd = (a - b) / (2 * e)
+    assert np.max(np.abs(t - fd)) <= 1e-7 * np.max(np.abs(fd))
+    for name in ("M", "W"):
+        t = dv.fields_phi_tangent(p, st, name=name)
+        dh = 1e-6 * getattr(p, name)
+        a = om.fields(om.Params(**dict(p.__dict__, **{name: getattr(p, name) + dh})), st)[0]
+        b = om.fields(om.Params(**dict(p.__dict__, **{name: getattr(p, name) - dh})), st)[0]
+        fd = (a - b) / (2 * dh)
+        assert np.max(np.abs(t - fd)) <= 1e-6 * np.max(np.abs(fd)), name
+    assert np.max(np.abs(dv.fields_phi_tangent(p, st, name="sigma"))) == 0.0
