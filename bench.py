@@ -195,7 +195,8 @@ def time_adjoint(steps, model="AC"):
     chaining lambda through two buffers. Algorithmic bytes per node: lambda
     read and written (2 x 26 x 8), the forward state read (26 x 8), six
     workspace values written and read (2 x 6 x 8); the CH model adds (phi u)
-    to the state (3 x 8 more in each of the three)."""
+    to the state (3 x 8 more in each of the three), the nonlocal model two
+    per-node workspace values (sum h and dL/dR, 2 x 2 x 8)."""
     import torch
     from paper_2511_11360_amd import workloads as wl
     from paper_2511_11360_amd.solver import Solver
@@ -232,7 +233,7 @@ def time_adjoint(steps, model="AC"):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     nodes = d["nx"] * d["ny"] * d["nz"]
-    nb = ADJ_BYTES + (3 * 3 * 8 if ch else 0)
+    nb = ADJ_BYTES + (3 * 3 * 8 if ch else 0) + (2 * 2 * 8 if model == "NL" else 0)
     return {"workload": "3-D sheared droplet, D3Q19+D3Q7, 128^3, walls moving at -+0.02 (adjoint "
                         "of the %s step, float64)" % model,
             "ms_per_step": round(ms, 4), "MLUPS": round(nodes / (ms * 1e-3) / 1e6, 1),
@@ -543,6 +544,9 @@ def main():
         torch.cuda.empty_cache()
         log("adjoint, CH")
         adjoint["ch"] = time_adjoint(100, "CH")
+        torch.cuda.empty_cache()
+        log("adjoint, nonlocal")
+        adjoint["nl"] = time_adjoint(100, "NL")
         torch.cuda.empty_cache()
         if not args.no_backward:
             log("backward pass")
