@@ -61,8 +61,9 @@ template <> struct Types<3> { using T = float;  using GS = uint16_t; using HS = 
 // the rounding is reproducible and independent of the launch shape. The
 // 32-bit integer finaliser "lowbias32" of C. Wellons' hash prospector mixes
 // the node index with the mixed step into the seed of a xorshift32 sequence
-// (G. Marsaglia, "Xorshift RNGs", J. Stat. Softw. 8(14), 2003), which yields
-// one word per population in a fixed order.
+// (G. Marsaglia, "Xorshift RNGs", J. Stat. Softw. 8(14), 2003). A store takes
+// at most 16 random bits (13 for fp16, 16 for bf16), so each word serves two
+// populations in a fixed order: its low half, then its high half.
 __host__ __device__ constexpr uint32_t sr_mix(uint32_t x) {
     x ^= x >> 16;
     x *= 0x7feb352du;
@@ -72,12 +73,20 @@ __host__ __device__ constexpr uint32_t sr_mix(uint32_t x) {
     return x;
 }
 struct SRBits {
-    uint32_t s;
+    uint32_t s, hi = 0;
+    bool have = false;   // hi holds the unused half of the last word
     __device__ __forceinline__ SRBits(uint32_t node, uint32_t step) : s(sr_mix(node ^ sr_mix(step)) | 1u) {}
+    // random bits in the low 16 of the result
     __device__ __forceinline__ uint32_t next() {
+        if (have) {
+            have = false;
+            return hi;
+        }
         s ^= s << 13;
         s ^= s >> 17;
         s ^= s << 5;
+        hi = s >> 16;
+        have = true;
         return s;
     }
 };
