@@ -249,7 +249,7 @@ int pflbm_checkpoint_bytes(const pflbm_t* h, size_t* bytes);
 int pflbm_save_state(pflbm_t* h, void* dev_dst);
 int pflbm_load_state(pflbm_t* h, const void* dev_src);
 
-/* Discrete adjoint (AC, CH and nonlocal models). The adjoint of one time step X^n -> X^{n+1}
+/* Discrete adjoint (AC, CH, nonlocal and Liang2018 models). The adjoint of one time step X^n -> X^{n+1}
    (X = canonical float64 post-streaming distributions, as returned by
    pflbm_get_distributions) given lambda^{n+1} = dL/dX^{n+1}: writes
    lambda^n = dL/dX^n and ADDS dL/d(sigma, M, W) of this step into dparams
@@ -259,25 +259,28 @@ int pflbm_load_state(pflbm_t* h, const void* dev_src);
    pflbm_adjoint_workspace_bytes(). Uses the handle's parameters; float64
    arithmetic whatever the handle's precision. The method's reverse mode is
    not in the paper: it is the exact transpose of the discrete step of
-   Sec. II.C.1 (AC), Sec. II.D.1 (CH) or Secs. II.C.3-4 (nonlocal AC, Eqs.
+   Sec. II.C.1 (AC), Sec. II.D.1 (CH), Secs. II.C.3-4 (nonlocal AC, Eqs.
    nonlocalAC, lagrange_multiplier, Chai_geq, Hu_G, with its global
-   multiplier) as implemented here, on every lattice pair. The CH state also
-   holds (phi u) of the previous step, so the CH model goes through
+   multiplier) or Sec. II.C.2 (Liang2018, Eqs. liang_feq, liang_F_final,
+   liang_velocity_update, liang_p_update, liang_geq, liang_G_final) as
+   implemented here, on every lattice pair. The CH and Liang2018 states also
+   hold (phi u) of the previous step, so those models go through
    pflbm_adjoint_step_pu; pflbm_adjoint_step returns PFLBM_EUNSUPPORTED for
-   it, and both return PFLBM_EUNSUPPORTED for the Liang2018 and Liang2014
-   models and for a frozen phase field. The nonlocal model's workspace is
-   larger (two more per-node arrays). */
+   them, and both return PFLBM_EUNSUPPORTED for the Liang2014 model and for
+   a frozen phase field. The nonlocal model's workspace is larger (two more
+   per-node arrays). */
 int pflbm_adjoint_workspace_bytes(const pflbm_t* h, size_t* bytes);
 int pflbm_adjoint_step(pflbm_t* h, const double* fwd_g, const double* fwd_h,
                        const double* lam_g, const double* lam_h,
                        double* lam_g_out, double* lam_h_out, double* dparams, void* work);
 
 /* The adjoint step with the (phi u) part of the state X = (g, h, pu) of the
-   CH model (Eqs. liang2_geq, liang2_G with the backward-Euler d(phi u)/dt):
+   CH model (Eqs. liang2_geq, liang2_G with the backward-Euler d(phi u)/dt)
+   and of the Liang2018 model (Eq. liang_G_final):
    fwd_pu holds (phi u) of the step before X^n (pflbm_get_phiu), lam_pu its
    adjoint dL/dpu^{n+1}, lam_pu_out receives dL/dpu^n; all [3][z][y][x]
-   device float64, lam_pu_out not aliasing lam_pu. For the AC model the three
-   pu pointers are ignored (may be NULL) and the call equals
+   device float64, lam_pu_out not aliasing lam_pu. For the AC and nonlocal
+   models the three pu pointers are ignored (may be NULL) and the call equals
    pflbm_adjoint_step. */
 int pflbm_adjoint_step_pu(pflbm_t* h, const double* fwd_g, const double* fwd_h, const double* fwd_pu,
                           const double* lam_g, const double* lam_h, const double* lam_pu,
@@ -303,8 +306,9 @@ int pflbm_adjoint_step_noalloc(pflbm_t* h, const double* fwd_g, const double* fw
    dL/dphi [z][y][x] (device float64), writes lambda = dL/dX for that state,
    lam_g [Qg][z][y][x] = 0 and lam_h [Qh][z][y][x] = dL/dphi for every
    population, the transpose of phi = sum_a h_a (Eq. fakhari_phi_update).
-   AC and CH models (PFLBM_EUNSUPPORTED otherwise); for CH the loss does not
-   depend on pu, so lam_pu of that state is zero (the caller's buffer).
+   AC, CH and Liang2018 models (PFLBM_EUNSUPPORTED otherwise); for CH and
+   Liang2018 the loss does not depend on pu, so lam_pu of that state is zero
+   (the caller's buffer).
    Asynchronous. */
 int pflbm_adjoint_seed_phi(pflbm_t* h, const double* dphi, double* lam_g, double* lam_h);
 
@@ -315,8 +319,8 @@ int pflbm_adjoint_seed_phi(pflbm_t* h, const double* dphi, double* lam_g, double
    gamma of Eq. lagrange_multiplier and on M and W through the source R: the
    seed applies its transpose and ADDS the M and W terms into dparams (device
    float64[3], may be NULL); work: workspace of
-   pflbm_adjoint_workspace_bytes(). For the AC and CH models it equals
-   pflbm_adjoint_seed_phi (fwd_h, dparams and work unused). */
+   pflbm_adjoint_workspace_bytes(). For the AC, CH and Liang2018 models it
+   equals pflbm_adjoint_seed_phi (fwd_h, dparams and work unused). */
 int pflbm_adjoint_seed(pflbm_t* h, const double* fwd_h, const double* dphi, double* lam_g, double* lam_h,
                        double* dparams, void* work);
 
@@ -332,7 +336,9 @@ int pflbm_adjoint_init(pflbm_t* h, const double* phi0, const double* u0, const d
    Eq. chemical_potential, on the step's Laplacian stencil), pu^0 = phi0 u0,
    depends on sigma and W through mu_phi: their terms are ADDED into dparams
    (device float64[3], may be NULL). work: workspace of
-   pflbm_adjoint_workspace_bytes(). For the AC model lam_pu, dparams and work
+   pflbm_adjoint_workspace_bytes(). Liang2018: f = f_eq of Eq. liang_feq at
+   rho(phi0), h of Eq. liang_geq, pu^0 = phi0 u0 (no parameter terms; dparams
+   and work unused). For the AC and nonlocal models lam_pu, dparams and work
    are ignored and the call equals pflbm_adjoint_init. */
 int pflbm_adjoint_init_pu(pflbm_t* h, const double* phi0, const double* u0, const double* p0,
                           const double* lam_g, const double* lam_h, const double* lam_pu,

@@ -1,6 +1,7 @@
-// Discrete adjoint of one conservative Allen-Cahn time step (the fused step of
-// kernels.hip, Sec. II.C.1 of the paper), float64, on canonical arrays
-// [q][z][y][x].
+// Discrete adjoint of one time step of the fused step kernel, float64, on
+// canonical arrays [q][z][y][x]: the conservative Allen-Cahn model (Sec.
+// II.C.1 of the paper), and the CH (Sec. II.D.1), nonlocal / hybrid AC (Secs.
+// II.C.3-4) and Liang2018 (Sec. II.C.2) variants.
 //
 // The forward step maps the post-streaming state X^n = (g, h) to X^{n+1}:
 //   phi = sum h;  grad phi, lap phi from phi at x + c_i (periodic image or wall
@@ -560,6 +561,306 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
         for (int k = 0; k < 3; ++k) a.partials[(size_t)wg * 3 + k] = red[k][0];
 }
 
+// pass 2 for Liang2018 (Sec. II.C): its conservative-form hydrodynamics,
+// f_eq of Eq. liang_feq, forcing of Eq. liang_F_final (F = F_s + F_b, with a
+// stress part), rho u = sum e f + F / 2, p of Eq. liang_p_update, and the
+// phase field of Eqs. liang_geq, liang_G_final (backward-Euler d(phi u)/dt:
+// (phi u) of the previous step is part of the state). Same outputs as the
+// other sweeps: dL/dg, dL/dphi, dL/dgrad phi, dL/dlap phi, dL/d(phi u)_prev
+// and the parameter partials.
+template <class PAIR>
+__global__ __launch_bounds__(256, 2) void k_adj_local_l18(const AdjArgs a) {
+    using GL = typename PAIR::G;
+    using HL = typename PAIR::H;
+    constexpr int Q = GL::Q, QH = HL::Q;
+    constexpr bool D3 = PAIR::dim == 3;
+    const long long nn = (long long)a.nx * a.ny * a.nz;
+    const int wg = xcd_block();
+    const long long n = (long long)wg * blockDim.x + threadIdx.x;
+    double th[3] = {0.0, 0.0, 0.0};
+    if (n < nn) {
+        const Node p = node_of(n, a);
+        const Phys& ph = a.ph;
+        double g[Q], h[QH], phin[Q];
+        for (int i = 0; i < Q; ++i) g[i] = a.fg[(size_t)i * nn + n];
+        for (int al = 0; al < QH; ++al) h[al] = a.fh[(size_t)al * nn + n];
+        const Nbr nb(a, p);
+        unroll<Q>([&](auto I) {
+            constexpr int i = I;
+            phin[i] = a.phi[nb.index(GL::c(i, 0), GL::c(i, 1), GL::c(i, 2))];
+        });
+        // ---------------- forward intermediates (as in the step kernel)
+        const double phi = phin[0];
+        double gr[3] = {0.0, 0.0, 0.0}, lap = 0.0;
+        unroll<Q>([&](auto I) {
+            constexpr int i = I;
+            if constexpr (i > 0) {
+                for (int k = 0; k < 3; ++k) gr[k] += 3.0 * GL::w(i) * GL::c(i, k) * phin[i];
+                lap += 6.0 * GL::w(i) * (phin[i] - phi);
+            }
+        });
+        const double dR = ph.dRho;
+        const double rho = ph.rhoL + phi * dR;
+        const double irho = 1.0 / rho;
+        const double numu = ph.muL + phi * ph.dMu;
+        const double nu = ph.visc_mu ? numu * irho : ph.nuL + phi * ph.dNu;
+        const double itau = 1.0 / (3.0 * nu + 0.5);
+        const double cub = phi * (phi - 1.0) * (phi - 0.5);
+        const double mu = ph.beta4 * cub - ph.kappa * lap;
+        double ps = 0.0, j[3] = {0.0, 0.0, 0.0}, m2[3][3] = {{0.0}};
+        unroll<Q>([&](auto I) {
+            constexpr int i = I;
+            ps += g[i];
+            for (int k = 0; k < 3; ++k) {
+                j[k] += GL::c(i, k) * g[i];
+                for (int l = 0; l < 3; ++l) m2[k][l] += GL::c(i, k) * GL::c(i, l) * g[i];
+            }
+        });
+        double F[3], u[3], grho[3], jF[3];
+        for (int k = 0; k < 3; ++k) {
+            F[k] = mu * gr[k] + rho * ph.body[k] + ph.force[k];
+            jF[k] = j[k] + 0.5 * F[k];
+            u[k] = jF[k] * irho;
+            grho[k] = dR * gr[k];
+        }
+        const double udr = u[0] * grho[0] + u[1] * grho[1] + u[2] * grho[2];
+        const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        constexpr double w0 = GL::w(0);
+        constexpr double cp = 1.0 / (3.0 * (1.0 - w0));
+        const double pres = cp * ((ps - g[0]) + 0.5 * udr - 1.5 * rho * w0 * usq);
+        const double so = ph.s_o;
+        const double dS = itau - so;
+        const double fh = 1.0 - 0.5 * so;
+        const double p3 = 3.0 * pres;
+        const double kin0 = -1.5 * rho * usq;
+        double Pi[3][3];
+        for (int k = 0; k < 3; ++k)
+            for (int l = 0; l < 3; ++l)
+                Pi[k][l] = m2[k][l] - rho * u[k] * u[l] + (1.0 / 6.0) * (u[k] * grho[l] + u[l] * grho[k]);
+        constexpr double N0 = stress_norm<GL, D3>(0), N1 = stress_norm<GL, D3>(1),
+                         N2 = stress_norm<GL, D3>(2), N3 = stress_norm<GL, D3>(3),
+                         N4 = stress_norm<GL, D3>(4);
+        double A[5];
+        if constexpr (D3) {
+            A[0] = (2.0 * Pi[0][0] - Pi[1][1] - Pi[2][2]) / N0;
+            A[1] = (Pi[1][1] - Pi[2][2]) / N1;
+            A[2] = Pi[0][1] / N2;
+            A[3] = Pi[1][2] / N3;
+            A[4] = Pi[0][2] / N4;
+        } else {
+            A[0] = (Pi[0][0] - Pi[1][1]) / N0;
+            A[1] = 0.0;
+            A[2] = Pi[0][1] / N2;
+            A[3] = 0.0;
+            A[4] = 0.0;
+        }
+        const double gg = gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2];
+        const double sn = gg + ph.eps2;
+        const double rn = sn > 0.0 ? 1.0 / sqrt(sn) : 0.0;
+        const double pp = phi * (1.0 - phi);
+        const double coef = ph.anti * pp * rn;
+        const double itp = ph.inv_tau_phi, gfp = ph.g_fac_phi;
+        double pu[3], dpu[3];
+        for (int k = 0; k < 3; ++k) {
+            pu[k] = phi * u[k];
+            dpu[k] = pu[k] - a.fpu[(size_t)k * nn + n];
+        }
+
+        // ---------------- reverse sweep; lambda* gathered through the stream transpose
+        double lg[Q], lh[QH];
+        unroll<Q>([&](auto I) {
+            constexpr int i = I;
+            constexpr int cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
+            const size_t e = nb.beyond(cx, cy, cz) ? (size_t)GL::opp(i) * nn + n
+                                                    : (size_t)i * nn + nb.index(cx, cy, cz);
+            lg[i] = a.lg[e];
+        });
+        unroll<QH>([&](auto J) {
+            constexpr int al = J;
+            constexpr int cx = HL::c(al, 0), cy = HL::c(al, 1), cz = HL::c(al, 2);
+            const size_t e = nb.beyond(cx, cy, cz) ? (size_t)HL::opp(al) * nn + n
+                                                    : (size_t)al * nn + nb.index(cx, cy, cz);
+            lh[al] = a.lh[e];
+        });
+        double b_phi = 0.0, b_gr[3] = {0.0, 0.0, 0.0}, b_u[3] = {0.0, 0.0, 0.0};
+        double b_itp = 0.0, b_gfp = 0.0, b_coef = 0.0;
+        // h*_a = (1 - itp) h_a + itp w phi (1 + 3 e.u) + gfp w e.(3 dpu + coef gr)
+        double b_pu[3], b_dpu[3] = {0.0, 0.0, 0.0};
+        for (int k = 0; k < 3; ++k) b_pu[k] = a.lpu[(size_t)k * nn + n];   // (phi u) stored for the next step
+        for (int al = 0; al < QH; ++al) {
+            const double w = HL::w(al);
+            const double ex = HL::c(al, 0), ey = HL::c(al, 1), ez = HL::c(al, 2);
+            const double eu = ex * u[0] + ey * u[1] + ez * u[2];
+            const double eg = ex * gr[0] + ey * gr[1] + ez * gr[2];
+            const double ed = ex * dpu[0] + ey * dpu[1] + ez * dpu[2];
+            const double heq = w * phi * (1.0 + 3.0 * eu);
+            const double G = w * (3.0 * ed + coef * eg);
+            const double lb = lh[al];
+            b_itp += (heq - h[al]) * lb;
+            b_gfp += G * lb;
+            const double bheq = itp * lb, bG = gfp * lb;
+            b_phi += bheq * w * (1.0 + 3.0 * eu);
+            b_u[0] += 3.0 * bheq * w * phi * ex;
+            b_u[1] += 3.0 * bheq * w * phi * ey;
+            b_u[2] += 3.0 * bheq * w * phi * ez;
+            b_dpu[0] += 3.0 * bG * w * ex;
+            b_dpu[1] += 3.0 * bG * w * ey;
+            b_dpu[2] += 3.0 * bG * w * ez;
+            b_coef += bG * w * eg;
+            b_gr[0] += bG * w * coef * ex;
+            b_gr[1] += bG * w * coef * ey;
+            b_gr[2] += bG * w * coef * ez;
+        }
+        // dpu = pu - pu_prev, pu = phi u
+        for (int k = 0; k < 3; ++k) {
+            b_pu[k] += b_dpu[k];
+            a.opu[(size_t)k * nn + n] = -b_dpu[k];
+            b_phi += u[k] * b_pu[k];
+            b_u[k] += phi * b_pu[k];
+        }
+        // coef = anti phi (1 - phi) (gg + eps^2)^(-1/2)
+        const double b_anti = b_coef * pp * rn;
+        b_phi += b_coef * ph.anti * (1.0 - 2.0 * phi) * rn;
+        {
+            const double b_gg = -0.5 * rn * rn * rn * b_coef * ph.anti * pp;
+            for (int k = 0; k < 3; ++k) b_gr[k] += 2.0 * gr[k] * b_gg;
+        }
+        // g*_0 = (1 - so) g_0 + so (p3 (w0 - 1) + w0 kin0)
+        double b_g[Q];
+        double b_p3 = so * (w0 - 1.0) * lg[0], b_kin0 = so * w0 * lg[0];
+        double b_rho = 0.0, b_dS = 0.0, b_A[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        double b_F[3] = {0.0, 0.0, 0.0}, b_grho[3] = {0.0, 0.0, 0.0};
+        b_g[0] = (1.0 - so) * lg[0];
+        // g*_i = (1 - so) g_i + so E_i + fh Fe_i - dS P_i + (so O_i + fh Fo_i), with
+        // E = w (p3 + kin0 + 4.5 rho cu^2), O = 3 w rho (c.u) (of opposite sign
+        // at opp(i)), Fe = 3 w (c.u)(c.grad rho), Fo = 3 w c.F
+        for (int i = 1; i < Q; ++i) {
+            const double w = GL::w(i);
+            const double cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
+            const double cu = cx * u[0] + cy * u[1] + cz * u[2];
+            const double cr = cx * grho[0] + cy * grho[1] + cz * grho[2];
+            double q[5];
+            for (int k = 0; k < 5; ++k) q[k] = stress_row<GL, D3>(k, i);
+            double P = 0.0;
+            for (int k = 0; k < 5; ++k) P += q[k] * A[k];
+            const double lb = lg[i];
+            b_g[i] = (1.0 - so) * lb;
+            const double bE = so * lb, bFe = fh * lb, bO = so * lb, bFo = fh * lb;
+            b_p3 += w * bE;
+            b_kin0 += w * bE;
+            b_rho += 4.5 * w * cu * cu * bE + 3.0 * w * cu * bO;
+            const double b_cu = 9.0 * w * rho * cu * bE + 3.0 * w * rho * bO + 3.0 * w * cr * bFe;
+            const double b_cr = 3.0 * w * cu * bFe;
+            b_u[0] += cx * b_cu;
+            b_u[1] += cy * b_cu;
+            b_u[2] += cz * b_cu;
+            b_grho[0] += cx * b_cr;
+            b_grho[1] += cy * b_cr;
+            b_grho[2] += cz * b_cr;
+            b_F[0] += 3.0 * w * cx * bFo;
+            b_F[1] += 3.0 * w * cy * bFo;
+            b_F[2] += 3.0 * w * cz * bFo;
+            for (int k = 0; k < 5; ++k) b_A[k] += -dS * q[k] * lb;
+            b_dS += -P * lb;
+        }
+        // A (linear in Pi), Pi_kl = m2_kl - rho u_k u_l + (u_k grho_l + u_l grho_k) / 6
+        double b_Pi[3][3] = {{0.0}};
+        if constexpr (D3) {
+            b_Pi[0][0] = 2.0 * b_A[0] / N0;
+            b_Pi[1][1] = -b_A[0] / N0 + b_A[1] / N1;
+            b_Pi[2][2] = -b_A[0] / N0 - b_A[1] / N1;
+            b_Pi[0][1] = b_A[2] / N2;
+            b_Pi[1][2] = b_A[3] / N3;
+            b_Pi[0][2] = b_A[4] / N4;
+        } else {
+            b_Pi[0][0] = b_A[0] / N0;
+            b_Pi[1][1] = -b_A[0] / N0;
+            b_Pi[0][1] = b_A[2] / N2;
+        }
+        double b_m2[3][3] = {{0.0}};
+        for (int k = 0; k < 3; ++k)
+            for (int l = k; l < 3; ++l) {
+                const double b = b_Pi[k][l];
+                b_m2[k][l] += b;
+                b_rho += -u[k] * u[l] * b;
+                b_u[k] += (-rho * u[l] + grho[l] / 6.0) * b;
+                b_u[l] += (-rho * u[k] + grho[k] / 6.0) * b;
+                b_grho[l] += u[k] / 6.0 * b;
+                b_grho[k] += u[l] / 6.0 * b;
+            }
+        // kin0 = -1.5 rho usq ; p3 = 3 p ; p = cp ((ps - g0) + udr / 2 - 1.5 rho w0 usq)
+        double b_usq = -1.5 * rho * b_kin0;
+        b_rho += -1.5 * usq * b_kin0;
+        const double b_pres = 3.0 * b_p3;
+        double b_ps = cp * b_pres;
+        b_g[0] += -cp * b_pres;
+        const double b_udr = 0.5 * cp * b_pres;
+        b_rho += -1.5 * w0 * usq * cp * b_pres;
+        b_usq += -1.5 * rho * w0 * cp * b_pres;
+        for (int k = 0; k < 3; ++k) {
+            b_u[k] += 2.0 * u[k] * b_usq + grho[k] * b_udr;
+            b_grho[k] += u[k] * b_udr;
+        }
+        // u = (j + F / 2) irho ; grho = dR gr ; F = mu gr + rho body + force
+        double b_j[3], b_irho = 0.0, b_mu = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            b_j[k] = irho * b_u[k];
+            b_F[k] += 0.5 * irho * b_u[k];
+            b_irho += jF[k] * b_u[k];
+            b_gr[k] += dR * b_grho[k];
+            b_mu += gr[k] * b_F[k];
+            b_gr[k] += mu * b_F[k];
+            b_rho += ph.body[k] * b_F[k];
+        }
+        // moments
+        for (int i = 0; i < Q; ++i) {
+            double b = b_ps;
+            for (int k = 0; k < 3; ++k) {
+                b += GL::c(i, k) * b_j[k];
+                for (int l = k; l < 3; ++l) b += GL::c(i, k) * GL::c(i, l) * b_m2[k][l];
+            }
+            b_g[i] += b;
+        }
+        // mu = beta4 phi (phi - 1)(phi - 1/2) - kappa lap
+        const double b_beta4 = b_mu * cub, b_kappa = -b_mu * lap;
+        const double b_lap = -ph.kappa * b_mu;
+        b_phi += b_mu * ph.beta4 * (3.0 * phi * phi - 3.0 * phi + 0.5);
+        // itau = 1 / (3 nu + 1/2), dS = itau - so ; nu ; irho ; rho
+        const double b_nu = 3.0 * (-itau * itau * b_dS);
+        if (ph.visc_mu) {
+            b_phi += ph.dMu * irho * b_nu;
+            b_irho += numu * b_nu;
+        } else {
+            b_phi += ph.dNu * b_nu;
+        }
+        b_rho += -irho * irho * b_irho;
+        b_phi += dR * b_rho;
+        // parameters: beta4 = 48 sigma / W, kappa = 1.5 sigma W, anti = 4 / W,
+        // itp = 1 / (3 M + 1/2), gfp = 1 - itp / 2
+        const double sigma = a.sigma, W = a.W;
+        th[0] = b_beta4 * 48.0 / W + b_kappa * 1.5 * W;
+        th[1] = -3.0 * itp * itp * (b_itp - 0.5 * b_gfp);
+        th[2] = -b_beta4 * 48.0 * sigma / (W * W) + b_kappa * 1.5 * sigma - b_anti * 4.0 / (W * W);
+
+        for (int i = 0; i < Q; ++i) a.og[(size_t)i * nn + n] = b_g[i];
+        a.work[n] = b_phi;
+        a.work[nn + n] = b_gr[0];
+        a.work[2 * nn + n] = b_gr[1];
+        a.work[3 * nn + n] = b_gr[2];
+        a.work[4 * nn + n] = b_lap;
+    }
+    __shared__ double red[3][256];
+    for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = th[k];
+    __syncthreads();
+    for (int s = 128; s >= 1; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 3; ++k) a.partials[(size_t)wg * 3 + k] = red[k][0];
+}
+
 // pass 3: transpose of grad phi(x) = 3 sum w c phi(src(x, i)) and
 // lap phi(x) = 6 sum w (phi(src(x, i)) - phi(x)), src = periodic image or wall
 // mirror of x + c_i, as a gather at y over {x : src(x, i) = y}; every h
@@ -794,7 +1095,7 @@ __global__ __launch_bounds__(256) void k_adj_nl_final(const AdjArgs a, double* l
 }
 
 // dL/dphi0 through the equilibrium initialisation h = h_eq(phi0, u0),
-// g = g_eq(3 p0 / rho(phi0), u0); MODEL 0 AC, 2 nonlocal
+// g = g_eq(3 p0 / rho(phi0), u0); MODEL 0 AC, 2 nonlocal, 3 Liang2018
 template <class PAIR, int MODEL>
 __global__ __launch_bounds__(256) void k_adj_init(const AdjInitArgs a) {
     using GL = typename PAIR::G;
@@ -812,11 +1113,21 @@ __global__ __launch_bounds__(256) void k_adj_init(const AdjInitArgs a) {
     double s = 0.0;
     for (int al = 0; al < HL::Q; ++al) {
         const double eu = HL::c(al, 0) * u[0] + HL::c(al, 1) * u[1] + HL::c(al, 2) * u[2];
-        // Eq. fakhari_geq (AC) or Eq. Chai_geq (nonlocal: first order in u)
-        const double dh = MODEL == 2 ? 1.0 + 3.0 * eu : 1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * usq;
+        // Eq. fakhari_geq (AC) or Eqs. Chai_geq, liang_geq (first order in u)
+        const double dh = MODEL == 2 || MODEL == 3 ? 1.0 + 3.0 * eu : 1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * usq;
         s += a.lh[(size_t)al * nn + n] * HL::w(al) * dh;
     }
-    if (a.p0) {
+    if constexpr (MODEL == 3) {
+        // Eq. liang_feq: (p0/c_s^2)(w - [i = 0]) + rho(phi0) w (3 c.u + 4.5 (c.u)^2
+        // - 1.5 u.u); (phi u) = phi0 u0
+        double sg = 0.0;
+        for (int i = 0; i < GL::Q; ++i) {
+            const double cu = GL::c(i, 0) * u[0] + GL::c(i, 1) * u[1] + GL::c(i, 2) * u[2];
+            sg += a.lg[(size_t)i * nn + n] * GL::w(i) * (3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+        }
+        s += a.ph.dRho * sg;
+        for (int k = 0; k < 3; ++k) s += a.lpu[(size_t)k * nn + n] * u[k];
+    } else if (a.p0) {
         const double phi = a.phi0[n];
         const double rho = a.ph.rhoL + phi * a.ph.dRho;
         const double dps = -3.0 * a.p0[n] * a.ph.dRho / (rho * rho);
@@ -937,6 +1248,7 @@ hipError_t launch_adjoint(int lattice, int model, const AdjArgs& a, double* dpar
             return;
         }
         if (model == 1) hipLaunchKernelGGL((k_adj_local<P_, 1>), grid, block, 0, st, a);
+        else if (model == 3) hipLaunchKernelGGL((k_adj_local_l18<P_>), grid, block, 0, st, a);
         else hipLaunchKernelGGL((k_adj_local<P_, 0>), grid, block, 0, st, a);
         hipLaunchKernelGGL((k_adj_stencil<P_, ST_STEP>), grid, block, 0, st, a);
     };
@@ -953,6 +1265,7 @@ hipError_t launch_adjoint_init(int lattice, int model, const AdjInitArgs& a, hip
     auto go = [&](auto pair) {
         using P_ = decltype(pair);
         if (model == 2) hipLaunchKernelGGL((k_adj_init<P_, 2>), grid, block, 0, st, a);
+        else if (model == 3) hipLaunchKernelGGL((k_adj_init<P_, 3>), grid, block, 0, st, a);
         else hipLaunchKernelGGL((k_adj_init<P_, 0>), grid, block, 0, st, a);
     };
     if (lattice == 0) go(Pair2D{});

@@ -143,7 +143,7 @@ struct GammaArgs {
     double w32;            // 4 beta / kappa
 };
 
-// discrete adjoint of one AC step on canonical float64 arrays [q][z][y][x]
+// discrete adjoint of one step on canonical float64 arrays [q][z][y][x]
 struct AdjArgs {
     const double* fg;      // forward state X^n (post-streaming)
     const double* fh;
@@ -170,6 +170,7 @@ struct AdjArgs {
 struct AdjInitArgs {
     const double* lg;
     const double* lh;
+    const double* lpu;     // Liang2018: lambda of (phi u) [3][nodes]
     const double* phi0;
     const double* u0;      // may be null
     const double* p0;      // may be null

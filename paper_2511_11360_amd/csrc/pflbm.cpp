@@ -660,10 +660,10 @@ int pflbm_adjoint_workspace_bytes(const pflbm_t* h, size_t* bytes) {
 static int adjoint_check(pflbm_t* h, bool with_pu) {
     int st = guard(h);
     if (st) return st;
-    if (h->p.model != PFLBM_AC && h->p.model != PFLBM_CH && h->p.model != PFLBM_NL)
-        return fail(h, PFLBM_EUNSUPPORTED, "adjoint implemented for the AC, CH and nonlocal models only");
-    if (h->p.model == PFLBM_CH && !with_pu)
-        return fail(h, PFLBM_EUNSUPPORTED, "the CH adjoint carries (phi u): use the _pu entry points");
+    if (h->p.model == PFLBM_L14)
+        return fail(h, PFLBM_EUNSUPPORTED, "adjoint not implemented for the Liang2014 model");
+    if ((h->p.model == PFLBM_CH || h->p.model == PFLBM_L18) && !with_pu)
+        return fail(h, PFLBM_EUNSUPPORTED, "the CH and Liang2018 adjoints carry (phi u): use the _pu entry points");
     if (h->p.freeze_phi) return fail(h, PFLBM_EUNSUPPORTED, "adjoint of a frozen phase field is not implemented");
     return PFLBM_OK;
 }
@@ -686,7 +686,7 @@ int pflbm_adjoint_step_pu(pflbm_t* h, const double* fwd_g, const double* fwd_h, 
                           double* lam_h_out, double* lam_pu_out, double* dparams, void* work) {
     if (int st = adjoint_check(h, true)) return st;
     if (!work) return fail(h, PFLBM_EINVAL, "null pointer");
-    if (h->p.model != PFLBM_CH) {
+    if (h->p.model != PFLBM_CH && h->p.model != PFLBM_L18) {
         fwd_pu = lam_pu = nullptr;
         lam_pu_out = nullptr;
     } else {
@@ -810,6 +810,25 @@ int pflbm_adjoint_init_pu(pflbm_t* h, const double* phi0, const double* u0, cons
                           const double* lam_g, const double* lam_h, const double* lam_pu, double* dphi0,
                           double* dparams, void* work) {
     if (int st = adjoint_check(h, true)) return st;
+    if (h->p.model == PFLBM_L18) {
+        // Eq. liang_feq and h_eq of Eq. liang_geq do not depend on sigma, M, W
+        if (!phi0 || !lam_g || !lam_h || !lam_pu || !dphi0) return fail(h, PFLBM_EINVAL, "null pointer");
+        AdjInitArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.lg = lam_g;
+        a.lh = lam_h;
+        a.lpu = lam_pu;
+        a.phi0 = phi0;
+        a.u0 = u0;
+        a.p0 = p0;
+        a.dphi0 = dphi0;
+        a.nx = h->p.nx;
+        a.ny = h->p.ny;
+        a.nz = h->p.nz;
+        a.ph = h->ph;
+        HIPCHK(h, launch_adjoint_init(h->p.lattice, h->p.model, a, h->stream), "adjoint init kernel");
+        return PFLBM_OK;
+    }
     if (h->p.model != PFLBM_CH) return pflbm_adjoint_init(h, phi0, u0, p0, lam_g, lam_h, dphi0);
     if (!phi0 || !lam_g || !lam_h || !lam_pu || !dphi0 || !work) return fail(h, PFLBM_EINVAL, "null pointer");
     AdjArgs a;
