@@ -249,7 +249,7 @@ int pflbm_checkpoint_bytes(const pflbm_t* h, size_t* bytes);
 int pflbm_save_state(pflbm_t* h, void* dev_dst);
 int pflbm_load_state(pflbm_t* h, const void* dev_src);
 
-/* Discrete adjoint (AC, CH, nonlocal and Liang2018 models). The adjoint of one time step X^n -> X^{n+1}
+/* Discrete adjoint (every model). The adjoint of one time step X^n -> X^{n+1}
    (X = canonical float64 post-streaming distributions, as returned by
    pflbm_get_distributions) given lambda^{n+1} = dL/dX^{n+1}: writes
    lambda^n = dL/dX^n and ADDS dL/d(sigma, M, W) of this step into dparams
@@ -261,22 +261,24 @@ int pflbm_load_state(pflbm_t* h, const void* dev_src);
    not in the paper: it is the exact transpose of the discrete step of
    Sec. II.C.1 (AC), Sec. II.D.1 (CH), Secs. II.C.3-4 (nonlocal AC, Eqs.
    nonlocalAC, lagrange_multiplier, Chai_geq, Hu_G, with its global
-   multiplier) or Sec. II.C.2 (Liang2018, Eqs. liang_feq, liang_F_final,
-   liang_velocity_update, liang_p_update, liang_geq, liang_G_final) as
-   implemented here, on every lattice pair. The CH and Liang2018 states also
+   multiplier), Sec. II.C.2 (Liang2018, Eqs. liang_feq, liang_F_final,
+   liang_velocity_update, liang_p_update, liang_geq, liang_G_final) or Sec.
+   II.D.1 with its hydrodynamics (Liang2014, Eqs. liang2_feq, liang2_F,
+   liang2014_velocity_update, whose F_a reads lap mu_phi) as implemented
+   here, on every lattice pair. The CH, Liang2018 and Liang2014 states also
    hold (phi u) of the previous step, so those models go through
    pflbm_adjoint_step_pu; pflbm_adjoint_step returns PFLBM_EUNSUPPORTED for
-   them, and both return PFLBM_EUNSUPPORTED for the Liang2014 model and for
-   a frozen phase field. The nonlocal model's workspace is larger (two more
-   per-node arrays). */
+   them, and both return PFLBM_EUNSUPPORTED for a frozen phase field. The
+   nonlocal model's workspace holds two more per-node arrays, Liang2014's
+   four more. */
 int pflbm_adjoint_workspace_bytes(const pflbm_t* h, size_t* bytes);
 int pflbm_adjoint_step(pflbm_t* h, const double* fwd_g, const double* fwd_h,
                        const double* lam_g, const double* lam_h,
                        double* lam_g_out, double* lam_h_out, double* dparams, void* work);
 
 /* The adjoint step with the (phi u) part of the state X = (g, h, pu) of the
-   CH model (Eqs. liang2_geq, liang2_G with the backward-Euler d(phi u)/dt)
-   and of the Liang2018 model (Eq. liang_G_final):
+   CH and Liang2014 models (Eqs. liang2_geq, liang2_G with the backward-Euler
+   d(phi u)/dt) and of the Liang2018 model (Eq. liang_G_final):
    fwd_pu holds (phi u) of the step before X^n (pflbm_get_phiu), lam_pu its
    adjoint dL/dpu^{n+1}, lam_pu_out receives dL/dpu^n; all [3][z][y][x]
    device float64, lam_pu_out not aliasing lam_pu. For the AC and nonlocal
@@ -306,9 +308,10 @@ int pflbm_adjoint_step_noalloc(pflbm_t* h, const double* fwd_g, const double* fw
    dL/dphi [z][y][x] (device float64), writes lambda = dL/dX for that state,
    lam_g [Qg][z][y][x] = 0 and lam_h [Qh][z][y][x] = dL/dphi for every
    population, the transpose of phi = sum_a h_a (Eq. fakhari_phi_update).
-   AC, CH and Liang2018 models (PFLBM_EUNSUPPORTED otherwise); for CH and
-   Liang2018 the loss does not depend on pu, so lam_pu of that state is zero
-   (the caller's buffer).
+   every model but the nonlocal one (PFLBM_EUNSUPPORTED there: its phase
+   field is corrected, use pflbm_adjoint_seed); for the models with a (phi u)
+   state the loss does not depend on pu, so lam_pu of that state is zero (the
+   caller's buffer).
    Asynchronous. */
 int pflbm_adjoint_seed_phi(pflbm_t* h, const double* dphi, double* lam_g, double* lam_h);
 
@@ -319,8 +322,8 @@ int pflbm_adjoint_seed_phi(pflbm_t* h, const double* dphi, double* lam_g, double
    gamma of Eq. lagrange_multiplier and on M and W through the source R: the
    seed applies its transpose and ADDS the M and W terms into dparams (device
    float64[3], may be NULL); work: workspace of
-   pflbm_adjoint_workspace_bytes(). For the AC, CH and Liang2018 models it
-   equals pflbm_adjoint_seed_phi (fwd_h, dparams and work unused). */
+   pflbm_adjoint_workspace_bytes(). For the other models it equals
+   pflbm_adjoint_seed_phi (fwd_h, dparams and work unused). */
 int pflbm_adjoint_seed(pflbm_t* h, const double* fwd_h, const double* dphi, double* lam_g, double* lam_h,
                        double* dparams, void* work);
 
@@ -332,9 +335,10 @@ int pflbm_adjoint_init(pflbm_t* h, const double* phi0, const double* u0, const d
                        const double* lam_g, const double* lam_h, double* dphi0);
 
 /* The same with the (phi u) part: lam_pu = dL/dpu^0 [3][z][y][x]. The CH
-   initialisation h = h_eq(phi0, mu_phi(phi0), u0) (Eq. liang2_geq, mu_phi of
-   Eq. chemical_potential, on the step's Laplacian stencil), pu^0 = phi0 u0,
-   depends on sigma and W through mu_phi: their terms are ADDED into dparams
+   (and Liang2014) initialisation h = h_eq(phi0, mu_phi(phi0), u0) (Eq.
+   liang2_geq, mu_phi of Eq. chemical_potential, on the step's Laplacian
+   stencil), pu^0 = phi0 u0 (Liang2014: f = f_eq of Eq. liang2_feq at
+   rho(phi0)), depends on sigma and W through mu_phi: their terms are ADDED into dparams
    (device float64[3], may be NULL). work: workspace of
    pflbm_adjoint_workspace_bytes(). Liang2018: f = f_eq of Eq. liang_feq at
    rho(phi0), h of Eq. liang_geq, pu^0 = phi0 u0 (no parameter terms; dparams

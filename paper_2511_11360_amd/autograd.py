@@ -21,8 +21,8 @@ class PhaseFieldRun(torch.autograd.Function):
     def forward(ctx, phi0, sigma, M, W, params, u0, nsteps, precision, k):
         d = dict(params)
         d["sigma"], d["M"], d["W"] = float(sigma), float(M), float(W)
-        if d.get("model", "AC") not in ("AC", "CH", "NL", "L18"):
-            raise ValueError("the adjoint is implemented for the AC, CH, nonlocal and Liang2018 models only")
+        if d.get("model", "AC") not in ("AC", "CH", "NL", "L18", "L14"):
+            raise ValueError("unknown phase-field model %r" % d.get("model"))
         s = Solver(d, precision=precision, device=phi0.device)
         s.init(phi0, u0)
         nsteps = int(nsteps)
@@ -50,9 +50,9 @@ class PhaseFieldRun(torch.autograd.Function):
         (phi0,) = ctx.saved_tensors
         dev = s.device
         shape = s.shape
-        # the CH and Liang2018 states also hold (phi u) of the previous step;
-        # L depends on phi alone, so its adjoint starts at zero
-        ch = s.d.get("model", "AC") in ("CH", "L18")
+        # the CH and Liang states also hold (phi u) of the previous step; L
+        # depends on phi alone, so its adjoint starts at zero
+        ch = s.d.get("model", "AC") in ("CH", "L18", "L14")
         lam_pu = torch.zeros((3,) + shape, dtype=torch.float64, device=dev) if ch else None
         out_pu = torch.empty_like(lam_pu) if ch else None
         dparams = torch.zeros(3, dtype=torch.float64, device=dev)

@@ -861,6 +861,403 @@ __global__ __launch_bounds__(256, 2) void k_adj_local_l18(const AdjArgs a) {
         for (int k = 0; k < 3; ++k) a.partials[(size_t)wg * 3 + k] = red[k][0];
 }
 
+// ---------------------------------------------------------------------------
+// Liang2014 (Sec. II.D.1): the CH phase field with its own hydrodynamics,
+// which read lap(mu_phi) (Eqs. liang2014_velocity_update, liang2_F with F_a),
+// a stencil of the field mu_phi = 4 beta phi (phi - 1)(phi - 1/2) - kappa
+// lap phi. Passes: phi; mu_phi and lap phi of every node; the reverse sweep,
+// which leaves dL/dmu_phi and dL/d(lap mu_phi) of each node; the transpose of
+// the mu_phi stencil (a gather, as the phi stencils), which turns them into
+// dL/dphi and dL/dlap phi of each node plus the sigma and W terms; then the
+// shared stencil transpose and parameter reduction. Workspace values: 0
+// dL/dphi, 1-3 dL/dgrad phi, 4 dL/dlap phi, 5 mu_phi, 6 lap phi, 7 dL/dmu_phi,
+// 8 dL/dlap mu_phi.
+
+template <class PAIR>
+__global__ __launch_bounds__(256) void k_adj_mu_fwd(const AdjArgs a) {
+    using GL = typename PAIR::G;
+    const long long nn = (long long)a.nx * a.ny * a.nz;
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    const Nbr nb(a, node_of(n, a));
+    const double phi = a.phi[n];
+    double lap = 0.0;
+    unroll<GL::Q - 1>([&](auto I) {
+        constexpr int i = I + 1;
+        lap += 6.0 * GL::w(i) * (a.phi[nb.index(GL::c(i, 0), GL::c(i, 1), GL::c(i, 2))] - phi);
+    });
+    a.work[5 * nn + n] = a.ph.beta4 * phi * (phi - 1.0) * (phi - 0.5) - a.ph.kappa * lap;
+    a.work[6 * nn + n] = lap;
+}
+
+template <class PAIR>
+__global__ __launch_bounds__(256, 2) void k_adj_local_l14(const AdjArgs a) {
+    using GL = typename PAIR::G;
+    using HL = typename PAIR::H;
+    constexpr int Q = GL::Q, QH = HL::Q;
+    constexpr bool D3 = PAIR::dim == 3;
+    const long long nn = (long long)a.nx * a.ny * a.nz;
+    const int wg = xcd_block();
+    const long long n = (long long)wg * blockDim.x + threadIdx.x;
+    double thM = 0.0;
+    if (n < nn) {
+        const Node p = node_of(n, a);
+        const Phys& ph = a.ph;
+        const double* MU = a.work + 5 * nn;
+        double g[Q], h[QH], phin[Q], mun[Q];
+        for (int i = 0; i < Q; ++i) g[i] = a.fg[(size_t)i * nn + n];
+        for (int al = 0; al < QH; ++al) h[al] = a.fh[(size_t)al * nn + n];
+        const Nbr nb(a, p);
+        unroll<Q>([&](auto I) {
+            constexpr int i = I;
+            const long long e = nb.index(GL::c(i, 0), GL::c(i, 1), GL::c(i, 2));
+            phin[i] = a.phi[e];
+            mun[i] = MU[e];
+        });
+        // ---------------- forward intermediates (as in the step kernel)
+        const double phi = phin[0], mu = mun[0];
+        double gr[3] = {0.0, 0.0, 0.0}, lapmu = 0.0;
+        unroll<Q>([&](auto I) {
+            constexpr int i = I;
+            if constexpr (i > 0) {
+                for (int k = 0; k < 3; ++k) gr[k] += 3.0 * GL::w(i) * GL::c(i, k) * phin[i];
+                lapmu += 6.0 * GL::w(i) * (mun[i] - mu);
+            }
+        });
+        const double dR = ph.dRho;
+        const double rho = ph.rhoL + phi * dR;
+        const double irho = 1.0 / rho;
+        const double numu = ph.muL + phi * ph.dMu;
+        const double nu = ph.visc_mu ? numu * irho : ph.nuL + phi * ph.dNu;
+        const double itau = 1.0 / (3.0 * nu + 0.5);
+        double ps = 0.0, j[3] = {0.0, 0.0, 0.0}, m2[3][3] = {{0.0}};
+        unroll<Q>([&](auto I) {
+            constexpr int i = I;
+            ps += g[i];
+            for (int k = 0; k < 3; ++k) {
+                j[k] += GL::c(i, k) * g[i];
+                for (int l = 0; l < 3; ++l) m2[k][l] += GL::c(i, k) * GL::c(i, l) * g[i];
+            }
+        });
+        const double dM = dR * ph.mob * lapmu;
+        const double den = rho - 0.5 * dM;
+        const double iden = 1.0 / den;
+        double fsb[3], jf[3], u[3], Fp[3], grho[3], Av[3], B[3];
+        for (int k = 0; k < 3; ++k) {
+            fsb[k] = mu * gr[k] + rho * ph.body[k] + ph.force[k];
+            jf[k] = j[k] + 0.5 * fsb[k];
+            u[k] = jf[k] * iden;
+            Fp[k] = fsb[k] + dM * u[k];
+            grho[k] = dR * gr[k];
+            Av[k] = grho[k] / 3.0;
+            B[k] = Av[k] + Fp[k];
+        }
+        const double udr = u[0] * grho[0] + u[1] * grho[1] + u[2] * grho[2];
+        const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        const double uB = u[0] * B[0] + u[1] * B[1] + u[2] * B[2];
+        const double uA = u[0] * Av[0] + u[1] * Av[1] + u[2] * Av[2];
+        const double uF = u[0] * Fp[0] + u[1] * Fp[1] + u[2] * Fp[2];
+        constexpr double w0 = GL::w(0);
+        constexpr double cp = 1.0 / (3.0 * (1.0 - w0));
+        const double pres = cp * ((ps - g[0]) + 0.5 * udr - 1.5 * rho * w0 * usq);
+        const double so = ph.s_o;
+        const double dS = itau - so;
+        const double fh = 1.0 - 0.5 * so;
+        const double p3 = 3.0 * pres;
+        const double kin0 = -1.5 * rho * usq;
+        double Pi[3][3];
+        for (int k = 0; k < 3; ++k)
+            for (int l = 0; l < 3; ++l)
+                Pi[k][l] = m2[k][l] - rho * u[k] * u[l] + 0.5 * (B[k] * u[l] + B[l] * u[k] - 3.0 * uB * u[k] * u[l]);
+        constexpr double N0 = stress_norm<GL, D3>(0), N1 = stress_norm<GL, D3>(1),
+                         N2 = stress_norm<GL, D3>(2), N3 = stress_norm<GL, D3>(3),
+                         N4 = stress_norm<GL, D3>(4);
+        double A[5];
+        if constexpr (D3) {
+            A[0] = (2.0 * Pi[0][0] - Pi[1][1] - Pi[2][2]) / N0;
+            A[1] = (Pi[1][1] - Pi[2][2]) / N1;
+            A[2] = Pi[0][1] / N2;
+            A[3] = Pi[1][2] / N3;
+            A[4] = Pi[0][2] / N4;
+        } else {
+            A[0] = (Pi[0][0] - Pi[1][1]) / N0;
+            A[1] = 0.0;
+            A[2] = Pi[0][1] / N2;
+            A[3] = 0.0;
+            A[4] = 0.0;
+        }
+        const double itp = ph.inv_tau_phi, gfp = ph.g_fac_phi;
+
+        // ---------------- reverse sweep; lambda* gathered through the stream transpose
+        double lg[Q], lh[QH];
+        unroll<Q>([&](auto I) {
+            constexpr int i = I;
+            constexpr int cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
+            const size_t e = nb.beyond(cx, cy, cz) ? (size_t)GL::opp(i) * nn + n
+                                                    : (size_t)i * nn + nb.index(cx, cy, cz);
+            lg[i] = a.lg[e];
+        });
+        unroll<QH>([&](auto J) {
+            constexpr int al = J;
+            constexpr int cx = HL::c(al, 0), cy = HL::c(al, 1), cz = HL::c(al, 2);
+            const size_t e = nb.beyond(cx, cy, cz) ? (size_t)HL::opp(al) * nn + n
+                                                    : (size_t)al * nn + nb.index(cx, cy, cz);
+            lh[al] = a.lh[e];
+        });
+        double b_phi = 0.0, b_u[3] = {0.0, 0.0, 0.0}, b_mu = 0.0;
+        double b_itp = 0.0, b_gfp = 0.0;
+        // h: the CH collision (Eqs. liang2_geq, liang2_G) with this model's u
+        {
+            double pu[3], pup[3], b_pu[3], b_pup[3] = {0.0, 0.0, 0.0};
+            for (int k = 0; k < 3; ++k) {
+                pu[k] = phi * u[k];
+                pup[k] = a.fpu[(size_t)k * nn + n];
+                b_pu[k] = a.lpu[(size_t)k * nn + n];
+            }
+            unroll<QH>([&](auto J) {
+                constexpr int al = J;
+                constexpr double w = HL::w(al);
+                constexpr int ex = HL::c(al, 0), ey = HL::c(al, 1), ez = HL::c(al, 2);
+                const double lb = lh[al];
+                const double bheq = itp * lb;
+                double heq, G = 0.0;
+                if constexpr (al == 0) {
+                    heq = phi + (w - 1.0) * ph.eta * mu;
+                    b_phi += bheq;
+                    b_mu += (w - 1.0) * ph.eta * bheq;
+                } else {
+                    const double ep = ex * pu[0] + ey * pu[1] + ez * pu[2];
+                    const double eq = ex * pup[0] + ey * pup[1] + ez * pup[2];
+                    heq = w * ph.eta * mu + 3.0 * w * ep;
+                    G = 3.0 * w * (ep - eq);
+                    b_mu += w * ph.eta * bheq;
+                    const double t = 3.0 * w * (bheq + gfp * lb);
+                    const double tp = 3.0 * w * gfp * lb;
+                    b_pu[0] += ex * t;
+                    b_pu[1] += ey * t;
+                    b_pu[2] += ez * t;
+                    b_pup[0] -= ex * tp;
+                    b_pup[1] -= ey * tp;
+                    b_pup[2] -= ez * tp;
+                }
+                b_itp += (heq - h[al]) * lb;
+                b_gfp += G * lb;
+            });
+            for (int k = 0; k < 3; ++k) {
+                b_phi += u[k] * b_pu[k];
+                b_u[k] += phi * b_pu[k];
+                a.opu[(size_t)k * nn + n] = b_pup[k];
+            }
+        }
+        // f*_i = (1 - so) f_i + so feq_i + fh F_i - dS P_i with
+        // feq_i = w (p3 + kin0 + 4.5 rho cu^2 + 3 rho cu) - [i = 0] p3,
+        // F_i = 3 ((c.A - u.A) Gam_i + (c.F' - u.F')(w + Gam_i)),
+        // Gam_i = w (3 cu + 4.5 cu^2 - 1.5 u.u)
+        double b_g[Q];
+        double b_p3 = 0.0, b_kin0 = 0.0, b_rho = 0.0, b_dS = 0.0, b_usq = 0.0;
+        double b_uA = 0.0, b_uF = 0.0, b_A[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        double b_Fp[3] = {0.0, 0.0, 0.0}, b_Av[3] = {0.0, 0.0, 0.0};
+        for (int i = 0; i < Q; ++i) {
+            const double w = GL::w(i);
+            const double cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
+            const double cu = cx * u[0] + cy * u[1] + cz * u[2];
+            const double cF = cx * Fp[0] + cy * Fp[1] + cz * Fp[2];
+            const double cA = cx * Av[0] + cy * Av[1] + cz * Av[2];
+            const double Gam = w * (3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+            double q[5];
+            for (int k = 0; k < 5; ++k) q[k] = stress_row<GL, D3>(k, i);
+            double P = 0.0;
+            for (int k = 0; k < 5; ++k) P += q[k] * A[k];
+            const double lb = lg[i];
+            b_g[i] = (1.0 - so) * lb;
+            const double bfeq = so * lb, bF = fh * lb;
+            b_p3 += (i == 0 ? w - 1.0 : w) * bfeq;
+            b_kin0 += w * bfeq;
+            b_rho += w * (4.5 * cu * cu + 3.0 * cu) * bfeq;
+            double b_cu = w * rho * (9.0 * cu + 3.0) * bfeq;
+            const double b_cA = 3.0 * Gam * bF, b_cF = 3.0 * (w + Gam) * bF;
+            b_uA += -3.0 * Gam * bF;
+            b_uF += -3.0 * (w + Gam) * bF;
+            const double b_Gam = 3.0 * ((cA - uA) + (cF - uF)) * bF;
+            b_cu += w * (3.0 + 9.0 * cu) * b_Gam;
+            b_usq += -1.5 * w * b_Gam;
+            b_u[0] += cx * b_cu;
+            b_u[1] += cy * b_cu;
+            b_u[2] += cz * b_cu;
+            b_Fp[0] += cx * b_cF;
+            b_Fp[1] += cy * b_cF;
+            b_Fp[2] += cz * b_cF;
+            b_Av[0] += cx * b_cA;
+            b_Av[1] += cy * b_cA;
+            b_Av[2] += cz * b_cA;
+            for (int k = 0; k < 5; ++k) b_A[k] += -dS * q[k] * lb;
+            b_dS += -P * lb;
+        }
+        // A (linear in Pi); Pi_kl = m2_kl - rho u_k u_l + (B_k u_l + B_l u_k - 3 (u.B) u_k u_l) / 2
+        double b_Pi[3][3] = {{0.0}};
+        if constexpr (D3) {
+            b_Pi[0][0] = 2.0 * b_A[0] / N0;
+            b_Pi[1][1] = -b_A[0] / N0 + b_A[1] / N1;
+            b_Pi[2][2] = -b_A[0] / N0 - b_A[1] / N1;
+            b_Pi[0][1] = b_A[2] / N2;
+            b_Pi[1][2] = b_A[3] / N3;
+            b_Pi[0][2] = b_A[4] / N4;
+        } else {
+            b_Pi[0][0] = b_A[0] / N0;
+            b_Pi[1][1] = -b_A[0] / N0;
+            b_Pi[0][1] = b_A[2] / N2;
+        }
+        double b_m2[3][3] = {{0.0}}, b_B[3] = {0.0, 0.0, 0.0}, b_uB = 0.0;
+        for (int k = 0; k < 3; ++k)
+            for (int l = k; l < 3; ++l) {
+                const double b = b_Pi[k][l];
+                b_m2[k][l] += b;
+                b_rho += -u[k] * u[l] * b;
+                b_u[k] += (-rho * u[l] + 0.5 * B[l] - 1.5 * uB * u[l]) * b;
+                b_u[l] += (-rho * u[k] + 0.5 * B[k] - 1.5 * uB * u[k]) * b;
+                b_B[k] += 0.5 * u[l] * b;
+                b_B[l] += 0.5 * u[k] * b;
+                b_uB += -1.5 * u[k] * u[l] * b;
+            }
+        // kin0, p3 = 3 p, p = cp ((ps - g0) + udr / 2 - 1.5 rho w0 usq)
+        b_rho += -1.5 * usq * b_kin0;
+        b_usq += -1.5 * rho * b_kin0;
+        const double b_pres = 3.0 * b_p3;
+        const double b_ps = cp * b_pres;
+        b_g[0] += -cp * b_pres;
+        const double b_udr = 0.5 * cp * b_pres;
+        b_rho += -1.5 * w0 * usq * cp * b_pres;
+        b_usq += -1.5 * rho * w0 * cp * b_pres;
+        // uB, uA, uF, B = A + F', usq, udr
+        double b_grho[3], b_fsb[3], b_dM = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            b_u[k] += B[k] * b_uB + Av[k] * b_uA + Fp[k] * b_uF + 2.0 * u[k] * b_usq + grho[k] * b_udr;
+            b_B[k] += u[k] * b_uB;
+            b_Av[k] += u[k] * b_uA + b_B[k];
+            b_Fp[k] += u[k] * b_uF + b_B[k];
+            b_grho[k] = u[k] * b_udr + b_Av[k] / 3.0;
+            // F' = fsb + dM u
+            b_fsb[k] = b_Fp[k];
+            b_dM += u[k] * b_Fp[k];
+            b_u[k] += dM * b_Fp[k];
+        }
+        // u = (j + fsb / 2) / den, den = rho - dM / 2
+        double b_j[3], b_iden = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            b_j[k] = iden * b_u[k];
+            b_fsb[k] += 0.5 * iden * b_u[k];
+            b_iden += jf[k] * b_u[k];
+        }
+        const double b_den = -iden * iden * b_iden;
+        b_rho += b_den;
+        b_dM += -0.5 * b_den;
+        // dM = dR M lap(mu) ; fsb = mu gr + rho body + force ; grho = dR gr
+        const double b_lapmu = dR * ph.mob * b_dM;
+        thM = dR * lapmu * b_dM;
+        double b_gr[3];
+        for (int k = 0; k < 3; ++k) {
+            b_mu += gr[k] * b_fsb[k];
+            b_gr[k] = mu * b_fsb[k] + dR * b_grho[k];
+            b_rho += ph.body[k] * b_fsb[k];
+        }
+        // moments
+        for (int i = 0; i < Q; ++i) {
+            double b = b_ps;
+            for (int k = 0; k < 3; ++k) {
+                b += GL::c(i, k) * b_j[k];
+                for (int l = k; l < 3; ++l) b += GL::c(i, k) * GL::c(i, l) * b_m2[k][l];
+            }
+            b_g[i] += b;
+        }
+        // itau, nu, irho, rho
+        const double b_nu = 3.0 * (-itau * itau * b_dS);
+        double b_irho = 0.0;
+        if (ph.visc_mu) {
+            b_phi += ph.dMu * irho * b_nu;
+            b_irho += numu * b_nu;
+        } else {
+            b_phi += ph.dNu * b_nu;
+        }
+        b_rho += -irho * irho * b_irho;
+        b_phi += dR * b_rho;
+        // tau_phi = 3 M / eta + 1/2 (itp, gfp = 1 - itp / 2); M also in F_a
+        thM += -3.0 / ph.eta * itp * itp * (b_itp - 0.5 * b_gfp);
+
+        for (int i = 0; i < Q; ++i) a.og[(size_t)i * nn + n] = b_g[i];
+        a.work[n] = b_phi;
+        a.work[nn + n] = b_gr[0];
+        a.work[2 * nn + n] = b_gr[1];
+        a.work[3 * nn + n] = b_gr[2];
+        a.work[7 * nn + n] = b_mu;
+        a.work[8 * nn + n] = b_lapmu;
+    }
+    const double th[3] = {0.0, thM, 0.0};
+    __shared__ double red[3][256];
+    for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = th[k];
+    __syncthreads();
+    for (int s = 128; s >= 1; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 3; ++k) a.partials[(size_t)wg * 3 + k] = red[k][0];
+}
+
+// transpose of the mu_phi stencil: dL/dmu_phi(y) = work[7](y) plus lap^T of
+// work[8]; then mu_phi = beta4 phi (phi - 1)(phi - 1/2) - kappa lap phi gives
+// dL/dphi(y) += beta4 (3 phi^2 - 3 phi + 1/2) dL/dmu_phi, dL/dlap phi(y) =
+// -kappa dL/dmu_phi, and the sigma and W terms (beta4 = 48 sigma / W, kappa =
+// 1.5 sigma W), added to the sweep's block partials
+template <class PAIR>
+__global__ __launch_bounds__(256) void k_adj_mu_l14(const AdjArgs a) {
+    using GL = typename PAIR::G;
+    constexpr int Q = GL::Q;
+    const long long nn = (long long)a.nx * a.ny * a.nz;
+    const int wg = xcd_block();
+    const long long n = (long long)wg * blockDim.x + threadIdx.x;
+    double th[3] = {0.0, 0.0, 0.0};
+    if (n < nn) {
+        const double* blap = a.work + 8 * nn;
+        double acc = a.work[7 * nn + n] - 6.0 * (1.0 - GL::w(0)) * blap[n];
+        const Nbr nb(a, node_of(n, a));
+        unroll<Q - 1>([&](auto I) {
+            constexpr int i = I + 1;
+            constexpr int c0 = GL::c(i, 0), c1 = GL::c(i, 1), c2 = GL::c(i, 2);
+            constexpr double w6 = 6.0 * GL::w(i);
+            if (!nb.beyond(-c0, -c1, -c2)) acc += w6 * blap[nb.index(-c0, -c1, -c2)];
+            unroll<3>([&](auto K) {
+                constexpr int k = K;
+                constexpr int ck = k == 0 ? c0 : (k == 1 ? c1 : c2);
+                if constexpr (ck != 0) {
+                    if (nb.bnd[k][ck + 1]) {
+                        constexpr int dx = k == 0 ? 0 : -c0, dy = k == 1 ? 0 : -c1, dz = k == 2 ? 0 : -c2;
+                        if (!nb.beyond(dx, dy, dz)) acc += w6 * blap[nb.index(dx, dy, dz)];
+                    }
+                }
+            });
+        });
+        const Phys& ph = a.ph;
+        const double phi = a.phi[n], lap = a.work[6 * nn + n];
+        const double cub = phi * (phi - 1.0) * (phi - 0.5);
+        a.work[n] += ph.beta4 * (3.0 * phi * phi - 3.0 * phi + 0.5) * acc;
+        a.work[4 * nn + n] = -ph.kappa * acc;
+        const double sigma = a.sigma, W = a.W;
+        th[0] = acc * (cub * 48.0 / W - lap * 1.5 * W);
+        th[2] = -acc * (cub * 48.0 * sigma / (W * W) + lap * 1.5 * sigma);
+    }
+    __shared__ double red[3][256];
+    for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = th[k];
+    __syncthreads();
+    for (int s = 128; s >= 1; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 3; ++k) a.partials[(size_t)wg * 3 + k] += red[k][0];
+}
+
 // pass 3: transpose of grad phi(x) = 3 sum w c phi(src(x, i)) and
 // lap phi(x) = 6 sum w (phi(src(x, i)) - phi(x)), src = periodic image or wall
 // mirror of x + c_i, as a gather at y over {x : src(x, i) = y}; every h
@@ -1138,10 +1535,11 @@ __global__ __launch_bounds__(256) void k_adj_init(const AdjInitArgs a) {
 
 // adjoint of the CH initialisation h = h_eq(phi0, mu_phi(phi0), u0) (Eq.
 // liang2_geq with mu_phi of Eq. chemical_potential), g = g_eq(3 p0 / rho(phi0),
-// u0), (phi u) = phi0 u0: the local part of dL/dphi0 into work[0],
+// u0) (MODEL 1; Liang2014, MODEL 4: f = f_eq of Eq. liang2_feq at rho(phi0)),
+// (phi u) = phi0 u0: the local part of dL/dphi0 into work[0],
 // dL/d(lap phi0) into work[4] (the stencil pass in init mode adds its
 // transpose), and the sigma and W terms of mu_phi into the block partials
-template <class PAIR>
+template <class PAIR, int MODEL>
 __global__ __launch_bounds__(256) void k_adj_init_ch(const AdjArgs a, const double* phi0, const double* u0,
                                                      const double* p0) {
     using GL = typename PAIR::G;
@@ -1180,7 +1578,16 @@ __global__ __launch_bounds__(256) void k_adj_init_ch(const AdjArgs a, const doub
         cmu *= ph.eta;   // dL/dmu_phi
         for (int k = 0; k < 3; ++k) s += a.lpu[(size_t)k * nn + n] * u[k];
         s += cmu * ph.beta4 * (3.0 * phi * phi - 3.0 * phi + 0.5);
-        if (p0) {
+        if constexpr (MODEL == 4) {
+            // Eq. liang2_feq: the kinetic part rho(phi0) w (3 c.u + 4.5 (c.u)^2 - 1.5 u.u)
+            const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+            double sg = 0.0;
+            for (int i = 0; i < GL::Q; ++i) {
+                const double cu = GL::c(i, 0) * u[0] + GL::c(i, 1) * u[1] + GL::c(i, 2) * u[2];
+                sg += a.lg[(size_t)i * nn + n] * GL::w(i) * (3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+            }
+            s += ph.dRho * sg;
+        } else if (p0) {
             const double rho = ph.rhoL + phi * ph.dRho;
             const double dps = -3.0 * p0[n] * ph.dRho / (rho * rho);
             for (int i = 0; i < GL::Q; ++i) s += a.lg[(size_t)i * nn + n] * GL::w(i) * dps;
@@ -1247,9 +1654,17 @@ hipError_t launch_adjoint(int lattice, int model, const AdjArgs& a, double* dpar
                                (double*)nullptr);
             return;
         }
-        if (model == 1) hipLaunchKernelGGL((k_adj_local<P_, 1>), grid, block, 0, st, a);
-        else if (model == 3) hipLaunchKernelGGL((k_adj_local_l18<P_>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((k_adj_local<P_, 0>), grid, block, 0, st, a);
+        if (model == 1) {
+            hipLaunchKernelGGL((k_adj_local<P_, 1>), grid, block, 0, st, a);
+        } else if (model == 3) {
+            hipLaunchKernelGGL((k_adj_local_l18<P_>), grid, block, 0, st, a);
+        } else if (model == 4) {
+            hipLaunchKernelGGL((k_adj_mu_fwd<P_>), grid, block, 0, st, a);
+            hipLaunchKernelGGL((k_adj_local_l14<P_>), grid, block, 0, st, a);
+            hipLaunchKernelGGL((k_adj_mu_l14<P_>), grid, block, 0, st, a);
+        } else {
+            hipLaunchKernelGGL((k_adj_local<P_, 0>), grid, block, 0, st, a);
+        }
         hipLaunchKernelGGL((k_adj_stencil<P_, ST_STEP>), grid, block, 0, st, a);
     };
     if (lattice == 0) go(Pair2D{});
@@ -1294,13 +1709,14 @@ hipError_t launch_adjoint_seed_nl(int lattice, const AdjArgs& a, const double* d
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint_init_ch(int lattice, const AdjArgs& a, const double* phi0, const double* u0,
+hipError_t launch_adjoint_init_ch(int lattice, int model, const AdjArgs& a, const double* phi0, const double* u0,
                                   const double* p0, double* dparams, hipStream_t st) {
     const long long nn = (long long)a.nx * a.ny * a.nz;
     const dim3 grid((unsigned)((nn + 255) / 256)), block(256);
     auto go = [&](auto pair) {
         using P_ = decltype(pair);
-        hipLaunchKernelGGL((k_adj_init_ch<P_>), grid, block, 0, st, a, phi0, u0, p0);
+        if (model == 4) hipLaunchKernelGGL((k_adj_init_ch<P_, 4>), grid, block, 0, st, a, phi0, u0, p0);
+        else hipLaunchKernelGGL((k_adj_init_ch<P_, 1>), grid, block, 0, st, a, phi0, u0, p0);
         hipLaunchKernelGGL((k_adj_stencil<P_, ST_INIT>), grid, block, 0, st, a);
     };
     if (lattice == 0) go(Pair2D{});

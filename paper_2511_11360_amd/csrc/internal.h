@@ -187,7 +187,7 @@ hipError_t launch_adjoint(int lattice, int model, const AdjArgs& a, double* dpar
 hipError_t launch_adjoint_init(int lattice, int model, const AdjInitArgs& a, hipStream_t s);
 hipError_t launch_adjoint_seed_nl(int lattice, const AdjArgs& a, const double* dphi, double* lam_g, double* lam_h,
                                   double* dparams, hipStream_t s);
-hipError_t launch_adjoint_init_ch(int lattice, const AdjArgs& a, const double* phi0, const double* u0,
+hipError_t launch_adjoint_init_ch(int lattice, int model, const AdjArgs& a, const double* phi0, const double* u0,
                                   const double* p0, double* dparams, hipStream_t s);
 hipError_t launch_phiu_io(int precision, bool get, void* pu, double* canon, int P, int nx, int ny, int nz,
                           hipStream_t s);

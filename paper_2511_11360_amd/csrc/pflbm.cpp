@@ -643,8 +643,11 @@ int pflbm_load_state(pflbm_t* h, const void* dev_src) {
 static size_t adj_nodes(const pflbm_t* h) { return (size_t)h->p.nx * h->p.ny * h->p.nz; }
 
 // per-node adjoint values of the workspace: dL/dphi, dL/dgrad phi, dL/dlap phi;
-// the nonlocal model adds dL/dR and phi = sum h
-static size_t adj_nwork(const pflbm_t* h) { return h->p.model == PFLBM_NL ? 7 : 5; }
+// the nonlocal model adds dL/dR and phi = sum h, Liang2014 mu_phi, lap phi,
+// dL/dmu_phi and dL/dlap mu_phi
+static size_t adj_nwork(const pflbm_t* h) {
+    return h->p.model == PFLBM_NL ? 7 : (h->p.model == PFLBM_L14 ? 9 : 5);
+}
 
 int pflbm_adjoint_workspace_bytes(const pflbm_t* h, size_t* bytes) {
     if (!h || !bytes) return PFLBM_EINVAL;
@@ -660,10 +663,9 @@ int pflbm_adjoint_workspace_bytes(const pflbm_t* h, size_t* bytes) {
 static int adjoint_check(pflbm_t* h, bool with_pu) {
     int st = guard(h);
     if (st) return st;
-    if (h->p.model == PFLBM_L14)
-        return fail(h, PFLBM_EUNSUPPORTED, "adjoint not implemented for the Liang2014 model");
-    if ((h->p.model == PFLBM_CH || h->p.model == PFLBM_L18) && !with_pu)
-        return fail(h, PFLBM_EUNSUPPORTED, "the CH and Liang2018 adjoints carry (phi u): use the _pu entry points");
+    const bool has_pu = h->p.model == PFLBM_CH || h->p.model == PFLBM_L18 || h->p.model == PFLBM_L14;
+    if (has_pu && !with_pu)
+        return fail(h, PFLBM_EUNSUPPORTED, "the CH and Liang adjoints carry (phi u): use the _pu entry points");
     if (h->p.freeze_phi) return fail(h, PFLBM_EUNSUPPORTED, "adjoint of a frozen phase field is not implemented");
     return PFLBM_OK;
 }
@@ -686,7 +688,7 @@ int pflbm_adjoint_step_pu(pflbm_t* h, const double* fwd_g, const double* fwd_h, 
                           double* lam_h_out, double* lam_pu_out, double* dparams, void* work) {
     if (int st = adjoint_check(h, true)) return st;
     if (!work) return fail(h, PFLBM_EINVAL, "null pointer");
-    if (h->p.model != PFLBM_CH && h->p.model != PFLBM_L18) {
+    if (h->p.model != PFLBM_CH && h->p.model != PFLBM_L18 && h->p.model != PFLBM_L14) {
         fwd_pu = lam_pu = nullptr;
         lam_pu_out = nullptr;
     } else {
@@ -829,7 +831,8 @@ int pflbm_adjoint_init_pu(pflbm_t* h, const double* phi0, const double* u0, cons
         HIPCHK(h, launch_adjoint_init(h->p.lattice, h->p.model, a, h->stream), "adjoint init kernel");
         return PFLBM_OK;
     }
-    if (h->p.model != PFLBM_CH) return pflbm_adjoint_init(h, phi0, u0, p0, lam_g, lam_h, dphi0);
+    if (h->p.model != PFLBM_CH && h->p.model != PFLBM_L14)
+        return pflbm_adjoint_init(h, phi0, u0, p0, lam_g, lam_h, dphi0);
     if (!phi0 || !lam_g || !lam_h || !lam_pu || !dphi0 || !work) return fail(h, PFLBM_EINVAL, "null pointer");
     AdjArgs a;
     adjoint_args(h, work, a);
@@ -837,7 +840,8 @@ int pflbm_adjoint_init_pu(pflbm_t* h, const double* phi0, const double* u0, cons
     a.lh = lam_h;
     a.lpu = lam_pu;
     a.dphi0 = dphi0;
-    HIPCHK(h, launch_adjoint_init_ch(h->p.lattice, a, phi0, u0, p0, dparams, h->stream), "adjoint init kernels");
+    HIPCHK(h, launch_adjoint_init_ch(h->p.lattice, h->p.model, a, phi0, u0, p0, dparams, h->stream),
+           "adjoint init kernels");
     return PFLBM_OK;
 }
 

@@ -131,7 +131,7 @@ class Solver:
     def load_state(self, buf):
         self._check(self.L.pflbm_load_state(self.h, _ptr(buf)), self.h)
 
-    # ---- discrete adjoint (AC, CH, nonlocal and Liang2018 models)
+    # ---- discrete adjoint (every model)
     def adjoint_workspace(self):
         n = ctypes.c_size_t()
         self._check(self.L.pflbm_adjoint_workspace_bytes(self.h, ctypes.byref(n)), self.h)
