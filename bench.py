@@ -194,15 +194,19 @@ def time_adjoint(steps, model="AC"):
     sheared droplet between moving walls, at the forward state after 20 steps,
     chaining lambda through two buffers. Algorithmic bytes per node: lambda
     read and written (2 x 26 x 8), the forward state read (26 x 8), six
-    workspace values written and read (2 x 6 x 8); the CH model adds (phi u)
-    to the state (3 x 8 more in each of the three), the nonlocal model two
-    per-node workspace values (sum h and dL/dR, 2 x 2 x 8)."""
+    workspace values written and read (2 x 6 x 8); the CH and Liang models
+    add (phi u) to the state (3 x 8 more in each of the three), the nonlocal
+    model two per-node workspace values (sum h and dL/dR, 2 x 2 x 8),
+    Liang2014 four (mu_phi, lap phi and their adjoints, 2 x 4 x 8). The Liang
+    models run between stationary walls (the only walls they take)."""
     import torch
     from paper_2511_11360_amd import workloads as wl
     from paper_2511_11360_amd.solver import Solver
     d, phi, u, _ = wl.sheared_droplet_3d()
     d = dict(d, model=model)
-    ch = model == "CH"
+    if model in ("L18", "L14"):
+        d["wall_u"] = ((0.0, 0.0, 0.0), (0.0, 0.0, 0.0))    # stationary walls (their velocity stays in u0)
+    ch = model in ("CH", "L18", "L14")
     s = Solver(d, precision="fp64")
     s.init(phi, u)
     s.step(20)
@@ -233,9 +237,11 @@ def time_adjoint(steps, model="AC"):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     nodes = d["nx"] * d["ny"] * d["nz"]
-    nb = ADJ_BYTES + (3 * 3 * 8 if ch else 0) + (2 * 2 * 8 if model == "NL" else 0)
-    return {"workload": "3-D sheared droplet, D3Q19+D3Q7, 128^3, walls moving at -+0.02 (adjoint "
-                        "of the %s step, float64)" % model,
+    nb = (ADJ_BYTES + (3 * 3 * 8 if ch else 0) + (2 * 2 * 8 if model == "NL" else 0)
+          + (2 * 4 * 8 if model == "L14" else 0))
+    walls = "stationary walls, shear in u0" if model in ("L18", "L14") else "walls moving at -+0.02"
+    return {"workload": "3-D sheared droplet, D3Q19+D3Q7, 128^3, %s (adjoint of the %s step, float64)"
+                        % (walls, model),
             "ms_per_step": round(ms, 4), "MLUPS": round(nodes / (ms * 1e-3) / 1e6, 1),
             "bytes_per_update": nb,
             "hbm_frac": round(nb * nodes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
@@ -545,9 +551,10 @@ def main():
         log("adjoint, CH")
         adjoint["ch"] = time_adjoint(100, "CH")
         torch.cuda.empty_cache()
-        log("adjoint, nonlocal")
-        adjoint["nl"] = time_adjoint(100, "NL")
-        torch.cuda.empty_cache()
+        for key, model in (("nl", "NL"), ("l18", "L18"), ("l14", "L14")):
+            log("adjoint, %s" % model)
+            adjoint[key] = time_adjoint(100, model)
+            torch.cuda.empty_cache()
         if not args.no_backward:
             log("backward pass")
             adjoint["backward"] = time_backward()
