@@ -144,6 +144,110 @@ __host__ __device__ constexpr double stress_norm(int k) {
     return s > 0 ? (double)s : 1.0;
 }
 
+// the rows' coefficients of the two-rate projector for the traceless
+// stress Pi (each row's sum over the populations divided by its squared
+// norm), and their transpose (added into b_Pi, upper triangle)
+template <class GL, bool D3>
+__device__ __forceinline__ void stress_coeffs(const double (&Pi)[3][3], double (&A)[5]) {
+    constexpr double N0 = stress_norm<GL, D3>(0), N1 = stress_norm<GL, D3>(1), N2 = stress_norm<GL, D3>(2),
+                     N3 = stress_norm<GL, D3>(3), N4 = stress_norm<GL, D3>(4);
+    if constexpr (D3) {
+        A[0] = (2.0 * Pi[0][0] - Pi[1][1] - Pi[2][2]) / N0;
+        A[1] = (Pi[1][1] - Pi[2][2]) / N1;
+        A[2] = Pi[0][1] / N2;
+        A[3] = Pi[1][2] / N3;
+        A[4] = Pi[0][2] / N4;
+    } else {
+        A[0] = (Pi[0][0] - Pi[1][1]) / N0;
+        A[1] = 0.0;
+        A[2] = Pi[0][1] / N2;
+        A[3] = 0.0;
+        A[4] = 0.0;
+    }
+}
+template <class GL, bool D3>
+__device__ __forceinline__ void stress_coeffs_T(const double (&b_A)[5], double (&b_Pi)[3][3]) {
+    constexpr double N0 = stress_norm<GL, D3>(0), N1 = stress_norm<GL, D3>(1), N2 = stress_norm<GL, D3>(2),
+                     N3 = stress_norm<GL, D3>(3), N4 = stress_norm<GL, D3>(4);
+    if constexpr (D3) {
+        b_Pi[0][0] += 2.0 * b_A[0] / N0;
+        b_Pi[1][1] += -b_A[0] / N0 + b_A[1] / N1;
+        b_Pi[2][2] += -b_A[0] / N0 - b_A[1] / N1;
+        b_Pi[0][1] += b_A[2] / N2;
+        b_Pi[1][2] += b_A[3] / N3;
+        b_Pi[0][2] += b_A[4] / N4;
+    } else {
+        b_Pi[0][0] += b_A[0] / N0;
+        b_Pi[1][1] += -b_A[0] / N0;
+        b_Pi[0][1] += b_A[2] / N2;
+    }
+}
+
+// moments of the hydrodynamic populations: sum g, sum c g, sum c c g; and
+// the transpose, added into b_g (b_m2 upper triangle)
+template <class GL>
+__device__ __forceinline__ void moments(const double (&g)[GL::Q], double& ps, double (&j)[3], double (&m2)[3][3]) {
+    ps = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        j[k] = 0.0;
+        for (int l = 0; l < 3; ++l) m2[k][l] = 0.0;
+    }
+    unroll<GL::Q>([&](auto I) {
+        constexpr int i = I;
+        ps += g[i];
+        for (int k = 0; k < 3; ++k) {
+            j[k] += GL::c(i, k) * g[i];
+            for (int l = 0; l < 3; ++l) m2[k][l] += GL::c(i, k) * GL::c(i, l) * g[i];
+        }
+    });
+}
+template <class GL>
+__device__ __forceinline__ void moments_T(double b_ps, const double (&b_j)[3], const double (&b_m2)[3][3],
+                                          double (&b_g)[GL::Q]) {
+    for (int i = 0; i < GL::Q; ++i) {
+        double b = b_ps;
+        for (int k = 0; k < 3; ++k) {
+            b += GL::c(i, k) * b_j[k];
+            for (int l = k; l < 3; ++l) b += GL::c(i, k) * GL::c(i, l) * b_m2[k][l];
+        }
+        b_g[i] += b;
+    }
+}
+
+// dL/dphi through nu(phi) (linear mu over rho, or linear nu), irho = 1 /
+// rho(phi) and rho = rhoL + phi dRho, from their adjoints
+__device__ __forceinline__ double phys_T(const Phys& ph, double irho, double numu, double b_nu, double b_irho,
+                                         double b_rho) {
+    double b_phi = 0.0;
+    if (ph.visc_mu) {
+        b_phi += ph.dMu * irho * b_nu;
+        b_irho += numu * b_nu;
+    } else {
+        b_phi += ph.dNu * b_nu;
+    }
+    b_rho += -irho * irho * b_irho;
+    return b_phi + ph.dRho * b_rho;
+}
+
+// 256-thread fixed-order block sums of K values per thread into
+// part[wg * STRIDE + k] (ADD: added to what is there)
+template <int K, int STRIDE, bool ADD = false>
+__device__ __forceinline__ void block_sums(const double (&v)[K], double* part, int wg) {
+    __shared__ double red[K][256];
+    for (int k = 0; k < K; ++k) red[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int s = 128; s >= 1; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < K; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < K; ++k) {
+            if constexpr (ADD) part[(size_t)wg * STRIDE + k] += red[k][0];
+            else part[(size_t)wg * STRIDE + k] = red[k][0];
+        }
+}
+
 }  // namespace
 
 __global__ __launch_bounds__(256) void k_adj_phi(const AdjArgs a) {
@@ -201,15 +305,8 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
         const double itau = 1.0 / tau;
         const double cub = phi * (phi - 1.0) * (phi - 0.5);
         const double mu = ph.beta4 * cub - ph.kappa * lap;
-        double ps = 0.0, j[3] = {0.0, 0.0, 0.0}, m2[3][3] = {{0.0}};
-        unroll<Q>([&](auto I) {
-            constexpr int i = I;
-            ps += g[i];
-            for (int k = 0; k < 3; ++k) {
-                j[k] += GL::c(i, k) * g[i];
-                for (int l = 0; l < 3; ++l) m2[k][l] += GL::c(i, k) * GL::c(i, l) * g[i];
-            }
-        });
+        double ps, j[3], m2[3][3];
+        moments<GL>(g, ps, j, m2);
         const double sg = mu - ps * dR / 3.0;
         double F0[3], us[3], S[3][3], F[3], u[3];
         for (int k = 0; k < 3; ++k) F0[k] = sg * gr[k] + rho * ph.body[k] + ph.force[k];
@@ -237,23 +334,8 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
                 Pi[k][l] = m2[k][l] - (k == l ? s3 : 0.0) - u[k] * u[l];
         // stress-projection coefficients (linear in Pi), each row's sum over
         // the populations divided by its squared norm
-        constexpr double N0 = stress_norm<GL, D3>(0), N1 = stress_norm<GL, D3>(1),
-                         N2 = stress_norm<GL, D3>(2), N3 = stress_norm<GL, D3>(3),
-                         N4 = stress_norm<GL, D3>(4);
         double A[5];
-        if constexpr (D3) {
-            A[0] = (2.0 * Pi[0][0] - Pi[1][1] - Pi[2][2]) / N0;
-            A[1] = (Pi[1][1] - Pi[2][2]) / N1;
-            A[2] = Pi[0][1] / N2;
-            A[3] = Pi[1][2] / N3;
-            A[4] = Pi[0][2] / N4;
-        } else {
-            A[0] = (Pi[0][0] - Pi[1][1]) / N0;
-            A[1] = 0.0;
-            A[2] = Pi[0][1] / N2;
-            A[3] = 0.0;
-            A[4] = 0.0;
-        }
+        stress_coeffs<GL, D3>(Pi, A);
         auto qrow = [&](int i, double* q) {   // stress rows evaluated at c_i
             for (int k = 0; k < 5; ++k) q[k] = stress_row<GL, D3>(k, i);
         };
@@ -422,18 +504,7 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
             for (int k = 0; k < 3; ++k) b_F[k] += ffac * w * GL::c(i, k) * lb;
         }
         // A (linear in Pi)
-        if constexpr (D3) {
-            b_Pi[0][0] += 2.0 * b_A[0] / N0;
-            b_Pi[1][1] += -b_A[0] / N0 + b_A[1] / N1;
-            b_Pi[2][2] += -b_A[0] / N0 - b_A[1] / N1;
-            b_Pi[0][1] += b_A[2] / N2;
-            b_Pi[1][2] += b_A[3] / N3;
-            b_Pi[0][2] += b_A[4] / N4;
-        } else {
-            b_Pi[0][0] += b_A[0] / N0;
-            b_Pi[1][1] += -b_A[0] / N0;
-            b_Pi[0][1] += b_A[2] / N2;
-        }
+        stress_coeffs_T<GL, D3>(b_A, b_Pi);
         // Pi_kl = m2_kl - delta s3 - u_k u_l (only k <= l entries carry adjoints)
         double b_m2[3][3] = {{0.0}}, b_s3 = 0.0;
         for (int k = 0; k < 3; ++k)
@@ -504,31 +575,15 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
         const double b_mu = b_sg + b_muh;
         b_ps += -b_sg * dR / 3.0;
         // moments
-        for (int i = 0; i < Q; ++i) {
-            double b = b_ps;
-            for (int k = 0; k < 3; ++k) {
-                b += GL::c(i, k) * b_j[k];
-                for (int l = k; l < 3; ++l) b += GL::c(i, k) * GL::c(i, l) * b_m2[k][l];
-            }
-            b_g[i] += b;
-        }
+        moments_T<GL>(b_ps, b_j, b_m2, b_g);
         // mu = beta4 phi (phi - 1)(phi - 1/2) - kappa lap
         const double b_beta4 = b_mu * cub;
         const double b_kappa = -b_mu * lap;
         b_lap += -ph.kappa * b_mu;
         b_phi += b_mu * ph.beta4 * (3.0 * phi * phi - 3.0 * phi + 0.5);
-        // itau = 1 / tau, tau = 3 nu + 1/2
+        // itau = 1 / tau, tau = 3 nu + 1/2; nu, irho = 1 / rho, rho = rhoL + phi dR
         b_nu += 3.0 * (-itau * itau * b_itau);
-        // nu
-        if (ph.visc_mu) {
-            b_phi += ph.dMu * irho * b_nu;
-            b_irho += numu * b_nu;
-        } else {
-            b_phi += ph.dNu * b_nu;
-        }
-        // irho = 1 / rho, rho = rhoL + phi dR
-        b_rho += -irho * irho * b_irho;
-        b_phi += dR * b_rho;
+        b_phi += phys_T(ph, irho, numu, b_nu, b_irho, b_rho);
 
         // parameters: beta4 = 48 sigma / W, kappa = 1.5 sigma W, anti = 4 / W,
         // itp = 1 / (3 M + 1/2), gfp = 1 - itp / 2 (the nonlocal source's M and
@@ -548,7 +603,9 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
         a.work[4 * nn + n] = b_lap;
         if constexpr (MODEL == 2) a.work[5 * nn + n] = b_R;
     }
-    // block sums of the parameter adjoints, fixed order
+    // block sums of the parameter adjoints, fixed order (written out rather
+    // than through block_sums: with the helper the compiler spills 68 bytes
+    // per lane in this sweep, with this form 20)
     __shared__ double red[3][256];
     for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = th[k];
     __syncthreads();
@@ -607,15 +664,8 @@ __global__ __launch_bounds__(256, 2) void k_adj_local_l18(const AdjArgs a) {
         const double itau = 1.0 / (3.0 * nu + 0.5);
         const double cub = phi * (phi - 1.0) * (phi - 0.5);
         const double mu = ph.beta4 * cub - ph.kappa * lap;
-        double ps = 0.0, j[3] = {0.0, 0.0, 0.0}, m2[3][3] = {{0.0}};
-        unroll<Q>([&](auto I) {
-            constexpr int i = I;
-            ps += g[i];
-            for (int k = 0; k < 3; ++k) {
-                j[k] += GL::c(i, k) * g[i];
-                for (int l = 0; l < 3; ++l) m2[k][l] += GL::c(i, k) * GL::c(i, l) * g[i];
-            }
-        });
+        double ps, j[3], m2[3][3];
+        moments<GL>(g, ps, j, m2);
         double F[3], u[3], grho[3], jF[3];
         for (int k = 0; k < 3; ++k) {
             F[k] = mu * gr[k] + rho * ph.body[k] + ph.force[k];
@@ -637,23 +687,8 @@ __global__ __launch_bounds__(256, 2) void k_adj_local_l18(const AdjArgs a) {
         for (int k = 0; k < 3; ++k)
             for (int l = 0; l < 3; ++l)
                 Pi[k][l] = m2[k][l] - rho * u[k] * u[l] + (1.0 / 6.0) * (u[k] * grho[l] + u[l] * grho[k]);
-        constexpr double N0 = stress_norm<GL, D3>(0), N1 = stress_norm<GL, D3>(1),
-                         N2 = stress_norm<GL, D3>(2), N3 = stress_norm<GL, D3>(3),
-                         N4 = stress_norm<GL, D3>(4);
         double A[5];
-        if constexpr (D3) {
-            A[0] = (2.0 * Pi[0][0] - Pi[1][1] - Pi[2][2]) / N0;
-            A[1] = (Pi[1][1] - Pi[2][2]) / N1;
-            A[2] = Pi[0][1] / N2;
-            A[3] = Pi[1][2] / N3;
-            A[4] = Pi[0][2] / N4;
-        } else {
-            A[0] = (Pi[0][0] - Pi[1][1]) / N0;
-            A[1] = 0.0;
-            A[2] = Pi[0][1] / N2;
-            A[3] = 0.0;
-            A[4] = 0.0;
-        }
+        stress_coeffs<GL, D3>(Pi, A);
         const double gg = gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2];
         const double sn = gg + ph.eps2;
         const double rn = sn > 0.0 ? 1.0 / sqrt(sn) : 0.0;
@@ -765,18 +800,7 @@ __global__ __launch_bounds__(256, 2) void k_adj_local_l18(const AdjArgs a) {
         }
         // A (linear in Pi), Pi_kl = m2_kl - rho u_k u_l + (u_k grho_l + u_l grho_k) / 6
         double b_Pi[3][3] = {{0.0}};
-        if constexpr (D3) {
-            b_Pi[0][0] = 2.0 * b_A[0] / N0;
-            b_Pi[1][1] = -b_A[0] / N0 + b_A[1] / N1;
-            b_Pi[2][2] = -b_A[0] / N0 - b_A[1] / N1;
-            b_Pi[0][1] = b_A[2] / N2;
-            b_Pi[1][2] = b_A[3] / N3;
-            b_Pi[0][2] = b_A[4] / N4;
-        } else {
-            b_Pi[0][0] = b_A[0] / N0;
-            b_Pi[1][1] = -b_A[0] / N0;
-            b_Pi[0][1] = b_A[2] / N2;
-        }
+        stress_coeffs_T<GL, D3>(b_A, b_Pi);
         double b_m2[3][3] = {{0.0}};
         for (int k = 0; k < 3; ++k)
             for (int l = k; l < 3; ++l) {
@@ -813,28 +837,13 @@ __global__ __launch_bounds__(256, 2) void k_adj_local_l18(const AdjArgs a) {
             b_rho += ph.body[k] * b_F[k];
         }
         // moments
-        for (int i = 0; i < Q; ++i) {
-            double b = b_ps;
-            for (int k = 0; k < 3; ++k) {
-                b += GL::c(i, k) * b_j[k];
-                for (int l = k; l < 3; ++l) b += GL::c(i, k) * GL::c(i, l) * b_m2[k][l];
-            }
-            b_g[i] += b;
-        }
+        moments_T<GL>(b_ps, b_j, b_m2, b_g);
         // mu = beta4 phi (phi - 1)(phi - 1/2) - kappa lap
         const double b_beta4 = b_mu * cub, b_kappa = -b_mu * lap;
         const double b_lap = -ph.kappa * b_mu;
         b_phi += b_mu * ph.beta4 * (3.0 * phi * phi - 3.0 * phi + 0.5);
         // itau = 1 / (3 nu + 1/2), dS = itau - so ; nu ; irho ; rho
-        const double b_nu = 3.0 * (-itau * itau * b_dS);
-        if (ph.visc_mu) {
-            b_phi += ph.dMu * irho * b_nu;
-            b_irho += numu * b_nu;
-        } else {
-            b_phi += ph.dNu * b_nu;
-        }
-        b_rho += -irho * irho * b_irho;
-        b_phi += dR * b_rho;
+        b_phi += phys_T(ph, irho, numu, 3.0 * (-itau * itau * b_dS), b_irho, b_rho);
         // parameters: beta4 = 48 sigma / W, kappa = 1.5 sigma W, anti = 4 / W,
         // itp = 1 / (3 M + 1/2), gfp = 1 - itp / 2
         const double sigma = a.sigma, W = a.W;
@@ -849,16 +858,7 @@ __global__ __launch_bounds__(256, 2) void k_adj_local_l18(const AdjArgs a) {
         a.work[3 * nn + n] = b_gr[2];
         a.work[4 * nn + n] = b_lap;
     }
-    __shared__ double red[3][256];
-    for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = th[k];
-    __syncthreads();
-    for (int s = 128; s >= 1; s >>= 1) {
-        if ((int)threadIdx.x < s)
-            for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0)
-        for (int k = 0; k < 3; ++k) a.partials[(size_t)wg * 3 + k] = red[k][0];
+    block_sums<3, 3>(th, a.partials, wg);
 }
 
 // ---------------------------------------------------------------------------
@@ -930,15 +930,8 @@ __global__ __launch_bounds__(256, 2) void k_adj_local_l14(const AdjArgs a) {
         const double numu = ph.muL + phi * ph.dMu;
         const double nu = ph.visc_mu ? numu * irho : ph.nuL + phi * ph.dNu;
         const double itau = 1.0 / (3.0 * nu + 0.5);
-        double ps = 0.0, j[3] = {0.0, 0.0, 0.0}, m2[3][3] = {{0.0}};
-        unroll<Q>([&](auto I) {
-            constexpr int i = I;
-            ps += g[i];
-            for (int k = 0; k < 3; ++k) {
-                j[k] += GL::c(i, k) * g[i];
-                for (int l = 0; l < 3; ++l) m2[k][l] += GL::c(i, k) * GL::c(i, l) * g[i];
-            }
-        });
+        double ps, j[3], m2[3][3];
+        moments<GL>(g, ps, j, m2);
         const double dM = dR * ph.mob * lapmu;
         const double den = rho - 0.5 * dM;
         const double iden = 1.0 / den;
@@ -969,23 +962,8 @@ __global__ __launch_bounds__(256, 2) void k_adj_local_l14(const AdjArgs a) {
         for (int k = 0; k < 3; ++k)
             for (int l = 0; l < 3; ++l)
                 Pi[k][l] = m2[k][l] - rho * u[k] * u[l] + 0.5 * (B[k] * u[l] + B[l] * u[k] - 3.0 * uB * u[k] * u[l]);
-        constexpr double N0 = stress_norm<GL, D3>(0), N1 = stress_norm<GL, D3>(1),
-                         N2 = stress_norm<GL, D3>(2), N3 = stress_norm<GL, D3>(3),
-                         N4 = stress_norm<GL, D3>(4);
         double A[5];
-        if constexpr (D3) {
-            A[0] = (2.0 * Pi[0][0] - Pi[1][1] - Pi[2][2]) / N0;
-            A[1] = (Pi[1][1] - Pi[2][2]) / N1;
-            A[2] = Pi[0][1] / N2;
-            A[3] = Pi[1][2] / N3;
-            A[4] = Pi[0][2] / N4;
-        } else {
-            A[0] = (Pi[0][0] - Pi[1][1]) / N0;
-            A[1] = 0.0;
-            A[2] = Pi[0][1] / N2;
-            A[3] = 0.0;
-            A[4] = 0.0;
-        }
+        stress_coeffs<GL, D3>(Pi, A);
         const double itp = ph.inv_tau_phi, gfp = ph.g_fac_phi;
 
         // ---------------- reverse sweep; lambda* gathered through the stream transpose
@@ -1095,18 +1073,7 @@ __global__ __launch_bounds__(256, 2) void k_adj_local_l14(const AdjArgs a) {
         }
         // A (linear in Pi); Pi_kl = m2_kl - rho u_k u_l + (B_k u_l + B_l u_k - 3 (u.B) u_k u_l) / 2
         double b_Pi[3][3] = {{0.0}};
-        if constexpr (D3) {
-            b_Pi[0][0] = 2.0 * b_A[0] / N0;
-            b_Pi[1][1] = -b_A[0] / N0 + b_A[1] / N1;
-            b_Pi[2][2] = -b_A[0] / N0 - b_A[1] / N1;
-            b_Pi[0][1] = b_A[2] / N2;
-            b_Pi[1][2] = b_A[3] / N3;
-            b_Pi[0][2] = b_A[4] / N4;
-        } else {
-            b_Pi[0][0] = b_A[0] / N0;
-            b_Pi[1][1] = -b_A[0] / N0;
-            b_Pi[0][1] = b_A[2] / N2;
-        }
+        stress_coeffs_T<GL, D3>(b_A, b_Pi);
         double b_m2[3][3] = {{0.0}}, b_B[3] = {0.0, 0.0, 0.0}, b_uB = 0.0;
         for (int k = 0; k < 3; ++k)
             for (int l = k; l < 3; ++l) {
@@ -1161,25 +1128,9 @@ __global__ __launch_bounds__(256, 2) void k_adj_local_l14(const AdjArgs a) {
             b_rho += ph.body[k] * b_fsb[k];
         }
         // moments
-        for (int i = 0; i < Q; ++i) {
-            double b = b_ps;
-            for (int k = 0; k < 3; ++k) {
-                b += GL::c(i, k) * b_j[k];
-                for (int l = k; l < 3; ++l) b += GL::c(i, k) * GL::c(i, l) * b_m2[k][l];
-            }
-            b_g[i] += b;
-        }
+        moments_T<GL>(b_ps, b_j, b_m2, b_g);
         // itau, nu, irho, rho
-        const double b_nu = 3.0 * (-itau * itau * b_dS);
-        double b_irho = 0.0;
-        if (ph.visc_mu) {
-            b_phi += ph.dMu * irho * b_nu;
-            b_irho += numu * b_nu;
-        } else {
-            b_phi += ph.dNu * b_nu;
-        }
-        b_rho += -irho * irho * b_irho;
-        b_phi += dR * b_rho;
+        b_phi += phys_T(ph, irho, numu, 3.0 * (-itau * itau * b_dS), 0.0, b_rho);
         // tau_phi = 3 M / eta + 1/2 (itp, gfp = 1 - itp / 2); M also in F_a
         thM += -3.0 / ph.eta * itp * itp * (b_itp - 0.5 * b_gfp);
 
@@ -1192,16 +1143,7 @@ __global__ __launch_bounds__(256, 2) void k_adj_local_l14(const AdjArgs a) {
         a.work[8 * nn + n] = b_lapmu;
     }
     const double th[3] = {0.0, thM, 0.0};
-    __shared__ double red[3][256];
-    for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = th[k];
-    __syncthreads();
-    for (int s = 128; s >= 1; s >>= 1) {
-        if ((int)threadIdx.x < s)
-            for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0)
-        for (int k = 0; k < 3; ++k) a.partials[(size_t)wg * 3 + k] = red[k][0];
+    block_sums<3, 3>(th, a.partials, wg);
 }
 
 // transpose of the mu_phi stencil: dL/dmu_phi(y) = work[7](y) plus lap^T of
@@ -1246,16 +1188,7 @@ __global__ __launch_bounds__(256) void k_adj_mu_l14(const AdjArgs a) {
         th[0] = acc * (cub * 48.0 / W - lap * 1.5 * W);
         th[2] = -acc * (cub * 48.0 * sigma / (W * W) + lap * 1.5 * sigma);
     }
-    __shared__ double red[3][256];
-    for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = th[k];
-    __syncthreads();
-    for (int s = 128; s >= 1; s >>= 1) {
-        if ((int)threadIdx.x < s)
-            for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0)
-        for (int k = 0; k < 3; ++k) a.partials[(size_t)wg * 3 + k] += red[k][0];
+    block_sums<3, 3, true>(th, a.partials, wg);
 }
 
 // pass 3: transpose of grad phi(x) = 3 sum w c phi(src(x, i)) and
@@ -1358,21 +1291,6 @@ __global__ __launch_bounds__(PARAMS_THREADS) void k_adj_params(const double* par
 // (0 when that denominator vanishes). Its transpose needs two global sums:
 // gamma of the state, and dL/dgamma = sum_x dL/dR(x) M phi(x) (1 - phi(x)).
 
-// 256-thread fixed-order block sum of K values per thread into part[wg][4]
-template <int K>
-__device__ __forceinline__ void block_sums(const double (&v)[K], double* part, int wg) {
-    __shared__ double red[K][256];
-    for (int k = 0; k < K; ++k) red[k][threadIdx.x] = v[k];
-    __syncthreads();
-    for (int s = 128; s >= 1; s >>= 1) {
-        if ((int)threadIdx.x < s)
-            for (int k = 0; k < K; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0)
-        for (int k = 0; k < K; ++k) part[(size_t)wg * 4 + k] = red[k][0];
-}
-
 // phi = sum h into work[6], partial sums of gamma's numerator and denominator
 __global__ __launch_bounds__(256) void k_adj_phi_nl(const AdjArgs a) {
     const long long nn = (long long)a.nx * a.ny * a.nz;
@@ -1386,7 +1304,7 @@ __global__ __launch_bounds__(256) void k_adj_phi_nl(const AdjArgs a) {
         v[0] = a.ph.w32 * (s - 1.0) * s * (s - 0.5);
         v[1] = s * (1.0 - s);
     }
-    block_sums<2>(v, a.nlpart, wg);
+    block_sums<2, 4>(v, a.nlpart, wg);
 }
 
 // one workgroup, fixed order. MODE 0: gamma = num / den (0 if den = 0) and
@@ -1456,7 +1374,7 @@ __global__ __launch_bounds__(256) void k_adj_nl_map(const AdjArgs a, const doubl
         v[1] = bR * Rm;
         v[2] = bR * (-2.0 * ph.mob * Rm / a.W);
     }
-    block_sums<3>(v, a.nlpart, wg);
+    block_sums<3, 4>(v, a.nlpart, wg);
 }
 
 // dL/dphi = work[0] + dL/dgamma dgamma/dphi, dgamma/dphi = ((32 / W^2)
@@ -1599,16 +1517,7 @@ __global__ __launch_bounds__(256) void k_adj_init_ch(const AdjArgs a, const doub
         th[0] = cmu * (cub * 48.0 / W - lap * 1.5 * W);
         th[2] = -cmu * (cub * 48.0 * sigma / (W * W) + lap * 1.5 * sigma);
     }
-    __shared__ double red[3][256];
-    for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = th[k];
-    __syncthreads();
-    for (int s = 128; s >= 1; s >>= 1) {
-        if ((int)threadIdx.x < s)
-            for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0)
-        for (int k = 0; k < 3; ++k) a.partials[(size_t)wg * 3 + k] = red[k][0];
+    block_sums<3, 3>(th, a.partials, wg);
 }
 
 // seed of the adjoint from dL/dphi of a state: phi = sum_a h_a (Eq.
