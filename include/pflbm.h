@@ -20,7 +20,8 @@
  *  - Every function returns an int status: PFLBM_OK (0) or a negative
  *    PFLBM_E* code. Nothing throws or aborts across the ABI. After an error on
  *    a handle, pflbm_last_error() returns a message owned by the handle.
- *    PFLBM_EINVAL leaves the handle as it was. After PFLBM_EHIP every later
+ *    PFLBM_EINVAL and PFLBM_EUNSUPPORTED (a rejected call: nothing launched)
+ *    leave the handle as it was. After PFLBM_EHIP every later
  *    call returns PFLBM_ESTATE until the handle is destroyed. After
  *    PFLBM_EUNSTABLE every later call returns PFLBM_ESTATE until
  *    pflbm_init() or pflbm_load_state() replaces the state (recovery from a

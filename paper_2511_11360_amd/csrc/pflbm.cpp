@@ -216,8 +216,9 @@ namespace {
 int fail(pflbm_t* h, int code, const std::string& msg) {
     if (h) {
         h->err = msg;
+        // a rejected call (EINVAL, EUNSUPPORTED) leaves the handle as it was
         if (code == PFLBM_EUNSTABLE) h->unstable = true;
-        else if (code != PFLBM_EINVAL) h->sticky = code;
+        else if (code == PFLBM_EHIP) h->sticky = code;
     }
     return code;
 }
