@@ -309,11 +309,10 @@ int pflbm_adjoint_step_noalloc(pflbm_t* h, const double* fwd_g, const double* fw
    dL/dphi [z][y][x] (device float64), writes lambda = dL/dX for that state,
    lam_g [Qg][z][y][x] = 0 and lam_h [Qh][z][y][x] = dL/dphi for every
    population, the transpose of phi = sum_a h_a (Eq. fakhari_phi_update).
-   every model but the nonlocal one (PFLBM_EUNSUPPORTED there: its phase
+   Every model but the nonlocal one (PFLBM_EUNSUPPORTED there: its phase
    field is corrected, use pflbm_adjoint_seed); for the models with a (phi u)
    state the loss does not depend on pu, so lam_pu of that state is zero (the
-   caller's buffer).
-   Asynchronous. */
+   caller's buffer). Asynchronous. */
 int pflbm_adjoint_seed_phi(pflbm_t* h, const double* dphi, double* lam_g, double* lam_h);
 
 /* The seed for every model with an adjoint: dphi = dL/dphi of the phase field
@@ -330,8 +329,8 @@ int pflbm_adjoint_seed(pflbm_t* h, const double* fwd_h, const double* dphi, doub
 
 /* dL/dphi0 of the equilibrium initialisation (pflbm_init) given
    lambda^0 = dL/dX^0: dphi0 [z][y][x] (device float64, overwritten). u0 and
-   p0 as passed to pflbm_init (NULL = zero). AC and nonlocal models (the CH
-   model goes through pflbm_adjoint_init_pu). */
+   p0 as passed to pflbm_init (NULL = zero). AC and nonlocal models (the
+   models with a (phi u) state go through pflbm_adjoint_init_pu). */
 int pflbm_adjoint_init(pflbm_t* h, const double* phi0, const double* u0, const double* p0,
                        const double* lam_g, const double* lam_h, double* dphi0);
 
@@ -339,8 +338,8 @@ int pflbm_adjoint_init(pflbm_t* h, const double* phi0, const double* u0, const d
    (and Liang2014) initialisation h = h_eq(phi0, mu_phi(phi0), u0) (Eq.
    liang2_geq, mu_phi of Eq. chemical_potential, on the step's Laplacian
    stencil), pu^0 = phi0 u0 (Liang2014: f = f_eq of Eq. liang2_feq at
-   rho(phi0)), depends on sigma and W through mu_phi: their terms are ADDED into dparams
-   (device float64[3], may be NULL). work: workspace of
+   rho(phi0)), depends on sigma and W through mu_phi: their terms are ADDED
+   into dparams (device float64[3], may be NULL). work: workspace of
    pflbm_adjoint_workspace_bytes(). Liang2018: f = f_eq of Eq. liang_feq at
    rho(phi0), h of Eq. liang_geq, pu^0 = phi0 u0 (no parameter terms; dparams
    and work unused). For the AC and nonlocal models lam_pu, dparams and work
