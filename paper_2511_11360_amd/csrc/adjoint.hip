@@ -1219,6 +1219,18 @@ __global__ __launch_bounds__(256) void k_adj_stencil(const AdjArgs a) {
     const double* blap = a.work + 4 * nn;
     double acc = bphi[n] - 6.0 * (1.0 - GL::w(0)) * blap[n];
     const Nbr nb(a, p);
+    // lambda_h^{n+1} through the transposed h streaming, gathered before any
+    // store (a store may alias it, so later loads could not pass it)
+    double lhv[HL::Q];
+    if constexpr (MODE == ST_STEP) {
+        unroll<HL::Q>([&](auto J) {
+            constexpr int al = J;
+            constexpr int cx = HL::c(al, 0), cy = HL::c(al, 1), cz = HL::c(al, 2);
+            const size_t e = nb.beyond(cx, cy, cz) ? (size_t)HL::opp(al) * nn + n
+                                                    : (size_t)al * nn + nb.index(cx, cy, cz);
+            lhv[al] = a.lh[e];
+        });
+    }
     unroll<Q - 1>([&](auto I) {
         constexpr int i = I + 1;
         constexpr int c0 = GL::c(i, 0), c1 = GL::c(i, 1), c2 = GL::c(i, 2);
@@ -1257,10 +1269,7 @@ __global__ __launch_bounds__(256) void k_adj_stencil(const AdjArgs a) {
     const double itp1 = 1.0 - a.ph.inv_tau_phi;
     unroll<HL::Q>([&](auto J) {
         constexpr int al = J;
-        constexpr int cx = HL::c(al, 0), cy = HL::c(al, 1), cz = HL::c(al, 2);
-        const size_t e = nb.beyond(cx, cy, cz) ? (size_t)HL::opp(al) * nn + n
-                                                : (size_t)al * nn + nb.index(cx, cy, cz);
-        a.oh[(size_t)al * nn + n] = itp1 * a.lh[e] + acc;
+        a.oh[(size_t)al * nn + n] = itp1 * lhv[al] + acc;
     });
 }
 
@@ -1399,12 +1408,17 @@ __global__ __launch_bounds__(256) void k_adj_nl_final(const AdjArgs a, double* l
     } else {
         const Nbr nb(a, node_of(n, a));
         const double itp1 = 1.0 - ph.inv_tau_phi;
+        double lhv[HL::Q];   // gathered before any store (see the stencil pass)
         unroll<HL::Q>([&](auto J) {
             constexpr int al = J;
             constexpr int cx = HL::c(al, 0), cy = HL::c(al, 1), cz = HL::c(al, 2);
             const size_t e = nb.beyond(cx, cy, cz) ? (size_t)HL::opp(al) * nn + n
                                                     : (size_t)al * nn + nb.index(cx, cy, cz);
-            a.oh[(size_t)al * nn + n] = itp1 * a.lh[e] + t;
+            lhv[al] = a.lh[e];
+        });
+        unroll<HL::Q>([&](auto J) {
+            constexpr int al = J;
+            a.oh[(size_t)al * nn + n] = itp1 * lhv[al] + t;
         });
     }
 }
