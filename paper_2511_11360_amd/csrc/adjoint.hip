@@ -1305,7 +1305,7 @@ __global__ __launch_bounds__(256) void k_adj_phi_nl(const AdjArgs a) {
     const long long nn = (long long)a.nx * a.ny * a.nz;
     const int wg = xcd_block();
     const long long n = (long long)wg * blockDim.x + threadIdx.x;
-    double v[2] = {0.0, 0.0};
+    double v[3] = {0.0, 0.0, 0.0};   // the third slot is unused (zero)
     if (n < nn) {
         double s = a.fh[n];
         for (int al = 1; al < a.qh; ++al) s += a.fh[(size_t)al * nn + n];
@@ -1313,7 +1313,7 @@ __global__ __launch_bounds__(256) void k_adj_phi_nl(const AdjArgs a) {
         v[0] = a.ph.w32 * (s - 1.0) * s * (s - 0.5);
         v[1] = s * (1.0 - s);
     }
-    block_sums<2, 4>(v, a.nlpart, wg);
+    block_sums<3, 4>(v, a.nlpart, wg);
 }
 
 // one workgroup, fixed order. MODE 0: gamma = num / den (0 if den = 0) and
