@@ -189,7 +189,7 @@ def probes(n, reps=20):
 ADJ_BYTES = 2 * (19 + 7) * 8 + 26 * 8 + 2 * 6 * 8   # lambda in + out, forward g, h, workspace
 
 
-def time_adjoint(steps, model="AC"):
+def time_adjoint(steps, model="AC", arith="fp64"):
     """The discrete adjoint step (float64, canonical layout) on the 128^3
     sheared droplet between moving walls, at the forward state after 20 steps,
     chaining lambda through two buffers. Algorithmic bytes per node: lambda
@@ -198,7 +198,9 @@ def time_adjoint(steps, model="AC"):
     add (phi u) to the state (3 x 8 more in each of the three), the nonlocal
     model two per-node workspace values (sum h and dL/dR, 2 x 2 x 8),
     Liang2014 four (mu_phi, lap phi and their adjoints, 2 x 4 x 8). The Liang
-    models run between stationary walls (the only walls they take)."""
+    models run between stationary walls (the only walls they take). arith
+    "fp32" times the float32 adjoint of the AC step (every array float32 but
+    the phase-field workspace: 368 bytes per node)."""
     import torch
     from paper_2511_11360_amd import workloads as wl
     from paper_2511_11360_amd.solver import Solver
@@ -210,12 +212,13 @@ def time_adjoint(steps, model="AC"):
     s = Solver(d, precision="fp64")
     s.init(phi, u)
     s.step(20)
-    fg, fh = s.get_distributions()
+    f32 = arith == "fp32"
+    fg, fh = s.get_distributions_f32() if f32 else s.get_distributions()
     fpu = s.get_phiu() if ch else None
     gen = torch.Generator(device=fg.device).manual_seed(5)
 
     def rnd(t):
-        return torch.randn(t.shape, dtype=torch.float64, device=fg.device, generator=gen)
+        return torch.randn(t.shape, dtype=t.dtype, device=fg.device, generator=gen)
     lam = [(rnd(fg), rnd(fh), rnd(fpu) if ch else None),
            (torch.empty_like(fg), torch.empty_like(fh), torch.empty_like(fpu) if ch else None)]
     dparams = torch.zeros(3, dtype=torch.float64, device=fg.device)
@@ -226,6 +229,8 @@ def time_adjoint(steps, model="AC"):
             a, b = lam[i % 2], lam[(i + 1) % 2]
             if ch:
                 s.adjoint_step_pu(fg, fh, fpu, a[0], a[1], a[2], b[0], b[1], b[2], dparams, work)
+            elif f32:
+                s.adjoint_step_f32(fg, fh, a[0], a[1], b[0], b[1], dparams, work)
             else:
                 s.adjoint_step(fg, fh, a[0], a[1], b[0], b[1], dparams, work)
     run(max(4, int(PREWARM_MS / 0.45)))
@@ -239,9 +244,11 @@ def time_adjoint(steps, model="AC"):
     nodes = d["nx"] * d["ny"] * d["nz"]
     nb = (ADJ_BYTES + (3 * 3 * 8 if ch else 0) + (2 * 2 * 8 if model == "NL" else 0)
           + (2 * 4 * 8 if model == "L14" else 0))
+    if f32:
+        nb = nb // 2 + 8       # float32 throughout but phi of the forward state (float64: 2 x 8)
     walls = "stationary walls, shear in u0" if model in ("L18", "L14") else "walls moving at -+0.02"
-    return {"workload": "3-D sheared droplet, D3Q19+D3Q7, 128^3, %s (adjoint of the %s step, float64)"
-                        % (walls, model),
+    return {"workload": "3-D sheared droplet, D3Q19+D3Q7, 128^3, %s (adjoint of the %s step, %s)"
+                        % (walls, model, "float32" if f32 else "float64"),
             "ms_per_step": round(ms, 4), "MLUPS": round(nodes / (ms * 1e-3) / 1e6, 1),
             "bytes_per_update": nb,
             "hbm_frac": round(nb * nodes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
@@ -252,8 +259,9 @@ def time_backward(nsteps=200):
     walls moving at -+0.02, loss 1/2 sum (phi_N - phi*)^2) through the
     autograd wrapper, with ceil(sqrt(nsteps)) checkpoints: per step, the
     recompute of the forward step from its segment's checkpoint, the read-out
-    of its state in canonical float64 and the adjoint step. Forward pass
-    (steps plus checkpoints) timed beside it. float64 and float32 forward."""
+    of its state in canonical form and the adjoint step. Forward pass
+    (steps plus checkpoints) timed beside it. float64 and float32 forward
+    with the float64 adjoint, and float32 forward with the float32 one."""
     import torch
     from paper_2511_11360_amd import workloads as wl
     from paper_2511_11360_amd.autograd import run_phase_field
@@ -262,19 +270,19 @@ def time_backward(nsteps=200):
                        "%d steps, %d checkpoints" % (nsteps, math.ceil(math.sqrt(nsteps)))}
     tg = torch.as_tensor(target, device="cuda")
     ut = torch.as_tensor(u, device="cuda")
-    for prec in ("fp64", "fp32"):
+    for key, prec, arith in (("fp64", "fp64", "fp64"), ("fp32", "fp32", "fp64"), ("fp32_adjoint_fp32", "fp32", "fp32")):
         phi0 = torch.as_tensor(phi, device="cuda").requires_grad_(True)
         params = [torch.tensor(d[k], dtype=torch.float64, requires_grad=True) for k in ("sigma", "M", "W")]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        phiN = run_phase_field(phi0, *params, d, ut, nsteps, precision=prec)
+        phiN = run_phase_field(phi0, *params, d, ut, nsteps, precision=prec, adjoint=arith)
         L = 0.5 * ((phiN - tg) ** 2).sum()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         L.backward()
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        out[prec] = {"forward_ms_per_step": round((t1 - t0) * 1e3 / nsteps, 4),
+        out[key] = {"forward_ms_per_step": round((t1 - t0) * 1e3 / nsteps, 4),
                      "backward_ms_per_step": round((t2 - t1) * 1e3 / nsteps, 4)}
         del phi0, params, phiN, L
         torch.cuda.empty_cache()
@@ -547,6 +555,9 @@ def main():
     if not args.no_adjoint:
         log("adjoint")
         adjoint = time_adjoint(100)
+        torch.cuda.empty_cache()
+        log("adjoint, float32")
+        adjoint["fp32"] = time_adjoint(100, arith="fp32")
         torch.cuda.empty_cache()
         log("adjoint, CH")
         adjoint["ch"] = time_adjoint(100, "CH")

@@ -220,6 +220,10 @@ int pflbm_volume(pflbm_t* h, const double* centre, double R, pflbm_diag* out);
    g [Qg][z][y][x] and hd [Qh][z][y][x] (Qh = 5 or 7, rest included). */
 int pflbm_get_distributions(pflbm_t* h, double* g, double* hd);
 
+/* The same read-out in float32 (g and hd float32 arrays of the same layout),
+   the forward state of the float32 adjoint. */
+int pflbm_get_distributions_f32(pflbm_t* h, float* g, float* hd);
+
 /* Overwrite the state from canonical float64 distributions (device pointers,
    same layout as pflbm_get_distributions); the storage form rounds them.
    For AC on D3Q7 the rest population of h must be zero. CH keeps its (phi u)
@@ -289,6 +293,25 @@ int pflbm_adjoint_step_pu(pflbm_t* h, const double* fwd_g, const double* fwd_h, 
                           const double* lam_g, const double* lam_h, const double* lam_pu,
                           double* lam_g_out, double* lam_h_out, double* lam_pu_out,
                           double* dparams, void* work);
+
+/* The float32 adjoint of the AC step (Sec. II.C.1): the passes of
+   pflbm_adjoint_step in float32 arithmetic on float32 arrays of the same
+   layouts (the forward state as pflbm_get_distributions_f32 returns it); the
+   parameter terms are still reduced, and ADDED into dparams, in float64.
+   The phase field of the forward state, its stencils, phi (1 - phi), the
+   cubic term of mu and the non-equilibrium h_eq - h are formed in float64
+   (float32 differences of them cancel inside a droplet); everything else
+   carries float32 rounding. It moves 368 bytes per node against the float64
+   adjoint's 720. work: the workspace of pflbm_adjoint_workspace_bytes().
+   pflbm_adjoint_seed_phi_f32 and pflbm_adjoint_init_f32 are the float32 forms
+   of the seed and of the initialisation adjoint (phi0, u0, p0 float64, as
+   for pflbm_init). PFLBM_EUNSUPPORTED for the other models. */
+int pflbm_adjoint_step_f32(pflbm_t* h, const float* fwd_g, const float* fwd_h,
+                           const float* lam_g, const float* lam_h,
+                           float* lam_g_out, float* lam_h_out, double* dparams, void* work);
+int pflbm_adjoint_seed_phi_f32(pflbm_t* h, const float* dphi, float* lam_g, float* lam_h);
+int pflbm_adjoint_init_f32(pflbm_t* h, const double* phi0, const double* u0, const double* p0,
+                           const float* lam_g, const float* lam_h, float* dphi0);
 
 /* The same adjoint step for callers that cannot allocate device memory
    (code under HIP graph capture, tight serving loops, harnesses that forbid

@@ -18,11 +18,15 @@ from .solver import Solver
 
 class PhaseFieldRun(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, phi0, sigma, M, W, params, u0, nsteps, precision, k):
+    def forward(ctx, phi0, sigma, M, W, params, u0, nsteps, precision, k, adjoint):
         d = dict(params)
         d["sigma"], d["M"], d["W"] = float(sigma), float(M), float(W)
         if d.get("model", "AC") not in ("AC", "CH", "NL", "L18", "L14"):
             raise ValueError("unknown phase-field model %r" % d.get("model"))
+        if adjoint not in ("fp64", "fp32"):
+            raise ValueError("adjoint precision must be 'fp64' or 'fp32', not %r" % (adjoint,))
+        if adjoint == "fp32" and d.get("model", "AC") != "AC":
+            raise ValueError("the float32 adjoint covers the AC model only")
         s = Solver(d, precision=precision, device=phi0.device)
         s.init(phi0, u0)
         nsteps = int(nsteps)
@@ -41,6 +45,7 @@ class PhaseFieldRun(torch.autograd.Function):
         ctx.k = k
         ctx.nsteps = nsteps
         ctx.u0 = u0
+        ctx.adjoint = adjoint
         ctx.save_for_backward(phi0)
         return phiN.to(phi0.dtype)
 
@@ -48,6 +53,8 @@ class PhaseFieldRun(torch.autograd.Function):
     def backward(ctx, grad_phi):
         s = ctx.solver
         (phi0,) = ctx.saved_tensors
+        if ctx.adjoint == "fp32":
+            return PhaseFieldRun._backward_f32(ctx, s, phi0, grad_phi)
         dev = s.device
         shape = s.shape
         # the CH and Liang states also hold (phi u) of the previous step; L
@@ -87,9 +94,38 @@ class PhaseFieldRun(torch.autograd.Function):
         else:
             dphi0 = s.adjoint_init(phi0, ctx.u0, None, lam_g, lam_h)
         return (dphi0.to(phi0.dtype).reshape(phi0.shape), dparams[0], dparams[1], dparams[2],
-                None, None, None, None, None)
+                None, None, None, None, None, None)
+
+    @staticmethod
+    def _backward_f32(ctx, s, phi0, grad_phi):
+        """The same schedule with the float32 adjoint of the AC step: states
+        read out in float32, lambda float32, parameter sums float64."""
+        dev = s.device
+        dparams = torch.zeros(3, dtype=torch.float64, device=dev)
+        work = s.adjoint_workspace()
+        lam_g, lam_h = s.adjoint_seed_phi_f32(grad_phi.to(device=dev).reshape(s.shape))
+        out_g = torch.empty_like(lam_g)
+        out_h = torch.empty_like(lam_h)
+        for start, buf in reversed(ctx.cks):
+            n = min(ctx.k, ctx.nsteps - start)
+            s.load_state(buf)
+            states = []
+            for _ in range(n):
+                states.append(s.get_distributions_f32())
+                s.step(1)
+            for g, h in reversed(states):
+                s.adjoint_step_f32(g, h, lam_g, lam_h, out_g, out_h, dparams, work)
+                lam_g, out_g = out_g, lam_g
+                lam_h, out_h = out_h, lam_h
+            del states
+        dphi0 = s.adjoint_init_f32(phi0, ctx.u0, None, lam_g, lam_h)
+        return (dphi0.to(phi0.dtype).reshape(phi0.shape), dparams[0], dparams[1], dparams[2],
+                None, None, None, None, None, None)
 
 
-def run_phase_field(phi0, sigma, M, W, params, u0=None, nsteps=1, precision="fp64", k=None):
-    """phi after nsteps steps; differentiable in phi0, sigma, M, W."""
-    return PhaseFieldRun.apply(phi0, sigma, M, W, params, u0, nsteps, precision, k)
+def run_phase_field(phi0, sigma, M, W, params, u0=None, nsteps=1, precision="fp64", k=None, adjoint="fp64"):
+    """phi after nsteps steps; differentiable in phi0, sigma, M, W. adjoint
+    picks the arithmetic of the backward pass: "fp64", or "fp32" (AC model
+    only: half the bytes per adjoint step, float32 rounding in the
+    gradient)."""
+    return PhaseFieldRun.apply(phi0, sigma, M, W, params, u0, nsteps, precision, k, adjoint)

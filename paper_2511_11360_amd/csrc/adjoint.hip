@@ -69,7 +69,8 @@ struct Node {
 
 // node coordinates of linear index n (boxes hold fewer than 2^31 nodes, so
 // 32-bit division suffices)
-__device__ __forceinline__ Node node_of(long long n, const AdjArgs& a) {
+template <class A>
+__device__ __forceinline__ Node node_of(long long n, const A& a) {
     const int m = (int)n;
     const int q = m / a.nx;
     Node d;
@@ -97,7 +98,8 @@ struct Nbr {
     int yo[3], xo[3];
     bool bnd[3][3];
 
-    __device__ __forceinline__ Nbr(const AdjArgs& a, Node p) {
+    template <class A>
+    __device__ __forceinline__ Nbr(const A& a, Node p) {
         const int v[3] = {p.x, p.y, p.z};
         const int n3[3] = {a.nx, a.ny, a.nz};
         int o[3][3];
@@ -147,30 +149,30 @@ __host__ __device__ constexpr double stress_norm(int k) {
 // the rows' coefficients of the two-rate projector for the traceless
 // stress Pi (each row's sum over the populations divided by its squared
 // norm), and their transpose (added into b_Pi, upper triangle)
-template <class GL, bool D3>
-__device__ __forceinline__ void stress_coeffs(const double (&Pi)[3][3], double (&A)[5]) {
-    constexpr double N0 = stress_norm<GL, D3>(0), N1 = stress_norm<GL, D3>(1), N2 = stress_norm<GL, D3>(2),
-                     N3 = stress_norm<GL, D3>(3), N4 = stress_norm<GL, D3>(4);
+template <class GL, bool D3, class R>
+__device__ __forceinline__ void stress_coeffs(const R (&Pi)[3][3], R (&A)[5]) {
+    constexpr R N0 = stress_norm<GL, D3>(0), N1 = stress_norm<GL, D3>(1), N2 = stress_norm<GL, D3>(2),
+                N3 = stress_norm<GL, D3>(3), N4 = stress_norm<GL, D3>(4);
     if constexpr (D3) {
-        A[0] = (2.0 * Pi[0][0] - Pi[1][1] - Pi[2][2]) / N0;
+        A[0] = (R(2) * Pi[0][0] - Pi[1][1] - Pi[2][2]) / N0;
         A[1] = (Pi[1][1] - Pi[2][2]) / N1;
         A[2] = Pi[0][1] / N2;
         A[3] = Pi[1][2] / N3;
         A[4] = Pi[0][2] / N4;
     } else {
         A[0] = (Pi[0][0] - Pi[1][1]) / N0;
-        A[1] = 0.0;
+        A[1] = R(0);
         A[2] = Pi[0][1] / N2;
-        A[3] = 0.0;
-        A[4] = 0.0;
+        A[3] = R(0);
+        A[4] = R(0);
     }
 }
-template <class GL, bool D3>
-__device__ __forceinline__ void stress_coeffs_T(const double (&b_A)[5], double (&b_Pi)[3][3]) {
-    constexpr double N0 = stress_norm<GL, D3>(0), N1 = stress_norm<GL, D3>(1), N2 = stress_norm<GL, D3>(2),
-                     N3 = stress_norm<GL, D3>(3), N4 = stress_norm<GL, D3>(4);
+template <class GL, bool D3, class R>
+__device__ __forceinline__ void stress_coeffs_T(const R (&b_A)[5], R (&b_Pi)[3][3]) {
+    constexpr R N0 = stress_norm<GL, D3>(0), N1 = stress_norm<GL, D3>(1), N2 = stress_norm<GL, D3>(2),
+                N3 = stress_norm<GL, D3>(3), N4 = stress_norm<GL, D3>(4);
     if constexpr (D3) {
-        b_Pi[0][0] += 2.0 * b_A[0] / N0;
+        b_Pi[0][0] += R(2) * b_A[0] / N0;
         b_Pi[1][1] += -b_A[0] / N0 + b_A[1] / N1;
         b_Pi[2][2] += -b_A[0] / N0 - b_A[1] / N1;
         b_Pi[0][1] += b_A[2] / N2;
@@ -185,12 +187,12 @@ __device__ __forceinline__ void stress_coeffs_T(const double (&b_A)[5], double (
 
 // moments of the hydrodynamic populations: sum g, sum c g, sum c c g; and
 // the transpose, added into b_g (b_m2 upper triangle)
-template <class GL>
-__device__ __forceinline__ void moments(const double (&g)[GL::Q], double& ps, double (&j)[3], double (&m2)[3][3]) {
-    ps = 0.0;
+template <class GL, class R>
+__device__ __forceinline__ void moments(const R (&g)[GL::Q], R& ps, R (&j)[3], R (&m2)[3][3]) {
+    ps = R(0);
     for (int k = 0; k < 3; ++k) {
-        j[k] = 0.0;
-        for (int l = 0; l < 3; ++l) m2[k][l] = 0.0;
+        j[k] = R(0);
+        for (int l = 0; l < 3; ++l) m2[k][l] = R(0);
     }
     unroll<GL::Q>([&](auto I) {
         constexpr int i = I;
@@ -201,11 +203,10 @@ __device__ __forceinline__ void moments(const double (&g)[GL::Q], double& ps, do
         }
     });
 }
-template <class GL>
-__device__ __forceinline__ void moments_T(double b_ps, const double (&b_j)[3], const double (&b_m2)[3][3],
-                                          double (&b_g)[GL::Q]) {
+template <class GL, class R>
+__device__ __forceinline__ void moments_T(R b_ps, const R (&b_j)[3], const R (&b_m2)[3][3], R (&b_g)[GL::Q]) {
     for (int i = 0; i < GL::Q; ++i) {
-        double b = b_ps;
+        R b = b_ps;
         for (int k = 0; k < 3; ++k) {
             b += GL::c(i, k) * b_j[k];
             for (int l = k; l < 3; ++l) b += GL::c(i, k) * GL::c(i, l) * b_m2[k][l];
@@ -216,9 +217,9 @@ __device__ __forceinline__ void moments_T(double b_ps, const double (&b_j)[3], c
 
 // dL/dphi through nu(phi) (linear mu over rho, or linear nu), irho = 1 /
 // rho(phi) and rho = rhoL + phi dRho, from their adjoints
-__device__ __forceinline__ double phys_T(const Phys& ph, double irho, double numu, double b_nu, double b_irho,
-                                         double b_rho) {
-    double b_phi = 0.0;
+template <class R>
+__device__ __forceinline__ R phys_T(const PhysT<R>& ph, R irho, R numu, R b_nu, R b_irho, R b_rho) {
+    R b_phi = R(0);
     if (ph.visc_mu) {
         b_phi += ph.dMu * irho * b_nu;
         b_irho += numu * b_nu;
@@ -227,6 +228,14 @@ __device__ __forceinline__ double phys_T(const Phys& ph, double irho, double num
     }
     b_rho += -irho * irho * b_irho;
     return b_phi + ph.dRho * b_rho;
+}
+
+// the physical parameters in the arithmetic type of a kernel (float64: the
+// kernel argument itself, read where used)
+template <class R>
+__device__ __forceinline__ decltype(auto) phys_as(const Phys& p) {
+    if constexpr (sizeof(R) == sizeof(double)) return (p);
+    else return to_float(p);
 }
 
 // 256-thread fixed-order block sums of K values per thread into
@@ -250,10 +259,15 @@ __device__ __forceinline__ void block_sums(const double (&v)[K], double* part, i
 
 }  // namespace
 
-__global__ __launch_bounds__(256) void k_adj_phi(const AdjArgs a) {
+template <class R>
+__global__ __launch_bounds__(256) void k_adj_phi(const AdjArgsT<R> a) {
     const long long nn = (long long)a.nx * a.ny * a.nz;
     const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= nn) return;
+    // summed in float64 also for the float32 adjoint: where phi is near 1
+    // and its gradient small (inside a droplet), the interface normal's
+    // adjoint scales with 1 / |grad phi|, and float32 differences of phi
+    // would carry absolute errors of one float32 ulp of 1 into it
     double s = a.fh[n];
     for (int al = 1; al < a.qh; ++al) s += a.fh[(size_t)al * nn + n];
     a.phi[n] = s;
@@ -265,8 +279,8 @@ __global__ __launch_bounds__(256) void k_adj_phi(const AdjArgs a) {
 // (phi u) of the previous step is part of the state); MODEL 2: the nonlocal
 // AC (Eqs. Chai_geq, Hu_G; phi here is the corrected phi* of the phase-field
 // pass, the nonlocal source R is formed from sum h of the node)
-template <class PAIR, int MODEL>
-__global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
+template <class PAIR, int MODEL, class R = double>
+__global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgsT<R> a) {
     using GL = typename PAIR::G;
     using HL = typename PAIR::H;
     constexpr int Q = GL::Q, QH = HL::Q;
@@ -274,11 +288,12 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
     const long long nn = (long long)a.nx * a.ny * a.nz;
     const int wg = xcd_block();
     const long long n = (long long)wg * blockDim.x + threadIdx.x;
-    double th[3] = {0.0, 0.0, 0.0};   // d sigma, d M, d W of this node
+    double th[3] = {R(0.0), R(0.0), R(0.0)};   // d sigma, d M, d W of this node
     if (n < nn) {
         const Node p = node_of(n, a);
-        const Phys& ph = a.ph;
-        double g[Q], h[QH], phin[Q];
+        const auto& ph = phys_as<R>(a.ph);
+        R g[Q], h[QH];
+        double phin[Q];
         for (int i = 0; i < Q; ++i) g[i] = a.fg[(size_t)i * nn + n];
         for (int al = 0; al < QH; ++al) h[al] = a.fh[(size_t)al * nn + n];
         const Nbr nb(a, p);
@@ -286,67 +301,74 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
             constexpr int i = I;
             phin[i] = a.phi[nb.index(GL::c(i, 0), GL::c(i, 1), GL::c(i, 2))];
         });
-        // ---------------- forward intermediates (as in the step kernel)
-        const double phi = phin[0];
-        double gr[3] = {0.0, 0.0, 0.0}, lap = 0.0;
-        unroll<Q>([&](auto I) {
-            constexpr int i = I;
-            if constexpr (i > 0) {
-                for (int k = 0; k < 3; ++k) gr[k] += 3.0 * GL::w(i) * GL::c(i, k) * phin[i];
-                lap += 6.0 * GL::w(i) * (phin[i] - phi);
-            }
-        });
-        const double dR = ph.dRho;
-        const double rho = ph.rhoL + phi * dR;
-        const double irho = 1.0 / rho;
-        const double numu = ph.muL + phi * ph.dMu;
-        const double nu = ph.visc_mu ? numu * irho : ph.nuL + phi * ph.dNu;
-        const double tau = 3.0 * nu + 0.5;
-        const double itau = 1.0 / tau;
-        const double cub = phi * (phi - 1.0) * (phi - 0.5);
-        const double mu = ph.beta4 * cub - ph.kappa * lap;
-        double ps, j[3], m2[3][3];
+        // ---------------- forward intermediates (as in the step kernel); the
+        // stencils and phi (1 - phi) are formed in float64 from the float64
+        // phi and rounded once (no cancellation left for the float32 form)
+        const R phi = R(phin[0]);
+        R gr[3], lap;
+        {
+            double grd[3] = {0.0, 0.0, 0.0}, lapd = 0.0;
+            unroll<Q>([&](auto I) {
+                constexpr int i = I;
+                if constexpr (i > 0) {
+                    for (int k = 0; k < 3; ++k) grd[k] += 3.0 * GL::w(i) * GL::c(i, k) * phin[i];
+                    lapd += 6.0 * GL::w(i) * (phin[i] - phin[0]);
+                }
+            });
+            for (int k = 0; k < 3; ++k) gr[k] = R(grd[k]);
+            lap = R(lapd);
+        }
+        const R dR = ph.dRho;
+        const R rho = ph.rhoL + phi * dR;
+        const R irho = R(1.0) / rho;
+        const R numu = ph.muL + phi * ph.dMu;
+        const R nu = ph.visc_mu ? numu * irho : ph.nuL + phi * ph.dNu;
+        const R tau = R(3.0) * nu + R(0.5);
+        const R itau = R(1.0) / tau;
+        const R cub = R(phin[0] * (phin[0] - 1.0) * (phin[0] - 0.5));
+        const R mu = ph.beta4 * cub - ph.kappa * lap;
+        R ps, j[3], m2[3][3];
         moments<GL>(g, ps, j, m2);
-        const double sg = mu - ps * dR / 3.0;
-        double F0[3], us[3], S[3][3], F[3], u[3];
+        const R sg = mu - ps * dR / R(3.0);
+        R F0[3], us[3], S[3][3], F[3], u[3];
         for (int k = 0; k < 3; ++k) F0[k] = sg * gr[k] + rho * ph.body[k] + ph.force[k];
-        for (int k = 0; k < 3; ++k) us[k] = j[k] + F0[k] * 0.5 * irho;
-        const double s3 = ps / 3.0;
-        const double sfac = -3.0 * itau;
+        for (int k = 0; k < 3; ++k) us[k] = j[k] + F0[k] * R(0.5) * irho;
+        const R s3 = ps / R(3.0);
+        const R sfac = -R(3.0) * itau;
         const int dmax = D3 ? 3 : 2;
         for (int k = 0; k < 3; ++k)
             for (int l = 0; l < 3; ++l)
                 S[k][l] = (k < dmax && l < dmax)
-                              ? sfac * (m2[k][l] - (k == l ? s3 : 0.0) - us[k] * us[l]) : 0.0;
-        const double nr = nu * dR;
-        double Sg[3];
+                              ? sfac * (m2[k][l] - (k == l ? s3 : R(0.0)) - us[k] * us[l]) : R(0.0);
+        const R nr = nu * dR;
+        R Sg[3];
         for (int k = 0; k < 3; ++k) Sg[k] = S[k][0] * gr[0] + S[k][1] * gr[1] + S[k][2] * gr[2];
         for (int k = 0; k < 3; ++k) F[k] = F0[k] + nr * Sg[k];
-        for (int k = 0; k < 3; ++k) u[k] = j[k] + F[k] * 0.5 * irho;
-        const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-        const double so = ph.s_o;
-        const double dS = itau - so;
-        const double ffac = (1.0 - 0.5 * so) * 3.0 * irho;
-        const double aeq = ps - 1.5 * usq;
-        double Pi[3][3];
+        for (int k = 0; k < 3; ++k) u[k] = j[k] + F[k] * R(0.5) * irho;
+        const R usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        const R so = ph.s_o;
+        const R dS = itau - so;
+        const R ffac = (R(1.0) - R(0.5) * so) * R(3.0) * irho;
+        const R aeq = ps - R(1.5) * usq;
+        R Pi[3][3];
         for (int k = 0; k < 3; ++k)
             for (int l = 0; l < 3; ++l)
-                Pi[k][l] = m2[k][l] - (k == l ? s3 : 0.0) - u[k] * u[l];
+                Pi[k][l] = m2[k][l] - (k == l ? s3 : R(0.0)) - u[k] * u[l];
         // stress-projection coefficients (linear in Pi), each row's sum over
         // the populations divided by its squared norm
-        double A[5];
+        R A[5];
         stress_coeffs<GL, D3>(Pi, A);
-        auto qrow = [&](int i, double* q) {   // stress rows evaluated at c_i
+        auto qrow = [&](int i, R* q) {   // stress rows evaluated at c_i
             for (int k = 0; k < 5; ++k) q[k] = stress_row<GL, D3>(k, i);
         };
-        const double gg = gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2];
-        const double sn = gg + ph.eps2;
-        const double rn = sn > 0.0 ? 1.0 / sqrt(sn) : 0.0;   // guarded normal at eps = 0
-        const double pp = phi * (1.0 - phi);
-        const double coef = ph.anti * pp * rn;
-        const double itp = ph.inv_tau_phi, gfp = ph.g_fac_phi;
+        const R gg = gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2];
+        const R sn = gg + ph.eps2;
+        const R rn = sn > R(0.0) ? R(1.0) / sqrt(sn) : R(0.0);   // guarded normal at eps = 0
+        const R pp = R(phin[0] * (1.0 - phin[0]));
+        const R coef = ph.anti * pp * rn;
+        const R itp = ph.inv_tau_phi, gfp = ph.g_fac_phi;
         // CH: (phi u) of this step and of the previous one (state)
-        double puc[3] = {0.0, 0.0, 0.0}, pup[3] = {0.0, 0.0, 0.0};
+        R puc[3] = {R(0.0), R(0.0), R(0.0)}, pup[3] = {R(0.0), R(0.0), R(0.0)};
         if constexpr (MODEL == 1) {
             for (int k = 0; k < 3; ++k) {
                 puc[k] = phi * u[k];
@@ -358,7 +380,7 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
         // lambda* : adjoint of the post-collision populations (stream transpose),
         // gathered here, where the sweep first needs it;
         // beyond a wall, the bounce-back slot opp(i) of the node itself
-        double lg[Q], lh[QH];
+        R lg[Q], lh[QH];
         unroll<Q>([&](auto I) {
             constexpr int i = I;
             constexpr int cx = GL::c(i, 0), cy = GL::c(i, 1), cz = GL::c(i, 2);
@@ -373,41 +395,41 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
                                                     : (size_t)al * nn + nb.index(cx, cy, cz);
             lh[al] = a.lh[e];
         });
-        double b_g[Q];
-        double b_phi = 0.0, b_gr[3] = {0.0, 0.0, 0.0}, b_lap = 0.0;
-        double b_u[3] = {0.0, 0.0, 0.0}, b_F[3] = {0.0, 0.0, 0.0};
-        double b_ps = 0.0, b_irho = 0.0, b_itau = 0.0, b_usq = 0.0, b_aeq = 0.0;
-        double b_coef = 0.0, b_anti = 0.0, b_itp = 0.0, b_gfp = 0.0;
-        double b_Pi[3][3] = {{0.0}};
-        double b_muh = 0.0;   // CH: mu_phi through h_eq
-        double b_R = 0.0;     // nonlocal: the source R through G
+        R b_g[Q];
+        R b_phi = R(0.0), b_gr[3] = {R(0.0), R(0.0), R(0.0)}, b_lap = R(0.0);
+        R b_u[3] = {R(0.0), R(0.0), R(0.0)}, b_F[3] = {R(0.0), R(0.0), R(0.0)};
+        R b_ps = R(0.0), b_irho = R(0.0), b_itau = R(0.0), b_usq = R(0.0), b_aeq = R(0.0);
+        R b_coef = R(0.0), b_anti = R(0.0), b_itp = R(0.0), b_gfp = R(0.0);
+        R b_Pi[3][3] = {{R(0.0)}};
+        R b_muh = R(0.0);   // CH: mu_phi through h_eq
+        R b_R = R(0.0);     // nonlocal: the source R through G
 
         if constexpr (MODEL == 1) {
             // h*_a = (1 - itp) h_a + itp heq_a + gfp G_a with
             // heq_0 = phi + (w_0 - 1) eta mu, heq_a = w_a eta mu + 3 w_a e_a . (phi u),
             // G_a = 3 w_a e_a . ((phi u) - (phi u)_prev); (phi u) is also stored
             // for the next step, whose adjoint lambda_pu^{n+1} arrives at the node
-            double b_puc[3], b_pup[3] = {0.0, 0.0, 0.0};
+            R b_puc[3], b_pup[3] = {R(0.0), R(0.0), R(0.0)};
             for (int k = 0; k < 3; ++k) b_puc[k] = a.lpu[(size_t)k * nn + n];
             unroll<QH>([&](auto J) {
                 constexpr int al = J;
-                constexpr double w = HL::w(al);
+                constexpr R w = R(HL::w(al));
                 constexpr int ex = HL::c(al, 0), ey = HL::c(al, 1), ez = HL::c(al, 2);
-                const double lb = lh[al];
-                const double bheq = itp * lb;
-                double heq, G = 0.0;
+                const R lb = lh[al];
+                const R bheq = itp * lb;
+                R heq, G = R(0.0);
                 if constexpr (al == 0) {
-                    heq = phi + (w - 1.0) * ph.eta * mu;
+                    heq = phi + (w - R(1.0)) * ph.eta * mu;
                     b_phi += bheq;
-                    b_muh += (w - 1.0) * ph.eta * bheq;
+                    b_muh += (w - R(1.0)) * ph.eta * bheq;
                 } else {
-                    const double ep = ex * puc[0] + ey * puc[1] + ez * puc[2];
-                    const double eq = ex * pup[0] + ey * pup[1] + ez * pup[2];
-                    heq = w * ph.eta * mu + 3.0 * w * ep;
-                    G = 3.0 * w * (ep - eq);
+                    const R ep = ex * puc[0] + ey * puc[1] + ez * puc[2];
+                    const R eq = ex * pup[0] + ey * pup[1] + ez * pup[2];
+                    heq = w * ph.eta * mu + R(3.0) * w * ep;
+                    G = R(3.0) * w * (ep - eq);
                     b_muh += w * ph.eta * bheq;
-                    const double t = 3.0 * w * (bheq + gfp * lb);
-                    const double tp = 3.0 * w * gfp * lb;
+                    const R t = R(3.0) * w * (bheq + gfp * lb);
+                    const R tp = R(3.0) * w * gfp * lb;
                     b_puc[0] += ex * t;
                     b_puc[1] += ey * t;
                     b_puc[2] += ez * t;
@@ -429,75 +451,77 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
             // (1 + 3 e_a . u), G_a = lam w_a coef (e_a . gr) + (1 - lam) w_a R,
             // R = M (gamma phi_s (1 - phi_s) - (32 / W^2) phi_s (phi_s - 1)
             // (phi_s - 1/2)) at phi_s = sum h (summed in the phi pass's order)
-            double hs = h[0];
+            R hs = h[0];
             for (int al = 1; al < QH; ++al) hs += h[al];
-            const double gam = a.nls[0];
-            const double R = ph.mob * (gam * hs * (1.0 - hs) - ph.w32 * (hs - 1.0) * hs * (hs - 0.5));
-            const double lam = ph.lam;
+            const R gam = a.nls[0];
+            const R Rs = ph.mob * (gam * hs * (R(1.0) - hs) - ph.w32 * (hs - R(1.0)) * hs * (hs - R(0.5)));
+            const R lam = ph.lam;
             for (int al = 0; al < QH; ++al) {
-                const double w = HL::w(al);
-                const double eu = HL::c(al, 0) * u[0] + HL::c(al, 1) * u[1] + HL::c(al, 2) * u[2];
-                const double eg = HL::c(al, 0) * gr[0] + HL::c(al, 1) * gr[1] + HL::c(al, 2) * gr[2];
-                const double heq = w * phi * (1.0 + 3.0 * eu);
-                const double lb = lh[al];
+                const R w = R(HL::w(al));
+                const R eu = HL::c(al, 0) * u[0] + HL::c(al, 1) * u[1] + HL::c(al, 2) * u[2];
+                const R eg = HL::c(al, 0) * gr[0] + HL::c(al, 1) * gr[1] + HL::c(al, 2) * gr[2];
+                const R heq = w * phi * (R(1.0) + R(3.0) * eu);
+                const R lb = lh[al];
                 b_itp += (heq - h[al]) * lb;
-                b_gfp += (lam * w * coef * eg + (1.0 - lam) * w * R) * lb;
+                b_gfp += (lam * w * coef * eg + (R(1.0) - lam) * w * Rs) * lb;
                 b_coef += gfp * lam * w * eg * lb;
                 for (int k = 0; k < 3; ++k) b_gr[k] += gfp * lam * w * coef * HL::c(al, k) * lb;
-                b_R += gfp * (1.0 - lam) * w * lb;
-                const double bheq = itp * lb;
-                b_phi += bheq * w * (1.0 + 3.0 * eu);
-                for (int k = 0; k < 3; ++k) b_u[k] += bheq * w * phi * 3.0 * HL::c(al, k);
+                b_R += gfp * (R(1.0) - lam) * w * lb;
+                const R bheq = itp * lb;
+                b_phi += bheq * w * (R(1.0) + R(3.0) * eu);
+                for (int k = 0; k < 3; ++k) b_u[k] += bheq * w * phi * R(3.0) * HL::c(al, k);
             }
             b_anti += b_coef * pp * rn;
-            b_phi += b_coef * ph.anti * (1.0 - 2.0 * phi) * rn;
-            const double b_rn = b_coef * ph.anti * pp;
-            const double b_gg = -0.5 * rn * rn * rn * b_rn;
-            for (int k = 0; k < 3; ++k) b_gr[k] += 2.0 * gr[k] * b_gg;
+            b_phi += b_coef * ph.anti * (R(1.0) - R(2.0) * phi) * rn;
+            const R b_rn = b_coef * ph.anti * pp;
+            const R b_gg = -R(0.5) * rn * rn * rn * b_rn;
+            for (int k = 0; k < 3; ++k) b_gr[k] += R(2.0) * gr[k] * b_gg;
         } else {
-        // h*_a = (1 - itp) h_a + itp heq_a + gfp w_a coef (e_a . gr)
+        // h*_a = (1 - itp) h_a + itp heq_a + gfp w_a coef (e_a . gr); the
+        // non-equilibrium heq_a - h_a (small against h_a) as (w_a phi - h_a),
+        // formed in float64, plus w_a phi (base - 1)
         for (int al = 0; al < QH; ++al) {
-            const double w = HL::w(al);
-            const double eu = HL::c(al, 0) * u[0] + HL::c(al, 1) * u[1] + HL::c(al, 2) * u[2];
-            const double eg = HL::c(al, 0) * gr[0] + HL::c(al, 1) * gr[1] + HL::c(al, 2) * gr[2];
-            const double base = 1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * usq;
-            const double heq = w * phi * base;
-            const double lb = lh[al];
-            b_itp += (heq - h[al]) * lb;
+            const R w = R(HL::w(al));
+            const R eu = HL::c(al, 0) * u[0] + HL::c(al, 1) * u[1] + HL::c(al, 2) * u[2];
+            const R eg = HL::c(al, 0) * gr[0] + HL::c(al, 1) * gr[1] + HL::c(al, 2) * gr[2];
+            const R bm1 = R(3.0) * eu + R(4.5) * eu * eu - R(1.5) * usq;
+            const R base = R(1.0) + bm1;
+            const R lb = lh[al];
+            b_itp += (R(HL::w(al) * phin[0] - (double)h[al]) + w * phi * bm1) * lb;
             b_gfp += w * coef * eg * lb;
             b_coef += gfp * w * eg * lb;
             for (int k = 0; k < 3; ++k) b_gr[k] += gfp * w * coef * HL::c(al, k) * lb;
-            const double bheq = itp * lb;
+            const R bheq = itp * lb;
             b_phi += bheq * w * base;
             for (int k = 0; k < 3; ++k)
-                b_u[k] += bheq * w * phi * (3.0 * HL::c(al, k) + 9.0 * eu * HL::c(al, k));
-            b_usq += -1.5 * bheq * w * phi;
+                b_u[k] += bheq * w * phi * (R(3.0) * HL::c(al, k) + R(9.0) * eu * HL::c(al, k));
+            b_usq += -R(1.5) * bheq * w * phi;
         }
         // coef = anti phi (1 - phi) (gg + eps^2)^(-1/2)
         b_anti += b_coef * pp * rn;
-        b_phi += b_coef * ph.anti * (1.0 - 2.0 * phi) * rn;
+        b_phi += b_coef * ph.anti * (R(1.0) - R(2.0) * phi) * rn;
         {
-            const double b_rn = b_coef * ph.anti * pp;
-            const double b_gg = -0.5 * rn * rn * rn * b_rn;
-            for (int k = 0; k < 3; ++k) b_gr[k] += 2.0 * gr[k] * b_gg;
+            const R b_rn = b_coef * ph.anti * pp;
+            const R b_gg = -R(0.5) * rn * rn * rn * b_rn;
+            for (int k = 0; k < 3; ++k) b_gr[k] += R(2.0) * gr[k] * b_gg;
         }
         }
         // g*_i = (1 - so) g_i + so geq_i - dS P_i + ffac w_i (c_i . F)
-        double b_A[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        double b_dS = 0.0, b_ffac = 0.0;
+        R b_A[5] = {R(0.0), R(0.0), R(0.0), R(0.0), R(0.0)};
+        R b_dS = R(0.0), b_ffac = R(0.0);
         for (int i = 0; i < Q; ++i) {
-            const double w = GL::w(i);
-            const double cu = GL::c(i, 0) * u[0] + GL::c(i, 1) * u[1] + GL::c(i, 2) * u[2];
-            const double cf = GL::c(i, 0) * F[0] + GL::c(i, 1) * F[1] + GL::c(i, 2) * F[2];
-            double q[5];
+            const R w = R(GL::w(i));
+            const R cu = GL::c(i, 0) * u[0] + GL::c(i, 1) * u[1] + GL::c(i, 2) * u[2];
+            const R cf = GL::c(i, 0) * F[0] + GL::c(i, 1) * F[1] + GL::c(i, 2) * F[2];
+            R q[5];
             qrow(i, q);
-            double P = 0.0;
+            R P = R(0.0);
             for (int k = 0; k < 5; ++k) P += q[k] * A[k];
-            const double lb = lg[i];
-            b_g[i] = (1.0 - so) * lb;
-            const double bgeq = so * lb;
+            const R lb = lg[i];
+            b_g[i] = (R(1.0) - so) * lb;
+            const R bgeq = so * lb;
             b_aeq += w * bgeq;
-            for (int k = 0; k < 3; ++k) b_u[k] += w * bgeq * (3.0 * GL::c(i, k) + 9.0 * cu * GL::c(i, k));
+            for (int k = 0; k < 3; ++k) b_u[k] += w * bgeq * (R(3.0) * GL::c(i, k) + R(9.0) * cu * GL::c(i, k));
             for (int k = 0; k < 5; ++k) b_A[k] += -dS * q[k] * lb;
             b_dS += -P * lb;
             b_ffac += w * cf * lb;
@@ -506,14 +530,14 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
         // A (linear in Pi)
         stress_coeffs_T<GL, D3>(b_A, b_Pi);
         // Pi_kl = m2_kl - delta s3 - u_k u_l (only k <= l entries carry adjoints)
-        double b_m2[3][3] = {{0.0}}, b_s3 = 0.0;
+        R b_m2[3][3] = {{R(0.0)}}, b_s3 = R(0.0);
         for (int k = 0; k < 3; ++k)
             for (int l = k; l < 3; ++l) {
-                const double b = b_Pi[k][l];
+                const R b = b_Pi[k][l];
                 b_m2[k][l] += b;
                 if (k == l) {
                     b_s3 -= b;
-                    b_u[k] -= 2.0 * u[k] * b;
+                    b_u[k] -= R(2.0) * u[k] * b;
                 } else {
                     b_u[k] -= u[l] * b;
                     b_u[l] -= u[k] * b;
@@ -521,19 +545,19 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
             }
         // aeq = ps - 1.5 usq ; usq = u.u ; dS = itau - so ; ffac = (1 - so/2) 3 irho
         b_ps += b_aeq;
-        b_usq += -1.5 * b_aeq;
-        for (int k = 0; k < 3; ++k) b_u[k] += 2.0 * u[k] * b_usq;
+        b_usq += -R(1.5) * b_aeq;
+        for (int k = 0; k < 3; ++k) b_u[k] += R(2.0) * u[k] * b_usq;
         b_itau += b_dS;
-        b_irho += (1.0 - 0.5 * so) * 3.0 * b_ffac;
+        b_irho += (R(1.0) - R(0.5) * so) * R(3.0) * b_ffac;
         // u = j + F irho / 2
-        double b_j[3];
+        R b_j[3];
         for (int k = 0; k < 3; ++k) {
             b_j[k] = b_u[k];
-            b_F[k] += 0.5 * irho * b_u[k];
-            b_irho += 0.5 * F[k] * b_u[k];
+            b_F[k] += R(0.5) * irho * b_u[k];
+            b_irho += R(0.5) * F[k] * b_u[k];
         }
         // F = F0 + nr S gr
-        double b_F0[3], b_S[3][3] = {{0.0}}, b_nr = 0.0;
+        R b_F0[3], b_S[3][3] = {{R(0.0)}}, b_nr = R(0.0);
         for (int k = 0; k < 3; ++k) {
             b_F0[k] = b_F[k];
             b_nr += b_F[k] * Sg[k];
@@ -542,57 +566,57 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgs a) {
                 b_gr[l] += nr * S[k][l] * b_F[k];
             }
         }
-        double b_nu = b_nr * dR;
+        R b_nu = b_nr * dR;
         // S_kl = sfac (m2_kl - delta s3 - us_k us_l)  (full symmetric 3 x 3)
-        double b_us[3] = {0.0, 0.0, 0.0}, b_sfac = 0.0;
+        R b_us[3] = {R(0.0), R(0.0), R(0.0)}, b_sfac = R(0.0);
         for (int k = 0; k < dmax; ++k)
             for (int l = 0; l < dmax; ++l) {
-                const double b = b_S[k][l];
-                b_sfac += b * (m2[k][l] - (k == l ? s3 : 0.0) - us[k] * us[l]);
-                const double bs = sfac * b;
+                const R b = b_S[k][l];
+                b_sfac += b * (m2[k][l] - (k == l ? s3 : R(0.0)) - us[k] * us[l]);
+                const R bs = sfac * b;
                 if (k <= l) b_m2[k][l] += bs;
                 else b_m2[l][k] += bs;
                 if (k == l) b_s3 -= bs;
                 b_us[k] -= bs * us[l];
                 b_us[l] -= bs * us[k];
             }
-        b_itau += -3.0 * b_sfac;
-        b_ps += b_s3 / 3.0;
+        b_itau += -R(3.0) * b_sfac;
+        b_ps += b_s3 / R(3.0);
         // us = j + F0 irho / 2
         for (int k = 0; k < 3; ++k) {
             b_j[k] += b_us[k];
-            b_F0[k] += 0.5 * irho * b_us[k];
-            b_irho += 0.5 * F0[k] * b_us[k];
+            b_F0[k] += R(0.5) * irho * b_us[k];
+            b_irho += R(0.5) * F0[k] * b_us[k];
         }
         // F0 = sg gr + rho body + force
-        double b_sg = 0.0, b_rho = 0.0;
+        R b_sg = R(0.0), b_rho = R(0.0);
         for (int k = 0; k < 3; ++k) {
             b_sg += b_F0[k] * gr[k];
             b_gr[k] += sg * b_F0[k];
             b_rho += ph.body[k] * b_F0[k];
         }
         // sg = mu - ps dR / 3
-        const double b_mu = b_sg + b_muh;
-        b_ps += -b_sg * dR / 3.0;
+        const R b_mu = b_sg + b_muh;
+        b_ps += -b_sg * dR / R(3.0);
         // moments
         moments_T<GL>(b_ps, b_j, b_m2, b_g);
         // mu = beta4 phi (phi - 1)(phi - 1/2) - kappa lap
-        const double b_beta4 = b_mu * cub;
-        const double b_kappa = -b_mu * lap;
+        const R b_beta4 = b_mu * cub;
+        const R b_kappa = -b_mu * lap;
         b_lap += -ph.kappa * b_mu;
-        b_phi += b_mu * ph.beta4 * (3.0 * phi * phi - 3.0 * phi + 0.5);
+        b_phi += b_mu * ph.beta4 * (R(3.0) * phi * phi - R(3.0) * phi + R(0.5));
         // itau = 1 / tau, tau = 3 nu + 1/2; nu, irho = 1 / rho, rho = rhoL + phi dR
-        b_nu += 3.0 * (-itau * itau * b_itau);
+        b_nu += R(3.0) * (-itau * itau * b_itau);
         b_phi += phys_T(ph, irho, numu, b_nu, b_irho, b_rho);
 
         // parameters: beta4 = 48 sigma / W, kappa = 1.5 sigma W, anti = 4 / W,
         // itp = 1 / (3 M + 1/2), gfp = 1 - itp / 2 (the nonlocal source's M and
         // W terms are formed with its total adjoint, after the stencil pass)
-        const double sigma = a.sigma, W = a.W;
-        th[0] = b_beta4 * 48.0 / W + b_kappa * 1.5 * W;
-        const double b_itp_tot = b_itp - 0.5 * b_gfp;
-        th[1] = -(MODEL == 1 ? 3.0 / ph.eta : 3.0) * itp * itp * b_itp_tot;   // tau_phi = 3 M (/ eta) + 1/2
-        th[2] = -b_beta4 * 48.0 * sigma / (W * W) + b_kappa * 1.5 * sigma - b_anti * 4.0 / (W * W);
+        const R sigma = R(a.sigma), W = R(a.W);
+        th[0] = b_beta4 * R(48.0) / W + b_kappa * R(1.5) * W;
+        const R b_itp_tot = b_itp - R(0.5) * b_gfp;
+        th[1] = -(MODEL == 1 ? R(3.0) / ph.eta : R(3.0)) * itp * itp * b_itp_tot;   // tau_phi = 3 M (/ eta) + 1/2
+        th[2] = -b_beta4 * R(48.0) * sigma / (W * W) + b_kappa * R(1.5) * sigma - b_anti * R(4.0) / (W * W);
 
         for (int i = 0; i < Q; ++i) a.og[(size_t)i * nn + n] = b_g[i];
         // the direct h adjoint (1 - itp) lambda*_h is formed by the stencil pass
@@ -1203,8 +1227,8 @@ __global__ __launch_bounds__(256) void k_adj_mu_l14(const AdjArgs a) {
 // total dL/dphi* into work[0] (in place: only this node reads it), the
 // nonlocal correction's transpose and the h populations follow.
 constexpr int ST_STEP = 0, ST_INIT = 1, ST_NL = 2;
-template <class PAIR, int MODE>
-__global__ __launch_bounds__(256) void k_adj_stencil(const AdjArgs a) {
+template <class PAIR, int MODE, class R = double>
+__global__ __launch_bounds__(256) void k_adj_stencil(const AdjArgsT<R> a) {
     constexpr bool INIT = MODE == ST_INIT;
     using GL = typename PAIR::G;
     using HL = typename PAIR::H;
@@ -1214,14 +1238,14 @@ __global__ __launch_bounds__(256) void k_adj_stencil(const AdjArgs a) {
     const long long n = (long long)wg * blockDim.x + threadIdx.x;
     if (n >= nn) return;
     const Node p = node_of(n, a);
-    const double* bphi = a.work;
-    const double* bgr = a.work + nn;
-    const double* blap = a.work + 4 * nn;
-    double acc = bphi[n] - 6.0 * (1.0 - GL::w(0)) * blap[n];
+    const R* bphi = a.work;
+    const R* bgr = a.work + nn;
+    const R* blap = a.work + 4 * nn;
+    R acc = bphi[n] - R(6.0) * (R(1.0) - R(GL::w(0))) * blap[n];
     const Nbr nb(a, p);
     // lambda_h^{n+1} through the transposed h streaming, gathered before any
     // store (a store may alias it, so later loads could not pass it)
-    double lhv[HL::Q];
+    R lhv[HL::Q];
     if constexpr (MODE == ST_STEP) {
         unroll<HL::Q>([&](auto J) {
             constexpr int al = J;
@@ -1234,10 +1258,10 @@ __global__ __launch_bounds__(256) void k_adj_stencil(const AdjArgs a) {
     unroll<Q - 1>([&](auto I) {
         constexpr int i = I + 1;
         constexpr int c0 = GL::c(i, 0), c1 = GL::c(i, 1), c2 = GL::c(i, 2);
-        constexpr double w3 = 3.0 * GL::w(i), w6 = 6.0 * GL::w(i);
+        constexpr R w3 = R(3.0) * R(GL::w(i)), w6 = R(6.0) * R(GL::w(i));
         // the terms of x's stencil that reach y (zero components skipped)
         auto contrib = [&](long long x) {
-            double t = w6 * blap[x];
+            R t = w6 * blap[x];
             if constexpr (!INIT && c0 != 0) t += (w3 * c0) * bgr[x];
             if constexpr (!INIT && c1 != 0) t += (w3 * c1) * bgr[nn + x];
             if constexpr (!INIT && c2 != 0) t += (w3 * c2) * bgr[2 * nn + x];
@@ -1266,7 +1290,7 @@ __global__ __launch_bounds__(256) void k_adj_stencil(const AdjArgs a) {
         a.work[n] = acc;
         return;
     }
-    const double itp1 = 1.0 - a.ph.inv_tau_phi;
+    const R itp1 = R(1.0) - R(a.ph.inv_tau_phi);
     unroll<HL::Q>([&](auto J) {
         constexpr int al = J;
         a.oh[(size_t)al * nn + n] = itp1 * lhv[al] + acc;
@@ -1425,42 +1449,42 @@ __global__ __launch_bounds__(256) void k_adj_nl_final(const AdjArgs a, double* l
 
 // dL/dphi0 through the equilibrium initialisation h = h_eq(phi0, u0),
 // g = g_eq(3 p0 / rho(phi0), u0); MODEL 0 AC, 2 nonlocal, 3 Liang2018
-template <class PAIR, int MODEL>
-__global__ __launch_bounds__(256) void k_adj_init(const AdjInitArgs a) {
+template <class PAIR, int MODEL, class R = double>
+__global__ __launch_bounds__(256) void k_adj_init(const AdjInitArgsT<R> a) {
     using GL = typename PAIR::G;
     using HL = typename PAIR::H;
     const long long nn = (long long)a.nx * a.ny * a.nz;
     const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= nn) return;
-    double u[3] = {0.0, 0.0, 0.0};
+    R u[3] = {R(0.0), R(0.0), R(0.0)};
     if (a.u0) {
         u[0] = a.u0[n];
         u[1] = a.u0[nn + n];
         if (PAIR::dim == 3) u[2] = a.u0[2 * nn + n];
     }
-    const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    double s = 0.0;
+    const R usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    R s = R(0.0);
     for (int al = 0; al < HL::Q; ++al) {
-        const double eu = HL::c(al, 0) * u[0] + HL::c(al, 1) * u[1] + HL::c(al, 2) * u[2];
+        const R eu = HL::c(al, 0) * u[0] + HL::c(al, 1) * u[1] + HL::c(al, 2) * u[2];
         // Eq. fakhari_geq (AC) or Eqs. Chai_geq, liang_geq (first order in u)
-        const double dh = MODEL == 2 || MODEL == 3 ? 1.0 + 3.0 * eu : 1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * usq;
-        s += a.lh[(size_t)al * nn + n] * HL::w(al) * dh;
+        const R dh = MODEL == 2 || MODEL == 3 ? R(1.0) + R(3.0) * eu : R(1.0) + R(3.0) * eu + R(4.5) * eu * eu - R(1.5) * usq;
+        s += a.lh[(size_t)al * nn + n] * R(HL::w(al)) * dh;
     }
     if constexpr (MODEL == 3) {
         // Eq. liang_feq: (p0/c_s^2)(w - [i = 0]) + rho(phi0) w (3 c.u + 4.5 (c.u)^2
         // - 1.5 u.u); (phi u) = phi0 u0
-        double sg = 0.0;
+        R sg = R(0.0);
         for (int i = 0; i < GL::Q; ++i) {
-            const double cu = GL::c(i, 0) * u[0] + GL::c(i, 1) * u[1] + GL::c(i, 2) * u[2];
-            sg += a.lg[(size_t)i * nn + n] * GL::w(i) * (3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+            const R cu = GL::c(i, 0) * u[0] + GL::c(i, 1) * u[1] + GL::c(i, 2) * u[2];
+            sg += a.lg[(size_t)i * nn + n] * R(GL::w(i)) * (R(3.0) * cu + R(4.5) * cu * cu - R(1.5) * usq);
         }
-        s += a.ph.dRho * sg;
+        s += R(a.ph.dRho) * sg;
         for (int k = 0; k < 3; ++k) s += a.lpu[(size_t)k * nn + n] * u[k];
     } else if (a.p0) {
-        const double phi = a.phi0[n];
-        const double rho = a.ph.rhoL + phi * a.ph.dRho;
-        const double dps = -3.0 * a.p0[n] * a.ph.dRho / (rho * rho);
-        for (int i = 0; i < GL::Q; ++i) s += a.lg[(size_t)i * nn + n] * GL::w(i) * dps;
+        const R phi = R(a.phi0[n]);
+        const R rho = R(a.ph.rhoL) + phi * R(a.ph.dRho);
+        const R dps = -R(3.0) * R(a.p0[n]) * R(a.ph.dRho) / (rho * rho);
+        for (int i = 0; i < GL::Q; ++i) s += a.lg[(size_t)i * nn + n] * R(GL::w(i)) * dps;
     }
     a.dphi0[n] = s;
 }
@@ -1536,19 +1560,19 @@ __global__ __launch_bounds__(256) void k_adj_init_ch(const AdjArgs a, const doub
 
 // seed of the adjoint from dL/dphi of a state: phi = sum_a h_a (Eq.
 // fakhari_phi_update) gives dL/dh_a = dL/dphi for every a, and dL/dg = 0
-__global__ __launch_bounds__(256) void k_adj_seed(const double* dphi, double* lg, double* lh, long long nn,
-                                                  int qg, int qh) {
+template <class R>
+__global__ __launch_bounds__(256) void k_adj_seed(const R* dphi, R* lg, R* lh, long long nn, int qg, int qh) {
     const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= nn) return;
-    const double v = dphi[n];
-    for (int i = 0; i < qg; ++i) lg[(size_t)i * nn + n] = 0.0;
+    const R v = dphi[n];
+    for (int i = 0; i < qg; ++i) lg[(size_t)i * nn + n] = R(0);
     for (int a = 0; a < qh; ++a) lh[(size_t)a * nn + n] = v;
 }
 
 hipError_t launch_adjoint_seed(const double* dphi, double* lg, double* lh, long long nn, int qg, int qh,
                                hipStream_t st) {
     const dim3 grid((unsigned)((nn + 255) / 256)), block(256);
-    hipLaunchKernelGGL(k_adj_seed, grid, block, 0, st, dphi, lg, lh, nn, qg, qh);
+    hipLaunchKernelGGL(k_adj_seed<double>, grid, block, 0, st, dphi, lg, lh, nn, qg, qh);
     return hipGetLastError();
 }
 
@@ -1562,7 +1586,7 @@ hipError_t launch_adjoint(int lattice, int model, const AdjArgs& a, double* dpar
                            (double*)nullptr);
         hipLaunchKernelGGL(k_adj_phistar, grid, block, 0, st, a);
     } else {
-        hipLaunchKernelGGL(k_adj_phi, grid, block, 0, st, a);
+        hipLaunchKernelGGL(k_adj_phi<double>, grid, block, 0, st, a);
     }
     auto go = [&](auto pair) {
         using P_ = decltype(pair);
@@ -1646,6 +1670,40 @@ hipError_t launch_adjoint_init_ch(int lattice, int model, const AdjArgs& a, cons
     else if (lattice == 1) go(Pair3D{});
     else go(Pair3D27{});
     if (dparams) hipLaunchKernelGGL(k_adj_params, dim3(1), dim3(PARAMS_THREADS), 0, st, a.partials, (int)grid.x, dparams);
+    return hipGetLastError();
+}
+
+// float32 adjoint of the AC step: the same passes in float32 arithmetic on
+// float32 arrays; the parameter partials and their reduction stay float64
+hipError_t launch_adjoint_f32(int lattice, const AdjArgsT<float>& a, double* dparams, hipStream_t st) {
+    const long long nn = (long long)a.nx * a.ny * a.nz;
+    const dim3 grid((unsigned)((nn + 255) / 256)), block(256);
+    hipLaunchKernelGGL(k_adj_phi<float>, grid, block, 0, st, a);
+    auto go = [&](auto pair) {
+        using P_ = decltype(pair);
+        hipLaunchKernelGGL((k_adj_local<P_, 0, float>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((k_adj_stencil<P_, ST_STEP, float>), grid, block, 0, st, a);
+    };
+    if (lattice == 0) go(Pair2D{});
+    else if (lattice == 1) go(Pair3D{});
+    else go(Pair3D27{});
+    if (dparams) hipLaunchKernelGGL(k_adj_params, dim3(1), dim3(PARAMS_THREADS), 0, st, a.partials, (int)grid.x, dparams);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_seed_f32(const float* dphi, float* lg, float* lh, long long nn, int qg, int qh,
+                                   hipStream_t st) {
+    const dim3 grid((unsigned)((nn + 255) / 256)), block(256);
+    hipLaunchKernelGGL(k_adj_seed<float>, grid, block, 0, st, dphi, lg, lh, nn, qg, qh);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_init_f32(int lattice, const AdjInitArgsT<float>& a, hipStream_t st) {
+    const long long nn = (long long)a.nx * a.ny * a.nz;
+    const dim3 grid((unsigned)((nn + 255) / 256)), block(256);
+    if (lattice == 0) hipLaunchKernelGGL((k_adj_init<Pair2D, 0, float>), grid, block, 0, st, a);
+    else if (lattice == 1) hipLaunchKernelGGL((k_adj_init<Pair3D, 0, float>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((k_adj_init<Pair3D27, 0, float>), grid, block, 0, st, a);
     return hipGetLastError();
 }
 

@@ -125,6 +125,8 @@ struct IOArgs {
     void* h;               // current phase-field buffer
     double* cg;            // canonical float64 g [Qg][nodes] (post-streaming)
     double* ch;            // canonical float64 h [Qh][nodes]
+    float* cgf;            // or, when set, canonical float32 g and h (read-out only)
+    float* chf;
     int P;
     int nx, ny, nz;
     int bc[3];
@@ -143,20 +145,23 @@ struct GammaArgs {
     double w32;            // 4 beta / kappa
 };
 
-// discrete adjoint of one step on canonical float64 arrays [q][z][y][x]
-struct AdjArgs {
-    const double* fg;      // forward state X^n (post-streaming)
-    const double* fh;
-    const double* lg;      // lambda^{n+1}
-    const double* lh;
-    double* og;            // lambda^n (must not alias lg / lh)
-    double* oh;
-    const double* fpu;     // CH: (phi u) of the step before X^n [3][nodes]
-    const double* lpu;     // CH: its adjoint lambda_pu^{n+1}
-    double* opu;           // CH: lambda_pu^n
-    double* dphi0;         // adjoint of the initialisation: dL/dphi0 (stencil pass, init mode)
-    double* phi;           // workspace [nodes]
-    double* work;          // workspace [5][nodes]
+// discrete adjoint of one step on canonical arrays [q][z][y][x]: float64 for
+// every model; float32 (R = float) for the AC model, its parameter partial
+// sums still float64
+template <class R>
+struct AdjArgsT {
+    const R* fg;           // forward state X^n (post-streaming)
+    const R* fh;
+    const R* lg;           // lambda^{n+1}
+    const R* lh;
+    R* og;                 // lambda^n (must not alias lg / lh)
+    R* oh;
+    const R* fpu;          // CH, Liang: (phi u) of the step before X^n [3][nodes]
+    const R* lpu;          // its adjoint lambda_pu^{n+1}
+    R* opu;                // lambda_pu^n
+    R* dphi0;              // adjoint of the initialisation: dL/dphi0 (stencil pass, init mode)
+    double* phi;           // workspace [nodes]: phi of the forward state, float64 in both forms
+    R* work;               // workspace [5..9][nodes]
     double* partials;      // workspace [blocks][3]
     double* nlpart;        // nonlocal model: workspace [blocks][4] of partial sums
     double* nls;           // nonlocal model: workspace [4]: gamma, its denominator, dL/dgamma
@@ -166,18 +171,21 @@ struct AdjArgs {
     double sigma, W;
     Phys ph;
 };
+using AdjArgs = AdjArgsT<double>;
 
-struct AdjInitArgs {
-    const double* lg;
-    const double* lh;
-    const double* lpu;     // Liang2018: lambda of (phi u) [3][nodes]
+template <class R>
+struct AdjInitArgsT {
+    const R* lg;
+    const R* lh;
+    const R* lpu;          // Liang2018: lambda of (phi u) [3][nodes]
     const double* phi0;
     const double* u0;      // may be null
     const double* p0;      // may be null
-    double* dphi0;
+    R* dphi0;
     int nx, ny, nz;
     Phys ph;
 };
+using AdjInitArgs = AdjInitArgsT<double>;
 
 // launchers (kernels.hip, adjoint.hip); return hipSuccess or the launch error
 hipError_t adjoint_scratch(int device, void** out);
@@ -185,6 +193,10 @@ hipError_t launch_adjoint_seed(const double* dphi, double* lg, double* lh, long 
                                hipStream_t st);
 hipError_t launch_adjoint(int lattice, int model, const AdjArgs& a, double* dparams, hipStream_t s);
 hipError_t launch_adjoint_init(int lattice, int model, const AdjInitArgs& a, hipStream_t s);
+hipError_t launch_adjoint_f32(int lattice, const AdjArgsT<float>& a, double* dparams, hipStream_t s);
+hipError_t launch_adjoint_seed_f32(const float* dphi, float* lg, float* lh, long long nn, int qg, int qh,
+                                   hipStream_t s);
+hipError_t launch_adjoint_init_f32(int lattice, const AdjInitArgsT<float>& a, hipStream_t s);
 hipError_t launch_adjoint_seed_nl(int lattice, const AdjArgs& a, const double* dphi, double* lam_g, double* lam_h,
                                   double* dparams, hipStream_t s);
 hipError_t launch_adjoint_init_ch(int lattice, int model, const AdjArgs& a, const double* phi0, const double* u0,

@@ -186,18 +186,19 @@ __global__ __launch_bounds__(256) void k_get(const IOArgs a) {
         const size_t e = pull_source<GL, i, GL::Q, 0>(a.nx, a.ny, a.nz, a.bc, x, y, z, a.P, w, side);
         T v = GC::template dec<GL, i, GS, T>(G[e]);
         if (w) v += (T)a.gcorr[side][GL::opp(i)];
-        a.cg[(size_t)i * nn + n] = (double)v;
+        if (a.cgf) a.cgf[(size_t)i * nn + n] = (float)v;
+        else a.cg[(size_t)i * nn + n] = (double)v;
     });
     unroll<HL::Q>([&](auto J) {
         constexpr int al = J;
-        if constexpr (al < HOFF) {
-            a.ch[(size_t)al * nn + n] = 0.0;
-        } else {
+        double v = 0.0;
+        if constexpr (al >= HOFF) {
             bool w;
             int side;
-            a.ch[(size_t)al * nn + n] =
-                (double)H[pull_source<HL, al, QHS, HOFF>(a.nx, a.ny, a.nz, a.bc, x, y, z, a.P, w, side)];
+            v = (double)H[pull_source<HL, al, QHS, HOFF>(a.nx, a.ny, a.nz, a.bc, x, y, z, a.P, w, side)];
         }
+        if (a.chf) a.chf[(size_t)al * nn + n] = (float)v;
+        else a.ch[(size_t)al * nn + n] = v;
     });
 }
 

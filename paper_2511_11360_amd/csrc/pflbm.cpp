@@ -560,6 +560,19 @@ int pflbm_get_distributions(pflbm_t* h, double* g, double* hd) {
     return PFLBM_OK;
 }
 
+int pflbm_get_distributions_f32(pflbm_t* h, float* g, float* hd) {
+    int st = guard(h);
+    if (st) return st;
+    if (!g || !hd) return fail(h, PFLBM_EINVAL, "null output");
+    if (!h->initialised) return fail(h, PFLBM_EINVAL, "pflbm_init not called");
+    IOArgs a;
+    io_args(h, a);
+    a.cgf = g;
+    a.chf = hd;
+    HIPCHK(h, launch_get(h->p.lattice, h->p.model, h->p.precision, a, h->stream), "get kernel");
+    return PFLBM_OK;
+}
+
 int pflbm_set_distributions(pflbm_t* h, const double* g, const double* hd) {
     int st = guard(h);
     if (st) return st;
@@ -719,7 +732,9 @@ int pflbm_adjoint_step_noalloc(pflbm_t* h, const double* fwd_g, const double* fw
 }
 
 // the workspace: phi [nodes], five adjoint values [5][nodes], block partials
-static void adjoint_args(pflbm_t* h, void* work, AdjArgs& a) {
+// (laid out for float64; the float32 adjoint uses the same offsets)
+extern "C++" template <class R>
+static void adjoint_args(pflbm_t* h, void* work, AdjArgsT<R>& a) {
     const size_t nn = adj_nodes(h);
     std::memset(&a, 0, sizeof(a));
     const size_t blocks = (nn + 255) / 256;
@@ -727,7 +742,7 @@ static void adjoint_args(pflbm_t* h, void* work, AdjArgs& a) {
     size_t off = 0;
     a.phi = (double*)(w + off);
     off += align_up(nn * 8, 256);
-    a.work = (double*)(w + off);
+    a.work = (R*)(w + off);
     off += align_up(adj_nwork(h) * nn * 8, 256);
     a.partials = (double*)(w + off);
     off += align_up(blocks * 3 * 8, 256);
@@ -764,6 +779,58 @@ static int adjoint_run(pflbm_t* h, const double* fwd_g, const double* fwd_h, con
     a.lpu = lam_pu;
     a.opu = lam_pu_out;
     HIPCHK(h, launch_adjoint(h->p.lattice, h->p.model, a, dparams, h->stream), "adjoint kernels");
+    return PFLBM_OK;
+}
+
+static int adjoint_check_f32(pflbm_t* h) {
+    if (int st = guard(h)) return st;
+    if (h->p.model != PFLBM_AC) return fail(h, PFLBM_EUNSUPPORTED, "the float32 adjoint covers the AC model");
+    return adjoint_check(h, false);
+}
+
+int pflbm_adjoint_step_f32(pflbm_t* h, const float* fwd_g, const float* fwd_h, const float* lam_g,
+                           const float* lam_h, float* lam_g_out, float* lam_h_out, double* dparams, void* work) {
+    if (int st = adjoint_check_f32(h)) return st;
+    if (!fwd_g || !fwd_h || !lam_g || !lam_h || !lam_g_out || !lam_h_out || !work)
+        return fail(h, PFLBM_EINVAL, "null pointer");
+    if (lam_g_out == lam_g || lam_h_out == lam_h) return fail(h, PFLBM_EINVAL, "lambda in and out must not alias");
+    AdjArgsT<float> a;
+    adjoint_args(h, work, a);
+    a.fg = fwd_g;
+    a.fh = fwd_h;
+    a.lg = lam_g;
+    a.lh = lam_h;
+    a.og = lam_g_out;
+    a.oh = lam_h_out;
+    HIPCHK(h, launch_adjoint_f32(h->p.lattice, a, dparams, h->stream), "adjoint kernels");
+    return PFLBM_OK;
+}
+
+int pflbm_adjoint_seed_phi_f32(pflbm_t* h, const float* dphi, float* lam_g, float* lam_h) {
+    if (int st = adjoint_check_f32(h)) return st;
+    if (!dphi || !lam_g || !lam_h) return fail(h, PFLBM_EINVAL, "null pointer");
+    HIPCHK(h, launch_adjoint_seed_f32(dphi, lam_g, lam_h, (long long)adj_nodes(h), h->L.Qg, h->L.Qh, h->stream),
+           "adjoint seed kernel");
+    return PFLBM_OK;
+}
+
+int pflbm_adjoint_init_f32(pflbm_t* h, const double* phi0, const double* u0, const double* p0,
+                           const float* lam_g, const float* lam_h, float* dphi0) {
+    if (int st = adjoint_check_f32(h)) return st;
+    if (!phi0 || !lam_g || !lam_h || !dphi0) return fail(h, PFLBM_EINVAL, "null pointer");
+    AdjInitArgsT<float> a;
+    std::memset(&a, 0, sizeof(a));
+    a.lg = lam_g;
+    a.lh = lam_h;
+    a.phi0 = phi0;
+    a.u0 = u0;
+    a.p0 = p0;
+    a.dphi0 = dphi0;
+    a.nx = h->p.nx;
+    a.ny = h->p.ny;
+    a.nz = h->p.nz;
+    a.ph = h->ph;
+    HIPCHK(h, launch_adjoint_init_f32(h->p.lattice, a, h->stream), "adjoint init kernel");
     return PFLBM_OK;
 }
 

@@ -94,6 +94,12 @@ class Solver:
         self._check(self.L.pflbm_get_distributions(self.h, _ptr(g), _ptr(h)), self.h)
         return g, h
 
+    def get_distributions_f32(self):
+        g = torch.empty((self.Qg,) + self.shape, dtype=torch.float32, device=self.device)
+        h = torch.empty((self.Qh,) + self.shape, dtype=torch.float32, device=self.device)
+        self._check(self.L.pflbm_get_distributions_f32(self.h, _ptr(g), _ptr(h)), self.h)
+        return g, h
+
     def set_distributions(self, g, h):
         g = self._dev(g, (self.Qg,) + self.shape)
         h = self._dev(h, (self.Qh,) + self.shape)
@@ -151,6 +157,29 @@ class Solver:
         self._check(self.L.pflbm_adjoint_step_pu(self.h, _ptr(fwd_g), _ptr(fwd_h), _ptr(fwd_pu), _ptr(lam_g),
                                                  _ptr(lam_h), _ptr(lam_pu), _ptr(out_g), _ptr(out_h),
                                                  _ptr(out_pu), _ptr(dparams), _ptr(work)), self.h)
+
+    def adjoint_step_f32(self, fwd_g, fwd_h, lam_g, lam_h, out_g, out_h, dparams, work):
+        """The float32 adjoint step of the AC model (float32 tensors; dparams
+        float64)."""
+        self._check(self.L.pflbm_adjoint_step_f32(self.h, _ptr(fwd_g), _ptr(fwd_h), _ptr(lam_g), _ptr(lam_h),
+                                                  _ptr(out_g), _ptr(out_h), _ptr(dparams), _ptr(work)), self.h)
+
+    def adjoint_seed_phi_f32(self, dphi):
+        dphi = torch.as_tensor(dphi, device=self.device).to(torch.float32).contiguous().reshape(self.shape)
+        lam_g = torch.empty((self.Qg,) + self.shape, dtype=torch.float32, device=self.device)
+        lam_h = torch.empty((self.Qh,) + self.shape, dtype=torch.float32, device=self.device)
+        self._keep = (dphi,)
+        self._check(self.L.pflbm_adjoint_seed_phi_f32(self.h, _ptr(dphi), _ptr(lam_g), _ptr(lam_h)), self.h)
+        return lam_g, lam_h
+
+    def adjoint_init_f32(self, phi0, u0, p0, lam_g, lam_h):
+        phi = self._dev(phi0, self.shape)
+        u = self._dev(u0, (self.dim,) + self.shape)
+        pr = self._dev(p0, self.shape)
+        out = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+        self._check(self.L.pflbm_adjoint_init_f32(self.h, _ptr(phi), _ptr(u), _ptr(pr), _ptr(lam_g), _ptr(lam_h),
+                                                  _ptr(out)), self.h)
+        return out
 
     def adjoint_step_noalloc(self, fwd_g, fwd_h, lam_g, lam_h, out_g, out_h, dparams):
         """adjoint_step without a workspace (the library's own device scratch)."""
