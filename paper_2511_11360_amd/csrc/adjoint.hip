@@ -1226,6 +1226,24 @@ __global__ __launch_bounds__(256) void k_adj_mu_l14(const AdjArgs a) {
 // h_eq): dL/dphi0 = work[0] + lap^T(work[4]). MODE 2 (nonlocal model): the
 // total dL/dphi* into work[0] (in place: only this node reads it), the
 // nonlocal correction's transpose and the h populations follow.
+// The sum of the sweep's per-workgroup parameter partials [nb][3], added into
+// out, by one 256-thread workgroup in a fixed order (bit-reproducible):
+// strided per-thread sums, a shuffle tree within each wave, the four waves in
+// order.
+__device__ __forceinline__ void params_fold(const double* part, int nb, double* out) {
+    __shared__ double wsum[3][4];
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nb; b += 256)
+        for (int k = 0; k < 3; ++k) s[k] += part[(size_t)b * 3 + k];
+    for (int k = 0; k < 3; ++k)
+        for (int off = 32; off >= 1; off >>= 1) s[k] += __shfl_down(s[k], off, 64);
+    if ((threadIdx.x & 63) == 0)
+        for (int k = 0; k < 3; ++k) wsum[k][threadIdx.x >> 6] = s[k];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 3; ++k) out[k] += ((wsum[k][0] + wsum[k][1]) + wsum[k][2]) + wsum[k][3];
+}
+
 constexpr int ST_STEP = 0, ST_INIT = 1, ST_NL = 2;
 template <class PAIR, int MODE, class R = double>
 __global__ __launch_bounds__(256) void k_adj_stencil(const AdjArgsT<R> a) {
@@ -1234,6 +1252,12 @@ __global__ __launch_bounds__(256) void k_adj_stencil(const AdjArgsT<R> a) {
     using HL = typename PAIR::H;
     constexpr int Q = GL::Q;
     const long long nn = (long long)a.nx * a.ny * a.nz;
+    // the sweep (the previous launch) has written every partial: the first
+    // workgroup to start sums them while the others run (in place of a launch
+    // of its own); every thread of the workgroup takes part, so this comes
+    // before the early return
+    if constexpr (MODE == ST_STEP)
+        if (a.dparams && blockIdx.x == 0) params_fold(a.partials, (int)gridDim.x, a.dparams);
     const int wg = xcd_block();
     const long long n = (long long)wg * blockDim.x + threadIdx.x;
     if (n >= nn) return;
@@ -1612,12 +1636,16 @@ hipError_t launch_adjoint(int lattice, int model, const AdjArgs& a, double* dpar
         } else {
             hipLaunchKernelGGL((k_adj_local<P_, 0>), grid, block, 0, st, a);
         }
-        hipLaunchKernelGGL((k_adj_stencil<P_, ST_STEP>), grid, block, 0, st, a);
+        // the stencil pass also sums the sweep's parameter partials
+        AdjArgs b = a;
+        b.dparams = dparams;
+        hipLaunchKernelGGL((k_adj_stencil<P_, ST_STEP>), grid, block, 0, st, b);
     };
     if (lattice == 0) go(Pair2D{});
     else if (lattice == 1) go(Pair3D{});
     else go(Pair3D27{});
-    if (dparams) hipLaunchKernelGGL(k_adj_params, dim3(1), dim3(PARAMS_THREADS), 0, st, a.partials, (int)grid.x, dparams);
+    if (model == 2 && dparams)
+        hipLaunchKernelGGL(k_adj_params, dim3(1), dim3(PARAMS_THREADS), 0, st, a.partials, (int)grid.x, dparams);
     return hipGetLastError();
 }
 
@@ -1682,12 +1710,13 @@ hipError_t launch_adjoint_f32(int lattice, const AdjArgsT<float>& a, double* dpa
     auto go = [&](auto pair) {
         using P_ = decltype(pair);
         hipLaunchKernelGGL((k_adj_local<P_, 0, float>), grid, block, 0, st, a);
-        hipLaunchKernelGGL((k_adj_stencil<P_, ST_STEP, float>), grid, block, 0, st, a);
+        AdjArgsT<float> b = a;
+        b.dparams = dparams;
+        hipLaunchKernelGGL((k_adj_stencil<P_, ST_STEP, float>), grid, block, 0, st, b);
     };
     if (lattice == 0) go(Pair2D{});
     else if (lattice == 1) go(Pair3D{});
     else go(Pair3D27{});
-    if (dparams) hipLaunchKernelGGL(k_adj_params, dim3(1), dim3(PARAMS_THREADS), 0, st, a.partials, (int)grid.x, dparams);
     return hipGetLastError();
 }
 

@@ -165,6 +165,7 @@ struct AdjArgsT {
     double* partials;      // workspace [blocks][3]
     double* nlpart;        // nonlocal model: workspace [blocks][4] of partial sums
     double* nls;           // nonlocal model: workspace [4]: gamma, its denominator, dL/dgamma
+    double* dparams;       // if set, the stencil pass adds the sum of the partials into it
     int nx, ny, nz;
     int bc[3];
     int qh;

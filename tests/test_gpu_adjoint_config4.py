@@ -9,7 +9,11 @@ target phi*.
   HIP float64 run within 1e-6 relative;
 - float32 forward pass (the workload's stated precision): the same gradients
   from the float64 adjoint applied to the recomputed float32 states, against
-  the float64 ones; their relative differences are printed and bounded.
+  the float64 ones; their relative differences are printed and bounded;
+- float32 forward and float32 adjoint: against the float64 adjoint of the
+  same float32 states, within sqrt(2000) x 1.2e-5 = 5.4e-4 (float32 roundings
+  of each adjoint step, n u = 1.2e-5, adding as independent errors), rounded
+  up to 1e-3, and against the float64 run within the float32 forward bound.
 """
 import sys
 
@@ -33,14 +37,14 @@ def _dev(a):
     return torch.as_tensor(a, dtype=torch.float64, device="cuda")
 
 
-def _grad(d, phi, u, target, v, precision):
+def _grad(d, phi, u, target, v, precision, adjoint="fp64"):
     import torch
     from paper_2511_11360_amd.autograd import run_phase_field
     phi0 = _dev(phi).requires_grad_(True)
     sig = torch.tensor(d["sigma"], dtype=torch.float64, requires_grad=True)
     M = torch.tensor(d["M"], dtype=torch.float64, requires_grad=True)
     W = torch.tensor(d["W"], dtype=torch.float64, requires_grad=True)
-    phiN = run_phase_field(phi0, sig, M, W, d, _dev(u), STEPS, precision=precision)
+    phiN = run_phase_field(phi0, sig, M, W, d, _dev(u), STEPS, precision=precision, adjoint=adjoint)
     L = 0.5 * ((phiN - _dev(target)) ** 2).sum()
     L.backward()
     gv = float((phi0.grad * _dev(v)).sum())
@@ -84,3 +88,13 @@ def test_sheared_droplet_128_full_run_gradients():
         _say("  dL/d%s float32 forward %.10e  float64 forward %.10e  rel %.2e"
              % (name, g32[name], g64[name], rel))
         assert rel < 1e-2
+
+    _say("case adjoint config 128^3, %d steps, float32 forward, float32 adjoint" % STEPS)
+    _, g3232 = _grad(d, phi, u, target, v, "fp32", adjoint="fp32")
+    for name in ("sigma", "M", "W", "phi0.v"):
+        rel = abs(g3232[name] - g32[name]) / abs(g32[name])
+        rel64 = abs(g3232[name] - g64[name]) / abs(g64[name])
+        _say("  dL/d%s float32 adjoint %.10e  rel to float64 adjoint (same states) %.2e, to float64 run %.2e"
+             % (name, g3232[name], rel, rel64))
+        assert rel < 1e-3
+        assert rel64 < 1e-2
