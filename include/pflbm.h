@@ -205,6 +205,17 @@ int pflbm_init(pflbm_t* h, const double* phi0, const double* u0, const double* p
    due under check_interval finds NaN/Inf in phi or u, or rho <= 0. */
 int pflbm_step(pflbm_t* h, int nsteps);
 
+/* One step, as pflbm_step(h, 1), that also writes the state it starts from:
+   g and hd as pflbm_get_distributions would have returned them just before
+   the step, and pu (if not NULL) as pflbm_get_phiu would have (CH, Liang2018,
+   Liang2014; ignored for the other models). Device pointers, canonical
+   layouts; the _f32 form writes float32 g and hd (the forward state of the
+   float32 adjoint). The read-out rides on the step's own pull of the state,
+   so the backward pass of a checkpointed run needs no separate read-out.
+   Float64 and float32 storage forms only (PFLBM_EUNSUPPORTED otherwise). */
+int pflbm_step_record(pflbm_t* h, double* g, double* hd, double* pu);
+int pflbm_step_record_f32(pflbm_t* h, float* g, float* hd);
+
 /* Macroscopic fields of the current state (the values the next step uses):
    phi, u (d components), p = rho c_s^2 sum g, rho. Device float64 outputs,
    any may be NULL. */

@@ -5,8 +5,9 @@ nsteps time steps as a differentiable function of the initial phase field and
 of sigma, M and W (0-d float64 tensors). The forward pass keeps a native
 checkpoint every k = ceil(sqrt(nsteps)) steps; the backward pass walks the
 segments in reverse, recomputes each segment's k states from its checkpoint
-and applies the adjoint step kernel to each, so memory is O(sqrt(nsteps))
-states. Every forward and adjoint step runs in libpflbm's kernels; this module
+(with the float64 and float32 forms the recomputing step writes the state it
+starts from, so no separate read-out runs) and applies the adjoint step
+kernel to each, so memory is O(sqrt(nsteps)) states. Every forward and adjoint step runs in libpflbm's kernels; this module
 only schedules them.
 """
 import math
@@ -72,14 +73,18 @@ class PhaseFieldRun(torch.autograd.Function):
         del h_final
         out_g = torch.empty_like(lam_g)
         out_h = torch.empty_like(lam_h)
+        record = s.precision in ("fp64", "fp32")
         for start, buf in reversed(ctx.cks):
             n = min(ctx.k, ctx.nsteps - start)
             s.load_state(buf)
             states = []
             for _ in range(n):
-                g, h = s.get_distributions()
-                states.append((g, h, s.get_phiu() if ch else None))
-                s.step(1)
+                if record:
+                    states.append(s.step_record())
+                else:
+                    g, h = s.get_distributions()
+                    states.append((g, h, s.get_phiu() if ch else None))
+                    s.step(1)
             for g, h, pu in reversed(states):
                 if ch:
                     s.adjoint_step_pu(g, h, pu, lam_g, lam_h, lam_pu, out_g, out_h, out_pu, dparams, work)
@@ -111,8 +116,11 @@ class PhaseFieldRun(torch.autograd.Function):
             s.load_state(buf)
             states = []
             for _ in range(n):
-                states.append(s.get_distributions_f32())
-                s.step(1)
+                if s.precision in ("fp64", "fp32"):
+                    states.append(s.step_record(f32=True))
+                else:
+                    states.append(s.get_distributions_f32())
+                    s.step(1)
             for g, h in reversed(states):
                 s.adjoint_step_f32(g, h, lam_g, lam_h, out_g, out_h, dparams, work)
                 lam_g, out_g = out_g, lam_g

@@ -18,7 +18,7 @@ constexpr int NDIAG = 12;       // per-block partial diagnostics (see kernels.hi
 constexpr int GAMMA_ZB = 16;    // z planes per workgroup of the nonlocal multiplier sums
 constexpr int MAXQ = 27;
 
-enum Mode { MODE_STEP = 0, MODE_FIELDS = 1, MODE_DIAG = 2 };
+enum Mode { MODE_STEP = 0, MODE_FIELDS = 1, MODE_DIAG = 2, MODE_RECORD = 3 };
 
 // Models: 0 conservative AC, 1 CH, 2 nonlocal / hybrid AC, 3 Liang2018,
 // 4 Liang2014 with its hydrodynamics. The CH phase field (1, 4) stores the
@@ -87,6 +87,10 @@ struct KArgs {
     double* f_u;
     double* f_p;
     double* f_rho;
+    void* xg;              // MODE_RECORD: the state the step starts from, canonical
+    void* xh;              //   g [Qg][nodes] and h [Qh][nodes], float64 (float32 if xf32)
+    double* xpu;           //   and (phi u) [3][nodes] of the CH and Liang models, may be null
+    int xf32;
     double* partials;      // MODE_DIAG per-block partials [nblocks][NDIAG]
     const double* gamma;   // nonlocal model: multiplier of this step (device)
     int P;                 // elements per population plane (>= nx * ny)

@@ -461,6 +461,30 @@ int pflbm_init(pflbm_t* h, const double* phi0, const double* u0, const double* p
     return PFLBM_OK;
 }
 
+// one step from the current buffers into the other ones; the tile, grid and
+// recording outputs are the caller's (a)
+static int step_once(pflbm_t* h, KArgs& a, int mode) {
+    a.gin = h->base + h->L.off_g[h->gcur];
+    a.gout = h->base + h->L.off_g[1 - h->gcur];
+    a.hin = h->base + h->L.off_h[h->hcur];
+    a.hout = h->base + h->L.off_h[1 - h->hcur];
+    a.step = (unsigned)h->steps;
+    if (int st = run_gamma(h, a)) return st;
+    HIPCHK(h, launch_step(h->p.lattice, h->p.model, h->p.precision, mode, a, h->stream), "step kernel");
+    if (!h->p.freeze_phi) h->hcur ^= 1;
+    h->gcur ^= 1;
+    h->steps += 1;
+    if (h->p.check_interval > 0 && h->steps % h->p.check_interval == 0) {
+        if (int st = run_diag(h, nullptr, 0.0, h->res_host)) return st;
+        if (h->res_host[10] > 0.0) {
+            char buf[128];
+            std::snprintf(buf, sizeof(buf), "NaN/Inf or rho <= 0 detected after step %lld", h->steps);
+            return fail(h, PFLBM_EUNSTABLE, buf);
+        }
+    }
+    return PFLBM_OK;
+}
+
 int pflbm_step(pflbm_t* h, int nsteps) {
     int st = guard(h);
     if (st) return st;
@@ -468,34 +492,44 @@ int pflbm_step(pflbm_t* h, int nsteps) {
     if (!h->initialised) return fail(h, PFLBM_EINVAL, "pflbm_init not called");
     KArgs a;
     base_args(h, a);
-    for (int k = 0; k < nsteps; ++k) {
-        a.gin = h->base + h->L.off_g[h->gcur];
-        a.gout = h->base + h->L.off_g[1 - h->gcur];
-        a.hin = h->base + h->L.off_h[h->hcur];
-        a.hout = h->base + h->L.off_h[1 - h->hcur];
-        a.tile = h->L.tile_step;
-        a.ntx = h->L.ntx_step;
-        a.nty = h->L.nty_step;
-        a.ntz = h->L.ntz_step;
-        a.zb = h->L.zb_step;
-        a.step = (unsigned)h->steps;
-        if ((st = run_gamma(h, a))) return st;
-        HIPCHK(h, launch_step(h->p.lattice, h->p.model, h->p.precision, MODE_STEP, a, h->stream), "step kernel");
-        if (!h->p.freeze_phi) h->hcur ^= 1;
-        h->gcur ^= 1;
-        h->steps += 1;
-        if (h->p.check_interval > 0 && h->steps % h->p.check_interval == 0) {
-            st = run_diag(h, nullptr, 0.0, h->res_host);
-            if (st) return st;
-            if (h->res_host[10] > 0.0) {
-                char buf[128];
-                std::snprintf(buf, sizeof(buf), "NaN/Inf or rho <= 0 detected after step %lld", h->steps);
-                return fail(h, PFLBM_EUNSTABLE, buf);
-            }
-        }
-    }
+    a.tile = h->L.tile_step;
+    a.ntx = h->L.ntx_step;
+    a.nty = h->L.nty_step;
+    a.ntz = h->L.ntz_step;
+    a.zb = h->L.zb_step;
+    for (int k = 0; k < nsteps; ++k)
+        if ((st = step_once(h, a, MODE_STEP))) return st;
     return PFLBM_OK;
 }
+
+// one step that also writes the state it starts from (canonical layout)
+static int step_record(pflbm_t* h, void* g, void* hd, double* pu, int f32) {
+    int st = guard(h);
+    if (st) return st;
+    if (!g || !hd) return fail(h, PFLBM_EINVAL, "null output");
+    if (!h->initialised) return fail(h, PFLBM_EINVAL, "pflbm_init not called");
+    if (h->p.precision != PFLBM_FP64 && h->p.precision != PFLBM_FP32)
+        return fail(h, PFLBM_EUNSUPPORTED, "the recording step covers the float64 and float32 forms");
+    KArgs a;
+    base_args(h, a);
+    a.xg = g;
+    a.xh = hd;
+    a.xpu = (h->p.model == PFLBM_CH || h->p.model == PFLBM_L18 || h->p.model == PFLBM_L14) ? pu : nullptr;
+    a.xf32 = f32;
+    // 128 x 2 tiles where the box is wide enough (64 x 4 otherwise), the
+    // layout's z depth
+    const int t = (h->L.dim == 3 && h->p.nx > 64) ? 1 : 0;
+    a.tile = t;
+    a.ntx = (h->p.nx + TILE_NX[t] - 1) / TILE_NX[t];
+    a.nty = (h->p.ny + TILE_NY[t] - 1) / TILE_NY[t];
+    a.zb = h->L.zb;
+    a.ntz = (h->p.nz + a.zb - 1) / a.zb;
+    return step_once(h, a, MODE_RECORD);
+}
+
+int pflbm_step_record(pflbm_t* h, double* g, double* hd, double* pu) { return step_record(h, g, hd, pu, 0); }
+
+int pflbm_step_record_f32(pflbm_t* h, float* g, float* hd) { return step_record(h, g, hd, nullptr, 1); }
 
 int pflbm_fields(pflbm_t* h, double* phi, double* u, double* p, double* rho) {
     int st = guard(h);

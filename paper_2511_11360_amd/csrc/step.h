@@ -1144,7 +1144,23 @@ __global__ __launch_bounds__(TILE_THREADS[TS]) void k_step(const KArgs a) {
         });
         NodeOut<T> mo;
         T pu_new[3];
-        if constexpr (MODE == MODE_STEP) {
+        if constexpr (MODE == MODE_RECORD) {
+            // the state this step starts from, as the canonical read-out forms it
+            const size_t nn = (size_t)nx * ny * nz;
+            const size_t idx = ((size_t)z * ny + y) * nx + x;
+            if (a.xf32) {
+                unroll<QG>([&](auto I) { constexpr int i = I; ((float*)a.xg)[i * nn + idx] = (float)g[i]; });
+                unroll<QH>([&](auto J) { constexpr int al = J; ((float*)a.xh)[al * nn + idx] = (float)h[al]; });
+            } else {
+                unroll<QG>([&](auto I) { constexpr int i = I; ((double*)a.xg)[i * nn + idx] = (double)g[i]; });
+                unroll<QH>([&](auto J) { constexpr int al = J; ((double*)a.xh)[al * nn + idx] = (double)h[al]; });
+            }
+            if constexpr (MODEL == 1 || MODEL == 3 || MODEL == 4) {
+                if (a.xpu)
+                    unroll<3>([&](auto A) { constexpr int c = A; a.xpu[c * nn + idx] = (double)pu_prev[c]; });
+            }
+        }
+        if constexpr (MODE == MODE_STEP || MODE == MODE_RECORD) {
             // post-collision populations at the node itself, in the other buffers;
             // streamed (non-temporal stores): no workgroup reads them this step.
             // The store offset is opaque here too, or one 64-bit lane pointer is
@@ -1320,6 +1336,22 @@ inline hipError_t step_mode(int mode, const KArgs& a, hipStream_t s) {
         case MODE_FIELDS:
             hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_FIELDS, 1, 0>), grid, block, 0, s, a);
             break;
+        case MODE_RECORD:
+            // float64 and float32 forms, tiles 64 x 4 and 128 x 2
+            if constexpr (PREC <= 1) {
+                if constexpr (PAIR::dim == 3) {
+                    if (a.tile == 1) {
+                        if (walls) hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_RECORD, 1, 1>), grid, block, 0, s, a);
+                        else hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_RECORD, 0, 1>), grid, block, 0, s, a);
+                        break;
+                    }
+                }
+                if (a.tile != 0) return hipErrorInvalidValue;
+                if (walls) hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_RECORD, 1, 0>), grid, block, 0, s, a);
+                else hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_RECORD, 0, 0>), grid, block, 0, s, a);
+                break;
+            }
+            return hipErrorInvalidValue;
         default:
             hipLaunchKernelGGL((k_step<PAIR, MODEL, PREC, MODE_DIAG, 1, 0>), grid, block, 0, s, a);
     }

@@ -94,6 +94,21 @@ class Solver:
         self._check(self.L.pflbm_get_distributions(self.h, _ptr(g), _ptr(h)), self.h)
         return g, h
 
+    def step_record(self, f32=False):
+        """One step; returns the state it started from: (g, h, pu) canonical
+        float64 (pu None for the models without (phi u)), or (g, h) float32."""
+        dt = torch.float32 if f32 else torch.float64
+        g = torch.empty((self.Qg,) + self.shape, dtype=dt, device=self.device)
+        h = torch.empty((self.Qh,) + self.shape, dtype=dt, device=self.device)
+        if f32:
+            self._check(self.L.pflbm_step_record_f32(self.h, _ptr(g), _ptr(h)), self.h)
+            return g, h
+        pu = None
+        if self.d.get("model", "AC") in ("CH", "L18", "L14"):
+            pu = torch.empty((3,) + self.shape, dtype=torch.float64, device=self.device)
+        self._check(self.L.pflbm_step_record(self.h, _ptr(g), _ptr(h), _ptr(pu)), self.h)
+        return g, h, pu
+
     def get_distributions_f32(self):
         g = torch.empty((self.Qg,) + self.shape, dtype=torch.float32, device=self.device)
         h = torch.empty((self.Qh,) + self.shape, dtype=torch.float32, device=self.device)
