@@ -16,10 +16,12 @@ class Solver:
     """One coupled PF-LB state on the current CUDA (HIP) device.
 
     params: workload dict (see workloads.base_params); precision: "fp64",
-    "fp32", "mixed_fp16" or "mixed_bf16"."""
+    "fp32", "mixed_fp16" or "mixed_bf16"; state: an optional caller-owned
+    uint8 device tensor of at least pflbm_state_bytes bytes to hold the
+    state (allocated here otherwise)."""
 
     def __init__(self, params, precision="fp64", check_interval=0, zblock=0, device=None,
-                 stream=None, tile="auto"):
+                 stream=None, tile="auto", state=None):
         if not torch.cuda.is_available():
             raise RuntimeError("libpflbm needs a GPU; none is visible")
         self.d = dict(params)
@@ -29,11 +31,14 @@ class Solver:
         self.L = P.lib()
         nb = ctypes.c_size_t()
         self._check(self.L.pflbm_state_bytes(ctypes.byref(self.p), ctypes.byref(nb)), None)
-        self.state = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        if state is None:
+            state = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        self.state = state
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
         self._check(self.L.pflbm_create(ctypes.byref(self.p), ctypes.c_void_p(self.stream.cuda_stream),
-                                        _ptr(self.state), nb, ctypes.byref(h)), None)
+                                        _ptr(self.state), ctypes.c_size_t(self.state.numel()), ctypes.byref(h)),
+                    None)
         self.h = h
         self.dim = 2 if self.d["lattice"] == "D2Q9_D2Q5" else 3
         self.shape = (int(self.d["nz"]), int(self.d["ny"]), int(self.d["nx"]))
