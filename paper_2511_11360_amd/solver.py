@@ -79,6 +79,35 @@ class Solver:
     def step(self, n=1):
         self._check(self.L.pflbm_step(self.h, int(n)), self.h)
 
+    def run(self, nsteps, every, log, centre=None, R=0.0):
+        """Advance nsteps, writing the float64 diagnostics of pflbm_volume as
+        one JSON line (step, V_phi, V_count, sum_phi, phi_min, phi_max, umax,
+        and with a centre the Laplace pressure jump dp = p_in - p_out) to log
+        (a path, appended to, or a text file) at the start and after every
+        `every` steps and the last one."""
+        import json
+        f = open(log, "a") if isinstance(log, (str, bytes)) or hasattr(log, "__fspath__") else log
+        try:
+            done = 0
+
+            def write():
+                v = self.volume(centre, R)
+                rec = {"step": self.step_count()}
+                rec.update({k: v[k] for k in ("V_phi", "V_count", "sum_phi", "phi_min", "phi_max", "umax")})
+                if centre is not None:
+                    rec["dp"] = v["p_in"] - v["p_out"]
+                f.write(json.dumps(rec) + "\n")
+            write()
+            while done < nsteps:
+                n = min(int(every), nsteps - done) if every > 0 else nsteps - done
+                self.step(n)
+                done += n
+                write()
+            f.flush()
+        finally:
+            if f is not log:
+                f.close()
+
     def fields(self):
         phi = torch.empty(self.shape, dtype=torch.float64, device=self.device)
         u = torch.empty((self.dim,) + self.shape, dtype=torch.float64, device=self.device)
