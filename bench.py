@@ -199,8 +199,8 @@ def time_adjoint(steps, model="AC", arith="fp64"):
     model two per-node workspace values (sum h and dL/dR, 2 x 2 x 8),
     Liang2014 four (mu_phi, lap phi and their adjoints, 2 x 4 x 8). The Liang
     models run between stationary walls (the only walls they take). arith
-    "fp32" times the float32 adjoint of the AC step (every array float32 but
-    the phase-field workspace: 368 bytes per node)."""
+    "fp32" times the float32 adjoint (AC, CH: every array float32 but the
+    phase-field workspace: 368 and 404 bytes per node)."""
     import torch
     from paper_2511_11360_amd import workloads as wl
     from paper_2511_11360_amd.solver import Solver
@@ -215,6 +215,8 @@ def time_adjoint(steps, model="AC", arith="fp64"):
     f32 = arith == "fp32"
     fg, fh = s.get_distributions_f32() if f32 else s.get_distributions()
     fpu = s.get_phiu() if ch else None
+    if ch and f32:
+        fpu = fpu.float()
     gen = torch.Generator(device=fg.device).manual_seed(5)
 
     def rnd(t):
@@ -227,7 +229,9 @@ def time_adjoint(steps, model="AC", arith="fp64"):
     def run(k):
         for i in range(k):
             a, b = lam[i % 2], lam[(i + 1) % 2]
-            if ch:
+            if ch and f32:
+                s.adjoint_step_pu_f32(fg, fh, fpu, a[0], a[1], a[2], b[0], b[1], b[2], dparams, work)
+            elif ch:
                 s.adjoint_step_pu(fg, fh, fpu, a[0], a[1], a[2], b[0], b[1], b[2], dparams, work)
             elif f32:
                 s.adjoint_step_f32(fg, fh, a[0], a[1], b[0], b[1], dparams, work)
@@ -565,6 +569,9 @@ def main():
         torch.cuda.empty_cache()
         log("adjoint, CH")
         adjoint["ch"] = time_adjoint(100, "CH")
+        torch.cuda.empty_cache()
+        log("adjoint, CH, float32")
+        adjoint["ch_fp32"] = time_adjoint(100, "CH", arith="fp32")
         torch.cuda.empty_cache()
         for key, model in (("nl", "NL"), ("l18", "L18"), ("l14", "L14")):
             log("adjoint, %s" % model)

@@ -209,12 +209,12 @@ int pflbm_step(pflbm_t* h, int nsteps);
    g and hd as pflbm_get_distributions would have returned them just before
    the step, and pu (if not NULL) as pflbm_get_phiu would have (CH, Liang2018,
    Liang2014; ignored for the other models). Device pointers, canonical
-   layouts; the _f32 form writes float32 g and hd (the forward state of the
-   float32 adjoint). The read-out rides on the step's own pull of the state,
+   layouts; the _f32 form writes float32 g, hd and pu (the forward state of
+   the float32 adjoint). The read-out rides on the step's own pull of the state,
    so the backward pass of a checkpointed run needs no separate read-out.
    Float64 and float32 storage forms only (PFLBM_EUNSUPPORTED otherwise). */
 int pflbm_step_record(pflbm_t* h, double* g, double* hd, double* pu);
-int pflbm_step_record_f32(pflbm_t* h, float* g, float* hd);
+int pflbm_step_record_f32(pflbm_t* h, float* g, float* hd, float* pu);
 
 /* Macroscopic fields of the current state (the values the next step uses):
    phi, u (d components), p = rho c_s^2 sum g, rho. Device float64 outputs,
@@ -305,10 +305,12 @@ int pflbm_adjoint_step_pu(pflbm_t* h, const double* fwd_g, const double* fwd_h, 
                           double* lam_g_out, double* lam_h_out, double* lam_pu_out,
                           double* dparams, void* work);
 
-/* The float32 adjoint of the AC step (Sec. II.C.1): the passes of
-   pflbm_adjoint_step in float32 arithmetic on float32 arrays of the same
-   layouts (the forward state as pflbm_get_distributions_f32 returns it); the
-   parameter terms are still reduced, and ADDED into dparams, in float64.
+/* The float32 adjoint of the AC step (Sec. II.C.1) and, through the _pu
+   forms, of the CH step (Sec. II.C.2): the passes of pflbm_adjoint_step and
+   pflbm_adjoint_step_pu in float32 arithmetic on float32 arrays of the same
+   layouts (the forward state as pflbm_get_distributions_f32 or
+   pflbm_step_record_f32 gives it); the parameter terms are still reduced,
+   and ADDED into dparams, in float64.
    The phase field of the forward state, its stencils, phi (1 - phi), the
    cubic term of mu and the non-equilibrium h_eq - h are formed in float64
    (float32 differences of them cancel inside a droplet); everything else
@@ -316,13 +318,23 @@ int pflbm_adjoint_step_pu(pflbm_t* h, const double* fwd_g, const double* fwd_h, 
    adjoint's 720. work: the workspace of pflbm_adjoint_workspace_bytes().
    pflbm_adjoint_seed_phi_f32 and pflbm_adjoint_init_f32 are the float32 forms
    of the seed and of the initialisation adjoint (phi0, u0, p0 float64, as
-   for pflbm_init). PFLBM_EUNSUPPORTED for the other models. */
+   for pflbm_init); pflbm_adjoint_step_pu_f32 and pflbm_adjoint_init_pu_f32
+   are those of the CH model, with the (phi u) arrays of pflbm_adjoint_step_pu
+   in float32. PFLBM_EUNSUPPORTED for the other models, and for a form that
+   does not match the model (the AC model has no (phi u), the CH model needs
+   it). */
 int pflbm_adjoint_step_f32(pflbm_t* h, const float* fwd_g, const float* fwd_h,
                            const float* lam_g, const float* lam_h,
                            float* lam_g_out, float* lam_h_out, double* dparams, void* work);
 int pflbm_adjoint_seed_phi_f32(pflbm_t* h, const float* dphi, float* lam_g, float* lam_h);
 int pflbm_adjoint_init_f32(pflbm_t* h, const double* phi0, const double* u0, const double* p0,
                            const float* lam_g, const float* lam_h, float* dphi0);
+int pflbm_adjoint_step_pu_f32(pflbm_t* h, const float* fwd_g, const float* fwd_h, const float* fwd_pu,
+                              const float* lam_g, const float* lam_h, const float* lam_pu, float* lam_g_out,
+                              float* lam_h_out, float* lam_pu_out, double* dparams, void* work);
+int pflbm_adjoint_init_pu_f32(pflbm_t* h, const double* phi0, const double* u0, const double* p0,
+                              const float* lam_g, const float* lam_h, const float* lam_pu, float* dphi0,
+                              double* dparams, void* work);
 
 /* The same adjoint step for callers that cannot allocate device memory
    (code under HIP graph capture, tight serving loops, harnesses that forbid

@@ -26,8 +26,8 @@ class PhaseFieldRun(torch.autograd.Function):
             raise ValueError("unknown phase-field model %r" % d.get("model"))
         if adjoint not in ("fp64", "fp32"):
             raise ValueError("adjoint precision must be 'fp64' or 'fp32', not %r" % (adjoint,))
-        if adjoint == "fp32" and d.get("model", "AC") != "AC":
-            raise ValueError("the float32 adjoint covers the AC model only")
+        if adjoint == "fp32" and d.get("model", "AC") not in ("AC", "CH"):
+            raise ValueError("the float32 adjoint covers the AC and CH models")
         s = Solver(d, precision=precision, device=phi0.device)
         s.init(phi0, u0)
         nsteps = int(nsteps)
@@ -103,37 +103,50 @@ class PhaseFieldRun(torch.autograd.Function):
 
     @staticmethod
     def _backward_f32(ctx, s, phi0, grad_phi):
-        """The same schedule with the float32 adjoint of the AC step: states
-        read out in float32, lambda float32, parameter sums float64."""
+        """The same schedule with the float32 adjoint (AC and CH): states in
+        float32, lambda float32, parameter sums float64."""
         dev = s.device
+        ch = s.d.get("model", "AC") == "CH"
         dparams = torch.zeros(3, dtype=torch.float64, device=dev)
         work = s.adjoint_workspace()
         lam_g, lam_h = s.adjoint_seed_phi_f32(grad_phi.to(device=dev).reshape(s.shape))
+        lam_pu = torch.zeros((3,) + s.shape, dtype=torch.float32, device=dev) if ch else None
+        out_pu = torch.empty_like(lam_pu) if ch else None
         out_g = torch.empty_like(lam_g)
         out_h = torch.empty_like(lam_h)
+        record = s.precision in ("fp64", "fp32")
+        if ch and not record:
+            raise ValueError("the float32 CH adjoint needs a float64 or float32 forward pass")
         for start, buf in reversed(ctx.cks):
             n = min(ctx.k, ctx.nsteps - start)
             s.load_state(buf)
             states = []
             for _ in range(n):
-                if s.precision in ("fp64", "fp32"):
+                if record:
                     states.append(s.step_record(f32=True))
                 else:
-                    states.append(s.get_distributions_f32())
+                    states.append(s.get_distributions_f32() + (None,))
                     s.step(1)
-            for g, h in reversed(states):
-                s.adjoint_step_f32(g, h, lam_g, lam_h, out_g, out_h, dparams, work)
+            for g, h, pu in reversed(states):
+                if ch:
+                    s.adjoint_step_pu_f32(g, h, pu, lam_g, lam_h, lam_pu, out_g, out_h, out_pu, dparams, work)
+                    lam_pu, out_pu = out_pu, lam_pu
+                else:
+                    s.adjoint_step_f32(g, h, lam_g, lam_h, out_g, out_h, dparams, work)
                 lam_g, out_g = out_g, lam_g
                 lam_h, out_h = out_h, lam_h
             del states
-        dphi0 = s.adjoint_init_f32(phi0, ctx.u0, None, lam_g, lam_h)
+        if ch:
+            dphi0 = s.adjoint_init_pu_f32(phi0, ctx.u0, None, lam_g, lam_h, lam_pu, dparams, work)
+        else:
+            dphi0 = s.adjoint_init_f32(phi0, ctx.u0, None, lam_g, lam_h)
         return (dphi0.to(phi0.dtype).reshape(phi0.shape), dparams[0], dparams[1], dparams[2],
                 None, None, None, None, None, None)
 
 
 def run_phase_field(phi0, sigma, M, W, params, u0=None, nsteps=1, precision="fp64", k=None, adjoint="fp64"):
     """phi after nsteps steps; differentiable in phi0, sigma, M, W. adjoint
-    picks the arithmetic of the backward pass: "fp64", or "fp32" (AC model
-    only: half the bytes per adjoint step, float32 rounding in the
+    picks the arithmetic of the backward pass: "fp64", or "fp32" (AC and CH
+    models: half the bytes per adjoint step, float32 rounding in the
     gradient)."""
     return PhaseFieldRun.apply(phi0, sigma, M, W, params, u0, nsteps, precision, k, adjoint)

@@ -437,7 +437,12 @@ __global__ __launch_bounds__(256, 2) void k_adj_local(const AdjArgsT<R> a) {
                     b_pup[1] -= ey * tp;
                     b_pup[2] -= ez * tp;
                 }
-                b_itp += (heq - h[al]) * lb;
+                // heq_0 - h_0 = (phi - h_0) + (w_0 - 1) eta mu, phi - h_0 formed
+                // in float64 (h_0 carries nearly all of phi)
+                if constexpr (al == 0)
+                    b_itp += (R(phin[0] - (double)h[0]) + (w - R(1.0)) * ph.eta * mu) * lb;
+                else
+                    b_itp += (heq - h[al]) * lb;
                 b_gfp += G * lb;
             });
             // (phi u) = phi u
@@ -1519,8 +1524,8 @@ __global__ __launch_bounds__(256) void k_adj_init(const AdjInitArgsT<R> a) {
 // (phi u) = phi0 u0: the local part of dL/dphi0 into work[0],
 // dL/d(lap phi0) into work[4] (the stencil pass in init mode adds its
 // transpose), and the sigma and W terms of mu_phi into the block partials
-template <class PAIR, int MODEL>
-__global__ __launch_bounds__(256) void k_adj_init_ch(const AdjArgs a, const double* phi0, const double* u0,
+template <class PAIR, int MODEL, class R = double>
+__global__ __launch_bounds__(256) void k_adj_init_ch(const AdjArgsT<R> a, const double* phi0, const double* u0,
                                                      const double* p0) {
     using GL = typename PAIR::G;
     using HL = typename PAIR::H;
@@ -1545,7 +1550,7 @@ __global__ __launch_bounds__(256) void k_adj_init_ch(const AdjArgs a, const doub
         }
         const double cub = phi * (phi - 1.0) * (phi - 0.5);
         // heq_0 = phi + (w_0 - 1) eta mu, heq_a = w_a eta mu + 3 w_a e_a . (phi u)
-        double s = a.lh[n], cmu = -a.lh[n];
+        double s = a.lh[n], cmu = -(double)a.lh[n];
         unroll<HL::Q>([&](auto J) {
             constexpr int al = J;
             const double lb = a.lh[(size_t)al * nn + n];
@@ -1572,8 +1577,8 @@ __global__ __launch_bounds__(256) void k_adj_init_ch(const AdjArgs a, const doub
             const double dps = -3.0 * p0[n] * ph.dRho / (rho * rho);
             for (int i = 0; i < GL::Q; ++i) s += a.lg[(size_t)i * nn + n] * GL::w(i) * dps;
         }
-        a.work[n] = s;
-        a.work[4 * nn + n] = -ph.kappa * cmu;
+        a.work[n] = R(s);
+        a.work[4 * nn + n] = R(-ph.kappa * cmu);
         // beta4 = 48 sigma / W, kappa = 1.5 sigma W
         const double sigma = a.sigma, W = a.W;
         th[0] = cmu * (cub * 48.0 / W - lap * 1.5 * W);
@@ -1703,13 +1708,14 @@ hipError_t launch_adjoint_init_ch(int lattice, int model, const AdjArgs& a, cons
 
 // float32 adjoint of the AC step: the same passes in float32 arithmetic on
 // float32 arrays; the parameter partials and their reduction stay float64
-hipError_t launch_adjoint_f32(int lattice, const AdjArgsT<float>& a, double* dparams, hipStream_t st) {
+hipError_t launch_adjoint_f32(int lattice, int model, const AdjArgsT<float>& a, double* dparams, hipStream_t st) {
     const long long nn = (long long)a.nx * a.ny * a.nz;
     const dim3 grid((unsigned)((nn + 255) / 256)), block(256);
     hipLaunchKernelGGL(k_adj_phi<float>, grid, block, 0, st, a);
     auto go = [&](auto pair) {
         using P_ = decltype(pair);
-        hipLaunchKernelGGL((k_adj_local<P_, 0, float>), grid, block, 0, st, a);
+        if (model == 1) hipLaunchKernelGGL((k_adj_local<P_, 1, float>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_adj_local<P_, 0, float>), grid, block, 0, st, a);
         AdjArgsT<float> b = a;
         b.dparams = dparams;
         hipLaunchKernelGGL((k_adj_stencil<P_, ST_STEP, float>), grid, block, 0, st, b);
@@ -1724,6 +1730,22 @@ hipError_t launch_adjoint_seed_f32(const float* dphi, float* lg, float* lh, long
                                    hipStream_t st) {
     const dim3 grid((unsigned)((nn + 255) / 256)), block(256);
     hipLaunchKernelGGL(k_adj_seed<float>, grid, block, 0, st, dphi, lg, lh, nn, qg, qh);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_init_ch_f32(int lattice, const AdjArgsT<float>& a, const double* phi0, const double* u0,
+                                      const double* p0, double* dparams, hipStream_t st) {
+    const long long nn = (long long)a.nx * a.ny * a.nz;
+    const dim3 grid((unsigned)((nn + 255) / 256)), block(256);
+    auto go = [&](auto pair) {
+        using P_ = decltype(pair);
+        hipLaunchKernelGGL((k_adj_init_ch<P_, 1, float>), grid, block, 0, st, a, phi0, u0, p0);
+        hipLaunchKernelGGL((k_adj_stencil<P_, ST_INIT, float>), grid, block, 0, st, a);
+    };
+    if (lattice == 0) go(Pair2D{});
+    else if (lattice == 1) go(Pair3D{});
+    else go(Pair3D27{});
+    if (dparams) hipLaunchKernelGGL(k_adj_params, dim3(1), dim3(PARAMS_THREADS), 0, st, a.partials, (int)grid.x, dparams);
     return hipGetLastError();
 }
 

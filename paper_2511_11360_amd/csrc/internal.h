@@ -89,7 +89,7 @@ struct KArgs {
     double* f_rho;
     void* xg;              // MODE_RECORD: the state the step starts from, canonical
     void* xh;              //   g [Qg][nodes] and h [Qh][nodes], float64 (float32 if xf32)
-    double* xpu;           //   and (phi u) [3][nodes] of the CH and Liang models, may be null
+    void* xpu;             //   and (phi u) [3][nodes] of the CH and Liang models, may be null
     int xf32;
     double* partials;      // MODE_DIAG per-block partials [nblocks][NDIAG]
     const double* gamma;   // nonlocal model: multiplier of this step (device)
@@ -198,7 +198,9 @@ hipError_t launch_adjoint_seed(const double* dphi, double* lg, double* lh, long 
                                hipStream_t st);
 hipError_t launch_adjoint(int lattice, int model, const AdjArgs& a, double* dparams, hipStream_t s);
 hipError_t launch_adjoint_init(int lattice, int model, const AdjInitArgs& a, hipStream_t s);
-hipError_t launch_adjoint_f32(int lattice, const AdjArgsT<float>& a, double* dparams, hipStream_t s);
+hipError_t launch_adjoint_f32(int lattice, int model, const AdjArgsT<float>& a, double* dparams, hipStream_t s);
+hipError_t launch_adjoint_init_ch_f32(int lattice, const AdjArgsT<float>& a, const double* phi0, const double* u0,
+                                      const double* p0, double* dparams, hipStream_t s);
 hipError_t launch_adjoint_seed_f32(const float* dphi, float* lg, float* lh, long long nn, int qg, int qh,
                                    hipStream_t s);
 hipError_t launch_adjoint_init_f32(int lattice, const AdjInitArgsT<float>& a, hipStream_t s);

@@ -503,7 +503,7 @@ int pflbm_step(pflbm_t* h, int nsteps) {
 }
 
 // one step that also writes the state it starts from (canonical layout)
-static int step_record(pflbm_t* h, void* g, void* hd, double* pu, int f32) {
+static int step_record(pflbm_t* h, void* g, void* hd, void* pu, int f32) {
     int st = guard(h);
     if (st) return st;
     if (!g || !hd) return fail(h, PFLBM_EINVAL, "null output");
@@ -529,7 +529,7 @@ static int step_record(pflbm_t* h, void* g, void* hd, double* pu, int f32) {
 
 int pflbm_step_record(pflbm_t* h, double* g, double* hd, double* pu) { return step_record(h, g, hd, pu, 0); }
 
-int pflbm_step_record_f32(pflbm_t* h, float* g, float* hd) { return step_record(h, g, hd, nullptr, 1); }
+int pflbm_step_record_f32(pflbm_t* h, float* g, float* hd, float* pu) { return step_record(h, g, hd, pu, 1); }
 
 int pflbm_fields(pflbm_t* h, double* phi, double* u, double* p, double* rho) {
     int st = guard(h);
@@ -816,15 +816,20 @@ static int adjoint_run(pflbm_t* h, const double* fwd_g, const double* fwd_h, con
     return PFLBM_OK;
 }
 
-static int adjoint_check_f32(pflbm_t* h) {
+// the float32 adjoint covers the AC model and, through the (phi u) forms,
+// the CH model; with_pu selects the form asked for
+static int adjoint_check_f32(pflbm_t* h, bool with_pu) {
     if (int st = guard(h)) return st;
-    if (h->p.model != PFLBM_AC) return fail(h, PFLBM_EUNSUPPORTED, "the float32 adjoint covers the AC model");
-    return adjoint_check(h, false);
+    if (h->p.model != PFLBM_AC && h->p.model != PFLBM_CH)
+        return fail(h, PFLBM_EUNSUPPORTED, "the float32 adjoint covers the AC and CH models");
+    if (with_pu && h->p.model != PFLBM_CH)
+        return fail(h, PFLBM_EUNSUPPORTED, "the AC model has no (phi u) state: use pflbm_adjoint_step_f32");
+    return adjoint_check(h, with_pu);
 }
 
-int pflbm_adjoint_step_f32(pflbm_t* h, const float* fwd_g, const float* fwd_h, const float* lam_g,
-                           const float* lam_h, float* lam_g_out, float* lam_h_out, double* dparams, void* work) {
-    if (int st = adjoint_check_f32(h)) return st;
+static int adjoint_run_f32(pflbm_t* h, const float* fwd_g, const float* fwd_h, const float* fwd_pu,
+                           const float* lam_g, const float* lam_h, const float* lam_pu, float* lam_g_out,
+                           float* lam_h_out, float* lam_pu_out, double* dparams, void* work) {
     if (!fwd_g || !fwd_h || !lam_g || !lam_h || !lam_g_out || !lam_h_out || !work)
         return fail(h, PFLBM_EINVAL, "null pointer");
     if (lam_g_out == lam_g || lam_h_out == lam_h) return fail(h, PFLBM_EINVAL, "lambda in and out must not alias");
@@ -836,12 +841,48 @@ int pflbm_adjoint_step_f32(pflbm_t* h, const float* fwd_g, const float* fwd_h, c
     a.lh = lam_h;
     a.og = lam_g_out;
     a.oh = lam_h_out;
-    HIPCHK(h, launch_adjoint_f32(h->p.lattice, a, dparams, h->stream), "adjoint kernels");
+    a.fpu = fwd_pu;
+    a.lpu = lam_pu;
+    a.opu = lam_pu_out;
+    HIPCHK(h, launch_adjoint_f32(h->p.lattice, h->p.model, a, dparams, h->stream), "adjoint kernels");
+    return PFLBM_OK;
+}
+
+int pflbm_adjoint_step_f32(pflbm_t* h, const float* fwd_g, const float* fwd_h, const float* lam_g,
+                           const float* lam_h, float* lam_g_out, float* lam_h_out, double* dparams, void* work) {
+    if (int st = adjoint_check_f32(h, false)) return st;
+    return adjoint_run_f32(h, fwd_g, fwd_h, nullptr, lam_g, lam_h, nullptr, lam_g_out, lam_h_out, nullptr, dparams,
+                           work);
+}
+
+int pflbm_adjoint_step_pu_f32(pflbm_t* h, const float* fwd_g, const float* fwd_h, const float* fwd_pu,
+                              const float* lam_g, const float* lam_h, const float* lam_pu, float* lam_g_out,
+                              float* lam_h_out, float* lam_pu_out, double* dparams, void* work) {
+    if (int st = adjoint_check_f32(h, true)) return st;
+    if (!fwd_pu || !lam_pu || !lam_pu_out) return fail(h, PFLBM_EINVAL, "null pointer");
+    if (lam_pu_out == lam_pu) return fail(h, PFLBM_EINVAL, "lambda in and out must not alias");
+    return adjoint_run_f32(h, fwd_g, fwd_h, fwd_pu, lam_g, lam_h, lam_pu, lam_g_out, lam_h_out, lam_pu_out, dparams,
+                           work);
+}
+
+int pflbm_adjoint_init_pu_f32(pflbm_t* h, const double* phi0, const double* u0, const double* p0,
+                              const float* lam_g, const float* lam_h, const float* lam_pu, float* dphi0,
+                              double* dparams, void* work) {
+    if (int st = adjoint_check_f32(h, true)) return st;
+    if (!phi0 || !lam_g || !lam_h || !lam_pu || !dphi0 || !work) return fail(h, PFLBM_EINVAL, "null pointer");
+    AdjArgsT<float> a;
+    adjoint_args(h, work, a);
+    a.lg = lam_g;
+    a.lh = lam_h;
+    a.lpu = lam_pu;
+    a.dphi0 = dphi0;
+    HIPCHK(h, launch_adjoint_init_ch_f32(h->p.lattice, a, phi0, u0, p0, dparams, h->stream), "adjoint init kernels");
     return PFLBM_OK;
 }
 
 int pflbm_adjoint_seed_phi_f32(pflbm_t* h, const float* dphi, float* lam_g, float* lam_h) {
-    if (int st = adjoint_check_f32(h)) return st;
+    if (int st = guard(h)) return st;
+    if (int st = adjoint_check_f32(h, h->p.model == PFLBM_CH)) return st;
     if (!dphi || !lam_g || !lam_h) return fail(h, PFLBM_EINVAL, "null pointer");
     HIPCHK(h, launch_adjoint_seed_f32(dphi, lam_g, lam_h, (long long)adj_nodes(h), h->L.Qg, h->L.Qh, h->stream),
            "adjoint seed kernel");
@@ -850,7 +891,7 @@ int pflbm_adjoint_seed_phi_f32(pflbm_t* h, const float* dphi, float* lam_g, floa
 
 int pflbm_adjoint_init_f32(pflbm_t* h, const double* phi0, const double* u0, const double* p0,
                            const float* lam_g, const float* lam_h, float* dphi0) {
-    if (int st = adjoint_check_f32(h)) return st;
+    if (int st = adjoint_check_f32(h, false)) return st;
     if (!phi0 || !lam_g || !lam_h || !dphi0) return fail(h, PFLBM_EINVAL, "null pointer");
     AdjInitArgsT<float> a;
     std::memset(&a, 0, sizeof(a));

@@ -1156,8 +1156,12 @@ __global__ __launch_bounds__(TILE_THREADS[TS]) void k_step(const KArgs a) {
                 unroll<QH>([&](auto J) { constexpr int al = J; ((double*)a.xh)[al * nn + idx] = (double)h[al]; });
             }
             if constexpr (MODEL == 1 || MODEL == 3 || MODEL == 4) {
-                if (a.xpu)
-                    unroll<3>([&](auto A) { constexpr int c = A; a.xpu[c * nn + idx] = (double)pu_prev[c]; });
+                if (a.xpu) {
+                    if (a.xf32)
+                        unroll<3>([&](auto A) { constexpr int c = A; ((float*)a.xpu)[c * nn + idx] = (float)pu_prev[c]; });
+                    else
+                        unroll<3>([&](auto A) { constexpr int c = A; ((double*)a.xpu)[c * nn + idx] = (double)pu_prev[c]; });
+                }
             }
         }
         if constexpr (MODE == MODE_STEP || MODE == MODE_RECORD) {

@@ -95,7 +95,9 @@ SIGNATURES = {
     "pflbm_adjoint_seed": (ctypes.c_int, [_P] * 7),
     "pflbm_get_distributions_f32": (ctypes.c_int, [_P] * 3),
     "pflbm_step_record": (ctypes.c_int, [_P] * 4),
-    "pflbm_step_record_f32": (ctypes.c_int, [_P] * 3),
+    "pflbm_step_record_f32": (ctypes.c_int, [_P] * 4),
+    "pflbm_adjoint_step_pu_f32": (ctypes.c_int, [_P] * 12),
+    "pflbm_adjoint_init_pu_f32": (ctypes.c_int, [_P] * 10),
     "pflbm_adjoint_step_f32": (ctypes.c_int, [_P] * 9),
     "pflbm_adjoint_seed_phi_f32": (ctypes.c_int, [_P] * 4),
     "pflbm_adjoint_init_f32": (ctypes.c_int, [_P] * 7),

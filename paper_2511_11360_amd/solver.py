@@ -129,18 +129,16 @@ class Solver:
         return g, h
 
     def step_record(self, f32=False):
-        """One step; returns the state it started from: (g, h, pu) canonical
-        float64 (pu None for the models without (phi u)), or (g, h) float32."""
+        """One step; returns the state it started from, (g, h, pu) canonical,
+        float64 or (f32) float32; pu is None for the models without (phi u)."""
         dt = torch.float32 if f32 else torch.float64
         g = torch.empty((self.Qg,) + self.shape, dtype=dt, device=self.device)
         h = torch.empty((self.Qh,) + self.shape, dtype=dt, device=self.device)
-        if f32:
-            self._check(self.L.pflbm_step_record_f32(self.h, _ptr(g), _ptr(h)), self.h)
-            return g, h
         pu = None
         if self.d.get("model", "AC") in ("CH", "L18", "L14"):
-            pu = torch.empty((3,) + self.shape, dtype=torch.float64, device=self.device)
-        self._check(self.L.pflbm_step_record(self.h, _ptr(g), _ptr(h), _ptr(pu)), self.h)
+            pu = torch.empty((3,) + self.shape, dtype=dt, device=self.device)
+        fn = self.L.pflbm_step_record_f32 if f32 else self.L.pflbm_step_record
+        self._check(fn(self.h, _ptr(g), _ptr(h), _ptr(pu)), self.h)
         return g, h, pu
 
     def get_distributions_f32(self):
@@ -212,6 +210,24 @@ class Solver:
         float64)."""
         self._check(self.L.pflbm_adjoint_step_f32(self.h, _ptr(fwd_g), _ptr(fwd_h), _ptr(lam_g), _ptr(lam_h),
                                                   _ptr(out_g), _ptr(out_h), _ptr(dparams), _ptr(work)), self.h)
+
+    def adjoint_step_pu_f32(self, fwd_g, fwd_h, fwd_pu, lam_g, lam_h, lam_pu, out_g, out_h, out_pu, dparams,
+                            work):
+        """The float32 adjoint step of the CH model, (phi u) included."""
+        self._check(self.L.pflbm_adjoint_step_pu_f32(
+            self.h, _ptr(fwd_g), _ptr(fwd_h), _ptr(fwd_pu), _ptr(lam_g), _ptr(lam_h), _ptr(lam_pu),
+            _ptr(out_g), _ptr(out_h), _ptr(out_pu), _ptr(dparams), _ptr(work)), self.h)
+
+    def adjoint_init_pu_f32(self, phi0, u0, p0, lam_g, lam_h, lam_pu, dparams, work):
+        """float32 dL/dphi0 of the CH initialisation; adds its sigma and W terms
+        into dparams (float64)."""
+        phi = self._dev(phi0, self.shape)
+        u = self._dev(u0, (self.dim,) + self.shape)
+        pr = self._dev(p0, self.shape)
+        out = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+        self._check(self.L.pflbm_adjoint_init_pu_f32(self.h, _ptr(phi), _ptr(u), _ptr(pr), _ptr(lam_g), _ptr(lam_h),
+                                                     _ptr(lam_pu), _ptr(out), _ptr(dparams), _ptr(work)), self.h)
+        return out
 
     def adjoint_seed_phi_f32(self, dphi):
         dphi = torch.as_tensor(dphi, device=self.device).to(torch.float32).contiguous().reshape(self.shape)

@@ -123,7 +123,7 @@ def test_poisoned_adjoint_workspace_and_outputs_change_nothing(lattice, model):
         assert torch.equal(a, b)
     if model == "AC":
         out = []
-        g32, h32 = s.step_record(f32=True)
+        g32, h32, _ = s.step_record(f32=True)
         for fill in (0, 255):
             work = s.adjoint_workspace().fill_(fill)
             og = torch.empty_like(g32).view(torch.uint8).fill_(fill).view(torch.float32)

@@ -66,11 +66,14 @@ def test_recorded_state_is_the_read_out_and_the_step_is_the_plain_step(lattice, 
     a1, b1 = s1.get_distributions()
     a2, b2 = s2.get_distributions()
     assert torch.equal(a1, a2) and torch.equal(b1, b2)
-    if model == "AC":
-        gf, hf = s1.step_record(f32=True)
-        g3, h3 = s2.get_distributions_f32()
-        assert gf.dtype == torch.float32
-        assert torch.equal(gf, g3) and torch.equal(hf, h3)
+    gf, hf, pf = s1.step_record(f32=True)
+    g3, h3 = s2.get_distributions_f32()
+    assert gf.dtype == torch.float32
+    assert torch.equal(gf, g3) and torch.equal(hf, h3)
+    if ch:
+        assert torch.equal(pf, s2.get_phiu().float())
+    else:
+        assert pf is None
 
 
 def test_record_refuses_the_16_bit_forms_and_null_outputs():
