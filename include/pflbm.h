@@ -306,7 +306,7 @@ int pflbm_adjoint_step_pu(pflbm_t* h, const double* fwd_g, const double* fwd_h, 
                           double* dparams, void* work);
 
 /* The float32 adjoint of the AC step (Sec. II.C.1) and, through the _pu
-   forms, of the CH step (Sec. II.C.2): the passes of pflbm_adjoint_step and
+   forms, of the CH step (Sec. II.D.1): the passes of pflbm_adjoint_step and
    pflbm_adjoint_step_pu in float32 arithmetic on float32 arrays of the same
    layouts (the forward state as pflbm_get_distributions_f32 or
    pflbm_step_record_f32 gives it); the parameter terms are still reduced,
@@ -315,7 +315,7 @@ int pflbm_adjoint_step_pu(pflbm_t* h, const double* fwd_g, const double* fwd_h, 
    cubic term of mu and the non-equilibrium h_eq - h are formed in float64
    (float32 differences of them cancel inside a droplet); everything else
    carries float32 rounding. It moves 368 bytes per node against the float64
-   adjoint's 720. work: the workspace of pflbm_adjoint_workspace_bytes().
+   adjoint's 720 (CH: 404 against 792). work: the workspace of pflbm_adjoint_workspace_bytes().
    pflbm_adjoint_seed_phi_f32 and pflbm_adjoint_init_f32 are the float32 forms
    of the seed and of the initialisation adjoint (phi0, u0, p0 float64, as
    for pflbm_init); pflbm_adjoint_step_pu_f32 and pflbm_adjoint_init_pu_f32
