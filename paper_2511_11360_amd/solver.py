@@ -1,6 +1,7 @@
 """Device-side driver of one solver instance: PyTorch provides the device
 buffer and the stream; every computation runs in libpflbm's kernels."""
 import ctypes
+import functools
 
 import numpy as np
 import torch
@@ -18,7 +19,12 @@ class Solver:
     params: workload dict (see workloads.base_params); precision: "fp64",
     "fp32", "mixed_fp16" or "mixed_bf16"; state: an optional caller-owned
     uint8 device tensor of at least pflbm_state_bytes bytes to hold the
-    state (allocated here otherwise)."""
+    state (allocated here otherwise); stream: the torch stream the library
+    launches on (default: the current one). Every method runs with that
+    stream current, so the tensors it allocates and returns belong to it;
+    as for any torch side stream, a caller that uses a returned tensor on
+    another stream, or passes in one produced on another stream, orders the
+    two streams itself."""
 
     def __init__(self, params, precision="fp64", check_interval=0, zblock=0, device=None,
                  stream=None, tile="auto", state=None):
@@ -31,10 +37,11 @@ class Solver:
         self.L = P.lib()
         nb = ctypes.c_size_t()
         self._check(self.L.pflbm_state_bytes(ctypes.byref(self.p), ctypes.byref(nb)), None)
-        if state is None:
-            state = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
-        self.state = state
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        if state is None:
+            with torch.cuda.stream(self.stream):
+                state = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        self.state = state
         h = ctypes.c_void_p()
         self._check(self.L.pflbm_create(ctypes.byref(self.p), ctypes.c_void_p(self.stream.cuda_stream),
                                         _ptr(self.state), ctypes.c_size_t(self.state.numel()), ctypes.byref(h)),
@@ -294,3 +301,19 @@ class Solver:
                                                  _ptr(lam_h), _ptr(lam_pu), _ptr(out), _ptr(dparams),
                                                  _ptr(work)), self.h)
         return out
+
+
+def _on_stream(fn):
+    @functools.wraps(fn)
+    def wrapped(self, *args, **kwargs):
+        if self.stream == torch.cuda.current_stream(self.device):
+            return fn(self, *args, **kwargs)
+        with torch.cuda.stream(self.stream):
+            return fn(self, *args, **kwargs)
+    return wrapped
+
+
+for _name, _fn in list(vars(Solver).items()):
+    if callable(_fn) and not _name.startswith("_") and _name not in ("close", "step_count", "checkpoint_bytes"):
+        setattr(Solver, _name, _on_stream(_fn))
+del _name, _fn
