@@ -65,7 +65,7 @@ extern "C" {
 /* status codes */
 #define PFLBM_OK            0
 #define PFLBM_EINVAL       -1   /* invalid argument; handle state unchanged */
-#define PFLBM_EUNSUPPORTED -2   /* valid but not supported by this build */
+#define PFLBM_EUNSUPPORTED -2   /* valid but not supported by this library */
 #define PFLBM_EHIP         -3   /* HIP runtime error (sticky) */
 #define PFLBM_EUNSTABLE    -4   /* NaN/Inf in phi or u, or rho <= 0, detected */
 #define PFLBM_ESTATE       -5   /* handle in an error state */
