@@ -41,6 +41,8 @@ class Solver:
         if state is None:
             with torch.cuda.stream(self.stream):
                 state = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        elif state.dtype != torch.uint8 or not state.is_contiguous() or state.device != self.device:
+            raise ValueError("state must be a contiguous uint8 tensor on %s" % self.device)
         self.state = state
         h = ctypes.c_void_p()
         self._check(self.L.pflbm_create(ctypes.byref(self.p), ctypes.c_void_p(self.stream.cuda_stream),
