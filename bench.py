@@ -189,6 +189,15 @@ def probes(n, reps=20):
 ADJ_BYTES = 2 * (19 + 7) * 8 + 26 * 8 + 2 * 6 * 8   # lambda in + out, forward g, h, workspace
 
 
+def adjoint_bytes(model="AC", arith="fp64"):
+    """Algorithmic bytes per node of one adjoint step (see time_adjoint)."""
+    nb = (ADJ_BYTES + (3 * 3 * 8 if model in ("CH", "L18", "L14") else 0) + (2 * 2 * 8 if model == "NL" else 0)
+          + (2 * 4 * 8 if model == "L14" else 0))
+    if arith == "fp32":
+        nb = nb // 2 + 8       # float32 throughout but phi of the forward state (float64: 2 x 8)
+    return nb
+
+
 def time_adjoint(steps, model="AC", arith="fp64"):
     """The discrete adjoint step (float64, canonical layout) on the 128^3
     sheared droplet between moving walls, at the forward state after 20 steps,
@@ -246,10 +255,7 @@ def time_adjoint(steps, model="AC", arith="fp64"):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     nodes = d["nx"] * d["ny"] * d["nz"]
-    nb = (ADJ_BYTES + (3 * 3 * 8 if ch else 0) + (2 * 2 * 8 if model == "NL" else 0)
-          + (2 * 4 * 8 if model == "L14" else 0))
-    if f32:
-        nb = nb // 2 + 8       # float32 throughout but phi of the forward state (float64: 2 x 8)
+    nb = adjoint_bytes(model, arith)
     walls = "stationary walls, shear in u0" if model in ("L18", "L14") else "walls moving at -+0.02"
     return {"workload": "3-D sheared droplet, D3Q19+D3Q7, 128^3, %s (adjoint of the %s step, %s)"
                         % (walls, model, "float32" if f32 else "float64"),

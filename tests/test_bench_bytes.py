@@ -45,3 +45,26 @@ def test_adjoint_bytes():
     # lambda in and out (2 x 26 x 8), forward state (26 x 8), 6 workspace values
     # written and read (2 x 6 x 8)
     assert _bench().ADJ_BYTES == 2 * 26 * 8 + 26 * 8 + 2 * 6 * 8 == 720
+
+
+def test_adjoint_bytes_per_model_and_precision():
+    b = _bench()
+    # (phi u) in the state, lambda in and out: 3 x 3 x 8 more
+    assert b.adjoint_bytes("CH") == b.adjoint_bytes("L18") == 720 + 72
+    # the nonlocal model's sum h and dL/dR, written and read: 2 x 2 x 8
+    assert b.adjoint_bytes("NL") == 720 + 32
+    # Liang2014: (phi u) and mu_phi, lap phi and their adjoints: 72 + 2 x 4 x 8
+    assert b.adjoint_bytes("L14") == 720 + 72 + 64
+    # float32: every array halved but the float64 phase field (written and read)
+    assert b.adjoint_bytes("AC", "fp32") == 26 * 4 + 2 * 26 * 4 + 2 * (8 + 5 * 4) == 368
+    assert b.adjoint_bytes("CH", "fp32") == 368 + 3 * 3 * 4 == 404
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, _bench().__file__, "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr and r.stdout == ""
+
