@@ -134,18 +134,19 @@ def test_full_size_d3q27_step_on_sampled_nodes(precision):
     _say("  D3Q27 %s 256^3 sampled step: worst %.3e" % (precision, worst))
 
 
-def _fp16_fraction(got_g, ref_g, got_h, ref_h, w, floor):
-    """Worst error as a fraction of the fp16-stored tolerance: g is stored as
-    fp16 of 4096 g / w, stochastically rounded (below one ulp, 2^-10
-    relative; the tolerance is twice that), h as float32, arithmetic float32;
-    the floor (in units of g / w) covers float32 rounding of the O(1) terms."""
-    eg = np.max(np.abs(got_g - ref_g) / w / (2.0 ** -9 * np.abs(ref_g / w) + 2.0 ** -24 + floor))
+def _fp16_fraction(got_g, ref_g, got_h, ref_h, w, floor, rel=2.0 ** -9):
+    """Worst error as a fraction of the 16-bit-stored tolerance: g is stored
+    as fp16 of 4096 g / w or bf16 of g / w, rounded below one ulp (2^-10
+    relative for fp16, 2^-7 for bf16; rel is twice that), h as float32,
+    arithmetic float32; the floor (in units of g / w) covers float32 rounding
+    of the O(1) terms."""
+    eg = np.max(np.abs(got_g - ref_g) / w / (rel * np.abs(ref_g / w) + 2.0 ** -24 + floor))
     eh = np.max(np.abs(got_h - ref_h) / (2e-6 * np.abs(ref_h) + 1e-7))
     return eg, eh
 
 
 @pytest.mark.parametrize("model", ["CH", "NL", "L18", "L14"])
-@pytest.mark.parametrize("precision", ["fp64", "mixed_fp16"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed_fp16", "mixed_bf16"])
 def test_full_size_models_step_on_sampled_nodes(model, precision):
     """The sampled check for the other models at 256^3, automatic tile and z
     block (the bench's model lines; nonlocal with lam = 0.5). CH, Liang2018 and
@@ -191,7 +192,8 @@ def test_full_size_models_step_on_sampled_nodes(model, precision):
             e = max(np.max(np.abs(got_g - ref_g)), np.max(np.abs(got_h - ref_h)))
             assert e <= 1e-14, ((x, y, z), e)
         else:
-            eg, eh = _fp16_fraction(got_g, ref_g, got_h, ref_h, w, 1e-6)
+            eg, eh = _fp16_fraction(got_g, ref_g, got_h, ref_h, w, 1e-6,
+                                    2.0 ** -9 if precision == "mixed_fp16" else 2.0 ** -6)
             e = max(eg, eh)
             assert e <= 1.0, ((x, y, z), eg, eh)
         worst = max(worst, e)
