@@ -100,7 +100,7 @@ def test_full_size_phase_conservation_fp64():
     assert v1["unstable"] == 0
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed_fp16"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "mixed_fp16", "mixed_bf16"])
 def test_full_size_d3q27_step_on_sampled_nodes(precision):
     """The same sampled check on D3Q27 hydrodynamics at 256^3 (the bench's
     D3Q27 line): a 5^3 periodic block around each sampled node, stepped by the
@@ -127,9 +127,8 @@ def test_full_size_d3q27_step_on_sampled_nodes(precision):
             e = max(np.max(np.abs(got_g - out.g[:, 2, 2, 2])), np.max(np.abs(got_h - out.h[:, 2, 2, 2])))
             assert e <= 1e-14, ((x, y, z), e)
         else:
-            eg = np.max(np.abs(got_g - out.g[:, 2, 2, 2]) / w / (2.0 ** -9 * np.abs(out.g[:, 2, 2, 2] / w)
-                                                               + 2.0 ** -24 + 1e-6))
-            eh = np.max(np.abs(got_h - out.h[:, 2, 2, 2]) / (2e-6 * np.abs(out.h[:, 2, 2, 2]) + 1e-7))
+            eg, eh = _fp16_fraction(got_g, out.g[:, 2, 2, 2], got_h, out.h[:, 2, 2, 2], w, 1e-6,
+                                    {"fp32": 2.0 ** -20, "mixed_fp16": 2.0 ** -9, "mixed_bf16": 2.0 ** -6}[precision])
             e = max(eg, eh)
             assert e <= 1.0, ((x, y, z), eg, eh)
         worst = max(worst, e)
