@@ -135,7 +135,7 @@ def _turbulence_512():
     return d, phi, u
 
 
-@pytest.mark.parametrize("precision", ["mixed_fp16", "fp32"])
+@pytest.mark.parametrize("precision", ["mixed_fp16", "mixed_bf16", "fp32", "fp64"])
 def test_turbulence_512_sampled_nodes(precision):
     import torch
     from paper_2511_11360_amd.solver import Solver
@@ -159,8 +159,16 @@ def test_turbulence_512_sampled_nodes(precision):
         ref_g, ref_h = out.g[:, 2, 2, 2], out.h[:, 2, 2, 2]
         got_g = g1[:, z, y, x].cpu().numpy()
         got_h = h1[:, z, y, x].cpu().numpy()
+        if precision == "fp64":
+            e = max(np.max(np.abs(got_g - ref_g)), np.max(np.abs(got_h - ref_h)))
+            assert e <= 1e-14, ((x, y, z), e)
+            worst = max(worst, e)
+            continue
         if precision == "fp32":
             eg, eh = _float_fraction(got_g[:, None], ref_g[:, None], got_h, ref_h, w, 2e-6, 2e-6)
+        elif precision == "mixed_bf16":
+            # bf16 of g / w, stochastically rounded: below one ulp (2^-7)
+            eg, eh = _float_fraction(got_g[:, None], ref_g[:, None], got_h, ref_h, w, 2.0 ** -6, 1e-6)
         else:
             # fp16 of 4096 g / w, stochastically rounded: below one ulp (2^-10
             # relative), tolerance twice that; float32 arithmetic
@@ -168,7 +176,8 @@ def test_turbulence_512_sampled_nodes(precision):
         e = max(eg, eh)
         assert e <= 1.0, ((x, y, z), eg, eh)
         worst = max(worst, e)
-    _say("  turbulence 512^3 %s, %d nodes: worst %.3e of tolerance" % (precision, len(pts), worst))
+    _say("  turbulence 512^3 %s, %d nodes: worst %.3e %s"
+         % (precision, len(pts), worst, "abs" if precision == "fp64" else "of tolerance"))
     del g0, h0, g1, h1, s
     torch.cuda.empty_cache()
 
