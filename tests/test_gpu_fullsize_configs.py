@@ -251,3 +251,69 @@ def test_adjoint_128_block_supported():
         _say("  d/d%s: oracle %.12e  hip %.12e" % (name, ref, dp[k]))
         assert abs(ref) > 1e-6 * np.abs(terms).sum()   # the interface block contributes
         assert abs(ref - dp[k]) <= 1e-12 * np.abs(terms).sum() + 1e-300
+
+
+def test_adjoint_128_block_supported_ch():
+    """The same full-size check for the CH model, whose state and adjoint also
+    carry (phi u) of the previous step: lambda (with lambda_pu) on the two
+    4^3 blocks, the perturbation (with v_pu) on the two 3^3 blocks."""
+    import torch
+    from paper_2511_11360_amd.solver import Solver
+    d, phi, u, _ = wl.sheared_droplet_3d()
+    d = dict(d, model="CH", eta=1.0)
+    n = d["nx"]
+    s = Solver(d, precision="fp64")
+    s.init(phi, u)
+    s.step(50)
+    fg, fh, fpu = s.step_record()
+    Qg, Qh = fg.shape[0], fh.shape[0]
+    rng = np.random.default_rng(8)
+    lam_blocks = [(40, 1, 70), (62, 62, 86)]
+    v_blocks = [(42, 3, 68), (63, 63, 88)]
+    lam = [torch.zeros_like(fg), torch.zeros_like(fh), torch.zeros_like(fpu)]
+    wvals, vvals = [], []
+    for (z, y, x) in lam_blocks:
+        ws = [rng.standard_normal((q, 4, 4, 4)) for q in (Qg, Qh, 3)]
+        for t, w_ in zip(lam, ws):
+            t[:, z:z + 4, y:y + 4, x:x + 4] = torch.as_tensor(w_, device="cuda")
+        wvals.append(ws)
+    for _ in v_blocks:
+        vvals.append([rng.standard_normal((q, 3, 3, 3)) * 1e-3 for q in (Qg, Qh, 3)])
+    work = s.adjoint_workspace()
+    dparams = torch.zeros(3, dtype=torch.float64, device="cuda")
+    out = [torch.empty_like(fg), torch.empty_like(fh), torch.empty_like(fpu)]
+    s.adjoint_step_pu(fg, fh, fpu, lam[0], lam[1], lam[2], out[0], out[1], out[2], dparams, work)
+    rhs_terms = []
+    for (z, y, x), vs in zip(v_blocks, vvals):
+        for t, v_ in zip(out, vs):
+            rhs_terms.append((v_ * t[:, z:z + 3, y:y + 3, x:x + 3].cpu().numpy()).ravel())
+    rhs_terms = np.concatenate(rhs_terms)
+    for t in out:
+        assert t[:, 80:100].abs().max().item() == 0.0
+    x0, z0, B = 60, 32, 40
+    xs, zs, ys = np.arange(x0, x0 + B), np.arange(z0, z0 + B), np.arange(n)
+    st = om.State(_cut(fg, zs, ys, xs), _cut(fh, zs, ys, xs), _cut(fpu, zs, ys, xs))
+    p = om.Params(**dict(d, nx=B, nz=B))
+    W = [np.zeros_like(st.g), np.zeros_like(st.h), np.zeros_like(st.phiu_prev)]
+    V = [np.zeros_like(st.g), np.zeros_like(st.h), np.zeros_like(st.phiu_prev)]
+    for (z, y, x), ws in zip(lam_blocks, wvals):
+        for A, w_ in zip(W, ws):
+            A[:, z - z0:z - z0 + 4, y:y + 4, x - x0:x - x0 + 4] = w_
+    for (z, y, x), vs in zip(v_blocks, vvals):
+        for A, v_ in zip(V, vs):
+            A[:, z - z0:z - z0 + 3, y:y + 3, x - x0:x - x0 + 3] = v_
+    J = dv.step_jvp(p, st, V[0], V[1], V[2])
+    lhs_terms = np.concatenate([(Jk * Wk).ravel() for Jk, Wk in zip(J, W)])
+    lhs, rhs = lhs_terms.sum(), rhs_terms.sum()
+    scale = np.abs(lhs_terms).sum() + np.abs(rhs_terms).sum()
+    _say("  128^3 CH adjoint: <Jv,w> %.15e  <v,J^T w> %.15e" % (lhs, rhs))
+    assert abs(lhs) > 1e-3 * scale
+    assert abs(lhs - rhs) <= 1e-12 * scale
+    dp = dparams.cpu().numpy()
+    for k, name in enumerate(("sigma", "M", "W")):
+        t = dv.step_param_tangent(p, st, name)
+        terms = np.concatenate([(tk * Wk).ravel() for tk, Wk in zip(t, W)])
+        ref = terms.sum()
+        _say("  d/d%s: oracle %.12e  hip %.12e" % (name, ref, dp[k]))
+        assert abs(ref) > 1e-6 * np.abs(terms).sum()
+        assert abs(ref - dp[k]) <= 1e-12 * np.abs(terms).sum() + 1e-300
