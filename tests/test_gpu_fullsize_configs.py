@@ -253,14 +253,19 @@ def test_adjoint_128_block_supported():
         assert abs(ref - dp[k]) <= 1e-12 * np.abs(terms).sum() + 1e-300
 
 
-def test_adjoint_128_block_supported_ch():
-    """The same full-size check for the CH model, whose state and adjoint also
-    carry (phi u) of the previous step: lambda (with lambda_pu) on the two
-    4^3 blocks, the perturbation (with v_pu) on the two 3^3 blocks."""
+@pytest.mark.parametrize("model", ["CH", "L18"])
+def test_adjoint_128_block_supported_pu(model):
+    """The same full-size check for the CH and Liang2018 models, whose state
+    and adjoint also carry (phi u) of the previous step: lambda (with
+    lambda_pu) on the two 4^3 blocks, the perturbation (with v_pu) on the two
+    3^3 blocks. Liang2018 takes stationary walls (its linear shear stays in
+    u0)."""
     import torch
     from paper_2511_11360_amd.solver import Solver
     d, phi, u, _ = wl.sheared_droplet_3d()
-    d = dict(d, model="CH", eta=1.0)
+    d = dict(d, model=model, eta=1.0)
+    if model == "L18":
+        d["wall_u"] = ((0.0, 0.0, 0.0), (0.0, 0.0, 0.0))
     n = d["nx"]
     s = Solver(d, precision="fp64")
     s.init(phi, u)
@@ -306,7 +311,7 @@ def test_adjoint_128_block_supported_ch():
     lhs_terms = np.concatenate([(Jk * Wk).ravel() for Jk, Wk in zip(J, W)])
     lhs, rhs = lhs_terms.sum(), rhs_terms.sum()
     scale = np.abs(lhs_terms).sum() + np.abs(rhs_terms).sum()
-    _say("  128^3 CH adjoint: <Jv,w> %.15e  <v,J^T w> %.15e" % (lhs, rhs))
+    _say("  128^3 %s adjoint: <Jv,w> %.15e  <v,J^T w> %.15e" % (model, lhs, rhs))
     assert abs(lhs) > 1e-3 * scale
     assert abs(lhs - rhs) <= 1e-12 * scale
     dp = dparams.cpu().numpy()
