@@ -127,3 +127,24 @@ def test_strerror():
     L = P.lib()
     assert L.pflbm_strerror(P.PFLBM_EUNSTABLE).decode().startswith("numerical")
     assert L.pflbm_create(None, None, None, 0, None) == P.PFLBM_EINVAL
+
+
+def test_every_handle_entry_point_rejects_a_null_handle():
+    """Each entry point that takes a handle returns PFLBM_EINVAL for a null
+    one (all other arguments null or zero too) before any HIP call, so this
+    runs without a GPU; pflbm_last_error names the null handle."""
+    import ctypes
+    from paper_2511_11360_amd import pflbm as P
+    L = P.lib()
+    skip = {"pflbm_state_bytes", "pflbm_create", "pflbm_probe_bytes", "pflbm_probe_stream", "pflbm_destroy",
+            "pflbm_last_error", "pflbm_strerror"}
+    checked = 0
+    for name, (res, args) in P.SIGNATURES.items():
+        if name in skip:
+            continue
+        vals = [0 if a in (ctypes.c_int, ctypes.c_double, ctypes.c_size_t) else None for a in args]
+        assert getattr(L, name)(*vals) == P.PFLBM_EINVAL, name
+        checked += 1
+    assert checked >= 28
+    assert L.pflbm_last_error(None) == b"null handle"
+    L.pflbm_destroy(None)   # a no-op
