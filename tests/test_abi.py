@@ -148,3 +148,20 @@ def test_every_handle_entry_point_rejects_a_null_handle():
     assert checked >= 28
     assert L.pflbm_last_error(None) == b"null handle"
     L.pflbm_destroy(None)   # a no-op
+
+
+def test_create_rejects_small_or_misaligned_buffers_without_a_gpu():
+    """pflbm_create checks the caller's buffer (null, fewer bytes than
+    pflbm_state_bytes, not 256-byte aligned) before any HIP call."""
+    import ctypes
+    from paper_2511_11360_amd import pflbm as P
+    L = P.lib()
+    d = wl.base_params(lattice="D3Q19_D3Q7", nx=16, ny=8, nz=4)
+    p = P.make_params(d, "fp64", 0, 0, "auto")
+    nb = ctypes.c_size_t()
+    assert L.pflbm_state_bytes(ctypes.byref(p), ctypes.byref(nb)) == 0
+    h = ctypes.c_void_p()
+    for ptr, size in ((None, nb.value), (4096, nb.value - 1), (4096 + 128, nb.value)):
+        assert L.pflbm_create(ctypes.byref(p), None, ptr, size, ctypes.byref(h)) == P.PFLBM_EINVAL
+        assert not h.value
+    assert L.pflbm_create(None, None, 4096, nb.value, ctypes.byref(h)) == P.PFLBM_EINVAL
