@@ -28,6 +28,8 @@ class PhaseFieldRun(torch.autograd.Function):
             raise ValueError("adjoint precision must be 'fp64' or 'fp32', not %r" % (adjoint,))
         if adjoint == "fp32" and d.get("model", "AC") not in ("AC", "CH"):
             raise ValueError("the float32 adjoint covers the AC and CH models")
+        if adjoint == "fp32" and d.get("model", "AC") == "CH" and precision not in ("fp64", "fp32"):
+            raise ValueError("the float32 CH adjoint needs a float64 or float32 forward pass")
         s = Solver(d, precision=precision, device=phi0.device)
         s.init(phi0, u0)
         nsteps = int(nsteps)

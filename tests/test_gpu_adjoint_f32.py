@@ -264,14 +264,14 @@ def _manual(d, phi, u, steps, target):
     return out
 
 
-def _grad(d, phi, u, steps, target, adjoint):
+def _grad(d, phi, u, steps, target, adjoint, precision="fp64"):
     import torch
     from paper_2511_11360_amd.autograd import run_phase_field
     phi0 = _dev(phi).requires_grad_(True)
     sig = torch.tensor(d["sigma"], dtype=torch.float64, requires_grad=True)
     M = torch.tensor(d["M"], dtype=torch.float64, requires_grad=True)
     W = torch.tensor(d["W"], dtype=torch.float64, requires_grad=True)
-    phiN = run_phase_field(phi0, sig, M, W, d, _dev(u), steps, adjoint=adjoint)
+    phiN = run_phase_field(phi0, sig, M, W, d, _dev(u), steps, precision=precision, adjoint=adjoint)
     L = 0.5 * ((phiN - _dev(target)) ** 2).sum()
     L.backward()
     return (phi0.grad.cpu().numpy(), np.array([float(t.grad.detach().cpu()) for t in (sig, M, W)]))
@@ -358,3 +358,26 @@ def test_f32_adjoint_error_paths():
     # the handle still works
     s.adjoint_step_f32(g, h, lg, h.clone(), torch.empty_like(g), torch.empty_like(h), None, work)
     s.step(1)
+
+
+@pytest.mark.parametrize("precision", ["mixed_fp16", "mixed_bf16"])
+def test_16_bit_forward_with_both_adjoints(precision):
+    """A 16-bit forward pass has no recording step: the backward pass reads
+    each recomputed state out (float64, or float32 for the float32 adjoint).
+    Both adjoints then differentiate the same 16-bit trajectory and agree to
+    the float32 trajectory tolerance; the CH model's float32 adjoint needs a
+    recording step and refuses such a forward pass."""
+    d, phi, u = _cases()["droplet2d"]
+    target = wl.droplet_phi(d, (16.5, 15.5), 9.4)
+    _say("case 16-bit forward", precision)
+    g64, p64 = _grad(d, phi, u, 24, target, "fp64", precision)
+    g32, p32 = _grad(d, phi, u, 24, target, "fp32", precision)
+    assert np.isfinite(g64).all() and np.isfinite(p64).all()
+    for k, name in enumerate(("sigma", "M", "W")):
+        _say("  dL/d%s f64 %.10e f32 %.10e" % (name, p64[k], p32[k]))
+        assert abs(p32[k] - p64[k]) <= TRAJ_TOL * abs(p64[k])
+    assert np.max(np.abs(g32 - g64)) <= TRAJ_TOL * np.max(np.abs(g64))
+    dc, phic, uc = _cases()["ch_droplet2d"]
+    with pytest.raises(ValueError, match="float64 or float32 forward"):
+        _grad(dc, phic, uc, 4, target, "fp32", precision)
+
